@@ -1,0 +1,225 @@
+/*
+ * fpt.h -- C ABI of the MI355X (gfx950) first-passage-time library.
+ *
+ * The library integrates many independent Langevin trajectories of single-field
+ * inflation in the phase space (phi, pi = dphi/dN), M_pl = 1, each from
+ * (phi_in, pi_in) until its first passage through phi_end, with Euler-Maruyama
+ * steps, 1D noise, an importance-sampling drift bias and accumulated
+ * log-weights, and reduces the first-passage times N to a weighted histogram of
+ * P(deltaN), deltaN = N - N_ref.
+ * Method: Jackson et al., "Stochastic inflation beyond slow roll: noise
+ * modelling and importance sampling", arXiv:2410.13683:
+ *   Langevin system .......................... Sec. 2.3, eq. (stochstic_eom)
+ *   Euler-Maruyama step ...................... Sec. 4.1, eq. (euler_step_phi_and_pi)
+ *   1D noise, biased 1D step ................. Sec. 4.1, eqs. (stochastic_eom_1D),
+ *                                              (importance_sampling_1D_noise_step)
+ *   bias parallel to the noise, B = A S ...... Sec. 4.1, eq. (2D_1D_noise_diussion_based_bias)
+ *   weight w = exp(-sum dA) .................. Sec. 4.1, eqs. (weight), (weight_A)
+ *   first-passage time, deltaN ............... Sec. 2.3 and Sec. 4.1
+ *   noise table .............................. Sec. 3.2, eq. (covariance_constant_nu);
+ *                                              Sec. 3.4, eq. (nu_squared_approximation)
+ *   piecewise-linear potential ............... Sec. 4.2, eq. (potential_starobinsky)
+ *
+ * Step n of a trajectory (n = 0, 1, ...), from state (phi, pi):
+ *   xi      = unit Gaussian number n of the trajectory (see "Random numbers")
+ *   r       = V'(phi)/V(phi)
+ *   (S, t)  = noise table at phi (S = sqrt(Xi_phiphi), t = tan theta_n)
+ *   a       = bias amplitude (0, the constant A, or the learned a(phi, pi))
+ *   phi'    = phi + (pi + a S) dN + S xi sqrt(dN)
+ *   pi'     = pi - (3 - pi^2/2)(pi + r) dN + t (a S dN + S xi sqrt(dN))
+ *   ln w   -= a xi sqrt(dN) + a^2 dN / 2            (only where S > 0)
+ *   if phi' <= phi_end: N = n dN + dN (phi - phi_end)/(phi - phi')   -> done
+ *   else if pi'^2 / 2 >= 1: N = (n + 1) dN, flagged "ended early"      -> done
+ *   A trajectory that reaches max_steps steps without either is "censored".
+ *
+ * Random numbers: Philox4x32-10 (Salmon et al., SC'11) with key = (seed low
+ * 32 bits, seed high 32 bits) and counter = (n >> 2, trajectory low 32 bits,
+ * trajectory high 32 bits, instance).  Its words w0..w3 give uniforms
+ * u_j = (w_j + 1/2) 2^-32 and, by Box-Muller, xi_{4m}, xi_{4m+1} =
+ * rho cos(2 pi u1), rho sin(2 pi u1), rho = sqrt(-2 ln u0), and xi_{4m+2},
+ * xi_{4m+3} from (u2, u3) likewise.  Trajectory indices are global
+ * (traj_offset + i), so a trajectory's result does not depend on the launch
+ * configuration, on how a run is split, or on which other trajectories run.
+ *
+ * Conventions: every function returns an int status (FPT_OK = 0, negative on
+ * error) unless stated; no function aborts or throws across the ABI.  "Host"
+ * pointers are ordinary CPU memory; "device" pointers are HIP device memory of
+ * the current device (for example a torch tensor's data_ptr()).  A context is
+ * bound to the device that is current at fpt_create and is not thread-safe:
+ * use one context per concurrently used stream.
+ */
+#ifndef FPT_H
+#define FPT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---------------------------------------------------------- */
+enum {
+    FPT_OK = 0,
+    FPT_EINVAL = -1,        /* an argument is out of its documented range */
+    FPT_ENOMEM = -2,        /* a device or host allocation failed */
+    FPT_EHIP = -3,          /* a HIP runtime call failed */
+    FPT_ESTATE = -4,        /* the call is not valid in the context's current state */
+    FPT_EUNSUPPORTED = -5   /* a valid request this build does not implement */
+};
+
+/* ---- enumerations ---------------------------------------------------------- */
+enum { FPT_POT_PIECEWISE_LINEAR = 0, FPT_POT_EXPONENTIAL = 1 };
+enum { FPT_BIAS_NONE = 0, FPT_BIAS_CONST = 1, FPT_BIAS_MLP = 2 };
+enum { FPT_FP64 = 0, FPT_FP32_STATE = 1 };
+enum { FPT_BINS_LINEAR = 0, FPT_BINS_LOG = 1 };
+
+#define FPT_FLAG_CENSORED 0x80000000u    /* in d_steps: reached max_steps */
+#define FPT_FLAG_ENDED_EARLY 0x40000000u /* in d_steps: eps_1 >= 1 before phi_end */
+#define FPT_STEP_MASK 0x3fffffffu        /* in d_steps: number of steps taken */
+#define FPT_MAX_STEPS 0x3fffffff
+#define FPT_MAX_TABLE 4096               /* noise-table nodes (staged in LDS) */
+#define FPT_MAX_BINS 1024
+#define FPT_MLP_HIDDEN 64
+#define FPT_MLP_NPARAM 4482              /* 2->64->64->2 network, see fpt_bias */
+
+/* ---- inputs ---------------------------------------------------------------- */
+
+/* Potential and the start / end of the trajectories (eq. potential_starobinsky).
+ *   PIECEWISE_LINEAR: V = V0 + A_plus (phi - phi_T) for phi >= phi_T,
+ *                     V0 + A_minus (phi - phi_T) for phi < phi_T.
+ *   EXPONENTIAL:      V = V0 exp(A_plus (phi - phi_T)), so V'/V = A_plus everywhere
+ *                     (A_minus unused).
+ * Requires finite values, phi_in > phi_end, and V > 0 on [phi_end, phi_in]. */
+typedef struct {
+    int32_t kind;
+    double V0, phi_T, A_plus, A_minus;
+    double phi_in, pi_in, phi_end;
+} fpt_potential;
+
+/* Noise as a function of phi (Sec. 3.2/3.4): n nodes phi_j = phi_lo + j h,
+ * h = (phi_hi - phi_lo)/(n - 1), with S_j = sqrt(Xi_phiphi) >= 0 and
+ * tan_theta_j = Xi_phipi / Xi_phiphi.  Between nodes the values are linearly
+ * interpolated; outside [phi_lo, phi_hi] the edge node applies.  n == 1 means
+ * constant noise (phi_lo, phi_hi ignored).  1 <= n <= FPT_MAX_TABLE.  The host
+ * arrays are copied by fpt_create. */
+typedef struct {
+    int32_t n;
+    double phi_lo, phi_hi;
+    const double *S;
+    const double *tan_theta;
+} fpt_noise_table;
+
+/* Importance-sampling bias (Sec. 4.1): B_phi = a S, B_pi = tan(theta_n) a S.
+ *   NONE:  a = 0 (direct sampling, w = 1).
+ *   CONST: a = A (the bias amplitude).
+ *   MLP:   a = out0 of a 2->64->64->2 network with tanh hidden layers and a
+ *          linear output, evaluated in FP32 at
+ *          x0 = (phi - norm[0]) / norm[1],  x1 = (ln max(|pi|, 1e-30) - norm[2]) / norm[3].
+ *          mlp_params (host, FPT_MLP_NPARAM floats, copied) is, row-major
+ *          (out x in): W1[64x2] b1[64] W2[64x64] b2[64] W3[2x64] b3[2].
+ *          Output 1 is not used with 1D noise.  mlp_every = k evaluates the
+ *          network at steps n = 0, k, 2k, ... and holds a in between (k >= 1). */
+typedef struct {
+    int32_t kind;
+    double A;
+    const float *mlp_params;
+    double norm[4];
+    int32_t mlp_every;
+} fpt_bias;
+
+/* Run options.  precision: FPT_FP64 keeps (phi, pi) in FP64; FPT_FP32_STATE
+ * keeps them as unevaluated float pairs updated with FP32 arithmetic (ln w,
+ * the passage interpolation and the histogram stay FP64).  Histogram of
+ * deltaN = N - N_ref over n_bins bins (1..FPT_MAX_BINS): LINEAR edges
+ * lo + j (hi - lo)/n_bins, LOG edges lo (hi/lo)^(j/n_bins) (lo > 0); bins are
+ * half-open [e_j, e_{j+1}), plus one underflow and one overflow bin.  The bin
+ * of x is floor(t) with t = (x - lo) * (n_bins/(hi - lo)) (LINEAR) or
+ * t = ln(x/lo) * (n_bins/ln(hi/lo)) (LOG, x <= 0 is underflow), in FP64.
+ * max_steps: 1..FPT_MAX_STEPS.  instance: the fourth Philox counter word.
+ * block_size (64..1024, multiple of 64), blocks_per_cu (>= 1) and chunk
+ * (steps between retire/refill, multiple of 4) select the launch; 0 picks the
+ * built-in default.  They never change results. */
+typedef struct {
+    int32_t precision;
+    int32_t bins_kind, n_bins;
+    double lo, hi, N_ref;
+    int64_t max_steps;
+    uint32_t instance;
+    int32_t block_size, blocks_per_cu, chunk;
+} fpt_options;
+
+/* Accumulated results.  The caller provides the five arrays of n_bins + 2
+ * entries each (index 0 = underflow, 1..n_bins, n_bins + 1 = overflow).
+ * Over trajectories that crossed phi_end: per bin count, sum w, sum w^2,
+ * sum ln w, sum (ln w)^2; totals sum_w, sum_w2, sum_wN, sum_wN2.  n_traj
+ * counts every trajectory run, n_steps_total every step taken.  The FP64 sums
+ * are accumulated with atomics, so their last bits may vary between runs. */
+typedef struct {
+    uint64_t n_traj, n_censored, n_ended_early, n_steps_total;
+    double sum_w, sum_w2, sum_wN, sum_wN2;
+    uint64_t *count;
+    double *sum_w_bin, *sum_w2_bin, *sum_lnw_bin, *sum_lnw2_bin;
+} fpt_hist;
+
+typedef struct fpt_ctx fpt_ctx;  /* opaque; owns its device table, histogram and counters */
+
+/* ---- core API ---------------------------------------------------------------- */
+
+/* Validate and copy the inputs, allocate the context's device memory on the
+ * current device.  No kernel is launched.  On success *out receives the
+ * context (free it with fpt_destroy).  Errors: FPT_EINVAL (see the structs'
+ * requirements; a NULL pointer; bias NULL is allowed and means NONE),
+ * FPT_ENOMEM, FPT_EHIP. */
+int fpt_create(const fpt_potential *pot, const fpt_noise_table *table, const fpt_bias *bias,
+               const fpt_options *opts, fpt_ctx **out);
+
+/* Run trajectories traj_offset .. traj_offset + n_traj - 1 with time step dN
+ * (> 0, finite) and the 64-bit seed, asynchronously on hip_stream (a
+ * hipStream_t of the context's device; NULL = the null stream).  The results
+ * are added to the context's histogram.  Optional per-trajectory outputs
+ * (device memory owned by the caller, n_traj entries each, entry i for
+ * trajectory traj_offset + i, any of them may be NULL): d_N (N; NaN if
+ * censored; the time of the end if ended early), d_lnw (ln w), d_steps (steps
+ * taken | FPT_FLAG_*).  n_traj == 0 is a no-op.  The buffers must stay valid
+ * until the stream reaches the end of the run.  Errors: FPT_EINVAL,
+ * FPT_EHIP. */
+int fpt_run(fpt_ctx *ctx, uint64_t n_traj, double dN, uint64_t seed, uint64_t traj_offset,
+            void *hip_stream, double *d_N, double *d_lnw, uint32_t *d_steps);
+
+/* Wait for the context's runs to finish and copy the accumulated histogram to
+ * *out (host).  Errors: FPT_EINVAL (NULL arrays), FPT_EHIP. */
+int fpt_histogram(fpt_ctx *ctx, fpt_hist *out);
+
+/* Zero the accumulated histogram (waits for outstanding runs first). */
+int fpt_reset(fpt_ctx *ctx);
+
+/* Wait for outstanding runs and free the context (NULL is allowed). */
+void fpt_destroy(fpt_ctx *ctx);
+
+/* Duration in milliseconds of the last fpt_run's kernel, measured with HIP
+ * events recorded on the run's stream around the launch (waits for it). */
+int fpt_last_kernel_ms(fpt_ctx *ctx, double *ms);
+
+/* Static text for a status code. */
+const char *fpt_strerror(int status);
+
+/* Text describing the last error of the calling thread ("" if none). */
+const char *fpt_last_error(void);
+
+/* ---- noise table ------------------------------------------------------------- */
+
+/* Fill S_out[n], tan_out[n] (host arrays owned by the caller) with the noise of
+ * eq. (covariance_constant_nu) -- Bunch-Davies Bessel coefficients evaluated at
+ * -k eta = sigma -- with nu(phi) from eq. (nu_squared_approximation) and
+ * H^2 = V(phi)/3, at the nodes phi_j = phi_lo + j (phi_hi - phi_lo)/(n - 1)
+ * (n == 1: phi_lo).  The values are computed by a device kernel on the current
+ * device.  Errors: FPT_EINVAL (n out of 1..FPT_MAX_TABLE, sigma <= 0,
+ * V <= 0 or nu^2 <= 0 at a node), FPT_EHIP. */
+int fpt_noise_table_bessel(const fpt_potential *pot, double sigma, int32_t n, double phi_lo,
+                           double phi_hi, double *S_out, double *tan_out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FPT_H */

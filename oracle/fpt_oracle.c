@@ -1,0 +1,525 @@
+/*
+ * fpt_oracle.c -- TEST INFRASTRUCTURE, NOT PART OF THE PRODUCT.
+ *
+ * A plain, slow, obviously-correct FP64 CPU reference for the stochastic-deltaN
+ * first-passage method of Jackson, Assadullahi, Gow, Koyama, Vennin, Wands,
+ * "Stochastic inflation beyond slow roll: noise modelling and importance
+ * sampling" (arXiv:2410.13683).  Only the tests, the smoke check and the
+ * benchmark's CPU-baseline leg load this file.  It shares no code, header,
+ * constant or helper with the GPU library, and it does not include or link
+ * anything from it.
+ *
+ * What it follows (sections / equations of the paper):
+ *   - Langevin system in (phi, pi = dphi/dN), M_pl = 1:        Sec. 2.3, eq. (stochstic_eom)
+ *   - Euler-Maruyama step:                                      Sec. 4.1, eq. (euler_step_phi_and_pi)
+ *   - 1D noise S_phiphi (1, tan theta_n):                       Sec. 4.1, eq. (stochastic_eom_1D)
+ *   - importance-sampled 1D step (sign of the drift restored):  Sec. 4.1, eq. (importance_sampling_1D_noise_step)
+ *   - bias parallel to the noise, diffusion-based amplitude:    Sec. 4.1, constraint below eq. (importance_sampling_1D_noise_step)
+ *                                                               and eq. (2D_1D_noise_diussion_based_bias)
+ *   - weight w = exp(-sum dA), dA of the Mazonka form:          Sec. 4.1, eqs. (weight), (weight_A)
+ *   - first-passage time N = n dN, deltaN = N - <N>:            Sec. 4.1 and Sec. 2.3
+ *   - piecewise-linear potential:                               Sec. 4.2, eq. (potential_starobinsky)
+ *   - constant-nu noise with Bunch-Davies coefficients:         Sec. 3.2, eq. (covariance_constant_nu)
+ *   - nu^2 as a function of phi only after the transition:      Sec. 3.4, eq. (nu_squared_approximation)
+ *
+ * Readings where the paper is silent or garbled (each listed in the design doc):
+ *   - the drift in the biased pi step carries the same minus sign as in the
+ *     unbiased step;
+ *   - the bias is parallel to the noise vector: B_pi = tan(theta_n) B_phi with
+ *     B_phi = A S_phiphi (the printed constraint has the two sides swapped);
+ *   - dA in 1D is eq. (weight_A) restricted to the noise direction:
+ *     dA = (B_phi dN / 2 + S_phiphi xi sqrt(dN)) B_phi / S_phiphi^2, and 0 where S = 0;
+ *   - absorption when phi <= phi_end; N is interpolated linearly in phi over
+ *     the crossing step; eps_1 = pi^2/2 >= 1 before phi_end only raises a flag;
+ *   - the noise is a function of phi (linear interpolation of a uniform table,
+ *     clamped to the edge nodes), H^2 = V/3 inside the table;
+ *   - random numbers: Philox4x32-10 keyed by the 64-bit seed, counter
+ *     (step>>2, trajectory lo, trajectory hi, instance); the four 32-bit words
+ *     give four uniforms u = (w + 1/2) 2^-32 and two Box-Muller pairs.
+ *
+ * Parity status: every function below is pinned by a CPU test (see the
+ * oracle section of the design doc); the learned-bias replay gradient is pinned by
+ * central finite differences of its own objective.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define ORC_POT_PIECEWISE_LINEAR 0
+#define ORC_POT_EXPONENTIAL 1
+
+#define ORC_BIAS_NONE 0
+#define ORC_BIAS_CONST 1
+#define ORC_BIAS_MLP 2
+
+#define ORC_FLAG_CENSORED 0x80000000u
+#define ORC_FLAG_ENDED_EARLY 0x40000000u
+#define ORC_STEP_MASK 0x3fffffffu
+
+/* ------------------------------------------------------------------------- */
+/* Philox4x32-10 (Salmon, Moraes, Dror, Shaw, "Parallel random numbers: as    */
+/* easy as 1, 2, 3", SC'11): ten rounds of two 32x32->64 multiplications,     */
+/* the key advanced by the Weyl constants between rounds.                     */
+/* ------------------------------------------------------------------------- */
+void orc_philox4x32_10(const uint32_t ctr_in[4], const uint32_t key_in[2], uint32_t out[4])
+{
+    const uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u;
+    const uint32_t W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
+    uint32_t c[4] = {ctr_in[0], ctr_in[1], ctr_in[2], ctr_in[3]};
+    uint32_t k[2] = {key_in[0], key_in[1]};
+    for (int round = 0; round < 10; ++round) {
+        uint64_t p0 = (uint64_t)M0 * (uint64_t)c[0];
+        uint64_t p1 = (uint64_t)M1 * (uint64_t)c[2];
+        uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+        uint32_t n0 = hi1 ^ c[1] ^ k[0];
+        uint32_t n1 = lo1;
+        uint32_t n2 = hi0 ^ c[3] ^ k[1];
+        uint32_t n3 = lo0;
+        c[0] = n0; c[1] = n1; c[2] = n2; c[3] = n3;
+        k[0] += W0;
+        k[1] += W1;
+    }
+    out[0] = c[0]; out[1] = c[1]; out[2] = c[2]; out[3] = c[3];
+}
+
+/* The unit Gaussian xi of step n of trajectory `traj` (global index) of
+ * instance `instance`.  Call m = n >> 2 of the generator yields four words;
+ * u_j = (w_j + 1/2) / 2^32 lies strictly inside (0, 1).  Box-Muller (1958):
+ * (u0, u1) -> rho cos(2 pi u1), rho sin(2 pi u1) with rho = sqrt(-2 ln u0),
+ * and (u2, u3) likewise; xi_n is entry n & 3 of these four. */
+static void orc_four_normals(uint64_t seed, uint32_t instance, uint64_t traj, uint64_t m, double z[4])
+{
+    uint32_t ctr[4] = {(uint32_t)m, (uint32_t)traj, (uint32_t)(traj >> 32), instance};
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    uint32_t w[4];
+    orc_philox4x32_10(ctr, key, w);
+    double u[4];
+    for (int j = 0; j < 4; ++j) u[j] = ((double)w[j] + 0.5) / 4294967296.0;
+    const double two_pi = 2.0 * M_PI;
+    double rho01 = sqrt(-2.0 * log(u[0]));
+    double rho23 = sqrt(-2.0 * log(u[2]));
+    z[0] = rho01 * cos(two_pi * u[1]);
+    z[1] = rho01 * sin(two_pi * u[1]);
+    z[2] = rho23 * cos(two_pi * u[3]);
+    z[3] = rho23 * sin(two_pi * u[3]);
+}
+
+/* xi_n for n = n0 .. n0+count-1 (exported for the tests). */
+void orc_normals(uint64_t seed, uint32_t instance, uint64_t traj, uint64_t n0, uint64_t count, double *z_out)
+{
+    for (uint64_t i = 0; i < count; ++i) {
+        uint64_t n = n0 + i;
+        double z[4];
+        orc_four_normals(seed, instance, traj, n >> 2, z);
+        z_out[i] = z[n & 3];
+    }
+}
+
+/* Uniforms u_j of call m (exported for the Box-Muller invariance tests). */
+void orc_uniforms(uint64_t seed, uint32_t instance, uint64_t traj, uint64_t m, double u_out[4])
+{
+    uint32_t ctr[4] = {(uint32_t)m, (uint32_t)traj, (uint32_t)(traj >> 32), instance};
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    uint32_t w[4];
+    orc_philox4x32_10(ctr, key, w);
+    for (int j = 0; j < 4; ++j) u_out[j] = ((double)w[j] + 0.5) / 4294967296.0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Potentials.  pot = {V0, phi_T, A_plus, A_minus}.                           */
+/*   piecewise linear, eq. (potential_starobinsky):                           */
+/*       V = V0 + A_+ (phi - phi_T) for phi >= phi_T, V0 + A_- (phi - phi_T)  */
+/*       otherwise (phi == phi_T takes the A_+ branch);                       */
+/*   exponential: V = V0 exp(A_+ (phi - phi_T)), for which V'/V = A_+ exactly */
+/*       and pi = -A_+ is an exact fixed point of the drift.                  */
+/* ------------------------------------------------------------------------- */
+double orc_V(int kind, const double pot[4], double phi)
+{
+    const double V0 = pot[0], phi_T = pot[1], Ap = pot[2], Am = pot[3];
+    if (kind == ORC_POT_EXPONENTIAL) return V0 * exp(Ap * (phi - phi_T));
+    if (phi >= phi_T) return V0 + Ap * (phi - phi_T);
+    return V0 + Am * (phi - phi_T);
+}
+
+double orc_dV(int kind, const double pot[4], double phi)
+{
+    const double phi_T = pot[1], Ap = pot[2], Am = pot[3];
+    if (kind == ORC_POT_EXPONENTIAL) return Ap * orc_V(kind, pot, phi);
+    return (phi >= phi_T) ? Ap : Am;
+}
+
+double orc_d2V(int kind, const double pot[4], double phi)
+{
+    const double Ap = pot[2];
+    if (kind == ORC_POT_EXPONENTIAL) return Ap * Ap * orc_V(kind, pot, phi);
+    (void)phi;
+    return 0.0; /* linear on each side of phi_T */
+}
+
+/* ------------------------------------------------------------------------- */
+/* Noise table of eq. (covariance_constant_nu) with nu(phi) from              */
+/* eq. (nu_squared_approximation):                                            */
+/*   nu^2 = 9/4 - 3 [V''/V - (V'/V)^2],  H^2 = V/3,                           */
+/*   Xi_phiphi = H^2/(4 pi^2) [Gamma(nu)/Gamma(3/2)]^2 (sigma/2)^(3 - 2 nu),  */
+/*   Xi_phipi  = (nu - 3/2) Xi_phiphi,                                        */
+/*   S_phiphi = sqrt(Xi_phiphi),  tan theta_n = Xi_phipi / Xi_phiphi.         */
+/* Nodes phi_j = phi_lo + j h, h = (phi_hi - phi_lo)/(n - 1); n == 1 gives a  */
+/* single node at phi_lo.  Returns 0, or -1 on invalid input.                 */
+/* ------------------------------------------------------------------------- */
+int orc_noise_table_bessel(int kind, const double pot[4], double sigma, int n,
+                           double phi_lo, double phi_hi, double *S_out, double *tan_out)
+{
+    if (n < 1 || !(sigma > 0.0)) return -1;
+    if (n > 1 && !(phi_hi > phi_lo)) return -1;
+    double h = (n > 1) ? (phi_hi - phi_lo) / (double)(n - 1) : 0.0;
+    for (int j = 0; j < n; ++j) {
+        double phi = phi_lo + (double)j * h;
+        double V = orc_V(kind, pot, phi);
+        if (!(V > 0.0)) return -1;
+        double dVV = orc_dV(kind, pot, phi) / V;
+        double d2VV = orc_d2V(kind, pot, phi) / V;
+        double nu2 = 9.0 / 4.0 - 3.0 * (d2VV - dVV * dVV);
+        if (!(nu2 > 0.0)) return -1;
+        double nu = sqrt(nu2);
+        double H2 = V / 3.0;
+        double g = tgamma(nu) / tgamma(1.5);
+        double Xi_pp = H2 / (4.0 * M_PI * M_PI) * g * g * pow(sigma / 2.0, 3.0 - 2.0 * nu);
+        double Xi_ppi = (nu - 1.5) * Xi_pp;
+        S_out[j] = sqrt(Xi_pp);
+        tan_out[j] = Xi_ppi / Xi_pp;
+    }
+    return 0;
+}
+
+/* Linear interpolation of the table at phi, clamped to the edge nodes. */
+static void orc_table_lookup(int n_tab, double phi_lo, double phi_hi, const double *S_tab,
+                             const double *t_tab, double phi, double *S, double *t)
+{
+    if (n_tab == 1) { *S = S_tab[0]; *t = t_tab[0]; return; }
+    double h = (phi_hi - phi_lo) / (double)(n_tab - 1);
+    double x = (phi - phi_lo) / h;
+    double jf = floor(x);
+    if (jf < 0.0) jf = 0.0;
+    if (jf > (double)(n_tab - 2)) jf = (double)(n_tab - 2);
+    int j = (int)jf;
+    double f = x - jf;
+    if (f < 0.0) f = 0.0;
+    if (f > 1.0) f = 1.0;
+    *S = S_tab[j] + f * (S_tab[j + 1] - S_tab[j]);
+    *t = t_tab[j] + f * (t_tab[j + 1] - t_tab[j]);
+}
+
+/* ------------------------------------------------------------------------- */
+/* Learned bias amplitude: a 2 -> 64 -> 64 -> 2 network with tanh hidden      */
+/* layers and a linear output, evaluated in FP64 from FP32 parameters.        */
+/* Layout (4482 floats, row-major, out x in): W1[64x2] b1[64] W2[64x64]       */
+/* b2[64] W3[2x64] b3[2].  Inputs x0 = (phi - c0)/s0,                         */
+/* x1 = (ln max(|pi|, 1e-30) - c1)/s1 with norm = {c0, s0, c1, s1}.            */
+/* Output 0 is the amplitude a(phi, pi); output 1 would bias a second noise   */
+/* direction and is unused with 1D noise.                                     */
+/* ------------------------------------------------------------------------- */
+#define MLP_H 64
+#define MLP_NPARAM 4482
+
+static void orc_mlp_inputs(const double norm[4], double phi, double pi_, double x[2])
+{
+    double ap = fabs(pi_);
+    if (ap < 1e-30) ap = 1e-30;
+    x[0] = (phi - norm[0]) / norm[1];
+    x[1] = (log(ap) - norm[2]) / norm[3];
+}
+
+/* Forward pass; also returns the hidden activations when h1/h2 are non-NULL. */
+static double orc_mlp_forward(const float *p, const double x[2], double *h1_out, double *h2_out)
+{
+    const float *W1 = p, *b1 = p + 128, *W2 = p + 192, *b2 = p + 4288, *W3 = p + 4352, *b3 = p + 4480;
+    double h1[MLP_H], h2[MLP_H];
+    for (int j = 0; j < MLP_H; ++j) {
+        double s = (double)b1[j];
+        for (int i = 0; i < 2; ++i) s += (double)W1[j * 2 + i] * x[i];
+        h1[j] = tanh(s);
+    }
+    for (int j = 0; j < MLP_H; ++j) {
+        double s = (double)b2[j];
+        for (int i = 0; i < MLP_H; ++i) s += (double)W2[j * MLP_H + i] * h1[i];
+        h2[j] = tanh(s);
+    }
+    double out0 = (double)b3[0];
+    for (int i = 0; i < MLP_H; ++i) out0 += (double)W3[i] * h2[i];
+    (void)W3; /* row 1 of W3 and b3[1] feed output 1, unused for 1D noise */
+    if (h1_out) memcpy(h1_out, h1, sizeof h1);
+    if (h2_out) memcpy(h2_out, h2, sizeof h2);
+    return out0;
+}
+
+double orc_mlp_eval(const float *params, const double norm[4], double phi, double pi_)
+{
+    double x[2];
+    orc_mlp_inputs(norm, phi, pi_, x);
+    return orc_mlp_forward(params, x, NULL, NULL);
+}
+
+/* d a / d params at (phi, pi): plain back-propagation through the network,
+ * accumulated with weight `scale` into grad[4482] (FP64). */
+static void orc_mlp_backward(const float *p, const double x[2], double scale, double *grad)
+{
+    const float *W2 = p + 192, *W3 = p + 4352;
+    double h1[MLP_H], h2[MLP_H];
+    orc_mlp_forward(p, x, h1, h2);
+    double *gW1 = grad, *gb1 = grad + 128, *gW2 = grad + 192, *gb2 = grad + 4288, *gW3 = grad + 4352, *gb3 = grad + 4480;
+    /* out0 = b3[0] + sum_i W3[0,i] h2[i] */
+    gb3[0] += scale;
+    double d2[MLP_H];
+    for (int i = 0; i < MLP_H; ++i) {
+        gW3[i] += scale * h2[i];
+        d2[i] = scale * (double)W3[i] * (1.0 - h2[i] * h2[i]);
+    }
+    double d1[MLP_H];
+    for (int i = 0; i < MLP_H; ++i) d1[i] = 0.0;
+    for (int j = 0; j < MLP_H; ++j) {
+        gb2[j] += d2[j];
+        for (int i = 0; i < MLP_H; ++i) {
+            gW2[j * MLP_H + i] += d2[j] * h1[i];
+            d1[i] += d2[j] * (double)W2[j * MLP_H + i];
+        }
+    }
+    for (int i = 0; i < MLP_H; ++i) {
+        double g = d1[i] * (1.0 - h1[i] * h1[i]);
+        gb1[i] += g;
+        gW1[i * 2 + 0] += g * x[0];
+        gW1[i * 2 + 1] += g * x[1];
+    }
+}
+
+/* ------------------------------------------------------------------------- */
+/* One trajectory, Sec. 4.1.  Writes N, ln w and the step count with flags.   */
+/* ------------------------------------------------------------------------- */
+typedef struct {
+    int kind;
+    double pot[4];
+    int n_tab;
+    double phi_lo, phi_hi;
+    const double *S_tab, *t_tab;
+    double phi_in, pi_in, phi_end;
+    int bias_kind;
+    double A_bias;
+    const float *mlp;
+    double norm[4];
+    double dN;
+    uint64_t seed;
+    uint32_t instance;
+    int64_t max_steps;
+} orc_problem;
+
+static void orc_trajectory(const orc_problem *P, uint64_t traj, double *N_out, double *lnw_out, uint32_t *steps_out)
+{
+    const double dN = P->dN;
+    const double sqrt_dN = sqrt(dN);
+    double phi = P->phi_in, pi_ = P->pi_in, lnw = 0.0;
+    int64_t n = 0;
+    double zbuf[4];
+    uint64_t zcall = UINT64_MAX;
+    for (;;) {
+        if (n >= P->max_steps) {
+            *N_out = NAN;
+            *lnw_out = lnw;
+            *steps_out = (uint32_t)n | ORC_FLAG_CENSORED;
+            return;
+        }
+        /* xi^(i) */
+        uint64_t call = (uint64_t)n >> 2;
+        if (call != zcall) { orc_four_normals(P->seed, P->instance, traj, call, zbuf); zcall = call; }
+        double xi = zbuf[n & 3];
+        /* drift vector D = (pi, -(3 - pi^2/2)(pi + V'/V)), eq. (stochstic_eom) */
+        double V = orc_V(P->kind, P->pot, phi);
+        double dV = orc_dV(P->kind, P->pot, phi);
+        double D_phi = pi_;
+        double D_pi = -(3.0 - pi_ * pi_ / 2.0) * (pi_ + dV / V);
+        /* 1D noise amplitude and direction at the local field value */
+        double S, tan_theta;
+        orc_table_lookup(P->n_tab, P->phi_lo, P->phi_hi, P->S_tab, P->t_tab, phi, &S, &tan_theta);
+        /* bias amplitude A (constant or learned) and bias vector parallel to the noise */
+        double A = 0.0;
+        if (P->bias_kind == ORC_BIAS_CONST) A = P->A_bias;
+        else if (P->bias_kind == ORC_BIAS_MLP) A = orc_mlp_eval(P->mlp, P->norm, phi, pi_);
+        double B_phi = A * S;
+        double B_pi = tan_theta * B_phi;
+        /* biased Euler-Maruyama step, eq. (importance_sampling_1D_noise_step) */
+        double phi_next = phi + D_phi * dN + B_phi * dN + S * xi * sqrt_dN;
+        double pi_next = pi_ + D_pi * dN + B_pi * dN + tan_theta * S * xi * sqrt_dN;
+        /* dA of eq. (weight_A) along the single noise direction */
+        if (S > 0.0) {
+            double dA = (B_phi / 2.0 * dN + S * xi * sqrt_dN) * B_phi / (S * S);
+            lnw -= dA;
+        }
+        n += 1;
+        if (phi_next <= P->phi_end) {
+            /* linear interpolation of the passage inside step n */
+            double frac = (phi - P->phi_end) / (phi - phi_next);
+            *N_out = (double)(n - 1) * dN + dN * frac;
+            *lnw_out = lnw;
+            *steps_out = (uint32_t)n;
+            return;
+        }
+        if (pi_next * pi_next / 2.0 >= 1.0) {
+            /* eps_1 >= 1: inflation ended before phi_end */
+            *N_out = (double)n * dN;
+            *lnw_out = lnw;
+            *steps_out = (uint32_t)n | ORC_FLAG_ENDED_EARLY;
+            return;
+        }
+        phi = phi_next;
+        pi_ = pi_next;
+    }
+}
+
+/* Run n_traj trajectories with global indices traj_offset .. traj_offset+n_traj-1.
+ * Returns 0, or -1 on invalid input.  n_threads <= 0 uses the OpenMP default. */
+int orc_run(int kind, const double pot[4],
+            int n_tab, double phi_lo, double phi_hi, const double *S_tab, const double *t_tab,
+            double phi_in, double pi_in, double phi_end,
+            int bias_kind, double A_bias, const float *mlp_params, const double *mlp_norm,
+            double dN, uint64_t seed, uint32_t instance, uint64_t traj_offset, uint64_t n_traj,
+            int64_t max_steps, double *N_out, double *lnw_out, uint32_t *steps_out, int n_threads)
+{
+    if (n_tab < 1 || !(dN > 0.0) || max_steps < 1 || max_steps > (int64_t)ORC_STEP_MASK) return -1;
+    if (!(phi_in > phi_end)) return -1;
+    if (bias_kind == ORC_BIAS_MLP && (!mlp_params || !mlp_norm)) return -1;
+    orc_problem P;
+    memset(&P, 0, sizeof P);
+    P.kind = kind;
+    memcpy(P.pot, pot, sizeof P.pot);
+    P.n_tab = n_tab; P.phi_lo = phi_lo; P.phi_hi = phi_hi; P.S_tab = S_tab; P.t_tab = t_tab;
+    P.phi_in = phi_in; P.pi_in = pi_in; P.phi_end = phi_end;
+    P.bias_kind = bias_kind; P.A_bias = A_bias; P.mlp = mlp_params;
+    if (mlp_norm) memcpy(P.norm, mlp_norm, sizeof P.norm);
+    P.dN = dN; P.seed = seed; P.instance = instance; P.max_steps = max_steps;
+#ifdef _OPENMP
+    if (n_threads > 0) omp_set_num_threads(n_threads);
+#else
+    (void)n_threads;
+#endif
+    int64_t nt = (int64_t)n_traj;
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t i = 0; i < nt; ++i)
+        orc_trajectory(&P, traj_offset + (uint64_t)i, &N_out[i], &lnw_out[i], &steps_out[i]);
+    return 0;
+}
+
+int orc_max_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+/* ------------------------------------------------------------------------- */
+/* Replay gradient of the learned-bias objective.                             */
+/*                                                                            */
+/* Paths are drawn once under the sampling amplitude a_old (the network at    */
+/* the parameters that generated them).  With e_k = a_old(x_k) dN + xi_k      */
+/* sqrt(dN) the noise-space increment of step k, the log-weight of the same   */
+/* path under a candidate amplitude a_theta is                                */
+/*     ln w_theta = sum_k ( -a_theta(x_k) e_k + a_theta(x_k)^2 dN / 2 ),      */
+/* which is eq. (weight_A) with the increment written in the unbiased noise.  */
+/* The objective is the second moment of the estimator on the tail set T:     */
+/*     J(theta) = (1/n) sum_{paths in T} w_old w_theta,                       */
+/* with gradient (1/n) sum_T w_old w_theta sum_k (-e_k + a_theta dN) grad a.  */
+/* Replaying at theta = theta_old gives w_old w_theta = w^2.                  */
+/* Only trajectories whose deltaN = N - N_ref lies in [tail_lo, +inf) count.  */
+/* grad_out has 4482 doubles; J_out receives J(theta).                        */
+/* ------------------------------------------------------------------------- */
+int orc_mlp_replay_grad(int kind, const double pot[4],
+                        int n_tab, double phi_lo, double phi_hi, const double *S_tab, const double *t_tab,
+                        double phi_in, double pi_in, double phi_end,
+                        const float *theta_old, const float *theta, const double *mlp_norm,
+                        double dN, uint64_t seed, uint32_t instance, uint64_t traj_offset, uint64_t n_traj,
+                        int64_t max_steps, double N_ref, double tail_lo,
+                        double *grad_out, double *J_out, int n_threads)
+{
+    if (n_tab < 1 || !(dN > 0.0) || max_steps < 1) return -1;
+    orc_problem P;
+    memset(&P, 0, sizeof P);
+    P.kind = kind;
+    memcpy(P.pot, pot, sizeof P.pot);
+    P.n_tab = n_tab; P.phi_lo = phi_lo; P.phi_hi = phi_hi; P.S_tab = S_tab; P.t_tab = t_tab;
+    P.phi_in = phi_in; P.pi_in = pi_in; P.phi_end = phi_end;
+    P.bias_kind = ORC_BIAS_MLP; P.mlp = theta_old;
+    memcpy(P.norm, mlp_norm, sizeof P.norm);
+    P.dN = dN; P.seed = seed; P.instance = instance; P.max_steps = max_steps;
+#ifdef _OPENMP
+    if (n_threads > 0) omp_set_num_threads(n_threads);
+#else
+    (void)n_threads;
+#endif
+    const double sqrt_dN = sqrt(dN);
+    int64_t nt = (int64_t)n_traj;
+    double J = 0.0;
+    for (int k = 0; k < MLP_NPARAM; ++k) grad_out[k] = 0.0;
+#pragma omp parallel
+    {
+        double *g_local = (double *)calloc(MLP_NPARAM, sizeof(double));
+        double *g_path = (double *)calloc(MLP_NPARAM, sizeof(double));
+        double J_local = 0.0;
+#pragma omp for schedule(dynamic, 4)
+        for (int64_t i = 0; i < nt; ++i) {
+            uint64_t traj = traj_offset + (uint64_t)i;
+            double N, lnw_old;
+            uint32_t steps;
+            orc_trajectory(&P, traj, &N, &lnw_old, &steps);
+            if (steps & (ORC_FLAG_CENSORED | ORC_FLAG_ENDED_EARLY)) continue;
+            if (!(N - N_ref >= tail_lo)) continue;
+            /* replay the same path: states and noise are those drawn under theta_old */
+            double phi = phi_in, pi_ = pi_in, lnw_new = 0.0;
+            memset(g_path, 0, MLP_NPARAM * sizeof(double));
+            uint32_t n_steps = steps & ORC_STEP_MASK;
+            double zbuf[4];
+            uint64_t zcall = UINT64_MAX;
+            for (uint32_t n = 0; n < n_steps; ++n) {
+                uint64_t call = (uint64_t)n >> 2;
+                if (call != zcall) { orc_four_normals(seed, instance, traj, call, zbuf); zcall = call; }
+                double xi = zbuf[n & 3];
+                double V = orc_V(kind, pot, phi);
+                double dV = orc_dV(kind, pot, phi);
+                double S, tan_theta;
+                orc_table_lookup(n_tab, phi_lo, phi_hi, S_tab, t_tab, phi, &S, &tan_theta);
+                double x[2];
+                orc_mlp_inputs(mlp_norm, phi, pi_, x);
+                double a_old = orc_mlp_forward(theta_old, x, NULL, NULL);
+                if (S > 0.0) {
+                    double a_new = orc_mlp_forward(theta, x, NULL, NULL);
+                    double e = a_old * dN + xi * sqrt_dN;
+                    lnw_new += -a_new * e + a_new * a_new * dN / 2.0;
+                    orc_mlp_backward(theta, x, -e + a_new * dN, g_path);
+                }
+                double B_phi = a_old * S;
+                double B_pi = tan_theta * B_phi;
+                double D_pi = -(3.0 - pi_ * pi_ / 2.0) * (pi_ + dV / V);
+                double phi_next = phi + pi_ * dN + B_phi * dN + S * xi * sqrt_dN;
+                double pi_next = pi_ + D_pi * dN + B_pi * dN + tan_theta * S * xi * sqrt_dN;
+                phi = phi_next;
+                pi_ = pi_next;
+            }
+            double ww = exp(lnw_old + lnw_new);
+            J_local += ww;
+            for (int k = 0; k < MLP_NPARAM; ++k) g_local[k] += ww * g_path[k];
+        }
+#pragma omp critical
+        {
+            J += J_local;
+            for (int k = 0; k < MLP_NPARAM; ++k) grad_out[k] += g_local[k];
+        }
+        free(g_local);
+        free(g_path);
+    }
+    for (int k = 0; k < MLP_NPARAM; ++k) grad_out[k] /= (double)n_traj;
+    *J_out = J / (double)n_traj;
+    return 0;
+}

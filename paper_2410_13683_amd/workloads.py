@@ -1,0 +1,160 @@
+"""Seeded, synthetic workload definitions shared by the tests, the benchmark
+and the smoke check.
+
+This module holds parameters only: potentials, start/end points, table grids,
+time steps, trajectory counts, seeds and histogram layouts.  It performs none
+of the method's arithmetic (no noise model, no drift, no stepping) and imports
+neither the GPU binding nor the CPU oracle, so both can be fed from it.
+
+The paper's numerical experiments (Sec. 4.2) use the piecewise-linear
+potential V = V0 + A_+-(phi - phi_T) of eq. (potential_starobinsky) with
+A_- = 1e-3 A_+.  The workloads below use V0 = 1e-10 and slope parameters
+eps_V = (A/V0)^2/2 of 0.01 (steep side) and 1e-8 (flat side), which give the
+same ratio A_-/A_+ = 1e-3.  No dataset is involved anywhere.
+
+Derived constants are stored rather than recomputed at import time:
+NOISE_S_HUBBLE (H/2pi with H^2 = V0/3), DELTA_E (the distance phi_e - phi_end for which the noise-free Euler-Maruyama
+passage time from phi_e is 10 e-folds at dN = 1e-4) and the noise-free
+reference times N_REF_*.  They were written by ``oracle/derive_constants.py``,
+which calls only the CPU oracle; ``tests/test_workloads.py`` re-derives them.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+POT_PIECEWISE_LINEAR = 0
+POT_EXPONENTIAL = 1
+BIAS_NONE = 0
+BIAS_CONST = 1
+BIAS_MLP = 2
+BINS_LINEAR = 0
+BINS_LOG = 1
+
+V0 = 1e-10
+EPS_PLUS = 0.01        # slope parameter on the slow-roll side, eps_V = (A_+/V0)^2 / 2
+EPS_MINUS = 1e-8       # slope parameter on the ultra-slow-roll side
+A_PLUS = V0 * math.sqrt(2.0 * EPS_PLUS)
+A_MINUS = V0 * math.sqrt(2.0 * EPS_MINUS)
+
+# Written by oracle/derive_constants.py (noise-free oracle runs).
+NOISE_S_HUBBLE = 9.188814923696534e-07  # H/2pi with H^2 = V0/3 (de Sitter noise amplitude)
+DELTA_E = 0.04857416112949248        # phi_e - phi_end giving N = 10 at dN = 1e-4
+N_REF_SRUSR = 9.999999999999952       # noise-free N for the SR->USR workloads at dN = 1e-4
+N_REF_LINEAR = 7.612929983590818       # noise-free N for the linear slow-roll workload at dN = 1e-3
+SIGMA_LIN_LINEAR = 1.918e-5          # linear-theory spread of N for the linear workload
+SIGMA_LIN_SRUSR = 0.0205             # linear-theory spread of N for the SR->USR workloads
+
+# Dyadic noise-table grid: phi_j = (j - 3300) 2^-16 for j = 0..4095, so every
+# node, including the transition phi_T = 0, is an exact double.
+TABLE_N = 4096
+TABLE_H = 2.0 ** -16
+TABLE_J_T = 3300
+TABLE_PHI_LO = -TABLE_J_T * TABLE_H
+TABLE_PHI_HI = (TABLE_N - 1 - TABLE_J_T) * TABLE_H
+
+
+@dataclass
+class Workload:
+    """One first-passage problem with its run and histogram settings."""
+    name: str
+    kind: int
+    V0: float
+    phi_T: float
+    A_plus: float
+    A_minus: float
+    phi_in: float
+    pi_in: float
+    phi_end: float
+    noise: str                      # "const": S = noise_S, tan = noise_tan (one table node);
+                                    # "bessel": eq. (covariance_constant_nu) table on the grid below
+    dN: float
+    n_traj: int
+    seed: int
+    noise_S: float = 0.0
+    noise_tan: float = 0.0
+    sigma: float = 1.0              # coarse-graining ratio k_sigma / aH
+    table_n: int = 1
+    table_lo: float = 0.0
+    table_hi: float = 0.0
+    bias_kind: int = BIAS_NONE
+    A_bias: float = 0.0
+    precision: int = 0              # 0 FP64, 1 FP32 state
+    bins_kind: int = BINS_LINEAR
+    n_bins: int = 64
+    lo: float = -1.0
+    hi: float = 1.0
+    N_ref: float = 0.0
+    max_steps: int = 0x3FFFFFFF
+    extra: dict = field(default_factory=dict)
+
+    def with_(self, **kw) -> "Workload":
+        d = dict(self.__dict__)
+        d.update(kw)
+        return Workload(**d)
+
+
+def linear_slow_roll(n_traj: int = 10_000, seed: int = 1) -> Workload:
+    """V = V0 (1 + sqrt(2 * 0.01) (phi - phi_end)), phi_in = phi_end + 1, pi_in = -V'/V(phi_in),
+    constant noise H/2pi, dN = 1e-3, 64 linear bins over deltaN in [-5, 5] sigma."""
+    alpha = math.sqrt(2.0 * EPS_PLUS)
+    return Workload(
+        name="linear_slow_roll", kind=POT_PIECEWISE_LINEAR, V0=V0, phi_T=0.0,
+        A_plus=V0 * alpha, A_minus=V0 * alpha, phi_in=1.0, pi_in=-alpha / (1.0 + alpha), phi_end=0.0,
+        noise="const", noise_S=NOISE_S_HUBBLE, noise_tan=0.0, dN=1e-3, n_traj=n_traj, seed=seed,
+        bins_kind=BINS_LINEAR, n_bins=64, lo=-5 * SIGMA_LIN_LINEAR, hi=5 * SIGMA_LIN_LINEAR,
+        N_ref=N_REF_LINEAR)
+
+
+def exponential_ig(n_traj: int = 20_000, seed: int = 7, alpha: float = 0.5, S: float = 0.05,
+                   delta_phi: float = 1.0, dN: float = 1e-4, A_bias: float = 0.0) -> Workload:
+    """V = V0 exp(alpha (phi - phi_end)) with pi_in = -alpha (an exact fixed point of the
+    drift) and constant noise S along phi only: phi is a Brownian motion with drift -alpha,
+    so N is inverse-Gaussian with mean delta_phi/alpha and shape delta_phi^2/S^2."""
+    return Workload(
+        name="exponential_ig", kind=POT_EXPONENTIAL, V0=V0, phi_T=0.0, A_plus=alpha, A_minus=0.0,
+        phi_in=delta_phi, pi_in=-alpha, phi_end=0.0, noise="const", noise_S=S, noise_tan=0.0,
+        dN=dN, n_traj=n_traj, seed=seed, bias_kind=BIAS_CONST if A_bias else BIAS_NONE,
+        A_bias=A_bias, bins_kind=BINS_LINEAR, n_bins=64,
+        lo=-1.0, hi=3.0, N_ref=delta_phi / alpha)
+
+
+def srusr_bessel(n_traj: int = 1_000_000, seed: int = 2) -> Workload:
+    """Piecewise-linear slow roll -> ultra-slow roll, phi_T = phi_e = 0 = phi_in,
+    pi_in = -sqrt(2 eps_+) (the slow-roll value at phi_e), phi_end = -DELTA_E,
+    Bessel-ansatz noise table (4096 nodes, sigma = 1), FP64, dN = 1e-4, no bias."""
+    return Workload(
+        name="srusr_bessel_fp64", kind=POT_PIECEWISE_LINEAR, V0=V0, phi_T=0.0,
+        A_plus=A_PLUS, A_minus=A_MINUS, phi_in=0.0, pi_in=-math.sqrt(2.0 * EPS_PLUS),
+        phi_end=-DELTA_E, noise="bessel", sigma=1.0, table_n=TABLE_N,
+        table_lo=TABLE_PHI_LO, table_hi=TABLE_PHI_HI, dN=1e-4, n_traj=n_traj, seed=seed,
+        bins_kind=BINS_LINEAR, n_bins=64, lo=-5 * SIGMA_LIN_SRUSR, hi=5 * SIGMA_LIN_SRUSR,
+        N_ref=N_REF_SRUSR)
+
+
+def srusr_is_fp32(A_bias: float = 2.0, n_traj: int = 100_000_000, seed: int = 3) -> Workload:
+    """The SR->USR problem with FP32 state and FP64 log-weights, constant IS bias, weighted
+    P(deltaN) on 256 log-spaced bins over deltaN in [sigma/2, 8 sigma]."""
+    return srusr_bessel(n_traj=n_traj, seed=seed).with_(
+        name=f"srusr_is_fp32_A{A_bias:g}", precision=1, bias_kind=BIAS_CONST, A_bias=A_bias,
+        bins_kind=BINS_LOG, n_bins=256, lo=0.5 * SIGMA_LIN_SRUSR, hi=8 * SIGMA_LIN_SRUSR)
+
+
+def batched_instances(n_inst: int = 64, seed: int = 4, n_min: float = 1e5, n_max: float = 1e7,
+                      max_steps: int = 1 << 20) -> list[Workload]:
+    """Instances of the SR->USR problem with eps_- log-uniform in [1e-10, 1e-6] and
+    phi_e - phi_end uniform in [0.1, 1]; trajectory counts log-uniform in [n_min, n_max];
+    a per-instance step cap censors the (very long) flat-branch runs."""
+    rng = np.random.default_rng(seed)
+    eps_m = 10.0 ** rng.uniform(-10, -6, n_inst)
+    delta = rng.uniform(0.1, 1.0, n_inst)
+    counts = np.round(10.0 ** rng.uniform(math.log10(n_min), math.log10(n_max), n_inst)).astype(np.int64)
+    out = []
+    for i in range(n_inst):
+        w = srusr_bessel(n_traj=int(counts[i]), seed=seed).with_(
+            name=f"batched_{i}", A_minus=V0 * math.sqrt(2.0 * eps_m[i]), phi_end=-float(delta[i]),
+            max_steps=int(max_steps), extra={"instance": i, "eps_minus": float(eps_m[i])})
+        out.append(w)
+    return out
