@@ -1,0 +1,227 @@
+"""Thin ctypes binding of the C ABI in include/fpt.h (argument marshalling only).
+
+Every step of the method runs in the HIP kernels of libfpt.so; this module only
+converts Python/numpy/torch arguments to the C structures and back.  It fails
+loudly when the library has not been built: there is no fallback path.
+
+torch is imported first so that the HIP runtime torch ships with is the one the
+library binds to (both carry the soname libamdhip64.so.7); device buffers and
+streams are torch's.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import numpy as np
+
+try:  # torch supplies device memory and streams; import it before loading the library
+    import torch  # noqa: F401
+except ImportError:  # pragma: no cover - torch is part of the image
+    torch = None
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(PKG)
+LIB_PATH = os.path.join(PKG, "libfpt.so")
+HEADER = os.path.join(ROOT, "include", "fpt.h")
+
+FPT_OK, FPT_EINVAL, FPT_ENOMEM, FPT_EHIP, FPT_ESTATE, FPT_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
+FPT_POT_PIECEWISE_LINEAR, FPT_POT_EXPONENTIAL = 0, 1
+FPT_BIAS_NONE, FPT_BIAS_CONST, FPT_BIAS_MLP = 0, 1, 2
+FPT_FP64, FPT_FP32_STATE = 0, 1
+FPT_BINS_LINEAR, FPT_BINS_LOG = 0, 1
+FPT_FLAG_CENSORED = 0x80000000
+FPT_FLAG_ENDED_EARLY = 0x40000000
+FPT_STEP_MASK = 0x3FFFFFFF
+FPT_MAX_STEPS = 0x3FFFFFFF
+FPT_MAX_TABLE = 4096
+FPT_MAX_BINS = 1024
+FPT_MLP_NPARAM = 4482
+
+_dp = ctypes.POINTER(ctypes.c_double)
+_fp = ctypes.POINTER(ctypes.c_float)
+_u32p = ctypes.POINTER(ctypes.c_uint32)
+_u64p = ctypes.POINTER(ctypes.c_uint64)
+
+
+class fpt_potential(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("V0", ctypes.c_double), ("phi_T", ctypes.c_double),
+                ("A_plus", ctypes.c_double), ("A_minus", ctypes.c_double), ("phi_in", ctypes.c_double),
+                ("pi_in", ctypes.c_double), ("phi_end", ctypes.c_double)]
+
+
+class fpt_noise_table(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("phi_lo", ctypes.c_double), ("phi_hi", ctypes.c_double),
+                ("S", _dp), ("tan_theta", _dp)]
+
+
+class fpt_bias(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("A", ctypes.c_double), ("mlp_params", _fp),
+                ("norm", ctypes.c_double * 4), ("mlp_every", ctypes.c_int32)]
+
+
+class fpt_options(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int32), ("bins_kind", ctypes.c_int32), ("n_bins", ctypes.c_int32),
+                ("lo", ctypes.c_double), ("hi", ctypes.c_double), ("N_ref", ctypes.c_double),
+                ("max_steps", ctypes.c_int64), ("instance", ctypes.c_uint32), ("block_size", ctypes.c_int32),
+                ("blocks_per_cu", ctypes.c_int32), ("chunk", ctypes.c_int32)]
+
+
+class fpt_hist(ctypes.Structure):
+    _fields_ = [("n_traj", ctypes.c_uint64), ("n_censored", ctypes.c_uint64), ("n_ended_early", ctypes.c_uint64),
+                ("n_steps_total", ctypes.c_uint64), ("sum_w", ctypes.c_double), ("sum_w2", ctypes.c_double),
+                ("sum_wN", ctypes.c_double), ("sum_wN2", ctypes.c_double), ("count", _u64p),
+                ("sum_w_bin", _dp), ("sum_w2_bin", _dp), ("sum_lnw_bin", _dp), ("sum_lnw2_bin", _dp)]
+
+
+class FptError(RuntimeError):
+    def __init__(self, status: int, where: str, detail: str):
+        super().__init__(f"{where}: {detail} (status {status})")
+        self.status = status
+
+
+_lib = None
+
+
+def header_functions() -> list[str]:
+    """Names of the functions include/fpt.h declares."""
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(fpt_[a-z0-9_]+)\s*\(", text)))
+
+
+def load():
+    """Load libfpt.so (raises if it is missing: the product has no CPU path)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build() (hipcc, gfx950)")
+    L = ctypes.CDLL(LIB_PATH)
+    P = ctypes.POINTER
+    L.fpt_create.argtypes = [P(fpt_potential), P(fpt_noise_table), P(fpt_bias), P(fpt_options),
+                             P(ctypes.c_void_p)]
+    L.fpt_run.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_double, ctypes.c_uint64, ctypes.c_uint64,
+                          ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+    L.fpt_histogram.argtypes = [ctypes.c_void_p, P(fpt_hist)]
+    L.fpt_reset.argtypes = [ctypes.c_void_p]
+    L.fpt_destroy.argtypes = [ctypes.c_void_p]
+    L.fpt_destroy.restype = None
+    L.fpt_last_kernel_ms.argtypes = [ctypes.c_void_p, _dp]
+    L.fpt_strerror.argtypes = [ctypes.c_int]
+    L.fpt_strerror.restype = ctypes.c_char_p
+    L.fpt_last_error.argtypes = []
+    L.fpt_last_error.restype = ctypes.c_char_p
+    L.fpt_noise_table_bessel.argtypes = [P(fpt_potential), ctypes.c_double, ctypes.c_int32, ctypes.c_double,
+                                         ctypes.c_double, _dp, _dp]
+    for name in ("fpt_create", "fpt_run", "fpt_histogram", "fpt_reset", "fpt_last_kernel_ms",
+                 "fpt_noise_table_bessel"):
+        getattr(L, name).restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def _check(rc: int, where: str):
+    if rc != FPT_OK:
+        L = load()
+        raise FptError(rc, where, f"{L.fpt_strerror(rc).decode()}: {L.fpt_last_error().decode()}")
+
+
+def _ptr(t):
+    """Device pointer of a torch tensor (or None / an int address)."""
+    if t is None:
+        return None
+    if isinstance(t, int):
+        return t
+    return t.data_ptr()
+
+
+def _stream_handle(stream):
+    if stream is None:
+        return None
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+def make_potential(kind, V0, phi_T, A_plus, A_minus, phi_in, pi_in, phi_end) -> fpt_potential:
+    return fpt_potential(kind, V0, phi_T, A_plus, A_minus, phi_in, pi_in, phi_end)
+
+
+def fpt_noise_table_bessel(pot: fpt_potential, sigma: float, n: int, phi_lo: float, phi_hi: float):
+    """Noise table of eq. (covariance_constant_nu) computed by the library's device kernel."""
+    S = np.empty(n, dtype=np.float64)
+    t = np.empty(n, dtype=np.float64)
+    _check(load().fpt_noise_table_bessel(ctypes.byref(pot), sigma, n, phi_lo, phi_hi,
+                                         S.ctypes.data_as(_dp), t.ctypes.data_as(_dp)), "fpt_noise_table_bessel")
+    return S, t
+
+
+class Context:
+    """Owns one fpt_ctx; mirrors fpt_run / fpt_histogram / fpt_reset / fpt_destroy."""
+
+    def __init__(self, pot: fpt_potential, S, tan_theta, phi_lo: float, phi_hi: float, *, bias_kind=FPT_BIAS_NONE,
+                 A=0.0, mlp_params=None, norm=(0.0, 1.0, 0.0, 1.0), mlp_every=1, precision=FPT_FP64,
+                 bins_kind=FPT_BINS_LINEAR, n_bins=64, lo=-1.0, hi=1.0, N_ref=0.0, max_steps=FPT_MAX_STEPS,
+                 instance=0, block_size=0, blocks_per_cu=0, chunk=0):
+        L = load()
+        self._S = np.ascontiguousarray(S, dtype=np.float64)
+        self._t = np.ascontiguousarray(tan_theta, dtype=np.float64)
+        table = fpt_noise_table(len(self._S), phi_lo, phi_hi, self._S.ctypes.data_as(_dp),
+                                self._t.ctypes.data_as(_dp))
+        self._mlp = (np.ascontiguousarray(mlp_params, dtype=np.float32) if mlp_params is not None else None)
+        bias = fpt_bias(bias_kind, A, self._mlp.ctypes.data_as(_fp) if self._mlp is not None else None,
+                        (ctypes.c_double * 4)(*norm), mlp_every)
+        self.n_bins = int(n_bins)
+        opts = fpt_options(precision, bins_kind, n_bins, lo, hi, N_ref, max_steps, instance, block_size,
+                           blocks_per_cu, chunk)
+        h = ctypes.c_void_p()
+        _check(L.fpt_create(ctypes.byref(pot), ctypes.byref(table), ctypes.byref(bias), ctypes.byref(opts),
+                            ctypes.byref(h)), "fpt_create")
+        self._h = h
+        self._lib = L
+
+    @property
+    def handle(self):
+        return self._h
+
+    def run(self, n_traj: int, dN: float, seed: int, traj_offset: int = 0, stream=None, d_N=None, d_lnw=None,
+            d_steps=None):
+        _check(self._lib.fpt_run(self._h, n_traj, dN, seed, traj_offset, _stream_handle(stream), _ptr(d_N),
+                                 _ptr(d_lnw), _ptr(d_steps)), "fpt_run")
+
+    def histogram(self) -> dict:
+        nb = self.n_bins + 2
+        arrs = {"count": np.zeros(nb, dtype=np.uint64), "sum_w": np.zeros(nb), "sum_w2": np.zeros(nb),
+                "sum_lnw": np.zeros(nb), "sum_lnw2": np.zeros(nb)}
+        h = fpt_hist()
+        h.count = arrs["count"].ctypes.data_as(_u64p)
+        h.sum_w_bin = arrs["sum_w"].ctypes.data_as(_dp)
+        h.sum_w2_bin = arrs["sum_w2"].ctypes.data_as(_dp)
+        h.sum_lnw_bin = arrs["sum_lnw"].ctypes.data_as(_dp)
+        h.sum_lnw2_bin = arrs["sum_lnw2"].ctypes.data_as(_dp)
+        _check(self._lib.fpt_histogram(self._h, ctypes.byref(h)), "fpt_histogram")
+        arrs.update(n_traj=h.n_traj, n_censored=h.n_censored, n_ended_early=h.n_ended_early,
+                    n_steps_total=h.n_steps_total, sum_w_total=h.sum_w, sum_w2_total=h.sum_w2, sum_wN=h.sum_wN,
+                    sum_wN2=h.sum_wN2)
+        return arrs
+
+    def reset(self):
+        _check(self._lib.fpt_reset(self._h), "fpt_reset")
+
+    def last_kernel_ms(self) -> float:
+        ms = ctypes.c_double()
+        _check(self._lib.fpt_last_kernel_ms(self._h, ctypes.byref(ms)), "fpt_last_kernel_ms")
+        return ms.value
+
+    def destroy(self):
+        if getattr(self, "_h", None):
+            self._lib.fpt_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass

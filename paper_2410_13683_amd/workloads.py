@@ -87,7 +87,7 @@ class Workload:
     lo: float = -1.0
     hi: float = 1.0
     N_ref: float = 0.0
-    max_steps: int = 0x3FFFFFFF
+    max_steps: int = 1 << 24         # far above every workload here (<= 1.2e5 steps per trajectory)
     extra: dict = field(default_factory=dict)
 
     def with_(self, **kw) -> "Workload":

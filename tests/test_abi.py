@@ -1,0 +1,99 @@
+"""CPU checks of the C ABI: the library loads, exports every function that
+include/fpt.h declares, the ctypes mirror has the C struct layout, and invalid
+arguments are rejected on the host before any device call."""
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+import pytest
+
+from paper_2410_13683_amd import fpt
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(fpt.LIB_PATH):
+        pytest.fail("libfpt.so is not built (run __graft_entry__.build())")
+    return fpt.load()
+
+
+def test_exports_every_declared_function(lib):
+    names = fpt.header_functions()
+    assert "fpt_create" in names and "fpt_run" in names and "fpt_histogram" in names
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_struct_layout_matches_c(tmp_path):
+    exe = tmp_path / "abi_layout"
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"),
+                    os.path.join(ROOT, "tests", "helpers", "abi_layout.c"), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout
+    for line in out.strip().splitlines():
+        key, val = line.split()
+        sname, field = key.split(".")
+        cls = getattr(fpt, sname)
+        got = ctypes.sizeof(cls) if field == "__size__" else getattr(cls, field).offset
+        assert got == int(val), (key, got, val)
+
+
+def _pot(**kw):
+    d = dict(kind=0, V0=1e-10, phi_T=0.0, A_plus=1.4e-11, A_minus=1.4e-14, phi_in=0.0, pi_in=-0.14,
+             phi_end=-0.05)
+    d.update(kw)
+    return fpt.make_potential(**d)
+
+
+@pytest.mark.parametrize("bad", [
+    dict(pot=dict(phi_in=-0.1)),              # phi_in <= phi_end
+    dict(pot=dict(V0=float("nan"))),
+    dict(pot=dict(V0=-1.0)),
+    dict(pot=dict(kind=7)),
+    dict(S=[-1e-6]),                           # negative noise
+    dict(S=[]),                                # empty table
+    dict(opts=dict(n_bins=0)),
+    dict(opts=dict(bins_kind=1, lo=0.0)),      # log bins need lo > 0
+    dict(opts=dict(max_steps=0)),
+    dict(opts=dict(block_size=100)),
+    dict(opts=dict(chunk=6)),
+    dict(bias=dict(kind=1, A=float("inf"))),
+])
+def test_invalid_arguments_are_rejected(lib, bad):
+    pot = _pot(**bad.get("pot", {}))
+    S = np.ascontiguousarray(bad.get("S", [1e-6]), dtype=np.float64)
+    t = np.zeros(max(len(S), 1))
+    tab = fpt.fpt_noise_table(len(S), 0.0, 0.0, S.ctypes.data_as(fpt._dp), t.ctypes.data_as(fpt._dp))
+    bd = dict(kind=0, A=0.0)
+    bd.update(bad.get("bias", {}))
+    bias = fpt.fpt_bias(bd["kind"], bd["A"], None, (ctypes.c_double * 4)(0, 1, 0, 1), 1)
+    od = dict(precision=0, bins_kind=0, n_bins=8, lo=-1.0, hi=1.0, N_ref=0.0, max_steps=1000, instance=0,
+              block_size=0, blocks_per_cu=0, chunk=0)
+    od.update(bad.get("opts", {}))
+    opts = fpt.fpt_options(**od)
+    h = ctypes.c_void_p()
+    rc = lib.fpt_create(ctypes.byref(pot), ctypes.byref(tab), ctypes.byref(bias), ctypes.byref(opts),
+                        ctypes.byref(h))
+    assert rc == fpt.FPT_EINVAL, (rc, lib.fpt_last_error())
+    assert not h.value
+    assert lib.fpt_last_error()
+
+
+def test_table_generator_rejects_bad_sizes(lib):
+    S = np.zeros(4)
+    t = np.zeros(4)
+    pot = _pot()
+    for n in (0, fpt.FPT_MAX_TABLE + 1):
+        rc = lib.fpt_noise_table_bessel(ctypes.byref(pot), 1.0, n, -0.1, 0.1, S.ctypes.data_as(fpt._dp),
+                                        t.ctypes.data_as(fpt._dp))
+        assert rc == fpt.FPT_EINVAL
+    rc = lib.fpt_noise_table_bessel(ctypes.byref(pot), -1.0, 4, -0.1, 0.1, S.ctypes.data_as(fpt._dp),
+                                    t.ctypes.data_as(fpt._dp))
+    assert rc == fpt.FPT_EINVAL
+
+
+def test_strerror(lib):
+    assert lib.fpt_strerror(0) == b"success"
+    assert lib.fpt_strerror(fpt.FPT_EINVAL) == b"invalid argument"

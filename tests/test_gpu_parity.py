@@ -1,0 +1,234 @@
+"""GPU parity of the HIP path against the CPU oracle, through the C ABI.
+
+FP64 state: per trajectory, N within 1e-9 relative and the same crossing step
+(a step may differ only at a floating-point near-tie with phi_end, where N
+still agrees), ln w within 1e-9 (relative to 1 + |ln w|).  FP32 state: coupled
+streams (same seeds and trajectories); per-trajectory N within a bound set by
+FP32 rounding and the weighted and unweighted KS distance of P(deltaN) below
+1e-3.  Sizes span several waves and a ragged tail; full-size runs are checked
+on sampled trajectories the oracle computes one by one.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+from oracle import oracle as orc  # noqa: E402
+from paper_2410_13683_amd import fpt  # noqa: E402
+from paper_2410_13683_amd import workloads as W  # noqa: E402
+from tests._glue import oracle_problem, oracle_run, oracle_table  # noqa: E402
+from tests._gpu import gpu_context, gpu_run, gpu_table  # noqa: E402
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def assert_fp64_parity(gpu, ora, max_step_mismatch=0.002):
+    Ng, lg, sg = gpu
+    No, lo_, so = ora
+    assert Ng.shape == No.shape
+    flags = orc.FLAG_CENSORED | orc.FLAG_ENDED_EARLY
+    assert np.array_equal(sg & flags, so & flags)
+    fin = (so & flags) == 0
+    same = sg == so
+    assert (1.0 - same.mean()) <= max_step_mismatch, f"{(~same).sum()} crossing steps differ"
+    diff_steps = np.abs((sg & orc.STEP_MASK).astype(np.int64) - (so & orc.STEP_MASK).astype(np.int64))
+    assert diff_steps.max(initial=0) <= 1
+    rel = np.abs(Ng[fin] - No[fin]) / np.abs(No[fin])
+    assert rel.max(initial=0.0) <= 1e-9, rel.max()
+    ok = same & fin
+    assert np.all(np.abs(lg[ok] - lo_[ok]) <= 1e-9 * (1.0 + np.abs(lo_[ok])))
+
+
+def test_noise_table_matches_oracle():
+    say("table: srusr 4096 nodes")
+    for w in (W.srusr_bessel(), W.srusr_bessel().with_(sigma=0.01)):
+        pot = fpt.make_potential(w.kind, w.V0, w.phi_T, w.A_plus, w.A_minus, w.phi_in, w.pi_in, w.phi_end)
+        S, t, _, _ = gpu_table(w, pot)
+        So, to, _, _ = oracle_table(w)
+        np.testing.assert_allclose(S, So, rtol=1e-13)
+        np.testing.assert_allclose(t, to, rtol=1e-12, atol=1e-15)
+    # exponential potential: nu = 3/2 exactly (de Sitter noise)
+    pot = fpt.make_potential(1, 1e-10, 0.0, 0.4, 0.0, 1.0, -0.4, 0.0)
+    S, t = fpt.fpt_noise_table_bessel(pot, 1.0, 5, -1.0, 1.0)
+    So, to = orc.noise_table_bessel(1, 1e-10, 0.0, 0.4, 0.0, 1.0, 5, -1.0, 1.0)
+    np.testing.assert_allclose(S, So, rtol=1e-13)
+    assert np.all(t == 0.0)
+
+
+def test_fp64_linear_slow_roll_full_size():
+    """Linear slow roll, constant noise, 1e4 trajectories, dN = 1e-3: per trajectory and histogram."""
+    w = W.linear_slow_roll()
+    say(f"fp64 {w.name} n={w.n_traj}")
+    gpu, hist = gpu_run(w)
+    ora = oracle_run(w)
+    assert_fp64_parity(gpu, ora)
+    assert np.all(gpu[1] == 0.0)
+    h_o = orc.histogram(*ora, w.N_ref, w.bins_kind, w.n_bins, w.lo, w.hi)
+    assert hist["n_traj"] == w.n_traj and hist["n_censored"] == 0 and hist["n_ended_early"] == 0
+    assert int(hist["count"].sum()) == w.n_traj
+    # bins can differ only for trajectories whose deltaN sits within rounding of an edge
+    assert np.abs(hist["count"].astype(np.int64) - h_o["count"].astype(np.int64)).sum() <= 2
+    assert hist["n_steps_total"] == h_o["n_steps_total"] or abs(
+        int(hist["n_steps_total"]) - int(h_o["n_steps_total"])) <= 2
+    np.testing.assert_allclose(hist["sum_w_total"], w.n_traj, rtol=1e-12)
+    np.testing.assert_allclose(hist["sum_wN"], np.sum(gpu[0]), rtol=1e-12)
+
+
+@pytest.mark.parametrize("A_bias", [0.0, 2.0])
+def test_fp64_srusr_bessel_ragged(A_bias):
+    """SR -> USR with the Bessel table, a ragged trajectory count and a non-zero offset."""
+    w = W.srusr_bessel(seed=5).with_(bias_kind=W.BIAS_CONST if A_bias else W.BIAS_NONE, A_bias=A_bias)
+    n, off = 1237, 1_000_003
+    say(f"fp64 srusr A={A_bias} n={n} offset={off}")
+    gpu, hist = gpu_run(w, n_traj=n, traj_offset=off)
+    ora = oracle_run(w, n_traj=n, traj_offset=off)
+    assert_fp64_parity(gpu, ora)
+    if A_bias:
+        assert np.std(gpu[1]) > 0.1
+    assert hist["n_traj"] == n
+
+
+def test_fp64_exponential_is_parity_and_tail():
+    """Exponential potential with constant bias: parity, and the weighted tail against the
+    inverse-Gaussian closed form at a size the oracle does not reach."""
+    w = W.exponential_ig(n_traj=4096, A_bias=2.6, seed=17)
+    say("fp64 exponential IS parity n=4096")
+    gpu, _ = gpu_run(w)
+    ora = oracle_run(w)
+    assert_fp64_parity(gpu, ora)
+    from tests.test_oracle_dynamics import _ig_params, _ig_sf
+    mu, lam = _ig_params(w)
+    sd = math.sqrt(mu**3 / lam)
+    n_big = 1_000_000
+    say(f"fp64 exponential IS tail n={n_big}")
+    (N, lnw, st), _ = gpu_run(w, n_traj=n_big)
+    for k in (6.0, 8.0, 9.0):
+        x = mu + k * sd
+        wts = np.exp(lnw) * (N > x)
+        est, se, exact = wts.mean(), wts.std() / math.sqrt(n_big), _ig_sf(x, mu, lam)
+        assert abs(est / exact - 1.0) < 0.05 + 4 * se / exact, (k, est, exact, se)
+
+
+def test_launch_configuration_does_not_change_results():
+    w = W.srusr_bessel(seed=9).with_(bias_kind=W.BIAS_CONST, A_bias=1.0)
+    n = 700
+    ref = None
+    for prec in (0, 1):
+        ref = None
+        for cfg in [dict(), dict(block_size=64, blocks_per_cu=1, chunk=4), dict(block_size=1024, chunk=256),
+                    dict(block_size=128, blocks_per_cu=3, chunk=36)]:
+            say(f"launch config prec={prec} {cfg}")
+            (N, lnw, st), _ = gpu_run(w.with_(precision=prec), n_traj=n, **cfg)
+            if ref is None:
+                ref = (N, lnw, st)
+            else:
+                assert np.array_equal(N, ref[0]) and np.array_equal(lnw, ref[1]) and np.array_equal(st, ref[2])
+
+
+def test_split_runs_equal_one_run():
+    w = W.linear_slow_roll(seed=4).with_(bias_kind=W.BIAS_CONST, A_bias=0.5)
+    say("split runs")
+    (N, lnw, st), h1 = gpu_run(w, n_traj=3000)
+    ctx = gpu_context(w)
+    (Na, la, sa), _ = gpu_run(w, n_traj=1000, ctx=ctx)
+    (Nb, lb, sb), h2 = gpu_run(w, n_traj=2000, traj_offset=1000, ctx=ctx)
+    ctx.destroy()
+    assert np.array_equal(N, np.concatenate([Na, Nb])) and np.array_equal(st, np.concatenate([sa, sb]))
+    assert np.array_equal(lnw, np.concatenate([la, lb]))
+    assert np.array_equal(h1["count"], h2["count"]) and h2["n_traj"] == 3000
+    np.testing.assert_allclose(h2["sum_w"], h1["sum_w"], rtol=1e-12)
+
+
+def test_edge_cases():
+    w = W.linear_slow_roll(seed=3)
+    say("edge: empty run")
+    ctx = gpu_context(w)
+    ctx.run(0, w.dN, w.seed)
+    h = ctx.histogram()
+    assert h["n_traj"] == 0 and int(h["count"].sum()) == 0
+    ctx.destroy()
+    say("edge: one trajectory")
+    gpu, _ = gpu_run(w, n_traj=1)
+    assert_fp64_parity(gpu, oracle_run(w, n_traj=1))
+    say("edge: censoring at max_steps")
+    for prec in (0, 1):
+        wc = w.with_(max_steps=1001, precision=prec)
+        (N, lnw, st), h = gpu_run(wc, n_traj=130)
+        assert np.all(st == (1001 | orc.FLAG_CENSORED)) and np.all(np.isnan(N))
+        assert h["n_censored"] == 130 and int(h["count"].sum()) == 0 and h["n_steps_total"] == 130 * 1001
+    say("edge: inflation ends before phi_end")
+    we = W.exponential_ig(n_traj=70).with_(pi_in=-1.6, A_plus=0.1, noise_S=1e-6)
+    for prec in (0, 1):
+        (N, lnw, st), h = gpu_run(we.with_(precision=prec))
+        assert np.all(st == (1 | orc.FLAG_ENDED_EARLY)) and h["n_ended_early"] == 70
+        np.testing.assert_allclose(N, we.dN)
+    say("edge: run errors")
+    ctx = gpu_context(w)
+    with pytest.raises(fpt.FptError):
+        ctx.run(10, -1.0, 1)
+    with pytest.raises(fpt.FptError):
+        ctx.run(10, float("nan"), 1)
+    ctx.destroy()
+
+
+def _ks(a, b, wa=None, wb=None):
+    xs = np.sort(np.concatenate([a, b]))
+    def cdf(x, wt):
+        o = np.argsort(x)
+        c = np.cumsum(np.ones_like(x) if wt is None else wt[o])
+        c /= c[-1]
+        return np.concatenate([[0.0], c])[np.searchsorted(x[o], xs, side="right")]
+    return np.max(np.abs(cdf(a, wa) - cdf(b, wb)))
+
+
+@pytest.mark.parametrize("A_bias", [0.0, 2.0])
+def test_fp32_state_coupled_with_oracle(A_bias):
+    """FP32 state vs the FP64 oracle on the same random streams."""
+    w = W.srusr_bessel(seed=13).with_(precision=1, bias_kind=W.BIAS_CONST if A_bias else W.BIAS_NONE,
+                                      A_bias=A_bias)
+    n = 4000
+    say(f"fp32 coupled A={A_bias} n={n}")
+    (Ng, lg, sg), _ = gpu_run(w, n_traj=n)
+    No, lo_, so = oracle_run(w, n_traj=n)
+    flags = orc.FLAG_CENSORED | orc.FLAG_ENDED_EARLY
+    assert np.all((sg & flags) == 0) and np.all((so & flags) == 0)
+    dn = np.abs(Ng - No)
+    say(f"  max |N32 - N64| = {dn.max():.3e}, median {np.median(dn):.3e}")
+    assert dn.max() < 2e-4
+    assert _ks(Ng, No) < 1e-3
+    if A_bias:
+        assert np.max(np.abs(lg - lo_)) < 1e-3
+        assert _ks(Ng, No, np.exp(lg), np.exp(lo_)) < 1e-3
+
+
+def test_full_size_srusr_fp64_sampled():
+    """The full SR -> USR FP64 workload (1e6 trajectories) in the default launch configuration,
+    checked on trajectories sampled across the range, plus histogram totals."""
+    w = W.srusr_bessel()
+    say(f"fp64 full size n={w.n_traj}")
+    (N, lnw, st), hist = gpu_run(w)
+    idx = np.unique(np.concatenate([np.linspace(0, w.n_traj - 1, 150).astype(np.int64),
+                                    [w.n_traj - 1, w.n_traj - 2]]))
+    for i in idx[:: max(1, len(idx) // 150)]:
+        No, lo_, so = oracle_run(w, n_traj=1, traj_offset=int(i))
+        assert_fp64_parity((N[i:i + 1], lnw[i:i + 1], st[i:i + 1]), (No, lo_, so), max_step_mismatch=1.0)
+    assert hist["n_traj"] == w.n_traj and int(hist["count"].sum()) == w.n_traj
+    assert hist["n_steps_total"] == int(np.sum((st & orc.STEP_MASK).astype(np.uint64)))
+    d = N - w.N_ref
+    say(f"  mean deltaN {d.mean():.4e} sd {d.std():.4e}")
+    assert abs(d.std() / W.SIGMA_LIN_SRUSR - 1.0) < 0.05
