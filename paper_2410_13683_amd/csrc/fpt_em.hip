@@ -24,7 +24,7 @@
 // Two state precisions: FP64 (phi, pi, ln w in double) and FP32 state (the
 // distance x = phi - phi_end and pi each held as an unevaluated pair of floats
 // hi + lo, increments computed in FP32 from the hi parts, uniforms
-// ((w >> 8) + 1/2) 2^-24 and hardware sin/cos/log; ln w, the crossing
+// fl32(w) 2^-32 + 2^-33 and hardware sin/cos/log; ln w, the crossing
 // interpolation and the histogram stay FP64).
 #include "internal.hpp"
 
@@ -68,13 +68,15 @@ __device__ __forceinline__ void box_muller64(uint32_t wa, uint32_t wb, double &z
     zb = rho * s;
 }
 
-// Box-Muller in FP32 on uniforms ((w >> 8) + 1/2) 2^-24 (exact in float).
-// v_log_f32 returns log2, v_sin_f32 / v_cos_f32 take their argument in turns.
+// Box-Muller in FP32 on uniforms fl32(w) 2^-32 + 2^-33: the same uniform as the
+// FP64 path, rounded to 24 significant bits (relative, not absolute, resolution,
+// so the radius stays accurate for small u).  Never 0; at most 1.0f, where the
+// radius is 0.  v_log_f32 returns log2, v_sin_f32 / v_cos_f32 take turns.
 __device__ __forceinline__ void box_muller32(uint32_t wa, uint32_t wb, float &za, float &zb)
 {
-    const float ua = fmaf((float)(wa >> 8), 0x1p-24f, 0x1p-25f);
-    const float ub = fmaf((float)(wb >> 8), 0x1p-24f, 0x1p-25f);
-    const float rho = __builtin_sqrtf(-1.3862943611198906f * __builtin_amdgcn_logf(ua));  // -2 ln u
+    const float ua = fmaf((float)wa, 0x1p-32f, 0x1p-33f);
+    const float ub = fmaf((float)wb, 0x1p-32f, 0x1p-33f);
+    const float rho = __builtin_sqrtf(fmaxf(-1.3862943611198906f * __builtin_amdgcn_logf(ua), 0.0f));  // -2 ln u
     za = rho * __builtin_amdgcn_cosf(ub);
     zb = rho * __builtin_amdgcn_sinf(ub);
 }

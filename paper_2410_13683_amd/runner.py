@@ -1,0 +1,57 @@
+"""Build a library context for a workload description and run it.
+
+Argument marshalling only: the noise table comes from the library's own device
+kernel (fpt_noise_table_bessel) and every trajectory step runs in libfpt.so.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import fpt
+from .workloads import Workload
+
+
+def potential_of(w: Workload) -> fpt.fpt_potential:
+    return fpt.make_potential(w.kind, w.V0, w.phi_T, w.A_plus, w.A_minus, w.phi_in, w.pi_in, w.phi_end)
+
+
+def table_of(w: Workload, pot=None):
+    """(S, tan_theta, phi_lo, phi_hi) of the workload's noise."""
+    if w.noise == "const":
+        return np.array([w.noise_S]), np.array([w.noise_tan]), 0.0, 0.0
+    if w.noise == "bessel":
+        S, t = fpt.fpt_noise_table_bessel(pot or potential_of(w), w.sigma, w.table_n, w.table_lo, w.table_hi)
+        return S, t, w.table_lo, w.table_hi
+    raise ValueError(f"unknown noise kind {w.noise!r}")
+
+
+def context_for(w: Workload, **overrides) -> fpt.Context:
+    pot = potential_of(w)
+    S, t, lo, hi = table_of(w, pot)
+    kw = dict(bias_kind=w.bias_kind, A=w.A_bias, precision=w.precision, bins_kind=w.bins_kind, n_bins=w.n_bins,
+              lo=w.lo, hi=w.hi, N_ref=w.N_ref, max_steps=w.max_steps, instance=w.extra.get("instance", 0))
+    kw.update(overrides)
+    return fpt.Context(pot, S, t, lo, hi, **kw)
+
+
+def tail_ess(hist: dict, n_bins: int, bins_kind: int, lo: float, hi: float, p_tail: float = 1e-10):
+    """Tail set T = bins from the lowest edge x* whose weighted tail mass
+    P(deltaN >= x*) = sum_{bins >= x*} w / n_traj is at most p_tail (overflow included).
+    Returns (x*, P(deltaN >= x*), ESS_T = (sum_T w)^2 / sum_T w^2, samples in T)."""
+    n = max(int(hist["n_traj"]), 1)
+    sw = np.asarray(hist["sum_w"], dtype=np.float64)
+    sw2 = np.asarray(hist["sum_w2"], dtype=np.float64)
+    cnt = np.asarray(hist["count"], dtype=np.float64)
+    tail = np.cumsum(sw[::-1])[::-1] / n        # tail[i] = sum over slots i.. (slot 0 = underflow)
+    if bins_kind == 0:
+        edges = lo + (hi - lo) * np.arange(n_bins + 1) / n_bins
+    else:
+        edges = lo * (hi / lo) ** (np.arange(n_bins + 1) / n_bins)
+    # slot j (1..n_bins) starts at edges[j-1]; slot n_bins+1 (overflow) starts at hi
+    for j in range(1, n_bins + 2):
+        if tail[j] <= p_tail and tail[j] > 0:
+            s_w, s_w2, c = sw[j:].sum(), sw2[j:].sum(), cnt[j:].sum()
+            ess = s_w * s_w / s_w2 if s_w2 > 0 else 0.0
+            x = edges[j - 1] if j <= n_bins else hi
+            return float(x), float(tail[j]), float(ess), int(c)
+    return None, 0.0, 0.0, 0
