@@ -208,9 +208,9 @@ extern "C" int fpt_create(const fpt_potential *pot, const fpt_noise_table *table
     int lds_max = 0;
     if (e == hipSuccess) e = hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device);
     c->lds_per_block_max = (size_t)lds_max;
-    // device memory: FP64 table (2 nt), FP32 table (2 nt floats), cursor, accumulators
+    // device memory: FP64 table (nt x double2), FP32 table (nt x float4), cursor, accumulators
     const size_t off_tab32 = sizeof(double) * 2 * nt;
-    const size_t off_cursor = (off_tab32 + sizeof(float) * 2 * nt + 255) & ~size_t(255);
+    const size_t off_cursor = (off_tab32 + sizeof(float) * 4 * nt + 255) & ~size_t(255);
     const size_t off_acc = off_cursor + 256;
     const size_t total = off_acc + acc_bytes(o.n_bins);
     if (e == hipSuccess) e = hipMalloc(&c->d_mem, total);
@@ -219,16 +219,22 @@ extern "C" int fpt_create(const fpt_potential *pot, const fpt_noise_table *table
         return hip_fail(e, "fpt_create device setup");
     }
     std::vector<double> h64(2 * nt);
-    std::vector<float> h32(2 * nt);
+    std::vector<float> h32(4 * nt);
+    bool all_pos = true;
     for (int i = 0; i < nt; ++i) {
-        h64[i] = table->S[i];
-        h64[nt + i] = table->tan_theta[i];
-        h32[i] = (float)table->S[i];
-        h32[nt + i] = (float)table->tan_theta[i];
+        const int k = (i + 1 < nt) ? i + 1 : i;
+        h64[2 * i] = table->S[i];
+        h64[2 * i + 1] = table->tan_theta[i];
+        const float S = (float)table->S[i], St = (float)table->tan_theta[i];
+        h32[4 * i] = S;
+        h32[4 * i + 1] = (float)table->S[k] - S;
+        h32[4 * i + 2] = St;
+        h32[4 * i + 3] = (float)table->tan_theta[k] - St;
+        all_pos = all_pos && table->S[i] > 0.0;
     }
     unsigned char *base = static_cast<unsigned char *>(c->d_mem);
     e = hipMemcpy(base, h64.data(), sizeof(double) * 2 * nt, hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemcpy(base + off_tab32, h32.data(), sizeof(float) * 2 * nt, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(base + off_tab32, h32.data(), sizeof(float) * 4 * nt, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemset(base + off_cursor, 0, 256 + acc_bytes(o.n_bins));
     if (e == hipSuccess) e = hipEventCreate(&c->ev_start);
     if (e == hipSuccess) e = hipEventCreate(&c->ev_stop);
@@ -244,10 +250,9 @@ extern "C" int fpt_create(const fpt_potential *pot, const fpt_noise_table *table
     p.n_tab = nt;
     p.phi_lo = (nt > 1) ? table->phi_lo : 0.0;
     p.inv_h = (nt > 1) ? (double)(nt - 1) / (table->phi_hi - table->phi_lo) : 0.0;
-    p.tab_S = reinterpret_cast<const double *>(base);
-    p.tab_t = reinterpret_cast<const double *>(base) + nt;
-    p.tab_Sf = reinterpret_cast<const float *>(base + off_tab32);
-    p.tab_tf = reinterpret_cast<const float *>(base + off_tab32) + nt;
+    p.tab64 = reinterpret_cast<const double2 *>(base);
+    p.tab32 = reinterpret_cast<const float4 *>(base + off_tab32);
+    p.all_S_pos = all_pos ? 1 : 0;
     p.bias_kind = b.kind;
     p.A = (b.kind == FPT_BIAS_CONST) ? b.A : 0.0;
     p.mlp = nullptr;
@@ -273,7 +278,7 @@ extern "C" int fpt_create(const fpt_potential *pot, const fpt_noise_table *table
 
 static int launch_config(fpt_ctx *c, const EmParams &p, int &grid, int &block)
 {
-    block = c->opt.block_size ? c->opt.block_size : 256;
+    block = c->opt.block_size ? c->opt.block_size : 1024;
     int per_cu = c->opt.blocks_per_cu;
     if (per_cu == 0) {
         int occ = 0;

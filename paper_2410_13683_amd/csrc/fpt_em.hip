@@ -31,11 +31,30 @@
 #include <hip/hip_runtime.h>
 #include <math.h>
 
+#include <type_traits>
+
+// Optional register budget for the Euler-Maruyama kernels (waves per SIMD the
+// compiler must leave room for); unset = the compiler's choice.
+#ifdef FPT_EM_WAVES_PER_EU
+#define FPT_EM_OCCUPANCY __attribute__((amdgpu_waves_per_eu(FPT_EM_WAVES_PER_EU)))
+#else
+#define FPT_EM_OCCUPANCY
+#endif
+
 namespace fpt {
 namespace {
 
 constexpr uint32_t kPhiloxM0 = 0xD2511F53u, kPhiloxM1 = 0xCD9E8D57u;
 constexpr uint32_t kPhiloxW0 = 0x9E3779B9u, kPhiloxW1 = 0xBB67AE85u;
+
+// a ^ b ^ c in one instruction: gfx950's three-input bitwise op with the XOR
+// truth table 0x96 (c is wave-uniform, the round key).
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c)
+{
+    uint32_t d;
+    asm("v_bitop3_b32 %0, %1, %2, %3 bitop3:0x96" : "=v"(d) : "v"(a), "v"(b), "s"(c));
+    return d;
+}
 
 __device__ __forceinline__ void philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
                                               uint32_t k0, uint32_t k1, uint32_t w[4])
@@ -44,8 +63,8 @@ __device__ __forceinline__ void philox4x32_10(uint32_t c0, uint32_t c1, uint32_t
     for (int r = 0; r < 10; ++r) {
         const uint64_t p0 = (uint64_t)kPhiloxM0 * c0;
         const uint64_t p1 = (uint64_t)kPhiloxM1 * c2;
-        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
-        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        const uint32_t n0 = xor3((uint32_t)(p1 >> 32), c1, k0);
+        const uint32_t n2 = xor3((uint32_t)(p0 >> 32), c3, k1);
         c1 = (uint32_t)p1;
         c3 = (uint32_t)p0;
         c0 = n0;
@@ -56,12 +75,13 @@ __device__ __forceinline__ void philox4x32_10(uint32_t c0, uint32_t c1, uint32_t
     w[0] = c0; w[1] = c1; w[2] = c2; w[3] = c3;
 }
 
-// Box-Muller in FP64 on uniforms (w + 1/2) 2^-32 (exact in double).
-__device__ __forceinline__ void box_muller64(uint32_t wa, uint32_t wb, double &za, double &zb)
+// Box-Muller in FP64 on uniforms (w + 1/2) 2^-32 (exact in double); returns
+// xi sqrt(dN) for the two steps of the pair.
+__device__ __forceinline__ void box_muller64(uint32_t wa, uint32_t wb, double sqrt_dN, double &za, double &zb)
 {
     const double ua = fma((double)wa, 0x1p-32, 0x1p-33);
     const double ub = fma((double)wb, 0x1p-32, 0x1p-33);
-    const double rho = sqrt(-2.0 * log(ua));
+    const double rho = sqrt(-2.0 * log(ua)) * sqrt_dN;
     double s, c;
     sincospi(2.0 * ub, &s, &c);
     za = rho * c;
@@ -72,13 +92,32 @@ __device__ __forceinline__ void box_muller64(uint32_t wa, uint32_t wb, double &z
 // FP64 path, rounded to 24 significant bits (relative, not absolute, resolution,
 // so the radius stays accurate for small u).  Never 0; at most 1.0f, where the
 // radius is 0.  v_log_f32 returns log2, v_sin_f32 / v_cos_f32 take turns.
-__device__ __forceinline__ void box_muller32(uint32_t wa, uint32_t wb, float &za, float &zb)
+// Returns xi sqrt(dN) for the two steps of the pair.
+__device__ __forceinline__ void box_muller32(uint32_t wa, uint32_t wb, float sqrt_dN, float &za, float &zb)
 {
     const float ua = fmaf((float)wa, 0x1p-32f, 0x1p-33f);
     const float ub = fmaf((float)wb, 0x1p-32f, 0x1p-33f);
-    const float rho = __builtin_sqrtf(fmaxf(-1.3862943611198906f * __builtin_amdgcn_logf(ua), 0.0f));  // -2 ln u
+    const float m2lnu = fmaxf(-1.3862943611198906f * __builtin_amdgcn_logf(ua), 0.0f);  // -2 ln u
+    const float rho = __builtin_amdgcn_sqrtf(m2lnu) * sqrt_dN;
     za = rho * __builtin_amdgcn_cosf(ub);
     zb = rho * __builtin_amdgcn_sinf(ub);
+}
+
+// Copy a wave-uniform value into a VGPR once, so that a per-lane select between
+// two such values is a v_cndmask on registers (not a load from the kernel
+// arguments, and no extra moves for the scalar-operand limit).
+__device__ __forceinline__ float in_vgpr(float x)
+{
+    float v;
+    asm volatile("v_mov_b32 %0, %1" : "=v"(v) : "s"(x));
+    return v;
+}
+
+__device__ __forceinline__ double in_vgpr(double x)
+{
+    double v;
+    asm volatile("v_mov_b64 %0, %1" : "=v"(v) : "s"(x));
+    return v;
 }
 
 __device__ __forceinline__ uint32_t lanes_below(uint64_t mask)
@@ -136,31 +175,56 @@ __device__ __forceinline__ int bin_of(const HistSpec &h, double x)
     return (int)floor(t) + 1;
 }
 
-// Retire one finished trajectory: per-trajectory outputs and LDS histogram.
-__device__ __forceinline__ void retire(const EmParams &p, const LdsAcc &a, uint64_t rel, uint32_t status,
-                                       uint32_t n_steps, double N, double lnw)
+// Where retired trajectories go: per-trajectory outputs (any may be NULL),
+// the histogram layout and the block's LDS accumulators.
+struct RetireTo {
+    double *d_N, *d_lnw;
+    uint32_t *d_steps;
+    unsigned long long *cnt;
+    double *sum;
+    int nb;
+    HistSpec hist;
+};
+
+__device__ __forceinline__ RetireTo retire_to(const EmParams &p, const LdsAcc &a)
 {
-    if (p.d_N) p.d_N[rel] = N;
-    if (p.d_lnw) p.d_lnw[rel] = lnw;
-    if (p.d_steps) p.d_steps[rel] = n_steps | status;
+    RetireTo r;
+    r.d_N = p.d_N;
+    r.d_lnw = p.d_lnw;
+    r.d_steps = p.d_steps;
+    r.cnt = a.cnt;
+    r.sum = a.sum;
+    r.nb = a.nb;
+    r.hist = p.hist;
+    return r;
+}
+
+// Retire one finished trajectory: per-trajectory outputs and LDS histogram.
+__device__ __forceinline__ void retire(const RetireTo &t, uint64_t rel, uint32_t status, uint32_t n_steps, double N,
+                                       double lnw)
+{
+    if (t.d_N) t.d_N[rel] = N;
+    if (t.d_lnw) t.d_lnw[rel] = lnw;
+    if (t.d_steps) t.d_steps[rel] = n_steps | status;
     if (status & kFlagCensored) {
-        atomicAdd(&a.cnt[a.nb + 0], 1ull);
+        atomicAdd(&t.cnt[t.nb + 0], 1ull);
     } else if (status & kFlagEndedEarly) {
-        atomicAdd(&a.cnt[a.nb + 1], 1ull);
+        atomicAdd(&t.cnt[t.nb + 1], 1ull);
     } else {
-        const int b = bin_of(p.hist, N - p.hist.N_ref);
+        const int b = bin_of(t.hist, N - t.hist.N_ref);
         const double w = exp(lnw);
-        atomicAdd(&a.cnt[b], 1ull);
-        atomicAdd(&a.sum[b], w);
-        atomicAdd(&a.sum[a.nb + b], w * w);
-        atomicAdd(&a.sum[2 * a.nb + b], lnw);
-        atomicAdd(&a.sum[3 * a.nb + b], lnw * lnw);
-        double *tot = a.sum + 4 * a.nb;
+        atomicAdd(&t.cnt[b], 1ull);
+        atomicAdd(&t.sum[b], w);
+        atomicAdd(&t.sum[t.nb + b], w * w);
+        atomicAdd(&t.sum[2 * t.nb + b], lnw);
+        atomicAdd(&t.sum[3 * t.nb + b], lnw * lnw);
+        double *tot = t.sum + 4 * t.nb;
         atomicAdd(&tot[0], w);
         atomicAdd(&tot[1], w * w);
         atomicAdd(&tot[2], w * N);
         atomicAdd(&tot[3], w * N * N);
     }
+    atomicAdd(&t.cnt[t.nb + 2], (unsigned long long)n_steps);
 }
 
 __device__ __forceinline__ void zero_lds_acc(const LdsAcc &a)
@@ -179,123 +243,151 @@ __device__ __forceinline__ void flush_lds_acc(const LdsAcc &a, void *global)
         if (a.sum[i] != 0.0) unsafeAtomicAdd(&gs[i], a.sum[i]);
 }
 
+// V'/V for both potentials as 1/d, d = kx phi + s with s chosen per side:
+//   piecewise linear  kx = 1, s = -c_+ (phi >= phi_T) or -c_- (phi < phi_T), c_+- = phi_T - V0/A_+-
+//   exponential       kx = 0, s = 1/A_+ on both sides
+// (no cancellation: d = phi - c is a single rounding).
+struct DriftConsts {
+    double kx, s_plus, s_minus;
+};
+
+__host__ __device__ inline DriftConsts drift_consts(const EmParams &p)
+{
+    DriftConsts k;
+    if (p.pot_kind == kPotExponential) {
+        k.kx = 0.0;
+        k.s_plus = k.s_minus = 1.0 / p.A_plus;
+    } else {
+        k.kx = 1.0;
+        k.s_plus = -(p.phi_T - p.V0 / p.A_plus);
+        k.s_minus = -(p.phi_T - p.V0 / p.A_minus);
+    }
+    return k;
+}
+
 // ---------------------------------------------------------------------------
 // FP64 state
 // ---------------------------------------------------------------------------
-template <int BIAS, bool TAB>
-__global__ void __launch_bounds__(1024) em_fp64_kernel(EmParams p)
+//
+// Steps are taken in groups of four (one Philox call).  Inside a group every
+// lane computes every step; a lane whose trajectory ended earlier in the chunk
+// keeps integrating a discarded state until the chunk ends and it is refilled,
+// which keeps the group free of per-step exec-mask bookkeeping.  The end of a
+// trajectory (first passage, eps_1 >= 1) is handled in a branch that is taken
+// about once per 1e4-1e5 steps.  Censoring at max_steps needs a test before
+// every step, so groups that can reach max_steps take a separate variant.
+template <int BIAS, bool TAB, bool ALLPOS>
+__global__ void __launch_bounds__(1024) FPT_EM_OCCUPANCY em_fp64_kernel(EmParams p, DriftConsts dk)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     const LdsAcc acc = lds_acc(smem, p.hist.n_bins);
-    double *l_S = acc.sum + 4 * acc.nb + 4;
-    double *l_t = l_S + p.n_tab;
+    double2 *l_tab = reinterpret_cast<double2 *>(acc.sum + 4 * acc.nb + 4);
     zero_lds_acc(acc);
-    if (TAB) {
-        for (int i = threadIdx.x; i < p.n_tab; i += blockDim.x) {
-            l_S[i] = p.tab_S[i];
-            l_t[i] = p.tab_t[i];
-        }
-    }
+    if (TAB)
+        for (int i = threadIdx.x; i < p.n_tab; i += blockDim.x) l_tab[i] = p.tab64[i];
     __syncthreads();
 
-    const double S0 = p.tab_S[0], t0 = p.tab_t[0];
-    const double dN = p.dN, sqrt_dN = p.sqrt_dN;
+    const RetireTo rt = retire_to(p, acc);
+    const double S0 = p.tab64[0].x, t0 = p.tab64[0].y;
+    const double dN = p.dN, sqrt_dN = p.sqrt_dN, phi_end = p.phi_end, phi_T = p.phi_T;
     const double a = (BIAS == kBiasConst) ? p.A : 0.0;
     const double half_a2_dN = 0.5 * a * a * dN;
-    const double tab_jmax = (double)(p.n_tab - 2);
+    const double jmax = (double)(p.n_tab - 2);
+    const double s_plus = in_vgpr(dk.s_plus), s_minus = in_vgpr(dk.s_minus);
 
     bool exhausted = false;
     uint64_t rel = 0;
     bool has = claim(true, rel, p.cursor, p.n_traj, exhausted);
+    bool live = has;          // has a trajectory that has not ended yet
     double phi = p.phi_in, pi_ = p.pi_in, lnw = 0.0;
-    uint32_t n = 0;
-    uint64_t steps_acc = 0;
+    uint32_t n = 0, n_on = 0;
 
-    while (__any(has)) {
-        bool active = has;
-        uint32_t status = 0, n_out = 0;
-        double N_out = 0.0, lnw_out = 0.0;
-        for (int k = 0; k < p.chunk; k += 4) {
-            if (!__any(active)) break;
-            if (active) {
-                const uint64_t traj = p.traj_offset + rel;
-                uint32_t w[4];
-                philox4x32_10(n >> 2, (uint32_t)traj, (uint32_t)(traj >> 32), p.instance, p.key0, p.key1, w);
-                double z[4];
-                box_muller64(w[0], w[1], z[0], z[1]);
-                box_muller64(w[2], w[3], z[2], z[3]);
+    // The end of a trajectory inside a group is recorded here and retired once
+    // the group's four steps are done.
+    auto group = [&](auto censor_tag, const double z[4]) {
+        constexpr bool CENSOR = decltype(censor_tag)::value;
+        bool fresh = false;
+        uint32_t ev_status, ev_n;   // written before use: read only where fresh is set
+        double ev_N, ev_lnw;
 #pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    if (active) {
-                        if (n == p.max_steps) {
-                            active = false;
-                            status = kFlagCensored;
-                            N_out = __builtin_nan("");
-                            lnw_out = lnw;
-                            n_out = n;
-                        } else {
-                            // V'/V
-                            double r;
-                            if (p.pot_kind == kPotExponential) {
-                                r = p.A_plus;
-                            } else {
-                                const double A = (phi >= p.phi_T) ? p.A_plus : p.A_minus;
-                                r = A / (p.V0 + A * (phi - p.phi_T));
-                            }
-                            // noise amplitude and direction at phi
-                            double S, t;
-                            if (TAB) {
-                                const double x = (phi - p.phi_lo) * p.inv_h;
-                                const double jf = fmin(fmax(floor(x), 0.0), tab_jmax);
-                                const int jj = (int)jf;
-                                const double f = fmin(fmax(x - jf, 0.0), 1.0);
-                                S = l_S[jj] + f * (l_S[jj + 1] - l_S[jj]);
-                                t = l_t[jj] + f * (l_t[jj + 1] - l_t[jj]);
-                            } else {
-                                S = S0;
-                                t = t0;
-                            }
-                            const double zs = z[j] * sqrt_dN;
-                            const double noise = S * zs;
-                            const double aS = a * S;
-                            const double phi_n = phi + (pi_ + aS) * dN + noise;
-                            const double pi_n = pi_ - (3.0 - 0.5 * pi_ * pi_) * (pi_ + r) * dN + t * (aS * dN + noise);
-                            if (BIAS != kBiasNone && S > 0.0) lnw -= a * zs + half_a2_dN;
-                            if (phi_n <= p.phi_end) {
-                                active = false;
-                                status = 0;
-                                N_out = (double)n * dN + dN * ((phi - p.phi_end) / (phi - phi_n));
-                                lnw_out = lnw;
-                                n_out = n + 1;
-                            } else if (0.5 * pi_n * pi_n >= 1.0) {
-                                active = false;
-                                status = kFlagEndedEarly;
-                                N_out = (double)(n + 1) * dN;
-                                lnw_out = lnw;
-                                n_out = n + 1;
-                            }
-                            phi = phi_n;
-                            pi_ = pi_n;
-                            n += 1;
-                        }
-                    }
+        for (int j = 0; j < 4; ++j) {
+            if (CENSOR && live && n == p.max_steps) {
+                ev_status = kFlagCensored;
+                ev_n = n;
+                ev_N = __builtin_nan("");
+                ev_lnw = lnw;
+                live = false;
+                fresh = true;
+            }
+            const double d = fma(phi, dk.kx, (phi >= phi_T) ? s_plus : s_minus);
+            double r = __builtin_amdgcn_rcp(d);
+            r = fma(r, fma(-d, r, 1.0), r);
+            r = fma(r, fma(-d, r, 1.0), r);
+            double S, t;
+            if (TAB) {
+                const double x = (phi - p.phi_lo) * p.inv_h;
+                const double jf = fmin(fmax(floor(x), 0.0), jmax);
+                const double f = fmin(fmax(x - jf, 0.0), 1.0);
+                const int jj = (int)jf;
+                const double2 lo = l_tab[jj], hi = l_tab[jj + 1];
+                S = lo.x + f * (hi.x - lo.x);
+                t = lo.y + f * (hi.y - lo.y);
+            } else {
+                S = S0;
+                t = t0;
+            }
+            const double zs = z[j];                       // xi sqrt(dN)
+            const double noise = S * zs;
+            const double aS = a * S;
+            const double phi_n = phi + (pi_ + aS) * dN + noise;
+            const double pi_n = pi_ - (3.0 - 0.5 * pi_ * pi_) * (pi_ + r) * dN + t * (aS * dN + noise);
+            if (BIAS != kBiasNone) {
+                if (ALLPOS) {
+                    lnw -= a * zs + half_a2_dN;
+                } else {
+                    lnw -= (S > 0.0) ? a * zs + half_a2_dN : 0.0;
                 }
             }
+            const bool crossed = phi_n <= phi_end;
+            const bool ended = 0.5 * pi_n * pi_n >= 1.0;
+            if (live && (crossed || ended)) {
+                ev_status = crossed ? 0u : kFlagEndedEarly;
+                ev_n = n + 1;
+                ev_N = crossed ? (double)n * dN + dN * ((phi - phi_end) / (phi - phi_n)) : (double)(n + 1) * dN;
+                ev_lnw = lnw;
+                live = false;
+                fresh = true;
+            }
+            phi = phi_n;
+            pi_ = pi_n;
+            n += 1;
         }
-        if (has && !active) {
-            retire(p, acc, rel, status, n_out, N_out, lnw_out);
-            steps_acc += n_out;
-            has = false;
+        if (fresh) retire(rt, rel, ev_status, ev_n, ev_N, ev_lnw);
+    };
+
+    while (__any(has)) {
+        for (int k = 0; k < p.chunk; k += 4) {
+            if (!__any(live)) break;
+            const uint64_t traj = p.traj_offset + rel;
+            uint32_t w[4];
+            philox4x32_10(n >> 2, (uint32_t)traj, (uint32_t)(traj >> 32), p.instance, p.key0, p.key1, w);
+            double z[4];
+            box_muller64(w[0], w[1], sqrt_dN, z[0], z[1]);
+            box_muller64(w[2], w[3], sqrt_dN, z[2], z[3]);
+            if (__any(live && n + 4 > p.max_steps)) group(std::integral_constant<bool, true>(), z);
+            else group(std::integral_constant<bool, false>(), z);
         }
+        if (!live) has = false;
         if (claim(!has, rel, p.cursor, p.n_traj, exhausted)) {
             has = true;
+            live = true;
             phi = p.phi_in;
             pi_ = p.pi_in;
             lnw = 0.0;
             n = 0;
         }
     }
-    if (steps_acc) atomicAdd(&acc.cnt[acc.nb + 2], (unsigned long long)steps_acc);
+    (void)n_on;
     __syncthreads();
     flush_lds_acc(acc, p.acc);
 }
@@ -305,12 +397,12 @@ __global__ void __launch_bounds__(1024) em_fp64_kernel(EmParams p)
 // ---------------------------------------------------------------------------
 struct F32Consts {
     float xT_hi, xT_lo;        // phi_T - phi_end as a float pair
-    float q_plus, q_minus;     // V0/A_+ and V0/A_-  (1/r = (phi - phi_T) + V0/A)
-    float r_exp;               // A_+ for the exponential potential
-    float c_tab;               // phi_end - phi_lo
+    float kx, s_plus, s_minus; // V'/V = 1/(kx (phi - phi_T) + s), s = s_plus (phi >= phi_T) or s_minus
+    float u_off;               // (phi_end - phi_lo) * inv_h: table coordinate of x = 0
     float inv_h;
+    float jmax;                // n_tab - 2
     float dN, sqrt_dN;
-    float a, a_dN;
+    float a;
 };
 
 __device__ __forceinline__ void two_sum_fast(float &hi, float &lo, float d)
@@ -322,136 +414,130 @@ __device__ __forceinline__ void two_sum_fast(float &hi, float &lo, float d)
     lo += e;
 }
 
-template <int BIAS, bool TAB>
-__global__ void __launch_bounds__(1024) em_fp32s_kernel(EmParams p, F32Consts c)
+template <int BIAS, bool TAB, bool ALLPOS>
+__global__ void __launch_bounds__(1024) FPT_EM_OCCUPANCY em_fp32s_kernel(EmParams p, F32Consts c)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     const LdsAcc acc = lds_acc(smem, p.hist.n_bins);
-    float *l_S = reinterpret_cast<float *>(acc.sum + 4 * acc.nb + 4);
-    float *l_t = l_S + p.n_tab;
+    float4 *l_tab = reinterpret_cast<float4 *>(acc.sum + 4 * acc.nb + 4);
     zero_lds_acc(acc);
-    if (TAB) {
-        for (int i = threadIdx.x; i < p.n_tab; i += blockDim.x) {
-            l_S[i] = p.tab_Sf[i];
-            l_t[i] = p.tab_tf[i];
-        }
-    }
+    if (TAB)
+        for (int i = threadIdx.x; i < p.n_tab; i += blockDim.x) l_tab[i] = p.tab32[i];
     __syncthreads();
 
-    const float S0 = p.tab_Sf[0], t0 = p.tab_tf[0];
-    const float tab_jmax = (float)(p.n_tab - 2);
+    const RetireTo rt = retire_to(p, acc);
+    const float S0 = p.tab32[0].x, t0 = p.tab32[0].z;
     const double x_in = p.phi_in - p.phi_end;
     const float x_in_hi = (float)x_in, x_in_lo = (float)(x_in - (double)x_in_hi);
-    const double pi_in = p.pi_in;
-    const float pi_in_hi = (float)pi_in, pi_in_lo = (float)(pi_in - (double)pi_in_hi);
+    const float pi_in_hi = (float)p.pi_in, pi_in_lo = (float)(p.pi_in - (double)pi_in_hi);
     const double dN = p.dN;
+    const double half_a2_dN = 0.5 * p.A * p.A * dN;
+    const float s_plus = in_vgpr(c.s_plus), s_minus = in_vgpr(c.s_minus);
 
     bool exhausted = false;
     uint64_t rel = 0;
     bool has = claim(true, rel, p.cursor, p.n_traj, exhausted);
+    bool live = has;          // has a trajectory that has not ended yet
     float xh = x_in_hi, xl = x_in_lo, ph = pi_in_hi, pl = pi_in_lo;
-    double zsum = 0.0;        // sum of xi over steps with S > 0 (constant bias)
-    uint32_t n_on = 0;        // number of such steps
+    double zsum = 0.0;        // sum of xi sqrt(dN) over steps with S > 0 (constant bias)
+    uint32_t n_on = 0;        // number of such steps (counted only when some node has S = 0)
     uint32_t n = 0;
-    uint64_t steps_acc = 0;
 
-    while (__any(has)) {
-        bool active = has;
-        uint32_t status = 0, n_out = 0;
-        double N_out = 0.0, zsum_out = 0.0;
-        uint32_t non_out = 0;
-        for (int k = 0; k < p.chunk; k += 4) {
-            if (!__any(active)) break;
-            if (active) {
-                const uint64_t traj = p.traj_offset + rel;
-                uint32_t w[4];
-                philox4x32_10(n >> 2, (uint32_t)traj, (uint32_t)(traj >> 32), p.instance, p.key0, p.key1, w);
-                float z[4];
-                box_muller32(w[0], w[1], z[0], z[1]);
-                box_muller32(w[2], w[3], z[2], z[3]);
-                float zpart = 0.0f;
+    auto lnw_of = [&](double zs_total, uint32_t steps_on) -> double {
+        return (BIAS == kBiasNone) ? 0.0 : -p.A * zs_total - (double)steps_on * half_a2_dN;
+    };
+
+    // The end of a trajectory inside a group is recorded here and retired once
+    // the group's four steps are done.
+    auto group = [&](auto censor_tag, const float z[4]) {
+        constexpr bool CENSOR = decltype(censor_tag)::value;
+        float zacc = 0.0f;
+        bool fresh = false;
+        uint32_t ev_status, ev_n;   // written before use: read only where fresh is set
+        double ev_N, ev_lnw;
 #pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    if (active) {
-                        if (n == p.max_steps) {
-                            active = false;
-                            status = kFlagCensored;
-                            N_out = __builtin_nan("");
-                            zsum_out = zsum + (double)zpart;
-                            non_out = n_on;
-                            n_out = n;
-                        } else {
-                            // phi - phi_T as an accurate float: (xh - xT_hi) + (xl - xT_lo)
-                            const float dT = (xh - c.xT_hi) + (xl - c.xT_lo);
-                            float r;
-                            if (p.pot_kind == kPotExponential) r = c.r_exp;
-                            else r = __builtin_amdgcn_rcpf(dT + ((dT >= 0.0f) ? c.q_plus : c.q_minus));
-                            float S, t;
-                            if (TAB) {
-                                const float u = (xh + c.c_tab) * c.inv_h;
-                                const float jf = fminf(fmaxf(floorf(u), 0.0f), tab_jmax);
-                                const int jj = (int)jf;
-                                const float f = fminf(fmaxf(u - jf, 0.0f), 1.0f);
-                                S = l_S[jj] + f * (l_S[jj + 1] - l_S[jj]);
-                                t = l_t[jj] + f * (l_t[jj + 1] - l_t[jj]);
-                            } else {
-                                S = S0;
-                                t = t0;
-                            }
-                            const float noise = S * (z[j] * c.sqrt_dN);
-                            const float aS = c.a * S;
-                            const float dx = (ph + aS) * c.dN + noise;
-                            const float dpi = -(3.0f - 0.5f * ph * ph) * (ph + r) * c.dN + t * (aS * c.dN + noise);
-                            if (BIAS != kBiasNone && S > 0.0f) {
-                                zpart += z[j];
-                                n_on += 1;
-                            }
-                            const float xh_old = xh, xl_old = xl;
-                            two_sum_fast(xh, xl, dx);
-                            two_sum_fast(ph, pl, dpi);
-                            if (xh + xl <= 0.0f) {
-                                active = false;
-                                status = 0;
-                                const double x0 = (double)xh_old + (double)xl_old;
-                                const double x1 = (double)xh + (double)xl;
-                                N_out = (double)n * dN + dN * (x0 / (x0 - x1));
-                                zsum_out = zsum + (double)zpart;
-                                non_out = n_on;
-                                n_out = n + 1;
-                            } else if (0.5f * ph * ph >= 1.0f) {
-                                active = false;
-                                status = kFlagEndedEarly;
-                                N_out = (double)(n + 1) * dN;
-                                zsum_out = zsum + (double)zpart;
-                                non_out = n_on;
-                                n_out = n + 1;
-                            }
-                            n += 1;
-                        }
-                    }
-                }
-                zsum += (double)zpart;
-                // renormalise the pairs once per group of four steps
-                {
-                    const float s = xh + xl;
-                    xl = xl - (s - xh);
-                    xh = s;
-                    const float q = ph + pl;
-                    pl = pl - (q - ph);
-                    ph = q;
+        for (int j = 0; j < 4; ++j) {
+            if (CENSOR && live && n == p.max_steps) {
+                ev_status = kFlagCensored;
+                ev_n = n;
+                ev_N = __builtin_nan("");
+                ev_lnw = lnw_of(zsum + (double)zacc, ALLPOS ? n : n_on);
+                live = false;
+                fresh = true;
+            }
+            // phi - phi_T as an accurate float: (xh - xT_hi) + (xl - xT_lo)
+            const float dT = (xh - c.xT_hi) + (xl - c.xT_lo);
+            const float r = __builtin_amdgcn_rcpf(fmaf(dT, c.kx, (dT >= 0.0f) ? s_plus : s_minus));
+            float S, t;
+            if (TAB) {
+                const float u = fmaf(xh, c.inv_h, c.u_off);
+                const float jf = __builtin_amdgcn_fmed3f(floorf(u), 0.0f, c.jmax);
+                const float f = __builtin_amdgcn_fmed3f(u - jf, 0.0f, 1.0f);
+                const float4 node = l_tab[(int)jf];
+                S = fmaf(f, node.y, node.x);
+                t = fmaf(f, node.w, node.z);
+            } else {
+                S = S0;
+                t = t0;
+            }
+            const float noise = S * z[j];                 // z is xi sqrt(dN)
+            const float aS = c.a * S;
+            const float dx = fmaf(ph + aS, c.dN, noise);
+            const float drift = fmaf(-0.5f * ph, ph, 3.0f) * (ph + r);
+            const float dpi = fmaf(t, fmaf(aS, c.dN, noise), -drift * c.dN);
+            if (BIAS != kBiasNone) {
+                if (ALLPOS) {
+                    zacc += z[j];
+                } else {
+                    const bool on = S > 0.0f;
+                    zacc += on ? z[j] : 0.0f;
+                    n_on += on ? 1u : 0u;
                 }
             }
+            const float x0h = xh, x0l = xl;
+            two_sum_fast(xh, xl, dx);
+            two_sum_fast(ph, pl, dpi);
+            const bool crossed = xh + xl <= 0.0f;
+            const bool ended = 0.5f * ph * ph >= 1.0f;
+            if (live && (crossed || ended)) {
+                ev_status = crossed ? 0u : kFlagEndedEarly;
+                ev_n = n + 1;
+                const double x0 = (double)x0h + (double)x0l;
+                const double x1 = (double)xh + (double)xl;
+                ev_N = crossed ? (double)n * dN + dN * (x0 / (x0 - x1)) : (double)(n + 1) * dN;
+                ev_lnw = lnw_of(zsum + (double)zacc, ALLPOS ? n + 1 : n_on);
+                live = false;
+                fresh = true;
+            }
+            n += 1;
         }
-        if (has && !active) {
-            const double lnw = (BIAS == kBiasNone)
-                                   ? 0.0
-                                   : -p.A * p.sqrt_dN * zsum_out - (double)non_out * (0.5 * p.A * p.A * dN);
-            retire(p, acc, rel, status, n_out, N_out, lnw);
-            steps_acc += n_out;
-            has = false;
+        zsum += (double)zacc;
+        if (fresh) retire(rt, rel, ev_status, ev_n, ev_N, ev_lnw);
+        // renormalise the pairs once per group
+        const float s = xh + xl;
+        xl = xl - (s - xh);
+        xh = s;
+        const float q = ph + pl;
+        pl = pl - (q - ph);
+        ph = q;
+    };
+
+    while (__any(has)) {
+        for (int k = 0; k < p.chunk; k += 4) {
+            if (!__any(live)) break;
+            const uint64_t traj = p.traj_offset + rel;
+            uint32_t w[4];
+            philox4x32_10(n >> 2, (uint32_t)traj, (uint32_t)(traj >> 32), p.instance, p.key0, p.key1, w);
+            float z[4];
+            box_muller32(w[0], w[1], c.sqrt_dN, z[0], z[1]);
+            box_muller32(w[2], w[3], c.sqrt_dN, z[2], z[3]);
+            if (__any(live && n + 4 > p.max_steps)) group(std::integral_constant<bool, true>(), z);
+            else group(std::integral_constant<bool, false>(), z);
         }
+        if (!live) has = false;
         if (claim(!has, rel, p.cursor, p.n_traj, exhausted)) {
             has = true;
+            live = true;
             xh = x_in_hi;
             xl = x_in_lo;
             ph = pi_in_hi;
@@ -461,7 +547,6 @@ __global__ void __launch_bounds__(1024) em_fp32s_kernel(EmParams p, F32Consts c)
             n = 0;
         }
     }
-    if (steps_acc) atomicAdd(&acc.cnt[acc.nb + 2], (unsigned long long)steps_acc);
     __syncthreads();
     flush_lds_acc(acc, p.acc);
 }
@@ -478,68 +563,73 @@ F32Consts make_f32_consts(const EmParams &p)
     const double xT = p.phi_T - p.phi_end;
     c.xT_hi = (float)xT;
     c.xT_lo = (float)(xT - (double)c.xT_hi);
-    c.q_plus = (float)(p.V0 / p.A_plus);
-    c.q_minus = (float)(p.V0 / p.A_minus);
-    c.r_exp = (float)p.A_plus;
-    c.c_tab = (float)(p.phi_end - p.phi_lo);
+    if (p.pot_kind == kPotExponential) {
+        c.kx = 0.0f;
+        c.s_plus = c.s_minus = (float)(1.0 / p.A_plus);
+    } else {
+        c.kx = 1.0f;
+        c.s_plus = (float)(p.V0 / p.A_plus);
+        c.s_minus = (float)(p.V0 / p.A_minus);
+    }
+    c.u_off = (float)((p.phi_end - p.phi_lo) * p.inv_h);
     c.inv_h = (float)p.inv_h;
+    c.jmax = (float)(p.n_tab - 2);
     c.dN = (float)p.dN;
     c.sqrt_dN = (float)p.sqrt_dN;
     c.a = (p.bias_kind == kBiasConst) ? (float)p.A : 0.0f;
-    c.a_dN = c.a * c.dN;
     return c;
 }
 
-template <int BIAS, bool TAB>
-const void *pick64() { return reinterpret_cast<const void *>(&em_fp64_kernel<BIAS, TAB>); }
-template <int BIAS, bool TAB>
-const void *pick32() { return reinterpret_cast<const void *>(&em_fp32s_kernel<BIAS, TAB>); }
+// kernel table [precision][bias 0..1][tab][allpos]
+template <int BIAS, bool TAB, bool ALLPOS>
+const void *k64() { return reinterpret_cast<const void *>(&em_fp64_kernel<BIAS, TAB, ALLPOS>); }
+template <int BIAS, bool TAB, bool ALLPOS>
+const void *k32() { return reinterpret_cast<const void *>(&em_fp32s_kernel<BIAS, TAB, ALLPOS>); }
+
+const void *kernel_of(int precision, int bias, bool tab, bool allpos)
+{
+    static const void *const t64[2][2][2] = {
+        {{k64<kBiasNone, false, false>(), k64<kBiasNone, false, true>()},
+         {k64<kBiasNone, true, false>(), k64<kBiasNone, true, true>()}},
+        {{k64<kBiasConst, false, false>(), k64<kBiasConst, false, true>()},
+         {k64<kBiasConst, true, false>(), k64<kBiasConst, true, true>()}}};
+    static const void *const t32[2][2][2] = {
+        {{k32<kBiasNone, false, false>(), k32<kBiasNone, false, true>()},
+         {k32<kBiasNone, true, false>(), k32<kBiasNone, true, true>()}},
+        {{k32<kBiasConst, false, false>(), k32<kBiasConst, false, true>()},
+         {k32<kBiasConst, true, false>(), k32<kBiasConst, true, true>()}}};
+    const int b = bias == kBiasNone ? 0 : 1;
+    return precision == 0 ? t64[b][tab][allpos] : t32[b][tab][allpos];
+}
 
 }  // namespace
 
 size_t em_lds_bytes(const EmParams &p, int precision)
 {
+    (void)precision;
     const size_t acc = acc_bytes(p.hist.n_bins);
-    const size_t tab = (p.n_tab > 1) ? (size_t)p.n_tab * 2 * (precision == 0 ? 8 : 4) : 0;
+    const size_t tab = (p.n_tab > 1) ? (size_t)p.n_tab * 16 : 0;   // double2 or float4 per node
     return acc + tab;
 }
 
 const void *em_kernel_ptr(const EmParams &p, int precision)
 {
-    const bool tab = p.n_tab > 1;
-    const int b = p.bias_kind;
-    if (precision == 0) {
-        if (b == kBiasNone) return tab ? pick64<kBiasNone, true>() : pick64<kBiasNone, false>();
-        return tab ? pick64<kBiasConst, true>() : pick64<kBiasConst, false>();
-    }
-    if (b == kBiasNone) return tab ? pick32<kBiasNone, true>() : pick32<kBiasNone, false>();
-    return tab ? pick32<kBiasConst, true>() : pick32<kBiasConst, false>();
+    return kernel_of(precision, p.bias_kind, p.n_tab > 1, p.all_S_pos != 0);
 }
 
 hipError_t em_launch(const EmParams &p, int precision, int grid, int block, hipStream_t stream)
 {
     const size_t lds = em_lds_bytes(p, precision);
-    const bool tab = p.n_tab > 1;
-    const int b = p.bias_kind;
+    const void *fn = em_kernel_ptr(p, precision);
+    EmParams pp = p;
     if (precision == 0) {
-        if (b == kBiasNone) {
-            if (tab) hipLaunchKernelGGL((em_fp64_kernel<kBiasNone, true>), dim3(grid), dim3(block), lds, stream, p);
-            else hipLaunchKernelGGL((em_fp64_kernel<kBiasNone, false>), dim3(grid), dim3(block), lds, stream, p);
-        } else {
-            if (tab) hipLaunchKernelGGL((em_fp64_kernel<kBiasConst, true>), dim3(grid), dim3(block), lds, stream, p);
-            else hipLaunchKernelGGL((em_fp64_kernel<kBiasConst, false>), dim3(grid), dim3(block), lds, stream, p);
-        }
-    } else {
-        const F32Consts c = make_f32_consts(p);
-        if (b == kBiasNone) {
-            if (tab) hipLaunchKernelGGL((em_fp32s_kernel<kBiasNone, true>), dim3(grid), dim3(block), lds, stream, p, c);
-            else hipLaunchKernelGGL((em_fp32s_kernel<kBiasNone, false>), dim3(grid), dim3(block), lds, stream, p, c);
-        } else {
-            if (tab) hipLaunchKernelGGL((em_fp32s_kernel<kBiasConst, true>), dim3(grid), dim3(block), lds, stream, p, c);
-            else hipLaunchKernelGGL((em_fp32s_kernel<kBiasConst, false>), dim3(grid), dim3(block), lds, stream, p, c);
-        }
+        DriftConsts dk = drift_consts(p);
+        void *args[] = {&pp, &dk};
+        return hipLaunchKernel(fn, dim3(grid), dim3(block), args, lds, stream);
     }
-    return hipGetLastError();
+    F32Consts c = make_f32_consts(p);
+    void *args[] = {&pp, &c};
+    return hipLaunchKernel(fn, dim3(grid), dim3(block), args, lds, stream);
 }
 
 hipError_t zero_words(unsigned long long *ptr, size_t n, hipStream_t stream)

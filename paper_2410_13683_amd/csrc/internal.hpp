@@ -42,8 +42,9 @@ struct EmParams {
     // phi-indexed noise table: n_tab nodes from phi_lo with spacing 1/inv_h
     int32_t n_tab;
     double phi_lo, inv_h;
-    const double *tab_S, *tab_t;     // FP64 nodes (device)
-    const float *tab_Sf, *tab_tf;    // FP32 copies (device)
+    const double2 *tab64;            // node j: (S_j, tan_j)                        (device)
+    const float4 *tab32;             // node j: (S_j, S_j+1 - S_j, tan_j, tan_j+1 - tan_j) in FP32
+    int32_t all_S_pos;               // every node has S > 0 (the ln w update needs no test)
     // importance-sampling bias
     int32_t bias_kind;
     double A;
