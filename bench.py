@@ -35,8 +35,8 @@ METRIC = "trajectory-steps/s and ESS-weighted tail samples/s at 5% P(δN) tail e
 # Algorithmic work of one trajectory step (constant bias, phi-indexed table,
 # piecewise-linear potential), counted operation by operation from the step's
 # definition; FMA = 2 FLOPs, a transcendental = 1.  Derivation in the design doc.
-ALG_FLOPS_PER_STEP = {"fp32": 60.5, "fp64": 56.5}
-ALG_INT_OPS_PER_STEP = 21.0          # Philox4x32-10 amortised over 4 steps + uniform conversion
+ALG_FLOPS_PER_STEP = {"fp32": 56.5, "fp64": 58.5}
+ALG_INT_OPS_PER_STEP = 16.0          # Philox4x32-10 amortised over 4 steps + uniform conversions
 PEAK_TFLOPS = {"fp32": 157.3, "fp64": 78.6}   # MI355X vector peaks (FP32 figure assumes packed issue)
 PEAK_HBM_GBS = 8000.0
 
