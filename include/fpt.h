@@ -218,6 +218,60 @@ const char *fpt_last_error(void);
 int fpt_noise_table_bessel(const fpt_potential *pot, double sigma, int32_t n, double phi_lo,
                            double phi_hi, double *S_out, double *tan_out);
 
+/* ---- batches: many problems in one persistent launch ------------------------- */
+
+/* Several contexts (each its own potential, noise table, bias amplitude,
+ * histogram, step cap and Philox instance word) integrated by one persistent
+ * kernel launch.  Each block takes a work item -- a slice of one instance's
+ * trajectories -- from a queue ordered longest estimated cost first, stages
+ * that instance's table and histogram in LDS, runs the slice and flushes the
+ * histogram into the instance's context; results are identical to fpt_run on
+ * each context with the same seed and trajectory range.  The launch is
+ * captured in a hipGraph on the first run on a (non-null) stream and replayed
+ * afterwards with the new work list, seed and dN.  The contexts must share the
+ * device and the precision; NONE and CONST biases may be mixed; MLP is not
+ * supported here.  Per-trajectory outputs are not produced. */
+typedef struct fpt_batch fpt_batch;
+
+typedef struct {
+    int32_t block_size;   /* 64..1024, multiple of 64; 0 = 1024 (or the tuned value) */
+    int32_t chunk;        /* steps between retire/refill, multiple of 4; 0 = 128 */
+    int32_t item_size;    /* trajectories per work item; 0 = 16 x block_size */
+    int32_t use_graph;    /* 1 = capture/replay the launch as a hipGraph (non-null streams) */
+} fpt_batch_options;
+
+/* Create a batch over ctx[0..n_inst-1] (the contexts must outlive it).
+ * opts may be NULL (defaults, no graph).  Errors: FPT_EINVAL (mixed devices
+ * or precisions, an MLP bias, tables/histograms too large for LDS),
+ * FPT_ESTATE (wrong current device), FPT_EHIP. */
+int fpt_batch_create(fpt_ctx *const *ctx, int32_t n_inst, const fpt_batch_options *opts, fpt_batch **out);
+
+/* Run n_traj[i] trajectories of instance i (indices traj_offset ..
+ * traj_offset + n_traj[i] - 1, host array of n_inst counts, zeros allowed)
+ * asynchronously on hip_stream; results accumulate into each context
+ * (read them with fpt_histogram).  Errors: FPT_EINVAL, FPT_ESTATE, FPT_EHIP. */
+int fpt_batch_run(fpt_batch *b, const uint64_t *n_traj, double dN, uint64_t seed, uint64_t traj_offset,
+                  void *hip_stream);
+
+/* Pick the block size and chunk for this batch: look the configuration up in
+ * cache_path (text lines "key block chunk"; may be NULL), else time a probe
+ * launch for each of block {256, 512, 1024} x chunk {32, 64, 128, 256} on
+ * trajectories beyond index 2^62 with private accumulators, keep the fastest,
+ * measure each instance's mean steps per trajectory for the work order and
+ * append the result to cache_path.  Contexts' histograms are not touched.
+ * Synchronous.  Errors: FPT_EINVAL, FPT_EHIP. */
+int fpt_batch_autotune(fpt_batch *b, const uint64_t *n_traj, double dN, uint64_t seed, const char *cache_path,
+                       void *hip_stream);
+
+/* The block size and chunk the batch currently uses. */
+int fpt_batch_config(fpt_batch *b, int32_t *block_size, int32_t *chunk);
+
+/* Duration in milliseconds of the last batch launch (HIP events on its stream; waits for it). */
+int fpt_batch_last_ms(fpt_batch *b, double *ms);
+
+/* Free the batch (waits for the device; NULL is allowed). */
+void fpt_batch_destroy(fpt_batch *b);
+
 #ifdef __cplusplus
 }
 #endif

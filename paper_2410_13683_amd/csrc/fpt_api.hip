@@ -11,6 +11,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <algorithm>
 #include <vector>
 
 using namespace fpt;
@@ -138,9 +139,9 @@ struct fpt_ctx {
     int cu_count = 0;
     size_t lds_per_block_max = 0;
     int precision = FPT_FP64;
-    fpt_potential pot{};
     fpt_options opt{};
-    EmParams base{};
+    Inst inst{};
+    unsigned long long *cursor = nullptr;
     void *d_mem = nullptr;
     hipEvent_t ev_start = nullptr, ev_stop = nullptr, ev_done = nullptr;
     bool ran = false;
@@ -200,7 +201,6 @@ extern "C" int fpt_create(const fpt_potential *pot, const fpt_noise_table *table
 
     fpt_ctx *c = new (std::nothrow) fpt_ctx();
     if (!c) return fail(FPT_ENOMEM, "host allocation failed");
-    c->pot = *pot;
     c->opt = o;
     c->precision = o.precision;
     hipError_t e = hipGetDevice(&c->device);
@@ -243,51 +243,46 @@ extern "C" int fpt_create(const fpt_potential *pot, const fpt_noise_table *table
         fpt_destroy(c);
         return hip_fail(e, "fpt_create initialisation");
     }
-    EmParams &p = c->base;
-    p.pot_kind = pot->kind;
-    p.V0 = pot->V0; p.phi_T = pot->phi_T; p.A_plus = pot->A_plus; p.A_minus = pot->A_minus;
-    p.phi_in = pot->phi_in; p.pi_in = pot->pi_in; p.phi_end = pot->phi_end;
-    p.n_tab = nt;
-    p.phi_lo = (nt > 1) ? table->phi_lo : 0.0;
-    p.inv_h = (nt > 1) ? (double)(nt - 1) / (table->phi_hi - table->phi_lo) : 0.0;
-    p.tab64 = reinterpret_cast<const double2 *>(base);
-    p.tab32 = reinterpret_cast<const float4 *>(base + off_tab32);
-    p.all_S_pos = all_pos ? 1 : 0;
-    p.bias_kind = b.kind;
-    p.A = (b.kind == FPT_BIAS_CONST) ? b.A : 0.0;
-    p.mlp = nullptr;
-    p.mlp_every = 1;
-    p.max_steps = (uint32_t)o.max_steps;
-    p.hist.bins_kind = o.bins_kind;
-    p.hist.n_bins = o.n_bins;
-    p.hist.lo = o.lo;
-    p.hist.N_ref = o.N_ref;
-    p.hist.scale = (o.bins_kind == FPT_BINS_LINEAR) ? (double)o.n_bins / (o.hi - o.lo)
+    Inst &I = c->inst;
+    I.pot_kind = pot->kind;
+    I.V0 = pot->V0; I.phi_T = pot->phi_T; I.A_plus = pot->A_plus; I.A_minus = pot->A_minus;
+    I.phi_in = pot->phi_in; I.pi_in = pot->pi_in; I.phi_end = pot->phi_end;
+    I.n_tab = nt;
+    I.phi_lo = (nt > 1) ? table->phi_lo : 0.0;
+    I.inv_h = (nt > 1) ? (double)(nt - 1) / (table->phi_hi - table->phi_lo) : 0.0;
+    I.tab64 = reinterpret_cast<const double2 *>(base);
+    I.tab32 = reinterpret_cast<const float4 *>(base + off_tab32);
+    I.all_S_pos = all_pos ? 1 : 0;
+    I.bias_kind = b.kind;
+    I.A = (b.kind == FPT_BIAS_CONST) ? b.A : 0.0;
+    I.instance = o.instance;
+    I.max_steps = (uint32_t)o.max_steps;
+    I.hist.bins_kind = o.bins_kind;
+    I.hist.n_bins = o.n_bins;
+    I.hist.lo = o.lo;
+    I.hist.N_ref = o.N_ref;
+    I.hist.scale = (o.bins_kind == FPT_BINS_LINEAR) ? (double)o.n_bins / (o.hi - o.lo)
                                                     : (double)o.n_bins / std::log(o.hi / o.lo);
-    p.cursor = reinterpret_cast<unsigned long long *>(base + off_cursor);
-    p.acc = base + off_acc;
-    p.instance = o.instance;
-    if (em_lds_bytes(p, c->precision) > c->lds_per_block_max) {
+    I.acc = base + off_acc;
+    c->cursor = reinterpret_cast<unsigned long long *>(base + off_cursor);
+    if (em_lds_bytes(o.n_bins, nt) > c->lds_per_block_max) {
         fpt_destroy(c);
         return fail(FPT_EINVAL, "noise table and histogram do not fit in LDS (%zu > %zu bytes)",
-                    em_lds_bytes(p, o.precision), (size_t)lds_max);
+                    em_lds_bytes(o.n_bins, nt), (size_t)lds_max);
     }
     *out = c;
     return FPT_OK;
 }
 
-static int launch_config(fpt_ctx *c, const EmParams &p, int &grid, int &block)
+static int occupancy_grid(const void *fn, int block, size_t lds, int cu_count, int per_cu, int &grid)
 {
-    block = c->opt.block_size ? c->opt.block_size : 1024;
-    int per_cu = c->opt.blocks_per_cu;
     if (per_cu == 0) {
         int occ = 0;
-        hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, em_kernel_ptr(p, c->precision), block,
-                                                                    em_lds_bytes(p, c->precision));
+        hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, fn, block, lds);
         if (e != hipSuccess) return hip_fail(e, "occupancy query");
         per_cu = occ > 0 ? occ : 1;
     }
-    grid = per_cu * c->cu_count;
+    grid = per_cu * cu_count;
     if (grid < 1) grid = 1;
     return FPT_OK;
 }
@@ -303,19 +298,24 @@ extern "C" int fpt_run(fpt_ctx *c, uint64_t n_traj, double dN, uint64_t seed, ui
     int dev = -1;
     HIP_TRY(hipGetDevice(&dev));
     if (dev != c->device) return fail(FPT_ESTATE, "current device %d differs from the context's %d", dev, c->device);
-    EmParams p = c->base;
-    p.dN = dN;
-    p.sqrt_dN = std::sqrt(dN);
-    p.key0 = (uint32_t)seed;
-    p.key1 = (uint32_t)(seed >> 32);
+    EmParams p{};
+    p.inst = c->inst;
+    p.run.dN = dN;
+    p.run.sqrt_dN = std::sqrt(dN);
+    p.run.key0 = (uint32_t)seed;
+    p.run.key1 = (uint32_t)(seed >> 32);
+    p.run.chunk = c->opt.chunk ? c->opt.chunk : 128;
     p.traj_offset = traj_offset;
     p.n_traj = n_traj;
-    p.chunk = c->opt.chunk ? c->opt.chunk : 128;
     p.d_N = d_N;
     p.d_lnw = d_lnw;
     p.d_steps = d_steps;
-    int grid = 0, block = 0;
-    int rc = launch_config(c, p, grid, block);
+    p.cursor = c->cursor;
+    const int block = c->opt.block_size ? c->opt.block_size : 1024;
+    int grid = 0;
+    const void *fn = em_kernel_ptr(c->precision, c->inst.bias_kind, c->inst.n_tab > 1, c->inst.all_S_pos != 0);
+    int rc = occupancy_grid(fn, block, em_lds_bytes(c->inst.hist.n_bins, c->inst.n_tab), c->cu_count,
+                            c->opt.blocks_per_cu, grid);
     if (rc) return rc;
     HIP_TRY(zero_words(p.cursor, 1, s));
     HIP_TRY(hipEventRecord(c->ev_start, s));
@@ -338,15 +338,11 @@ extern "C" int fpt_last_kernel_ms(fpt_ctx *c, double *ms)
     return FPT_OK;
 }
 
-extern "C" int fpt_histogram(fpt_ctx *c, fpt_hist *out)
+static int read_acc(const void *d_acc, int n_bins, fpt_hist *out, uint64_t n_traj_total)
 {
-    if (!c || !out) return fail(FPT_EINVAL, "NULL argument");
-    if (!out->count || !out->sum_w_bin || !out->sum_w2_bin || !out->sum_lnw_bin || !out->sum_lnw2_bin)
-        return fail(FPT_EINVAL, "histogram arrays are NULL");
-    if (c->ran) HIP_TRY(hipEventSynchronize(c->ev_done));
-    const int nb = c->opt.n_bins + 2;
-    std::vector<unsigned char> h(acc_bytes(c->opt.n_bins));
-    HIP_TRY(hipMemcpy(h.data(), c->base.acc, h.size(), hipMemcpyDeviceToHost));
+    const int nb = n_bins + 2;
+    std::vector<unsigned char> h(acc_bytes(n_bins));
+    HIP_TRY(hipMemcpy(h.data(), d_acc, h.size(), hipMemcpyDeviceToHost));
     const unsigned long long *cnt = reinterpret_cast<const unsigned long long *>(h.data());
     const double *sum = reinterpret_cast<const double *>(cnt + nb + 4);
     for (int i = 0; i < nb; ++i) {
@@ -356,7 +352,7 @@ extern "C" int fpt_histogram(fpt_ctx *c, fpt_hist *out)
         out->sum_lnw_bin[i] = sum[2 * nb + i];
         out->sum_lnw2_bin[i] = sum[3 * nb + i];
     }
-    out->n_traj = c->n_traj_total;
+    out->n_traj = n_traj_total;
     out->n_censored = cnt[nb + 0];
     out->n_ended_early = cnt[nb + 1];
     out->n_steps_total = cnt[nb + 2];
@@ -367,11 +363,21 @@ extern "C" int fpt_histogram(fpt_ctx *c, fpt_hist *out)
     return FPT_OK;
 }
 
+extern "C" int fpt_histogram(fpt_ctx *c, fpt_hist *out)
+{
+    if (!c || !out) return fail(FPT_EINVAL, "NULL argument");
+    if (!out->count || !out->sum_w_bin || !out->sum_w2_bin || !out->sum_lnw_bin || !out->sum_lnw2_bin)
+        return fail(FPT_EINVAL, "histogram arrays are NULL");
+    if (c->ran) HIP_TRY(hipEventSynchronize(c->ev_done));
+    HIP_TRY(hipDeviceSynchronize());
+    return read_acc(c->inst.acc, c->opt.n_bins, out, c->n_traj_total);
+}
+
 extern "C" int fpt_reset(fpt_ctx *c)
 {
     if (!c) return fail(FPT_EINVAL, "context is NULL");
-    if (c->ran) HIP_TRY(hipEventSynchronize(c->ev_done));
-    HIP_TRY(hipMemset(c->base.acc, 0, acc_bytes(c->opt.n_bins)));
+    HIP_TRY(hipDeviceSynchronize());
+    HIP_TRY(hipMemset(c->inst.acc, 0, acc_bytes(c->opt.n_bins)));
     HIP_TRY(hipDeviceSynchronize());
     c->n_traj_total = 0;
     return FPT_OK;
@@ -381,12 +387,404 @@ extern "C" void fpt_destroy(fpt_ctx *c)
 {
     if (!c) return;
     // teardown errors cannot be reported through a void function
-    if (c->ran && c->ev_done) (void)hipEventSynchronize(c->ev_done);
+    (void)hipDeviceSynchronize();
     if (c->ev_start) (void)hipEventDestroy(c->ev_start);
     if (c->ev_stop) (void)hipEventDestroy(c->ev_stop);
     if (c->ev_done) (void)hipEventDestroy(c->ev_done);
     if (c->d_mem) (void)hipFree(c->d_mem);
     delete c;
+}
+
+// ---------------------------------------------------------------------------
+// batches of instances: one persistent launch over many contexts
+// ---------------------------------------------------------------------------
+struct fpt_batch {
+    int device = 0, cu_count = 0;
+    size_t lds_max = 0;
+    int precision = 0, bias_kind = 0;
+    bool all_pos = true;
+    int n_inst = 0;
+    std::vector<fpt_ctx *> ctx;
+    int max_bins = 1, max_tab = 1;
+    int block = 1024, chunk = 128, item_size = 0;
+    bool use_graph = true;
+    std::vector<double> est_steps;          // mean steps per trajectory (0 = unknown)
+    Inst *d_inst = nullptr, *d_inst_probe = nullptr;
+    void *d_probe_acc = nullptr;
+    std::vector<size_t> probe_acc_off;
+    WorkItem *d_items = nullptr;
+    size_t items_cap = 0;
+    BatchRun *d_run = nullptr;
+    unsigned long long *d_item_cursor = nullptr;
+    WorkItem *h_items = nullptr;            // pinned staging
+    size_t h_items_cap = 0;
+    BatchRun *h_run = nullptr;              // pinned staging
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    hipStream_t graph_stream = nullptr;
+    int graph_block = 0;
+    const void *graph_items = nullptr;
+    hipEvent_t ev_start = nullptr, ev_stop = nullptr;
+    bool ran = false;
+};
+
+static void batch_free(fpt_batch *b)
+{
+    if (!b) return;
+    (void)hipDeviceSynchronize();
+    if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    if (b->d_inst) (void)hipFree(b->d_inst);
+    if (b->d_inst_probe) (void)hipFree(b->d_inst_probe);
+    if (b->d_probe_acc) (void)hipFree(b->d_probe_acc);
+    if (b->d_items) (void)hipFree(b->d_items);
+    if (b->d_run) (void)hipFree(b->d_run);
+    if (b->h_items) (void)hipHostFree(b->h_items);
+    if (b->h_run) (void)hipHostFree(b->h_run);
+    if (b->ev_start) (void)hipEventDestroy(b->ev_start);
+    if (b->ev_stop) (void)hipEventDestroy(b->ev_stop);
+    delete b;
+}
+
+extern "C" void fpt_batch_destroy(fpt_batch *b) { batch_free(b); }
+
+extern "C" int fpt_batch_create(fpt_ctx *const *ctx, int32_t n_inst, const fpt_batch_options *opts, fpt_batch **out)
+{
+    if (!out) return fail(FPT_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!ctx || n_inst < 1) return fail(FPT_EINVAL, "need at least one context");
+    fpt_batch_options o{};
+    if (opts) o = *opts;
+    if (o.block_size != 0 && (o.block_size < 64 || o.block_size > 1024 || o.block_size % 64))
+        return fail(FPT_EINVAL, "block_size must be a multiple of 64 in 64..1024");
+    if (o.chunk != 0 && (o.chunk < 4 || o.chunk % 4)) return fail(FPT_EINVAL, "chunk must be a positive multiple of 4");
+    if (o.item_size < 0) return fail(FPT_EINVAL, "item_size must be >= 0");
+    for (int i = 0; i < n_inst; ++i) {
+        if (!ctx[i]) return fail(FPT_EINVAL, "context %d is NULL", i);
+        if (ctx[i]->device != ctx[0]->device) return fail(FPT_EINVAL, "contexts live on different devices");
+        if (ctx[i]->precision != ctx[0]->precision) return fail(FPT_EINVAL, "contexts mix FP64 and FP32 state");
+    }
+    int dev = -1;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev != ctx[0]->device) return fail(FPT_ESTATE, "current device differs from the contexts'");
+    fpt_batch *b = new (std::nothrow) fpt_batch();
+    if (!b) return fail(FPT_ENOMEM, "host allocation failed");
+    b->device = ctx[0]->device;
+    b->cu_count = ctx[0]->cu_count;
+    b->lds_max = ctx[0]->lds_per_block_max;
+    b->precision = ctx[0]->precision;
+    b->n_inst = n_inst;
+    b->ctx.assign(ctx, ctx + n_inst);
+    b->est_steps.assign(n_inst, 0.0);
+    b->bias_kind = FPT_BIAS_NONE;
+    std::vector<Inst> h(n_inst), hp(n_inst);
+    size_t probe_bytes = 0;
+    for (int i = 0; i < n_inst; ++i) {
+        const Inst &I = ctx[i]->inst;
+        h[i] = I;
+        if (I.bias_kind == FPT_BIAS_CONST) b->bias_kind = FPT_BIAS_CONST;
+        b->all_pos = b->all_pos && I.all_S_pos;
+        b->max_bins = std::max(b->max_bins, I.hist.n_bins);
+        b->max_tab = std::max(b->max_tab, I.n_tab);
+        b->probe_acc_off.push_back(probe_bytes);
+        probe_bytes += acc_bytes(I.hist.n_bins);
+    }
+    if (em_lds_bytes(b->max_bins, b->max_tab) > b->lds_max) {
+        batch_free(b);
+        return fail(FPT_EINVAL, "largest table and histogram do not fit in LDS");
+    }
+    b->block = o.block_size ? o.block_size : 1024;
+    b->chunk = o.chunk ? o.chunk : 128;
+    b->item_size = o.item_size;
+    b->use_graph = o.use_graph != 0;
+    hipError_t e = hipMalloc(&b->d_inst, sizeof(Inst) * n_inst);
+    if (e == hipSuccess) e = hipMalloc(&b->d_inst_probe, sizeof(Inst) * n_inst);
+    if (e == hipSuccess) e = hipMalloc(&b->d_probe_acc, probe_bytes);
+    if (e == hipSuccess) e = hipMalloc(&b->d_run, 256 + sizeof(BatchRun));
+    if (e == hipSuccess) e = hipHostMalloc(&b->h_run, sizeof(BatchRun));
+    if (e == hipSuccess) e = hipEventCreate(&b->ev_start);
+    if (e == hipSuccess) e = hipEventCreate(&b->ev_stop);
+    if (e == hipSuccess) {
+        static_assert(sizeof(BatchRun) <= 128, "run parameters and cursor share one allocation");
+        b->d_item_cursor = reinterpret_cast<unsigned long long *>(reinterpret_cast<unsigned char *>(b->d_run) + 128);
+        for (int i = 0; i < n_inst; ++i) {
+            hp[i] = h[i];
+            hp[i].acc = static_cast<unsigned char *>(b->d_probe_acc) + b->probe_acc_off[i];
+        }
+        e = hipMemcpy(b->d_inst, h.data(), sizeof(Inst) * n_inst, hipMemcpyHostToDevice);
+    }
+    if (e == hipSuccess) e = hipMemcpy(b->d_inst_probe, hp.data(), sizeof(Inst) * n_inst, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        batch_free(b);
+        return hip_fail(e, "fpt_batch_create");
+    }
+    *out = b;
+    return FPT_OK;
+}
+
+static int ensure_items(fpt_batch *b, size_t n)
+{
+    if (n > b->items_cap) {
+        if (b->d_items) HIP_TRY(hipFree(b->d_items));
+        b->d_items = nullptr;
+        size_t cap = std::max<size_t>(n, 2 * b->items_cap);
+        HIP_TRY(hipMalloc(&b->d_items, sizeof(WorkItem) * cap));
+        b->items_cap = cap;
+    }
+    if (n > b->h_items_cap) {
+        if (b->h_items) HIP_TRY(hipHostFree(b->h_items));
+        b->h_items = nullptr;
+        size_t cap = std::max<size_t>(n, 2 * b->h_items_cap);
+        HIP_TRY(hipHostMalloc(&b->h_items, sizeof(WorkItem) * cap));
+        b->h_items_cap = cap;
+    }
+    return FPT_OK;
+}
+
+// Work items of every instance, longest estimated cost first (longest-processing-time order).
+static std::vector<WorkItem> make_items(const fpt_batch *b, const uint64_t *n_traj, uint64_t traj_offset,
+                                        int item_size)
+{
+    std::vector<WorkItem> items;
+    std::vector<double> cost;
+    for (int i = 0; i < b->n_inst; ++i) {
+        const double steps = b->est_steps[i] > 0.0 ? b->est_steps[i] : 1.0;
+        for (uint64_t k = 0; k < n_traj[i]; k += (uint64_t)item_size) {
+            WorkItem w{};
+            w.inst = (uint32_t)i;
+            w.begin = traj_offset + k;
+            w.count = std::min<uint64_t>((uint64_t)item_size, n_traj[i] - k);
+            items.push_back(w);
+            cost.push_back(steps * (double)w.count);
+        }
+    }
+    std::vector<size_t> order(items.size());
+    for (size_t k = 0; k < order.size(); ++k) order[k] = k;
+    std::stable_sort(order.begin(), order.end(), [&](size_t x, size_t y) { return cost[x] > cost[y]; });
+    std::vector<WorkItem> sorted(items.size());
+    for (size_t k = 0; k < order.size(); ++k) sorted[k] = items[order[k]];
+    return sorted;
+}
+
+// One persistent launch over `items` with descriptors `d_inst` (direct, or through a captured graph).
+static int batch_launch_items(fpt_batch *b, const std::vector<WorkItem> &items, const Inst *d_inst, double dN,
+                              uint64_t seed, int block, int chunk, hipStream_t s, bool graph)
+{
+    int rc = ensure_items(b, items.size());
+    if (rc) return rc;
+    if (b->ran) HIP_TRY(hipEventSynchronize(b->ev_stop));   // the previous launch has read its items
+    std::copy(items.begin(), items.end(), b->h_items);
+    b->h_run->run.dN = dN;
+    b->h_run->run.sqrt_dN = std::sqrt(dN);
+    b->h_run->run.key0 = (uint32_t)seed;
+    b->h_run->run.key1 = (uint32_t)(seed >> 32);
+    b->h_run->run.chunk = chunk;
+    b->h_run->n_items = items.size();
+    HIP_TRY(hipMemcpyAsync(b->d_items, b->h_items, sizeof(WorkItem) * items.size(), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(b->d_run, b->h_run, sizeof(BatchRun), hipMemcpyHostToDevice, s));
+    const void *fn = batch_kernel_ptr(b->precision, b->bias_kind, b->all_pos);
+    int grid = 0;
+    rc = occupancy_grid(fn, block, em_lds_bytes(b->max_bins, b->max_tab), b->cu_count, 0, grid);
+    if (rc) return rc;
+    if (graph) {
+        if (!b->gexec || b->graph_stream != s || b->graph_block != block || b->graph_items != b->d_items) {
+            if (b->gexec) HIP_TRY(hipGraphExecDestroy(b->gexec));
+            if (b->graph) HIP_TRY(hipGraphDestroy(b->graph));
+            b->gexec = nullptr;
+            b->graph = nullptr;
+            HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+            hipError_t e1 = zero_words(b->d_item_cursor, 1, s);
+            hipError_t e2 = batch_launch(b->precision, b->bias_kind, b->all_pos, d_inst, b->d_items, b->d_run,
+                                         b->d_item_cursor, b->max_bins, b->max_tab, grid, block, s);
+            hipError_t e3 = hipStreamEndCapture(s, &b->graph);
+            if (e1 != hipSuccess) return hip_fail(e1, "capture: cursor reset");
+            if (e2 != hipSuccess) return hip_fail(e2, "capture: batch kernel");
+            if (e3 != hipSuccess) return hip_fail(e3, "hipStreamEndCapture");
+            HIP_TRY(hipGraphInstantiate(&b->gexec, b->graph, nullptr, nullptr, 0));
+            b->graph_stream = s;
+            b->graph_block = block;
+            b->graph_items = b->d_items;
+        }
+        HIP_TRY(hipEventRecord(b->ev_start, s));
+        HIP_TRY(hipGraphLaunch(b->gexec, s));
+        HIP_TRY(hipEventRecord(b->ev_stop, s));
+    } else {
+        HIP_TRY(zero_words(b->d_item_cursor, 1, s));
+        HIP_TRY(hipEventRecord(b->ev_start, s));
+        HIP_TRY(batch_launch(b->precision, b->bias_kind, b->all_pos, d_inst, b->d_items, b->d_run,
+                             b->d_item_cursor, b->max_bins, b->max_tab, grid, block, s));
+        HIP_TRY(hipEventRecord(b->ev_stop, s));
+    }
+    b->ran = true;
+    return FPT_OK;
+}
+
+static int check_batch_run(fpt_batch *b, const uint64_t *n_traj, double dN, uint64_t traj_offset)
+{
+    if (!b || !n_traj) return fail(FPT_EINVAL, "NULL argument");
+    if (!(dN > 0.0) || !is_finite(dN)) return fail(FPT_EINVAL, "dN must be finite and > 0");
+    for (int i = 0; i < b->n_inst; ++i)
+        if (traj_offset + n_traj[i] < traj_offset) return fail(FPT_EINVAL, "trajectory range overflows 64 bits");
+    int dev = -1;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev != b->device) return fail(FPT_ESTATE, "current device differs from the batch's");
+    return FPT_OK;
+}
+
+extern "C" int fpt_batch_run(fpt_batch *b, const uint64_t *n_traj, double dN, uint64_t seed, uint64_t traj_offset,
+                             void *hip_stream)
+{
+    int rc = check_batch_run(b, n_traj, dN, traj_offset);
+    if (rc) return rc;
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    const int item_size = b->item_size ? b->item_size : 16 * b->block;
+    std::vector<WorkItem> items = make_items(b, n_traj, traj_offset, item_size);
+    if (items.empty()) return FPT_OK;
+    // graph capture needs a stream other than the legacy null stream
+    rc = batch_launch_items(b, items, b->d_inst, dN, seed, b->block, b->chunk, s, b->use_graph && s != nullptr);
+    if (rc) return rc;
+    for (int i = 0; i < b->n_inst; ++i) {
+        b->ctx[i]->n_traj_total += n_traj[i];
+        b->ctx[i]->ran = false;     // its accumulators were written by the batch: fpt_histogram syncs the device
+    }
+    return FPT_OK;
+}
+
+extern "C" int fpt_batch_last_ms(fpt_batch *b, double *ms)
+{
+    if (!b || !ms) return fail(FPT_EINVAL, "NULL argument");
+    if (!b->ran) return fail(FPT_ESTATE, "no batch run recorded");
+    HIP_TRY(hipEventSynchronize(b->ev_stop));
+    float f = 0.0f;
+    HIP_TRY(hipEventElapsedTime(&f, b->ev_start, b->ev_stop));
+    *ms = (double)f;
+    return FPT_OK;
+}
+
+extern "C" int fpt_batch_config(fpt_batch *b, int32_t *block_size, int32_t *chunk)
+{
+    if (!b) return fail(FPT_EINVAL, "NULL argument");
+    if (block_size) *block_size = b->block;
+    if (chunk) *chunk = b->chunk;
+    return FPT_OK;
+}
+
+// Steps taken per instance in the probe accumulators (and zero them).
+static int probe_steps(fpt_batch *b, std::vector<uint64_t> &steps)
+{
+    steps.assign(b->n_inst, 0);
+    for (int i = 0; i < b->n_inst; ++i) {
+        const int nb = b->ctx[i]->inst.hist.n_bins + 2;
+        unsigned long long w = 0;
+        const unsigned char *acc = static_cast<unsigned char *>(b->d_probe_acc) + b->probe_acc_off[i];
+        HIP_TRY(hipMemcpy(&w, acc + sizeof(unsigned long long) * (nb + 2), sizeof w, hipMemcpyDeviceToHost));
+        steps[i] = w;
+    }
+    size_t total = b->probe_acc_off.back() + acc_bytes(b->ctx.back()->inst.hist.n_bins);
+    HIP_TRY(hipMemset(b->d_probe_acc, 0, total));
+    return FPT_OK;
+}
+
+static std::string tune_key(const fpt_batch *b)
+{
+    hipDeviceProp_t prop{};
+    std::string arch = "unknown";
+    if (hipGetDeviceProperties(&prop, b->device) == hipSuccess) arch = prop.gcnArchName;
+    char buf[256];
+    snprintf(buf, sizeof buf, "%s/cu%d/prec%d/bias%d/pos%d/inst%d/tab%d/bins%d", arch.c_str(), b->cu_count,
+             b->precision, b->bias_kind, b->all_pos ? 1 : 0, b->n_inst, b->max_tab, b->max_bins);
+    for (char &ch : buf)
+        if (ch == ' ') ch = '_';
+    return buf;
+}
+
+extern "C" int fpt_batch_autotune(fpt_batch *b, const uint64_t *n_traj, double dN, uint64_t seed,
+                                  const char *cache_path, void *hip_stream)
+{
+    int rc = check_batch_run(b, n_traj, dN, 0);
+    if (rc) return rc;
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    const std::string key = tune_key(b);
+    if (cache_path) {
+        FILE *f = fopen(cache_path, "r");
+        if (f) {
+            char k[256];
+            int blk = 0, chk = 0;
+            bool found = false;
+            while (fscanf(f, "%255s %d %d", k, &blk, &chk) == 3)
+                if (key == k && blk >= 64 && blk <= 1024 && blk % 64 == 0 && chk >= 4 && chk % 4 == 0) {
+                    b->block = blk;
+                    b->chunk = chk;
+                    found = true;
+                }
+            fclose(f);
+            if (found) return FPT_OK;
+        }
+    }
+    // probe: one trajectory per lane of a full grid, spread over the instances in proportion to
+    // their counts, with a step cap so that each probe launch stays short; the probe's results
+    // go to private accumulators and trajectory indices beyond 2^62.
+    std::vector<Inst> hp(b->n_inst);
+    HIP_TRY(hipMemcpy(hp.data(), b->d_inst_probe, sizeof(Inst) * b->n_inst, hipMemcpyDeviceToHost));
+    const uint32_t probe_cap = 1u << 15;
+    for (Inst &I : hp) I.max_steps = std::min(I.max_steps, probe_cap);
+    HIP_TRY(hipMemcpy(b->d_inst_probe, hp.data(), sizeof(Inst) * b->n_inst, hipMemcpyHostToDevice));
+    double total = 0.0;
+    for (int i = 0; i < b->n_inst; ++i) total += (double)n_traj[i];
+    if (!(total > 0.0)) return fail(FPT_EINVAL, "no trajectories to tune on");
+    const double lanes = (double)b->cu_count * 2048.0;
+    std::vector<uint64_t> probe_n(b->n_inst);
+    for (int i = 0; i < b->n_inst; ++i)
+        probe_n[i] = n_traj[i] ? std::max<uint64_t>(64, (uint64_t)(lanes * (double)n_traj[i] / total)) : 0;
+    std::vector<uint64_t> steps;
+    rc = probe_steps(b, steps);   // zero
+    if (rc) return rc;
+    const int blocks[] = {256, 512, 1024};
+    const int chunks[] = {32, 64, 128, 256};
+    double best = -1.0;
+    int best_block = b->block, best_chunk = b->chunk;
+    const uint64_t probe_offset = 1ull << 62;
+    for (int blk : blocks)
+        for (int chk : chunks) {
+            std::vector<WorkItem> items = make_items(b, probe_n.data(), probe_offset, 4 * blk);
+            rc = batch_launch_items(b, items, b->d_inst_probe, dN, seed, blk, chk, s, false);
+            if (rc) return rc;
+            double ms = 0.0;
+            rc = fpt_batch_last_ms(b, &ms);
+            if (rc) return rc;
+            rc = probe_steps(b, steps);
+            if (rc) return rc;
+            double n_steps = 0.0;
+            for (uint64_t v : steps) n_steps += (double)v;
+            const double rate = n_steps / std::max(ms, 1e-3);
+            if (rate > best) {
+                best = rate;
+                best_block = blk;
+                best_chunk = chk;
+            }
+        }
+    b->block = best_block;
+    b->chunk = best_chunk;
+    // mean steps per trajectory of each instance under its own cap, for the work order
+    for (int i = 0; i < b->n_inst; ++i) hp[i].max_steps = b->ctx[i]->inst.max_steps;
+    HIP_TRY(hipMemcpy(b->d_inst_probe, hp.data(), sizeof(Inst) * b->n_inst, hipMemcpyHostToDevice));
+    std::vector<uint64_t> few(b->n_inst);
+    for (int i = 0; i < b->n_inst; ++i) few[i] = n_traj[i] ? 64 : 0;
+    std::vector<WorkItem> items = make_items(b, few.data(), probe_offset, 64);
+    rc = batch_launch_items(b, items, b->d_inst_probe, dN, seed, best_block, best_chunk, s, false);
+    if (rc) return rc;
+    HIP_TRY(hipEventSynchronize(b->ev_stop));
+    rc = probe_steps(b, steps);
+    if (rc) return rc;
+    for (int i = 0; i < b->n_inst; ++i) b->est_steps[i] = few[i] ? (double)steps[i] / (double)few[i] : 0.0;
+    if (cache_path) {
+        FILE *f = fopen(cache_path, "a");
+        if (f) {
+            fprintf(f, "%s %d %d\n", key.c_str(), best_block, best_chunk);
+            fclose(f);
+        }
+    }
+    return FPT_OK;
 }
 
 extern "C" const char *fpt_strerror(int status)

@@ -186,19 +186,6 @@ struct RetireTo {
     HistSpec hist;
 };
 
-__device__ __forceinline__ RetireTo retire_to(const EmParams &p, const LdsAcc &a)
-{
-    RetireTo r;
-    r.d_N = p.d_N;
-    r.d_lnw = p.d_lnw;
-    r.d_steps = p.d_steps;
-    r.cnt = a.cnt;
-    r.sum = a.sum;
-    r.nb = a.nb;
-    r.hist = p.hist;
-    return r;
-}
-
 // Retire one finished trajectory: per-trajectory outputs and LDS histogram.
 __device__ __forceinline__ void retire(const RetireTo &t, uint64_t rel, uint32_t status, uint32_t n_steps, double N,
                                        double lnw)
@@ -251,59 +238,68 @@ struct DriftConsts {
     double kx, s_plus, s_minus;
 };
 
-__host__ __device__ inline DriftConsts drift_consts(const EmParams &p)
+__device__ __forceinline__ DriftConsts drift_consts(const Inst &I)
 {
     DriftConsts k;
-    if (p.pot_kind == kPotExponential) {
+    if (I.pot_kind == kPotExponential) {
         k.kx = 0.0;
-        k.s_plus = k.s_minus = 1.0 / p.A_plus;
+        k.s_plus = k.s_minus = 1.0 / I.A_plus;
     } else {
         k.kx = 1.0;
-        k.s_plus = -(p.phi_T - p.V0 / p.A_plus);
-        k.s_minus = -(p.phi_T - p.V0 / p.A_minus);
+        k.s_plus = -(I.phi_T - I.V0 / I.A_plus);
+        k.s_minus = -(I.phi_T - I.V0 / I.A_minus);
     }
     return k;
 }
 
+// The table size used by the kernels: a single node (constant noise) is
+// staged as two equal nodes so one lookup serves every table.
+__device__ __forceinline__ int staged_nodes(const Inst &I) { return I.n_tab > 1 ? I.n_tab : 2; }
+
+__device__ __forceinline__ void stage_table64(const Inst &I, double2 *l_tab)
+{
+    const int n = staged_nodes(I);
+    for (int i = threadIdx.x; i < n; i += blockDim.x) l_tab[i] = I.tab64[I.n_tab > 1 ? i : 0];
+}
+
+__device__ __forceinline__ void stage_table32(const Inst &I, float4 *l_tab)
+{
+    const int n = staged_nodes(I);
+    for (int i = threadIdx.x; i < n; i += blockDim.x) l_tab[i] = I.tab32[I.n_tab > 1 ? i : 0];
+}
+
 // ---------------------------------------------------------------------------
-// FP64 state
-// ---------------------------------------------------------------------------
+// FP64 state: the lanes of one wave integrate trajectories of instance I,
+// claimed from `cursor` (global or LDS), until the range is exhausted.
 //
 // Steps are taken in groups of four (one Philox call).  Inside a group every
 // lane computes every step; a lane whose trajectory ended earlier in the chunk
 // keeps integrating a discarded state until the chunk ends and it is refilled,
 // which keeps the group free of per-step exec-mask bookkeeping.  The end of a
-// trajectory (first passage, eps_1 >= 1) is handled in a branch that is taken
-// about once per 1e4-1e5 steps.  Censoring at max_steps needs a test before
-// every step, so groups that can reach max_steps take a separate variant.
+// trajectory (first passage, eps_1 >= 1) is recorded in a branch that is taken
+// about once per 1e4-1e5 steps and retired once the group is done.  Censoring
+// at max_steps needs a test before every step, so groups that can reach
+// max_steps take a separate variant.
+// ---------------------------------------------------------------------------
 template <int BIAS, bool TAB, bool ALLPOS>
-__global__ void __launch_bounds__(1024) FPT_EM_OCCUPANCY em_fp64_kernel(EmParams p, DriftConsts dk)
+__device__ __forceinline__ void lanes_fp64(const Inst &I, const RunArgs &R, const double2 *l_tab, const RetireTo &rt,
+                                           unsigned long long *cursor, uint64_t n_traj, uint64_t traj_offset)
 {
-    extern __shared__ __align__(16) unsigned char smem[];
-    const LdsAcc acc = lds_acc(smem, p.hist.n_bins);
-    double2 *l_tab = reinterpret_cast<double2 *>(acc.sum + 4 * acc.nb + 4);
-    zero_lds_acc(acc);
-    if (TAB)
-        for (int i = threadIdx.x; i < p.n_tab; i += blockDim.x) l_tab[i] = p.tab64[i];
-    __syncthreads();
-
-    const RetireTo rt = retire_to(p, acc);
-    const double S0 = p.tab64[0].x, t0 = p.tab64[0].y;
-    const double dN = p.dN, sqrt_dN = p.sqrt_dN, phi_end = p.phi_end, phi_T = p.phi_T;
-    const double a = (BIAS == kBiasConst) ? p.A : 0.0;
+    const DriftConsts dk = drift_consts(I);
+    const double S0 = l_tab[0].x, t0 = l_tab[0].y;
+    const double dN = R.dN, sqrt_dN = R.sqrt_dN, phi_end = I.phi_end, phi_T = I.phi_T;
+    const double a = (BIAS == kBiasConst) ? I.A : 0.0;
     const double half_a2_dN = 0.5 * a * a * dN;
-    const double jmax = (double)(p.n_tab - 2);
+    const double jmax = (double)(staged_nodes(I) - 2);
     const double s_plus = in_vgpr(dk.s_plus), s_minus = in_vgpr(dk.s_minus);
 
     bool exhausted = false;
     uint64_t rel = 0;
-    bool has = claim(true, rel, p.cursor, p.n_traj, exhausted);
+    bool has = claim(true, rel, cursor, n_traj, exhausted);
     bool live = has;          // has a trajectory that has not ended yet
-    double phi = p.phi_in, pi_ = p.pi_in, lnw = 0.0;
-    uint32_t n = 0, n_on = 0;
+    double phi = I.phi_in, pi_ = I.pi_in, lnw = 0.0;
+    uint32_t n = 0;
 
-    // The end of a trajectory inside a group is recorded here and retired once
-    // the group's four steps are done.
     auto group = [&](auto censor_tag, const double z[4]) {
         constexpr bool CENSOR = decltype(censor_tag)::value;
         bool fresh = false;
@@ -311,7 +307,7 @@ __global__ void __launch_bounds__(1024) FPT_EM_OCCUPANCY em_fp64_kernel(EmParams
         double ev_N, ev_lnw;
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-            if (CENSOR && live && n == p.max_steps) {
+            if (CENSOR && live && n == I.max_steps) {
                 ev_status = kFlagCensored;
                 ev_n = n;
                 ev_N = __builtin_nan("");
@@ -325,7 +321,7 @@ __global__ void __launch_bounds__(1024) FPT_EM_OCCUPANCY em_fp64_kernel(EmParams
             r = fma(r, fma(-d, r, 1.0), r);
             double S, t;
             if (TAB) {
-                const double x = (phi - p.phi_lo) * p.inv_h;
+                const double x = (phi - I.phi_lo) * I.inv_h;
                 const double jf = fmin(fmax(floor(x), 0.0), jmax);
                 const double f = fmin(fmax(x - jf, 0.0), 1.0);
                 const int jj = (int)jf;
@@ -366,30 +362,27 @@ __global__ void __launch_bounds__(1024) FPT_EM_OCCUPANCY em_fp64_kernel(EmParams
     };
 
     while (__any(has)) {
-        for (int k = 0; k < p.chunk; k += 4) {
+        for (int k = 0; k < R.chunk; k += 4) {
             if (!__any(live)) break;
-            const uint64_t traj = p.traj_offset + rel;
+            const uint64_t traj = traj_offset + rel;
             uint32_t w[4];
-            philox4x32_10(n >> 2, (uint32_t)traj, (uint32_t)(traj >> 32), p.instance, p.key0, p.key1, w);
+            philox4x32_10(n >> 2, (uint32_t)traj, (uint32_t)(traj >> 32), I.instance, R.key0, R.key1, w);
             double z[4];
             box_muller64(w[0], w[1], sqrt_dN, z[0], z[1]);
             box_muller64(w[2], w[3], sqrt_dN, z[2], z[3]);
-            if (__any(live && n + 4 > p.max_steps)) group(std::integral_constant<bool, true>(), z);
+            if (__any(live && n + 4 > I.max_steps)) group(std::integral_constant<bool, true>(), z);
             else group(std::integral_constant<bool, false>(), z);
         }
         if (!live) has = false;
-        if (claim(!has, rel, p.cursor, p.n_traj, exhausted)) {
+        if (claim(!has, rel, cursor, n_traj, exhausted)) {
             has = true;
             live = true;
-            phi = p.phi_in;
-            pi_ = p.pi_in;
+            phi = I.phi_in;
+            pi_ = I.pi_in;
             lnw = 0.0;
             n = 0;
         }
     }
-    (void)n_on;
-    __syncthreads();
-    flush_lds_acc(acc, p.acc);
 }
 
 // ---------------------------------------------------------------------------
@@ -405,6 +398,29 @@ struct F32Consts {
     float a;
 };
 
+__device__ __forceinline__ F32Consts f32_consts(const Inst &I, const RunArgs &R)
+{
+    F32Consts c;
+    const double xT = I.phi_T - I.phi_end;
+    c.xT_hi = (float)xT;
+    c.xT_lo = (float)(xT - (double)c.xT_hi);
+    if (I.pot_kind == kPotExponential) {
+        c.kx = 0.0f;
+        c.s_plus = c.s_minus = (float)(1.0 / I.A_plus);
+    } else {
+        c.kx = 1.0f;
+        c.s_plus = (float)(I.V0 / I.A_plus);
+        c.s_minus = (float)(I.V0 / I.A_minus);
+    }
+    c.u_off = (float)((I.phi_end - I.phi_lo) * I.inv_h);
+    c.inv_h = (float)I.inv_h;
+    c.jmax = (float)(staged_nodes(I) - 2);
+    c.dN = (float)R.dN;
+    c.sqrt_dN = (float)R.sqrt_dN;
+    c.a = (I.bias_kind == kBiasConst) ? (float)I.A : 0.0f;
+    return c;
+}
+
 __device__ __forceinline__ void two_sum_fast(float &hi, float &lo, float d)
 {
     // hi + lo += d with |hi| >= |d| (Fast2Sum of hi and d, error folded into lo)
@@ -415,28 +431,22 @@ __device__ __forceinline__ void two_sum_fast(float &hi, float &lo, float d)
 }
 
 template <int BIAS, bool TAB, bool ALLPOS>
-__global__ void __launch_bounds__(1024) FPT_EM_OCCUPANCY em_fp32s_kernel(EmParams p, F32Consts c)
+__device__ __forceinline__ void lanes_fp32(const Inst &I, const RunArgs &R, const float4 *l_tab, const RetireTo &rt,
+                                           unsigned long long *cursor, uint64_t n_traj, uint64_t traj_offset)
 {
-    extern __shared__ __align__(16) unsigned char smem[];
-    const LdsAcc acc = lds_acc(smem, p.hist.n_bins);
-    float4 *l_tab = reinterpret_cast<float4 *>(acc.sum + 4 * acc.nb + 4);
-    zero_lds_acc(acc);
-    if (TAB)
-        for (int i = threadIdx.x; i < p.n_tab; i += blockDim.x) l_tab[i] = p.tab32[i];
-    __syncthreads();
-
-    const RetireTo rt = retire_to(p, acc);
-    const float S0 = p.tab32[0].x, t0 = p.tab32[0].z;
-    const double x_in = p.phi_in - p.phi_end;
+    const F32Consts c = f32_consts(I, R);
+    const float S0 = l_tab[0].x, t0 = l_tab[0].z;
+    const double x_in = I.phi_in - I.phi_end;
     const float x_in_hi = (float)x_in, x_in_lo = (float)(x_in - (double)x_in_hi);
-    const float pi_in_hi = (float)p.pi_in, pi_in_lo = (float)(p.pi_in - (double)pi_in_hi);
-    const double dN = p.dN;
-    const double half_a2_dN = 0.5 * p.A * p.A * dN;
+    const float pi_in_hi = (float)I.pi_in, pi_in_lo = (float)(I.pi_in - (double)pi_in_hi);
+    const double dN = R.dN;
+    const double A = (BIAS == kBiasConst) ? I.A : 0.0;
+    const double half_a2_dN = 0.5 * A * A * dN;
     const float s_plus = in_vgpr(c.s_plus), s_minus = in_vgpr(c.s_minus);
 
     bool exhausted = false;
     uint64_t rel = 0;
-    bool has = claim(true, rel, p.cursor, p.n_traj, exhausted);
+    bool has = claim(true, rel, cursor, n_traj, exhausted);
     bool live = has;          // has a trajectory that has not ended yet
     float xh = x_in_hi, xl = x_in_lo, ph = pi_in_hi, pl = pi_in_lo;
     double zsum = 0.0;        // sum of xi sqrt(dN) over steps with S > 0 (constant bias)
@@ -444,11 +454,9 @@ __global__ void __launch_bounds__(1024) FPT_EM_OCCUPANCY em_fp32s_kernel(EmParam
     uint32_t n = 0;
 
     auto lnw_of = [&](double zs_total, uint32_t steps_on) -> double {
-        return (BIAS == kBiasNone) ? 0.0 : -p.A * zs_total - (double)steps_on * half_a2_dN;
+        return (BIAS == kBiasNone) ? 0.0 : -A * zs_total - (double)steps_on * half_a2_dN;
     };
 
-    // The end of a trajectory inside a group is recorded here and retired once
-    // the group's four steps are done.
     auto group = [&](auto censor_tag, const float z[4]) {
         constexpr bool CENSOR = decltype(censor_tag)::value;
         float zacc = 0.0f;
@@ -457,7 +465,7 @@ __global__ void __launch_bounds__(1024) FPT_EM_OCCUPANCY em_fp32s_kernel(EmParam
         double ev_N, ev_lnw;
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-            if (CENSOR && live && n == p.max_steps) {
+            if (CENSOR && live && n == I.max_steps) {
                 ev_status = kFlagCensored;
                 ev_n = n;
                 ev_N = __builtin_nan("");
@@ -523,19 +531,19 @@ __global__ void __launch_bounds__(1024) FPT_EM_OCCUPANCY em_fp32s_kernel(EmParam
     };
 
     while (__any(has)) {
-        for (int k = 0; k < p.chunk; k += 4) {
+        for (int k = 0; k < R.chunk; k += 4) {
             if (!__any(live)) break;
-            const uint64_t traj = p.traj_offset + rel;
+            const uint64_t traj = traj_offset + rel;
             uint32_t w[4];
-            philox4x32_10(n >> 2, (uint32_t)traj, (uint32_t)(traj >> 32), p.instance, p.key0, p.key1, w);
+            philox4x32_10(n >> 2, (uint32_t)traj, (uint32_t)(traj >> 32), I.instance, R.key0, R.key1, w);
             float z[4];
             box_muller32(w[0], w[1], c.sqrt_dN, z[0], z[1]);
             box_muller32(w[2], w[3], c.sqrt_dN, z[2], z[3]);
-            if (__any(live && n + 4 > p.max_steps)) group(std::integral_constant<bool, true>(), z);
+            if (__any(live && n + 4 > I.max_steps)) group(std::integral_constant<bool, true>(), z);
             else group(std::integral_constant<bool, false>(), z);
         }
         if (!live) has = false;
-        if (claim(!has, rel, p.cursor, p.n_traj, exhausted)) {
+        if (claim(!has, rel, cursor, n_traj, exhausted)) {
             has = true;
             live = true;
             xh = x_in_hi;
@@ -547,8 +555,97 @@ __global__ void __launch_bounds__(1024) FPT_EM_OCCUPANCY em_fp32s_kernel(EmParam
             n = 0;
         }
     }
+}
+
+// ---------------------------------------------------------------------------
+// Single-problem kernels: a persistent grid over one instance.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ RetireTo retire_to(const EmParams &p, const LdsAcc &a)
+{
+    RetireTo r;
+    r.d_N = p.d_N;
+    r.d_lnw = p.d_lnw;
+    r.d_steps = p.d_steps;
+    r.cnt = a.cnt;
+    r.sum = a.sum;
+    r.nb = a.nb;
+    r.hist = p.inst.hist;
+    return r;
+}
+
+template <int PREC, int BIAS, bool TAB, bool ALLPOS>
+__global__ void __launch_bounds__(1024) FPT_EM_OCCUPANCY em_kernel(EmParams p)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const LdsAcc acc = lds_acc(smem, p.inst.hist.n_bins);
+    void *l_tab = acc.sum + 4 * acc.nb + 4;
+    zero_lds_acc(acc);
+    if (PREC == 0) stage_table64(p.inst, static_cast<double2 *>(l_tab));
+    else stage_table32(p.inst, static_cast<float4 *>(l_tab));
     __syncthreads();
-    flush_lds_acc(acc, p.acc);
+    const RetireTo rt = retire_to(p, acc);
+    if (PREC == 0)
+        lanes_fp64<BIAS, TAB, ALLPOS>(p.inst, p.run, static_cast<const double2 *>(l_tab), rt, p.cursor, p.n_traj,
+                                      p.traj_offset);
+    else
+        lanes_fp32<BIAS, TAB, ALLPOS>(p.inst, p.run, static_cast<const float4 *>(l_tab), rt, p.cursor, p.n_traj,
+                                      p.traj_offset);
+    __syncthreads();
+    flush_lds_acc(acc, p.inst.acc);
+}
+
+// ---------------------------------------------------------------------------
+// Batch kernel: a persistent grid over many instances.  A block takes one
+// work item (a slice of one instance's trajectories) at a time from a global
+// queue ordered longest-first, stages that instance's table and histogram in
+// LDS, lets its waves claim the slice's trajectories from an LDS cursor,
+// flushes the histogram to the instance's accumulators and takes the next
+// item.  The run parameters are read from device memory so that a captured
+// graph can be replayed with a new seed or time step.
+// ---------------------------------------------------------------------------
+template <int PREC, int BIAS, bool ALLPOS>
+__global__ void __launch_bounds__(1024) FPT_EM_OCCUPANCY batch_kernel(const Inst *insts, const WorkItem *items,
+                                                                      const BatchRun *brun,
+                                                                      unsigned long long *item_cursor, int max_bins)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ unsigned long long s_item, s_cursor;
+    const RunArgs R = brun->run;
+    const uint64_t n_items = brun->n_items;
+    for (;;) {
+        if (threadIdx.x == 0) {
+            s_item = atomicAdd(item_cursor, 1ull);
+            s_cursor = 0ull;
+        }
+        __syncthreads();
+        const uint64_t it = s_item;
+        if (it >= n_items) break;
+        const WorkItem W = items[it];
+        const Inst I = insts[W.inst];
+        const LdsAcc acc = lds_acc(smem, I.hist.n_bins);
+        void *l_tab = reinterpret_cast<unsigned char *>(smem) + acc_bytes(max_bins);
+        zero_lds_acc(acc);
+        if (PREC == 0) stage_table64(I, static_cast<double2 *>(l_tab));
+        else stage_table32(I, static_cast<float4 *>(l_tab));
+        __syncthreads();
+        RetireTo rt;
+        rt.d_N = nullptr;
+        rt.d_lnw = nullptr;
+        rt.d_steps = nullptr;
+        rt.cnt = acc.cnt;
+        rt.sum = acc.sum;
+        rt.nb = acc.nb;
+        rt.hist = I.hist;
+        if (PREC == 0)
+            lanes_fp64<BIAS, true, ALLPOS>(I, R, static_cast<const double2 *>(l_tab), rt, &s_cursor, W.count,
+                                           W.begin);
+        else
+            lanes_fp32<BIAS, true, ALLPOS>(I, R, static_cast<const float4 *>(l_tab), rt, &s_cursor, W.count,
+                                           W.begin);
+        __syncthreads();
+        flush_lds_acc(acc, I.acc);
+        __syncthreads();
+    }
 }
 
 __global__ void zero_words_kernel(unsigned long long *ptr, size_t n)
@@ -557,78 +654,60 @@ __global__ void zero_words_kernel(unsigned long long *ptr, size_t n)
         ptr[i] = 0ull;
 }
 
-F32Consts make_f32_consts(const EmParams &p)
-{
-    F32Consts c;
-    const double xT = p.phi_T - p.phi_end;
-    c.xT_hi = (float)xT;
-    c.xT_lo = (float)(xT - (double)c.xT_hi);
-    if (p.pot_kind == kPotExponential) {
-        c.kx = 0.0f;
-        c.s_plus = c.s_minus = (float)(1.0 / p.A_plus);
-    } else {
-        c.kx = 1.0f;
-        c.s_plus = (float)(p.V0 / p.A_plus);
-        c.s_minus = (float)(p.V0 / p.A_minus);
-    }
-    c.u_off = (float)((p.phi_end - p.phi_lo) * p.inv_h);
-    c.inv_h = (float)p.inv_h;
-    c.jmax = (float)(p.n_tab - 2);
-    c.dN = (float)p.dN;
-    c.sqrt_dN = (float)p.sqrt_dN;
-    c.a = (p.bias_kind == kBiasConst) ? (float)p.A : 0.0f;
-    return c;
-}
-
-// kernel table [precision][bias 0..1][tab][allpos]
-template <int BIAS, bool TAB, bool ALLPOS>
-const void *k64() { return reinterpret_cast<const void *>(&em_fp64_kernel<BIAS, TAB, ALLPOS>); }
-template <int BIAS, bool TAB, bool ALLPOS>
-const void *k32() { return reinterpret_cast<const void *>(&em_fp32s_kernel<BIAS, TAB, ALLPOS>); }
-
-const void *kernel_of(int precision, int bias, bool tab, bool allpos)
-{
-    static const void *const t64[2][2][2] = {
-        {{k64<kBiasNone, false, false>(), k64<kBiasNone, false, true>()},
-         {k64<kBiasNone, true, false>(), k64<kBiasNone, true, true>()}},
-        {{k64<kBiasConst, false, false>(), k64<kBiasConst, false, true>()},
-         {k64<kBiasConst, true, false>(), k64<kBiasConst, true, true>()}}};
-    static const void *const t32[2][2][2] = {
-        {{k32<kBiasNone, false, false>(), k32<kBiasNone, false, true>()},
-         {k32<kBiasNone, true, false>(), k32<kBiasNone, true, true>()}},
-        {{k32<kBiasConst, false, false>(), k32<kBiasConst, false, true>()},
-         {k32<kBiasConst, true, false>(), k32<kBiasConst, true, true>()}}};
-    const int b = bias == kBiasNone ? 0 : 1;
-    return precision == 0 ? t64[b][tab][allpos] : t32[b][tab][allpos];
-}
+template <int PREC, int BIAS, bool TAB, bool ALLPOS>
+const void *kptr() { return reinterpret_cast<const void *>(&em_kernel<PREC, BIAS, TAB, ALLPOS>); }
+template <int PREC, int BIAS, bool ALLPOS>
+const void *bptr() { return reinterpret_cast<const void *>(&batch_kernel<PREC, BIAS, ALLPOS>); }
 
 }  // namespace
 
-size_t em_lds_bytes(const EmParams &p, int precision)
+size_t em_lds_bytes(int n_bins, int n_tab)
 {
-    (void)precision;
-    const size_t acc = acc_bytes(p.hist.n_bins);
-    const size_t tab = (p.n_tab > 1) ? (size_t)p.n_tab * 16 : 0;   // double2 or float4 per node
-    return acc + tab;
+    const int nodes = n_tab > 1 ? n_tab : 2;
+    return acc_bytes(n_bins) + (size_t)nodes * 16;   // double2 or float4 per node
 }
 
-const void *em_kernel_ptr(const EmParams &p, int precision)
+const void *em_kernel_ptr(int precision, int bias_kind, bool table, bool all_pos)
 {
-    return kernel_of(precision, p.bias_kind, p.n_tab > 1, p.all_S_pos != 0);
+    // [precision][bias: none, const][table][all_pos]
+    static const void *const t[2][2][2][2] = {
+        {{{kptr<0, kBiasNone, false, false>(), kptr<0, kBiasNone, false, true>()},
+          {kptr<0, kBiasNone, true, false>(), kptr<0, kBiasNone, true, true>()}},
+         {{kptr<0, kBiasConst, false, false>(), kptr<0, kBiasConst, false, true>()},
+          {kptr<0, kBiasConst, true, false>(), kptr<0, kBiasConst, true, true>()}}},
+        {{{kptr<1, kBiasNone, false, false>(), kptr<1, kBiasNone, false, true>()},
+          {kptr<1, kBiasNone, true, false>(), kptr<1, kBiasNone, true, true>()}},
+         {{kptr<1, kBiasConst, false, false>(), kptr<1, kBiasConst, false, true>()},
+          {kptr<1, kBiasConst, true, false>(), kptr<1, kBiasConst, true, true>()}}}};
+    return t[precision ? 1 : 0][bias_kind == kBiasNone ? 0 : 1][table ? 1 : 0][all_pos ? 1 : 0];
 }
 
 hipError_t em_launch(const EmParams &p, int precision, int grid, int block, hipStream_t stream)
 {
-    const size_t lds = em_lds_bytes(p, precision);
-    const void *fn = em_kernel_ptr(p, precision);
+    const size_t lds = em_lds_bytes(p.inst.hist.n_bins, p.inst.n_tab);
+    const void *fn = em_kernel_ptr(precision, p.inst.bias_kind, p.inst.n_tab > 1, p.inst.all_S_pos != 0);
     EmParams pp = p;
-    if (precision == 0) {
-        DriftConsts dk = drift_consts(p);
-        void *args[] = {&pp, &dk};
-        return hipLaunchKernel(fn, dim3(grid), dim3(block), args, lds, stream);
-    }
-    F32Consts c = make_f32_consts(p);
-    void *args[] = {&pp, &c};
+    void *args[] = {&pp};
+    return hipLaunchKernel(fn, dim3(grid), dim3(block), args, lds, stream);
+}
+
+const void *batch_kernel_ptr(int precision, int bias_kind, bool all_pos)
+{
+    static const void *const t[2][2][2] = {
+        {{bptr<0, kBiasNone, false>(), bptr<0, kBiasNone, true>()},
+         {bptr<0, kBiasConst, false>(), bptr<0, kBiasConst, true>()}},
+        {{bptr<1, kBiasNone, false>(), bptr<1, kBiasNone, true>()},
+         {bptr<1, kBiasConst, false>(), bptr<1, kBiasConst, true>()}}};
+    return t[precision ? 1 : 0][bias_kind == kBiasNone ? 0 : 1][all_pos ? 1 : 0];
+}
+
+hipError_t batch_launch(int precision, int bias_kind, bool all_pos, const Inst *insts, const WorkItem *items,
+                        const BatchRun *run, unsigned long long *item_cursor, int max_bins, int max_tab, int grid,
+                        int block, hipStream_t stream)
+{
+    const size_t lds = em_lds_bytes(max_bins, max_tab);
+    const void *fn = batch_kernel_ptr(precision, bias_kind, all_pos);
+    void *args[] = {&insts, &items, &run, &item_cursor, &max_bins};
     return hipLaunchKernel(fn, dim3(grid), dim3(block), args, lds, stream);
 }
 

@@ -33,42 +33,65 @@ struct HistSpec {
 __host__ __device__ inline size_t acc_words(int n_bins) { return (size_t)(n_bins + 2) * 5 + 8; }
 __host__ __device__ inline size_t acc_bytes(int n_bins) { return acc_words(n_bins) * 8; }
 
-// Everything one launch of the Euler-Maruyama kernel needs.
-struct EmParams {
-    // potential (eq. potential_starobinsky; exponential companion)
+// One first-passage problem as the kernels see it: potential, start and end,
+// noise table, bias, step cap, Philox instance word and histogram target.
+struct Inst {
     int32_t pot_kind;
     double V0, phi_T, A_plus, A_minus;
     double phi_in, pi_in, phi_end;
     // phi-indexed noise table: n_tab nodes from phi_lo with spacing 1/inv_h
     int32_t n_tab;
     double phi_lo, inv_h;
-    const double2 *tab64;            // node j: (S_j, tan_j)                        (device)
+    const double2 *tab64;            // node j: (S_j, tan_j)                                  (device)
     const float4 *tab32;             // node j: (S_j, S_j+1 - S_j, tan_j, tan_j+1 - tan_j) in FP32
     int32_t all_S_pos;               // every node has S > 0 (the ln w update needs no test)
-    // importance-sampling bias
     int32_t bias_kind;
     double A;
-    const float *mlp;                // device, kMlpParams floats
-    double norm[4];
-    int32_t mlp_every;
-    // run
-    double dN, sqrt_dN;
-    uint32_t key0, key1, instance;
-    uint64_t traj_offset, n_traj;
+    uint32_t instance;               // fourth Philox counter word
     uint32_t max_steps;
-    int32_t chunk;
     HistSpec hist;
-    // outputs
-    double *d_N, *d_lnw;
+    void *acc;                       // global accumulators (acc_bytes(hist.n_bins))
+};
+
+// Per-run values shared by every instance of a launch.
+struct RunArgs {
+    double dN, sqrt_dN;
+    uint32_t key0, key1;             // Philox key = seed
+    int32_t chunk;                   // steps between retire/refill (multiple of 4)
+};
+
+// One launch of the single-problem Euler-Maruyama kernel.
+struct EmParams {
+    Inst inst;
+    RunArgs run;
+    uint64_t traj_offset, n_traj;
+    double *d_N, *d_lnw;             // optional per-trajectory outputs (device, caller-owned)
     uint32_t *d_steps;
     unsigned long long *cursor;      // work-queue head (relative trajectory index)
-    void *acc;                       // global accumulators (acc_bytes(n_bins))
+};
+
+// A slice of one instance's trajectories, processed by one block of the batch kernel.
+struct WorkItem {
+    uint32_t inst;
+    uint32_t pad;
+    uint64_t begin, count;
+};
+
+// Device-resident parameters of a batch launch (read by the kernel, so a
+// captured graph can be replayed with new values).
+struct BatchRun {
+    RunArgs run;
+    uint64_t n_items;
 };
 
 // Euler-Maruyama kernels (fpt_em.hip).
-size_t em_lds_bytes(const EmParams &p, int precision);
-const void *em_kernel_ptr(const EmParams &p, int precision);
+size_t em_lds_bytes(int n_bins, int n_tab);
+const void *em_kernel_ptr(int precision, int bias_kind, bool table, bool all_pos);
 hipError_t em_launch(const EmParams &p, int precision, int grid, int block, hipStream_t stream);
+const void *batch_kernel_ptr(int precision, int bias_kind, bool all_pos);
+hipError_t batch_launch(int precision, int bias_kind, bool all_pos, const Inst *insts, const WorkItem *items,
+                        const BatchRun *run, unsigned long long *item_cursor, int max_bins, int max_tab, int grid,
+                        int block, hipStream_t stream);
 hipError_t zero_words(unsigned long long *ptr, size_t n, hipStream_t stream);
 
 }  // namespace fpt

@@ -75,6 +75,11 @@ class fpt_hist(ctypes.Structure):
                 ("sum_w_bin", _dp), ("sum_w2_bin", _dp), ("sum_lnw_bin", _dp), ("sum_lnw2_bin", _dp)]
 
 
+class fpt_batch_options(ctypes.Structure):
+    _fields_ = [("block_size", ctypes.c_int32), ("chunk", ctypes.c_int32), ("item_size", ctypes.c_int32),
+                ("use_graph", ctypes.c_int32)]
+
+
 class FptError(RuntimeError):
     def __init__(self, status: int, where: str, detail: str):
         super().__init__(f"{where}: {detail} (status {status})")
@@ -115,8 +120,18 @@ def load():
     L.fpt_last_error.restype = ctypes.c_char_p
     L.fpt_noise_table_bessel.argtypes = [P(fpt_potential), ctypes.c_double, ctypes.c_int32, ctypes.c_double,
                                          ctypes.c_double, _dp, _dp]
+    L.fpt_batch_create.argtypes = [P(ctypes.c_void_p), ctypes.c_int32, P(fpt_batch_options), P(ctypes.c_void_p)]
+    L.fpt_batch_run.argtypes = [ctypes.c_void_p, _u64p, ctypes.c_double, ctypes.c_uint64, ctypes.c_uint64,
+                                ctypes.c_void_p]
+    L.fpt_batch_autotune.argtypes = [ctypes.c_void_p, _u64p, ctypes.c_double, ctypes.c_uint64, ctypes.c_char_p,
+                                     ctypes.c_void_p]
+    L.fpt_batch_config.argtypes = [ctypes.c_void_p, P(ctypes.c_int32), P(ctypes.c_int32)]
+    L.fpt_batch_last_ms.argtypes = [ctypes.c_void_p, _dp]
+    L.fpt_batch_destroy.argtypes = [ctypes.c_void_p]
+    L.fpt_batch_destroy.restype = None
     for name in ("fpt_create", "fpt_run", "fpt_histogram", "fpt_reset", "fpt_last_kernel_ms",
-                 "fpt_noise_table_bessel"):
+                 "fpt_noise_table_bessel", "fpt_batch_create", "fpt_batch_run", "fpt_batch_autotune",
+                 "fpt_batch_config", "fpt_batch_last_ms"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -218,6 +233,58 @@ class Context:
     def destroy(self):
         if getattr(self, "_h", None):
             self._lib.fpt_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Owns one fpt_batch over a list of Contexts (which must outlive it)."""
+
+    def __init__(self, contexts, *, block_size=0, chunk=0, item_size=0, use_graph=True):
+        L = load()
+        self._ctxs = list(contexts)
+        arr = (ctypes.c_void_p * len(self._ctxs))(*[c.handle.value for c in self._ctxs])
+        opts = fpt_batch_options(block_size, chunk, item_size, 1 if use_graph else 0)
+        h = ctypes.c_void_p()
+        _check(L.fpt_batch_create(arr, len(self._ctxs), ctypes.byref(opts), ctypes.byref(h)), "fpt_batch_create")
+        self._h = h
+        self._lib = L
+
+    def _counts(self, n_traj):
+        a = np.ascontiguousarray(n_traj, dtype=np.uint64)
+        if a.shape != (len(self._ctxs),):
+            raise ValueError("one trajectory count per instance")
+        return a
+
+    def run(self, n_traj, dN: float, seed: int, traj_offset: int = 0, stream=None):
+        a = self._counts(n_traj)
+        _check(self._lib.fpt_batch_run(self._h, a.ctypes.data_as(_u64p), dN, seed, traj_offset,
+                                       _stream_handle(stream)), "fpt_batch_run")
+
+    def autotune(self, n_traj, dN: float, seed: int, cache_path=None, stream=None):
+        a = self._counts(n_traj)
+        path = cache_path.encode() if cache_path else None
+        _check(self._lib.fpt_batch_autotune(self._h, a.ctypes.data_as(_u64p), dN, seed, path,
+                                            _stream_handle(stream)), "fpt_batch_autotune")
+
+    def config(self):
+        b, c = ctypes.c_int32(), ctypes.c_int32()
+        _check(self._lib.fpt_batch_config(self._h, ctypes.byref(b), ctypes.byref(c)), "fpt_batch_config")
+        return b.value, c.value
+
+    def last_ms(self) -> float:
+        ms = ctypes.c_double()
+        _check(self._lib.fpt_batch_last_ms(self._h, ctypes.byref(ms)), "fpt_batch_last_ms")
+        return ms.value
+
+    def destroy(self):
+        if getattr(self, "_h", None):
+            self._lib.fpt_batch_destroy(self._h)
             self._h = None
 
     def __del__(self):

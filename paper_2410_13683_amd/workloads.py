@@ -146,7 +146,8 @@ def batched_instances(n_inst: int = 64, seed: int = 4, n_min: float = 1e5, n_max
                       max_steps: int = 1 << 20) -> list[Workload]:
     """Instances of the SR->USR problem with eps_- log-uniform in [1e-10, 1e-6] and
     phi_e - phi_end uniform in [0.1, 1]; trajectory counts log-uniform in [n_min, n_max];
-    a per-instance step cap censors the (very long) flat-branch runs."""
+    a per-instance step cap censors the (very long) flat-branch runs.  The noise table
+    uses 4096 nodes phi_j = (j - 2100) 2^-11, covering [-1.03, 0.97] with a node at phi_T."""
     rng = np.random.default_rng(seed)
     eps_m = 10.0 ** rng.uniform(-10, -6, n_inst)
     delta = rng.uniform(0.1, 1.0, n_inst)
@@ -155,6 +156,7 @@ def batched_instances(n_inst: int = 64, seed: int = 4, n_min: float = 1e5, n_max
     for i in range(n_inst):
         w = srusr_bessel(n_traj=int(counts[i]), seed=seed).with_(
             name=f"batched_{i}", A_minus=V0 * math.sqrt(2.0 * eps_m[i]), phi_end=-float(delta[i]),
+            table_lo=-2100 * 2.0 ** -11, table_hi=(4095 - 2100) * 2.0 ** -11,
             max_steps=int(max_steps), extra={"instance": i, "eps_minus": float(eps_m[i])})
         out.append(w)
     return out

@@ -23,5 +23,7 @@ int main(void)
     F(fpt_hist, n_steps_total); F(fpt_hist, sum_w); F(fpt_hist, sum_w2); F(fpt_hist, sum_wN);
     F(fpt_hist, sum_wN2); F(fpt_hist, count); F(fpt_hist, sum_w_bin); F(fpt_hist, sum_w2_bin);
     F(fpt_hist, sum_lnw_bin); F(fpt_hist, sum_lnw2_bin);
+    S(fpt_batch_options); F(fpt_batch_options, block_size); F(fpt_batch_options, chunk);
+    F(fpt_batch_options, item_size); F(fpt_batch_options, use_graph);
     return 0;
 }
