@@ -297,6 +297,63 @@ static void orc_mlp_backward(const float *p, const double x[2], double scale, do
 }
 
 /* ------------------------------------------------------------------------- */
+/* Tabulated learned amplitude: the network evaluated on a uniform grid of the  */
+/* normalised inputs (x0, x1) with n0 x n1 nodes over [lo0, hi0] x [lo1, hi1],  */
+/* stored row-major a[i n1 + j]; between nodes bilinear interpolation, outside  */
+/* the grid the edge nodes.  Any deterministic function of the state is an      */
+/* admissible control for importance sampling, and the weights use the same     */
+/* function, so sampling with the tabulated network stays unbiased.             */
+/* ------------------------------------------------------------------------- */
+typedef struct {
+    int n0, n1;
+    double lo0, hi0, lo1, hi1;
+} orc_grid;
+
+static double orc_grid_x(const orc_grid *g, int axis, int k)
+{
+    const int n = axis ? g->n1 : g->n0;
+    const double lo = axis ? g->lo1 : g->lo0, hi = axis ? g->hi1 : g->hi0;
+    return lo + (hi - lo) * (double)k / (double)(n - 1);
+}
+
+int orc_mlp_tabulate(const float *params, int n0, int n1, double lo0, double hi0, double lo1, double hi1,
+                     double *a_out)
+{
+    if (n0 < 2 || n1 < 2 || !(hi0 > lo0) || !(hi1 > lo1)) return -1;
+    orc_grid g = {n0, n1, lo0, hi0, lo1, hi1};
+    for (int i = 0; i < n0; ++i)
+        for (int j = 0; j < n1; ++j) {
+            double x[2] = {orc_grid_x(&g, 0, i), orc_grid_x(&g, 1, j)};
+            a_out[i * n1 + j] = orc_mlp_forward(params, x, NULL, NULL);
+        }
+    return 0;
+}
+
+/* Bilinear value at (x0, x1); the four corner indices and weights are returned. */
+static double orc_grid_eval(const orc_grid *g, const double *a, double x0, double x1, int idx[4], double beta[4])
+{
+    double u0 = (x0 - g->lo0) / (g->hi0 - g->lo0) * (double)(g->n0 - 1);
+    double u1 = (x1 - g->lo1) / (g->hi1 - g->lo1) * (double)(g->n1 - 1);
+    double i0 = floor(u0), i1 = floor(u1);
+    if (i0 < 0.0) i0 = 0.0;
+    if (i0 > (double)(g->n0 - 2)) i0 = (double)(g->n0 - 2);
+    if (i1 < 0.0) i1 = 0.0;
+    if (i1 > (double)(g->n1 - 2)) i1 = (double)(g->n1 - 2);
+    double f0 = u0 - i0, f1 = u1 - i1;
+    if (f0 < 0.0) f0 = 0.0;
+    if (f0 > 1.0) f0 = 1.0;
+    if (f1 < 0.0) f1 = 0.0;
+    if (f1 > 1.0) f1 = 1.0;
+    const int k = (int)i0 * g->n1 + (int)i1;
+    idx[0] = k; idx[1] = k + g->n1; idx[2] = k + 1; idx[3] = k + g->n1 + 1;
+    beta[0] = (1.0 - f0) * (1.0 - f1);
+    beta[1] = f0 * (1.0 - f1);
+    beta[2] = (1.0 - f0) * f1;
+    beta[3] = f0 * f1;
+    return beta[0] * a[idx[0]] + beta[1] * a[idx[1]] + beta[2] * a[idx[2]] + beta[3] * a[idx[3]];
+}
+
+/* ------------------------------------------------------------------------- */
 /* One trajectory, Sec. 4.1.  Writes N, ln w and the step count with flags.   */
 /* ------------------------------------------------------------------------- */
 typedef struct {
@@ -310,6 +367,9 @@ typedef struct {
     double A_bias;
     const float *mlp;
     double norm[4];
+    int mlp_every;            /* >= 1: the network every k steps; 0: the tabulated network */
+    orc_grid grid;
+    const double *grid_a;     /* tabulated amplitude (mlp_every == 0) */
     double dN;
     uint64_t seed;
     uint32_t instance;
@@ -324,6 +384,7 @@ static void orc_trajectory(const orc_problem *P, uint64_t traj, double *N_out, d
     int64_t n = 0;
     double zbuf[4];
     uint64_t zcall = UINT64_MAX;
+    double A_held = 0.0;
     for (;;) {
         if (n >= P->max_steps) {
             *N_out = NAN;
@@ -345,8 +406,20 @@ static void orc_trajectory(const orc_problem *P, uint64_t traj, double *N_out, d
         orc_table_lookup(P->n_tab, P->phi_lo, P->phi_hi, P->S_tab, P->t_tab, phi, &S, &tan_theta);
         /* bias amplitude A (constant or learned) and bias vector parallel to the noise */
         double A = 0.0;
-        if (P->bias_kind == ORC_BIAS_CONST) A = P->A_bias;
-        else if (P->bias_kind == ORC_BIAS_MLP) A = orc_mlp_eval(P->mlp, P->norm, phi, pi_);
+        if (P->bias_kind == ORC_BIAS_CONST) {
+            A = P->A_bias;
+        } else if (P->bias_kind == ORC_BIAS_MLP) {
+            if (P->mlp_every > 0) {
+                if (n % P->mlp_every == 0) A_held = orc_mlp_eval(P->mlp, P->norm, phi, pi_);
+                A = A_held;
+            } else {
+                double x[2];
+                int idx[4];
+                double beta[4];
+                orc_mlp_inputs(P->norm, phi, pi_, x);
+                A = orc_grid_eval(&P->grid, P->grid_a, x[0], x[1], idx, beta);
+            }
+        }
         double B_phi = A * S;
         double B_pi = tan_theta * B_phi;
         /* biased Euler-Maruyama step, eq. (importance_sampling_1D_noise_step) */
@@ -384,14 +457,27 @@ int orc_run(int kind, const double pot[4],
             int n_tab, double phi_lo, double phi_hi, const double *S_tab, const double *t_tab,
             double phi_in, double pi_in, double phi_end,
             int bias_kind, double A_bias, const float *mlp_params, const double *mlp_norm,
+            int mlp_every, const int grid_n[2], const double grid_range[4],
             double dN, uint64_t seed, uint32_t instance, uint64_t traj_offset, uint64_t n_traj,
             int64_t max_steps, double *N_out, double *lnw_out, uint32_t *steps_out, int n_threads)
 {
     if (n_tab < 1 || !(dN > 0.0) || max_steps < 1 || max_steps > (int64_t)ORC_STEP_MASK) return -1;
     if (!(phi_in > phi_end)) return -1;
-    if (bias_kind == ORC_BIAS_MLP && (!mlp_params || !mlp_norm)) return -1;
+    if (bias_kind == ORC_BIAS_MLP && (!mlp_params || !mlp_norm || mlp_every < 0)) return -1;
     orc_problem P;
     memset(&P, 0, sizeof P);
+    double *grid_a = NULL;
+    if (bias_kind == ORC_BIAS_MLP && mlp_every == 0) {
+        orc_grid g = {grid_n[0], grid_n[1], grid_range[0], grid_range[1], grid_range[2], grid_range[3]};
+        grid_a = (double *)malloc(sizeof(double) * (size_t)(g.n0 > 1 ? g.n0 : 1) * (size_t)(g.n1 > 1 ? g.n1 : 1));
+        if (!grid_a || orc_mlp_tabulate(mlp_params, g.n0, g.n1, g.lo0, g.hi0, g.lo1, g.hi1, grid_a) != 0) {
+            free(grid_a);
+            return -1;
+        }
+        P.grid = g;
+        P.grid_a = grid_a;
+    }
+    P.mlp_every = mlp_every;
     P.kind = kind;
     memcpy(P.pot, pot, sizeof P.pot);
     P.n_tab = n_tab; P.phi_lo = phi_lo; P.phi_hi = phi_hi; P.S_tab = S_tab; P.t_tab = t_tab;
@@ -408,6 +494,7 @@ int orc_run(int kind, const double pot[4],
 #pragma omp parallel for schedule(dynamic, 16)
     for (int64_t i = 0; i < nt; ++i)
         orc_trajectory(&P, traj_offset + (uint64_t)i, &N_out[i], &lnw_out[i], &steps_out[i]);
+    free(grid_a);
     return 0;
 }
 
@@ -451,7 +538,7 @@ int orc_mlp_replay_grad(int kind, const double pot[4],
     memcpy(P.pot, pot, sizeof P.pot);
     P.n_tab = n_tab; P.phi_lo = phi_lo; P.phi_hi = phi_hi; P.S_tab = S_tab; P.t_tab = t_tab;
     P.phi_in = phi_in; P.pi_in = pi_in; P.phi_end = phi_end;
-    P.bias_kind = ORC_BIAS_MLP; P.mlp = theta_old;
+    P.bias_kind = ORC_BIAS_MLP; P.mlp = theta_old; P.mlp_every = 1;
     memcpy(P.norm, mlp_norm, sizeof P.norm);
     P.dN = dN; P.seed = seed; P.instance = instance; P.max_steps = max_steps;
 #ifdef _OPENMP
@@ -521,5 +608,131 @@ int orc_mlp_replay_grad(int kind, const double pot[4],
     }
     for (int k = 0; k < MLP_NPARAM; ++k) grad_out[k] /= (double)n_traj;
     *J_out = J / (double)n_traj;
+    return 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Replay gradient with the tabulated control.  Paths are drawn with the grid  */
+/* of theta_old; a candidate theta changes the grid values, so the amplitude   */
+/* at step k is a_theta,k = sum_c beta_c(x_k) net_theta(x_c) over the four     */
+/* corners c of the cell holding x_k, and                                      */
+/*   ln w_theta = sum_k ( -a_theta,k e_k + a_theta,k^2 dN / 2 ),               */
+/*   e_k = a_old,k dN + xi_k sqrt(dN)      (steps with S > 0),                 */
+/*   J(theta) = (1/n) sum_{paths in T} w_old w_theta,                          */
+/*   grad J = (1/n) sum_T w_old w_theta sum_k (-e_k + a_theta,k dN)            */
+/*                 sum_c beta_c(x_k) grad net_theta(x_c).                      */
+/* The grid-node weights G_c are accumulated over paths first and then         */
+/* propagated through the network once per node.                               */
+/* ------------------------------------------------------------------------- */
+int orc_grid_replay_grad(int kind, const double pot[4],
+                         int n_tab, double phi_lo, double phi_hi, const double *S_tab, const double *t_tab,
+                         double phi_in, double pi_in, double phi_end,
+                         const float *theta_old, const float *theta, const double *mlp_norm,
+                         const int grid_n[2], const double grid_range[4],
+                         double dN, uint64_t seed, uint32_t instance, uint64_t traj_offset, uint64_t n_traj,
+                         int64_t max_steps, double N_ref, double tail_lo,
+                         double *grad_out, double *J_out, double *G_out, int n_threads)
+{
+    if (n_tab < 1 || !(dN > 0.0) || max_steps < 1) return -1;
+    orc_grid g = {grid_n[0], grid_n[1], grid_range[0], grid_range[1], grid_range[2], grid_range[3]};
+    const size_t ng = (size_t)g.n0 * (size_t)g.n1;
+    double *a_old = (double *)malloc(sizeof(double) * ng);
+    double *a_new = (double *)malloc(sizeof(double) * ng);
+    double *G = (double *)calloc(ng, sizeof(double));
+    if (!a_old || !a_new || !G || orc_mlp_tabulate(theta_old, g.n0, g.n1, g.lo0, g.hi0, g.lo1, g.hi1, a_old) ||
+        orc_mlp_tabulate(theta, g.n0, g.n1, g.lo0, g.hi0, g.lo1, g.hi1, a_new)) {
+        free(a_old); free(a_new); free(G);
+        return -1;
+    }
+    orc_problem P;
+    memset(&P, 0, sizeof P);
+    P.kind = kind;
+    memcpy(P.pot, pot, sizeof P.pot);
+    P.n_tab = n_tab; P.phi_lo = phi_lo; P.phi_hi = phi_hi; P.S_tab = S_tab; P.t_tab = t_tab;
+    P.phi_in = phi_in; P.pi_in = pi_in; P.phi_end = phi_end;
+    P.bias_kind = ORC_BIAS_MLP; P.mlp = theta_old; P.mlp_every = 0; P.grid = g; P.grid_a = a_old;
+    memcpy(P.norm, mlp_norm, sizeof P.norm);
+    P.dN = dN; P.seed = seed; P.instance = instance; P.max_steps = max_steps;
+#ifdef _OPENMP
+    if (n_threads > 0) omp_set_num_threads(n_threads);
+#else
+    (void)n_threads;
+#endif
+    const double sqrt_dN = sqrt(dN);
+    const int64_t nt = (int64_t)n_traj;
+    double J = 0.0;
+#pragma omp parallel
+    {
+        double *G_local = (double *)calloc(ng, sizeof(double));
+        double J_local = 0.0;
+#pragma omp for schedule(dynamic, 4)
+        for (int64_t i = 0; i < nt; ++i) {
+            const uint64_t traj = traj_offset + (uint64_t)i;
+            double N, lnw_old;
+            uint32_t steps;
+            orc_trajectory(&P, traj, &N, &lnw_old, &steps);
+            if (steps & (ORC_FLAG_CENSORED | ORC_FLAG_ENDED_EARLY)) continue;
+            if (!(N - N_ref >= tail_lo)) continue;
+            const uint32_t n_steps = steps & ORC_STEP_MASK;
+            double lnw_new = 0.0, ww = 0.0;
+            for (int pass = 0; pass < 2; ++pass) {
+                /* pass 0: ln w_theta of the path; pass 1: its node weights, scaled by w_old w_theta */
+                double phi = phi_in, pi_ = pi_in;
+                double zbuf[4];
+                uint64_t zcall = UINT64_MAX;
+                for (uint32_t n = 0; n < n_steps; ++n) {
+                    const uint64_t call = (uint64_t)n >> 2;
+                    if (call != zcall) { orc_four_normals(seed, instance, traj, call, zbuf); zcall = call; }
+                    const double xi = zbuf[n & 3];
+                    const double V = orc_V(kind, pot, phi), dV = orc_dV(kind, pot, phi);
+                    double S, tan_theta;
+                    orc_table_lookup(n_tab, phi_lo, phi_hi, S_tab, t_tab, phi, &S, &tan_theta);
+                    double x[2], beta[4];
+                    int idx[4];
+                    orc_mlp_inputs(mlp_norm, phi, pi_, x);
+                    const double a_o = orc_grid_eval(&g, a_old, x[0], x[1], idx, beta);
+                    if (S > 0.0) {
+                        const double a_n = beta[0] * a_new[idx[0]] + beta[1] * a_new[idx[1]] +
+                                           beta[2] * a_new[idx[2]] + beta[3] * a_new[idx[3]];
+                        const double e = a_o * dN + xi * sqrt_dN;
+                        if (pass == 0) {
+                            lnw_new += -a_n * e + a_n * a_n * dN / 2.0;
+                        } else {
+                            const double c = ww * (-e + a_n * dN);
+                            for (int q = 0; q < 4; ++q) G_local[idx[q]] += c * beta[q];
+                        }
+                    }
+                    const double B_phi = a_o * S, B_pi = tan_theta * B_phi;
+                    const double D_pi = -(3.0 - pi_ * pi_ / 2.0) * (pi_ + dV / V);
+                    const double phi_next = phi + pi_ * dN + B_phi * dN + S * xi * sqrt_dN;
+                    const double pi_next = pi_ + D_pi * dN + B_pi * dN + tan_theta * S * xi * sqrt_dN;
+                    phi = phi_next;
+                    pi_ = pi_next;
+                }
+                if (pass == 0) {
+                    ww = exp(lnw_old + lnw_new);
+                    J_local += ww;
+                }
+            }
+        }
+#pragma omp critical
+        {
+            J += J_local;
+            for (size_t k = 0; k < ng; ++k) G[k] += G_local[k];
+        }
+        free(G_local);
+    }
+    for (int k = 0; k < MLP_NPARAM; ++k) grad_out[k] = 0.0;
+    for (int i = 0; i < g.n0; ++i)
+        for (int j = 0; j < g.n1; ++j) {
+            const size_t k = (size_t)i * g.n1 + j;
+            G[k] /= (double)n_traj;
+            if (G[k] == 0.0) continue;
+            double x[2] = {orc_grid_x(&g, 0, i), orc_grid_x(&g, 1, j)};
+            orc_mlp_backward(theta, x, G[k], grad_out);
+        }
+    if (G_out) memcpy(G_out, G, sizeof(double) * ng);
+    *J_out = J / (double)n_traj;
+    free(a_old); free(a_new); free(G);
     return 0;
 }

@@ -71,9 +71,10 @@ def lib():
         L.orc_noise_table_bessel.argtypes = [ctypes.c_int, dp, ctypes.c_double, ctypes.c_int,
                                              ctypes.c_double, ctypes.c_double, dp, dp]
         L.orc_noise_table_bessel.restype = ctypes.c_int
+        ip = ctypes.POINTER(ctypes.c_int)
         L.orc_run.argtypes = [ctypes.c_int, dp, ctypes.c_int, ctypes.c_double, ctypes.c_double, dp, dp,
                               ctypes.c_double, ctypes.c_double, ctypes.c_double,
-                              ctypes.c_int, ctypes.c_double, fp, dp,
+                              ctypes.c_int, ctypes.c_double, fp, dp, ctypes.c_int, ip, dp,
                               ctypes.c_double, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint64,
                               ctypes.c_uint64, ctypes.c_int64, dp, dp, u32p, ctypes.c_int]
         L.orc_run.restype = ctypes.c_int
@@ -87,6 +88,15 @@ def lib():
                                           ctypes.c_uint64, ctypes.c_uint64, ctypes.c_int64,
                                           ctypes.c_double, ctypes.c_double, dp, dp, ctypes.c_int]
         L.orc_mlp_replay_grad.restype = ctypes.c_int
+        L.orc_mlp_tabulate.argtypes = [fp, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                       ctypes.c_double, ctypes.c_double, dp]
+        L.orc_mlp_tabulate.restype = ctypes.c_int
+        L.orc_grid_replay_grad.argtypes = [ctypes.c_int, dp, ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                           dp, dp, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                           fp, fp, dp, ip, dp, ctypes.c_double, ctypes.c_uint64,
+                                           ctypes.c_uint32, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_int64,
+                                           ctypes.c_double, ctypes.c_double, dp, dp, dp, ctypes.c_int]
+        L.orc_grid_replay_grad.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -148,6 +158,9 @@ class Problem:
     A_bias: float = 0.0
     mlp_params: np.ndarray | None = None
     mlp_norm: np.ndarray | None = None
+    mlp_every: int = 1                # >= 1: the network every k steps; 0: the tabulated network
+    grid_n: tuple = (2, 2)            # tabulation grid over the normalised inputs (x0, x1)
+    grid_range: tuple = (-1.0, 1.0, -1.0, 1.0)
 
     def pot(self) -> np.ndarray:
         return np.array([self.V0, self.phi_T, self.A_plus, self.A_minus], dtype=np.float64)
@@ -183,10 +196,12 @@ def run(prob: Problem, dN: float, seed: int, n_traj: int, traj_offset: int = 0, 
     norm = (np.ascontiguousarray(prob.mlp_norm, dtype=np.float64)
             if prob.mlp_norm is not None else np.array([0.0, 1.0, 0.0, 1.0]))
     pot = prob.pot()
+    gn = (ctypes.c_int * 2)(*prob.grid_n)
+    gr = np.ascontiguousarray(prob.grid_range, dtype=np.float64)
     rc = lib().orc_run(prob.kind, _dp(pot), len(S), prob.phi_lo, prob.phi_hi, _dp(S), _dp(t),
                        prob.phi_in, prob.pi_in, prob.phi_end, prob.bias_kind, prob.A_bias,
-                       _fp(mlp), _dp(norm), dN, seed, instance, traj_offset, n_traj, max_steps,
-                       _dp(N), _dp(lnw), _u32p(steps), n_threads)
+                       _fp(mlp), _dp(norm), prob.mlp_every, gn, _dp(gr), dN, seed, instance, traj_offset,
+                       n_traj, max_steps, _dp(N), _dp(lnw), _u32p(steps), n_threads)
     if rc != 0:
         raise ValueError("invalid oracle problem")
     return N, lnw, steps
@@ -221,6 +236,40 @@ def mlp_replay_grad(prob: Problem, theta_old: np.ndarray, theta: np.ndarray, dN:
     if rc != 0:
         raise ValueError("invalid oracle problem")
     return grad, float(J[0])
+
+
+def mlp_tabulate(params: np.ndarray, grid_n, grid_range) -> np.ndarray:
+    """Network output 0 on the grid (x0_i, x1_j), row-major [n0, n1]."""
+    p = np.ascontiguousarray(params, dtype=np.float32)
+    out = np.empty(grid_n[0] * grid_n[1], dtype=np.float64)
+    rc = lib().orc_mlp_tabulate(_fp(p), grid_n[0], grid_n[1], *[float(v) for v in grid_range], _dp(out))
+    if rc != 0:
+        raise ValueError("invalid grid")
+    return out.reshape(grid_n[0], grid_n[1])
+
+
+def grid_replay_grad(prob: Problem, theta_old: np.ndarray, theta: np.ndarray, dN: float, seed: int,
+                     n_traj: int, N_ref: float, tail_lo: float, traj_offset: int = 0, instance: int = 0,
+                     max_steps: int = STEP_MASK, n_threads: int = 0):
+    """J(theta), its gradient and the grid-node weights G for paths drawn with the tabulated theta_old."""
+    S = np.ascontiguousarray(prob.S, dtype=np.float64)
+    t = np.ascontiguousarray(prob.tan_theta, dtype=np.float64)
+    told = np.ascontiguousarray(theta_old, dtype=np.float32)
+    tnew = np.ascontiguousarray(theta, dtype=np.float32)
+    norm = np.ascontiguousarray(prob.mlp_norm, dtype=np.float64)
+    gn = (ctypes.c_int * 2)(*prob.grid_n)
+    gr = np.ascontiguousarray(prob.grid_range, dtype=np.float64)
+    grad = np.empty(MLP_NPARAM, dtype=np.float64)
+    G = np.empty(prob.grid_n[0] * prob.grid_n[1], dtype=np.float64)
+    J = np.zeros(1, dtype=np.float64)
+    pot = prob.pot()
+    rc = lib().orc_grid_replay_grad(prob.kind, _dp(pot), len(S), prob.phi_lo, prob.phi_hi, _dp(S), _dp(t),
+                                    prob.phi_in, prob.pi_in, prob.phi_end, _fp(told), _fp(tnew), _dp(norm),
+                                    gn, _dp(gr), dN, seed, instance, traj_offset, n_traj, max_steps, N_ref,
+                                    tail_lo, _dp(grad), _dp(J), _dp(G), n_threads)
+    if rc != 0:
+        raise ValueError("invalid oracle problem")
+    return grad, float(J[0]), G.reshape(prob.grid_n[0], prob.grid_n[1])
 
 
 # --------------------------------------------------------------------------

@@ -133,3 +133,78 @@ def test_replay_gradient_matches_finite_differences(orc):
         _, Jm = orc.mlp_replay_grad(prob, theta_old, tm, w.dN, w.seed, w.n_traj, w.N_ref, tail_lo)
         fd = (Jp - Jm) / (hp + hm)
         assert abs(fd - grad[k]) <= 2e-3 * abs(grad[k]) + 1e-6 * abs(J), (k, fd, grad[k])
+
+
+# --------------------------------------------------------------------------
+# tabulated learned control
+# --------------------------------------------------------------------------
+GRID_N = (24, 12)
+GRID_RANGE = (-0.2, 1.2, -1.5, 1.5)
+
+
+def test_tabulation_matches_numpy(orc):
+    rng = np.random.default_rng(7)
+    p = _random_params(rng)
+    a = orc.mlp_tabulate(p, GRID_N, GRID_RANGE)
+    x0 = np.linspace(GRID_RANGE[0], GRID_RANGE[1], GRID_N[0])
+    x1 = np.linspace(GRID_RANGE[2], GRID_RANGE[3], GRID_N[1])
+    for i in (0, 5, GRID_N[0] - 1):
+        for j in (0, 7, GRID_N[1] - 1):
+            assert math.isclose(a[i, j], _numpy_mlp(p, np.array([x0[i], x1[j]]))[0], rel_tol=1e-12, abs_tol=1e-14)
+
+
+def test_tabulated_constant_network_is_the_constant_bias(orc):
+    rng = np.random.default_rng(8)
+    p = _random_params(rng)
+    p[4352:4480] = 0.0
+    p[4480] = 1.25
+    w = W.linear_slow_roll(n_traj=48).with_(bias_kind=W.BIAS_CONST, A_bias=1.25)
+    Nc, lc, sc = oracle_run(w)
+    prob = oracle_problem(w.with_(bias_kind=W.BIAS_MLP), mlp_params=p, mlp_norm=np.array([0.5, 0.5, -2.0, 1.0]))
+    for every in (0, 1, 5):
+        prob.mlp_every = every
+        prob.grid_n, prob.grid_range = GRID_N, GRID_RANGE
+        Nm, lm, sm = orc.run(prob, w.dN, w.seed, w.n_traj)
+        assert np.array_equal(sc, sm)
+        np.testing.assert_allclose(Nm, Nc, rtol=1e-13)
+        np.testing.assert_allclose(lm, lc, rtol=1e-12, atol=1e-12)
+
+
+def _grid_problem(theta):
+    w, norm = _mlp_problem()
+    prob = oracle_problem(w, mlp_params=theta, mlp_norm=norm)
+    prob.mlp_every = 0
+    prob.grid_n, prob.grid_range = GRID_N, GRID_RANGE
+    return w, prob
+
+
+def test_grid_replay_objective_matches_forward_weights(orc):
+    rng = np.random.default_rng(12)
+    theta = _random_params(rng, scale=0.2, out_bias=1.0)
+    w, prob = _grid_problem(theta)
+    N, lnw, steps = orc.run(prob, w.dN, w.seed, w.n_traj)
+    tail_lo = 0.05
+    T = (N - w.N_ref) >= tail_lo
+    J_fwd = np.sum(np.exp(2 * lnw[T])) / w.n_traj
+    grad, J, G = orc.grid_replay_grad(prob, theta, theta, w.dN, w.seed, w.n_traj, w.N_ref, tail_lo)
+    assert T.sum() > 5
+    assert math.isclose(J, J_fwd, rel_tol=1e-10)
+    assert np.count_nonzero(G) > 4 and np.all(np.isfinite(grad))
+
+
+def test_grid_replay_gradient_matches_finite_differences(orc):
+    rng = np.random.default_rng(13)
+    theta_old = _random_params(rng, scale=0.2, out_bias=1.0)
+    theta = theta_old.copy()
+    theta[4480] += np.float32(0.2)
+    w, prob = _grid_problem(theta_old)
+    tail_lo = 0.0
+    grad, J, _ = orc.grid_replay_grad(prob, theta_old, theta, w.dN, w.seed, w.n_traj, w.N_ref, tail_lo)
+    for k in [4480, 4352 + 9, 4288 + 3, 192 + 64 * 5 + 17, 128 + 30, 2 * 40 + 1]:
+        h = np.float32(1e-2) if k >= 4352 else np.float32(2e-2)
+        tp = theta.copy(); tp[k] += h
+        tm = theta.copy(); tm[k] -= h
+        _, Jp, _ = orc.grid_replay_grad(prob, theta_old, tp, w.dN, w.seed, w.n_traj, w.N_ref, tail_lo)
+        _, Jm, _ = orc.grid_replay_grad(prob, theta_old, tm, w.dN, w.seed, w.n_traj, w.N_ref, tail_lo)
+        fd = (Jp - Jm) / ((float(tp[k]) - float(theta[k])) + (float(theta[k]) - float(tm[k])))
+        assert abs(fd - grad[k]) <= 2e-3 * abs(grad[k]) + 1e-6 * abs(J), (k, fd, grad[k])
