@@ -81,6 +81,7 @@ enum { FPT_BINS_LINEAR = 0, FPT_BINS_LOG = 1 };
 #define FPT_MAX_BINS 1024
 #define FPT_MLP_HIDDEN 64
 #define FPT_MLP_NPARAM 4482              /* 2->64->64->2 network, see fpt_bias */
+#define FPT_MLP_MAX_GRID 1024            /* nodes of the tabulated network */
 
 /* ---- inputs ---------------------------------------------------------------- */
 
@@ -112,19 +113,33 @@ typedef struct {
 /* Importance-sampling bias (Sec. 4.1): B_phi = a S, B_pi = tan(theta_n) a S.
  *   NONE:  a = 0 (direct sampling, w = 1).
  *   CONST: a = A (the bias amplitude).
- *   MLP:   a = out0 of a 2->64->64->2 network with tanh hidden layers and a
- *          linear output, evaluated in FP32 at
- *          x0 = (phi - norm[0]) / norm[1],  x1 = (ln max(|pi|, 1e-30) - norm[2]) / norm[3].
+ *   MLP:   a learned amplitude a(phi, pi) (Sec. 5 notes that the
+ *          diffusion-based bias may not suffice in general and that the best
+ *          bias in 2D phase space is an open question): output 0 of a 2->64->64->2
+ *          network with tanh hidden layers and a linear output, whose inputs
+ *          are the normalised state
+ *            x0 = (phi - norm[0]) / norm[1],  x1 = (ln max(|pi|, 1e-30) - norm[2]) / norm[3].
  *          mlp_params (host, FPT_MLP_NPARAM floats, copied) is, row-major
  *          (out x in): W1[64x2] b1[64] W2[64x64] b2[64] W3[2x64] b3[2].
- *          Output 1 is not used with 1D noise.  mlp_every = k evaluates the
- *          network at steps n = 0, k, 2k, ... and holds a in between (k >= 1). */
+ *          Output 1 is not used with 1D noise.  The network is evaluated in
+ *          FP64 on grid_n[0] x grid_n[1] nodes spanning x0 in [grid_range[0],
+ *          grid_range[1]] and x1 in [grid_range[2], grid_range[3]] (node
+ *          (i, j) at x0 = lo0 + (hi0 - lo0) i/(n0 - 1), likewise x1); a(phi, pi)
+ *          is the bilinear interpolation of the node values at (x0, x1),
+ *          clamped to the edge cells.  mlp_every must be 0 (the tabulated
+ *          network; other values are reserved: FPT_EUNSUPPORTED).  Any
+ *          deterministic function of the state is an admissible control; the
+ *          weights use the same a, so the estimates stay unbiased.
+ *          Requires 2 <= grid_n[k], grid_n[0] grid_n[1] <= FPT_MLP_MAX_GRID,
+ *          finite norm with norm[1], norm[3] != 0, finite ranges with hi > lo. */
 typedef struct {
     int32_t kind;
     double A;
     const float *mlp_params;
     double norm[4];
     int32_t mlp_every;
+    int32_t grid_n[2];
+    double grid_range[4];
 } fpt_bias;
 
 /* Run options.  precision: FPT_FP64 keeps (phi, pi) in FP64; FPT_FP32_STATE
@@ -166,7 +181,8 @@ typedef struct fpt_ctx fpt_ctx;  /* opaque; owns its device table, histogram and
 /* ---- core API ---------------------------------------------------------------- */
 
 /* Validate and copy the inputs, allocate the context's device memory on the
- * current device.  No kernel is launched.  On success *out receives the
+ * current device.  No kernel is launched, except that an MLP bias is
+ * tabulated by a kernel on the null stream (waited for) before the return.  On success *out receives the
  * context (free it with fpt_destroy).  Errors: FPT_EINVAL (see the structs'
  * requirements; a NULL pointer; bias NULL is allowed and means NONE),
  * FPT_ENOMEM, FPT_EHIP. */
@@ -205,6 +221,53 @@ const char *fpt_strerror(int status);
 
 /* Text describing the last error of the calling thread ("" if none). */
 const char *fpt_last_error(void);
+
+/* ---- learned bias: inference and training ------------------------------------ */
+
+/* The context's network parameters (FPT_BIAS_MLP contexts only).  fpt_mlp_set
+ * copies FPT_MLP_NPARAM floats from params (host or device memory), clears the
+ * Adam moments and step count, and tabulates the network again; fpt_mlp_get
+ * copies the parameters out (host or device memory) and waits for the copy.
+ * Both are ordered on hip_stream: runs on other streams must be ordered after
+ * it by the caller, and the source of fpt_mlp_set must stay valid until the
+ * stream has reached the copy.  Errors: FPT_EINVAL (NULL, not an MLP
+ * context), FPT_ESTATE (wrong current device), FPT_EHIP. */
+int fpt_mlp_set(fpt_ctx *ctx, const float *params, void *hip_stream);
+int fpt_mlp_get(fpt_ctx *ctx, float *params, void *hip_stream);
+
+/* The tabulated amplitudes, node (i, j) at a_out[i grid_n[1] + j] (host array
+ * of grid_n[0] grid_n[1] doubles).  Waits for the device first. */
+int fpt_mlp_table(fpt_ctx *ctx, double *a_out);
+
+/* Gradient of the tail second moment J(theta) = E[w^2 1_T], T = {trajectories
+ * that crossed phi_end with deltaN = N - N_ref >= tail_lo}, at the context's
+ * current parameters theta, estimated from trajectories traj_offset ..
+ * traj_offset + n_traj - 1 sampled with the current control (seed, dN as in
+ * fpt_run; the context's histogram is not touched):
+ *   J = (1/n) sum_T w^2,
+ *   dJ/dtheta = (1/n) sum_T w^2 sum_k (-xi_k sqrt(dN)) da(x_k)/dtheta,
+ * the on-policy value of the replay gradient of E_old[w_old w_theta 1_T]
+ * (minimising J minimises the log-weight variance on the tail under the
+ * lognormal weight model of Sec. 4.1).  Tail trajectories are integrated again
+ * (replayed from their counter-based random numbers) to accumulate the
+ * grid-node weights G_c = (1/n) sum_T w^2 sum_k (-xi_k sqrt(dN)) beta_c(x_k),
+ * which are propagated through the network at the nodes.  Outputs: d_grad
+ * (device, FPT_MLP_NPARAM floats, required), d_G (device, grid_n[0] grid_n[1]
+ * doubles, or NULL), J_out and n_tail_out (host, or NULL; if either is given
+ * the call waits for the device).  Asynchronous on hip_stream otherwise;
+ * device scratch of about 36 bytes per trajectory (at most 2^22 at a time) is
+ * allocated on first use and kept.  Errors: FPT_EINVAL, FPT_ENOMEM, FPT_EHIP. */
+int fpt_mlp_grad(fpt_ctx *ctx, uint64_t n_traj, double dN, uint64_t seed, uint64_t traj_offset, double tail_lo,
+                 void *hip_stream, float *d_grad, double *d_G, double *J_out, uint64_t *n_tail_out);
+
+/* One Adam step (Kingma and Ba, 2015) on the context's parameters with the
+ * gradient d_grad (device, FPT_MLP_NPARAM floats): m = b1 m + (1 - b1) g,
+ * v = b2 v + (1 - b2) g^2, theta -= lr (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps),
+ * t = the context's step count + 1, computed in FP64 and stored in FP32; then
+ * the network is tabulated again.  Ordered on hip_stream.  Errors: FPT_EINVAL
+ * (lr <= 0, b1 or b2 outside [0, 1), eps <= 0, non-finite values), FPT_EHIP. */
+int fpt_mlp_adam(fpt_ctx *ctx, const float *d_grad, double lr, double beta1, double beta2, double eps,
+                 void *hip_stream);
 
 /* ---- noise table ------------------------------------------------------------- */
 

@@ -736,3 +736,28 @@ int orc_grid_replay_grad(int kind, const double pot[4],
     free(a_old); free(a_new); free(G);
     return 0;
 }
+
+/* ------------------------------------------------------------------------- */
+/* Adam (Kingma and Ba, "Adam: a method for stochastic optimization", 2015),   */
+/* the textbook update: step t of                                              */
+/*   m <- b1 m + (1 - b1) g,   v <- b2 v + (1 - b2) g^2,                       */
+/*   theta <- theta - lr mhat / (sqrt(vhat) + eps),                           */
+/*   mhat = m / (1 - b1^t),    vhat = v / (1 - b2^t),                          */
+/* in FP64, with theta, m and v stored in FP32 between steps.                  */
+/* ------------------------------------------------------------------------- */
+void orc_adam_step(float *theta, float *m, float *v, const float *grad, int n, int t, double lr, double b1,
+                   double b2, double eps)
+{
+    const double bc1 = 1.0 - pow(b1, (double)t);
+    const double bc2 = 1.0 - pow(b2, (double)t);
+    for (int i = 0; i < n; ++i) {
+        const double g = (double)grad[i];
+        const double mi = b1 * (double)m[i] + (1.0 - b1) * g;
+        const double vi = b2 * (double)v[i] + (1.0 - b2) * g * g;
+        m[i] = (float)mi;
+        v[i] = (float)vi;
+        const double mhat = mi / bc1;
+        const double vhat = vi / bc2;
+        theta[i] = (float)((double)theta[i] - lr * mhat / (sqrt(vhat) + eps));
+    }
+}

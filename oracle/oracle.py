@@ -97,6 +97,9 @@ def lib():
                                            ctypes.c_uint32, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_int64,
                                            ctypes.c_double, ctypes.c_double, dp, dp, dp, ctypes.c_int]
         L.orc_grid_replay_grad.restype = ctypes.c_int
+        L.orc_adam_step.argtypes = [fp, fp, fp, fp, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                    ctypes.c_double, ctypes.c_double]
+        L.orc_adam_step.restype = None
         _lib = L
     return _lib
 
@@ -270,6 +273,15 @@ def grid_replay_grad(prob: Problem, theta_old: np.ndarray, theta: np.ndarray, dN
     if rc != 0:
         raise ValueError("invalid oracle problem")
     return grad, float(J[0]), G.reshape(prob.grid_n[0], prob.grid_n[1])
+
+
+def adam_step(theta: np.ndarray, m: np.ndarray, v: np.ndarray, grad: np.ndarray, t: int, lr: float,
+              b1: float = 0.9, b2: float = 0.999, eps: float = 1e-8):
+    """Step t (1-based) of Adam on float32 arrays, updated in place."""
+    for a in (theta, m, v):
+        assert a.dtype == np.float32 and a.flags.c_contiguous
+    g = np.ascontiguousarray(grad, dtype=np.float32)
+    lib().orc_adam_step(_fp(theta), _fp(m), _fp(v), _fp(g), len(theta), t, lr, b1, b2, eps)
 
 
 # --------------------------------------------------------------------------

@@ -146,7 +146,78 @@ struct fpt_ctx {
     hipEvent_t ev_start = nullptr, ev_stop = nullptr, ev_done = nullptr;
     bool ran = false;
     uint64_t n_traj_total = 0;
+    // learned control (FPT_BIAS_MLP)
+    GridSpec grid{};
+    void *d_mlp = nullptr;                   // fixed-size part, carved below
+    float *d_params = nullptr, *d_adam_m = nullptr, *d_adam_v = nullptr;
+    double *d_node_a = nullptr, *d_G = nullptr, *d_work = nullptr, *d_J = nullptr;
+    double2 *d_grid64 = nullptr;
+    float4 *d_grid32 = nullptr;
+    unsigned long long *d_counters = nullptr;  // [0] tail count of a slice, [1] total, [2] mismatches, [3] replay cursor
+    void *d_train_acc = nullptr;             // private histogram of gradient runs
+    int adam_t = 0;
+    // per-trajectory scratch of gradient runs, grown on demand
+    void *d_scratch = nullptr;
+    size_t scratch_cap = 0;
 };
+
+static const size_t kGradSlice = size_t(1) << 22;
+
+// Device memory and first tabulation of the learned control of context c
+// (bias already validated).  Grid coordinates of the kernels:
+//   u0 = (x0 - lo0)(n0 - 1)/(hi0 - lo0) with x0 = (phi - c0)/s0, i.e. phi k0 + off0,
+//   u1 likewise from ln max(|pi|, 1e-30).
+static int mlp_setup(fpt_ctx *c, const fpt_bias &b)
+{
+    GridSpec &g = c->grid;
+    g.n0 = b.grid_n[0];
+    g.n1 = b.grid_n[1];
+    g.lo0 = b.grid_range[0];
+    g.hi0 = b.grid_range[1];
+    g.lo1 = b.grid_range[2];
+    g.hi1 = b.grid_range[3];
+    const size_t nn = (size_t)g.n0 * g.n1, nc = (size_t)(g.n0 - 1) * (g.n1 - 1);
+    const size_t nbytes_p = sizeof(float) * FPT_MLP_NPARAM;
+    size_t off = 0;
+    auto carve = [&](size_t bytes) {
+        const size_t o = off;
+        off = (off + bytes + 255) & ~size_t(255);
+        return o;
+    };
+    const size_t o_params = carve(nbytes_p), o_m = carve(2 * nbytes_p);   // m and v adjacent
+    const size_t o_node = carve(8 * nn), o_G = carve(8 * nn), o_work = carve(8 * 4 * nn * kMlpHidden);
+    const size_t o_J = carve(8), o_g64 = carve(32 * nc), o_g32 = carve(16 * nc), o_cnt = carve(8 * 4);
+    const size_t o_acc = carve(acc_bytes(c->opt.n_bins));
+    HIP_TRY(hipMalloc(&c->d_mlp, off));
+    unsigned char *base = static_cast<unsigned char *>(c->d_mlp);
+    c->d_params = reinterpret_cast<float *>(base + o_params);
+    c->d_adam_m = reinterpret_cast<float *>(base + o_m);
+    c->d_adam_v = c->d_adam_m + FPT_MLP_NPARAM;
+    c->d_node_a = reinterpret_cast<double *>(base + o_node);
+    c->d_G = reinterpret_cast<double *>(base + o_G);
+    c->d_work = reinterpret_cast<double *>(base + o_work);
+    c->d_J = reinterpret_cast<double *>(base + o_J);
+    c->d_grid64 = reinterpret_cast<double2 *>(base + o_g64);
+    c->d_grid32 = reinterpret_cast<float4 *>(base + o_g32);
+    c->d_counters = reinterpret_cast<unsigned long long *>(base + o_cnt);
+    c->d_train_acc = base + o_acc;
+    HIP_TRY(hipMemset(c->d_mlp, 0, off));
+    HIP_TRY(hipMemcpy(c->d_params, b.mlp_params, nbytes_p, hipMemcpyHostToDevice));
+    Inst &I = c->inst;
+    I.bias_kind = kBiasMlp;
+    I.g_n0 = g.n0;
+    I.g_n1 = g.n1;
+    const double q0 = (double)(g.n0 - 1) / (g.hi0 - g.lo0), q1 = (double)(g.n1 - 1) / (g.hi1 - g.lo1);
+    I.g_k0 = q0 / b.norm[1];
+    I.g_off0 = -(b.norm[0] / b.norm[1] + g.lo0) * q0;
+    I.g_k1 = q1 / b.norm[3];
+    I.g_off1 = -(b.norm[2] / b.norm[3] + g.lo1) * q1;
+    I.grid64 = c->d_grid64;
+    I.grid32 = c->d_grid32;
+    HIP_TRY(mlp_tabulate(c->d_params, g, c->d_node_a, c->d_grid64, c->d_grid32, nullptr));
+    HIP_TRY(hipDeviceSynchronize());
+    return FPT_OK;
+}
 
 extern "C" int fpt_create(const fpt_potential *pot, const fpt_noise_table *table, const fpt_bias *bias,
                           const fpt_options *opts, fpt_ctx **out)
@@ -180,7 +251,19 @@ extern "C" int fpt_create(const fpt_potential *pot, const fpt_noise_table *table
     if (b.kind != FPT_BIAS_NONE && b.kind != FPT_BIAS_CONST && b.kind != FPT_BIAS_MLP)
         return fail(FPT_EINVAL, "unknown bias kind %d", b.kind);
     if (!is_finite(b.A)) return fail(FPT_EINVAL, "bias amplitude must be finite");
-    if (b.kind == FPT_BIAS_MLP) return fail(FPT_EUNSUPPORTED, "learned bias is not available in fpt_create yet");
+    if (b.kind == FPT_BIAS_MLP) {
+        if (!b.mlp_params) return fail(FPT_EINVAL, "MLP bias needs mlp_params");
+        for (int i = 0; i < 4; ++i)
+            if (!is_finite(b.norm[i]) || !is_finite(b.grid_range[i])) return fail(FPT_EINVAL, "MLP norm and grid range must be finite");
+        if (b.norm[1] == 0.0 || b.norm[3] == 0.0) return fail(FPT_EINVAL, "MLP norm scales must be non-zero");
+        if (b.mlp_every != 0) return fail(FPT_EUNSUPPORTED, "only the tabulated network (mlp_every = 0) is implemented");
+        if (b.grid_n[0] < 2 || b.grid_n[1] < 2 || (int64_t)b.grid_n[0] * b.grid_n[1] > FPT_MLP_MAX_GRID)
+            return fail(FPT_EINVAL, "MLP grid needs 2 <= n0, n1 and n0 n1 <= %d", FPT_MLP_MAX_GRID);
+        if (!(b.grid_range[1] > b.grid_range[0]) || !(b.grid_range[3] > b.grid_range[2]))
+            return fail(FPT_EINVAL, "MLP grid ranges need hi > lo");
+        for (int i = 0; i < FPT_MLP_NPARAM; ++i)
+            if (!std::isfinite(b.mlp_params[i])) return fail(FPT_EINVAL, "MLP parameters must be finite");
+    }
     // options
     const fpt_options &o = *opts;
     if (o.precision != FPT_FP64 && o.precision != FPT_FP32_STATE)
@@ -265,10 +348,21 @@ extern "C" int fpt_create(const fpt_potential *pot, const fpt_noise_table *table
                                                     : (double)o.n_bins / std::log(o.hi / o.lo);
     I.acc = base + off_acc;
     c->cursor = reinterpret_cast<unsigned long long *>(base + off_cursor);
-    if (em_lds_bytes(o.n_bins, nt) > c->lds_per_block_max) {
+    if (b.kind == FPT_BIAS_MLP) {
+        rc = mlp_setup(c, b);
+        if (rc) {
+            fpt_destroy(c);
+            return rc;
+        }
+    }
+    const int n_cells = grid_cells(I);
+    size_t need = em_lds_bytes(o.n_bins, nt, o.precision, n_cells);
+    if (b.kind == FPT_BIAS_MLP)
+        need = std::max(need, replay_lds_bytes(nt, o.precision, n_cells, c->grid.n0 * c->grid.n1));
+    if (need > c->lds_per_block_max) {
         fpt_destroy(c);
-        return fail(FPT_EINVAL, "noise table and histogram do not fit in LDS (%zu > %zu bytes)",
-                    em_lds_bytes(o.n_bins, nt), (size_t)lds_max);
+        return fail(FPT_EINVAL, "noise table, control grid and histogram do not fit in LDS (%zu > %zu bytes)", need,
+                    (size_t)lds_max);
     }
     *out = c;
     return FPT_OK;
@@ -314,8 +408,9 @@ extern "C" int fpt_run(fpt_ctx *c, uint64_t n_traj, double dN, uint64_t seed, ui
     const int block = c->opt.block_size ? c->opt.block_size : 1024;
     int grid = 0;
     const void *fn = em_kernel_ptr(c->precision, c->inst.bias_kind, c->inst.n_tab > 1, c->inst.all_S_pos != 0);
-    int rc = occupancy_grid(fn, block, em_lds_bytes(c->inst.hist.n_bins, c->inst.n_tab), c->cu_count,
-                            c->opt.blocks_per_cu, grid);
+    int rc = occupancy_grid(fn, block, em_lds_bytes(c->inst.hist.n_bins, c->inst.n_tab, c->precision,
+                                                     grid_cells(c->inst)),
+                            c->cu_count, c->opt.blocks_per_cu, grid);
     if (rc) return rc;
     HIP_TRY(zero_words(p.cursor, 1, s));
     HIP_TRY(hipEventRecord(c->ev_start, s));
@@ -392,7 +487,182 @@ extern "C" void fpt_destroy(fpt_ctx *c)
     if (c->ev_stop) (void)hipEventDestroy(c->ev_stop);
     if (c->ev_done) (void)hipEventDestroy(c->ev_done);
     if (c->d_mem) (void)hipFree(c->d_mem);
+    if (c->d_mlp) (void)hipFree(c->d_mlp);
+    if (c->d_scratch) (void)hipFree(c->d_scratch);
     delete c;
+}
+
+// ---------------------------------------------------------------------------
+// learned control: parameters, gradient, Adam
+// ---------------------------------------------------------------------------
+static int mlp_check(fpt_ctx *c)
+{
+    if (!c) return fail(FPT_EINVAL, "context is NULL");
+    if (c->inst.bias_kind != kBiasMlp) return fail(FPT_EINVAL, "the context has no learned bias");
+    int dev = -1;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev != c->device) return fail(FPT_ESTATE, "current device %d differs from the context's %d", dev, c->device);
+    return FPT_OK;
+}
+
+extern "C" int fpt_mlp_set(fpt_ctx *c, const float *params, void *hip_stream)
+{
+    int rc = mlp_check(c);
+    if (rc) return rc;
+    if (!params) return fail(FPT_EINVAL, "params is NULL");
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    HIP_TRY(hipMemcpyAsync(c->d_params, params, sizeof(float) * FPT_MLP_NPARAM, hipMemcpyDefault, s));
+    // the Adam moments m and v are adjacent: 2 x 4482 floats = 4482 words
+    HIP_TRY(zero_words(reinterpret_cast<unsigned long long *>(c->d_adam_m), FPT_MLP_NPARAM, s));
+    c->adam_t = 0;
+    HIP_TRY(mlp_tabulate(c->d_params, c->grid, c->d_node_a, c->d_grid64, c->d_grid32, s));
+    return FPT_OK;
+}
+
+extern "C" int fpt_mlp_get(fpt_ctx *c, float *params, void *hip_stream)
+{
+    int rc = mlp_check(c);
+    if (rc) return rc;
+    if (!params) return fail(FPT_EINVAL, "params is NULL");
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    HIP_TRY(hipMemcpyAsync(params, c->d_params, sizeof(float) * FPT_MLP_NPARAM, hipMemcpyDefault, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    return FPT_OK;
+}
+
+extern "C" int fpt_mlp_table(fpt_ctx *c, double *a_out)
+{
+    int rc = mlp_check(c);
+    if (rc) return rc;
+    if (!a_out) return fail(FPT_EINVAL, "a_out is NULL");
+    HIP_TRY(hipDeviceSynchronize());
+    HIP_TRY(hipMemcpy(a_out, c->d_node_a, sizeof(double) * c->grid.n0 * c->grid.n1, hipMemcpyDeviceToHost));
+    return FPT_OK;
+}
+
+extern "C" int fpt_mlp_grad(fpt_ctx *c, uint64_t n_traj, double dN, uint64_t seed, uint64_t traj_offset,
+                            double tail_lo, void *hip_stream, float *d_grad, double *d_G, double *J_out,
+                            uint64_t *n_tail_out)
+{
+    int rc = mlp_check(c);
+    if (rc) return rc;
+    if (!d_grad) return fail(FPT_EINVAL, "d_grad is NULL");
+    if (!(dN > 0.0) || !is_finite(dN)) return fail(FPT_EINVAL, "dN must be finite and > 0");
+    if (!is_finite(tail_lo)) return fail(FPT_EINVAL, "tail_lo must be finite");
+    if (n_traj == 0) return fail(FPT_EINVAL, "n_traj must be > 0");
+    if (traj_offset + n_traj < traj_offset) return fail(FPT_EINVAL, "trajectory range overflows 64 bits");
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    // per-trajectory scratch: N, ln w (8 B each), steps (4 B) and a tail entry (16 B)
+    const size_t slice = std::min<uint64_t>(n_traj, kGradSlice);
+    if (slice > c->scratch_cap) {
+        if (c->d_scratch) {
+            HIP_TRY(hipDeviceSynchronize());
+            HIP_TRY(hipFree(c->d_scratch));
+            c->d_scratch = nullptr;
+            c->scratch_cap = 0;
+        }
+        const size_t bytes = slice * (8 + 8 + 4 + 16) + 1024;
+        if (hipMalloc(&c->d_scratch, bytes) != hipSuccess) {
+            c->d_scratch = nullptr;
+            return fail(FPT_ENOMEM, "gradient scratch of %zu bytes", bytes);
+        }
+        c->scratch_cap = slice;
+    }
+    const size_t cap = c->scratch_cap;
+    unsigned char *sb = static_cast<unsigned char *>(c->d_scratch);
+    TailEntry *d_tail = reinterpret_cast<TailEntry *>(sb);
+    double *d_N = reinterpret_cast<double *>(sb + 16 * cap);
+    double *d_lnw = d_N + cap;
+    uint32_t *d_steps = reinterpret_cast<uint32_t *>(d_lnw + cap);
+    unsigned long long *cnt = c->d_counters;
+    const GridSpec &g = c->grid;
+    const size_t n_nodes = (size_t)g.n0 * g.n1;
+
+    HIP_TRY(zero_words(reinterpret_cast<unsigned long long *>(c->d_G), n_nodes, s));
+    HIP_TRY(zero_words(reinterpret_cast<unsigned long long *>(c->d_J), 1, s));
+    HIP_TRY(zero_words(cnt, 4, s));
+
+    EmParams p{};
+    p.inst = c->inst;
+    p.inst.acc = c->d_train_acc;
+    p.run.dN = dN;
+    p.run.sqrt_dN = std::sqrt(dN);
+    p.run.key0 = (uint32_t)seed;
+    p.run.key1 = (uint32_t)(seed >> 32);
+    p.run.chunk = c->opt.chunk ? c->opt.chunk : 128;
+    p.cursor = c->cursor;
+    p.d_N = d_N;
+    p.d_lnw = d_lnw;
+    p.d_steps = d_steps;
+    const int block = c->opt.block_size ? c->opt.block_size : 1024;
+    int grid_em = 0, grid_rp = 0;
+    const int n_cells = grid_cells(c->inst);
+    rc = occupancy_grid(em_kernel_ptr(c->precision, kBiasMlp, c->inst.n_tab > 1, c->inst.all_S_pos != 0), block,
+                        em_lds_bytes(c->opt.n_bins, c->inst.n_tab, c->precision, n_cells), c->cu_count,
+                        c->opt.blocks_per_cu, grid_em);
+    if (rc) return rc;
+    rc = occupancy_grid(replay_kernel_ptr(c->precision, c->inst.all_S_pos != 0), block,
+                        replay_lds_bytes(c->inst.n_tab, c->precision, n_cells, (int)n_nodes), c->cu_count,
+                        c->opt.blocks_per_cu, grid_rp);
+    if (rc) return rc;
+    ReplayParams rp{};
+    rp.inst = c->inst;
+    rp.run = p.run;
+    rp.tail = d_tail;
+    rp.n_tail = &cnt[0];
+    rp.d_G = c->d_G;
+    rp.cursor = &cnt[3];
+    rp.mismatch = &cnt[2];
+    for (uint64_t done = 0; done < n_traj; done += cap) {
+        const uint64_t m = std::min<uint64_t>(cap, n_traj - done);
+        HIP_TRY(zero_words(reinterpret_cast<unsigned long long *>(c->d_train_acc), acc_words(c->opt.n_bins), s));
+        HIP_TRY(zero_words(c->cursor, 1, s));
+        HIP_TRY(zero_words(&cnt[0], 1, s));
+        HIP_TRY(zero_words(&cnt[3], 1, s));
+        p.traj_offset = traj_offset + done;
+        p.n_traj = m;
+        HIP_TRY(em_launch(p, c->precision, grid_em, block, s));
+        HIP_TRY(mlp_tail_compact(d_N, d_lnw, d_steps, m, traj_offset + done, c->opt.N_ref, tail_lo, d_tail, &cnt[0],
+                                 &cnt[1], c->d_J, s));
+        HIP_TRY(replay_launch(rp, c->precision, grid_rp, block, s));
+    }
+    HIP_TRY(mlp_backprop(c->d_params, g, c->d_G, (double)n_traj, c->d_work, d_grad, s));
+    if (d_G) {
+        // G / n as documented (scaled copy on the device)
+        HIP_TRY(mlp_scale_copy(c->d_G, 1.0 / (double)n_traj, d_G, n_nodes, s));
+    }
+    if (J_out || n_tail_out) {
+        double J = 0.0;
+        unsigned long long h_cnt[4] = {0, 0, 0, 0};
+        HIP_TRY(hipMemcpyAsync(&J, c->d_J, sizeof J, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipMemcpyAsync(h_cnt, cnt, sizeof h_cnt, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        if (h_cnt[2] != 0)
+            return fail(FPT_EHIP, "%llu replayed trajectories did not end with a passage", (unsigned long long)h_cnt[2]);
+        if (J_out) *J_out = J / (double)n_traj;
+        if (n_tail_out) *n_tail_out = h_cnt[1];
+    }
+    return FPT_OK;
+}
+
+extern "C" int fpt_mlp_adam(fpt_ctx *c, const float *d_grad, double lr, double beta1, double beta2, double eps,
+                            void *hip_stream)
+{
+    int rc = mlp_check(c);
+    if (rc) return rc;
+    if (!d_grad) return fail(FPT_EINVAL, "d_grad is NULL");
+    if (!is_finite(lr) || !(lr > 0.0)) return fail(FPT_EINVAL, "lr must be finite and > 0");
+    if (!(beta1 >= 0.0 && beta1 < 1.0) || !(beta2 >= 0.0 && beta2 < 1.0))
+        return fail(FPT_EINVAL, "beta1 and beta2 must lie in [0, 1)");
+    if (!is_finite(eps) || !(eps > 0.0)) return fail(FPT_EINVAL, "eps must be finite and > 0");
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    const int t = c->adam_t + 1;
+    const double bc1 = 1.0 - std::pow(beta1, (double)t), bc2 = 1.0 - std::pow(beta2, (double)t);
+    HIP_TRY(mlp_adam(c->d_params, c->d_adam_m, c->d_adam_v, d_grad, FPT_MLP_NPARAM, lr, beta1, beta2, eps, bc1, bc2,
+                     s));
+    HIP_TRY(mlp_tabulate(c->d_params, c->grid, c->d_node_a, c->d_grid64, c->d_grid32, s));
+    c->adam_t = t;
+    return FPT_OK;
 }
 
 // ---------------------------------------------------------------------------
@@ -463,6 +733,7 @@ extern "C" int fpt_batch_create(fpt_ctx *const *ctx, int32_t n_inst, const fpt_b
         if (!ctx[i]) return fail(FPT_EINVAL, "context %d is NULL", i);
         if (ctx[i]->device != ctx[0]->device) return fail(FPT_EINVAL, "contexts live on different devices");
         if (ctx[i]->precision != ctx[0]->precision) return fail(FPT_EINVAL, "contexts mix FP64 and FP32 state");
+        if (ctx[i]->inst.bias_kind == kBiasMlp) return fail(FPT_EINVAL, "a batch cannot hold a learned bias");
     }
     int dev = -1;
     HIP_TRY(hipGetDevice(&dev));
@@ -489,7 +760,7 @@ extern "C" int fpt_batch_create(fpt_ctx *const *ctx, int32_t n_inst, const fpt_b
         b->probe_acc_off.push_back(probe_bytes);
         probe_bytes += acc_bytes(I.hist.n_bins);
     }
-    if (em_lds_bytes(b->max_bins, b->max_tab) > b->lds_max) {
+    if (em_lds_bytes(b->max_bins, b->max_tab, b->precision, 0) > b->lds_max) {
         batch_free(b);
         return fail(FPT_EINVAL, "largest table and histogram do not fit in LDS");
     }
@@ -584,7 +855,7 @@ static int batch_launch_items(fpt_batch *b, const std::vector<WorkItem> &items, 
     HIP_TRY(hipMemcpyAsync(b->d_run, b->h_run, sizeof(BatchRun), hipMemcpyHostToDevice, s));
     const void *fn = batch_kernel_ptr(b->precision, b->bias_kind, b->all_pos);
     int grid = 0;
-    rc = occupancy_grid(fn, block, em_lds_bytes(b->max_bins, b->max_tab), b->cu_count, 0, grid);
+    rc = occupancy_grid(fn, block, em_lds_bytes(b->max_bins, b->max_tab, b->precision, 0), b->cu_count, 0, grid);
     if (rc) return rc;
     if (graph) {
         if (!b->gexec || b->graph_stream != s || b->graph_block != block || b->graph_items != b->d_items) {

@@ -269,6 +269,128 @@ __device__ __forceinline__ void stage_table32(const Inst &I, float4 *l_tab)
 }
 
 // ---------------------------------------------------------------------------
+// Learned control, tabulated: the amplitude a(phi, pi) is the bilinear
+// interpolation of the network's values on a uniform grid of the normalised
+// inputs (x0, x1) = ((phi - c0)/s0, (ln max(|pi|, 1e-30) - c1)/s1), clamped to
+// the edge cells.  A deterministic function of the state is an admissible
+// importance-sampling control (Sec. 4.1: the bias may depend on the state as
+// long as the weight uses the same bias), and the weights below use this same
+// amplitude, so the estimator stays unbiased.
+//
+// Replay (gradient) mode: the lanes integrate listed trajectories again with
+// the same control and scatter each step's factor -xi sqrt(dN) (the on-policy
+// value of -(e_k - a_k dN), e_k = a_k dN + xi_k sqrt(dN)) onto the four nodes
+// of the step's cell with the bilinear weights, scaled by the path's w^2.  A
+// lane keeps running sums for its current cell in registers and adds them to
+// the block's LDS node array when the path leaves the cell or ends.
+// ---------------------------------------------------------------------------
+struct GridConsts64 {
+    double k0, off0, k1, off1, imax0, imax1;
+    int n1c;                   // cells per row, n1 - 1
+};
+
+__device__ __forceinline__ GridConsts64 grid_consts64(const Inst &I)
+{
+    GridConsts64 g;
+    g.k0 = I.g_k0;
+    g.off0 = I.g_off0;
+    g.k1 = I.g_k1;
+    g.off1 = I.g_off1;
+    g.imax0 = (double)(I.g_n0 - 2);
+    g.imax1 = (double)(I.g_n1 - 2);
+    g.n1c = I.g_n1 - 1;
+    return g;
+}
+
+// a(phi, pi) from the staged cells; also the cell and the fractions inside it.
+// fmin/fmax map NaN and infinite coordinates onto the edge cells, so the cell
+// index stays inside the table for any state.
+__device__ __forceinline__ double grid_amp64(const GridConsts64 &g, const double2 *l_grid, double phi, double pi_,
+                                             int &cell, double &f0, double &f1)
+{
+    const double u0 = fma(phi, g.k0, g.off0);
+    const double u1 = fma(log(fmax(fabs(pi_), 1e-30)), g.k1, g.off1);
+    const double i0 = fmin(fmax(floor(u0), 0.0), g.imax0);
+    const double i1 = fmin(fmax(floor(u1), 0.0), g.imax1);
+    f0 = fmin(fmax(u0 - i0, 0.0), 1.0);
+    f1 = fmin(fmax(u1 - i1, 0.0), 1.0);
+    cell = (int)i0 * g.n1c + (int)i1;
+    const double2 c0 = l_grid[2 * cell], c1 = l_grid[2 * cell + 1];
+    const double b0 = fma(f0, c0.y - c0.x, c0.x);
+    const double b1 = fma(f0, c1.y - c1.x, c1.x);
+    return fma(f1, b1 - b0, b0);
+}
+
+struct GridConsts32 {
+    float k0, off0;            // u0 = x k0 + off0 with x = phi - phi_end
+    float k1, off1;            // u1 = log2 max(|pi|, 1e-30) k1 + off1
+    float imax0, imax1;
+    int n1c;
+};
+
+__device__ __forceinline__ GridConsts32 grid_consts32(const Inst &I)
+{
+    GridConsts32 g;
+    g.k0 = (float)I.g_k0;
+    g.off0 = (float)fma(I.phi_end, I.g_k0, I.g_off0);
+    g.k1 = (float)(I.g_k1 * 0.69314718055994531);
+    g.off1 = (float)I.g_off1;
+    g.imax0 = (float)(I.g_n0 - 2);
+    g.imax1 = (float)(I.g_n1 - 2);
+    g.n1c = I.g_n1 - 1;
+    return g;
+}
+
+__device__ __forceinline__ float grid_amp32(const GridConsts32 &g, const float4 *l_grid, float x, float pi_, int &cell,
+                                            float &f0, float &f1)
+{
+    const float u0 = fmaf(x, g.k0, g.off0);
+    const float u1 = fmaf(__builtin_amdgcn_logf(fmaxf(fabsf(pi_), 1e-30f)), g.k1, g.off1);
+    const float i0 = fminf(fmaxf(floorf(u0), 0.0f), g.imax0);
+    const float i1 = fminf(fmaxf(floorf(u1), 0.0f), g.imax1);
+    f0 = fminf(fmaxf(u0 - i0, 0.0f), 1.0f);
+    f1 = fminf(fmaxf(u1 - i1, 0.0f), 1.0f);
+    cell = (int)i0 * g.n1c + (int)i1;
+    const float4 c = l_grid[cell];
+    const float b0 = fmaf(f0, c.y - c.x, c.x);
+    const float b1 = fmaf(f0, c.w - c.z, c.z);
+    return fmaf(f1, b1 - b0, b0);
+}
+
+// Where a replay sends its results.
+struct ReplayTo {
+    const TailEntry *tail;
+    double *l_G;                       // node weights of the block (LDS), n0 n1
+    unsigned long long *mismatch;      // global count of replays that did not end with a passage
+};
+
+// Add a lane's running sums for `cell` (corner order (i0, i1), (i0 + 1, i1),
+// (i0, i1 + 1), (i0 + 1, i1 + 1)) times ww to the LDS node weights.
+template <typename T>
+__device__ __forceinline__ void grad_flush(const ReplayTo &rp, int n1c, int cell, T s[4], double ww)
+{
+    if (cell >= 0) {
+        const int k = cell + cell / n1c;          // node (i0, i1)
+        const int n1 = n1c + 1;
+        atomicAdd(&rp.l_G[k], ww * (double)s[0]);
+        atomicAdd(&rp.l_G[k + n1], ww * (double)s[1]);
+        atomicAdd(&rp.l_G[k + 1], ww * (double)s[2]);
+        atomicAdd(&rp.l_G[k + n1 + 1], ww * (double)s[3]);
+    }
+    s[0] = s[1] = s[2] = s[3] = T(0);
+}
+
+template <typename T>
+__device__ __forceinline__ void grad_add(T s[4], T c, T f0, T f1)
+{
+    const T p1 = c * f1, p0 = c - p1;        // c f1, c (1 - f1)
+    s[0] += p0 - p0 * f0;
+    s[1] += p0 * f0;
+    s[2] += p1 - p1 * f0;
+    s[3] += p1 * f0;
+}
+
+// ---------------------------------------------------------------------------
 // FP64 state: the lanes of one wave integrate trajectories of instance I,
 // claimed from `cursor` (global or LDS), until the range is exhausted.
 //
@@ -279,17 +401,23 @@ __device__ __forceinline__ void stage_table32(const Inst &I, float4 *l_tab)
 // trajectory (first passage, eps_1 >= 1) is recorded in a branch that is taken
 // about once per 1e4-1e5 steps and retired once the group is done.  Censoring
 // at max_steps needs a test before every step, so groups that can reach
-// max_steps take a separate variant.
+// max_steps take a separate variant.  GRAD: replay the trajectories listed in
+// rp.tail (cursor over the list) and scatter the gradient factors instead of
+// retiring into the histogram.
 // ---------------------------------------------------------------------------
-template <int BIAS, bool TAB, bool ALLPOS>
-__device__ __forceinline__ void lanes_fp64(const Inst &I, const RunArgs &R, const double2 *l_tab, const RetireTo &rt,
-                                           unsigned long long *cursor, uint64_t n_traj, uint64_t traj_offset)
+template <int BIAS, bool TAB, bool ALLPOS, bool GRAD>
+__device__ __forceinline__ void lanes_fp64(const Inst &I, const RunArgs &R, const double2 *l_tab, const double2 *l_grid,
+                                           const RetireTo &rt, const ReplayTo &rp, unsigned long long *cursor,
+                                           uint64_t n_traj, uint64_t traj_offset)
 {
+    static_assert(!GRAD || BIAS == kBiasMlp, "replay needs the tabulated control");
     const DriftConsts dk = drift_consts(I);
+    const GridConsts64 gc = grid_consts64(I);
     const double S0 = l_tab[0].x, t0 = l_tab[0].y;
     const double dN = R.dN, sqrt_dN = R.sqrt_dN, phi_end = I.phi_end, phi_T = I.phi_T;
-    const double a = (BIAS == kBiasConst) ? I.A : 0.0;
-    const double half_a2_dN = 0.5 * a * a * dN;
+    const double a_const = (BIAS == kBiasConst) ? I.A : 0.0;
+    const double half_a2_dN = 0.5 * a_const * a_const * dN;
+    const double half_dN = 0.5 * dN;
     const double jmax = (double)(staged_nodes(I) - 2);
     const double s_plus = in_vgpr(dk.s_plus), s_minus = in_vgpr(dk.s_minus);
 
@@ -299,6 +427,14 @@ __device__ __forceinline__ void lanes_fp64(const Inst &I, const RunArgs &R, cons
     bool live = has;          // has a trajectory that has not ended yet
     double phi = I.phi_in, pi_ = I.pi_in, lnw = 0.0;
     uint32_t n = 0;
+    uint64_t traj = 0;        // GRAD: the listed trajectory
+    double ww = 0.0;          // GRAD: its weight w^2
+    int g_cell = -1;          // GRAD: cell of the running sums
+    double g_s[4] = {0.0, 0.0, 0.0, 0.0};
+    if (GRAD && has) {
+        traj = rp.tail[rel].traj;
+        ww = rp.tail[rel].ww;
+    }
 
     auto group = [&](auto censor_tag, const double z[4]) {
         constexpr bool CENSOR = decltype(censor_tag)::value;
@@ -332,17 +468,31 @@ __device__ __forceinline__ void lanes_fp64(const Inst &I, const RunArgs &R, cons
                 S = S0;
                 t = t0;
             }
+            double a = a_const;
+            int cell = 0;
+            double f0 = 0.0, f1 = 0.0;
+            if (BIAS == kBiasMlp) a = grid_amp64(gc, l_grid, phi, pi_, cell, f0, f1);
             const double zs = z[j];                       // xi sqrt(dN)
             const double noise = S * zs;
             const double aS = a * S;
             const double phi_n = phi + (pi_ + aS) * dN + noise;
             const double pi_n = pi_ - (3.0 - 0.5 * pi_ * pi_) * (pi_ + r) * dN + t * (aS * dN + noise);
-            if (BIAS != kBiasNone) {
+            if (BIAS == kBiasConst) {
                 if (ALLPOS) {
                     lnw -= a * zs + half_a2_dN;
                 } else {
                     lnw -= (S > 0.0) ? a * zs + half_a2_dN : 0.0;
                 }
+            } else if (BIAS == kBiasMlp) {
+                const double dA = fma(a, zs, a * a * half_dN);
+                lnw -= (ALLPOS || S > 0.0) ? dA : 0.0;
+            }
+            if (GRAD && live) {
+                if (cell != g_cell) {
+                    grad_flush(rp, gc.n1c, g_cell, g_s, ww);
+                    g_cell = cell;
+                }
+                grad_add(g_s, (ALLPOS || S > 0.0) ? -zs : 0.0, f0, f1);
             }
             const bool crossed = phi_n <= phi_end;
             const bool ended = 0.5 * pi_n * pi_n >= 1.0;
@@ -358,15 +508,23 @@ __device__ __forceinline__ void lanes_fp64(const Inst &I, const RunArgs &R, cons
             pi_ = pi_n;
             n += 1;
         }
-        if (fresh) retire(rt, rel, ev_status, ev_n, ev_N, ev_lnw);
+        if (fresh) {
+            if (GRAD) {
+                grad_flush(rp, gc.n1c, g_cell, g_s, ww);
+                g_cell = -1;
+                if (ev_status != 0u) atomicAdd(rp.mismatch, 1ull);
+            } else {
+                retire(rt, rel, ev_status, ev_n, ev_N, ev_lnw);
+            }
+        }
     };
 
     while (__any(has)) {
         for (int k = 0; k < R.chunk; k += 4) {
             if (!__any(live)) break;
-            const uint64_t traj = traj_offset + rel;
+            const uint64_t tr = GRAD ? traj : traj_offset + rel;
             uint32_t w[4];
-            philox4x32_10(n >> 2, (uint32_t)traj, (uint32_t)(traj >> 32), I.instance, R.key0, R.key1, w);
+            philox4x32_10(n >> 2, (uint32_t)tr, (uint32_t)(tr >> 32), I.instance, R.key0, R.key1, w);
             double z[4];
             box_muller64(w[0], w[1], sqrt_dN, z[0], z[1]);
             box_muller64(w[2], w[3], sqrt_dN, z[2], z[3]);
@@ -381,6 +539,10 @@ __device__ __forceinline__ void lanes_fp64(const Inst &I, const RunArgs &R, cons
             pi_ = I.pi_in;
             lnw = 0.0;
             n = 0;
+            if (GRAD) {
+                traj = rp.tail[rel].traj;
+                ww = rp.tail[rel].ww;
+            }
         }
     }
 }
@@ -430,11 +592,14 @@ __device__ __forceinline__ void two_sum_fast(float &hi, float &lo, float d)
     lo += e;
 }
 
-template <int BIAS, bool TAB, bool ALLPOS>
-__device__ __forceinline__ void lanes_fp32(const Inst &I, const RunArgs &R, const float4 *l_tab, const RetireTo &rt,
-                                           unsigned long long *cursor, uint64_t n_traj, uint64_t traj_offset)
+template <int BIAS, bool TAB, bool ALLPOS, bool GRAD>
+__device__ __forceinline__ void lanes_fp32(const Inst &I, const RunArgs &R, const float4 *l_tab, const float4 *l_grid,
+                                           const RetireTo &rt, const ReplayTo &rp, unsigned long long *cursor,
+                                           uint64_t n_traj, uint64_t traj_offset)
 {
+    static_assert(!GRAD || BIAS == kBiasMlp, "replay needs the tabulated control");
     const F32Consts c = f32_consts(I, R);
+    const GridConsts32 gc = grid_consts32(I);
     const float S0 = l_tab[0].x, t0 = l_tab[0].z;
     const double x_in = I.phi_in - I.phi_end;
     const float x_in_hi = (float)x_in, x_in_lo = (float)(x_in - (double)x_in_hi);
@@ -442,6 +607,7 @@ __device__ __forceinline__ void lanes_fp32(const Inst &I, const RunArgs &R, cons
     const double dN = R.dN;
     const double A = (BIAS == kBiasConst) ? I.A : 0.0;
     const double half_a2_dN = 0.5 * A * A * dN;
+    const float half_dN = 0.5f * c.dN;
     const float s_plus = in_vgpr(c.s_plus), s_minus = in_vgpr(c.s_minus);
 
     bool exhausted = false;
@@ -449,9 +615,18 @@ __device__ __forceinline__ void lanes_fp32(const Inst &I, const RunArgs &R, cons
     bool has = claim(true, rel, cursor, n_traj, exhausted);
     bool live = has;          // has a trajectory that has not ended yet
     float xh = x_in_hi, xl = x_in_lo, ph = pi_in_hi, pl = pi_in_lo;
-    double zsum = 0.0;        // sum of xi sqrt(dN) over steps with S > 0 (constant bias)
-    uint32_t n_on = 0;        // number of such steps (counted only when some node has S = 0)
+    double zsum = 0.0;        // constant bias: sum of xi sqrt(dN) over steps with S > 0
+    uint32_t n_on = 0;        // constant bias: number of such steps (counted only when some node has S = 0)
+    double lnw = 0.0;         // learned bias: ln w up to the current group
     uint32_t n = 0;
+    uint64_t traj = 0;        // GRAD: the listed trajectory
+    double ww = 0.0;          // GRAD: its weight w^2
+    int g_cell = -1;          // GRAD: cell of the running sums
+    float g_s[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+    if (GRAD && has) {
+        traj = rp.tail[rel].traj;
+        ww = rp.tail[rel].ww;
+    }
 
     auto lnw_of = [&](double zs_total, uint32_t steps_on) -> double {
         return (BIAS == kBiasNone) ? 0.0 : -A * zs_total - (double)steps_on * half_a2_dN;
@@ -459,17 +634,21 @@ __device__ __forceinline__ void lanes_fp32(const Inst &I, const RunArgs &R, cons
 
     auto group = [&](auto censor_tag, const float z[4]) {
         constexpr bool CENSOR = decltype(censor_tag)::value;
-        float zacc = 0.0f;
+        float zacc = 0.0f;        // constant bias: sum of this group's xi sqrt(dN); learned: of its dA
         bool fresh = false;
         uint32_t ev_status, ev_n;   // written before use: read only where fresh is set
         double ev_N, ev_lnw;
+        auto lnw_now = [&](uint32_t steps) -> double {
+            if (BIAS == kBiasMlp) return lnw - (double)zacc;
+            return lnw_of(zsum + (double)zacc, ALLPOS ? steps : n_on);
+        };
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             if (CENSOR && live && n == I.max_steps) {
                 ev_status = kFlagCensored;
                 ev_n = n;
                 ev_N = __builtin_nan("");
-                ev_lnw = lnw_of(zsum + (double)zacc, ALLPOS ? n : n_on);
+                ev_lnw = lnw_now(n);
                 live = false;
                 fresh = true;
             }
@@ -488,12 +667,16 @@ __device__ __forceinline__ void lanes_fp32(const Inst &I, const RunArgs &R, cons
                 S = S0;
                 t = t0;
             }
+            float a = c.a;
+            int cell = 0;
+            float f0 = 0.0f, f1 = 0.0f;
+            if (BIAS == kBiasMlp) a = grid_amp32(gc, l_grid, xh, ph, cell, f0, f1);
             const float noise = S * z[j];                 // z is xi sqrt(dN)
-            const float aS = c.a * S;
+            const float aS = a * S;
             const float dx = fmaf(ph + aS, c.dN, noise);
             const float drift = fmaf(-0.5f * ph, ph, 3.0f) * (ph + r);
             const float dpi = fmaf(t, fmaf(aS, c.dN, noise), -drift * c.dN);
-            if (BIAS != kBiasNone) {
+            if (BIAS == kBiasConst) {
                 if (ALLPOS) {
                     zacc += z[j];
                 } else {
@@ -501,6 +684,16 @@ __device__ __forceinline__ void lanes_fp32(const Inst &I, const RunArgs &R, cons
                     zacc += on ? z[j] : 0.0f;
                     n_on += on ? 1u : 0u;
                 }
+            } else if (BIAS == kBiasMlp) {
+                const float dA = fmaf(a, z[j], a * a * half_dN);
+                zacc += (ALLPOS || S > 0.0f) ? dA : 0.0f;
+            }
+            if (GRAD && live) {
+                if (cell != g_cell) {
+                    grad_flush(rp, gc.n1c, g_cell, g_s, ww);
+                    g_cell = cell;
+                }
+                grad_add(g_s, (ALLPOS || S > 0.0f) ? -z[j] : 0.0f, f0, f1);
             }
             const float x0h = xh, x0l = xl;
             two_sum_fast(xh, xl, dx);
@@ -513,14 +706,23 @@ __device__ __forceinline__ void lanes_fp32(const Inst &I, const RunArgs &R, cons
                 const double x0 = (double)x0h + (double)x0l;
                 const double x1 = (double)xh + (double)xl;
                 ev_N = crossed ? (double)n * dN + dN * (x0 / (x0 - x1)) : (double)(n + 1) * dN;
-                ev_lnw = lnw_of(zsum + (double)zacc, ALLPOS ? n + 1 : n_on);
+                ev_lnw = lnw_now(n + 1);
                 live = false;
                 fresh = true;
             }
             n += 1;
         }
-        zsum += (double)zacc;
-        if (fresh) retire(rt, rel, ev_status, ev_n, ev_N, ev_lnw);
+        if (BIAS == kBiasMlp) lnw -= (double)zacc;
+        else zsum += (double)zacc;
+        if (fresh) {
+            if (GRAD) {
+                grad_flush(rp, gc.n1c, g_cell, g_s, ww);
+                g_cell = -1;
+                if (ev_status != 0u) atomicAdd(rp.mismatch, 1ull);
+            } else {
+                retire(rt, rel, ev_status, ev_n, ev_N, ev_lnw);
+            }
+        }
         // renormalise the pairs once per group
         const float s = xh + xl;
         xl = xl - (s - xh);
@@ -533,9 +735,9 @@ __device__ __forceinline__ void lanes_fp32(const Inst &I, const RunArgs &R, cons
     while (__any(has)) {
         for (int k = 0; k < R.chunk; k += 4) {
             if (!__any(live)) break;
-            const uint64_t traj = traj_offset + rel;
+            const uint64_t tr = GRAD ? traj : traj_offset + rel;
             uint32_t w[4];
-            philox4x32_10(n >> 2, (uint32_t)traj, (uint32_t)(traj >> 32), I.instance, R.key0, R.key1, w);
+            philox4x32_10(n >> 2, (uint32_t)tr, (uint32_t)(tr >> 32), I.instance, R.key0, R.key1, w);
             float z[4];
             box_muller32(w[0], w[1], c.sqrt_dN, z[0], z[1]);
             box_muller32(w[2], w[3], c.sqrt_dN, z[2], z[3]);
@@ -552,8 +754,37 @@ __device__ __forceinline__ void lanes_fp32(const Inst &I, const RunArgs &R, cons
             pl = pi_in_lo;
             zsum = 0.0;
             n_on = 0;
+            lnw = 0.0;
             n = 0;
+            if (GRAD) {
+                traj = rp.tail[rel].traj;
+                ww = rp.tail[rel].ww;
+            }
         }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// LDS layout of the kernels: [accumulators][noise table][control cells][node
+// weights], each part starting on a 16-byte boundary.
+// ---------------------------------------------------------------------------
+__host__ __device__ __forceinline__ size_t align16(size_t b) { return (b + 15) & ~(size_t)15; }
+__host__ __device__ __forceinline__ size_t tab_bytes(int n_tab) { return (size_t)(n_tab > 1 ? n_tab : 2) * 16; }
+__host__ __device__ __forceinline__ size_t cell_bytes(int precision, int n_cells)
+{
+    return (size_t)n_cells * (precision == 0 ? 32 : 16);
+}
+
+template <int PREC>
+__device__ __forceinline__ void stage_grid(const Inst &I, void *l_grid)
+{
+    const int nc = grid_cells(I);
+    if (PREC == 0) {
+        double2 *g = static_cast<double2 *>(l_grid);
+        for (int i = threadIdx.x; i < 2 * nc; i += blockDim.x) g[i] = I.grid64[i];
+    } else {
+        float4 *g = static_cast<float4 *>(l_grid);
+        for (int i = threadIdx.x; i < nc; i += blockDim.x) g[i] = I.grid32[i];
     }
 }
 
@@ -578,20 +809,57 @@ __global__ void __launch_bounds__(1024) FPT_EM_OCCUPANCY em_kernel(EmParams p)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     const LdsAcc acc = lds_acc(smem, p.inst.hist.n_bins);
-    void *l_tab = acc.sum + 4 * acc.nb + 4;
+    unsigned char *l_tab = smem + align16(acc_bytes(p.inst.hist.n_bins));
+    unsigned char *l_grid = l_tab + tab_bytes(p.inst.n_tab);
     zero_lds_acc(acc);
-    if (PREC == 0) stage_table64(p.inst, static_cast<double2 *>(l_tab));
-    else stage_table32(p.inst, static_cast<float4 *>(l_tab));
+    if (PREC == 0) stage_table64(p.inst, reinterpret_cast<double2 *>(l_tab));
+    else stage_table32(p.inst, reinterpret_cast<float4 *>(l_tab));
+    if (BIAS == kBiasMlp) stage_grid<PREC>(p.inst, l_grid);
     __syncthreads();
     const RetireTo rt = retire_to(p, acc);
+    const ReplayTo rp{nullptr, nullptr, nullptr};
     if (PREC == 0)
-        lanes_fp64<BIAS, TAB, ALLPOS>(p.inst, p.run, static_cast<const double2 *>(l_tab), rt, p.cursor, p.n_traj,
-                                      p.traj_offset);
+        lanes_fp64<BIAS, TAB, ALLPOS, false>(p.inst, p.run, reinterpret_cast<const double2 *>(l_tab),
+                                             reinterpret_cast<const double2 *>(l_grid), rt, rp, p.cursor, p.n_traj,
+                                             p.traj_offset);
     else
-        lanes_fp32<BIAS, TAB, ALLPOS>(p.inst, p.run, static_cast<const float4 *>(l_tab), rt, p.cursor, p.n_traj,
-                                      p.traj_offset);
+        lanes_fp32<BIAS, TAB, ALLPOS, false>(p.inst, p.run, reinterpret_cast<const float4 *>(l_tab),
+                                             reinterpret_cast<const float4 *>(l_grid), rt, rp, p.cursor, p.n_traj,
+                                             p.traj_offset);
     __syncthreads();
     flush_lds_acc(acc, p.inst.acc);
+}
+
+// Replay kernel: the listed trajectories with the tabulated control, scattering
+// gradient factors onto the grid nodes (LDS, then global atomics).
+template <int PREC, bool ALLPOS>
+__global__ void __launch_bounds__(1024) FPT_EM_OCCUPANCY replay_kernel(ReplayParams p)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const Inst &I = p.inst;
+    unsigned char *l_tab = smem;
+    unsigned char *l_grid = l_tab + tab_bytes(I.n_tab);
+    double *l_G = reinterpret_cast<double *>(l_grid + cell_bytes(PREC, grid_cells(I)));
+    const int n_nodes = I.g_n0 * I.g_n1;
+    for (int i = threadIdx.x; i < n_nodes; i += blockDim.x) l_G[i] = 0.0;
+    if (PREC == 0) stage_table64(I, reinterpret_cast<double2 *>(l_tab));
+    else stage_table32(I, reinterpret_cast<float4 *>(l_tab));
+    stage_grid<PREC>(I, l_grid);
+    __syncthreads();
+    RetireTo rt{};
+    const ReplayTo rp{p.tail, l_G, p.mismatch};
+    const uint64_t n_tail = *p.n_tail;
+    if (PREC == 0)
+        lanes_fp64<kBiasMlp, true, ALLPOS, true>(I, p.run, reinterpret_cast<const double2 *>(l_tab),
+                                                 reinterpret_cast<const double2 *>(l_grid), rt, rp, p.cursor, n_tail,
+                                                 0);
+    else
+        lanes_fp32<kBiasMlp, true, ALLPOS, true>(I, p.run, reinterpret_cast<const float4 *>(l_tab),
+                                                 reinterpret_cast<const float4 *>(l_grid), rt, rp, p.cursor, n_tail,
+                                                 0);
+    __syncthreads();
+    for (int i = threadIdx.x; i < n_nodes; i += blockDim.x)
+        if (l_G[i] != 0.0) unsafeAtomicAdd(&p.d_G[i], l_G[i]);
 }
 
 // ---------------------------------------------------------------------------
@@ -623,10 +891,10 @@ __global__ void __launch_bounds__(1024) FPT_EM_OCCUPANCY batch_kernel(const Inst
         const WorkItem W = items[it];
         const Inst I = insts[W.inst];
         const LdsAcc acc = lds_acc(smem, I.hist.n_bins);
-        void *l_tab = reinterpret_cast<unsigned char *>(smem) + acc_bytes(max_bins);
+        unsigned char *l_tab = smem + align16(acc_bytes(max_bins));
         zero_lds_acc(acc);
-        if (PREC == 0) stage_table64(I, static_cast<double2 *>(l_tab));
-        else stage_table32(I, static_cast<float4 *>(l_tab));
+        if (PREC == 0) stage_table64(I, reinterpret_cast<double2 *>(l_tab));
+        else stage_table32(I, reinterpret_cast<float4 *>(l_tab));
         __syncthreads();
         RetireTo rt;
         rt.d_N = nullptr;
@@ -636,12 +904,13 @@ __global__ void __launch_bounds__(1024) FPT_EM_OCCUPANCY batch_kernel(const Inst
         rt.sum = acc.sum;
         rt.nb = acc.nb;
         rt.hist = I.hist;
+        const ReplayTo rp{nullptr, nullptr, nullptr};
         if (PREC == 0)
-            lanes_fp64<BIAS, true, ALLPOS>(I, R, static_cast<const double2 *>(l_tab), rt, &s_cursor, W.count,
-                                           W.begin);
+            lanes_fp64<BIAS, true, ALLPOS, false>(I, R, reinterpret_cast<const double2 *>(l_tab), nullptr, rt, rp,
+                                                  &s_cursor, W.count, W.begin);
         else
-            lanes_fp32<BIAS, true, ALLPOS>(I, R, static_cast<const float4 *>(l_tab), rt, &s_cursor, W.count,
-                                           W.begin);
+            lanes_fp32<BIAS, true, ALLPOS, false>(I, R, reinterpret_cast<const float4 *>(l_tab), nullptr, rt, rp,
+                                                  &s_cursor, W.count, W.begin);
         __syncthreads();
         flush_lds_acc(acc, I.acc);
         __syncthreads();
@@ -659,34 +928,60 @@ const void *kptr() { return reinterpret_cast<const void *>(&em_kernel<PREC, BIAS
 template <int PREC, int BIAS, bool ALLPOS>
 const void *bptr() { return reinterpret_cast<const void *>(&batch_kernel<PREC, BIAS, ALLPOS>); }
 
+template <int PREC, int BIAS>
+struct KTab {
+    const void *p[2][2] = {{kptr<PREC, BIAS, false, false>(), kptr<PREC, BIAS, false, true>()},
+                           {kptr<PREC, BIAS, true, false>(), kptr<PREC, BIAS, true, true>()}};
+};
+
 }  // namespace
 
-size_t em_lds_bytes(int n_bins, int n_tab)
+size_t em_lds_bytes(int n_bins, int n_tab, int precision, int n_cells)
 {
-    const int nodes = n_tab > 1 ? n_tab : 2;
-    return acc_bytes(n_bins) + (size_t)nodes * 16;   // double2 or float4 per node
+    return align16(acc_bytes(n_bins)) + tab_bytes(n_tab) + cell_bytes(precision, n_cells);
+}
+
+size_t replay_lds_bytes(int n_tab, int precision, int n_cells, int n_nodes)
+{
+    return tab_bytes(n_tab) + cell_bytes(precision, n_cells) + (size_t)n_nodes * 8;
 }
 
 const void *em_kernel_ptr(int precision, int bias_kind, bool table, bool all_pos)
 {
-    // [precision][bias: none, const][table][all_pos]
-    static const void *const t[2][2][2][2] = {
-        {{{kptr<0, kBiasNone, false, false>(), kptr<0, kBiasNone, false, true>()},
-          {kptr<0, kBiasNone, true, false>(), kptr<0, kBiasNone, true, true>()}},
-         {{kptr<0, kBiasConst, false, false>(), kptr<0, kBiasConst, false, true>()},
-          {kptr<0, kBiasConst, true, false>(), kptr<0, kBiasConst, true, true>()}}},
-        {{{kptr<1, kBiasNone, false, false>(), kptr<1, kBiasNone, false, true>()},
-          {kptr<1, kBiasNone, true, false>(), kptr<1, kBiasNone, true, true>()}},
-         {{kptr<1, kBiasConst, false, false>(), kptr<1, kBiasConst, false, true>()},
-          {kptr<1, kBiasConst, true, false>(), kptr<1, kBiasConst, true, true>()}}}};
-    return t[precision ? 1 : 0][bias_kind == kBiasNone ? 0 : 1][table ? 1 : 0][all_pos ? 1 : 0];
+    static const KTab<0, kBiasNone> f0n;
+    static const KTab<0, kBiasConst> f0c;
+    static const KTab<0, kBiasMlp> f0m;
+    static const KTab<1, kBiasNone> f1n;
+    static const KTab<1, kBiasConst> f1c;
+    static const KTab<1, kBiasMlp> f1m;
+    const void *const(*t)[2];
+    if (precision == 0) t = bias_kind == kBiasNone ? f0n.p : bias_kind == kBiasConst ? f0c.p : f0m.p;
+    else t = bias_kind == kBiasNone ? f1n.p : bias_kind == kBiasConst ? f1c.p : f1m.p;
+    return t[table ? 1 : 0][all_pos ? 1 : 0];
 }
 
 hipError_t em_launch(const EmParams &p, int precision, int grid, int block, hipStream_t stream)
 {
-    const size_t lds = em_lds_bytes(p.inst.hist.n_bins, p.inst.n_tab);
+    const size_t lds = em_lds_bytes(p.inst.hist.n_bins, p.inst.n_tab, precision, grid_cells(p.inst));
     const void *fn = em_kernel_ptr(precision, p.inst.bias_kind, p.inst.n_tab > 1, p.inst.all_S_pos != 0);
     EmParams pp = p;
+    void *args[] = {&pp};
+    return hipLaunchKernel(fn, dim3(grid), dim3(block), args, lds, stream);
+}
+
+const void *replay_kernel_ptr(int precision, bool all_pos)
+{
+    static const void *const t[2][2] = {
+        {reinterpret_cast<const void *>(&replay_kernel<0, false>), reinterpret_cast<const void *>(&replay_kernel<0, true>)},
+        {reinterpret_cast<const void *>(&replay_kernel<1, false>), reinterpret_cast<const void *>(&replay_kernel<1, true>)}};
+    return t[precision ? 1 : 0][all_pos ? 1 : 0];
+}
+
+hipError_t replay_launch(const ReplayParams &p, int precision, int grid, int block, hipStream_t stream)
+{
+    const size_t lds = replay_lds_bytes(p.inst.n_tab, precision, grid_cells(p.inst), p.inst.g_n0 * p.inst.g_n1);
+    const void *fn = replay_kernel_ptr(precision, p.inst.all_S_pos != 0);
+    ReplayParams pp = p;
     void *args[] = {&pp};
     return hipLaunchKernel(fn, dim3(grid), dim3(block), args, lds, stream);
 }
@@ -705,7 +1000,7 @@ hipError_t batch_launch(int precision, int bias_kind, bool all_pos, const Inst *
                         const BatchRun *run, unsigned long long *item_cursor, int max_bins, int max_tab, int grid,
                         int block, hipStream_t stream)
 {
-    const size_t lds = em_lds_bytes(max_bins, max_tab);
+    const size_t lds = em_lds_bytes(max_bins, max_tab, precision, 0);
     const void *fn = batch_kernel_ptr(precision, bias_kind, all_pos);
     void *args[] = {&insts, &items, &run, &item_cursor, &max_bins};
     return hipLaunchKernel(fn, dim3(grid), dim3(block), args, lds, stream);

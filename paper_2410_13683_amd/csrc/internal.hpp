@@ -16,6 +16,7 @@ constexpr uint32_t kFlagCensored = 0x80000000u;
 constexpr uint32_t kFlagEndedEarly = 0x40000000u;
 constexpr int kMlpHidden = 64;
 constexpr int kMlpParams = 4482;
+constexpr int kMlpMaxGrid = 1024;    // nodes of the tabulated network
 
 // Histogram of deltaN = N - N_ref.  scale = n_bins/(hi - lo) for linear bins,
 // n_bins/ln(hi/lo) for log bins.
@@ -47,6 +48,12 @@ struct Inst {
     int32_t all_S_pos;               // every node has S > 0 (the ln w update needs no test)
     int32_t bias_kind;
     double A;
+    // learned amplitude tabulated on g_n0 x g_n1 nodes of the normalised inputs;
+    // grid coordinates u0 = phi g_k0 + g_off0, u1 = ln max(|pi|, 1e-30) g_k1 + g_off1
+    int32_t g_n0, g_n1;
+    double g_k0, g_off0, g_k1, g_off1;
+    const double2 *grid64;           // cell c = i0 (n1 - 1) + i1: [2c] = (a00, a10), [2c+1] = (a01, a11)
+    const float4 *grid32;            // cell c: (a00, a10, a01, a11) in FP32
     uint32_t instance;               // fourth Philox counter word
     uint32_t max_steps;
     HistSpec hist;
@@ -84,14 +91,57 @@ struct BatchRun {
     uint64_t n_items;
 };
 
+// One entry of the list of trajectories whose gradient contribution is replayed.
+struct TailEntry {
+    uint64_t traj;                   // global trajectory index
+    double ww;                       // w_old w_theta of the path (w^2 on-policy)
+};
+
+// One launch of the replay kernel: the trajectories of `tail`, integrated again
+// with the instance's tabulated control, scatter their per-step gradient factors
+// onto the grid nodes `d_G` (n0 n1 doubles, accumulated with atomics).
+struct ReplayParams {
+    Inst inst;
+    RunArgs run;
+    const TailEntry *tail;
+    const unsigned long long *n_tail;  // device count of entries
+    double *d_G;
+    unsigned long long *cursor;
+    unsigned long long *mismatch;      // replays that did not end with a passage
+};
+
 // Euler-Maruyama kernels (fpt_em.hip).
-size_t em_lds_bytes(int n_bins, int n_tab);
+__host__ __device__ inline int grid_cells(const Inst &I) { return I.bias_kind == kBiasMlp ? (I.g_n0 - 1) * (I.g_n1 - 1) : 0; }
+size_t em_lds_bytes(int n_bins, int n_tab, int precision, int n_cells);
+size_t replay_lds_bytes(int n_tab, int precision, int n_cells, int n_nodes);
 const void *em_kernel_ptr(int precision, int bias_kind, bool table, bool all_pos);
 hipError_t em_launch(const EmParams &p, int precision, int grid, int block, hipStream_t stream);
+const void *replay_kernel_ptr(int precision, bool all_pos);
+hipError_t replay_launch(const ReplayParams &p, int precision, int grid, int block, hipStream_t stream);
 const void *batch_kernel_ptr(int precision, int bias_kind, bool all_pos);
 hipError_t batch_launch(int precision, int bias_kind, bool all_pos, const Inst *insts, const WorkItem *items,
                         const BatchRun *run, unsigned long long *item_cursor, int max_bins, int max_tab, int grid,
                         int block, hipStream_t stream);
 hipError_t zero_words(unsigned long long *ptr, size_t n, hipStream_t stream);
+
+// Learned-control kernels (fpt_mlp.hip).  params: 4482 FP32 values,
+// W1[64x2] b1 W2[64x64] b2 W3[2x64] b3; the network is evaluated in FP64.
+struct GridSpec {
+    int32_t n0, n1;
+    double lo0, hi0, lo1, hi1;       // ranges of the normalised inputs covered by the nodes
+};
+hipError_t mlp_tabulate(const float *params, const GridSpec &g, double *node_a, double2 *grid64, float4 *grid32,
+                        hipStream_t stream);
+hipError_t mlp_tail_compact(const double *d_N, const double *d_lnw, const uint32_t *d_steps, uint64_t n,
+                            uint64_t traj_offset, double N_ref, double tail_lo, TailEntry *tail,
+                            unsigned long long *n_tail, unsigned long long *n_tail_total, double *J_sum,
+                            hipStream_t stream);
+// grad[4482] (FP32) = sum_c G_c / n_scale d a(x_c)/d theta over the grid nodes;
+// work: 4 n0 n1 64 doubles of scratch.
+hipError_t mlp_backprop(const float *params, const GridSpec &g, const double *G, double n_scale, double *work,
+                        float *grad, hipStream_t stream);
+hipError_t mlp_scale_copy(const double *src, double scale, double *dst, size_t n, hipStream_t stream);
+hipError_t mlp_adam(float *params, float *m, float *v, const float *grad, int n, double lr, double beta1,
+                    double beta2, double eps, double bc1, double bc2, hipStream_t stream);
 
 }  // namespace fpt

@@ -38,6 +38,7 @@ FPT_MAX_STEPS = 0x3FFFFFFF
 FPT_MAX_TABLE = 4096
 FPT_MAX_BINS = 1024
 FPT_MLP_NPARAM = 4482
+FPT_MLP_MAX_GRID = 1024
 
 _dp = ctypes.POINTER(ctypes.c_double)
 _fp = ctypes.POINTER(ctypes.c_float)
@@ -58,7 +59,8 @@ class fpt_noise_table(ctypes.Structure):
 
 class fpt_bias(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("A", ctypes.c_double), ("mlp_params", _fp),
-                ("norm", ctypes.c_double * 4), ("mlp_every", ctypes.c_int32)]
+                ("norm", ctypes.c_double * 4), ("mlp_every", ctypes.c_int32), ("grid_n", ctypes.c_int32 * 2),
+                ("grid_range", ctypes.c_double * 4)]
 
 
 class fpt_options(ctypes.Structure):
@@ -129,9 +131,17 @@ def load():
     L.fpt_batch_last_ms.argtypes = [ctypes.c_void_p, _dp]
     L.fpt_batch_destroy.argtypes = [ctypes.c_void_p]
     L.fpt_batch_destroy.restype = None
+    L.fpt_mlp_set.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+    L.fpt_mlp_get.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+    L.fpt_mlp_table.argtypes = [ctypes.c_void_p, _dp]
+    L.fpt_mlp_grad.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_double, ctypes.c_uint64, ctypes.c_uint64,
+                               ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, _dp, _u64p]
+    L.fpt_mlp_adam.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                               ctypes.c_double, ctypes.c_void_p]
     for name in ("fpt_create", "fpt_run", "fpt_histogram", "fpt_reset", "fpt_last_kernel_ms",
                  "fpt_noise_table_bessel", "fpt_batch_create", "fpt_batch_run", "fpt_batch_autotune",
-                 "fpt_batch_config", "fpt_batch_last_ms"):
+                 "fpt_batch_config", "fpt_batch_last_ms", "fpt_mlp_set", "fpt_mlp_get", "fpt_mlp_table",
+                 "fpt_mlp_grad", "fpt_mlp_adam"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -177,7 +187,8 @@ class Context:
     """Owns one fpt_ctx; mirrors fpt_run / fpt_histogram / fpt_reset / fpt_destroy."""
 
     def __init__(self, pot: fpt_potential, S, tan_theta, phi_lo: float, phi_hi: float, *, bias_kind=FPT_BIAS_NONE,
-                 A=0.0, mlp_params=None, norm=(0.0, 1.0, 0.0, 1.0), mlp_every=1, precision=FPT_FP64,
+                 A=0.0, mlp_params=None, norm=(0.0, 1.0, 0.0, 1.0), mlp_every=0, grid_n=(2, 2),
+                 grid_range=(-1.0, 1.0, -1.0, 1.0), precision=FPT_FP64,
                  bins_kind=FPT_BINS_LINEAR, n_bins=64, lo=-1.0, hi=1.0, N_ref=0.0, max_steps=FPT_MAX_STEPS,
                  instance=0, block_size=0, blocks_per_cu=0, chunk=0):
         L = load()
@@ -187,7 +198,9 @@ class Context:
                                 self._t.ctypes.data_as(_dp))
         self._mlp = (np.ascontiguousarray(mlp_params, dtype=np.float32) if mlp_params is not None else None)
         bias = fpt_bias(bias_kind, A, self._mlp.ctypes.data_as(_fp) if self._mlp is not None else None,
-                        (ctypes.c_double * 4)(*norm), mlp_every)
+                        (ctypes.c_double * 4)(*norm), mlp_every, (ctypes.c_int32 * 2)(*grid_n),
+                        (ctypes.c_double * 4)(*grid_range))
+        self.grid_n = (int(grid_n[0]), int(grid_n[1]))
         self.n_bins = int(n_bins)
         opts = fpt_options(precision, bins_kind, n_bins, lo, hi, N_ref, max_steps, instance, block_size,
                            blocks_per_cu, chunk)
@@ -229,6 +242,44 @@ class Context:
         ms = ctypes.c_double()
         _check(self._lib.fpt_last_kernel_ms(self._h, ctypes.byref(ms)), "fpt_last_kernel_ms")
         return ms.value
+
+    # ---- learned bias -------------------------------------------------------
+    def mlp_set(self, params, stream=None):
+        """params: a device tensor, or host values (copied through a float32 array)."""
+        if torch is not None and isinstance(params, torch.Tensor) and params.is_cuda:
+            src = params.contiguous()
+            _check(self._lib.fpt_mlp_set(self._h, src.data_ptr(), _stream_handle(stream)), "fpt_mlp_set")
+            return
+        a = np.ascontiguousarray(params, dtype=np.float32)
+        if a.size != FPT_MLP_NPARAM:
+            raise ValueError(f"need {FPT_MLP_NPARAM} parameters")
+        _check(self._lib.fpt_mlp_set(self._h, a.ctypes.data, _stream_handle(stream)), "fpt_mlp_set")
+        torch.cuda.synchronize()     # the host array must outlive the copy
+
+    def mlp_get(self, stream=None) -> np.ndarray:
+        a = np.empty(FPT_MLP_NPARAM, dtype=np.float32)
+        _check(self._lib.fpt_mlp_get(self._h, a.ctypes.data, _stream_handle(stream)), "fpt_mlp_get")
+        return a
+
+    def mlp_table(self) -> np.ndarray:
+        a = np.empty(self.grid_n[0] * self.grid_n[1], dtype=np.float64)
+        _check(self._lib.fpt_mlp_table(self._h, a.ctypes.data_as(_dp)), "fpt_mlp_table")
+        return a.reshape(self.grid_n)
+
+    def mlp_grad(self, n_traj: int, dN: float, seed: int, tail_lo: float, d_grad, traj_offset: int = 0, stream=None,
+                 d_G=None, want_J: bool = True):
+        """Fill d_grad (device, 4482 float32) with dJ/dtheta; returns (J, n_tail) when want_J."""
+        J = ctypes.c_double()
+        nt = ctypes.c_uint64()
+        _check(self._lib.fpt_mlp_grad(self._h, n_traj, dN, seed, traj_offset, tail_lo, _stream_handle(stream),
+                                      _ptr(d_grad), _ptr(d_G), ctypes.byref(J) if want_J else None,
+                                      ctypes.byref(nt) if want_J else None), "fpt_mlp_grad")
+        return (J.value, int(nt.value)) if want_J else None
+
+    def mlp_adam(self, d_grad, lr: float, beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8,
+                 stream=None):
+        _check(self._lib.fpt_mlp_adam(self._h, _ptr(d_grad), lr, beta1, beta2, eps, _stream_handle(stream)),
+               "fpt_mlp_adam")
 
     def destroy(self):
         if getattr(self, "_h", None):

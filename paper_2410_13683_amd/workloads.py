@@ -22,6 +22,7 @@ from __future__ import annotations
 
 import math
 from dataclasses import dataclass, field
+from typing import Optional
 
 import numpy as np
 
@@ -88,6 +89,12 @@ class Workload:
     hi: float = 1.0
     N_ref: float = 0.0
     max_steps: int = 1 << 24         # far above every workload here (<= 1.2e5 steps per trajectory)
+    # learned control (bias_kind == BIAS_MLP): network parameters (4482 float32), input
+    # normalisation (c0, s0, c1, s1) and the tabulation grid over the normalised inputs
+    mlp_params: Optional[np.ndarray] = None
+    mlp_norm: tuple = (0.0, 1.0, 0.0, 1.0)
+    grid_n: tuple = (2, 2)
+    grid_range: tuple = (-1.0, 1.0, -1.0, 1.0)
     extra: dict = field(default_factory=dict)
 
     def with_(self, **kw) -> "Workload":
@@ -160,3 +167,55 @@ def batched_instances(n_inst: int = 64, seed: int = 4, n_min: float = 1e5, n_max
             max_steps=int(max_steps), extra={"instance": i, "eps_minus": float(eps_m[i])})
         out.append(w)
     return out
+
+
+# ---------------------------------------------------------------------------
+# learned control
+# ---------------------------------------------------------------------------
+MLP_NPARAM = 4482
+MLP_HIDDEN = 64
+
+
+def mlp_constant_init(A: float, seed: int = 0, gain: float = 1.0) -> np.ndarray:
+    """Initial parameters whose output 0 is the constant A: W1, W2 drawn N(0, gain^2/fan_in)
+    (seeded), biases 0, W3 = 0, b3 = (A, 0).  Training starts from the constant-bias control."""
+    rng = np.random.default_rng(seed)
+    p = np.zeros(MLP_NPARAM, dtype=np.float32)
+    p[:128] = rng.standard_normal(128) * gain / math.sqrt(2.0)
+    p[192:4288] = rng.standard_normal(4096) * gain / math.sqrt(MLP_HIDDEN)
+    p[4480] = A
+    return p
+
+
+def mlp_random(seed: int, scale: float = 0.2, out_bias: float = 1.0) -> np.ndarray:
+    """Random parameters (every entry N(0, scale^2)) with output bias b3[0] = out_bias: a
+    smoothly varying amplitude around out_bias, for parity tests."""
+    p = (np.random.default_rng(seed).standard_normal(MLP_NPARAM) * scale).astype(np.float32)
+    p[4480] = out_bias
+    return p
+
+
+def srusr_learned(n_traj: int = 10_000_000, seed: int = 5, A_init: float = 1.0,
+                  grid_n: tuple = (32, 32)) -> Workload:
+    """The SR->USR problem with FP32 state and a learned control: inputs
+    x0 = (phi - phi_mid)/(DELTA_E/2) (phi_mid halfway between phi_end and phi_in) and
+    x1 = (ln|pi| - c1)/s1 mapping ln|pi| from ln sqrt(2 eps_+) (start) to ln sqrt(2 eps_-)
+    (the flat-branch attractor) onto [1, -1]; tabulated on grid_n nodes over
+    x0 in [-1.05, 1.05], x1 in [-1.2, 1.2]; the network starts as the constant A_init."""
+    ln_hi, ln_lo = 0.5 * math.log(2.0 * EPS_PLUS), 0.5 * math.log(2.0 * EPS_MINUS)
+    return srusr_is_fp32(A_bias=0.0, n_traj=n_traj, seed=seed).with_(
+        name="srusr_learned_fp32", bias_kind=BIAS_MLP, A_bias=0.0,
+        mlp_params=mlp_constant_init(A_init, seed=seed),
+        mlp_norm=(-0.5 * DELTA_E, 0.5 * DELTA_E, 0.5 * (ln_hi + ln_lo), 0.5 * (ln_hi - ln_lo)),
+        grid_n=tuple(grid_n), grid_range=(-1.05, 1.05, -1.2, 1.2))
+
+
+def exponential_ig_learned(n_traj: int = 4000, seed: int = 29, dN: float = 2e-3, params=None,
+                           grid_n: tuple = (24, 12)) -> Workload:
+    """The inverse-Gaussian companion with a learned control: x0 = (phi - 0.5)/0.5 (phi from
+    phi_in = 1 to phi_end = 0 maps to [1, -1]), x1 = ln|pi| - ln 0.5 (pi stays at -alpha = -0.5
+    without bias; the bias moves only phi, so x1 = 0), grid over x0 in [-1.05, 1.05] and
+    x1 in [-1.5, 1.5]."""
+    return exponential_ig(n_traj=n_traj, seed=seed, dN=dN).with_(
+        name="exponential_ig_learned", bias_kind=BIAS_MLP, mlp_params=params,
+        mlp_norm=(0.5, 0.5, math.log(0.5), 1.0), grid_n=tuple(grid_n), grid_range=(-1.05, 1.05, -1.5, 1.5))

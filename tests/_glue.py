@@ -23,11 +23,41 @@ def oracle_table(w: Workload):
 
 
 def oracle_problem(w: Workload, mlp_params=None, mlp_norm=None) -> orc.Problem:
+    """The oracle problem of a workload.  A learned control given by the workload
+    (w.mlp_params) is the tabulated network on the workload's grid; parameters passed
+    here instead select the network evaluated at every step."""
     S, t, lo, hi = oracle_table(w)
-    return orc.Problem(kind=w.kind, V0=w.V0, phi_T=w.phi_T, A_plus=w.A_plus, A_minus=w.A_minus,
-                       phi_in=w.phi_in, pi_in=w.pi_in, phi_end=w.phi_end, S=S, tan_theta=t,
-                       phi_lo=lo, phi_hi=hi, bias_kind=w.bias_kind, A_bias=w.A_bias,
-                       mlp_params=mlp_params, mlp_norm=mlp_norm)
+    p = orc.Problem(kind=w.kind, V0=w.V0, phi_T=w.phi_T, A_plus=w.A_plus, A_minus=w.A_minus,
+                    phi_in=w.phi_in, pi_in=w.pi_in, phi_end=w.phi_end, S=S, tan_theta=t,
+                    phi_lo=lo, phi_hi=hi, bias_kind=w.bias_kind, A_bias=w.A_bias,
+                    mlp_params=mlp_params, mlp_norm=mlp_norm)
+    if mlp_params is None and w.mlp_params is not None:
+        p.mlp_params = np.ascontiguousarray(w.mlp_params, dtype=np.float32)
+        p.mlp_norm = np.asarray(w.mlp_norm, dtype=np.float64)
+        p.mlp_every = 0
+        p.grid_n = tuple(w.grid_n)
+        p.grid_range = tuple(w.grid_range)
+    return p
+
+
+def assert_fp64_parity(gpu, ora, max_step_mismatch=0.002):
+    """Per-trajectory FP64 parity: same flags, N within 1e-9 relative, the same crossing step
+    except at floating-point near-ties with phi_end (at most max_step_mismatch of them, and
+    then off by one step), ln w within 1e-9 relative to 1 + |ln w| where the steps agree."""
+    Ng, lg, sg = gpu
+    No, lo_, so = ora
+    assert Ng.shape == No.shape
+    flags = orc.FLAG_CENSORED | orc.FLAG_ENDED_EARLY
+    assert np.array_equal(sg & flags, so & flags)
+    fin = (so & flags) == 0
+    same = sg == so
+    assert (1.0 - same.mean()) <= max_step_mismatch, f"{(~same).sum()} crossing steps differ"
+    diff_steps = np.abs((sg & orc.STEP_MASK).astype(np.int64) - (so & orc.STEP_MASK).astype(np.int64))
+    assert diff_steps.max(initial=0) <= 1
+    rel = np.abs(Ng[fin] - No[fin]) / np.abs(No[fin])
+    assert rel.max(initial=0.0) <= 1e-9, rel.max()
+    ok = same & fin
+    assert np.all(np.abs(lg[ok] - lo_[ok]) <= 1e-9 * (1.0 + np.abs(lo_[ok])))
 
 
 def oracle_run(w: Workload, n_traj=None, traj_offset=0, n_threads=0, **kw):

@@ -23,6 +23,9 @@ def gpu_context(w: Workload, **kw) -> fpt.Context:
     args = dict(bias_kind=w.bias_kind, A=w.A_bias, precision=w.precision, bins_kind=w.bins_kind,
                 n_bins=w.n_bins, lo=w.lo, hi=w.hi, N_ref=w.N_ref, max_steps=w.max_steps,
                 instance=w.extra.get("instance", 0))
+    if w.bias_kind == 2:
+        args.update(mlp_params=w.mlp_params, norm=w.mlp_norm, mlp_every=0, grid_n=w.grid_n,
+                    grid_range=w.grid_range)
     args.update(kw)
     return fpt.Context(pot, S, t, lo, hi, **args)
 

@@ -15,7 +15,7 @@ int main(void)
     S(fpt_noise_table); F(fpt_noise_table, n); F(fpt_noise_table, phi_lo); F(fpt_noise_table, phi_hi);
     F(fpt_noise_table, S); F(fpt_noise_table, tan_theta);
     S(fpt_bias); F(fpt_bias, kind); F(fpt_bias, A); F(fpt_bias, mlp_params); F(fpt_bias, norm);
-    F(fpt_bias, mlp_every);
+    F(fpt_bias, mlp_every); F(fpt_bias, grid_n); F(fpt_bias, grid_range);
     S(fpt_options); F(fpt_options, precision); F(fpt_options, bins_kind); F(fpt_options, n_bins);
     F(fpt_options, lo); F(fpt_options, hi); F(fpt_options, N_ref); F(fpt_options, max_steps);
     F(fpt_options, instance); F(fpt_options, block_size); F(fpt_options, blocks_per_cu); F(fpt_options, chunk);

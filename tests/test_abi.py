@@ -60,15 +60,27 @@ def _pot(**kw):
     dict(opts=dict(block_size=100)),
     dict(opts=dict(chunk=6)),
     dict(bias=dict(kind=1, A=float("inf"))),
+    dict(bias=dict(kind=2, params=False)),                       # learned bias without parameters
+    dict(bias=dict(kind=2, grid_n=(1, 8))),                      # grid needs two nodes per axis
+    dict(bias=dict(kind=2, grid_n=(64, 64))),                    # more nodes than FPT_MLP_MAX_GRID
+    dict(bias=dict(kind=2, norm=(0.0, 0.0, 0.0, 1.0))),          # zero input scale
+    dict(bias=dict(kind=2, grid_range=(1.0, -1.0, -1.0, 1.0))),  # reversed range
+    dict(bias=dict(kind=2, nan_param=True)),                     # non-finite parameter
 ])
 def test_invalid_arguments_are_rejected(lib, bad):
     pot = _pot(**bad.get("pot", {}))
     S = np.ascontiguousarray(bad.get("S", [1e-6]), dtype=np.float64)
     t = np.zeros(max(len(S), 1))
     tab = fpt.fpt_noise_table(len(S), 0.0, 0.0, S.ctypes.data_as(fpt._dp), t.ctypes.data_as(fpt._dp))
-    bd = dict(kind=0, A=0.0)
+    bd = dict(kind=0, A=0.0, params=True, grid_n=(8, 8), norm=(0.0, 1.0, 0.0, 1.0), grid_range=(-1.0, 1.0, -1.0, 1.0),
+              nan_param=False, every=0)
     bd.update(bad.get("bias", {}))
-    bias = fpt.fpt_bias(bd["kind"], bd["A"], None, (ctypes.c_double * 4)(0, 1, 0, 1), 1)
+    params = np.zeros(fpt.FPT_MLP_NPARAM, dtype=np.float32)
+    if bd["nan_param"]:
+        params[77] = np.nan
+    bias = fpt.fpt_bias(bd["kind"], bd["A"], params.ctypes.data_as(fpt._fp) if bd["params"] else None,
+                        (ctypes.c_double * 4)(*bd["norm"]), bd["every"], (ctypes.c_int32 * 2)(*bd["grid_n"]),
+                        (ctypes.c_double * 4)(*bd["grid_range"]))
     od = dict(precision=0, bins_kind=0, n_bins=8, lo=-1.0, hi=1.0, N_ref=0.0, max_steps=1000, instance=0,
               block_size=0, blocks_per_cu=0, chunk=0)
     od.update(bad.get("opts", {}))
@@ -79,6 +91,30 @@ def test_invalid_arguments_are_rejected(lib, bad):
     assert rc == fpt.FPT_EINVAL, (rc, lib.fpt_last_error())
     assert not h.value
     assert lib.fpt_last_error()
+
+
+def test_in_loop_network_is_reported_unsupported(lib):
+    pot = _pot()
+    S = np.array([1e-6])
+    t = np.zeros(1)
+    tab = fpt.fpt_noise_table(1, 0.0, 0.0, S.ctypes.data_as(fpt._dp), t.ctypes.data_as(fpt._dp))
+    params = np.zeros(fpt.FPT_MLP_NPARAM, dtype=np.float32)
+    bias = fpt.fpt_bias(2, 0.0, params.ctypes.data_as(fpt._fp), (ctypes.c_double * 4)(0, 1, 0, 1), 4,
+                        (ctypes.c_int32 * 2)(8, 8), (ctypes.c_double * 4)(-1, 1, -1, 1))
+    opts = fpt.fpt_options(0, 0, 8, -1.0, 1.0, 0.0, 1000, 0, 0, 0, 0)
+    h = ctypes.c_void_p()
+    rc = lib.fpt_create(ctypes.byref(pot), ctypes.byref(tab), ctypes.byref(bias), ctypes.byref(opts),
+                        ctypes.byref(h))
+    assert rc == fpt.FPT_EUNSUPPORTED and not h.value
+
+
+def test_mlp_entry_points_reject_null_contexts(lib):
+    g = np.zeros(4, dtype=np.float32)
+    assert lib.fpt_mlp_set(None, g.ctypes.data, None) == fpt.FPT_EINVAL
+    assert lib.fpt_mlp_get(None, g.ctypes.data, None) == fpt.FPT_EINVAL
+    assert lib.fpt_mlp_table(None, None) == fpt.FPT_EINVAL
+    assert lib.fpt_mlp_grad(None, 1, 1e-3, 1, 0, 0.0, None, g.ctypes.data, None, None, None) == fpt.FPT_EINVAL
+    assert lib.fpt_mlp_adam(None, g.ctypes.data, 1e-3, 0.9, 0.999, 1e-8, None) == fpt.FPT_EINVAL
 
 
 def test_table_generator_rejects_bad_sizes(lib):

@@ -21,7 +21,7 @@ torch = pytest.importorskip("torch")
 from oracle import oracle as orc  # noqa: E402
 from paper_2410_13683_amd import fpt  # noqa: E402
 from paper_2410_13683_amd import workloads as W  # noqa: E402
-from tests._glue import oracle_problem, oracle_run, oracle_table  # noqa: E402
+from tests._glue import assert_fp64_parity, oracle_problem, oracle_run, oracle_table  # noqa: E402
 from tests._gpu import gpu_context, gpu_run, gpu_table  # noqa: E402
 
 
@@ -35,23 +35,6 @@ def _gpu():
 def say(msg):
     print(msg, flush=True)
     sys.stdout.flush()
-
-
-def assert_fp64_parity(gpu, ora, max_step_mismatch=0.002):
-    Ng, lg, sg = gpu
-    No, lo_, so = ora
-    assert Ng.shape == No.shape
-    flags = orc.FLAG_CENSORED | orc.FLAG_ENDED_EARLY
-    assert np.array_equal(sg & flags, so & flags)
-    fin = (so & flags) == 0
-    same = sg == so
-    assert (1.0 - same.mean()) <= max_step_mismatch, f"{(~same).sum()} crossing steps differ"
-    diff_steps = np.abs((sg & orc.STEP_MASK).astype(np.int64) - (so & orc.STEP_MASK).astype(np.int64))
-    assert diff_steps.max(initial=0) <= 1
-    rel = np.abs(Ng[fin] - No[fin]) / np.abs(No[fin])
-    assert rel.max(initial=0.0) <= 1e-9, rel.max()
-    ok = same & fin
-    assert np.all(np.abs(lg[ok] - lo_[ok]) <= 1e-9 * (1.0 + np.abs(lo_[ok])))
 
 
 def test_noise_table_matches_oracle():

@@ -208,3 +208,40 @@ def test_grid_replay_gradient_matches_finite_differences(orc):
         _, Jm, _ = orc.grid_replay_grad(prob, theta_old, tm, w.dN, w.seed, w.n_traj, w.N_ref, tail_lo)
         fd = (Jp - Jm) / ((float(tp[k]) - float(theta[k])) + (float(theta[k]) - float(tm[k])))
         assert abs(fd - grad[k]) <= 2e-3 * abs(grad[k]) + 1e-6 * abs(J), (k, fd, grad[k])
+
+
+# --------------------------------------------------------------------------
+# Adam
+# --------------------------------------------------------------------------
+def test_adam_first_step_is_the_signed_learning_rate(orc):
+    """From zero moments the bias-corrected first step is lr g / (|g| + eps) against the gradient."""
+    rng = np.random.default_rng(21)
+    g = (rng.standard_normal(50) * 10.0 ** rng.uniform(-4, 2, 50)).astype(np.float32)
+    th0 = rng.standard_normal(50).astype(np.float32)
+    th, m, v = th0.copy(), np.zeros(50, np.float32), np.zeros(50, np.float32)
+    lr, eps = 1e-2, 1e-8
+    orc.adam_step(th, m, v, g, 1, lr, 0.9, 0.999, eps)
+    gd = g.astype(np.float64)
+    expect = th0.astype(np.float64) - lr * gd / (np.abs(gd) + eps)
+    np.testing.assert_allclose(th, expect.astype(np.float32), rtol=2e-7, atol=1e-9)
+    np.testing.assert_allclose(m, (0.1 * gd).astype(np.float32), rtol=1e-6)
+    np.testing.assert_allclose(v, (0.001 * gd * gd).astype(np.float32), rtol=1e-6)
+
+
+def test_adam_constant_gradient_moves_linearly(orc):
+    """A constant gradient keeps the bias-corrected moments at g and g^2, so after t steps the
+    parameter has moved by t lr g/(|g| + eps); a zero gradient afterwards only decays m and v."""
+    g = np.array([3.0, -0.5, 1e-3, -20.0], dtype=np.float32)
+    th = np.zeros(4, np.float32)
+    m, v = np.zeros(4, np.float32), np.zeros(4, np.float32)
+    lr, eps, T = 1e-3, 1e-8, 40
+    for t in range(1, T + 1):
+        orc.adam_step(th, m, v, g, t, lr, 0.8, 0.99, eps)
+    gd = g.astype(np.float64)
+    np.testing.assert_allclose(th, -T * lr * gd / (np.abs(gd) + eps), rtol=2e-5)
+    m0, v0 = m.copy(), v.copy()
+    th_before = th.copy()
+    orc.adam_step(th, m, v, np.zeros(4, np.float32), T + 1, lr, 0.8, 0.99, eps)
+    np.testing.assert_allclose(m, 0.8 * m0.astype(np.float64), rtol=1e-6)
+    np.testing.assert_allclose(v, 0.99 * v0.astype(np.float64), rtol=1e-6)
+    assert np.all(np.sign(th - th_before) == -np.sign(gd))      # momentum keeps moving downhill
