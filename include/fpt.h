@@ -251,14 +251,21 @@ int fpt_mlp_table(fpt_ctx *ctx, double *a_out);
  * lognormal weight model of Sec. 4.1).  Tail trajectories are integrated again
  * (replayed from their counter-based random numbers) to accumulate the
  * grid-node weights G_c = (1/n) sum_T w^2 sum_k (-xi_k sqrt(dN)) beta_c(x_k),
- * which are propagated through the network at the nodes.  Outputs: d_grad
- * (device, FPT_MLP_NPARAM floats, required), d_G (device, grid_n[0] grid_n[1]
+ * which are propagated through the network at the nodes.  objective
+ * FPT_MLP_OBJ_J gives dJ/dtheta; FPT_MLP_OBJ_LOG_J gives d ln J/dtheta =
+ * (dJ/dtheta)/J (J divided out on the device), whose scale does not depend on
+ * how rare T is (J ~ P_T^2), which suits optimisers with absolute
+ * tolerances such as Adam's eps.  Outputs: d_grad
+ * (device, FPT_MLP_NPARAM floats, required; all zero when no trajectory is in
+ * T), d_G (device, grid_n[0] grid_n[1]
  * doubles, or NULL), J_out and n_tail_out (host, or NULL; if either is given
  * the call waits for the device).  Asynchronous on hip_stream otherwise;
  * device scratch of about 36 bytes per trajectory (at most 2^22 at a time) is
  * allocated on first use and kept.  Errors: FPT_EINVAL, FPT_ENOMEM, FPT_EHIP. */
+enum { FPT_MLP_OBJ_J = 0, FPT_MLP_OBJ_LOG_J = 1 };
 int fpt_mlp_grad(fpt_ctx *ctx, uint64_t n_traj, double dN, uint64_t seed, uint64_t traj_offset, double tail_lo,
-                 void *hip_stream, float *d_grad, double *d_G, double *J_out, uint64_t *n_tail_out);
+                 int32_t objective, void *hip_stream, float *d_grad, double *d_G, double *J_out,
+                 uint64_t *n_tail_out);
 
 /* One Adam step (Kingma and Ba, 2015) on the context's parameters with the
  * gradient d_grad (device, FPT_MLP_NPARAM floats): m = b1 m + (1 - b1) g,

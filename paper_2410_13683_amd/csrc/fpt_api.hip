@@ -541,14 +541,16 @@ extern "C" int fpt_mlp_table(fpt_ctx *c, double *a_out)
 }
 
 extern "C" int fpt_mlp_grad(fpt_ctx *c, uint64_t n_traj, double dN, uint64_t seed, uint64_t traj_offset,
-                            double tail_lo, void *hip_stream, float *d_grad, double *d_G, double *J_out,
-                            uint64_t *n_tail_out)
+                            double tail_lo, int32_t objective, void *hip_stream, float *d_grad, double *d_G,
+                            double *J_out, uint64_t *n_tail_out)
 {
     int rc = mlp_check(c);
     if (rc) return rc;
     if (!d_grad) return fail(FPT_EINVAL, "d_grad is NULL");
     if (!(dN > 0.0) || !is_finite(dN)) return fail(FPT_EINVAL, "dN must be finite and > 0");
     if (!is_finite(tail_lo)) return fail(FPT_EINVAL, "tail_lo must be finite");
+    if (objective != FPT_MLP_OBJ_J && objective != FPT_MLP_OBJ_LOG_J)
+        return fail(FPT_EINVAL, "unknown objective %d", objective);
     if (n_traj == 0) return fail(FPT_EINVAL, "n_traj must be > 0");
     if (traj_offset + n_traj < traj_offset) return fail(FPT_EINVAL, "trajectory range overflows 64 bits");
     hipStream_t s = static_cast<hipStream_t>(hip_stream);
@@ -626,7 +628,9 @@ extern "C" int fpt_mlp_grad(fpt_ctx *c, uint64_t n_traj, double dN, uint64_t see
                                  &cnt[1], c->d_J, s));
         HIP_TRY(replay_launch(rp, c->precision, grid_rp, block, s));
     }
-    HIP_TRY(mlp_backprop(c->d_params, g, c->d_G, (double)n_traj, c->d_work, d_grad, s));
+    // d_J holds sum_T w^2 = n J: dividing G by it gives d ln J / d theta
+    HIP_TRY(mlp_backprop(c->d_params, g, c->d_G, (double)n_traj, objective == FPT_MLP_OBJ_LOG_J ? c->d_J : nullptr,
+                         c->d_work, d_grad, s));
     if (d_G) {
         // G / n as documented (scaled copy on the device)
         HIP_TRY(mlp_scale_copy(c->d_G, 1.0 / (double)n_traj, d_G, n_nodes, s));

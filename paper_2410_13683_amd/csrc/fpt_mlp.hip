@@ -120,15 +120,21 @@ __global__ void tail_compact_kernel(const double *d_N, const double *d_lnw, cons
 
 // Backward pass at every node: work = [H1 | H2 | D2 | G1], each n_nodes x 64,
 // with D2 = G_c W3 (1 - h2^2) and G1 = (W2^T D2)(1 - h1^2).
+__device__ __forceinline__ double inv_den(double n_scale, const double *d_den)
+{
+    const double den = d_den ? *d_den : n_scale;
+    return den != 0.0 ? 1.0 / den : 0.0;
+}
+
 __global__ void __launch_bounds__(64) backprop_node_kernel(const float *p, GridSpec g, const double *G,
-                                                           double n_scale, double *work)
+                                                           double n_scale, const double *d_den, double *work)
 {
     __shared__ double l_h1[H], l_h2[H], l_d2[H];
     const int node = blockIdx.x, t = threadIdx.x;
     const int n_nodes = g.n0 * g.n1;
     const int i = node / g.n1, j = node % g.n1;
     (void)net_forward(p, grid_x(g.lo0, g.hi0, g.n0, i), grid_x(g.lo1, g.hi1, g.n1, j), l_h1, l_h2);
-    const double Gc = G[node] / n_scale;
+    const double Gc = G[node] * inv_den(n_scale, d_den);
     const double h1 = l_h1[t], h2 = l_h2[t];
     const double d2 = Gc * (double)p[kOffW3 + t] * (1.0 - h2 * h2);
     l_d2[t] = d2;
@@ -144,10 +150,12 @@ __global__ void __launch_bounds__(64) backprop_node_kernel(const float *p, GridS
 }
 
 // One thread per parameter: the sum over nodes (fixed order) of its factors.
-__global__ void backprop_param_kernel(GridSpec g, const double *G, double n_scale, const double *work, float *grad)
+__global__ void backprop_param_kernel(GridSpec g, const double *G, double n_scale, const double *d_den,
+                                      const double *work, float *grad)
 {
     const int q = blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= kMlpParams) return;
+    const double inv = inv_den(n_scale, d_den);
     const int n_nodes = g.n0 * g.n1;
     const double *H1 = work, *H2 = work + (size_t)n_nodes * H, *D2 = work + 2 * (size_t)n_nodes * H,
                  *G1 = work + 3 * (size_t)n_nodes * H;
@@ -169,9 +177,9 @@ __global__ void backprop_param_kernel(GridSpec g, const double *G, double n_scal
         for (int c = 0; c < n_nodes; ++c) s += D2[(size_t)c * H + u];
     } else if (q < kOffW3 + H) {              // W3[0, v]
         const int v = q - kOffW3;
-        for (int c = 0; c < n_nodes; ++c) s += G[c] / n_scale * H2[(size_t)c * H + v];
+        for (int c = 0; c < n_nodes; ++c) s += G[c] * inv * H2[(size_t)c * H + v];
     } else if (q == kOffB3) {                 // b3[0]
-        for (int c = 0; c < n_nodes; ++c) s += G[c] / n_scale;
+        for (int c = 0; c < n_nodes; ++c) s += G[c] * inv;
     }                                         // W3[1, .] and b3[1] feed the unused output
     grad[q] = (float)s;
 }
@@ -220,14 +228,15 @@ hipError_t mlp_tail_compact(const double *d_N, const double *d_lnw, const uint32
     return hipGetLastError();
 }
 
-hipError_t mlp_backprop(const float *params, const GridSpec &g, const double *G, double n_scale, double *work,
-                        float *grad, hipStream_t stream)
+hipError_t mlp_backprop(const float *params, const GridSpec &g, const double *G, double n_scale,
+                        const double *d_den, double *work, float *grad, hipStream_t stream)
 {
-    hipLaunchKernelGGL(backprop_node_kernel, dim3(g.n0 * g.n1), dim3(H), 0, stream, params, g, G, n_scale, work);
+    hipLaunchKernelGGL(backprop_node_kernel, dim3(g.n0 * g.n1), dim3(H), 0, stream, params, g, G, n_scale, d_den,
+                       work);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(backprop_param_kernel, dim3((kMlpParams + 255) / 256), dim3(256), 0, stream, g, G, n_scale,
-                       work, grad);
+                       d_den, work, grad);
     return hipGetLastError();
 }
 

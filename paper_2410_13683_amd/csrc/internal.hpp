@@ -136,10 +136,11 @@ hipError_t mlp_tail_compact(const double *d_N, const double *d_lnw, const uint32
                             uint64_t traj_offset, double N_ref, double tail_lo, TailEntry *tail,
                             unsigned long long *n_tail, unsigned long long *n_tail_total, double *J_sum,
                             hipStream_t stream);
-// grad[4482] (FP32) = sum_c G_c / n_scale d a(x_c)/d theta over the grid nodes;
-// work: 4 n0 n1 64 doubles of scratch.
-hipError_t mlp_backprop(const float *params, const GridSpec &g, const double *G, double n_scale, double *work,
-                        float *grad, hipStream_t stream);
+// grad[4482] (FP32) = sum_c G_c / den d a(x_c)/d theta over the grid nodes, with
+// den = *d_den when d_den is given (a device value; den = 0 gives a zero gradient),
+// else n_scale; work: 4 n0 n1 64 doubles of scratch.
+hipError_t mlp_backprop(const float *params, const GridSpec &g, const double *G, double n_scale,
+                        const double *d_den, double *work, float *grad, hipStream_t stream);
 hipError_t mlp_scale_copy(const double *src, double scale, double *dst, size_t n, hipStream_t stream);
 hipError_t mlp_adam(float *params, float *m, float *v, const float *grad, int n, double lr, double beta1,
                     double beta2, double eps, double bc1, double bc2, hipStream_t stream);

@@ -39,6 +39,7 @@ FPT_MAX_TABLE = 4096
 FPT_MAX_BINS = 1024
 FPT_MLP_NPARAM = 4482
 FPT_MLP_MAX_GRID = 1024
+FPT_MLP_OBJ_J, FPT_MLP_OBJ_LOG_J = 0, 1
 
 _dp = ctypes.POINTER(ctypes.c_double)
 _fp = ctypes.POINTER(ctypes.c_float)
@@ -135,7 +136,8 @@ def load():
     L.fpt_mlp_get.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
     L.fpt_mlp_table.argtypes = [ctypes.c_void_p, _dp]
     L.fpt_mlp_grad.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_double, ctypes.c_uint64, ctypes.c_uint64,
-                               ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, _dp, _u64p]
+                               ctypes.c_double, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, _dp,
+                               _u64p]
     L.fpt_mlp_adam.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                ctypes.c_double, ctypes.c_void_p]
     for name in ("fpt_create", "fpt_run", "fpt_histogram", "fpt_reset", "fpt_last_kernel_ms",
@@ -267,11 +269,13 @@ class Context:
         return a.reshape(self.grid_n)
 
     def mlp_grad(self, n_traj: int, dN: float, seed: int, tail_lo: float, d_grad, traj_offset: int = 0, stream=None,
-                 d_G=None, want_J: bool = True):
-        """Fill d_grad (device, 4482 float32) with dJ/dtheta; returns (J, n_tail) when want_J."""
+                 d_G=None, want_J: bool = True, objective: int = FPT_MLP_OBJ_J):
+        """Fill d_grad (device, 4482 float32) with dJ/dtheta (or d ln J/dtheta); returns (J, n_tail)
+        when want_J."""
         J = ctypes.c_double()
         nt = ctypes.c_uint64()
-        _check(self._lib.fpt_mlp_grad(self._h, n_traj, dN, seed, traj_offset, tail_lo, _stream_handle(stream),
+        _check(self._lib.fpt_mlp_grad(self._h, n_traj, dN, seed, traj_offset, tail_lo, objective,
+                                      _stream_handle(stream),
                                       _ptr(d_grad), _ptr(d_G), ctypes.byref(J) if want_J else None,
                                       ctypes.byref(nt) if want_J else None), "fpt_mlp_grad")
         return (J.value, int(nt.value)) if want_J else None

@@ -113,7 +113,7 @@ def test_mlp_entry_points_reject_null_contexts(lib):
     assert lib.fpt_mlp_set(None, g.ctypes.data, None) == fpt.FPT_EINVAL
     assert lib.fpt_mlp_get(None, g.ctypes.data, None) == fpt.FPT_EINVAL
     assert lib.fpt_mlp_table(None, None) == fpt.FPT_EINVAL
-    assert lib.fpt_mlp_grad(None, 1, 1e-3, 1, 0, 0.0, None, g.ctypes.data, None, None, None) == fpt.FPT_EINVAL
+    assert lib.fpt_mlp_grad(None, 1, 1e-3, 1, 0, 0.0, 0, None, g.ctypes.data, None, None, None) == fpt.FPT_EINVAL
     assert lib.fpt_mlp_adam(None, g.ctypes.data, 1e-3, 0.9, 0.999, 1e-8, None) == fpt.FPT_EINVAL
 
 

@@ -156,7 +156,12 @@ def _grad_case(w, q=0.8):
     d_G = torch.zeros(w.grid_n[0] * w.grid_n[1], dtype=torch.float64, device="cuda")
     J, n_tail = ctx.mlp_grad(w.n_traj, w.dN, w.seed, tail_lo, d_grad, d_G=d_G)
     torch.cuda.synchronize()
-    out = dict(J=J, n_tail=n_tail, grad=d_grad.cpu().numpy().astype(np.float64),
+    g_plain = d_grad.cpu().numpy().astype(np.float64)
+    # the log objective divides by J on the device
+    ctx.mlp_grad(w.n_traj, w.dN, w.seed, tail_lo, d_grad, objective=fpt.FPT_MLP_OBJ_LOG_J, want_J=False)
+    g_log = d_grad.cpu().numpy().astype(np.float64)
+    np.testing.assert_allclose(g_log, g_plain / J, rtol=1e-5, atol=1e-6 * np.abs(g_plain).max() / J)
+    out = dict(J=J, n_tail=n_tail, grad=g_plain,
                G=d_G.cpu().numpy().reshape(w.grid_n), J_o=J_o, n_tail_o=n_tail_o, grad_o=grad_o, G_o=G_o,
                gap=gap)
     # the context's histogram is not touched by gradient runs
