@@ -1,6 +1,6 @@
 """Benchmark of the first-passage hot path on one MI355X.
 
-    python bench.py [--steps K] [--warmup W] [--workload srusr_is_fp32|srusr_fp64]
+    python bench.py [--steps K] [--warmup W] [--workload srusr_is_fp32|srusr_fp64|srusr_learned]
                     [--n-traj N] [--no-cpu-baseline]
 
 One bench step is one full pass of the hot path over the workload's batch of
@@ -16,6 +16,13 @@ Prints one JSON line: trajectory-steps/s (device step counter / wall time), the
 ESS-weighted tail-sample rate at the P = 1e-10 tail, the roofline of the EM
 kernel (algorithmic FP operations per step x launches / HIP-event kernel time)
 and the CPU oracle timed on a bounded sample on the host cores.
+
+--workload srusr_learned measures the learned control on the same problem: the
+constant-bias fallback A in {0.5, 1, 2} (one pass each; its best ESS_T rate is
+the comparison), then training of the 2->64->64->2 network from the constant
+A = 1 on 1e7 generated trajectories (replay gradient of ln E[w^2 1_T] with T the
+P = 1e-10 tail found by the A = 2 pass, Adam), then the timed passes with the
+trained, tabulated control.
 """
 from __future__ import annotations
 
@@ -36,6 +43,9 @@ METRIC = "trajectory-steps/s and ESS-weighted tail samples/s at 5% P(δN) tail e
 # piecewise-linear potential), counted operation by operation from the step's
 # definition; FMA = 2 FLOPs, a transcendental = 1.  Derivation in the design doc.
 ALG_FLOPS_PER_STEP = {"fp32": 56.5, "fp64": 58.5}
+# the tabulated learned control adds its grid coordinates (ln|pi| included), the clamped
+# cell and fractions, the bilinear interpolation and the per-step dA = a xi sqrt(dN) + a^2 dN/2
+ALG_FLOPS_LEARNED_EXTRA = {"fp32": 31.0, "fp64": 31.0}
 ALG_INT_OPS_PER_STEP = 16.0          # Philox4x32-10 amortised over 4 steps + uniform conversions
 PEAK_TFLOPS = {"fp32": 157.3, "fp64": 78.6}   # MI355X vector peaks (FP32 figure assumes packed issue)
 PEAK_HBM_GBS = 8000.0
@@ -47,6 +57,8 @@ def _workload(name: str, n_traj: int | None):
         w = W.srusr_is_fp32(A_bias=2.0)
     elif name == "srusr_fp64":
         w = W.srusr_bessel()
+    elif name == "srusr_learned":
+        w = W.srusr_learned(n_traj=100_000_000, A_init=1.0)
     else:
         raise SystemExit(f"unknown workload {name}")
     if n_traj:
@@ -74,6 +86,67 @@ def cpu_baseline(w, target_s: float = 20.0) -> dict:
             "sample": f"trajectories {n0}..{n0 + n1 - 1} of the same workload ({steps1} steps, "
                       f"{dt1:.1f} s, FP64 oracle, OpenMP over trajectories)",
             "seconds": dt1}
+
+
+def tail_at(hist, w, x):
+    """(P(deltaN >= x), ESS over those bins, samples there) for a bin edge x of the workload."""
+    import numpy as np
+    edges = w.lo * (w.hi / w.lo) ** (np.arange(w.n_bins + 1) / w.n_bins) if w.bins_kind else \
+        w.lo + (w.hi - w.lo) * np.arange(w.n_bins + 1) / w.n_bins
+    j = int(np.argmin(np.abs(edges - x)))            # slot j + 1 starts at edges[j]
+    sw = float(hist["sum_w"][j + 1:].sum())
+    sw2 = float(hist["sum_w2"][j + 1:].sum())
+    n = max(int(hist["n_traj"]), 1)
+    return sw / n, (sw * sw / sw2 if sw2 > 0 else 0.0), int(hist["count"][j + 1:].sum())
+
+
+def train_learned(w, stream, train_traj: float = 1e7, iters: int = 40, lr: float = 0.03) -> dict:
+    """Constant-bias fallback passes, then GPU training of the learned control (see the module
+    docstring).  Returns the context holding the trained network and the figures."""
+    import torch
+    from paper_2410_13683_amd import fpt, runner
+    from paper_2410_13683_amd import workloads as W
+    out = {"constant_fallback": []}
+    x_star = None
+    for A in (0.5, 1.0, 2.0):
+        wc = W.srusr_is_fp32(A_bias=A, n_traj=w.n_traj)
+        c = runner.context_for(wc)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        c.run(wc.n_traj, wc.dN, wc.seed, 0, stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        h = c.histogram()
+        c.destroy()
+        if A == 2.0:
+            x_star = runner.tail_ess(h, wc.n_bins, wc.bins_kind, wc.lo, wc.hi, 1e-10)[0]
+        out["constant_fallback"].append({"A": A, "wall_s": wall, "steps": int(h["n_steps_total"]), "hist": h})
+        print(f"[bench] constant A={A}: {wall:.1f} s", file=sys.stderr, flush=True)
+    for r in out["constant_fallback"]:
+        h = r.pop("hist")
+        p, ess, nT = tail_at(h, w, x_star)
+        r.update(P_tail=p, ESS_T=ess, samples_in_T=nT, ess_tail_per_s=ess / r["wall_s"])
+    out["deltaN_star"] = x_star
+    ctx = runner.context_for(w, mlp_params=w.mlp_params, norm=w.mlp_norm, mlp_every=0, grid_n=w.grid_n,
+                             grid_range=w.grid_range)
+    d_grad = torch.zeros(fpt.FPT_MLP_NPARAM, dtype=torch.float32, device="cuda")
+    n_it = int(train_traj) // iters
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    Js = []
+    for it in range(iters):
+        # fresh trajectories every iteration, disjoint from the timed passes (index offset 2^40)
+        J, _ = ctx.mlp_grad(n_it, w.dN, w.seed, x_star, d_grad, traj_offset=(1 << 40) + it * n_it, stream=stream,
+                            objective=fpt.FPT_MLP_OBJ_LOG_J)
+        ctx.mlp_adam(d_grad, lr, stream=stream)
+        Js.append(J)
+    torch.cuda.synchronize()
+    out.update(ctx=ctx, train_trajectories=n_it * iters, train_iterations=iters, lr=lr, A_init=1.0,
+               train_s=time.perf_counter() - t0, J_first=Js[0], J_last=Js[-1],
+               objective="ln E[w^2 1(deltaN >= deltaN_star)]")
+    print(f"[bench] training: {out['train_s']:.1f} s, J {Js[0]:.3e} -> {Js[-1]:.3e}", file=sys.stderr,
+          flush=True)
+    return out
 
 
 def main() -> int:
@@ -110,8 +183,13 @@ def main() -> int:
         del src, dst
     w = _workload(args.workload, args.n_traj)
     prec = "fp32" if w.precision == 1 else "fp64"
-    ctx = runner.context_for(w)
     stream = torch.cuda.current_stream()
+    learned = None
+    if w.bias_kind == 2:
+        learned = train_learned(w, stream)
+        ctx = learned.pop("ctx")
+    else:
+        ctx = runner.context_for(w)
     print(f"[bench] workload {w.name}: {w.n_traj:.3g} trajectories, warmup {args.warmup}, steps {args.steps}",
           file=sys.stderr, flush=True)
     for i in range(args.warmup):
@@ -135,10 +213,15 @@ def main() -> int:
     steps_total = int(hist["n_steps_total"])
     value = steps_total / wall
     x_star, p_star, ess_T, n_T = runner.tail_ess(hist, w.n_bins, w.bins_kind, w.lo, w.hi, 1e-10)
+    if learned:
+        # the same tail as the constant fallback passes
+        x_star = learned["deltaN_star"]
+        p_star, ess_T, n_T = tail_at(hist, w, x_star)
     ess_rate = ess_T / wall
     avg_ms = float(np.mean(kernel_ms))
     steps_per_launch = steps_total / args.steps
-    achieved = ALG_FLOPS_PER_STEP[prec] * steps_per_launch / (avg_ms * 1e-3) / 1e12
+    flops_step = ALG_FLOPS_PER_STEP[prec] + (ALG_FLOPS_LEARNED_EXTRA[prec] if learned else 0.0)
+    achieved = flops_step * steps_per_launch / (avg_ms * 1e-3) / 1e12
     result = {
         "metric": METRIC,
         "value": value,
@@ -157,7 +240,7 @@ def main() -> int:
             "potential": "piecewise-linear slow roll -> ultra-slow roll, V0=1e-10, eps+=0.01, eps-=1e-8",
             "noise": f"Bessel-ansatz table, {w.table_n} phi nodes, sigma={w.sigma}",
             "state": "FP32 pairs + FP64 log-weights" if prec == "fp32" else "FP64",
-            "bias_A": w.A_bias,
+            "bias": "learned 2-64-64-2 tanh network, tabulated" if learned else f"constant A={w.A_bias:g}",
             "trajectories_per_step": w.n_traj,
             "dN": w.dN,
             "bins": f"{w.n_bins} {'log' if w.bins_kind else 'linear'} over deltaN in [{w.lo:.4g}, {w.hi:.4g})",
@@ -175,11 +258,17 @@ def main() -> int:
             "traffic": None,
             "kernel": "em_fp32s_kernel" if prec == "fp32" else "em_fp64_kernel",
             "kernel_ms": avg_ms,
-            "flops_per_step": ALG_FLOPS_PER_STEP[prec],
+            "flops_per_step": flops_step,
             "int_ops_per_step": ALG_INT_OPS_PER_STEP,
         },
     }
-    if not args.no_fp64_side and prec == "fp32":
+    if learned:
+        best = max(learned["constant_fallback"], key=lambda r: r["ess_tail_per_s"])
+        learned["ess_tail_per_s_vs_best_constant"] = ess_rate / best["ess_tail_per_s"] if best["ess_tail_per_s"] else None
+        # per equal trajectory count: the fallback passes ran one batch each, the timed run `steps` batches
+        learned["ESS_T_per_batch_vs_best_constant"] = (ess_T / args.steps) / best["ESS_T"] if best["ESS_T"] else None
+        result["learned"] = learned
+    if not args.no_fp64_side and prec == "fp32" and not learned:
         w64 = _workload("srusr_fp64", None)
         c64 = runner.context_for(w64)
         c64.run(w64.n_traj, w64.dN, w64.seed, 0, stream)
