@@ -1,7 +1,7 @@
 """Benchmark of the first-passage hot path on one MI355X.
 
-    python bench.py [--steps K] [--warmup W] [--workload srusr_is_fp32|srusr_fp64|srusr_learned]
-                    [--n-traj N] [--no-cpu-baseline]
+    python bench.py [--steps K] [--warmup W] [--n-traj N] [--no-cpu-baseline]
+                    [--workload srusr_is_fp32|srusr_fp64|srusr_learned|batched]
 
 One bench step is one full pass of the hot path over the workload's batch of
 trajectories: Philox -> Box-Muller -> noise-table lookup -> drift -> bias ->
@@ -23,6 +23,14 @@ the comparison), then training of the 2->64->64->2 network from the constant
 A = 1 on 1e7 generated trajectories (replay gradient of ln E[w^2 1_T] with T the
 P = 1e-10 tail found by the A = 2 pass, Adam), then the timed passes with the
 trained, tabulated control.
+
+--workload batched measures many problems in one persistent launch: the 64
+SR -> USR instances with eps_- log-uniform in [1e-10, 1e-6], phi_e - phi_end
+uniform in [0.1, 1] and trajectory counts log-uniform in [1e4, 1e6] (a tenth of
+the [1e5, 1e7] range, so one pass takes seconds), FP32 state, a cap of 2^20
+steps per trajectory (most flat-branch runs are censored); the batch is
+autotuned, captured as a hipGraph and replayed for the timed passes, and the
+same work as 64 consecutive single-problem launches is timed beside it.
 """
 from __future__ import annotations
 
@@ -149,13 +157,89 @@ def train_learned(w, stream, train_traj: float = 1e7, iters: int = 40, lr: float
     return out
 
 
+def bench_batched(args) -> dict:
+    """Timed passes of the 64-instance batch (see the module docstring)."""
+    import tempfile
+    import numpy as np
+    import torch
+    from paper_2410_13683_amd import fpt, runner
+    from paper_2410_13683_amd import workloads as W
+    scale = args.n_traj if args.n_traj else 0.1
+    ws = [w.with_(precision=1) for w in W.batched_instances()]
+    counts = np.array([max(1, int(round(w.n_traj * scale))) for w in ws], dtype=np.uint64)
+    ctxs = [runner.context_for(w) for w in ws]
+    stream = torch.cuda.Stream()
+    batch = fpt.Batch(ctxs, use_graph=True)
+    dN, seed = ws[0].dN, ws[0].seed
+    cache = os.path.join(tempfile.gettempdir(), "fpt_batch_tune.txt")
+    t0 = time.perf_counter()
+    batch.autotune(counts, dN, seed, cache_path=cache, stream=stream)
+    tune_s = time.perf_counter() - t0
+    block, chunk = batch.config()
+    print(f"[bench] batched: {int(counts.sum())} trajectories over {len(ws)} instances; tuned block {block} "
+          f"chunk {chunk} in {tune_s:.1f} s", file=sys.stderr, flush=True)
+    with torch.cuda.stream(stream):
+        for i in range(args.warmup):
+            batch.run(counts, dN, seed, 0, stream=stream)
+            stream.synchronize()
+            print(f"[bench] warmup {i + 1} done ({batch.last_ms():.0f} ms)", file=sys.stderr, flush=True)
+        for c in ctxs:
+            c.reset()
+        kernel_ms = []
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(args.steps):
+            batch.run(counts, dN, seed, (k + 1) * (1 << 32), stream=stream)
+            kernel_ms.append(batch.last_ms())
+            print(f"[bench] step {k + 1}/{args.steps}: {kernel_ms[-1]:.0f} ms", file=sys.stderr, flush=True)
+        stream.synchronize()
+        wall = time.perf_counter() - t0
+    hists = [c.histogram() for c in ctxs]
+    steps_total = int(sum(h["n_steps_total"] for h in hists))
+    censored = int(sum(h["n_censored"] for h in hists))
+    # the same trajectories as consecutive single-problem launches (one pass)
+    for c in ctxs:
+        c.reset()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    single_ms = 0.0
+    for c, w, n in zip(ctxs, ws, counts):
+        c.run(int(n), dN, seed, 1 << 32, None)
+        single_ms += c.last_kernel_ms()
+    torch.cuda.synchronize()
+    wall_single = time.perf_counter() - t1
+    steps_single = int(sum(c.histogram()["n_steps_total"] for c in ctxs))
+    batch.destroy()
+    for c in ctxs:
+        c.destroy()
+    avg_ms = float(np.mean(kernel_ms))
+    achieved = ALG_FLOPS_PER_STEP["fp32"] * (steps_total / args.steps) / (avg_ms * 1e-3) / 1e12
+    return {
+        "metric": METRIC, "value": steps_total / wall, "unit": "trajectory-steps/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": wall * 1e3 / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "batched_64_fp32", "instances": len(ws),
+                   "trajectories_per_step": int(counts.sum()),
+                   "counts": "log-uniform in [1e4, 1e6]" if scale == 0.1 else f"batched_instances x {scale}",
+                   "step_cap": int(ws[0].max_steps), "dN": dN, "graph": True,
+                   "tuned_block": block, "tuned_chunk": chunk, "tune_s": tune_s},
+        "trajectory_steps": steps_total, "censored": censored,
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_TFLOPS["fp32"], "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_TFLOPS["fp32"], "traffic": None, "kernel": "batch_kernel",
+                     "kernel_ms": avg_ms, "flops_per_step": ALG_FLOPS_PER_STEP["fp32"]},
+        "single_launches": {"trajectory_steps_per_s": steps_single / wall_single, "kernel_ms_sum": single_ms,
+                            "batch_speedup": (steps_total / wall) / (steps_single / wall_single)},
+    }
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="srusr_is_fp32")
-    ap.add_argument("--n-traj", type=float, default=None)
+    ap.add_argument("--n-traj", type=float, default=None,
+                    help="trajectories per step (batched: scale factor of the instance counts, default 0.1)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-side", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
@@ -174,6 +258,9 @@ def main() -> int:
     from paper_2410_13683_amd import runner
 
     torch.cuda.set_device(0)
+    if args.workload == "batched":
+        print(json.dumps(bench_batched(args)), flush=True)
+        return 0
     if args.copy_calibration:
         src = torch.ones(args.copy_calibration // 4, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)

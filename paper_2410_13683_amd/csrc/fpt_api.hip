@@ -13,6 +13,7 @@
 #include <string>
 #include <algorithm>
 #include <vector>
+#include <limits>
 
 using namespace fpt;
 
@@ -146,6 +147,7 @@ struct fpt_ctx {
     hipEvent_t ev_start = nullptr, ev_stop = nullptr, ev_done = nullptr;
     bool ran = false;
     uint64_t n_traj_total = 0;
+    bool drift_table_used = false;           // FP32 V'/V intervals (see build_drift_table)
     // learned control (FPT_BIAS_MLP)
     GridSpec grid{};
     void *d_mlp = nullptr;                   // fixed-size part, carved below
@@ -162,6 +164,60 @@ struct fpt_ctx {
 };
 
 static const size_t kGradSlice = size_t(1) << 22;
+
+// V'/V per interval of the noise table for the FP32-state kernels: entry j is
+// (r(phi_j), r(phi_j+1) - r(phi_j)) on the potential branch of interval j, with
+// r = V'/V, so r is the linear interpolation of the interval.  The branch kink
+// phi_T must be a node (or lie outside the table) and the interpolation must
+// stay within 2^-25 of V'/V at every interval's midpoint; otherwise every entry
+// is NaN.  The entries of the two edge intervals (where coordinates outside the
+// table are clamped) and of the two intervals that meet at phi_T (where the
+// FP32 coordinate may round to the wrong side) are always NaN.  The kernels
+// compute V'/V exactly wherever they read NaN.  Returns whether any entry is
+// usable.
+static bool build_drift_table(const fpt_potential &p, int nt, double phi_lo, double phi_hi, std::vector<float> &r)
+{
+    const float nan = std::numeric_limits<float>::quiet_NaN();
+    r.assign(2 * (size_t)nt, nan);
+    if (nt < 4) return false;
+    const double h = (phi_hi - phi_lo) / (double)(nt - 1);
+    int j_T = -1;                             // node at the kink, if inside the table
+    if (p.kind == FPT_POT_PIECEWISE_LINEAR && p.phi_T > phi_lo && p.phi_T < phi_hi) {
+        const double q = (p.phi_T - phi_lo) / h;
+        const double qr = std::nearbyint(q);
+        if (std::fabs(q - qr) > 1e-9) return false;
+        j_T = (int)qr;
+    }
+    std::vector<float> t(2 * (size_t)nt, nan);
+    for (int j = 0; j + 1 < nt; ++j) {
+        const double a = phi_lo + (double)j * h, b = phi_lo + (double)(j + 1) * h, m = 0.5 * (a + b);
+        double ra, rb, rm;
+        if (p.kind == FPT_POT_EXPONENTIAL) {
+            ra = rb = rm = p.A_plus;
+        } else {
+            const double A = (m >= p.phi_T) ? p.A_plus : p.A_minus;
+            const double Va = p.V0 + A * (a - p.phi_T), Vb = p.V0 + A * (b - p.phi_T), Vm = p.V0 + A * (m - p.phi_T);
+            if (!(Va > 0.0 && Vb > 0.0 && Vm > 0.0)) return false;
+            ra = A / Va;
+            rb = A / Vb;
+            rm = A / Vm;
+        }
+        if (!(std::fabs(0.5 * (ra + rb) - rm) <= 0x1p-25 * std::fabs(rm))) return false;
+        t[2 * j] = (float)ra;
+        t[2 * j + 1] = (float)(rb - ra);
+    }
+    auto mark = [&](int j) {
+        if (j >= 0 && j + 1 < nt) t[2 * j] = t[2 * j + 1] = nan;
+    };
+    mark(0);
+    mark(nt - 2);
+    if (j_T >= 0) {
+        mark(j_T - 1);
+        mark(j_T);
+    }
+    r = t;
+    return true;
+}
 
 // Device memory and first tabulation of the learned control of context c
 // (bias already validated).  Grid coordinates of the kernels:
@@ -291,9 +347,11 @@ extern "C" int fpt_create(const fpt_potential *pot, const fpt_noise_table *table
     int lds_max = 0;
     if (e == hipSuccess) e = hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device);
     c->lds_per_block_max = (size_t)lds_max;
-    // device memory: FP64 table (nt x double2), FP32 table (nt x float4), cursor, accumulators
+    // device memory: FP64 table (nt x double2), FP32 table (nt x float4), FP32 V'/V intervals
+    // (nt x float2), cursor, accumulators
     const size_t off_tab32 = sizeof(double) * 2 * nt;
-    const size_t off_cursor = (off_tab32 + sizeof(float) * 4 * nt + 255) & ~size_t(255);
+    const size_t off_rtab = off_tab32 + sizeof(float) * 4 * nt;
+    const size_t off_cursor = (off_rtab + sizeof(float) * 2 * nt + 255) & ~size_t(255);
     const size_t off_acc = off_cursor + 256;
     const size_t total = off_acc + acc_bytes(o.n_bins);
     if (e == hipSuccess) e = hipMalloc(&c->d_mem, total);
@@ -318,6 +376,9 @@ extern "C" int fpt_create(const fpt_potential *pot, const fpt_noise_table *table
     unsigned char *base = static_cast<unsigned char *>(c->d_mem);
     e = hipMemcpy(base, h64.data(), sizeof(double) * 2 * nt, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(base + off_tab32, h32.data(), sizeof(float) * 4 * nt, hipMemcpyHostToDevice);
+    std::vector<float> hr;
+    c->drift_table_used = build_drift_table(*pot, nt, table->phi_lo, table->phi_hi, hr);
+    if (e == hipSuccess) e = hipMemcpy(base + off_rtab, hr.data(), sizeof(float) * 2 * nt, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemset(base + off_cursor, 0, 256 + acc_bytes(o.n_bins));
     if (e == hipSuccess) e = hipEventCreate(&c->ev_start);
     if (e == hipSuccess) e = hipEventCreate(&c->ev_stop);
@@ -335,6 +396,7 @@ extern "C" int fpt_create(const fpt_potential *pot, const fpt_noise_table *table
     I.inv_h = (nt > 1) ? (double)(nt - 1) / (table->phi_hi - table->phi_lo) : 0.0;
     I.tab64 = reinterpret_cast<const double2 *>(base);
     I.tab32 = reinterpret_cast<const float4 *>(base + off_tab32);
+    I.rtab32 = reinterpret_cast<const float2 *>(base + off_rtab);
     I.all_S_pos = all_pos ? 1 : 0;
     I.bias_kind = b.kind;
     I.A = (b.kind == FPT_BIAS_CONST) ? b.A : 0.0;

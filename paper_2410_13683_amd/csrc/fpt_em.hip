@@ -262,10 +262,15 @@ __device__ __forceinline__ void stage_table64(const Inst &I, double2 *l_tab)
     for (int i = threadIdx.x; i < n; i += blockDim.x) l_tab[i] = I.tab64[I.n_tab > 1 ? i : 0];
 }
 
+// FP32 staging: the noise nodes, then the V'/V intervals right after them (all
+// NaN for a single-node table, so that V'/V is computed exactly there).
 __device__ __forceinline__ void stage_table32(const Inst &I, float4 *l_tab)
 {
     const int n = staged_nodes(I);
     for (int i = threadIdx.x; i < n; i += blockDim.x) l_tab[i] = I.tab32[I.n_tab > 1 ? i : 0];
+    float2 *l_r = reinterpret_cast<float2 *>(l_tab + n);
+    const float nan = __builtin_nanf("");
+    for (int i = threadIdx.x; i < n; i += blockDim.x) l_r[i] = I.n_tab > 1 ? I.rtab32[i] : make_float2(nan, nan);
 }
 
 // ---------------------------------------------------------------------------
@@ -601,6 +606,7 @@ __device__ __forceinline__ void lanes_fp32(const Inst &I, const RunArgs &R, cons
     const F32Consts c = f32_consts(I, R);
     const GridConsts32 gc = grid_consts32(I);
     const float S0 = l_tab[0].x, t0 = l_tab[0].z;
+    const float2 *l_rtab = reinterpret_cast<const float2 *>(l_tab + staged_nodes(I));
     const double x_in = I.phi_in - I.phi_end;
     const float x_in_hi = (float)x_in, x_in_lo = (float)(x_in - (double)x_in_hi);
     const float pi_in_hi = (float)I.pi_in, pi_in_lo = (float)(I.pi_in - (double)pi_in_hi);
@@ -652,20 +658,35 @@ __device__ __forceinline__ void lanes_fp32(const Inst &I, const RunArgs &R, cons
                 live = false;
                 fresh = true;
             }
-            // phi - phi_T as an accurate float: (xh - xT_hi) + (xl - xT_lo)
-            const float dT = (xh - c.xT_hi) + (xl - c.xT_lo);
-            const float r = __builtin_amdgcn_rcpf(fmaf(dT, c.kx, (dT >= 0.0f) ? s_plus : s_minus));
-            float S, t;
+            // V'/V exactly: 1/(kx (phi - phi_T) + s), phi - phi_T = (xh - xT_hi) + (xl - xT_lo)
+            auto drift_exact = [&]() -> float {
+                const float dT = (xh - c.xT_hi) + (xl - c.xT_lo);
+                return __builtin_amdgcn_rcpf(fmaf(dT, c.kx, (dT >= 0.0f) ? s_plus : s_minus));
+            };
+            float S, t, r;
             if (TAB) {
                 const float u = fmaf(xh, c.inv_h, c.u_off);
                 const float jf = __builtin_amdgcn_fmed3f(floorf(u), 0.0f, c.jmax);
                 const float f = __builtin_amdgcn_fmed3f(u - jf, 0.0f, 1.0f);
                 const float4 node = l_tab[(int)jf];
+                const float2 rn = l_rtab[(int)jf];
                 S = fmaf(f, node.y, node.x);
                 t = fmaf(f, node.w, node.z);
+                // V'/V interpolated in the interval (error below FP32 resolution); NaN marks the
+                // intervals where it is computed exactly instead: the two edge intervals, which
+                // also take every clamped coordinate outside the table, the two intervals at the
+                // kink phi_T, and every interval of a table that does not qualify
+                r = fmaf(f, rn.y, rn.x);
+                if (__any(r != r)) {
+                    // a real branch (rarely taken): the volatile asm keeps the compiler from
+                    // computing the exact value in every step and selecting
+                    asm volatile("; exact V'/V");
+                    if (r != r) r = drift_exact();
+                }
             } else {
                 S = S0;
                 t = t0;
+                r = drift_exact();
             }
             float a = c.a;
             int cell = 0;
@@ -699,7 +720,9 @@ __device__ __forceinline__ void lanes_fp32(const Inst &I, const RunArgs &R, cons
             two_sum_fast(xh, xl, dx);
             two_sum_fast(ph, pl, dpi);
             const bool crossed = xh + xl <= 0.0f;
-            const bool ended = 0.5f * ph * ph >= 1.0f;
+            // eps_1 = pi^2/2 >= 1: |pi| >= the float just above sqrt(2) (no float lies between
+            // sqrt(2) and it, so this is pi^2 >= 2 for float pi)
+            const bool ended = fabsf(ph) >= 0x1.6a09e8p+0f;
             if (live && (crossed || ended)) {
                 ev_status = crossed ? 0u : kFlagEndedEarly;
                 ev_n = n + 1;
@@ -769,7 +792,11 @@ __device__ __forceinline__ void lanes_fp32(const Inst &I, const RunArgs &R, cons
 // weights], each part starting on a 16-byte boundary.
 // ---------------------------------------------------------------------------
 __host__ __device__ __forceinline__ size_t align16(size_t b) { return (b + 15) & ~(size_t)15; }
-__host__ __device__ __forceinline__ size_t tab_bytes(int n_tab) { return (size_t)(n_tab > 1 ? n_tab : 2) * 16; }
+// FP64: double2 per node; FP32: float4 per node plus the float2 V'/V interval
+__host__ __device__ __forceinline__ size_t tab_bytes(int precision, int n_tab)
+{
+    return align16((size_t)(n_tab > 1 ? n_tab : 2) * (precision == 0 ? 16 : 24));
+}
 __host__ __device__ __forceinline__ size_t cell_bytes(int precision, int n_cells)
 {
     return (size_t)n_cells * (precision == 0 ? 32 : 16);
@@ -810,7 +837,7 @@ __global__ void __launch_bounds__(1024) FPT_EM_OCCUPANCY em_kernel(EmParams p)
     extern __shared__ __align__(16) unsigned char smem[];
     const LdsAcc acc = lds_acc(smem, p.inst.hist.n_bins);
     unsigned char *l_tab = smem + align16(acc_bytes(p.inst.hist.n_bins));
-    unsigned char *l_grid = l_tab + tab_bytes(p.inst.n_tab);
+    unsigned char *l_grid = l_tab + tab_bytes(PREC, p.inst.n_tab);
     zero_lds_acc(acc);
     if (PREC == 0) stage_table64(p.inst, reinterpret_cast<double2 *>(l_tab));
     else stage_table32(p.inst, reinterpret_cast<float4 *>(l_tab));
@@ -838,7 +865,7 @@ __global__ void __launch_bounds__(1024) FPT_EM_OCCUPANCY replay_kernel(ReplayPar
     extern __shared__ __align__(16) unsigned char smem[];
     const Inst &I = p.inst;
     unsigned char *l_tab = smem;
-    unsigned char *l_grid = l_tab + tab_bytes(I.n_tab);
+    unsigned char *l_grid = l_tab + tab_bytes(PREC, I.n_tab);
     double *l_G = reinterpret_cast<double *>(l_grid + cell_bytes(PREC, grid_cells(I)));
     const int n_nodes = I.g_n0 * I.g_n1;
     for (int i = threadIdx.x; i < n_nodes; i += blockDim.x) l_G[i] = 0.0;
@@ -938,12 +965,12 @@ struct KTab {
 
 size_t em_lds_bytes(int n_bins, int n_tab, int precision, int n_cells)
 {
-    return align16(acc_bytes(n_bins)) + tab_bytes(n_tab) + cell_bytes(precision, n_cells);
+    return align16(acc_bytes(n_bins)) + tab_bytes(precision, n_tab) + cell_bytes(precision, n_cells);
 }
 
 size_t replay_lds_bytes(int n_tab, int precision, int n_cells, int n_nodes)
 {
-    return tab_bytes(n_tab) + cell_bytes(precision, n_cells) + (size_t)n_nodes * 8;
+    return tab_bytes(precision, n_tab) + cell_bytes(precision, n_cells) + (size_t)n_nodes * 8;
 }
 
 const void *em_kernel_ptr(int precision, int bias_kind, bool table, bool all_pos)

@@ -45,6 +45,9 @@ struct Inst {
     double phi_lo, inv_h;
     const double2 *tab64;            // node j: (S_j, tan_j)                                  (device)
     const float4 *tab32;             // node j: (S_j, S_j+1 - S_j, tan_j, tan_j+1 - tan_j) in FP32
+    // FP32 V'/V per table interval j: (r_j, r_j+1 - r_j) of the interval's own branch of the
+    // potential, or NaN where V'/V must be computed exactly (see fpt_api.hip)
+    const float2 *rtab32;
     int32_t all_S_pos;               // every node has S > 0 (the ln w update needs no test)
     int32_t bias_kind;
     double A;
