@@ -306,7 +306,8 @@ typedef struct fpt_batch fpt_batch;
 typedef struct {
     int32_t block_size;   /* 64..1024, multiple of 64; 0 = 1024 (or the tuned value) */
     int32_t chunk;        /* steps between retire/refill, multiple of 4; 0 = 128 */
-    int32_t item_size;    /* trajectories per work item; 0 = 16 x block_size */
+    int32_t item_size;    /* trajectories per work item; 0 = k x block_size with k in 1..16 chosen
+                             so that each resident block takes about 32 items per run */
     int32_t use_graph;    /* 1 = capture/replay the launch as a hipGraph (non-null streams) */
 } fpt_batch_options;
 
@@ -326,7 +327,9 @@ int fpt_batch_run(fpt_batch *b, const uint64_t *n_traj, double dN, uint64_t seed
 /* Pick the block size and chunk for this batch: look the configuration up in
  * cache_path (text lines "key block chunk"; may be NULL), else time a probe
  * launch for each of block {256, 512, 1024} x chunk {32, 64, 128, 256} on
- * trajectories beyond index 2^62 with private accumulators, keep the fastest,
+ * about 8192 trajectories per compute unit (spread over the instances in
+ * proportion to n_traj, capped at 2^15 steps, one trajectory per lane per work
+ * item) beyond index 2^62 with private accumulators, keep the fastest,
  * measure each instance's mean steps per trajectory for the work order and
  * append the result to cache_path.  Contexts' histograms are not touched.
  * Synchronous.  Errors: FPT_EINVAL, FPT_EHIP. */

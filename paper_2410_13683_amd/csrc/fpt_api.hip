@@ -879,6 +879,26 @@ static int ensure_items(fpt_batch *b, size_t n)
 }
 
 // Work items of every instance, longest estimated cost first (longest-processing-time order).
+// Default work-item size: whole trajectories per lane (1..16 per lane of a
+// block), as many as keep about 32 items per resident block, so the queue,
+// taken longest first, ends with short items and the blocks finish together.
+static int default_item_size(const fpt_batch *b, const uint64_t *n_traj, int block)
+{
+    uint64_t total = 0;
+    for (int i = 0; i < b->n_inst; ++i) total += n_traj[i];
+    int per_cu = 1;
+    const void *fn = batch_kernel_ptr(b->precision, b->bias_kind, b->all_pos);
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, block,
+                                                     em_lds_bytes(b->max_bins, b->max_tab, b->precision, 0)) !=
+            hipSuccess ||
+        per_cu < 1)
+        per_cu = 1;
+    const double blocks = (double)per_cu * (double)b->cu_count;
+    const double per_lane = (double)total / (32.0 * blocks * (double)block);
+    const int k = (int)std::max(1.0, std::min(16.0, std::floor(per_lane)));
+    return k * block;
+}
+
 static std::vector<WorkItem> make_items(const fpt_batch *b, const uint64_t *n_traj, uint64_t traj_offset,
                                         int item_size)
 {
@@ -974,7 +994,7 @@ extern "C" int fpt_batch_run(fpt_batch *b, const uint64_t *n_traj, double dN, ui
     int rc = check_batch_run(b, n_traj, dN, traj_offset);
     if (rc) return rc;
     hipStream_t s = static_cast<hipStream_t>(hip_stream);
-    const int item_size = b->item_size ? b->item_size : 16 * b->block;
+    const int item_size = b->item_size ? b->item_size : default_item_size(b, n_traj, b->block);
     std::vector<WorkItem> items = make_items(b, n_traj, traj_offset, item_size);
     if (items.empty()) return FPT_OK;
     // graph capture needs a stream other than the legacy null stream
@@ -1028,7 +1048,8 @@ static std::string tune_key(const fpt_batch *b)
     std::string arch = "unknown";
     if (hipGetDeviceProperties(&prop, b->device) == hipSuccess) arch = prop.gcnArchName;
     char buf[256];
-    snprintf(buf, sizeof buf, "%s/cu%d/prec%d/bias%d/pos%d/inst%d/tab%d/bins%d", arch.c_str(), b->cu_count,
+    // "t2": the probe layout; entries written by an older probe do not match
+    snprintf(buf, sizeof buf, "t2/%s/cu%d/prec%d/bias%d/pos%d/inst%d/tab%d/bins%d", arch.c_str(), b->cu_count,
              b->precision, b->bias_kind, b->all_pos ? 1 : 0, b->n_inst, b->max_tab, b->max_bins);
     for (char &ch : buf)
         if (ch == ' ') ch = '_';
@@ -1069,7 +1090,9 @@ extern "C" int fpt_batch_autotune(fpt_batch *b, const uint64_t *n_traj, double d
     double total = 0.0;
     for (int i = 0; i < b->n_inst; ++i) total += (double)n_traj[i];
     if (!(total > 0.0)) return fail(FPT_EINVAL, "no trajectories to tune on");
-    const double lanes = (double)b->cu_count * 2048.0;
+    // enough probe trajectories for about 8 one-trajectory-per-lane items per CU at block 1024
+    // (fewer items than resident blocks would leave CUs idle and bias the probe to small blocks)
+    const double lanes = (double)b->cu_count * 8192.0;
     std::vector<uint64_t> probe_n(b->n_inst);
     for (int i = 0; i < b->n_inst; ++i)
         probe_n[i] = n_traj[i] ? std::max<uint64_t>(64, (uint64_t)(lanes * (double)n_traj[i] / total)) : 0;
@@ -1083,7 +1106,7 @@ extern "C" int fpt_batch_autotune(fpt_batch *b, const uint64_t *n_traj, double d
     const uint64_t probe_offset = 1ull << 62;
     for (int blk : blocks)
         for (int chk : chunks) {
-            std::vector<WorkItem> items = make_items(b, probe_n.data(), probe_offset, 4 * blk);
+            std::vector<WorkItem> items = make_items(b, probe_n.data(), probe_offset, blk);
             rc = batch_launch_items(b, items, b->d_inst_probe, dN, seed, blk, chk, s, false);
             if (rc) return rc;
             double ms = 0.0;
