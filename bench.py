@@ -47,16 +47,49 @@ if ROOT not in sys.path:
 
 METRIC = "trajectory-steps/s and ESS-weighted tail samples/s at 5% P(δN) tail error"
 
-# Algorithmic work of one trajectory step (constant bias, phi-indexed table,
-# piecewise-linear potential), counted operation by operation from the step's
-# definition; FMA = 2 FLOPs, a transcendental = 1.  Derivation in the design doc.
-ALG_FLOPS_PER_STEP = {"fp32": 56.5, "fp64": 58.5}
+# Floating-point work of one trajectory step (constant bias, phi-indexed table,
+# piecewise-linear potential), counted operation by operation as the kernels do
+# it; FMA = 2 FLOPs, a transcendental or a compare = 1.  The FP32 path takes V'/V
+# from the interval table (an interpolation and a NaN test) where the FP64 path
+# computes the reciprocal.  Derivation in the design doc.
+ALG_FLOPS_PER_STEP = {"fp32": 51.5, "fp64": 58.5}
 # the tabulated learned control adds its grid coordinates (ln|pi| included), the clamped
 # cell and fractions, the bilinear interpolation and the per-step dA = a xi sqrt(dN) + a^2 dN/2
 ALG_FLOPS_LEARNED_EXTRA = {"fp32": 31.0, "fp64": 31.0}
 ALG_INT_OPS_PER_STEP = 16.0          # Philox4x32-10 amortised over 4 steps + uniform conversions
-PEAK_TFLOPS = {"fp32": 157.3, "fp64": 78.6}   # MI355X vector peaks (FP32 figure assumes packed issue)
+PEAK_TFLOPS = {"fp32": 157.3, "fp64": 78.6}   # MI355X published vector peaks
 PEAK_HBM_GBS = 8000.0
+
+# HBM traffic of one launch of the default workload's kernel (FP32 state, constant bias, 1e8
+# trajectories), from two rocprofv3 --pmc runs (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch),
+# each scaled by what the same counter reads for a 1 GiB device-to-device copy in the same
+# process (FETCH_SIZE reads 0.5 GiB: x2.0; WRITE_SIZE reads 1 GiB: x1.0).  Valid only for the
+# kernel source it was measured on (hash of the kernel file and its header).
+MEASURED_TRAFFIC = {
+    "source_sha256": "290ed555d15646d2776ec6e3690d5a945e072c16f0d659b649e154222371879d",
+    "workload": "srusr_is_fp32_A2", "n_traj": 100_000_000,
+    "fetch_bytes": 465.0 * 1024 * 2.0, "write_bytes": 2082788.0625 * 1024 * 1.0,
+}
+
+
+def kernel_source_sha() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("fpt_em.hip", "internal.hpp"):
+        with open(os.path.join(ROOT, "paper_2410_13683_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(w):
+    m = MEASURED_TRAFFIC
+    if w.name != m["workload"] or w.n_traj != m["n_traj"] or kernel_source_sha() != m["source_sha256"]:
+        return None, None
+    detail = {"fetch_bytes": m["fetch_bytes"], "write_bytes": m["write_bytes"],
+              "per_trajectory_bytes": (m["fetch_bytes"] + m["write_bytes"]) / m["n_traj"],
+              "note": "writes are the work-queue claims (device-scope atomics, performed at the memory side); "
+                      "no per-step traffic"}
+    return m["fetch_bytes"] + m["write_bytes"], detail
 
 
 def _workload(name: str, n_traj: int | None):
@@ -343,12 +376,18 @@ def main() -> int:
             "unit": "TFLOP/s",
             "frac": achieved / PEAK_TFLOPS[prec],
             "traffic": None,
-            "kernel": "em_fp32s_kernel" if prec == "fp32" else "em_fp64_kernel",
+            "kernel": "em_kernel<FP32 state, const bias, table>" if prec == "fp32" else "em_kernel<FP64>",
             "kernel_ms": avg_ms,
             "flops_per_step": flops_step,
             "int_ops_per_step": ALG_INT_OPS_PER_STEP,
         },
     }
+    if not learned:
+        traffic, detail = measured_traffic(w)
+        result["roofline"]["traffic"] = traffic
+        if detail:
+            result["roofline"]["traffic_detail"] = detail
+            result["roofline"]["traffic_GBs"] = traffic / (avg_ms * 1e-3) / 1e9
     if learned:
         best = max(learned["constant_fallback"], key=lambda r: r["ess_tail_per_s"])
         learned["ess_tail_per_s_vs_best_constant"] = ess_rate / best["ess_tail_per_s"] if best["ess_tail_per_s"] else None
