@@ -41,6 +41,7 @@
  * oracle section of the design doc); the learned-bias replay gradient is pinned by
  * central finite differences of its own objective.
  */
+#include <complex.h>
 #include <math.h>
 #include <stdint.h>
 #include <stdlib.h>
@@ -760,4 +761,275 @@ void orc_adam_step(float *theta, float *m, float *v, const float *grad, int n, i
         const double vhat = vi / bc2;
         theta[i] = (float)((double)theta[i] - lr * mhat / (sqrt(vhat) + eps));
     }
+}
+
+/* ========================================================================= */
+/* Two-dimensional noise.                                                    */
+/* ========================================================================= */
+
+/* Noise covariance of eq. (covariance_matrix_direct): the full mode function */
+/* of eq. (delta_phi_bessel) with the Bunch-Davies coefficients of            */
+/* eq. (A_k_and_B_k) -- the exact mode for constant nu -- and its N-derivative */
+/* at -k eta = sigma.  With y = -k eta, sqrt(-eta)/a = H (y/k)^(3/2) and        */
+/* d/dN = -y d/dy:                                                             */
+/*   delta phi_k = H k^(-3/2) F(y),  F = y^(3/2) [A J_nu(y) + B Y_nu(y)],       */
+/*   delta pi_k  = H k^(-3/2) (-y F'(y)),                                      */
+/*   Xi = k^3/(2 pi^2) [[|dphi|^2, Re(dphi dpi*)], [., |dpi|^2]]               */
+/*      = H^2/(2 pi^2) [[|F|^2, Re(F conj(-y F'))], [., |y F'|^2]].             */
+/* Y_nu = (J_nu cos(nu pi) - J_-nu)/sin(nu pi) and the power series            */
+/* J_mu(y) = sum_m (-1)^m (y/2)^(2m + mu) / (m! Gamma(m + mu + 1)) give        */
+/*   F = sum_{mu = nu, -nu} alpha_mu sum_m c_m(mu) y^(2m + mu + 3/2),           */
+/*   -y F' = -sum alpha_mu sum_m (2m + mu + 3/2) c_m(mu) y^(2m + mu + 3/2),     */
+/* alpha_nu = A + B cot(nu pi), alpha_-nu = -B / sin(nu pi),                   */
+/* c_m(mu) = (-1)^m / (m! Gamma(m + mu + 1) 2^(2m + mu)).  The m = 0 terms are */
+/* the homogeneous growing (mu = -nu) and decaying (mu = nu) modes of          */
+/* eq. (bessel_matched_homogeneous).  30 terms per series: for sigma <= 2 the  */
+/* remainder is below 1e-40 of the leading term.  nu and H^2 = V/3 as for the  */
+/* 1D table.                                                                    */
+/* ------------------------------------------------------------------------- */
+int orc_noise_table_bessel2d(int kind, const double pot[4], double sigma, int n, double phi_lo, double phi_hi,
+                             double *Xpp_out, double *Xpq_out, double *Xqq_out)
+{
+    if (n < 1 || !(sigma > 0.0) || sigma > 2.0) return -1;
+    if (n > 1 && !(phi_hi > phi_lo)) return -1;
+    const double h = (n > 1) ? (phi_hi - phi_lo) / (double)(n - 1) : 0.0;
+    for (int j = 0; j < n; ++j) {
+        const double phi = phi_lo + (double)j * h;
+        const double V = orc_V(kind, pot, phi);
+        if (!(V > 0.0)) return -1;
+        const double dVV = orc_dV(kind, pot, phi) / V;
+        const double d2VV = orc_d2V(kind, pot, phi) / V;
+        const double nu2 = 9.0 / 4.0 - 3.0 * (d2VV - dVV * dVV);
+        if (!(nu2 > 0.0)) return -1;
+        const double nu = sqrt(nu2);
+        if (fabs(sin(M_PI * nu)) < 1e-3) return -1;   /* Y_nu's formula needs non-integer nu */
+        const double H2 = V / 3.0;
+        const double complex A = 0.5 * sqrt(M_PI) * cexp(I * (nu + 0.5) * M_PI / 2.0);
+        const double complex B = 0.5 * sqrt(M_PI) * cexp(I * (nu + 1.5) * M_PI / 2.0);
+        const double complex alpha[2] = {A + B * cos(M_PI * nu) / sin(M_PI * nu), -B / sin(M_PI * nu)};
+        const double mus[2] = {nu, -nu};
+        double complex F = 0.0, G = 0.0;   /* F and -y F' */
+        for (int k = 0; k < 2; ++k) {
+            const double mu = mus[k];
+            for (int m = 0; m < 30; ++m) {
+                const double c = ((m % 2) ? -1.0 : 1.0) / (tgamma((double)m + 1.0) * tgamma((double)m + mu + 1.0) *
+                                                            pow(2.0, 2.0 * m + mu));
+                const double p = 2.0 * m + mu + 1.5;
+                const double term = c * pow(sigma, p);
+                F += alpha[k] * term;
+                G -= alpha[k] * p * term;
+            }
+        }
+        const double c = H2 / (2.0 * M_PI * M_PI);
+        Xpp_out[j] = c * creal(F * conj(F));
+        Xpq_out[j] = c * creal(F * conj(G));
+        Xqq_out[j] = c * creal(G * conj(G));
+    }
+    return 0;
+}
+
+/* The symmetric positive semi-definite square root of [[a, b], [b, c]]:      */
+/* S = (Xi + s 1)/t with s = sqrt(det Xi), t = sqrt(tr Xi + 2 s) (S^2 = Xi by  */
+/* the Cayley-Hamilton identity Xi^2 - tr(Xi) Xi + det(Xi) 1 = 0); zero for   */
+/* Xi = 0.  Returns -1 if Xi is not positive semi-definite.                   */
+int orc_sqrt_sym2(double a, double b, double c, double *Spp, double *Spq, double *Sqq)
+{
+    const double det = a * c - b * b;
+    if (!(a >= 0.0) || !(c >= 0.0) || !(det >= 0.0)) return -1;
+    const double s = sqrt(det);
+    const double tr = a + c + 2.0 * s;
+    if (tr == 0.0) { *Spp = *Spq = *Sqq = 0.0; return 0; }
+    const double t = sqrt(tr);
+    *Spp = (a + s) / t;
+    *Spq = b / t;
+    *Sqq = (c + s) / t;
+    return 0;
+}
+
+/* The two unit Gaussians (xi_1, xi_2) of step n with 2D noise: call m = n >> 1 */
+/* of the generator gives (xi_1, xi_2) of step 2m from (u0, u1) and of step   */
+/* 2m + 1 from (u2, u3) (same Box-Muller pairs as the 1D stream).              */
+void orc_normals2d(uint64_t seed, uint32_t instance, uint64_t traj, uint64_t n0, uint64_t count, double *z_out)
+{
+    for (uint64_t i = 0; i < count; ++i) {
+        const uint64_t n = n0 + i;
+        double z[4];
+        orc_four_normals(seed, instance, traj, n >> 1, z);
+        z_out[2 * i] = z[2 * (n & 1)];
+        z_out[2 * i + 1] = z[2 * (n & 1) + 1];
+    }
+}
+
+typedef struct {
+    int kind;
+    double pot[4];
+    int n_tab;
+    double phi_lo, phi_hi;
+    const double *Spp, *Spq, *Sqq;   /* square roots of the node covariances */
+    const double *e1, *e2;           /* unit principal axis of the node covariances */
+    double phi_in, pi_in, phi_end;
+    int bias_kind;
+    double A_bias;
+    double dN;
+    uint64_t seed;
+    uint32_t instance;
+    int64_t max_steps;
+} orc_problem2d;
+
+/* Unit eigenvector of [[a, b], [b, c]] (symmetric) for its largest eigenvalue        */
+/* lambda = (a + c)/2 + r, r = sqrt(((a - c)/2)^2 + b^2), with a non-negative phi       */
+/* component; (1, 0) when the eigenvalues coincide (b = 0, a = c) or the matrix is 0. */
+void orc_principal_axis(double a, double b, double c, double *e1, double *e2)
+{
+    const double r = sqrt(0.25 * (a - c) * (a - c) + b * b);
+    double v1, v2;
+    if (a >= c) {            /* (lambda - c, b) */
+        v1 = 0.5 * (a - c) + r;
+        v2 = b;
+    } else {                 /* (b, lambda - a) */
+        v1 = b;
+        v2 = 0.5 * (c - a) + r;
+    }
+    if (v1 < 0.0) { v1 = -v1; v2 = -v2; }
+    const double norm = sqrt(v1 * v1 + v2 * v2);
+    if (norm == 0.0) { *e1 = 1.0; *e2 = 0.0; return; }
+    *e1 = v1 / norm;
+    *e2 = v2 / norm;
+}
+
+/* S(phi) and e(phi): linear interpolation of the nodes' square roots and principal */
+/* axes, clamped to the edge nodes.                                                  */
+static void orc_table2d_lookup(const orc_problem2d *P, double phi, double S[3], double e[2])
+{
+    if (P->n_tab == 1) {
+        S[0] = P->Spp[0]; S[1] = P->Spq[0]; S[2] = P->Sqq[0];
+        e[0] = P->e1[0]; e[1] = P->e2[0];
+        return;
+    }
+    const double h = (P->phi_hi - P->phi_lo) / (double)(P->n_tab - 1);
+    const double x = (phi - P->phi_lo) / h;
+    double jf = floor(x);
+    if (jf < 0.0) jf = 0.0;
+    if (jf > (double)(P->n_tab - 2)) jf = (double)(P->n_tab - 2);
+    const int j = (int)jf;
+    double f = x - jf;
+    if (f < 0.0) f = 0.0;
+    if (f > 1.0) f = 1.0;
+    S[0] = P->Spp[j] + f * (P->Spp[j + 1] - P->Spp[j]);
+    S[1] = P->Spq[j] + f * (P->Spq[j + 1] - P->Spq[j]);
+    S[2] = P->Sqq[j] + f * (P->Sqq[j + 1] - P->Sqq[j]);
+    e[0] = P->e1[j] + f * (P->e1[j + 1] - P->e1[j]);
+    e[1] = P->e2[j] + f * (P->e2[j + 1] - P->e2[j]);
+}
+
+/* One trajectory with 2D noise: eq. (full_langevin_equation) stepped with    */
+/* eq. (euler_step_phi_and_pi) plus the bias, weight of eq. (weight_A) with    */
+/* Xi = S^2.  The diffusion-based bias in 2D is B = A S e, e the unit principal */
+/* axis of Xi (phi component >= 0), i.e. the push A along e in noise space:    */
+/* in the rank-1 limit Xi = s s^T it is B = A s, the 1D bias of Sec. 4.1.       */
+static void orc_trajectory2d(const orc_problem2d *P, uint64_t traj, double *N_out, double *lnw_out,
+                             uint32_t *steps_out)
+{
+    const double dN = P->dN;
+    const double sqrt_dN = sqrt(dN);
+    double phi = P->phi_in, pi_ = P->pi_in, lnw = 0.0;
+    int64_t n = 0;
+    double zbuf[4];
+    uint64_t zcall = UINT64_MAX;
+    for (;;) {
+        if (n >= P->max_steps) {
+            *N_out = NAN;
+            *lnw_out = lnw;
+            *steps_out = (uint32_t)n | ORC_FLAG_CENSORED;
+            return;
+        }
+        const uint64_t call = (uint64_t)n >> 1;
+        if (call != zcall) { orc_four_normals(P->seed, P->instance, traj, call, zbuf); zcall = call; }
+        const double xi1 = zbuf[2 * (n & 1)], xi2 = zbuf[2 * (n & 1) + 1];
+        /* drift vector D, eq. (full_langevin_equation) */
+        const double V = orc_V(P->kind, P->pot, phi);
+        const double dV = orc_dV(P->kind, P->pot, phi);
+        const double D_phi = pi_;
+        const double D_pi = -(3.0 - pi_ * pi_ / 2.0) * (pi_ + dV / V);
+        /* noise matrix S, principal axis e, bias B = A S e */
+        double S[3], e[2];
+        orc_table2d_lookup(P, phi, S, e);
+        const double A = (P->bias_kind == ORC_BIAS_CONST) ? P->A_bias : 0.0;
+        const double B_phi = A * (S[0] * e[0] + S[1] * e[1]);
+        const double B_pi = A * (S[1] * e[0] + S[2] * e[1]);
+        const double noise_phi = (S[0] * xi1 + S[1] * xi2) * sqrt_dN;
+        const double noise_pi = (S[1] * xi1 + S[2] * xi2) * sqrt_dN;
+        const double phi_next = phi + D_phi * dN + B_phi * dN + noise_phi;
+        const double pi_next = pi_ + D_pi * dN + B_pi * dN + noise_pi;
+        /* dA of eq. (weight_A), (B dN/2 + S xi sqrt(dN))^T Xi^-1 B with Xi = S S, evaluated as  */
+        /* u . (u dN/2 + xi sqrt(dN)) with u = S^-1 B (S symmetric, so Xi^-1 = S^-1 S^-1)       */
+        if (A != 0.0 && (S[0] != 0.0 || S[1] != 0.0 || S[2] != 0.0)) {
+            const double detS = S[0] * S[2] - S[1] * S[1];
+            const double u1 = (S[2] * B_phi - S[1] * B_pi) / detS;
+            const double u2 = (S[0] * B_pi - S[1] * B_phi) / detS;
+            const double dA = u1 * (u1 * dN / 2.0 + xi1 * sqrt_dN) + u2 * (u2 * dN / 2.0 + xi2 * sqrt_dN);
+            lnw -= dA;
+        }
+        n += 1;
+        if (phi_next <= P->phi_end) {
+            const double frac = (phi - P->phi_end) / (phi - phi_next);
+            *N_out = (double)(n - 1) * dN + dN * frac;
+            *lnw_out = lnw;
+            *steps_out = (uint32_t)n;
+            return;
+        }
+        if (pi_next * pi_next / 2.0 >= 1.0) {
+            *N_out = (double)n * dN;
+            *lnw_out = lnw;
+            *steps_out = (uint32_t)n | ORC_FLAG_ENDED_EARLY;
+            return;
+        }
+        phi = phi_next;
+        pi_ = pi_next;
+    }
+}
+
+/* Trajectories traj_offset .. traj_offset + n_traj - 1 with 2D noise given by */
+/* the node covariances Xi (each zero or positive definite).  bias_kind: NONE  */
+/* or CONST.  Returns 0, or -1 on invalid input.                               */
+int orc_run2d(int kind, const double pot[4], int n_tab, double phi_lo, double phi_hi, const double *Xpp,
+              const double *Xpq, const double *Xqq, double phi_in, double pi_in, double phi_end, int bias_kind,
+              double A_bias, double dN, uint64_t seed, uint32_t instance, uint64_t traj_offset, uint64_t n_traj,
+              int64_t max_steps, double *N_out, double *lnw_out, uint32_t *steps_out, int n_threads)
+{
+    if (n_tab < 1 || !(dN > 0.0) || max_steps < 1 || max_steps > (int64_t)ORC_STEP_MASK) return -1;
+    if (!(phi_in > phi_end)) return -1;
+    if (bias_kind != ORC_BIAS_NONE && bias_kind != ORC_BIAS_CONST) return -1;
+    double *S = (double *)malloc(sizeof(double) * 5 * (size_t)n_tab);
+    if (!S) return -1;
+    for (int j = 0; j < n_tab; ++j) {
+        const double det = Xpp[j] * Xqq[j] - Xpq[j] * Xpq[j];
+        const int zero = Xpp[j] == 0.0 && Xpq[j] == 0.0 && Xqq[j] == 0.0;
+        if ((!zero && !(Xpp[j] > 0.0 && det > 0.0)) ||
+            orc_sqrt_sym2(Xpp[j], Xpq[j], Xqq[j], &S[j], &S[n_tab + j], &S[2 * n_tab + j]) != 0) {
+            free(S);
+            return -1;
+        }
+        orc_principal_axis(Xpp[j], Xpq[j], Xqq[j], &S[3 * n_tab + j], &S[4 * n_tab + j]);
+    }
+    orc_problem2d P;
+    memset(&P, 0, sizeof P);
+    P.kind = kind;
+    memcpy(P.pot, pot, sizeof P.pot);
+    P.n_tab = n_tab; P.phi_lo = phi_lo; P.phi_hi = phi_hi;
+    P.Spp = S; P.Spq = S + n_tab; P.Sqq = S + 2 * n_tab; P.e1 = S + 3 * n_tab; P.e2 = S + 4 * n_tab;
+    P.phi_in = phi_in; P.pi_in = pi_in; P.phi_end = phi_end;
+    P.bias_kind = bias_kind; P.A_bias = A_bias;
+    P.dN = dN; P.seed = seed; P.instance = instance; P.max_steps = max_steps;
+#ifdef _OPENMP
+    if (n_threads > 0) omp_set_num_threads(n_threads);
+#else
+    (void)n_threads;
+#endif
+    const int64_t nt = (int64_t)n_traj;
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t i = 0; i < nt; ++i)
+        orc_trajectory2d(&P, traj_offset + (uint64_t)i, &N_out[i], &lnw_out[i], &steps_out[i]);
+    free(S);
+    return 0;
 }

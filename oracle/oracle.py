@@ -100,6 +100,21 @@ def lib():
         L.orc_adam_step.argtypes = [fp, fp, fp, fp, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double,
                                     ctypes.c_double, ctypes.c_double]
         L.orc_adam_step.restype = None
+        L.orc_noise_table_bessel2d.argtypes = [ctypes.c_int, dp, ctypes.c_double, ctypes.c_int, ctypes.c_double,
+                                               ctypes.c_double, dp, dp, dp]
+        L.orc_noise_table_bessel2d.restype = ctypes.c_int
+        L.orc_sqrt_sym2.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_double, dp, dp, dp]
+        L.orc_sqrt_sym2.restype = ctypes.c_int
+        L.orc_normals2d.argtypes = [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_uint64,
+                                    ctypes.c_uint64, dp]
+        L.orc_normals2d.restype = None
+        L.orc_run2d.argtypes = [ctypes.c_int, dp, ctypes.c_int, ctypes.c_double, ctypes.c_double, dp, dp, dp,
+                                ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_int, ctypes.c_double,
+                                ctypes.c_double, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_uint64,
+                                ctypes.c_int64, dp, dp, u32p, ctypes.c_int]
+        L.orc_run2d.restype = ctypes.c_int
+        L.orc_principal_axis.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_double, dp, dp]
+        L.orc_principal_axis.restype = None
         _lib = L
     return _lib
 
@@ -282,6 +297,77 @@ def adam_step(theta: np.ndarray, m: np.ndarray, v: np.ndarray, grad: np.ndarray,
         assert a.dtype == np.float32 and a.flags.c_contiguous
     g = np.ascontiguousarray(grad, dtype=np.float32)
     lib().orc_adam_step(_fp(theta), _fp(m), _fp(v), _fp(g), len(theta), t, lr, b1, b2, eps)
+
+
+# --------------------------------------------------------------------------
+# two-dimensional noise
+# --------------------------------------------------------------------------
+@dataclass
+class Problem2D:
+    """A first-passage problem with 2D noise: node covariances Xi (phi-phi, phi-pi, pi-pi)."""
+    kind: int
+    V0: float
+    phi_T: float
+    A_plus: float
+    A_minus: float
+    phi_in: float
+    pi_in: float
+    phi_end: float
+    Xpp: np.ndarray
+    Xpq: np.ndarray
+    Xqq: np.ndarray
+    phi_lo: float = 0.0
+    phi_hi: float = 0.0
+    bias_kind: int = BIAS_NONE
+    A_bias: float = 0.0
+
+    def pot(self) -> np.ndarray:
+        return np.array([self.V0, self.phi_T, self.A_plus, self.A_minus], dtype=np.float64)
+
+
+def noise_table_bessel2d(kind, V0, phi_T, A_plus, A_minus, sigma, n, phi_lo, phi_hi):
+    """(Xi_pp, Xi_pq, Xi_qq) at the nodes: both homogeneous modes of eq. (bessel_matched_homogeneous)."""
+    p = np.array([V0, phi_T, A_plus, A_minus], dtype=np.float64)
+    X = [np.empty(n, dtype=np.float64) for _ in range(3)]
+    rc = lib().orc_noise_table_bessel2d(kind, _dp(p), sigma, n, phi_lo, phi_hi, *[_dp(x) for x in X])
+    if rc != 0:
+        raise ValueError("invalid noise-table parameters")
+    return tuple(X)
+
+
+def sqrt_sym2(a: float, b: float, c: float):
+    out = [np.zeros(1) for _ in range(3)]
+    if lib().orc_sqrt_sym2(a, b, c, *[_dp(x) for x in out]) != 0:
+        raise ValueError("not positive semi-definite")
+    return tuple(float(x[0]) for x in out)
+
+
+def principal_axis(a: float, b: float, c: float):
+    e = [np.zeros(1), np.zeros(1)]
+    lib().orc_principal_axis(a, b, c, _dp(e[0]), _dp(e[1]))
+    return float(e[0][0]), float(e[1][0])
+
+
+def normals2d(seed: int, instance: int, traj: int, n0: int, count: int) -> np.ndarray:
+    """(xi_1, xi_2) of steps n0 .. n0+count-1 of one trajectory with 2D noise, shape (count, 2)."""
+    z = np.empty(2 * count, dtype=np.float64)
+    lib().orc_normals2d(seed, instance, traj, n0, count, _dp(z))
+    return z.reshape(count, 2)
+
+
+def run2d(prob: Problem2D, dN: float, seed: int, n_traj: int, traj_offset: int = 0, instance: int = 0,
+          max_steps: int = STEP_MASK, n_threads: int = 0):
+    X = [np.ascontiguousarray(x, dtype=np.float64) for x in (prob.Xpp, prob.Xpq, prob.Xqq)]
+    N = np.empty(n_traj, dtype=np.float64)
+    lnw = np.empty(n_traj, dtype=np.float64)
+    steps = np.empty(n_traj, dtype=np.uint32)
+    pot = prob.pot()
+    rc = lib().orc_run2d(prob.kind, _dp(pot), len(X[0]), prob.phi_lo, prob.phi_hi, *[_dp(x) for x in X],
+                         prob.phi_in, prob.pi_in, prob.phi_end, prob.bias_kind, prob.A_bias, dN, seed, instance,
+                         traj_offset, n_traj, max_steps, _dp(N), _dp(lnw), _u32p(steps), n_threads)
+    if rc != 0:
+        raise ValueError("invalid oracle problem")
+    return N, lnw, steps
 
 
 # --------------------------------------------------------------------------
