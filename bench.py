@@ -1,7 +1,7 @@
 """Benchmark of the first-passage hot path on one MI355X.
 
     python bench.py [--steps K] [--warmup W] [--n-traj N] [--no-cpu-baseline]
-                    [--workload srusr_is_fp32|srusr_fp64|srusr_learned|batched]
+                    [--workload srusr_is_fp32|srusr_fp64|srusr_2d|srusr_learned|batched]
 
 One bench step is one full pass of the hot path over the workload's batch of
 trajectories: Philox -> Box-Muller -> noise-table lookup -> drift -> bias ->
@@ -23,6 +23,9 @@ the comparison), then training of the 2->64->64->2 network from the constant
 A = 1 on 1e7 generated trajectories (replay gradient of ln E[w^2 1_T] with T the
 P = 1e-10 tail found by the A = 2 pass, Adam), then the timed passes with the
 trained, tabulated control.
+
+--workload srusr_2d runs the SR -> USR problem with 2D noise (the covariance of the
+full Bunch-Davies mode at -k eta = 0.1 on 2048 nodes), FP64 state, 1e6 trajectories.
 
 --workload batched measures many problems in one persistent launch: the 64
 SR -> USR instances with eps_- log-uniform in [1e-10, 1e-6], phi_e - phi_end
@@ -56,6 +59,10 @@ ALG_FLOPS_PER_STEP = {"fp32": 51.5, "fp64": 58.5}
 # the tabulated learned control adds its grid coordinates (ln|pi| included), the clamped
 # cell and fractions, the bilinear interpolation and the per-step dA = a xi sqrt(dN) + a^2 dN/2
 ALG_FLOPS_LEARNED_EXTRA = {"fp32": 31.0, "fp64": 31.0}
+# FP64 state with 2D noise, no bias: a Box-Muller pair per step (13), V'/V (13), five interpolated
+# table entries (23), the 2x2 noise product (6), the update (12), events (4); a constant bias adds
+# B = a S e (8) and dA (10)
+ALG_FLOPS_2D = {"none": 71.0, "const": 89.0}
 ALG_INT_OPS_PER_STEP = 16.0          # Philox4x32-10 amortised over 4 steps + uniform conversions
 PEAK_TFLOPS = {"fp32": 157.3, "fp64": 78.6}   # MI355X published vector peaks
 PEAK_HBM_GBS = 8000.0
@@ -100,6 +107,8 @@ def _workload(name: str, n_traj: int | None):
         w = W.srusr_bessel()
     elif name == "srusr_learned":
         w = W.srusr_learned(n_traj=100_000_000, A_init=1.0)
+    elif name == "srusr_2d":
+        w = W.srusr_2d()
     else:
         raise SystemExit(f"unknown workload {name}")
     if n_traj:
@@ -341,6 +350,8 @@ def main() -> int:
     avg_ms = float(np.mean(kernel_ms))
     steps_per_launch = steps_total / args.steps
     flops_step = ALG_FLOPS_PER_STEP[prec] + (ALG_FLOPS_LEARNED_EXTRA[prec] if learned else 0.0)
+    if w.noise == "bessel2d":
+        flops_step = ALG_FLOPS_2D["const" if w.bias_kind else "none"]
     achieved = flops_step * steps_per_launch / (avg_ms * 1e-3) / 1e12
     result = {
         "metric": METRIC,
@@ -358,7 +369,8 @@ def main() -> int:
         "config": {
             "workload": w.name,
             "potential": "piecewise-linear slow roll -> ultra-slow roll, V0=1e-10, eps+=0.01, eps-=1e-8",
-            "noise": f"Bessel-ansatz table, {w.table_n} phi nodes, sigma={w.sigma}",
+            "noise": (f"2D noise, full Bunch-Davies mode at -k eta = {w.sigma}, {w.table_n} phi nodes"
+                      if w.noise == "bessel2d" else f"Bessel-ansatz table, {w.table_n} phi nodes, sigma={w.sigma}"),
             "state": "FP32 pairs + FP64 log-weights" if prec == "fp32" else "FP64",
             "bias": "learned 2-64-64-2 tanh network, tabulated" if learned else f"constant A={w.A_bias:g}",
             "trajectories_per_step": w.n_traj,
@@ -376,7 +388,8 @@ def main() -> int:
             "unit": "TFLOP/s",
             "frac": achieved / PEAK_TFLOPS[prec],
             "traffic": None,
-            "kernel": "em_kernel<FP32 state, const bias, table>" if prec == "fp32" else "em_kernel<FP64>",
+            "kernel": ("em2d_kernel<FP64, 2D noise>" if w.noise == "bessel2d" else
+                       "em_kernel<FP32 state, const bias, table>" if prec == "fp32" else "em_kernel<FP64>"),
             "kernel_ms": avg_ms,
             "flops_per_step": flops_step,
             "int_ops_per_step": ALG_INT_OPS_PER_STEP,

@@ -98,16 +98,28 @@ typedef struct {
 } fpt_potential;
 
 /* Noise as a function of phi (Sec. 3.2/3.4): n nodes phi_j = phi_lo + j h,
- * h = (phi_hi - phi_lo)/(n - 1), with S_j = sqrt(Xi_phiphi) >= 0 and
- * tan_theta_j = Xi_phipi / Xi_phiphi.  Between nodes the values are linearly
+ * h = (phi_hi - phi_lo)/(n - 1).  Between nodes the values are linearly
  * interpolated; outside [phi_lo, phi_hi] the edge node applies.  n == 1 means
  * constant noise (phi_lo, phi_hi ignored).  1 <= n <= FPT_MAX_TABLE.  The host
- * arrays are copied by fpt_create. */
+ * arrays are copied by fpt_create.
+ *   dim 0 or 1 -- 1D noise S (1, tan theta_n) xi (eq. stochastic_eom_1D):
+ *     S_j = sqrt(Xi_phiphi) >= 0, tan_theta_j = Xi_phipi / Xi_phiphi.
+ *   dim 2 -- 2D noise S (xi_1, xi_2) (eq. full_langevin_equation) from the node
+ *     covariances Xi_pp, Xi_pq, Xi_qq (each node zero or positive definite);
+ *     fpt_create takes each node's symmetric square root S and the unit
+ *     principal axis e of Xi (phi component >= 0) and the kernels interpolate
+ *     both.  The bias is B = a S e (the push a along e in noise space; with
+ *     Xi = s s^T it is the 1D bias a s) and dA = a e.xi sqrt(dN) + a^2 |e|^2 dN/2,
+ *     eq. (weight_A) for B = S (a e).  Each step takes two normals: call n >> 1
+ *     of the generator, (u0, u1) for step 2m and (u2, u3) for step 2m + 1.
+ *     Supported with FP64 state and no or constant bias. */
 typedef struct {
     int32_t n;
     double phi_lo, phi_hi;
     const double *S;
     const double *tan_theta;
+    int32_t dim;
+    const double *Xi_pp, *Xi_pq, *Xi_qq;
 } fpt_noise_table;
 
 /* Importance-sampling bias (Sec. 4.1): B_phi = a S, B_pi = tan(theta_n) a S.
@@ -287,6 +299,20 @@ int fpt_mlp_adam(fpt_ctx *ctx, const float *d_grad, double lr, double beta1, dou
  * V <= 0 or nu^2 <= 0 at a node), FPT_EHIP. */
 int fpt_noise_table_bessel(const fpt_potential *pot, double sigma, int32_t n, double phi_lo,
                            double phi_hi, double *S_out, double *tan_out);
+
+/* Fill Xpp_out, Xpq_out, Xqq_out (host arrays of n) with the 2D noise covariance
+ * of eq. (covariance_matrix_direct): the full mode function of eq. (delta_phi_bessel)
+ * with the Bunch-Davies coefficients of eq. (A_k_and_B_k) -- exact for constant nu,
+ * nu(phi) from eq. (nu_squared_approximation) -- and its N-derivative at
+ * -k eta = sigma, H^2 = V(phi)/3:
+ *   Xi = H^2/(2 pi^2) [[|F|^2, Re(F G*)], [., |G|^2]],  F = y^(3/2)(A J_nu + B Y_nu),
+ *   G = -y dF/dy,  y = sigma,
+ * evaluated by the power series of J_nu and J_-nu (Y_nu = (J_nu cos nu pi -
+ * J_-nu)/sin nu pi) on the device.  det Xi = (H^2 sigma^3/(4 pi^2))^2.  Errors:
+ * FPT_EINVAL (n out of 1..FPT_MAX_TABLE, sigma outside (0, 2], V <= 0, nu^2 <= 0
+ * or nu within 1e-3/pi of an integer at a node), FPT_EHIP. */
+int fpt_noise_table_bessel2d(const fpt_potential *pot, double sigma, int32_t n, double phi_lo, double phi_hi,
+                             double *Xpp_out, double *Xpq_out, double *Xqq_out);
 
 /* ---- batches: many problems in one persistent launch ------------------------- */
 

@@ -133,6 +133,100 @@ extern "C" int fpt_noise_table_bessel(const fpt_potential *pot, double sigma, in
 }
 
 // ---------------------------------------------------------------------------
+// 2D noise table kernel: eq. (covariance_matrix_direct) from the full
+// Bunch-Davies mode of eq. (delta_phi_bessel) at -k eta = sigma
+// ---------------------------------------------------------------------------
+struct cplx {
+    double re, im;
+};
+__device__ __forceinline__ cplx cmul(cplx a, cplx b) { return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re}; }
+__device__ __forceinline__ cplx cscale(cplx a, double s) { return {a.re * s, a.im * s}; }
+__device__ __forceinline__ cplx cadd(cplx a, cplx b) { return {a.re + b.re, a.im + b.im}; }
+
+__global__ void table_bessel2d_kernel(int kind, double V0, double phi_T, double Ap, double Am, double sigma, int n,
+                                      double phi_lo, double h, double *Xpp, double *Xpq, double *Xqq, int *bad)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    const double phi = phi_lo + (double)j * h;
+    double V, r1, r2;
+    if (kind == FPT_POT_EXPONENTIAL) {
+        V = V0 * exp(Ap * (phi - phi_T));
+        r1 = Ap;
+        r2 = Ap * Ap;
+    } else {
+        const double A = (phi >= phi_T) ? Ap : Am;
+        V = V0 + A * (phi - phi_T);
+        r1 = A / V;
+        r2 = 0.0;
+    }
+    const double nu2 = 2.25 - 3.0 * (r2 - r1 * r1);
+    const double nu = nu2 > 0.0 ? sqrt(nu2) : 0.0;
+    double sn, cs;
+    sincospi(nu, &sn, &cs);
+    if (!(V > 0.0) || !(nu2 > 0.0) || fabs(sn) < 1e-3) {
+        atomicOr(bad, 1);
+        Xpp[j] = Xpq[j] = Xqq[j] = 0.0;
+        return;
+    }
+    // A_k, B_k of eq. (A_k_and_B_k): sqrt(pi)/2 exp(i (nu + 1/2) pi/2), sqrt(pi)/2 exp(i (nu + 3/2) pi/2)
+    const double hs = 0.5 * sqrt(M_PI);
+    double sa, ca, sb, cb;
+    sincospi(0.5 * (nu + 0.5), &sa, &ca);
+    sincospi(0.5 * (nu + 1.5), &sb, &cb);
+    const cplx Ak = {hs * ca, hs * sa}, Bk = {hs * cb, hs * sb};
+    // y^(3/2) (A J_nu + B Y_nu) = alpha_+ y^(3/2) J_nu + alpha_- y^(3/2) J_-nu
+    const cplx alpha[2] = {cadd(Ak, cscale(Bk, cs / sn)), cscale(Bk, -1.0 / sn)};
+    const double mus[2] = {nu, -nu};
+    cplx F = {0.0, 0.0}, G = {0.0, 0.0};
+    for (int k = 0; k < 2; ++k) {
+        const double mu = mus[k];
+        for (int m = 0; m < 30; ++m) {
+            const double p = 2.0 * m + mu + 1.5;
+            const double term = ((m & 1) ? -1.0 : 1.0) * pow(sigma, p) /
+                                (tgamma((double)m + 1.0) * tgamma((double)m + mu + 1.0) * pow(2.0, 2.0 * m + mu));
+            F = cadd(F, cscale(alpha[k], term));
+            G = cadd(G, cscale(alpha[k], -p * term));
+        }
+    }
+    const double c = (V / 3.0) / (2.0 * M_PI * M_PI);
+    Xpp[j] = c * (F.re * F.re + F.im * F.im);
+    Xpq[j] = c * (F.re * G.re + F.im * G.im);      // Re(F conj(G))
+    Xqq[j] = c * (G.re * G.re + G.im * G.im);
+}
+
+extern "C" int fpt_noise_table_bessel2d(const fpt_potential *pot, double sigma, int32_t n, double phi_lo,
+                                        double phi_hi, double *Xpp_out, double *Xpq_out, double *Xqq_out)
+{
+    int rc = check_potential(pot);
+    if (rc) return rc;
+    if (n < 1 || n > FPT_MAX_TABLE) return fail(FPT_EINVAL, "table size %d out of 1..%d", n, FPT_MAX_TABLE);
+    if (!(sigma > 0.0) || !(sigma <= 2.0)) return fail(FPT_EINVAL, "sigma must lie in (0, 2]");
+    if (!is_finite(phi_lo) || !is_finite(phi_hi) || (n > 1 && !(phi_hi > phi_lo)))
+        return fail(FPT_EINVAL, "need phi_hi > phi_lo");
+    if (!Xpp_out || !Xpq_out || !Xqq_out) return fail(FPT_EINVAL, "output arrays are NULL");
+    const double h = (n > 1) ? (phi_hi - phi_lo) / (double)(n - 1) : 0.0;
+    double *d = nullptr;
+    HIP_TRY(hipMalloc(&d, 3 * sizeof(double) * n + sizeof(int)));
+    int *d_bad = reinterpret_cast<int *>(d + 3 * n);
+    hipError_t e = hipMemset(d_bad, 0, sizeof(int));
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(table_bessel2d_kernel, dim3((n + 255) / 256), dim3(256), 0, 0, pot->kind, pot->V0,
+                           pot->phi_T, pot->A_plus, pot->A_minus, sigma, n, phi_lo, h, d, d + n, d + 2 * n, d_bad);
+        e = hipGetLastError();
+    }
+    int bad = 0;
+    if (e == hipSuccess) e = hipMemcpy(Xpp_out, d, sizeof(double) * n, hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = hipMemcpy(Xpq_out, d + n, sizeof(double) * n, hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = hipMemcpy(Xqq_out, d + 2 * n, sizeof(double) * n, hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = hipMemcpy(&bad, d_bad, sizeof(int), hipMemcpyDeviceToHost);
+    (void)hipFree(d);
+    if (e != hipSuccess) return hip_fail(e, "2D noise table kernel");
+    if (bad) return fail(FPT_EINVAL, "V <= 0, nu^2 <= 0 or nu near an integer at a table node");
+    return FPT_OK;
+}
+
+// ---------------------------------------------------------------------------
 // context
 // ---------------------------------------------------------------------------
 struct fpt_ctx {
@@ -164,6 +258,43 @@ struct fpt_ctx {
 };
 
 static const size_t kGradSlice = size_t(1) << 22;
+
+// Symmetric positive semi-definite square root of [[a, b], [b, c]]:
+// (Xi + sqrt(det) 1)/sqrt(tr + 2 sqrt(det)) (Cayley-Hamilton); zero for Xi = 0.
+static void sym_sqrt2(double a, double b, double c, double &Spp, double &Spq, double &Sqq)
+{
+    const double s = std::sqrt(std::max(a * c - b * b, 0.0));
+    const double t2 = a + c + 2.0 * s;
+    if (t2 == 0.0) {
+        Spp = Spq = Sqq = 0.0;
+        return;
+    }
+    const double t = std::sqrt(t2);
+    Spp = (a + s) / t;
+    Spq = b / t;
+    Sqq = (c + s) / t;
+}
+
+// Unit eigenvector of [[a, b], [b, c]] for its largest eigenvalue, phi component >= 0;
+// (1, 0) when the eigenvalues coincide or the matrix is zero.
+static void principal_axis2(double a, double b, double c, double &e1, double &e2)
+{
+    const double r = std::sqrt(0.25 * (a - c) * (a - c) + b * b);
+    double v1 = a >= c ? 0.5 * (a - c) + r : b;
+    double v2 = a >= c ? b : 0.5 * (c - a) + r;
+    if (v1 < 0.0) {
+        v1 = -v1;
+        v2 = -v2;
+    }
+    const double nrm = std::sqrt(v1 * v1 + v2 * v2);
+    if (nrm == 0.0) {
+        e1 = 1.0;
+        e2 = 0.0;
+        return;
+    }
+    e1 = v1 / nrm;
+    e2 = v2 / nrm;
+}
 
 // V'/V per interval of the noise table for the FP32-state kernels: entry j is
 // (r(phi_j), r(phi_j+1) - r(phi_j)) on the potential branch of interval j, with
@@ -293,11 +424,27 @@ extern "C" int fpt_create(const fpt_potential *pot, const fpt_noise_table *table
     // noise table
     const int nt = table->n;
     if (nt < 1 || nt > FPT_MAX_TABLE) return fail(FPT_EINVAL, "table size %d out of 1..%d", nt, FPT_MAX_TABLE);
-    if (!table->S || !table->tan_theta) return fail(FPT_EINVAL, "table arrays are NULL");
-    for (int i = 0; i < nt; ++i) {
-        if (!is_finite(table->S[i]) || !is_finite(table->tan_theta[i]))
-            return fail(FPT_EINVAL, "table entries must be finite");
-        if (table->S[i] < 0.0) return fail(FPT_EINVAL, "table S must be >= 0");
+    const int dim = table->dim == 2 ? 2 : 1;
+    if (table->dim != 0 && table->dim != 1 && table->dim != 2) return fail(FPT_EINVAL, "table dim must be 1 or 2");
+    if (dim == 1) {
+        if (!table->S || !table->tan_theta) return fail(FPT_EINVAL, "table arrays are NULL");
+        for (int i = 0; i < nt; ++i) {
+            if (!is_finite(table->S[i]) || !is_finite(table->tan_theta[i]))
+                return fail(FPT_EINVAL, "table entries must be finite");
+            if (table->S[i] < 0.0) return fail(FPT_EINVAL, "table S must be >= 0");
+        }
+    } else {
+        if (!table->Xi_pp || !table->Xi_pq || !table->Xi_qq) return fail(FPT_EINVAL, "2D table arrays are NULL");
+        for (int i = 0; i < nt; ++i) {
+            const double a = table->Xi_pp[i], b = table->Xi_pq[i], c = table->Xi_qq[i];
+            if (!is_finite(a) || !is_finite(b) || !is_finite(c)) return fail(FPT_EINVAL, "table entries must be finite");
+            const bool zero = a == 0.0 && b == 0.0 && c == 0.0;
+            if (!zero && !(a > 0.0 && a * c - b * b > 0.0))
+                return fail(FPT_EINVAL, "2D table node %d is neither zero nor positive definite", i);
+        }
+        if (opts && opts->precision != FPT_FP64)
+            return fail(FPT_EUNSUPPORTED, "2D noise is implemented with FP64 state only");
+        if (bias && bias->kind == FPT_BIAS_MLP) return fail(FPT_EUNSUPPORTED, "2D noise takes no learned bias");
     }
     if (nt > 1 && (!is_finite(table->phi_lo) || !is_finite(table->phi_hi) || !(table->phi_hi > table->phi_lo)))
         return fail(FPT_EINVAL, "table needs phi_hi > phi_lo");
@@ -351,7 +498,8 @@ extern "C" int fpt_create(const fpt_potential *pot, const fpt_noise_table *table
     // (nt x float2), cursor, accumulators
     const size_t off_tab32 = sizeof(double) * 2 * nt;
     const size_t off_rtab = off_tab32 + sizeof(float) * 4 * nt;
-    const size_t off_cursor = (off_rtab + sizeof(float) * 2 * nt + 255) & ~size_t(255);
+    const size_t off_tab2d = (off_rtab + sizeof(float) * 2 * nt + 15) & ~size_t(15);
+    const size_t off_cursor = (off_tab2d + (dim == 2 ? sizeof(double) * 6 * nt : 0) + 255) & ~size_t(255);
     const size_t off_acc = off_cursor + 256;
     const size_t total = off_acc + acc_bytes(o.n_bins);
     if (e == hipSuccess) e = hipMalloc(&c->d_mem, total);
@@ -362,7 +510,8 @@ extern "C" int fpt_create(const fpt_potential *pot, const fpt_noise_table *table
     std::vector<double> h64(2 * nt);
     std::vector<float> h32(4 * nt);
     bool all_pos = true;
-    for (int i = 0; i < nt; ++i) {
+    std::vector<double> h2d(dim == 2 ? 6 * (size_t)nt : 0);
+    for (int i = 0; i < nt && dim == 1; ++i) {
         const int k = (i + 1 < nt) ? i + 1 : i;
         h64[2 * i] = table->S[i];
         h64[2 * i + 1] = table->tan_theta[i];
@@ -373,12 +522,22 @@ extern "C" int fpt_create(const fpt_potential *pot, const fpt_noise_table *table
         h32[4 * i + 3] = (float)table->tan_theta[k] - St;
         all_pos = all_pos && table->S[i] > 0.0;
     }
+    for (int i = 0; i < nt && dim == 2; ++i) {
+        const double a = table->Xi_pp[i], b = table->Xi_pq[i], cc = table->Xi_qq[i];
+        double *q = &h2d[6 * (size_t)i];
+        sym_sqrt2(a, b, cc, q[0], q[1], q[2]);
+        principal_axis2(a, b, cc, q[3], q[4]);
+        q[5] = 0.0;
+        all_pos = all_pos && !(a == 0.0 && b == 0.0 && cc == 0.0);
+    }
     unsigned char *base = static_cast<unsigned char *>(c->d_mem);
     e = hipMemcpy(base, h64.data(), sizeof(double) * 2 * nt, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(base + off_tab32, h32.data(), sizeof(float) * 4 * nt, hipMemcpyHostToDevice);
     std::vector<float> hr;
     c->drift_table_used = build_drift_table(*pot, nt, table->phi_lo, table->phi_hi, hr);
     if (e == hipSuccess) e = hipMemcpy(base + off_rtab, hr.data(), sizeof(float) * 2 * nt, hipMemcpyHostToDevice);
+    if (e == hipSuccess && dim == 2)
+        e = hipMemcpy(base + off_tab2d, h2d.data(), sizeof(double) * h2d.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemset(base + off_cursor, 0, 256 + acc_bytes(o.n_bins));
     if (e == hipSuccess) e = hipEventCreate(&c->ev_start);
     if (e == hipSuccess) e = hipEventCreate(&c->ev_stop);
@@ -397,6 +556,8 @@ extern "C" int fpt_create(const fpt_potential *pot, const fpt_noise_table *table
     I.tab64 = reinterpret_cast<const double2 *>(base);
     I.tab32 = reinterpret_cast<const float4 *>(base + off_tab32);
     I.rtab32 = reinterpret_cast<const float2 *>(base + off_rtab);
+    I.noise_dim = dim;
+    I.tab64_2d = reinterpret_cast<const double2 *>(base + off_tab2d);
     I.all_S_pos = all_pos ? 1 : 0;
     I.bias_kind = b.kind;
     I.A = (b.kind == FPT_BIAS_CONST) ? b.A : 0.0;
@@ -418,7 +579,7 @@ extern "C" int fpt_create(const fpt_potential *pot, const fpt_noise_table *table
         }
     }
     const int n_cells = grid_cells(I);
-    size_t need = em_lds_bytes(o.n_bins, nt, o.precision, n_cells);
+    size_t need = dim == 2 ? em2d_lds_bytes(o.n_bins, nt) : em_lds_bytes(o.n_bins, nt, o.precision, n_cells);
     if (b.kind == FPT_BIAS_MLP)
         need = std::max(need, replay_lds_bytes(nt, o.precision, n_cells, c->grid.n0 * c->grid.n1));
     if (need > c->lds_per_block_max) {
@@ -469,14 +630,17 @@ extern "C" int fpt_run(fpt_ctx *c, uint64_t n_traj, double dN, uint64_t seed, ui
     p.cursor = c->cursor;
     const int block = c->opt.block_size ? c->opt.block_size : 1024;
     int grid = 0;
-    const void *fn = em_kernel_ptr(c->precision, c->inst.bias_kind, c->inst.n_tab > 1, c->inst.all_S_pos != 0);
-    int rc = occupancy_grid(fn, block, em_lds_bytes(c->inst.hist.n_bins, c->inst.n_tab, c->precision,
-                                                     grid_cells(c->inst)),
-                            c->cu_count, c->opt.blocks_per_cu, grid);
+    const bool two_d = c->inst.noise_dim == 2;
+    const void *fn = two_d ? em2d_kernel_ptr(c->inst.bias_kind, c->inst.all_S_pos != 0)
+                           : em_kernel_ptr(c->precision, c->inst.bias_kind, c->inst.n_tab > 1, c->inst.all_S_pos != 0);
+    const size_t lds = two_d ? em2d_lds_bytes(c->inst.hist.n_bins, c->inst.n_tab)
+                             : em_lds_bytes(c->inst.hist.n_bins, c->inst.n_tab, c->precision, grid_cells(c->inst));
+    int rc = occupancy_grid(fn, block, lds, c->cu_count, c->opt.blocks_per_cu, grid);
     if (rc) return rc;
     HIP_TRY(zero_words(p.cursor, 1, s));
     HIP_TRY(hipEventRecord(c->ev_start, s));
-    HIP_TRY(em_launch(p, c->precision, grid, block, s));
+    if (two_d) HIP_TRY(em2d_launch(p, grid, block, s));
+    else HIP_TRY(em_launch(p, c->precision, grid, block, s));
     HIP_TRY(hipEventRecord(c->ev_stop, s));
     HIP_TRY(hipEventRecord(c->ev_done, s));
     c->ran = true;
@@ -800,6 +964,7 @@ extern "C" int fpt_batch_create(fpt_ctx *const *ctx, int32_t n_inst, const fpt_b
         if (ctx[i]->device != ctx[0]->device) return fail(FPT_EINVAL, "contexts live on different devices");
         if (ctx[i]->precision != ctx[0]->precision) return fail(FPT_EINVAL, "contexts mix FP64 and FP32 state");
         if (ctx[i]->inst.bias_kind == kBiasMlp) return fail(FPT_EINVAL, "a batch cannot hold a learned bias");
+        if (ctx[i]->inst.noise_dim == 2) return fail(FPT_EINVAL, "a batch cannot hold 2D noise");
     }
     int dev = -1;
     HIP_TRY(hipGetDevice(&dev));

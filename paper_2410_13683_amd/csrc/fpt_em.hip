@@ -788,6 +788,134 @@ __device__ __forceinline__ void lanes_fp32(const Inst &I, const RunArgs &R, cons
 }
 
 // ---------------------------------------------------------------------------
+// FP64 state with 2D noise (eq. full_langevin_equation): two normals per step,
+// noise S (xi_1, xi_2) sqrt(dN) with S the interpolated symmetric square root of
+// the covariance, bias B = a S e with e the interpolated principal axis, and
+// dA = a e.xi sqrt(dN) + a^2 |e|^2 dN / 2, eq. (weight_A) for B = S (a e).  Step
+// n takes call n >> 1 of the generator: (u0, u1) for step 2m, (u2, u3) for
+// 2m + 1, so a group of four steps takes two calls.  The structure (groups,
+// event capture, claims) is that of lanes_fp64.
+// ---------------------------------------------------------------------------
+struct Node2d {
+    double Spp, Spq, Sqq, e1, e2;
+};
+
+__device__ __forceinline__ Node2d lerp_node2d(const double2 *l_tab, int j, double f)
+{
+    const double2 a0 = l_tab[3 * j], a1 = l_tab[3 * j + 1], a2 = l_tab[3 * j + 2];
+    const double2 b0 = l_tab[3 * j + 3], b1 = l_tab[3 * j + 4], b2 = l_tab[3 * j + 5];
+    Node2d n;
+    n.Spp = a0.x + f * (b0.x - a0.x);
+    n.Spq = a0.y + f * (b0.y - a0.y);
+    n.Sqq = a1.x + f * (b1.x - a1.x);
+    n.e1 = a1.y + f * (b1.y - a1.y);
+    n.e2 = a2.x + f * (b2.x - a2.x);
+    return n;
+}
+
+template <int BIAS, bool ALLPOS>
+__device__ __forceinline__ void lanes_fp64_2d(const Inst &I, const RunArgs &R, const double2 *l_tab,
+                                              const RetireTo &rt, unsigned long long *cursor, uint64_t n_traj,
+                                              uint64_t traj_offset)
+{
+    const DriftConsts dk = drift_consts(I);
+    const double dN = R.dN, sqrt_dN = R.sqrt_dN, phi_end = I.phi_end, phi_T = I.phi_T;
+    const double a = (BIAS == kBiasConst) ? I.A : 0.0;
+    const double half_a2_dN = 0.5 * a * a * dN;
+    const double jmax = (double)(staged_nodes(I) - 2);
+    const double s_plus = in_vgpr(dk.s_plus), s_minus = in_vgpr(dk.s_minus);
+
+    bool exhausted = false;
+    uint64_t rel = 0;
+    bool has = claim(true, rel, cursor, n_traj, exhausted);
+    bool live = has;
+    double phi = I.phi_in, pi_ = I.pi_in, lnw = 0.0;
+    uint32_t n = 0;
+
+    // groups of two steps: one Philox call gives both steps' (xi_1, xi_2)
+    auto group = [&](auto censor_tag, const double z[4]) {
+        constexpr bool CENSOR = decltype(censor_tag)::value;
+        bool fresh = false;
+        uint32_t ev_status, ev_n;   // written before use: read only where fresh is set
+        double ev_N, ev_lnw;
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            if (CENSOR && live && n == I.max_steps) {
+                ev_status = kFlagCensored;
+                ev_n = n;
+                ev_N = __builtin_nan("");
+                ev_lnw = lnw;
+                live = false;
+                fresh = true;
+            }
+            const double d = fma(phi, dk.kx, (phi >= phi_T) ? s_plus : s_minus);
+            double r = __builtin_amdgcn_rcp(d);
+            r = fma(r, fma(-d, r, 1.0), r);
+            r = fma(r, fma(-d, r, 1.0), r);
+            const double x = (phi - I.phi_lo) * I.inv_h;
+            const double jf = fmin(fmax(floor(x), 0.0), jmax);
+            const double f = fmin(fmax(x - jf, 0.0), 1.0);
+            const Node2d S = lerp_node2d(l_tab, (int)jf, f);
+            const double z1 = z[2 * j], z2 = z[2 * j + 1];          // xi sqrt(dN)
+            const double noise_phi = S.Spp * z1 + S.Spq * z2;
+            const double noise_pi = S.Spq * z1 + S.Sqq * z2;
+            const double B_phi = a * (S.Spp * S.e1 + S.Spq * S.e2);
+            const double B_pi = a * (S.Spq * S.e1 + S.Sqq * S.e2);
+            const double phi_n = phi + (pi_ + B_phi) * dN + noise_phi;
+            const double pi_n = pi_ - (3.0 - 0.5 * pi_ * pi_) * (pi_ + r) * dN + B_pi * dN + noise_pi;
+            if (BIAS != kBiasNone) {
+                const double dA = a * (S.e1 * z1 + S.e2 * z2) + half_a2_dN * (S.e1 * S.e1 + S.e2 * S.e2);
+                if (ALLPOS) lnw -= dA;
+                else lnw -= (S.Spp != 0.0 || S.Spq != 0.0 || S.Sqq != 0.0) ? dA : 0.0;
+            }
+            const bool crossed = phi_n <= phi_end;
+            const bool ended = 0.5 * pi_n * pi_n >= 1.0;
+            if (live && (crossed || ended)) {
+                ev_status = crossed ? 0u : kFlagEndedEarly;
+                ev_n = n + 1;
+                ev_N = crossed ? (double)n * dN + dN * ((phi - phi_end) / (phi - phi_n)) : (double)(n + 1) * dN;
+                ev_lnw = lnw;
+                live = false;
+                fresh = true;
+            }
+            phi = phi_n;
+            pi_ = pi_n;
+            n += 1;
+        }
+        if (fresh) retire(rt, rel, ev_status, ev_n, ev_N, ev_lnw);
+    };
+
+    while (__any(has)) {
+        for (int k = 0; k < R.chunk; k += 2) {
+            if (!__any(live)) break;
+            const uint64_t traj = traj_offset + rel;
+            uint32_t w[4];
+            philox4x32_10(n >> 1, (uint32_t)traj, (uint32_t)(traj >> 32), I.instance, R.key0, R.key1, w);
+            double z[4];
+            box_muller64(w[0], w[1], sqrt_dN, z[0], z[1]);
+            box_muller64(w[2], w[3], sqrt_dN, z[2], z[3]);
+            if (__any(live && n + 2 > I.max_steps)) group(std::integral_constant<bool, true>(), z);
+            else group(std::integral_constant<bool, false>(), z);
+        }
+        if (!live) has = false;
+        if (claim(!has, rel, cursor, n_traj, exhausted)) {
+            has = true;
+            live = true;
+            phi = I.phi_in;
+            pi_ = I.pi_in;
+            lnw = 0.0;
+            n = 0;
+        }
+    }
+}
+
+__device__ __forceinline__ void stage_table64_2d(const Inst &I, double2 *l_tab)
+{
+    const int n = staged_nodes(I);
+    for (int i = threadIdx.x; i < 3 * n; i += blockDim.x) l_tab[i] = I.tab64_2d[I.n_tab > 1 ? i : i % 3];
+}
+
+// ---------------------------------------------------------------------------
 // LDS layout of the kernels: [accumulators][noise table][control cells][node
 // weights], each part starting on a 16-byte boundary.
 // ---------------------------------------------------------------------------
@@ -853,6 +981,22 @@ __global__ void __launch_bounds__(1024) FPT_EM_OCCUPANCY em_kernel(EmParams p)
         lanes_fp32<BIAS, TAB, ALLPOS, false>(p.inst, p.run, reinterpret_cast<const float4 *>(l_tab),
                                              reinterpret_cast<const float4 *>(l_grid), rt, rp, p.cursor, p.n_traj,
                                              p.traj_offset);
+    __syncthreads();
+    flush_lds_acc(acc, p.inst.acc);
+}
+
+// FP64 state with 2D noise: a persistent grid over one instance.
+template <int BIAS, bool ALLPOS>
+__global__ void __launch_bounds__(1024) FPT_EM_OCCUPANCY em2d_kernel(EmParams p)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const LdsAcc acc = lds_acc(smem, p.inst.hist.n_bins);
+    double2 *l_tab = reinterpret_cast<double2 *>(smem + align16(acc_bytes(p.inst.hist.n_bins)));
+    zero_lds_acc(acc);
+    stage_table64_2d(p.inst, l_tab);
+    __syncthreads();
+    const RetireTo rt = retire_to(p, acc);
+    lanes_fp64_2d<BIAS, ALLPOS>(p.inst, p.run, l_tab, rt, p.cursor, p.n_traj, p.traj_offset);
     __syncthreads();
     flush_lds_acc(acc, p.inst.acc);
 }
@@ -991,6 +1135,30 @@ hipError_t em_launch(const EmParams &p, int precision, int grid, int block, hipS
 {
     const size_t lds = em_lds_bytes(p.inst.hist.n_bins, p.inst.n_tab, precision, grid_cells(p.inst));
     const void *fn = em_kernel_ptr(precision, p.inst.bias_kind, p.inst.n_tab > 1, p.inst.all_S_pos != 0);
+    EmParams pp = p;
+    void *args[] = {&pp};
+    return hipLaunchKernel(fn, dim3(grid), dim3(block), args, lds, stream);
+}
+
+size_t em2d_lds_bytes(int n_bins, int n_tab)
+{
+    return align16(acc_bytes(n_bins)) + (size_t)(n_tab > 1 ? n_tab : 2) * 48;
+}
+
+const void *em2d_kernel_ptr(int bias_kind, bool all_pos)
+{
+    static const void *const t[2][2] = {
+        {reinterpret_cast<const void *>(&em2d_kernel<kBiasNone, false>),
+         reinterpret_cast<const void *>(&em2d_kernel<kBiasNone, true>)},
+        {reinterpret_cast<const void *>(&em2d_kernel<kBiasConst, false>),
+         reinterpret_cast<const void *>(&em2d_kernel<kBiasConst, true>)}};
+    return t[bias_kind == kBiasNone ? 0 : 1][all_pos ? 1 : 0];
+}
+
+hipError_t em2d_launch(const EmParams &p, int grid, int block, hipStream_t stream)
+{
+    const size_t lds = em2d_lds_bytes(p.inst.hist.n_bins, p.inst.n_tab);
+    const void *fn = em2d_kernel_ptr(p.inst.bias_kind, p.inst.all_S_pos != 0);
     EmParams pp = p;
     void *args[] = {&pp};
     return hipLaunchKernel(fn, dim3(grid), dim3(block), args, lds, stream);

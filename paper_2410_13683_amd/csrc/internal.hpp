@@ -49,6 +49,10 @@ struct Inst {
     // potential, or NaN where V'/V must be computed exactly (see fpt_api.hip)
     const float2 *rtab32;
     int32_t all_S_pos;               // every node has S > 0 (the ln w update needs no test)
+    // 2D noise (noise_dim == 2): node j is (S_pp, S_pq), (S_qq, e_phi), (e_pi, 0) -- the symmetric
+    // square root of the node covariance and its unit principal axis
+    int32_t noise_dim;
+    const double2 *tab64_2d;
     int32_t bias_kind;
     double A;
     // learned amplitude tabulated on g_n0 x g_n1 nodes of the normalised inputs;
@@ -120,6 +124,9 @@ size_t replay_lds_bytes(int n_tab, int precision, int n_cells, int n_nodes);
 const void *em_kernel_ptr(int precision, int bias_kind, bool table, bool all_pos);
 hipError_t em_launch(const EmParams &p, int precision, int grid, int block, hipStream_t stream);
 const void *replay_kernel_ptr(int precision, bool all_pos);
+size_t em2d_lds_bytes(int n_bins, int n_tab);
+const void *em2d_kernel_ptr(int bias_kind, bool all_pos);
+hipError_t em2d_launch(const EmParams &p, int grid, int block, hipStream_t stream);
 hipError_t replay_launch(const ReplayParams &p, int precision, int grid, int block, hipStream_t stream);
 const void *batch_kernel_ptr(int precision, int bias_kind, bool all_pos);
 hipError_t batch_launch(int precision, int bias_kind, bool all_pos, const Inst *insts, const WorkItem *items,

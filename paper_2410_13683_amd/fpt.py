@@ -55,7 +55,8 @@ class fpt_potential(ctypes.Structure):
 
 class fpt_noise_table(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int32), ("phi_lo", ctypes.c_double), ("phi_hi", ctypes.c_double),
-                ("S", _dp), ("tan_theta", _dp)]
+                ("S", _dp), ("tan_theta", _dp), ("dim", ctypes.c_int32), ("Xi_pp", _dp), ("Xi_pq", _dp),
+                ("Xi_qq", _dp)]
 
 
 class fpt_bias(ctypes.Structure):
@@ -123,6 +124,8 @@ def load():
     L.fpt_last_error.restype = ctypes.c_char_p
     L.fpt_noise_table_bessel.argtypes = [P(fpt_potential), ctypes.c_double, ctypes.c_int32, ctypes.c_double,
                                          ctypes.c_double, _dp, _dp]
+    L.fpt_noise_table_bessel2d.argtypes = [P(fpt_potential), ctypes.c_double, ctypes.c_int32, ctypes.c_double,
+                                           ctypes.c_double, _dp, _dp, _dp]
     L.fpt_batch_create.argtypes = [P(ctypes.c_void_p), ctypes.c_int32, P(fpt_batch_options), P(ctypes.c_void_p)]
     L.fpt_batch_run.argtypes = [ctypes.c_void_p, _u64p, ctypes.c_double, ctypes.c_uint64, ctypes.c_uint64,
                                 ctypes.c_void_p]
@@ -141,7 +144,7 @@ def load():
     L.fpt_mlp_adam.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                ctypes.c_double, ctypes.c_void_p]
     for name in ("fpt_create", "fpt_run", "fpt_histogram", "fpt_reset", "fpt_last_kernel_ms",
-                 "fpt_noise_table_bessel", "fpt_batch_create", "fpt_batch_run", "fpt_batch_autotune",
+                 "fpt_noise_table_bessel", "fpt_noise_table_bessel2d", "fpt_batch_create", "fpt_batch_run", "fpt_batch_autotune",
                  "fpt_batch_config", "fpt_batch_last_ms", "fpt_mlp_set", "fpt_mlp_get", "fpt_mlp_table",
                  "fpt_mlp_grad", "fpt_mlp_adam"):
         getattr(L, name).restype = ctypes.c_int
@@ -185,19 +188,33 @@ def fpt_noise_table_bessel(pot: fpt_potential, sigma: float, n: int, phi_lo: flo
     return S, t
 
 
+def fpt_noise_table_bessel2d(pot: fpt_potential, sigma: float, n: int, phi_lo: float, phi_hi: float):
+    """2D noise covariance (Xi_pp, Xi_pq, Xi_qq) of eq. (covariance_matrix_direct), device kernel."""
+    X = [np.empty(n, dtype=np.float64) for _ in range(3)]
+    _check(load().fpt_noise_table_bessel2d(ctypes.byref(pot), sigma, n, phi_lo, phi_hi, *[x.ctypes.data_as(_dp) for x in X]),
+           "fpt_noise_table_bessel2d")
+    return tuple(X)
+
+
 class Context:
-    """Owns one fpt_ctx; mirrors fpt_run / fpt_histogram / fpt_reset / fpt_destroy."""
+    """Owns one fpt_ctx; mirrors fpt_run / fpt_histogram / fpt_reset / fpt_destroy.  S, tan_theta give a
+    1D noise table; Xi = (Xi_pp, Xi_pq, Xi_qq) a 2D one (S and tan_theta are then ignored)."""
 
     def __init__(self, pot: fpt_potential, S, tan_theta, phi_lo: float, phi_hi: float, *, bias_kind=FPT_BIAS_NONE,
                  A=0.0, mlp_params=None, norm=(0.0, 1.0, 0.0, 1.0), mlp_every=0, grid_n=(2, 2),
                  grid_range=(-1.0, 1.0, -1.0, 1.0), precision=FPT_FP64,
                  bins_kind=FPT_BINS_LINEAR, n_bins=64, lo=-1.0, hi=1.0, N_ref=0.0, max_steps=FPT_MAX_STEPS,
-                 instance=0, block_size=0, blocks_per_cu=0, chunk=0):
+                 instance=0, block_size=0, blocks_per_cu=0, chunk=0, Xi=None):
         L = load()
-        self._S = np.ascontiguousarray(S, dtype=np.float64)
-        self._t = np.ascontiguousarray(tan_theta, dtype=np.float64)
-        table = fpt_noise_table(len(self._S), phi_lo, phi_hi, self._S.ctypes.data_as(_dp),
-                                self._t.ctypes.data_as(_dp))
+        if Xi is not None:
+            self._X = [np.ascontiguousarray(x, dtype=np.float64) for x in Xi]
+            n_tab = len(self._X[0])
+            table = fpt_noise_table(n_tab, phi_lo, phi_hi, None, None, 2, *[x.ctypes.data_as(_dp) for x in self._X])
+        else:
+            self._S = np.ascontiguousarray(S, dtype=np.float64)
+            self._t = np.ascontiguousarray(tan_theta, dtype=np.float64)
+            table = fpt_noise_table(len(self._S), phi_lo, phi_hi, self._S.ctypes.data_as(_dp),
+                                    self._t.ctypes.data_as(_dp))
         self._mlp = (np.ascontiguousarray(mlp_params, dtype=np.float32) if mlp_params is not None else None)
         bias = fpt_bias(bias_kind, A, self._mlp.ctypes.data_as(_fp) if self._mlp is not None else None,
                         (ctypes.c_double * 4)(*norm), mlp_every, (ctypes.c_int32 * 2)(*grid_n),

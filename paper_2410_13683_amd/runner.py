@@ -16,7 +16,13 @@ def potential_of(w: Workload) -> fpt.fpt_potential:
 
 
 def table_of(w: Workload, pot=None):
-    """(S, tan_theta, phi_lo, phi_hi) of the workload's noise."""
+    """(S, tan_theta, phi_lo, phi_hi) of the workload's noise; for 2D noise S is the tuple
+    (Xi_pp, Xi_pq, Xi_qq) and tan_theta is None."""
+    if w.noise == "xi_const":
+        return tuple(np.array([v]) for v in w.noise_Xi), None, 0.0, 0.0
+    if w.noise == "bessel2d":
+        X = fpt.fpt_noise_table_bessel2d(pot or potential_of(w), w.sigma, w.table_n, w.table_lo, w.table_hi)
+        return X, None, w.table_lo, w.table_hi
     if w.noise == "const":
         return np.array([w.noise_S]), np.array([w.noise_tan]), 0.0, 0.0
     if w.noise == "bessel":
@@ -30,6 +36,11 @@ def context_for(w: Workload, **overrides) -> fpt.Context:
     S, t, lo, hi = table_of(w, pot)
     kw = dict(bias_kind=w.bias_kind, A=w.A_bias, precision=w.precision, bins_kind=w.bins_kind, n_bins=w.n_bins,
               lo=w.lo, hi=w.hi, N_ref=w.N_ref, max_steps=w.max_steps, instance=w.extra.get("instance", 0))
+    if w.bias_kind == 2:
+        kw.update(mlp_params=w.mlp_params, norm=w.mlp_norm, mlp_every=0, grid_n=w.grid_n, grid_range=w.grid_range)
+    if t is None:
+        kw["Xi"] = S
+        S = None
     kw.update(overrides)
     return fpt.Context(pot, S, t, lo, hi, **kw)
 

@@ -70,12 +70,15 @@ class Workload:
     pi_in: float
     phi_end: float
     noise: str                      # "const": S = noise_S, tan = noise_tan (one table node);
-                                    # "bessel": eq. (covariance_constant_nu) table on the grid below
+                                    # "bessel": eq. (covariance_constant_nu) table on the grid below;
+                                    # "xi_const": 2D noise with covariance noise_Xi (one node);
+                                    # "bessel2d": 2D noise of eq. (covariance_matrix_direct) on the grid
     dN: float
     n_traj: int
     seed: int
     noise_S: float = 0.0
     noise_tan: float = 0.0
+    noise_Xi: tuple = (0.0, 0.0, 0.0)   # (Xi_pp, Xi_pq, Xi_qq) for "xi_const"
     sigma: float = 1.0              # coarse-graining ratio k_sigma / aH
     table_n: int = 1
     table_lo: float = 0.0
@@ -219,3 +222,30 @@ def exponential_ig_learned(n_traj: int = 4000, seed: int = 29, dN: float = 2e-3,
     return exponential_ig(n_traj=n_traj, seed=seed, dN=dN).with_(
         name="exponential_ig_learned", bias_kind=BIAS_MLP, mlp_params=params,
         mlp_norm=(0.5, 0.5, math.log(0.5), 1.0), grid_n=tuple(grid_n), grid_range=(-1.05, 1.05, -1.5, 1.5))
+
+
+# ---------------------------------------------------------------------------
+# two-dimensional noise
+# ---------------------------------------------------------------------------
+TABLE2D_N = 2048
+TABLE2D_H = 2.0 ** -15
+TABLE2D_J_T = 1650          # node at phi_T = 0; same range as the 1D grid
+
+
+def srusr_2d(n_traj: int = 1_000_000, seed: int = 6, sigma: float = 0.1, A_bias: float = 0.0) -> Workload:
+    """The SR -> USR problem with 2D noise: the covariance of the full Bunch-Davies mode at
+    -k eta = sigma (eq. covariance_matrix_direct; sigma << 1 as that approach requires) on 2048
+    nodes phi_j = (j - 1650) 2^-15, FP64 state, dN = 1e-4, optional constant bias."""
+    return srusr_bessel(n_traj=n_traj, seed=seed).with_(
+        name=f"srusr_2d_sigma{sigma:g}", noise="bessel2d", sigma=sigma, table_n=TABLE2D_N,
+        table_lo=-TABLE2D_J_T * TABLE2D_H, table_hi=(TABLE2D_N - 1 - TABLE2D_J_T) * TABLE2D_H,
+        bias_kind=BIAS_CONST if A_bias else BIAS_NONE, A_bias=A_bias)
+
+
+def exponential_2d(n_traj: int = 4000, seed: int = 9, S: float = 0.05, rho: float = 0.8, ratio: float = 1.0,
+                   dN: float = 1e-3, A_bias: float = 0.0) -> Workload:
+    """The exponential companion with a constant, correlated 2D noise: Xi = S^2 [[1, rho r], [rho r, r^2]]
+    (r = ratio of the pi to the phi amplitude), acting on phi and pi."""
+    return exponential_ig(n_traj=n_traj, seed=seed, S=S, dN=dN).with_(
+        name="exponential_2d", noise="xi_const", noise_Xi=(S * S, rho * ratio * S * S, ratio * ratio * S * S),
+        bias_kind=BIAS_CONST if A_bias else BIAS_NONE, A_bias=A_bias)

@@ -11,6 +11,11 @@ from paper_2410_13683_amd.workloads import Workload
 
 
 def gpu_table(w: Workload, pot):
+    if w.noise == "xi_const":
+        return tuple(np.array([v]) for v in w.noise_Xi), None, 0.0, 0.0
+    if w.noise == "bessel2d":
+        X = fpt.fpt_noise_table_bessel2d(pot, w.sigma, w.table_n, w.table_lo, w.table_hi)
+        return X, None, w.table_lo, w.table_hi
     if w.noise == "const":
         return np.array([w.noise_S]), np.array([w.noise_tan]), 0.0, 0.0
     S, t = fpt.fpt_noise_table_bessel(pot, w.sigma, w.table_n, w.table_lo, w.table_hi)
@@ -26,6 +31,9 @@ def gpu_context(w: Workload, **kw) -> fpt.Context:
     if w.bias_kind == 2:
         args.update(mlp_params=w.mlp_params, norm=w.mlp_norm, mlp_every=0, grid_n=w.grid_n,
                     grid_range=w.grid_range)
+    if t is None:
+        args["Xi"] = S
+        S = None
     args.update(kw)
     return fpt.Context(pot, S, t, lo, hi, **args)
 

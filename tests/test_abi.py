@@ -93,6 +93,24 @@ def test_invalid_arguments_are_rejected(lib, bad):
     assert lib.fpt_last_error()
 
 
+@pytest.mark.parametrize("case", ["indefinite", "dim3", "fp32", "mlp"])
+def test_2d_table_validation(lib, case):
+    pot = _pot()
+    X = [np.array([1e-12]), np.array([2e-12 if case == "indefinite" else 1e-13]), np.array([1e-12])]
+    tab = fpt.fpt_noise_table(1, 0.0, 0.0, None, None, 3 if case == "dim3" else 2,
+                              *[x.ctypes.data_as(fpt._dp) for x in X])
+    params = np.zeros(fpt.FPT_MLP_NPARAM, dtype=np.float32)
+    bias = fpt.fpt_bias(2 if case == "mlp" else 0, 0.0, params.ctypes.data_as(fpt._fp),
+                        (ctypes.c_double * 4)(0, 1, 0, 1), 0, (ctypes.c_int32 * 2)(4, 4),
+                        (ctypes.c_double * 4)(-1, 1, -1, 1))
+    opts = fpt.fpt_options(1 if case == "fp32" else 0, 0, 8, -1.0, 1.0, 0.0, 1000, 0, 0, 0, 0)
+    h = ctypes.c_void_p()
+    rc = lib.fpt_create(ctypes.byref(pot), ctypes.byref(tab), ctypes.byref(bias), ctypes.byref(opts),
+                        ctypes.byref(h))
+    expect = fpt.FPT_EUNSUPPORTED if case in ("fp32", "mlp") else fpt.FPT_EINVAL
+    assert rc == expect and not h.value, (rc, lib.fpt_last_error())
+
+
 def test_in_loop_network_is_reported_unsupported(lib):
     pot = _pot()
     S = np.array([1e-6])

@@ -1,0 +1,109 @@
+"""GPU parity of the two-dimensional noise path (FP64 state) against the CPU
+oracle through the C ABI: the covariance table of the full Bunch-Davies mode,
+per-trajectory results with and without bias (N within 1e-9 relative, the same
+crossing step, ln w within 1e-9), independence of the launch configuration, the
+full-size workload on sampled trajectories, and the comparison of 1D and 2D
+noise at the same coarse-graining ratio (Sec. 4.2: the 1D noise approximates
+the 2D noise well after the transition)."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+from oracle import oracle as orc  # noqa: E402
+from paper_2410_13683_amd import fpt  # noqa: E402
+from paper_2410_13683_amd import workloads as W  # noqa: E402
+from tests._glue import assert_fp64_parity, oracle_run  # noqa: E402
+from tests._gpu import gpu_run  # noqa: E402
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.mark.parametrize("sigma", [0.01, 0.1, 1.0])
+def test_table2d_matches_oracle(sigma):
+    w = W.srusr_2d(sigma=sigma)
+    say(f"2D table sigma={sigma}")
+    pot = fpt.make_potential(w.kind, w.V0, w.phi_T, w.A_plus, w.A_minus, w.phi_in, w.pi_in, w.phi_end)
+    X = fpt.fpt_noise_table_bessel2d(pot, sigma, w.table_n, w.table_lo, w.table_hi)
+    Xo = orc.noise_table_bessel2d(w.kind, w.V0, w.phi_T, w.A_plus, w.A_minus, sigma, w.table_n, w.table_lo,
+                                  w.table_hi)
+    for k in range(3):
+        np.testing.assert_allclose(X[k], Xo[k], rtol=1e-11, atol=1e-13 * np.abs(Xo[0]).max())
+    # de Sitter: exponential potential
+    pot = fpt.make_potential(1, 1e-10, 0.0, 0.3, 0.0, 1.0, -0.3, 0.0)
+    X = fpt.fpt_noise_table_bessel2d(pot, sigma, 3, -0.5, 0.5)
+    Xo = orc.noise_table_bessel2d(1, 1e-10, 0.0, 0.3, 0.0, sigma, 3, -0.5, 0.5)
+    for k in range(3):
+        np.testing.assert_allclose(X[k], Xo[k], rtol=1e-12, atol=1e-14 * np.abs(Xo[0]).max())
+
+
+@pytest.mark.parametrize("A_bias", [0.0, 1.2])
+def test_fp64_2d_exponential_parity(A_bias):
+    """Constant, strongly correlated 2D noise acting on phi and pi (3000 trajectories: 46 waves and a
+    ragged tail)."""
+    w = W.exponential_2d(n_traj=3000, A_bias=A_bias)
+    say(f"fp64 2D exponential A={A_bias}")
+    gpu, _ = gpu_run(w)
+    ora = oracle_run(w)
+    assert_fp64_parity(gpu, ora)
+    if A_bias:
+        assert np.std(gpu[1]) > 0.1
+
+
+@pytest.mark.parametrize("A_bias", [0.0, 2.0])
+def test_fp64_2d_srusr_parity(A_bias):
+    """SR -> USR with the 2D Bessel table (2048 nodes, sigma = 0.1), 1500 trajectories."""
+    w = W.srusr_2d(n_traj=1500, A_bias=A_bias)
+    say(f"fp64 2D srusr A={A_bias}")
+    gpu, _ = gpu_run(w)
+    ora = oracle_run(w)
+    assert_fp64_parity(gpu, ora)
+
+
+def test_2d_launch_configuration_does_not_change_results():
+    w = W.srusr_2d(n_traj=5000, A_bias=1.0)
+    a, ha = gpu_run(w)
+    b, hb = gpu_run(w, block_size=256, chunk=32)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]) and np.array_equal(a[2], b[2])
+    assert np.array_equal(ha["count"], hb["count"])
+
+
+def test_2d_full_size_sampled():
+    """1e6 trajectories of the 2D SR -> USR workload, checked on trajectories sampled across the range."""
+    w = W.srusr_2d()
+    say(f"fp64 2D full size n={w.n_traj}")
+    (N, lnw, st), hist = gpu_run(w)
+    idx = np.unique(np.concatenate([np.linspace(0, w.n_traj - 1, 100).astype(np.int64), [w.n_traj - 1]]))
+    for i in idx:
+        No, lo_, so = oracle_run(w, n_traj=1, traj_offset=int(i))
+        assert_fp64_parity((N[i:i + 1], lnw[i:i + 1], st[i:i + 1]), (No, lo_, so), max_step_mismatch=1.0)
+    assert hist["n_traj"] == w.n_traj and int(hist["count"].sum()) == w.n_traj
+
+
+def test_1d_and_2d_noise_agree_at_small_sigma():
+    """At sigma = 0.1 the 2D noise (full mode) and the 1D noise (growing mode) give the same P(deltaN) up to
+    the O(sigma^2) gradient correction of the noise amplitude: mean and spread of N within 2 %."""
+    w2 = W.srusr_2d(n_traj=200_000, seed=21)
+    w1 = W.srusr_bessel(n_traj=200_000, seed=22).with_(sigma=0.1)
+    say("1D vs 2D at sigma = 0.1")
+    (N2, _, _), _ = gpu_run(w2)
+    (N1, _, _), _ = gpu_run(w1)
+    d2, d1 = N2 - w2.N_ref, N1 - w1.N_ref
+    say(f"  mean {d1.mean():.4e} / {d2.mean():.4e}; std {d1.std():.4e} / {d2.std():.4e}")
+    assert abs(d2.std() / d1.std() - 1.0) < 0.02
+    assert abs(d2.mean() - d1.mean()) < 0.02 * d1.std()
