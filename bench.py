@@ -119,17 +119,15 @@ def _workload(name: str, n_traj: int | None):
 def cpu_baseline(w, target_s: float = 20.0) -> dict:
     """The CPU oracle, as it stands, on the first trajectories of the same workload."""
     from oracle import oracle as orc
-    from tests._glue import oracle_problem
-    prob = oracle_problem(w)
+    from tests._glue import oracle_run
     threads = orc.max_threads()
     n0 = max(64, threads * 8)
     t0 = time.perf_counter()
-    _, _, st = orc.run(prob, w.dN, w.seed, n0, max_steps=w.max_steps)
+    _, _, st = oracle_run(w, n_traj=n0)
     dt0 = time.perf_counter() - t0
-    steps0 = int((st & orc.STEP_MASK).astype("uint64").sum())
     n1 = int(min(max(n0, n0 * target_s / max(dt0, 1e-3)), 2_000_000))
     t1 = time.perf_counter()
-    _, _, st = orc.run(prob, w.dN, w.seed, n1, traj_offset=n0, max_steps=w.max_steps)
+    _, _, st = oracle_run(w, n_traj=n1, traj_offset=n0)
     dt1 = time.perf_counter() - t1
     steps1 = int((st & orc.STEP_MASK).astype("uint64").sum())
     return {"value": steps1 / dt1, "unit": "trajectory-steps/s", "cores": threads, "kind": "oracle",
