@@ -1033,3 +1033,288 @@ int orc_run2d(int kind, const double pot[4], int n_tab, double phi_lo, double ph
     free(S);
     return 0;
 }
+
+/* ========================================================================= */
+/* Bessel-matched noise table (Sec. 3.4).                                     */
+/* ========================================================================= */
+
+/* J_mu(y) and y dJ_mu/dy by the power series; non-integer mu, y of order 1. */
+static void orc_bessel_j_series(double mu, double y, double *J, double *yJp)
+{
+    double s = 0.0, sd = 0.0;
+    for (int m = 0; m < 40; ++m) {
+        const double p = 2.0 * m + mu;
+        const double c = ((m % 2) ? -1.0 : 1.0) / (tgamma((double)m + 1.0) * tgamma((double)m + mu + 1.0)) *
+                         pow(0.5 * y, p);
+        s += c;
+        sd += p * c;
+    }
+    *J = s;
+    *yJp = sd;
+}
+
+/* Bessel coefficients of eq. (bessel_matching).  The mode is written as       */
+/* delta phi_k = u / pref, u = A J_nu(y) + B Y_nu(y), y = -k eta, pref =        */
+/* a/sqrt(-eta) (eq. delta_phi_bessel).  With d/dN y = -y and d/dN pref =       */
+/* (3/2) pref (de Sitter, epsilon_1 << 1), the two conditions u = pref dphi,    */
+/* du/dN = pref (3/2 dphi + d dphi/dN) give A and B by Cramer's rule.           */
+/* Y_nu = (J_nu cos nu pi - J_-nu) / sin nu pi.  dphi, ddphi, A, B are complex  */
+/* (re, im).                                                                    */
+void orc_bessel_match(double nu, double y, double pref, const double dphi[2], const double ddphi[2], double A[2],
+                      double B[2])
+{
+    double Jn, yJn, Jm, yJm;
+    orc_bessel_j_series(nu, y, &Jn, &yJn);
+    orc_bessel_j_series(-nu, y, &Jm, &yJm);
+    const double sn = sin(M_PI * nu), cn = cos(M_PI * nu);
+    const double Y = (Jn * cn - Jm) / sn, yYp = (yJn * cn - yJm) / sn;
+    const double dJ = -yJn, dY = -yYp;                       /* d/dN of J_nu(y), Y_nu(y) */
+    const double den = Jn * dY - dJ * Y;
+    const double complex f = dphi[0] + I * dphi[1], fp = ddphi[0] + I * ddphi[1];
+    const double complex g = 1.5 * f + fp;                   /* (du/dN) / pref */
+    const double complex a = pref * (f * dY - g * Y) / den;
+    const double complex b = -pref * (f * dJ - g * Jn) / den;
+    A[0] = creal(a); A[1] = cimag(a);
+    B[0] = creal(b); B[1] = cimag(b);
+}
+
+/* Background (phi, pi) and one Fourier mode in e-fold time.  The background    */
+/* follows eq. (klein_gordon) with eq. (Friedmann), H^2 = V/(3 - eps1); the     */
+/* mode follows eq. (full_delta_phi) divided by H^2:                            */
+/*   dphi'' + (3 - eps1) dphi' + [k^2 e^(-2N)/H^2 + V''/H^2 - pi^2 (3 - eps1)   */
+/*            - 2 pi pi'] dphi = 0,                                             */
+/* where the last two terms are a^-3 d/dt(a^3 phidot^2/H) / H^2 and a = e^N.    */
+/* On each side of the kink of the piecewise-linear potential V'' = 0; the      */
+/* kink itself is handled in orc_mode_advance.                                  */
+typedef struct { double phi, pi_, fr, fi, gr, gi; } orc_mode_state;   /* f = dphi, g = d dphi/dN */
+
+/* `upper` evaluates the piecewise-linear potential on its phi >= phi_T branch */
+/* (extended below phi_T), for the step that ends on the kink.                 */
+static void orc_mode_rhs(int kind, const double pot[4], double k, double N, const orc_mode_state *s, int with_mode,
+                         int upper, orc_mode_state *d)
+{
+    double V = orc_V(kind, pot, s->phi), dV = orc_dV(kind, pot, s->phi);
+    if (upper && kind == ORC_POT_PIECEWISE_LINEAR) {
+        V = pot[0] + pot[2] * (s->phi - pot[1]);
+        dV = pot[2];
+    }
+    const double eps1 = 0.5 * s->pi_ * s->pi_;
+    const double dpi = -(3.0 - eps1) * (s->pi_ + dV / V);
+    d->phi = s->pi_;
+    d->pi_ = dpi;
+    if (!with_mode) { d->fr = d->fi = d->gr = d->gi = 0.0; return; }
+    const double H2 = V / (3.0 - eps1);
+    const double d2V = orc_d2V(kind, pot, s->phi);
+    const double mass = k * k * exp(-2.0 * N) / H2 + d2V / H2 - s->pi_ * s->pi_ * (3.0 - eps1) - 2.0 * s->pi_ * dpi;
+    d->fr = s->gr;
+    d->fi = s->gi;
+    d->gr = -(3.0 - eps1) * s->gr - mass * s->fr;
+    d->gi = -(3.0 - eps1) * s->gi - mass * s->fi;
+}
+
+static void orc_mode_axpy(orc_mode_state *o, const orc_mode_state *s, const orc_mode_state *k, double c)
+{
+    o->phi = s->phi + c * k->phi; o->pi_ = s->pi_ + c * k->pi_;
+    o->fr = s->fr + c * k->fr; o->fi = s->fi + c * k->fi;
+    o->gr = s->gr + c * k->gr; o->gi = s->gi + c * k->gi;
+}
+
+/* One classical fourth-order Runge-Kutta step of size h. */
+static void orc_mode_rk4(int kind, const double pot[4], double k, double N, double h, orc_mode_state *s, int with_mode,
+                         int upper)
+{
+    orc_mode_state k1, k2, k3, k4, t;
+    orc_mode_rhs(kind, pot, k, N, s, with_mode, upper, &k1);
+    orc_mode_axpy(&t, s, &k1, 0.5 * h);
+    orc_mode_rhs(kind, pot, k, N + 0.5 * h, &t, with_mode, upper, &k2);
+    orc_mode_axpy(&t, s, &k2, 0.5 * h);
+    orc_mode_rhs(kind, pot, k, N + 0.5 * h, &t, with_mode, upper, &k3);
+    orc_mode_axpy(&t, s, &k3, h);
+    orc_mode_rhs(kind, pot, k, N + h, &t, with_mode, upper, &k4);
+    s->phi += h / 6.0 * (k1.phi + 2.0 * k2.phi + 2.0 * k3.phi + k4.phi);
+    s->pi_ += h / 6.0 * (k1.pi_ + 2.0 * k2.pi_ + 2.0 * k3.pi_ + k4.pi_);
+    s->fr += h / 6.0 * (k1.fr + 2.0 * k2.fr + 2.0 * k3.fr + k4.fr);
+    s->fi += h / 6.0 * (k1.fi + 2.0 * k2.fi + 2.0 * k3.fi + k4.fi);
+    s->gr += h / 6.0 * (k1.gr + 2.0 * k2.gr + 2.0 * k3.gr + k4.gr);
+    s->gi += h / 6.0 * (k1.gi + 2.0 * k2.gi + 2.0 * k3.gi + k4.gi);
+}
+
+/* Advance from N to N_stop in RK4 steps of at most h_max and, with the mode   */
+/* on, at most 1/200 of its oscillation period 2 pi aH/k.  With `kink` set and  */
+/* the piecewise-linear potential, a step that would take phi from above the    */
+/* kink phi_T to at or below it is shortened (by bisection of its size) to end  */
+/* on phi_T, with every stage on the upper branch; there the delta function in V'' = (A_+ - A_-) delta(phi - phi_T)  */
+/* changes d dphi/dN by -(A_+ - A_-) dphi / (H^2 |pi|) (its integral over N,    */
+/* dN = dphi/|pi|), and phi is moved one ulp below phi_T.                      */
+static void orc_mode_advance(int kind, const double pot[4], double k, double *N, double N_stop, orc_mode_state *s,
+                             int with_mode, int kink, double h_max)
+{
+    const double phi_T = pot[1];
+    while (*N < N_stop) {
+        double h = fmin(h_max, N_stop - *N);
+        if (with_mode) {
+            const double aH = exp(*N) * sqrt(orc_V(kind, pot, s->phi) / (3.0 - 0.5 * s->pi_ * s->pi_));
+            h = fmin(h, 2.0 * M_PI * aH / (800.0 * k));
+        }
+        orc_mode_state t = *s;
+        orc_mode_rk4(kind, pot, k, *N, h, &t, with_mode, 0);
+        if (!(kink && kind == ORC_POT_PIECEWISE_LINEAR && s->phi > phi_T && t.phi <= phi_T)) {
+            *s = t;
+            *N += h;
+            continue;
+        }
+        double lo = 0.0, hi = h;
+        for (int it = 0; it < 64; ++it) {
+            const double mid = 0.5 * (lo + hi);
+            orc_mode_state u = *s;
+            orc_mode_rk4(kind, pot, k, *N, mid, &u, with_mode, 1);
+            if (u.phi > phi_T) lo = mid; else hi = mid;
+        }
+        orc_mode_rk4(kind, pot, k, *N, hi, s, with_mode, 1);
+        *N += hi;
+        if (with_mode) {
+            const double H2 = orc_V(kind, pot, phi_T) / (3.0 - 0.5 * s->pi_ * s->pi_);
+            const double kick = -(pot[2] - pot[3]) / (H2 * fabs(s->pi_));
+            s->gr += kick * s->fr;
+            s->gi += kick * s->fi;
+        }
+        s->phi = nextafter(phi_T, -INFINITY);
+    }
+}
+
+/* nu(phi) of eq. (nu_squared_approximation); NaN where nu^2 <= 0. */
+static double orc_nu_approx(int kind, const double pot[4], double phi)
+{
+    const double V = orc_V(kind, pot, phi);
+    const double dVV = orc_dV(kind, pot, phi) / V, d2VV = orc_d2V(kind, pot, phi) / V;
+    const double nu2 = 9.0 / 4.0 - 3.0 * (d2VV - dVV * dVV);
+    return nu2 > 0.0 ? sqrt(nu2) : NAN;
+}
+
+/* Bessel-matched 1D noise table, eq. (covariance_constant_nu_bessel_matched). */
+/* The classical trajectory starts at (phi_start, pi_start) at N = 0.  For each */
+/* node phi_j it reaches, N_sigma is the time it passes phi_j and the mode is   */
+/* k_j = sigma a H there.  That mode starts at the time k_j = 100 a H in the    */
+/* Bunch-Davies state, eq. (bunch_davies) with the first correction of the     */
+/* Hankel function's large-argument expansion, e^(i y) (1 + i c/y) / (a         */
+/* sqrt(2k)), c = (4 nu^2 - 1)/8, y = k/(aH) (overall phase dropped), and is    */
+/* evolved through eq. (full_delta_phi) to N_sigma, where eq. (bessel_matching) */
+/* with nu = nu(phi_j) and -k eta = sigma gives B_k.  The node's noise is the   */
+/* Bunch-Davies table's (eq. covariance_constant_nu) times sqrt(4 |B_k|^2/pi); */
+/* tan theta_n = nu - 3/2 is unchanged.  Nodes the trajectory does not reach    */
+/* keep the factor 1.  The mode of a node below the kink takes the kink's kick; */
+/* that of a node at or above it stops before it.  fac_out[j] = 4 |B_k|^2/pi.   */
+/* Returns 0; -1 on invalid input, on a node reached before its mode can start  */
+/* at k = 100 aH at N >= 0, or on a non-finite result.                         */
+int orc_noise_table_matched(int kind, const double pot[4], double sigma, int n, double phi_lo, double phi_hi,
+                            double phi_start, double pi_start, double *S_out, double *tan_out, double *fac_out,
+                            int n_threads)
+{
+    if (orc_noise_table_bessel(kind, pot, sigma, n, phi_lo, phi_hi, S_out, tan_out) != 0) return -1;
+    if (!(sigma > 0.0) || sigma > 2.0) return -1;
+    const double h = (n > 1) ? (phi_hi - phi_lo) / (double)(n - 1) : 0.0;
+    const double phi_T = pot[1];
+
+    /* classical trajectory, sampled every 1e-4 e-folds, until phi < phi_lo,    */
+    /* eps1 >= 1 or N > 200                                                     */
+    const double hb = 1e-4;
+    size_t cap = (size_t)1 << 16, nb = 0;
+    double *bN = NULL, *bphi = NULL, *bpi = NULL;
+    orc_mode_state s = {phi_start, pi_start, 0.0, 0.0, 0.0, 0.0};
+    double N = 0.0;
+    int fail = 0;
+    for (;;) {
+        if (nb == 0 || nb == cap) {
+            if (nb) cap *= 2;
+            double *a = (double *)realloc(bN, sizeof(double) * cap), *b = a ? (double *)realloc(bphi, sizeof(double) * cap) : NULL;
+            double *c = b ? (double *)realloc(bpi, sizeof(double) * cap) : NULL;
+            if (a) bN = a;
+            if (b) bphi = b;
+            if (c) bpi = c;
+            if (!a || !b || !c) { fail = 1; break; }
+        }
+        bN[nb] = N; bphi[nb] = s.phi; bpi[nb] = s.pi_; ++nb;
+        if (s.phi < phi_lo || 0.5 * s.pi_ * s.pi_ >= 1.0 || N > 200.0) break;
+        orc_mode_advance(kind, pot, 0.0, &N, N + hb, &s, 0, 1, hb);
+    }
+    if (fail) { free(bN); free(bphi); free(bpi); return -1; }
+
+#ifdef _OPENMP
+    if (n_threads > 0) omp_set_num_threads(n_threads);
+#else
+    (void)n_threads;
+#endif
+    int bad = 0;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int j = 0; j < n; ++j) {
+        fac_out[j] = 1.0;
+        const double phi_j = phi_lo + (double)j * h;
+        if (!(bphi[0] > phi_j)) continue;                     /* at or above the start */
+        size_t i = 1;
+        while (i < nb && bphi[i] > phi_j) ++i;
+        if (i >= nb) continue;                                /* never reached */
+        /* N_sigma: root of the cubic Hermite interpolant of phi(N) on [N_{i-1}, N_i] */
+        const double N0 = bN[i - 1], dn = bN[i] - bN[i - 1];
+        const double p0 = bphi[i - 1], p1 = bphi[i], m0 = bpi[i - 1] * dn, m1 = bpi[i] * dn;
+        double t = (p0 - phi_j) / (p0 - p1);
+        for (int it = 0; it < 50; ++it) {
+            const double t2 = t * t, t3 = t2 * t;
+            const double v = (2 * t3 - 3 * t2 + 1) * p0 + (t3 - 2 * t2 + t) * m0 + (-2 * t3 + 3 * t2) * p1 +
+                             (t3 - t2) * m1 - phi_j;
+            const double dv = (6 * t2 - 6 * t) * p0 + (3 * t2 - 4 * t + 1) * m0 + (-6 * t2 + 6 * t) * p1 +
+                              (3 * t2 - 2 * t) * m1;
+            const double step = v / dv;
+            t -= step;
+            if (fabs(step) < 1e-16) break;
+        }
+        const double Ns = N0 + t * dn;
+        const double pis = bpi[i - 1] + t * (bpi[i] - bpi[i - 1]);
+        const double Hs = sqrt(orc_V(kind, pot, phi_j) / (3.0 - 0.5 * pis * pis));
+        const double k = sigma * exp(Ns) * Hs;
+        /* start: the last sample with k >= 100 aH */
+        size_t i0 = 0;
+        {
+            const double aH0 = sqrt(orc_V(kind, pot, bphi[0]) / (3.0 - 0.5 * bpi[0] * bpi[0]));
+            if (k < 100.0 * aH0) {
+#pragma omp atomic write
+                bad = 1;
+                continue;
+            }
+        }
+        while (i0 + 1 < nb) {
+            const double aH = exp(bN[i0 + 1]) * sqrt(orc_V(kind, pot, bphi[i0 + 1]) /
+                                                     (3.0 - 0.5 * bpi[i0 + 1] * bpi[i0 + 1]));
+            if (k < 100.0 * aH) break;
+            ++i0;
+        }
+        orc_mode_state st = {bphi[i0], bpi[i0], 0.0, 0.0, 0.0, 0.0};
+        double Nm = bN[i0];
+        {
+            const double a = exp(Nm);
+            const double y = k / (a * sqrt(orc_V(kind, pot, st.phi) / (3.0 - 0.5 * st.pi_ * st.pi_)));
+            const double nu0 = orc_nu_approx(kind, pot, st.phi);
+            const double c = (4.0 * nu0 * nu0 - 1.0) / 8.0;
+            const double complex F = (1.0 + I * c / y) / (a * sqrt(2.0 * k));
+            /* d/dN [e^(iy) (1 + ic/y) / a] e^(-iy) = [(-1 - iy)(1 + ic/y) + ic/y] / a */
+            const double complex G = ((-1.0 - I * y) * (1.0 + I * c / y) + I * c / y) / (a * sqrt(2.0 * k));
+            st.fr = creal(F); st.fi = cimag(F);
+            st.gr = creal(G); st.gi = cimag(G);
+        }
+        orc_mode_advance(kind, pot, k, &Nm, Ns, &st, 1, phi_j < phi_T, 2.5e-4);
+        const double nu_j = orc_nu_approx(kind, pot, phi_j);
+        const double dphi[2] = {st.fr, st.fi}, ddphi[2] = {st.gr, st.gi};
+        double A[2], B[2];
+        /* a/sqrt(-eta) at -k eta = sigma: e^N sqrt(k/sigma) */
+        orc_bessel_match(nu_j, sigma, exp(Nm) * sqrt(k / sigma), dphi, ddphi, A, B);
+        const double fac = 4.0 * (B[0] * B[0] + B[1] * B[1]) / M_PI;
+        if (!(fac > 0.0) || !isfinite(fac)) {
+#pragma omp atomic write
+            bad = 1;
+            continue;
+        }
+        fac_out[j] = fac;
+        S_out[j] *= sqrt(fac);
+    }
+    free(bN); free(bphi); free(bpi);
+    return bad ? -1 : 0;
+}

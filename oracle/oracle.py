@@ -115,6 +115,12 @@ def lib():
         L.orc_run2d.restype = ctypes.c_int
         L.orc_principal_axis.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_double, dp, dp]
         L.orc_principal_axis.restype = None
+        L.orc_bessel_match.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_double, dp, dp, dp, dp]
+        L.orc_bessel_match.restype = None
+        L.orc_noise_table_matched.argtypes = [ctypes.c_int, dp, ctypes.c_double, ctypes.c_int, ctypes.c_double,
+                                              ctypes.c_double, ctypes.c_double, ctypes.c_double, dp, dp, dp,
+                                              ctypes.c_int]
+        L.orc_noise_table_matched.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -199,6 +205,28 @@ def noise_table_bessel(kind, V0, phi_T, A_plus, A_minus, sigma, n, phi_lo, phi_h
     if rc != 0:
         raise ValueError("invalid noise-table parameters")
     return S, t
+
+
+def bessel_match(nu: float, y: float, pref: float, dphi: complex, ddphi: complex):
+    """(A_k, B_k) of eq. (bessel_matching) from the mode and its N-derivative at -k eta = y, with
+    pref = a/sqrt(-eta)."""
+    f = np.array([dphi.real, dphi.imag]); g = np.array([ddphi.real, ddphi.imag])
+    A = np.zeros(2); B = np.zeros(2)
+    lib().orc_bessel_match(nu, y, pref, _dp(f), _dp(g), _dp(A), _dp(B))
+    return complex(A[0], A[1]), complex(B[0], B[1])
+
+
+def noise_table_matched(kind, V0, phi_T, A_plus, A_minus, sigma, n, phi_lo, phi_hi, phi_start, pi_start,
+                        n_threads: int = 0):
+    """Eq. (covariance_constant_nu_bessel_matched) on the nodes: (S, tan_theta, 4|B_k|^2/pi), with B_k
+    from the mode equation solved along the classical trajectory from (phi_start, pi_start)."""
+    p = np.array([V0, phi_T, A_plus, A_minus], dtype=np.float64)
+    S = np.empty(n); t = np.empty(n); fac = np.empty(n)
+    rc = lib().orc_noise_table_matched(kind, _dp(p), sigma, n, phi_lo, phi_hi, phi_start, pi_start,
+                                       _dp(S), _dp(t), _dp(fac), n_threads)
+    if rc != 0:
+        raise ValueError("invalid matched noise-table parameters (or phi_start too late for a node)")
+    return S, t, fac
 
 
 def run(prob: Problem, dN: float, seed: int, n_traj: int, traj_offset: int = 0, instance: int = 0,
