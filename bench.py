@@ -109,6 +109,8 @@ def _workload(name: str, n_traj: int | None):
         w = W.srusr_learned(n_traj=100_000_000, A_init=1.0)
     elif name == "srusr_2d":
         w = W.srusr_2d()
+    elif name == "srusr_matched":
+        w = W.srusr_is_fp32_matched(A_bias=2.0)
     else:
         raise SystemExit(f"unknown workload {name}")
     if n_traj:
@@ -312,11 +314,14 @@ def main() -> int:
     prec = "fp32" if w.precision == 1 else "fp64"
     stream = torch.cuda.current_stream()
     learned = None
+    table_s = None
     if w.bias_kind == 2:
         learned = train_learned(w, stream)
         ctx = learned.pop("ctx")
     else:
+        t_tab = time.perf_counter()
         ctx = runner.context_for(w)
+        table_s = time.perf_counter() - t_tab
     print(f"[bench] workload {w.name}: {w.n_traj:.3g} trajectories, warmup {args.warmup}, steps {args.steps}",
           file=sys.stderr, flush=True)
     for i in range(args.warmup):
@@ -368,7 +373,9 @@ def main() -> int:
             "workload": w.name,
             "potential": "piecewise-linear slow roll -> ultra-slow roll, V0=1e-10, eps+=0.01, eps-=1e-8",
             "noise": (f"2D noise, full Bunch-Davies mode at -k eta = {w.sigma}, {w.table_n} phi nodes"
-                      if w.noise == "bessel2d" else f"Bessel-ansatz table, {w.table_n} phi nodes, sigma={w.sigma}"),
+                      if w.noise == "bessel2d" else
+                      f"Bessel-matched table (B_k from the mode equation), {w.table_n} phi nodes, sigma={w.sigma}"
+                      if w.noise == "matched" else f"Bessel-ansatz table, {w.table_n} phi nodes, sigma={w.sigma}"),
             "state": "FP32 pairs + FP64 log-weights" if prec == "fp32" else "FP64",
             "bias": "learned 2-64-64-2 tanh network, tabulated" if learned else f"constant A={w.A_bias:g}",
             "trajectories_per_step": w.n_traj,
@@ -379,6 +386,7 @@ def main() -> int:
         "tail": {"deltaN_star": x_star, "P_tail": p_star, "ESS_T": ess_T, "samples_in_T": n_T,
                  "t_5pct_s": (400.0 / ess_rate) if ess_rate > 0 else None},
         "trajectory_steps": steps_total,
+        "table_setup_s": table_s,
         "roofline": {
             "bound": "alu",
             "achieved": achieved,

@@ -314,6 +314,33 @@ int fpt_noise_table_bessel(const fpt_potential *pot, double sigma, int32_t n, do
 int fpt_noise_table_bessel2d(const fpt_potential *pot, double sigma, int32_t n, double phi_lo, double phi_hi,
                              double *Xpp_out, double *Xpq_out, double *Xqq_out);
 
+/* Fill S_out[n], tan_out[n] and, unless NULL, fac_out[n] (host arrays owned by
+ * the caller) with the Bessel-matched noise of eq. (covariance_constant_nu_bessel_matched)
+ * (Sec. 3.4) at the nodes phi_j = phi_lo + j (phi_hi - phi_lo)/(n - 1):
+ *   S_j = S_j^BD sqrt(fac_j),  fac_j = 4 |B_k|^2 / pi,  tan_j = nu(phi_j) - 3/2,
+ * where S_j^BD is fpt_noise_table_bessel's node and B_k comes from the mode that
+ * crosses the coarse-graining scale, k = sigma a H, when the classical trajectory
+ * started at (phi_start, pi_start) at N = 0 passes phi_j: that mode starts at
+ * k = 100 aH in the Bunch-Davies state of eq. (bunch_davies) (with the first
+ * correction of the Hankel function's large-argument expansion), is evolved
+ * through eq. (full_delta_phi) (RK4, FP64; the kink of the piecewise-linear
+ * potential, a delta function in V'', changes d dphi/dN by
+ * -(A_+ - A_-) dphi/(H^2 |pi|)) and is matched by eq. (bessel_matching) with
+ * nu = nu(phi_j) of eq. (nu_squared_approximation) at -k eta = sigma.  In that
+ * matching the N-derivative of (a/sqrt(-eta)) dphi is (a/sqrt(-eta))
+ * (3/2 dphi + d dphi/dN), which reproduces the Bunch-Davies coefficients of
+ * eq. (A_k_and_B_k) from the Bunch-Davies mode.  A node at or above phi_start, or
+ * never reached (the trajectory is followed until phi < phi_lo, eps1 >= 1 or
+ * N > 200), keeps fac = 1.  A node at phi_T takes the mode before the kink.
+ * Computed by device kernels on the current device (a one-thread trajectory
+ * kernel, then one thread per node; about 50 MB of device scratch for the call).
+ * Errors: FPT_EINVAL (n out of 1..FPT_MAX_TABLE, sigma outside (0, 2], V <= 0 or
+ * nu^2 <= 0 at a node, non-finite or eps1 >= 1 start, a reached node whose
+ * mode would start before N = 0 -- start the trajectory earlier -- or whose nu
+ * lies within 1e-3/pi of an integer), FPT_EHIP. */
+int fpt_noise_table_matched(const fpt_potential *pot, double sigma, int32_t n, double phi_lo, double phi_hi,
+                            double phi_start, double pi_start, double *S_out, double *tan_out, double *fac_out);
+
 /* ---- batches: many problems in one persistent launch ------------------------- */
 
 /* Several contexts (each its own potential, noise table, bias amplitude,

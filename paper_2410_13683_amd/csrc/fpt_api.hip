@@ -226,6 +226,46 @@ extern "C" int fpt_noise_table_bessel2d(const fpt_potential *pot, double sigma, 
     return FPT_OK;
 }
 
+// Bessel-matched table: trajectory and mode solves in fpt_table.hip.
+extern "C" int fpt_noise_table_matched(const fpt_potential *pot, double sigma, int32_t n, double phi_lo,
+                                       double phi_hi, double phi_start, double pi_start, double *S_out,
+                                       double *tan_out, double *fac_out)
+{
+    int rc = check_potential(pot);
+    if (rc) return rc;
+    if (n < 1 || n > FPT_MAX_TABLE) return fail(FPT_EINVAL, "table size %d out of 1..%d", n, FPT_MAX_TABLE);
+    if (!(sigma > 0.0) || !(sigma <= 2.0)) return fail(FPT_EINVAL, "sigma must lie in (0, 2]");
+    if (!is_finite(phi_lo) || !is_finite(phi_hi) || (n > 1 && !(phi_hi > phi_lo)))
+        return fail(FPT_EINVAL, "need phi_hi > phi_lo");
+    if (!is_finite(phi_start) || !is_finite(pi_start)) return fail(FPT_EINVAL, "start must be finite");
+    if (!(pot_V(*pot, phi_start) > 0.0)) return fail(FPT_EINVAL, "V(phi_start) must be > 0");
+    if (!(0.5 * pi_start * pi_start < 1.0)) return fail(FPT_EINVAL, "the start needs eps1 = pi^2/2 < 1");
+    if (!S_out || !tan_out) return fail(FPT_EINVAL, "output arrays are NULL");
+    const double h = (n > 1) ? (phi_hi - phi_lo) / (double)(n - 1) : 0.0;
+    const size_t scratch = fpt::matched_scratch_bytes(n);
+    const size_t out_off = (scratch + 255) & ~(size_t)255;
+    char *d = nullptr;
+    HIP_TRY(hipMalloc(&d, out_off + 3 * sizeof(double) * n + sizeof(int)));
+    double *d_S = reinterpret_cast<double *>(d + out_off);
+    int *d_status = reinterpret_cast<int *>(d_S + 3 * n);
+    hipError_t e = hipMemset(d_status, 0, sizeof(int));
+    if (e == hipSuccess)
+        e = fpt::matched_table_launch(pot->kind, pot->V0, pot->phi_T, pot->A_plus, pot->A_minus, sigma, n, phi_lo,
+                                      h, phi_start, pi_start, d, d_S, d_S + n, d_S + 2 * n, d_status, nullptr);
+    int status = 0;
+    if (e == hipSuccess) e = hipMemcpy(S_out, d_S, sizeof(double) * n, hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = hipMemcpy(tan_out, d_S + n, sizeof(double) * n, hipMemcpyDeviceToHost);
+    if (e == hipSuccess && fac_out) e = hipMemcpy(fac_out, d_S + 2 * n, sizeof(double) * n, hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = hipMemcpy(&status, d_status, sizeof(int), hipMemcpyDeviceToHost);
+    (void)hipFree(d);
+    if (e != hipSuccess) return hip_fail(e, "matched noise table kernels");
+    if (status & 1) return fail(FPT_EINVAL, "V <= 0 or nu^2 <= 0 at a table node");
+    if (status & 2) return fail(FPT_EINVAL, "a node is reached before its mode can start at k = 100 aH: start earlier");
+    if (status & 8) return fail(FPT_EINVAL, "nu within 1e-3/pi of an integer at a reached node");
+    if (status & 4) return fail(FPT_EINVAL, "non-finite or zero Bessel coefficient at a node");
+    return FPT_OK;
+}
+
 // ---------------------------------------------------------------------------
 // context
 // ---------------------------------------------------------------------------

@@ -155,4 +155,14 @@ hipError_t mlp_scale_copy(const double *src, double scale, double *dst, size_t n
 hipError_t mlp_adam(float *params, float *m, float *v, const float *grad, int n, double lr, double beta1,
                     double beta2, double eps, double bc1, double bc2, hipStream_t stream);
 
+// Bessel-matched noise table (fpt_table.hip).  Scratch: kMatchCap trajectory samples
+// (N, phi, pi) then n + 1 ints; matched_scratch_bytes(n) bytes.  d_status collects
+// 1 (V <= 0 or nu^2 <= 0 at a node), 2 (a node reached before its mode can start),
+// 4 (non-finite or zero B_k), 8 (nu within 1e-3/pi of an integer at a reached node).
+constexpr int kMatchCap = (1 << 21) + 16;
+size_t matched_scratch_bytes(int n);
+hipError_t matched_table_launch(int kind, double V0, double phi_T, double Ap, double Am, double sigma, int n,
+                                double phi_lo, double h_node, double phi_start, double pi_start, void *scratch,
+                                double *d_S, double *d_tan, double *d_fac, int *d_status, hipStream_t stream);
+
 }  // namespace fpt

@@ -126,6 +126,8 @@ def load():
                                          ctypes.c_double, _dp, _dp]
     L.fpt_noise_table_bessel2d.argtypes = [P(fpt_potential), ctypes.c_double, ctypes.c_int32, ctypes.c_double,
                                            ctypes.c_double, _dp, _dp, _dp]
+    L.fpt_noise_table_matched.argtypes = [P(fpt_potential), ctypes.c_double, ctypes.c_int32, ctypes.c_double,
+                                          ctypes.c_double, ctypes.c_double, ctypes.c_double, _dp, _dp, _dp]
     L.fpt_batch_create.argtypes = [P(ctypes.c_void_p), ctypes.c_int32, P(fpt_batch_options), P(ctypes.c_void_p)]
     L.fpt_batch_run.argtypes = [ctypes.c_void_p, _u64p, ctypes.c_double, ctypes.c_uint64, ctypes.c_uint64,
                                 ctypes.c_void_p]
@@ -144,7 +146,7 @@ def load():
     L.fpt_mlp_adam.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                ctypes.c_double, ctypes.c_void_p]
     for name in ("fpt_create", "fpt_run", "fpt_histogram", "fpt_reset", "fpt_last_kernel_ms",
-                 "fpt_noise_table_bessel", "fpt_noise_table_bessel2d", "fpt_batch_create", "fpt_batch_run", "fpt_batch_autotune",
+                 "fpt_noise_table_bessel", "fpt_noise_table_bessel2d", "fpt_noise_table_matched", "fpt_batch_create", "fpt_batch_run", "fpt_batch_autotune",
                  "fpt_batch_config", "fpt_batch_last_ms", "fpt_mlp_set", "fpt_mlp_get", "fpt_mlp_table",
                  "fpt_mlp_grad", "fpt_mlp_adam"):
         getattr(L, name).restype = ctypes.c_int
@@ -194,6 +196,19 @@ def fpt_noise_table_bessel2d(pot: fpt_potential, sigma: float, n: int, phi_lo: f
     _check(load().fpt_noise_table_bessel2d(ctypes.byref(pot), sigma, n, phi_lo, phi_hi, *[x.ctypes.data_as(_dp) for x in X]),
            "fpt_noise_table_bessel2d")
     return tuple(X)
+
+
+def fpt_noise_table_matched(pot: fpt_potential, sigma: float, n: int, phi_lo: float, phi_hi: float,
+                            phi_start: float, pi_start: float):
+    """(S, tan_theta, 4|B_k|^2/pi) of the Bessel-matched table, eq. (covariance_constant_nu_bessel_matched),
+    along the classical trajectory from (phi_start, pi_start); device kernels."""
+    S = np.empty(n, dtype=np.float64)
+    t = np.empty(n, dtype=np.float64)
+    fac = np.empty(n, dtype=np.float64)
+    _check(load().fpt_noise_table_matched(ctypes.byref(pot), sigma, n, phi_lo, phi_hi, phi_start, pi_start,
+                                          S.ctypes.data_as(_dp), t.ctypes.data_as(_dp), fac.ctypes.data_as(_dp)),
+           "fpt_noise_table_matched")
+    return S, t, fac
 
 
 class Context:

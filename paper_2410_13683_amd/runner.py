@@ -1,7 +1,8 @@
 """Build a library context for a workload description and run it.
 
 Argument marshalling only: the noise table comes from the library's own device
-kernel (fpt_noise_table_bessel) and every trajectory step runs in libfpt.so.
+kernels (fpt_noise_table_bessel, _bessel2d, _matched) and every trajectory step
+runs in libfpt.so.
 """
 from __future__ import annotations
 
@@ -27,6 +28,10 @@ def table_of(w: Workload, pot=None):
         return np.array([w.noise_S]), np.array([w.noise_tan]), 0.0, 0.0
     if w.noise == "bessel":
         S, t = fpt.fpt_noise_table_bessel(pot or potential_of(w), w.sigma, w.table_n, w.table_lo, w.table_hi)
+        return S, t, w.table_lo, w.table_hi
+    if w.noise == "matched":
+        S, t, _ = fpt.fpt_noise_table_matched(pot or potential_of(w), w.sigma, w.table_n, w.table_lo, w.table_hi,
+                                              *w.match_start)
         return S, t, w.table_lo, w.table_hi
     raise ValueError(f"unknown noise kind {w.noise!r}")
 

@@ -72,7 +72,9 @@ class Workload:
     noise: str                      # "const": S = noise_S, tan = noise_tan (one table node);
                                     # "bessel": eq. (covariance_constant_nu) table on the grid below;
                                     # "xi_const": 2D noise with covariance noise_Xi (one node);
-                                    # "bessel2d": 2D noise of eq. (covariance_matrix_direct) on the grid
+                                    # "bessel2d": 2D noise of eq. (covariance_matrix_direct) on the grid;
+                                    # "matched": eq. (covariance_constant_nu_bessel_matched) on the grid,
+                                    # B_k from the classical trajectory started at match_start
     dN: float
     n_traj: int
     seed: int
@@ -80,6 +82,7 @@ class Workload:
     noise_tan: float = 0.0
     noise_Xi: tuple = (0.0, 0.0, 0.0)   # (Xi_pp, Xi_pq, Xi_qq) for "xi_const"
     sigma: float = 1.0              # coarse-graining ratio k_sigma / aH
+    match_start: tuple = (0.0, 0.0)  # (phi, pi) at which the "matched" table's classical trajectory starts
     table_n: int = 1
     table_lo: float = 0.0
     table_hi: float = 0.0
@@ -150,6 +153,27 @@ def srusr_is_fp32(A_bias: float = 2.0, n_traj: int = 100_000_000, seed: int = 3)
     return srusr_bessel(n_traj=n_traj, seed=seed).with_(
         name=f"srusr_is_fp32_A{A_bias:g}", precision=1, bias_kind=BIAS_CONST, A_bias=A_bias,
         bins_kind=BINS_LOG, n_bins=256, lo=0.5 * SIGMA_LIN_SRUSR, hi=8 * SIGMA_LIN_SRUSR)
+
+
+# The matched table's classical trajectory starts 7 e-folds of slow roll above the transition,
+# on the steep branch's attractor, so every node's mode can start at k = 100 aH with sigma = 1.
+MATCH_PHI_START = 1.0
+
+
+def srusr_matched(n_traj: int = 1_000_000, seed: int = 7, sigma: float = 1.0) -> Workload:
+    """The SR -> USR problem with the Bessel-matched noise of eq. (covariance_constant_nu_bessel_matched)
+    on the 4096-node grid: B_k from the mode equation solved along the classical trajectory from
+    phi = 1 (pi = -V'/V there), FP64, dN = 1e-4, no bias."""
+    pi0 = -A_PLUS / (V0 + A_PLUS * MATCH_PHI_START)
+    return srusr_bessel(n_traj=n_traj, seed=seed).with_(
+        name=f"srusr_matched_sigma{sigma:g}", noise="matched", sigma=sigma, match_start=(MATCH_PHI_START, pi0))
+
+
+def srusr_is_fp32_matched(A_bias: float = 2.0, n_traj: int = 100_000_000, seed: int = 3) -> Workload:
+    """srusr_is_fp32 with the Bessel-matched noise table."""
+    m = srusr_matched()
+    return srusr_is_fp32(A_bias=A_bias, n_traj=n_traj, seed=seed).with_(
+        name=f"srusr_is_fp32_matched_A{A_bias:g}", noise="matched", match_start=m.match_start)
 
 
 def batched_instances(n_inst: int = 64, seed: int = 4, n_min: float = 1e5, n_max: float = 1e7,

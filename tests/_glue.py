@@ -19,6 +19,10 @@ def oracle_table(w: Workload):
         S, t = orc.noise_table_bessel(w.kind, w.V0, w.phi_T, w.A_plus, w.A_minus, w.sigma,
                                       w.table_n, w.table_lo, w.table_hi)
         return S, t, w.table_lo, w.table_hi
+    if w.noise == "matched":
+        S, t, _ = orc.noise_table_matched(w.kind, w.V0, w.phi_T, w.A_plus, w.A_minus, w.sigma, w.table_n,
+                                          w.table_lo, w.table_hi, *w.match_start)
+        return S, t, w.table_lo, w.table_hi
     raise ValueError(w.noise)
 
 

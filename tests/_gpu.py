@@ -18,6 +18,9 @@ def gpu_table(w: Workload, pot):
         return X, None, w.table_lo, w.table_hi
     if w.noise == "const":
         return np.array([w.noise_S]), np.array([w.noise_tan]), 0.0, 0.0
+    if w.noise == "matched":
+        S, t, _ = fpt.fpt_noise_table_matched(pot, w.sigma, w.table_n, w.table_lo, w.table_hi, *w.match_start)
+        return S, t, w.table_lo, w.table_hi
     S, t = fpt.fpt_noise_table_bessel(pot, w.sigma, w.table_n, w.table_lo, w.table_hi)
     return S, t, w.table_lo, w.table_hi
 

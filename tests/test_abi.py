@@ -151,3 +151,29 @@ def test_table_generator_rejects_bad_sizes(lib):
 def test_strerror(lib):
     assert lib.fpt_strerror(0) == b"success"
     assert lib.fpt_strerror(fpt.FPT_EINVAL) == b"invalid argument"
+
+
+@pytest.mark.parametrize("case", ["n0", "nbig", "sigma0", "sigma3", "start_nan", "start_eps1", "start_V", "null"])
+def test_matched_table_validation(lib, case):
+    S, t, f = np.zeros(4), np.zeros(4), np.zeros(4)
+    pot = _pot()
+    args = dict(sigma=1.0, n=4, lo=-0.1, hi=0.1, phi_start=1.0, pi_start=-0.1)
+    if case == "n0":
+        args["n"] = 0
+    elif case == "nbig":
+        args["n"] = fpt.FPT_MAX_TABLE + 1
+    elif case == "sigma0":
+        args["sigma"] = 0.0
+    elif case == "sigma3":
+        args["sigma"] = 3.0
+    elif case == "start_nan":
+        args["phi_start"] = float("nan")
+    elif case == "start_eps1":
+        args["pi_start"] = -1.5
+    elif case == "start_V":
+        args["phi_start"] = -1e5
+    outs = (None, None, None) if case == "null" else (S.ctypes.data_as(fpt._dp), t.ctypes.data_as(fpt._dp),
+                                                      f.ctypes.data_as(fpt._dp))
+    rc = lib.fpt_noise_table_matched(ctypes.byref(pot), args["sigma"], args["n"], args["lo"], args["hi"],
+                                     args["phi_start"], args["pi_start"], *outs)
+    assert rc == fpt.FPT_EINVAL
