@@ -5,6 +5,7 @@ exactly 10 e-folds from phi_e at dN = 1e-4) and the noise-free reference
 passage times N_REF_SRUSR and N_REF_LINEAR stored in the workloads module.
 
     python -m oracle.derive_constants
+    python -m oracle.derive_constants --bump     (the Gaussian-bump workload's constants)
 """
 from __future__ import annotations
 
@@ -59,9 +60,81 @@ def hubble_noise() -> float:
     return float(S[0])
 
 
-if __name__ == "__main__":
+if __name__ == "__main__" and "--bump" not in sys.argv:
     print(f"NOISE_S_HUBBLE = {hubble_noise()!r}")
     d = derive_delta_e()
     print(f"DELTA_E = {d!r}")
     print(f"N_REF_SRUSR = {noise_free_N(-d)!r}")
     print(f"N_REF_LINEAR = {linear_N_ref()!r}")
+
+
+# ---------------------------------------------------------------------------
+# Gaussian bump, eq. (potential_swagat)
+# ---------------------------------------------------------------------------
+BUMP = (0.5, 1.17e-3, 1.59e-2)     # m, K, Sigma
+BUMP_PHI0 = 2.18812
+BUMP_PHI_START = 3.2               # on the slow-roll attractor, ~42 e-folds before the transition
+
+
+def _bump_background():
+    """Classical trajectory of the bump from the slow-roll attractor at BUMP_PHI_START (scipy DOP853
+    on eqs. klein_gordon + Friedmann in e-folds, with the oracle's V'/V) until eps1 = 1."""
+    from scipy.integrate import solve_ivp
+
+    def dlnV(p):
+        V, dV, _ = orc.potential(orc.POT_GAUSSIAN_BUMP, 1.0, BUMP_PHI0, 0.0, 0.0, p, bump=BUMP)
+        return dV / V
+
+    def rhs(N, s):
+        return [s[1], -(3.0 - 0.5 * s[1] ** 2) * (s[1] + dlnV(s[0]))]
+
+    end = lambda N, s: 0.5 * s[1] ** 2 - 1.0
+    end.terminal = True
+    sol = solve_ivp(rhs, [0.0, 200.0], [BUMP_PHI_START, -dlnV(BUMP_PHI_START)], events=end, rtol=1e-12,
+                    atol=1e-16, method="DOP853", dense_output=True)
+    return sol, rhs, dlnV
+
+
+def bump_constants():
+    """N_T (first eps2 < -3), the USR interval, the noise window and the CMB-normalised V0."""
+    from scipy.optimize import brentq
+    sol, rhs, dlnV = _bump_background()
+    N_end = float(sol.t_events[0][0])
+
+    def eps2(N):
+        p, q = sol.sol(N)
+        return 2.0 * rhs(N, [p, q])[1] / q
+
+    grid = np.arange(0.0, N_end, 0.01)
+    e2 = np.array([eps2(N) for N in grid])
+    i = int(np.argmax(e2 < -3.0))
+    N_T = brentq(lambda N: eps2(N) + 3.0, grid[i - 1], grid[i], xtol=1e-13)
+    k = i + int(np.argmax(e2[i:] > -3.0))
+    N_usr_end = brentq(lambda N: eps2(N) + 3.0, grid[k - 1], grid[k], xtol=1e-13)
+    # noise window (sigma = 1): from the middle of ultra-slow roll to N_T + 4.7, in the constant-eps2 phase
+    N_lo, N_hi = 0.5 * (N_T + N_usr_end), N_T + 4.7
+    phi_in, pi_in = (float(x) for x in sol.sol(N_lo))
+    phi_lo = float(sol.sol(N_hi)[0])
+    # CMB normalisation P_R = V/(24 pi^2 eps_V) = 2.1e-9 at N_end - 55
+    p_star = float(sol.sol(N_end - 55.0)[0])
+    u = orc.potential(orc.POT_GAUSSIAN_BUMP, 1.0, BUMP_PHI0, 0.0, 0.0, p_star, bump=BUMP)[0]
+    eps_V = 0.5 * dlnV(p_star) ** 2
+    V0 = 2.1e-9 * 24.0 * math.pi ** 2 * eps_V / u
+    return dict(N_T=N_T, N_usr_end=N_usr_end, N_end=N_end, eps2_hi=eps2(N_hi), phi_in=phi_in, pi_in=pi_in,
+                phi_lo=phi_lo, V0=V0, phi_star=p_star)
+
+
+def bump_noise_free_N(c, phi_end: float, dN: float) -> float:
+    p = orc.Problem(kind=orc.POT_GAUSSIAN_BUMP, V0=c["V0"], phi_T=BUMP_PHI0, A_plus=0.0, A_minus=0.0,
+                    phi_in=c["phi_in"], pi_in=c["pi_in"], phi_end=phi_end, S=np.zeros(1), tan_theta=np.zeros(1),
+                    bump=BUMP)
+    N, _, steps = orc.run(p, dN, seed=0, n_traj=1)
+    assert steps[0] & (orc.FLAG_CENSORED | orc.FLAG_ENDED_EARLY) == 0
+    return float(N[0])
+
+
+if __name__ == "__main__" and "--bump" in sys.argv:
+    c = bump_constants()
+    for k_, v_ in c.items():
+        print(f"BUMP_{k_.upper()} = {v_!r}")
+    print(f"BUMP_N_REF = {bump_noise_free_N(c, 2.0, 1e-3)!r}   # phi_end = 2.0, dN = 1e-3")

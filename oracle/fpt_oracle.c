@@ -52,6 +52,7 @@
 
 #define ORC_POT_PIECEWISE_LINEAR 0
 #define ORC_POT_EXPONENTIAL 1
+#define ORC_POT_GAUSSIAN_BUMP 2
 
 #define ORC_BIAS_NONE 0
 #define ORC_BIAS_CONST 1
@@ -132,32 +133,64 @@ void orc_uniforms(uint64_t seed, uint32_t instance, uint64_t traj, uint64_t m, d
 }
 
 /* ------------------------------------------------------------------------- */
-/* Potentials.  pot = {V0, phi_T, A_plus, A_minus}.                           */
+/* Potentials.  pot = {V0, phi_T, A_plus, A_minus, m, K, Sigma}.              */
 /*   piecewise linear, eq. (potential_starobinsky):                           */
 /*       V = V0 + A_+ (phi - phi_T) for phi >= phi_T, V0 + A_- (phi - phi_T)  */
 /*       otherwise (phi == phi_T takes the A_+ branch);                       */
 /*   exponential: V = V0 exp(A_+ (phi - phi_T)), for which V'/V = A_+ exactly */
-/*       and pi = -A_+ is an exact fixed point of the drift.                  */
+/*       and pi = -A_+ is an exact fixed point of the drift;                  */
+/*   Gaussian bump, eq. (potential_swagat):                                   */
+/*       V = V0 u(phi) (1 + g(phi)),  u = phi^2/(m^2 + phi^2),                */
+/*       g = K exp(-x^2/2),  x = (phi - phi_0)/Sigma,  phi_0 = phi_T.         */
 /* ------------------------------------------------------------------------- */
-double orc_V(int kind, const double pot[4], double phi)
+/* u, g and their first two derivatives for the Gaussian bump. */
+static void orc_bump_parts(const double pot[7], double phi, double u[3], double g[3])
+{
+    const double m2 = pot[4] * pot[4], K = pot[5], Sig = pot[6];
+    const double q = m2 + phi * phi;
+    u[0] = phi * phi / q;
+    u[1] = 2.0 * m2 * phi / (q * q);
+    u[2] = 2.0 * m2 * (m2 - 3.0 * phi * phi) / (q * q * q);
+    const double x = (phi - pot[1]) / Sig;
+    g[0] = K * exp(-0.5 * x * x);
+    g[1] = -x / Sig * g[0];
+    g[2] = (x * x - 1.0) / (Sig * Sig) * g[0];
+}
+
+double orc_V(int kind, const double pot[7], double phi)
 {
     const double V0 = pot[0], phi_T = pot[1], Ap = pot[2], Am = pot[3];
     if (kind == ORC_POT_EXPONENTIAL) return V0 * exp(Ap * (phi - phi_T));
+    if (kind == ORC_POT_GAUSSIAN_BUMP) {
+        double u[3], g[3];
+        orc_bump_parts(pot, phi, u, g);
+        return V0 * u[0] * (1.0 + g[0]);
+    }
     if (phi >= phi_T) return V0 + Ap * (phi - phi_T);
     return V0 + Am * (phi - phi_T);
 }
 
-double orc_dV(int kind, const double pot[4], double phi)
+double orc_dV(int kind, const double pot[7], double phi)
 {
     const double phi_T = pot[1], Ap = pot[2], Am = pot[3];
     if (kind == ORC_POT_EXPONENTIAL) return Ap * orc_V(kind, pot, phi);
+    if (kind == ORC_POT_GAUSSIAN_BUMP) {
+        double u[3], g[3];
+        orc_bump_parts(pot, phi, u, g);
+        return pot[0] * (u[1] * (1.0 + g[0]) + u[0] * g[1]);
+    }
     return (phi >= phi_T) ? Ap : Am;
 }
 
-double orc_d2V(int kind, const double pot[4], double phi)
+double orc_d2V(int kind, const double pot[7], double phi)
 {
     const double Ap = pot[2];
     if (kind == ORC_POT_EXPONENTIAL) return Ap * Ap * orc_V(kind, pot, phi);
+    if (kind == ORC_POT_GAUSSIAN_BUMP) {
+        double u[3], g[3];
+        orc_bump_parts(pot, phi, u, g);
+        return pot[0] * (u[2] * (1.0 + g[0]) + 2.0 * u[1] * g[1] + u[0] * g[2]);
+    }
     (void)phi;
     return 0.0; /* linear on each side of phi_T */
 }
@@ -172,7 +205,7 @@ double orc_d2V(int kind, const double pot[4], double phi)
 /* Nodes phi_j = phi_lo + j h, h = (phi_hi - phi_lo)/(n - 1); n == 1 gives a  */
 /* single node at phi_lo.  Returns 0, or -1 on invalid input.                 */
 /* ------------------------------------------------------------------------- */
-int orc_noise_table_bessel(int kind, const double pot[4], double sigma, int n,
+int orc_noise_table_bessel(int kind, const double pot[7], double sigma, int n,
                            double phi_lo, double phi_hi, double *S_out, double *tan_out)
 {
     if (n < 1 || !(sigma > 0.0)) return -1;
@@ -359,7 +392,7 @@ static double orc_grid_eval(const orc_grid *g, const double *a, double x0, doubl
 /* ------------------------------------------------------------------------- */
 typedef struct {
     int kind;
-    double pot[4];
+    double pot[7];
     int n_tab;
     double phi_lo, phi_hi;
     const double *S_tab, *t_tab;
@@ -454,7 +487,7 @@ static void orc_trajectory(const orc_problem *P, uint64_t traj, double *N_out, d
 
 /* Run n_traj trajectories with global indices traj_offset .. traj_offset+n_traj-1.
  * Returns 0, or -1 on invalid input.  n_threads <= 0 uses the OpenMP default. */
-int orc_run(int kind, const double pot[4],
+int orc_run(int kind, const double pot[7],
             int n_tab, double phi_lo, double phi_hi, const double *S_tab, const double *t_tab,
             double phi_in, double pi_in, double phi_end,
             int bias_kind, double A_bias, const float *mlp_params, const double *mlp_norm,
@@ -524,7 +557,7 @@ int orc_max_threads(void)
 /* Only trajectories whose deltaN = N - N_ref lies in [tail_lo, +inf) count.  */
 /* grad_out has 4482 doubles; J_out receives J(theta).                        */
 /* ------------------------------------------------------------------------- */
-int orc_mlp_replay_grad(int kind, const double pot[4],
+int orc_mlp_replay_grad(int kind, const double pot[7],
                         int n_tab, double phi_lo, double phi_hi, const double *S_tab, const double *t_tab,
                         double phi_in, double pi_in, double phi_end,
                         const float *theta_old, const float *theta, const double *mlp_norm,
@@ -625,7 +658,7 @@ int orc_mlp_replay_grad(int kind, const double pot[4],
 /* The grid-node weights G_c are accumulated over paths first and then         */
 /* propagated through the network once per node.                               */
 /* ------------------------------------------------------------------------- */
-int orc_grid_replay_grad(int kind, const double pot[4],
+int orc_grid_replay_grad(int kind, const double pot[7],
                          int n_tab, double phi_lo, double phi_hi, const double *S_tab, const double *t_tab,
                          double phi_in, double pi_in, double phi_end,
                          const float *theta_old, const float *theta, const double *mlp_norm,
@@ -787,7 +820,7 @@ void orc_adam_step(float *theta, float *m, float *v, const float *grad, int n, i
 /* remainder is below 1e-40 of the leading term.  nu and H^2 = V/3 as for the  */
 /* 1D table.                                                                    */
 /* ------------------------------------------------------------------------- */
-int orc_noise_table_bessel2d(int kind, const double pot[4], double sigma, int n, double phi_lo, double phi_hi,
+int orc_noise_table_bessel2d(int kind, const double pot[7], double sigma, int n, double phi_lo, double phi_hi,
                              double *Xpp_out, double *Xpq_out, double *Xqq_out)
 {
     if (n < 1 || !(sigma > 0.0) || sigma > 2.0) return -1;
@@ -862,7 +895,7 @@ void orc_normals2d(uint64_t seed, uint32_t instance, uint64_t traj, uint64_t n0,
 
 typedef struct {
     int kind;
-    double pot[4];
+    double pot[7];
     int n_tab;
     double phi_lo, phi_hi;
     const double *Spp, *Spq, *Sqq;   /* square roots of the node covariances */
@@ -992,7 +1025,7 @@ static void orc_trajectory2d(const orc_problem2d *P, uint64_t traj, double *N_ou
 /* Trajectories traj_offset .. traj_offset + n_traj - 1 with 2D noise given by */
 /* the node covariances Xi (each zero or positive definite).  bias_kind: NONE  */
 /* or CONST.  Returns 0, or -1 on invalid input.                               */
-int orc_run2d(int kind, const double pot[4], int n_tab, double phi_lo, double phi_hi, const double *Xpp,
+int orc_run2d(int kind, const double pot[7], int n_tab, double phi_lo, double phi_hi, const double *Xpp,
               const double *Xpq, const double *Xqq, double phi_in, double pi_in, double phi_end, int bias_kind,
               double A_bias, double dN, uint64_t seed, uint32_t instance, uint64_t traj_offset, uint64_t n_traj,
               int64_t max_steps, double *N_out, double *lnw_out, uint32_t *steps_out, int n_threads)
@@ -1057,25 +1090,32 @@ static void orc_bessel_j_series(double mu, double y, double *J, double *yJp)
 /* delta phi_k = u / pref, u = A J_nu(y) + B Y_nu(y), y = -k eta, pref =        */
 /* a/sqrt(-eta) (eq. delta_phi_bessel).  With d/dN y = -y and d/dN pref =       */
 /* (3/2) pref (de Sitter, epsilon_1 << 1), the two conditions u = pref dphi,    */
-/* du/dN = pref (3/2 dphi + d dphi/dN) give A and B by Cramer's rule.           */
-/* Y_nu = (J_nu cos nu pi - J_-nu) / sin nu pi.  dphi, ddphi, A, B are complex  */
-/* (re, im).                                                                    */
+/* du/dN = pref (3/2 dphi + d dphi/dN) give A and B by Cramer's rule.  Their    */
+/* common denominator J dY/dN - Y dJ/dN is -y W[J_nu, Y_nu](y) = -2/pi, the     */
+/* Wronskian of the Bessel functions, so B needs J_nu only and holds for every */
+/* nu > 0.  A needs Y_nu = (J_nu cos nu pi - J_-nu)/sin nu pi and is NaN where */
+/* |sin nu pi| < 1e-3.  dphi, ddphi, A, B are complex (re, im).                 */
 void orc_bessel_match(double nu, double y, double pref, const double dphi[2], const double ddphi[2], double A[2],
                       double B[2])
 {
-    double Jn, yJn, Jm, yJm;
+    double Jn, yJn;
     orc_bessel_j_series(nu, y, &Jn, &yJn);
-    orc_bessel_j_series(-nu, y, &Jm, &yJm);
-    const double sn = sin(M_PI * nu), cn = cos(M_PI * nu);
-    const double Y = (Jn * cn - Jm) / sn, yYp = (yJn * cn - yJm) / sn;
-    const double dJ = -yJn, dY = -yYp;                       /* d/dN of J_nu(y), Y_nu(y) */
-    const double den = Jn * dY - dJ * Y;
+    const double dJ = -yJn;                                  /* d/dN of J_nu(y) */
+    const double den = -2.0 / M_PI;
     const double complex f = dphi[0] + I * dphi[1], fp = ddphi[0] + I * ddphi[1];
     const double complex g = 1.5 * f + fp;                   /* (du/dN) / pref */
-    const double complex a = pref * (f * dY - g * Y) / den;
     const double complex b = -pref * (f * dJ - g * Jn) / den;
-    A[0] = creal(a); A[1] = cimag(a);
     B[0] = creal(b); B[1] = cimag(b);
+    const double sn = sin(M_PI * nu), cn = cos(M_PI * nu);
+    if (fabs(sn) < 1e-3) {
+        A[0] = A[1] = NAN;
+        return;
+    }
+    double Jm, yJm;
+    orc_bessel_j_series(-nu, y, &Jm, &yJm);
+    const double Y = (Jn * cn - Jm) / sn, dY = -(yJn * cn - yJm) / sn;
+    const double complex a = pref * (f * dY - g * Y) / den;
+    A[0] = creal(a); A[1] = cimag(a);
 }
 
 /* Background (phi, pi) and one Fourier mode in e-fold time.  The background    */
@@ -1090,7 +1130,7 @@ typedef struct { double phi, pi_, fr, fi, gr, gi; } orc_mode_state;   /* f = dph
 
 /* `upper` evaluates the piecewise-linear potential on its phi >= phi_T branch */
 /* (extended below phi_T), for the step that ends on the kink.                 */
-static void orc_mode_rhs(int kind, const double pot[4], double k, double N, const orc_mode_state *s, int with_mode,
+static void orc_mode_rhs(int kind, const double pot[7], double k, double N, const orc_mode_state *s, int with_mode,
                          int upper, orc_mode_state *d)
 {
     double V = orc_V(kind, pot, s->phi), dV = orc_dV(kind, pot, s->phi);
@@ -1120,7 +1160,7 @@ static void orc_mode_axpy(orc_mode_state *o, const orc_mode_state *s, const orc_
 }
 
 /* One classical fourth-order Runge-Kutta step of size h. */
-static void orc_mode_rk4(int kind, const double pot[4], double k, double N, double h, orc_mode_state *s, int with_mode,
+static void orc_mode_rk4(int kind, const double pot[7], double k, double N, double h, orc_mode_state *s, int with_mode,
                          int upper)
 {
     orc_mode_state k1, k2, k3, k4, t;
@@ -1146,7 +1186,7 @@ static void orc_mode_rk4(int kind, const double pot[4], double k, double N, doub
 /* on phi_T, with every stage on the upper branch; there the delta function in V'' = (A_+ - A_-) delta(phi - phi_T)  */
 /* changes d dphi/dN by -(A_+ - A_-) dphi / (H^2 |pi|) (its integral over N,    */
 /* dN = dphi/|pi|), and phi is moved one ulp below phi_T.                      */
-static void orc_mode_advance(int kind, const double pot[4], double k, double *N, double N_stop, orc_mode_state *s,
+static void orc_mode_advance(int kind, const double pot[7], double k, double *N, double N_stop, orc_mode_state *s,
                              int with_mode, int kink, double h_max)
 {
     const double phi_T = pot[1];
@@ -1182,12 +1222,17 @@ static void orc_mode_advance(int kind, const double pot[4], double k, double *N,
     }
 }
 
-/* nu(phi) of eq. (nu_squared_approximation); NaN where nu^2 <= 0. */
-static double orc_nu_approx(int kind, const double pot[4], double phi)
+/* nu^2(phi) of eq. (nu_squared_approximation), and nu (NaN where nu^2 <= 0). */
+static double orc_nu2_approx(int kind, const double pot[7], double phi)
 {
     const double V = orc_V(kind, pot, phi);
     const double dVV = orc_dV(kind, pot, phi) / V, d2VV = orc_d2V(kind, pot, phi) / V;
-    const double nu2 = 9.0 / 4.0 - 3.0 * (d2VV - dVV * dVV);
+    return 9.0 / 4.0 - 3.0 * (d2VV - dVV * dVV);
+}
+
+static double orc_nu_approx(int kind, const double pot[7], double phi)
+{
+    const double nu2 = orc_nu2_approx(kind, pot, phi);
     return nu2 > 0.0 ? sqrt(nu2) : NAN;
 }
 
@@ -1206,7 +1251,7 @@ static double orc_nu_approx(int kind, const double pot[4], double phi)
 /* that of a node at or above it stops before it.  fac_out[j] = 4 |B_k|^2/pi.   */
 /* Returns 0; -1 on invalid input, on a node reached before its mode can start  */
 /* at k = 100 aH at N >= 0, or on a non-finite result.                         */
-int orc_noise_table_matched(int kind, const double pot[4], double sigma, int n, double phi_lo, double phi_hi,
+int orc_noise_table_matched(int kind, const double pot[7], double sigma, int n, double phi_lo, double phi_hi,
                             double phi_start, double pi_start, double *S_out, double *tan_out, double *fac_out,
                             int n_threads)
 {
@@ -1292,8 +1337,7 @@ int orc_noise_table_matched(int kind, const double pot[4], double sigma, int n, 
         {
             const double a = exp(Nm);
             const double y = k / (a * sqrt(orc_V(kind, pot, st.phi) / (3.0 - 0.5 * st.pi_ * st.pi_)));
-            const double nu0 = orc_nu_approx(kind, pot, st.phi);
-            const double c = (4.0 * nu0 * nu0 - 1.0) / 8.0;
+            const double c = (4.0 * orc_nu2_approx(kind, pot, st.phi) - 1.0) / 8.0;
             const double complex F = (1.0 + I * c / y) / (a * sqrt(2.0 * k));
             /* d/dN [e^(iy) (1 + ic/y) / a] e^(-iy) = [(-1 - iy)(1 + ic/y) + ic/y] / a */
             const double complex G = ((-1.0 - I * y) * (1.0 + I * c / y) + I * c / y) / (a * sqrt(2.0 * k));

@@ -26,6 +26,7 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 
 POT_PIECEWISE_LINEAR = 0
 POT_EXPONENTIAL = 1
+POT_GAUSSIAN_BUMP = 2
 BIAS_NONE = 0
 BIAS_CONST = 1
 BIAS_MLP = 2
@@ -185,20 +186,26 @@ class Problem:
     mlp_every: int = 1                # >= 1: the network every k steps; 0: the tabulated network
     grid_n: tuple = (2, 2)            # tabulation grid over the normalised inputs (x0, x1)
     grid_range: tuple = (-1.0, 1.0, -1.0, 1.0)
+    bump: tuple = (0.0, 0.0, 0.0)     # (m, K, Sigma) of the Gaussian bump (phi_0 = phi_T)
 
     def pot(self) -> np.ndarray:
-        return np.array([self.V0, self.phi_T, self.A_plus, self.A_minus], dtype=np.float64)
+        return _pot_array(self.V0, self.phi_T, self.A_plus, self.A_minus, self.bump)
 
 
-def potential(kind, V0, phi_T, A_plus, A_minus, phi):
-    p = np.array([V0, phi_T, A_plus, A_minus], dtype=np.float64)
+def _pot_array(V0, phi_T, A_plus, A_minus, bump=(0.0, 0.0, 0.0)) -> np.ndarray:
+    """{V0, phi_T, A_plus, A_minus, m, K, Sigma}, the oracle's potential parameters."""
+    return np.array([V0, phi_T, A_plus, A_minus, *bump], dtype=np.float64)
+
+
+def potential(kind, V0, phi_T, A_plus, A_minus, phi, bump=(0.0, 0.0, 0.0)):
+    p = _pot_array(V0, phi_T, A_plus, A_minus, bump)
     L = lib()
     return L.orc_V(kind, _dp(p), phi), L.orc_dV(kind, _dp(p), phi), L.orc_d2V(kind, _dp(p), phi)
 
 
-def noise_table_bessel(kind, V0, phi_T, A_plus, A_minus, sigma, n, phi_lo, phi_hi):
+def noise_table_bessel(kind, V0, phi_T, A_plus, A_minus, sigma, n, phi_lo, phi_hi, bump=(0.0, 0.0, 0.0)):
     """Eq. (covariance_constant_nu) with nu(phi) from eq. (nu_squared_approximation)."""
-    p = np.array([V0, phi_T, A_plus, A_minus], dtype=np.float64)
+    p = _pot_array(V0, phi_T, A_plus, A_minus, bump)
     S = np.empty(n, dtype=np.float64)
     t = np.empty(n, dtype=np.float64)
     rc = lib().orc_noise_table_bessel(kind, _dp(p), sigma, n, phi_lo, phi_hi, _dp(S), _dp(t))
@@ -217,10 +224,10 @@ def bessel_match(nu: float, y: float, pref: float, dphi: complex, ddphi: complex
 
 
 def noise_table_matched(kind, V0, phi_T, A_plus, A_minus, sigma, n, phi_lo, phi_hi, phi_start, pi_start,
-                        n_threads: int = 0):
+                        n_threads: int = 0, bump=(0.0, 0.0, 0.0)):
     """Eq. (covariance_constant_nu_bessel_matched) on the nodes: (S, tan_theta, 4|B_k|^2/pi), with B_k
     from the mode equation solved along the classical trajectory from (phi_start, pi_start)."""
-    p = np.array([V0, phi_T, A_plus, A_minus], dtype=np.float64)
+    p = _pot_array(V0, phi_T, A_plus, A_minus, bump)
     S = np.empty(n); t = np.empty(n); fac = np.empty(n)
     rc = lib().orc_noise_table_matched(kind, _dp(p), sigma, n, phi_lo, phi_hi, phi_start, pi_start,
                                        _dp(S), _dp(t), _dp(fac), n_threads)
@@ -350,12 +357,12 @@ class Problem2D:
     A_bias: float = 0.0
 
     def pot(self) -> np.ndarray:
-        return np.array([self.V0, self.phi_T, self.A_plus, self.A_minus], dtype=np.float64)
+        return _pot_array(self.V0, self.phi_T, self.A_plus, self.A_minus)
 
 
-def noise_table_bessel2d(kind, V0, phi_T, A_plus, A_minus, sigma, n, phi_lo, phi_hi):
+def noise_table_bessel2d(kind, V0, phi_T, A_plus, A_minus, sigma, n, phi_lo, phi_hi, bump=(0.0, 0.0, 0.0)):
     """(Xi_pp, Xi_pq, Xi_qq) at the nodes: both homogeneous modes of eq. (bessel_matched_homogeneous)."""
-    p = np.array([V0, phi_T, A_plus, A_minus], dtype=np.float64)
+    p = _pot_array(V0, phi_T, A_plus, A_minus, bump)
     X = [np.empty(n, dtype=np.float64) for _ in range(3)]
     rc = lib().orc_noise_table_bessel2d(kind, _dp(p), sigma, n, phi_lo, phi_hi, *[_dp(x) for x in X])
     if rc != 0:

@@ -28,6 +28,7 @@ import numpy as np
 
 POT_PIECEWISE_LINEAR = 0
 POT_EXPONENTIAL = 1
+POT_GAUSSIAN_BUMP = 2
 BIAS_NONE = 0
 BIAS_CONST = 1
 BIAS_MLP = 2
@@ -83,6 +84,8 @@ class Workload:
     noise_Xi: tuple = (0.0, 0.0, 0.0)   # (Xi_pp, Xi_pq, Xi_qq) for "xi_const"
     sigma: float = 1.0              # coarse-graining ratio k_sigma / aH
     match_start: tuple = (0.0, 0.0)  # (phi, pi) at which the "matched" table's classical trajectory starts
+    noise_cut_below: bool = False    # the table's lowest node carries no noise: none below the table
+    bump: tuple = (0.0, 0.0, 0.0)    # (m, K, Sigma) of the Gaussian bump (centre phi_0 = phi_T)
     table_n: int = 1
     table_lo: float = 0.0
     table_hi: float = 0.0
@@ -174,6 +177,46 @@ def srusr_is_fp32_matched(A_bias: float = 2.0, n_traj: int = 100_000_000, seed: 
     m = srusr_matched()
     return srusr_is_fp32(A_bias=A_bias, n_traj=n_traj, seed=seed).with_(
         name=f"srusr_is_fp32_matched_A{A_bias:g}", noise="matched", match_start=m.match_start)
+
+
+# Gaussian bump, eq. (potential_swagat), with the paper's K, m, Sigma and phi_0.  Written by
+# `python -m oracle.derive_constants --bump` (oracle potential, scipy background from phi = 3.2
+# on the slow-roll attractor): the transition N_T (first eps2 < -3) is 42.1417 e-folds after
+# phi = 3.2 and ultra-slow roll ends at 44.5506.  The noise acts (sigma = 1) from the middle of
+# ultra-slow roll, N = 43.346 (phi_in, pi_in), to N_T + 4.7 (BUMP_PHI_LO), where eps2 = 0.7316 in
+# the constant-eps2 phase.  V0 is set by P_R = V/(24 pi^2 eps_V) = 2.1e-9 at 55 e-folds before eps1 = 1.
+BUMP = (0.5, 1.17e-3, 1.59e-2)
+BUMP_PHI0 = 2.18812
+BUMP_V0 = 8.885867165645307e-11
+BUMP_PHI_IN = 2.2034255935977227
+BUMP_PI_IN = -0.0010119120161906673
+BUMP_PHI_LO = 2.20304329338396
+BUMP_EPS2 = 0.7316306386485752      # eps2 at N_T + 4.7 (the last mode's coarse-graining crossing)
+BUMP_PHI_END = 2.0                  # on the slow-roll attractor again, ~16 e-folds after phi_in
+BUMP_N_REF = 16.010232287737356     # noise-free passage to BUMP_PHI_END at dN = 1e-3
+BUMP_MATCH_START = 2.5              # the matched table's classical trajectory starts here
+
+
+def gaussian_bump(n_traj: int = 1_000_000, seed: int = 11, A_bias: float = 0.0, dN: float = 1e-3) -> Workload:
+    """The Gaussian-bump model of eq. (potential_swagat) (K = 1.17e-3, m = 0.5, Sigma = 1.59e-2,
+    phi_0 = 2.18812), FP64 state.  Bessel-matched noise (sigma = 1) on 4096 nodes over the window
+    [BUMP_PHI_LO, BUMP_PHI_IN]; none below it.  From (phi_in, pi_in) on the classical trajectory to
+    phi_end = 2.0; constant bias A_bias.  64 linear bins over deltaN in [-0.5, 1.5)."""
+    dlnV0 = 2 * 0.25 / (BUMP_MATCH_START * (0.25 + BUMP_MATCH_START ** 2))   # V'/V at phi = 2.5 (bump ~ 0)
+    return Workload(
+        name=f"gaussian_bump_A{A_bias:g}", kind=POT_GAUSSIAN_BUMP, V0=BUMP_V0, phi_T=BUMP_PHI0, A_plus=0.0,
+        A_minus=0.0, phi_in=BUMP_PHI_IN, pi_in=BUMP_PI_IN, phi_end=BUMP_PHI_END, noise="matched", sigma=1.0,
+        table_n=TABLE_N, table_lo=BUMP_PHI_LO, table_hi=BUMP_PHI_IN, match_start=(BUMP_MATCH_START, -dlnV0),
+        noise_cut_below=True, bump=BUMP, dN=dN, n_traj=n_traj, seed=seed,
+        bias_kind=BIAS_CONST if A_bias else BIAS_NONE, A_bias=A_bias, bins_kind=BINS_LINEAR, n_bins=64,
+        lo=-0.5, hi=1.5, N_ref=BUMP_N_REF)
+
+
+def gaussian_bump_is(A_bias: float = 3.0, n_traj: int = 10_000_000, seed: int = 12) -> Workload:
+    """gaussian_bump with a constant bias and 96 log-spaced bins over deltaN in [0.02, 3): the far
+    tail, where the classical constant-eps2 form of eq. (delta_N_pdf_constant_epsilon_2) applies."""
+    return gaussian_bump(n_traj=n_traj, seed=seed, A_bias=A_bias).with_(
+        name=f"gaussian_bump_is_A{A_bias:g}", bins_kind=BINS_LOG, n_bins=96, lo=0.02, hi=3.0)
 
 
 def batched_instances(n_inst: int = 64, seed: int = 4, n_min: float = 1e5, n_max: float = 1e7,

@@ -17,11 +17,13 @@ def oracle_table(w: Workload):
         return np.array([w.noise_S]), np.array([w.noise_tan]), 0.0, 0.0
     if w.noise == "bessel":
         S, t = orc.noise_table_bessel(w.kind, w.V0, w.phi_T, w.A_plus, w.A_minus, w.sigma,
-                                      w.table_n, w.table_lo, w.table_hi)
+                                      w.table_n, w.table_lo, w.table_hi, bump=w.bump)
         return S, t, w.table_lo, w.table_hi
     if w.noise == "matched":
         S, t, _ = orc.noise_table_matched(w.kind, w.V0, w.phi_T, w.A_plus, w.A_minus, w.sigma, w.table_n,
-                                          w.table_lo, w.table_hi, *w.match_start)
+                                          w.table_lo, w.table_hi, *w.match_start, bump=w.bump)
+        if w.noise_cut_below:
+            S[0] = 0.0
         return S, t, w.table_lo, w.table_hi
     raise ValueError(w.noise)
 
@@ -34,7 +36,7 @@ def oracle_problem(w: Workload, mlp_params=None, mlp_norm=None) -> orc.Problem:
     p = orc.Problem(kind=w.kind, V0=w.V0, phi_T=w.phi_T, A_plus=w.A_plus, A_minus=w.A_minus,
                     phi_in=w.phi_in, pi_in=w.pi_in, phi_end=w.phi_end, S=S, tan_theta=t,
                     phi_lo=lo, phi_hi=hi, bias_kind=w.bias_kind, A_bias=w.A_bias,
-                    mlp_params=mlp_params, mlp_norm=mlp_norm)
+                    mlp_params=mlp_params, mlp_norm=mlp_norm, bump=w.bump)
     if mlp_params is None and w.mlp_params is not None:
         p.mlp_params = np.ascontiguousarray(w.mlp_params, dtype=np.float32)
         p.mlp_norm = np.asarray(w.mlp_norm, dtype=np.float64)
