@@ -63,6 +63,10 @@ ALG_FLOPS_LEARNED_EXTRA = {"fp32": 31.0, "fp64": 31.0}
 # table entries (23), the 2x2 noise product (6), the update (12), events (4); a constant bias adds
 # B = a S e (8) and dA (10)
 ALG_FLOPS_2D = {"none": 71.0, "const": 89.0}
+# the Gaussian bump's V'/V (FP64): x, x^2/2, exp, K g, phi (m^2 + phi^2), Sigma (1 + g), the
+# numerator 2 m^2 d2 - x g d1, the denominator and an IEEE division (reciprocal, two Newton steps and
+# the correction) = 28 FLOPs in place of the linear potentials' 13
+ALG_FLOPS_BUMP_FP64 = 58.5 - 13.0 + 28.0
 ALG_INT_OPS_PER_STEP = 16.0          # Philox4x32-10 amortised over 4 steps + uniform conversions
 PEAK_TFLOPS = {"fp32": 157.3, "fp64": 78.6}   # MI355X published vector peaks
 PEAK_HBM_GBS = 8000.0
@@ -111,6 +115,8 @@ def _workload(name: str, n_traj: int | None):
         w = W.srusr_2d()
     elif name == "srusr_matched":
         w = W.srusr_is_fp32_matched(A_bias=2.0)
+    elif name == "bump":
+        w = W.gaussian_bump_is(A_bias=3.0)
     else:
         raise SystemExit(f"unknown workload {name}")
     if n_traj:
@@ -119,17 +125,25 @@ def _workload(name: str, n_traj: int | None):
 
 
 def cpu_baseline(w, target_s: float = 20.0) -> dict:
-    """The CPU oracle, as it stands, on the first trajectories of the same workload."""
+    """The CPU oracle, as it stands, on the first trajectories of the same workload (its noise table
+    built once, outside the timing)."""
     from oracle import oracle as orc
-    from tests._glue import oracle_run
+    from tests._glue import oracle_problem, oracle_problem2d
     threads = orc.max_threads()
+    kw = dict(instance=w.extra.get("instance", 0), max_steps=w.max_steps)
+    if w.noise in ("xi_const", "bessel2d"):
+        p2 = oracle_problem2d(w)
+        run = lambda n, off: orc.run2d(p2, w.dN, w.seed, n, traj_offset=off, **kw)
+    else:
+        p1 = oracle_problem(w)
+        run = lambda n, off: orc.run(p1, w.dN, w.seed, n, traj_offset=off, **kw)
     n0 = max(64, threads * 8)
     t0 = time.perf_counter()
-    _, _, st = oracle_run(w, n_traj=n0)
+    _, _, st = run(n0, 0)
     dt0 = time.perf_counter() - t0
     n1 = int(min(max(n0, n0 * target_s / max(dt0, 1e-3)), 2_000_000))
     t1 = time.perf_counter()
-    _, _, st = oracle_run(w, n_traj=n1, traj_offset=n0)
+    _, _, st = run(n1, n0)
     dt1 = time.perf_counter() - t1
     steps1 = int((st & orc.STEP_MASK).astype("uint64").sum())
     return {"value": steps1 / dt1, "unit": "trajectory-steps/s", "cores": threads, "kind": "oracle",
@@ -355,6 +369,8 @@ def main() -> int:
     flops_step = ALG_FLOPS_PER_STEP[prec] + (ALG_FLOPS_LEARNED_EXTRA[prec] if learned else 0.0)
     if w.noise == "bessel2d":
         flops_step = ALG_FLOPS_2D["const" if w.bias_kind else "none"]
+    if w.kind == 2:
+        flops_step = ALG_FLOPS_BUMP_FP64
     achieved = flops_step * steps_per_launch / (avg_ms * 1e-3) / 1e12
     result = {
         "metric": METRIC,
@@ -371,7 +387,9 @@ def main() -> int:
         "data": "synthetic",
         "config": {
             "workload": w.name,
-            "potential": "piecewise-linear slow roll -> ultra-slow roll, V0=1e-10, eps+=0.01, eps-=1e-8",
+            "potential": ("Gaussian bump, K=1.17e-3, m=0.5, Sigma=1.59e-2, phi0=2.18812, CMB-normalised V0"
+                          if w.kind == 2 else
+                          "piecewise-linear slow roll -> ultra-slow roll, V0=1e-10, eps+=0.01, eps-=1e-8"),
             "noise": (f"2D noise, full Bunch-Davies mode at -k eta = {w.sigma}, {w.table_n} phi nodes"
                       if w.noise == "bessel2d" else
                       f"Bessel-matched table (B_k from the mode equation), {w.table_n} phi nodes, sigma={w.sigma}"
@@ -395,6 +413,7 @@ def main() -> int:
             "frac": achieved / PEAK_TFLOPS[prec],
             "traffic": None,
             "kernel": ("em2d_kernel<FP64, 2D noise>" if w.noise == "bessel2d" else
+                       "em_kernel<FP64, Gaussian bump>" if w.kind == 2 else
                        "em_kernel<FP32 state, const bias, table>" if prec == "fp32" else "em_kernel<FP64>"),
             "kernel_ms": avg_ms,
             "flops_per_step": flops_step,

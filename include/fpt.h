@@ -68,7 +68,7 @@ enum {
 };
 
 /* ---- enumerations ---------------------------------------------------------- */
-enum { FPT_POT_PIECEWISE_LINEAR = 0, FPT_POT_EXPONENTIAL = 1 };
+enum { FPT_POT_PIECEWISE_LINEAR = 0, FPT_POT_EXPONENTIAL = 1, FPT_POT_GAUSSIAN_BUMP = 2 };
 enum { FPT_BIAS_NONE = 0, FPT_BIAS_CONST = 1, FPT_BIAS_MLP = 2 };
 enum { FPT_FP64 = 0, FPT_FP32_STATE = 1 };
 enum { FPT_BINS_LINEAR = 0, FPT_BINS_LOG = 1 };
@@ -85,16 +85,24 @@ enum { FPT_BINS_LINEAR = 0, FPT_BINS_LOG = 1 };
 
 /* ---- inputs ---------------------------------------------------------------- */
 
-/* Potential and the start / end of the trajectories (eq. potential_starobinsky).
- *   PIECEWISE_LINEAR: V = V0 + A_plus (phi - phi_T) for phi >= phi_T,
- *                     V0 + A_minus (phi - phi_T) for phi < phi_T.
+/* Potential and the start / end of the trajectories.
+ *   PIECEWISE_LINEAR: eq. (potential_starobinsky), V = V0 + A_plus (phi - phi_T)
+ *                     for phi >= phi_T, V0 + A_minus (phi - phi_T) for phi < phi_T.
  *   EXPONENTIAL:      V = V0 exp(A_plus (phi - phi_T)), so V'/V = A_plus everywhere
  *                     (A_minus unused).
+ *   GAUSSIAN_BUMP:    eq. (potential_swagat), V = V0 phi^2/(m^2 + phi^2)
+ *                     [1 + K exp(-(phi - phi_T)^2/(2 Sigma^2))], with m = bump_m,
+ *                     K = bump_K, Sigma = bump_Sigma and the bump's centre phi_0 =
+ *                     phi_T (A_plus, A_minus unused).  Requires m > 0, Sigma > 0,
+ *                     K > -1 and phi_end > 0 (V > 0 for phi != 0).  Runs take FP64
+ *                     state, 1D noise and no or a constant bias (else
+ *                     FPT_EUNSUPPORTED at fpt_create), and no batches.
  * Requires finite values, phi_in > phi_end, and V > 0 on [phi_end, phi_in]. */
 typedef struct {
     int32_t kind;
     double V0, phi_T, A_plus, A_minus;
     double phi_in, pi_in, phi_end;
+    double bump_m, bump_K, bump_Sigma;   /* FPT_POT_GAUSSIAN_BUMP only */
 } fpt_potential;
 
 /* Noise as a function of phi (Sec. 3.2/3.4): n nodes phi_j = phi_lo + j h,
@@ -329,15 +337,15 @@ int fpt_noise_table_bessel2d(const fpt_potential *pot, double sigma, int32_t n, 
  * nu = nu(phi_j) of eq. (nu_squared_approximation) at -k eta = sigma.  In that
  * matching the N-derivative of (a/sqrt(-eta)) dphi is (a/sqrt(-eta))
  * (3/2 dphi + d dphi/dN), which reproduces the Bunch-Davies coefficients of
- * eq. (A_k_and_B_k) from the Bunch-Davies mode.  A node at or above phi_start, or
+ * eq. (A_k_and_B_k) from the Bunch-Davies mode.  The matching's denominator is
+ * the Bessel Wronskian, -2/pi, so B_k needs J_nu only and every nu > 0 works.  A node at or above phi_start, or
  * never reached (the trajectory is followed until phi < phi_lo, eps1 >= 1 or
  * N > 200), keeps fac = 1.  A node at phi_T takes the mode before the kink.
  * Computed by device kernels on the current device (a one-thread trajectory
  * kernel, then one thread per node; about 50 MB of device scratch for the call).
  * Errors: FPT_EINVAL (n out of 1..FPT_MAX_TABLE, sigma outside (0, 2], V <= 0 or
- * nu^2 <= 0 at a node, non-finite or eps1 >= 1 start, a reached node whose
- * mode would start before N = 0 -- start the trajectory earlier -- or whose nu
- * lies within 1e-3/pi of an integer), FPT_EHIP. */
+ * nu^2 <= 0 at a node, non-finite or eps1 >= 1 start, or a reached node whose
+ * mode would start before N = 0 -- start the trajectory earlier), FPT_EHIP. */
 int fpt_noise_table_matched(const fpt_potential *pot, double sigma, int32_t n, double phi_lo, double phi_hi,
                             double phi_start, double pi_start, double *S_out, double *tan_out, double *fac_out);
 

@@ -3,6 +3,7 @@
 // the device kernel that evaluates the Bessel-ansatz noise table.
 #include "fpt.h"
 #include "internal.hpp"
+#include "potential.hpp"
 
 #include <hip/hip_runtime.h>
 
@@ -45,23 +46,34 @@ int hip_fail(hipError_t e, const char *what)
 
 bool is_finite(double v) { return std::isfinite(v); }
 
+PotParams pot_params(const fpt_potential &p)
+{
+    return PotParams{p.kind, p.V0, p.phi_T, p.A_plus, p.A_minus, p.bump_m, p.bump_K, p.bump_Sigma};
+}
+
 double pot_V(const fpt_potential &p, double phi)
 {
-    if (p.kind == FPT_POT_EXPONENTIAL) return p.V0 * std::exp(p.A_plus * (phi - p.phi_T));
-    return p.V0 + ((phi >= p.phi_T) ? p.A_plus : p.A_minus) * (phi - p.phi_T);
+    double V, dV, d2V;
+    pot_eval(pot_params(p), phi, false, V, dV, d2V);
+    return V;
 }
 
 int check_potential(const fpt_potential *pot)
 {
     if (!pot) return fail(FPT_EINVAL, "potential is NULL");
-    if (pot->kind != FPT_POT_PIECEWISE_LINEAR && pot->kind != FPT_POT_EXPONENTIAL)
+    if (pot->kind != FPT_POT_PIECEWISE_LINEAR && pot->kind != FPT_POT_EXPONENTIAL &&
+        pot->kind != FPT_POT_GAUSSIAN_BUMP)
         return fail(FPT_EINVAL, "unknown potential kind %d", pot->kind);
-    const double v[] = {pot->V0, pot->phi_T, pot->A_plus, pot->A_minus, pot->phi_in, pot->pi_in, pot->phi_end};
+    const double v[] = {pot->V0,      pot->phi_T,  pot->A_plus, pot->A_minus,  pot->phi_in,
+                        pot->pi_in,   pot->phi_end, pot->bump_m, pot->bump_K, pot->bump_Sigma};
     for (double x : v)
         if (!is_finite(x)) return fail(FPT_EINVAL, "potential parameters must be finite");
     if (!(pot->V0 > 0.0)) return fail(FPT_EINVAL, "V0 must be > 0");
     if (pot->kind == FPT_POT_PIECEWISE_LINEAR && (pot->A_plus == 0.0 || pot->A_minus == 0.0))
         return fail(FPT_EINVAL, "A_plus and A_minus must be non-zero");
+    if (pot->kind == FPT_POT_GAUSSIAN_BUMP &&
+        (!(pot->bump_m > 0.0) || !(pot->bump_Sigma > 0.0) || !(pot->bump_K > -1.0)))
+        return fail(FPT_EINVAL, "the Gaussian bump needs m > 0, Sigma > 0 and K > -1");
     return FPT_OK;
 }
 
@@ -70,23 +82,15 @@ int check_potential(const fpt_potential *pot)
 // ---------------------------------------------------------------------------
 // noise table kernel: eq. (covariance_constant_nu) with eq. (nu_squared_approximation)
 // ---------------------------------------------------------------------------
-__global__ void table_bessel_kernel(int kind, double V0, double phi_T, double Ap, double Am, double sigma, int n,
-                                    double phi_lo, double h, double *S, double *t, int *bad)
+__global__ void table_bessel_kernel(PotParams pp, double sigma, int n, double phi_lo, double h, double *S,
+                                    double *t, int *bad)
 {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= n) return;
     const double phi = phi_lo + (double)j * h;
-    double V, r1, r2;
-    if (kind == FPT_POT_EXPONENTIAL) {
-        V = V0 * exp(Ap * (phi - phi_T));
-        r1 = Ap;          // V'/V
-        r2 = Ap * Ap;     // V''/V
-    } else {
-        const double A = (phi >= phi_T) ? Ap : Am;
-        V = V0 + A * (phi - phi_T);
-        r1 = A / V;
-        r2 = 0.0;
-    }
+    double V, dV, d2V;
+    pot_eval(pp, phi, false, V, dV, d2V);
+    const double r1 = dV / V, r2 = d2V / V;   // V'/V, V''/V
     const double nu2 = 2.25 - 3.0 * (r2 - r1 * r1);
     if (!(V > 0.0) || !(nu2 > 0.0)) {
         atomicOr(bad, 1);
@@ -118,8 +122,8 @@ extern "C" int fpt_noise_table_bessel(const fpt_potential *pot, double sigma, in
     d_bad = reinterpret_cast<int *>(d + 2 * n);
     hipError_t e = hipMemset(d_bad, 0, sizeof(int));
     if (e == hipSuccess) {
-        hipLaunchKernelGGL(table_bessel_kernel, dim3((n + 255) / 256), dim3(256), 0, 0, pot->kind, pot->V0,
-                           pot->phi_T, pot->A_plus, pot->A_minus, sigma, n, phi_lo, h, d, d + n, d_bad);
+        hipLaunchKernelGGL(table_bessel_kernel, dim3((n + 255) / 256), dim3(256), 0, 0, pot_params(*pot), sigma, n,
+                           phi_lo, h, d, d + n, d_bad);
         e = hipGetLastError();
     }
     int bad = 0;
@@ -143,23 +147,15 @@ __device__ __forceinline__ cplx cmul(cplx a, cplx b) { return {a.re * b.re - a.i
 __device__ __forceinline__ cplx cscale(cplx a, double s) { return {a.re * s, a.im * s}; }
 __device__ __forceinline__ cplx cadd(cplx a, cplx b) { return {a.re + b.re, a.im + b.im}; }
 
-__global__ void table_bessel2d_kernel(int kind, double V0, double phi_T, double Ap, double Am, double sigma, int n,
-                                      double phi_lo, double h, double *Xpp, double *Xpq, double *Xqq, int *bad)
+__global__ void table_bessel2d_kernel(PotParams pp, double sigma, int n, double phi_lo, double h, double *Xpp,
+                                      double *Xpq, double *Xqq, int *bad)
 {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= n) return;
     const double phi = phi_lo + (double)j * h;
-    double V, r1, r2;
-    if (kind == FPT_POT_EXPONENTIAL) {
-        V = V0 * exp(Ap * (phi - phi_T));
-        r1 = Ap;
-        r2 = Ap * Ap;
-    } else {
-        const double A = (phi >= phi_T) ? Ap : Am;
-        V = V0 + A * (phi - phi_T);
-        r1 = A / V;
-        r2 = 0.0;
-    }
+    double V, dV, d2V;
+    pot_eval(pp, phi, false, V, dV, d2V);
+    const double r1 = dV / V, r2 = d2V / V;
     const double nu2 = 2.25 - 3.0 * (r2 - r1 * r1);
     const double nu = nu2 > 0.0 ? sqrt(nu2) : 0.0;
     double sn, cs;
@@ -211,8 +207,8 @@ extern "C" int fpt_noise_table_bessel2d(const fpt_potential *pot, double sigma, 
     int *d_bad = reinterpret_cast<int *>(d + 3 * n);
     hipError_t e = hipMemset(d_bad, 0, sizeof(int));
     if (e == hipSuccess) {
-        hipLaunchKernelGGL(table_bessel2d_kernel, dim3((n + 255) / 256), dim3(256), 0, 0, pot->kind, pot->V0,
-                           pot->phi_T, pot->A_plus, pot->A_minus, sigma, n, phi_lo, h, d, d + n, d + 2 * n, d_bad);
+        hipLaunchKernelGGL(table_bessel2d_kernel, dim3((n + 255) / 256), dim3(256), 0, 0, pot_params(*pot), sigma, n,
+                           phi_lo, h, d, d + n, d + 2 * n, d_bad);
         e = hipGetLastError();
     }
     int bad = 0;
@@ -250,8 +246,8 @@ extern "C" int fpt_noise_table_matched(const fpt_potential *pot, double sigma, i
     int *d_status = reinterpret_cast<int *>(d_S + 3 * n);
     hipError_t e = hipMemset(d_status, 0, sizeof(int));
     if (e == hipSuccess)
-        e = fpt::matched_table_launch(pot->kind, pot->V0, pot->phi_T, pot->A_plus, pot->A_minus, sigma, n, phi_lo,
-                                      h, phi_start, pi_start, d, d_S, d_S + n, d_S + 2 * n, d_status, nullptr);
+        e = fpt::matched_table_launch(pot_params(*pot), sigma, n, phi_lo, h, phi_start, pi_start, d, d_S, d_S + n,
+                                      d_S + 2 * n, d_status, nullptr);
     int status = 0;
     if (e == hipSuccess) e = hipMemcpy(S_out, d_S, sizeof(double) * n, hipMemcpyDeviceToHost);
     if (e == hipSuccess) e = hipMemcpy(tan_out, d_S + n, sizeof(double) * n, hipMemcpyDeviceToHost);
@@ -261,7 +257,6 @@ extern "C" int fpt_noise_table_matched(const fpt_potential *pot, double sigma, i
     if (e != hipSuccess) return hip_fail(e, "matched noise table kernels");
     if (status & 1) return fail(FPT_EINVAL, "V <= 0 or nu^2 <= 0 at a table node");
     if (status & 2) return fail(FPT_EINVAL, "a node is reached before its mode can start at k = 100 aH: start earlier");
-    if (status & 8) return fail(FPT_EINVAL, "nu within 1e-3/pi of an integer at a reached node");
     if (status & 4) return fail(FPT_EINVAL, "non-finite or zero Bessel coefficient at a node");
     return FPT_OK;
 }
@@ -461,6 +456,15 @@ extern "C" int fpt_create(const fpt_potential *pot, const fpt_noise_table *table
         if (pot->phi_T > pot->phi_end && pot->phi_T < pot->phi_in) ok = ok && pot_V(*pot, pot->phi_T) > 0.0;
         if (!ok) return fail(FPT_EINVAL, "V <= 0 on [phi_end, phi_in]");
     }
+    if (pot->kind == FPT_POT_GAUSSIAN_BUMP) {
+        // V > 0 wherever phi != 0 (m > 0, K > -1); the run stays at phi > phi_end
+        if (!(pot->phi_end > 0.0)) return fail(FPT_EINVAL, "the Gaussian bump needs phi_end > 0");
+        if (opts && opts->precision != FPT_FP64)
+            return fail(FPT_EUNSUPPORTED, "the Gaussian bump is implemented with FP64 state only");
+        if (bias && bias->kind == FPT_BIAS_MLP)
+            return fail(FPT_EUNSUPPORTED, "the Gaussian bump takes no learned bias");
+        if (table && table->dim == 2) return fail(FPT_EUNSUPPORTED, "the Gaussian bump takes 1D noise only");
+    }
     // noise table
     const int nt = table->n;
     if (nt < 1 || nt > FPT_MAX_TABLE) return fail(FPT_EINVAL, "table size %d out of 1..%d", nt, FPT_MAX_TABLE);
@@ -590,6 +594,7 @@ extern "C" int fpt_create(const fpt_potential *pot, const fpt_noise_table *table
     I.pot_kind = pot->kind;
     I.V0 = pot->V0; I.phi_T = pot->phi_T; I.A_plus = pot->A_plus; I.A_minus = pot->A_minus;
     I.phi_in = pot->phi_in; I.pi_in = pot->pi_in; I.phi_end = pot->phi_end;
+    I.bump_m2 = pot->bump_m * pot->bump_m; I.bump_K = pot->bump_K; I.bump_Sigma = pot->bump_Sigma;
     I.n_tab = nt;
     I.phi_lo = (nt > 1) ? table->phi_lo : 0.0;
     I.inv_h = (nt > 1) ? (double)(nt - 1) / (table->phi_hi - table->phi_lo) : 0.0;
@@ -672,7 +677,8 @@ extern "C" int fpt_run(fpt_ctx *c, uint64_t n_traj, double dN, uint64_t seed, ui
     int grid = 0;
     const bool two_d = c->inst.noise_dim == 2;
     const void *fn = two_d ? em2d_kernel_ptr(c->inst.bias_kind, c->inst.all_S_pos != 0)
-                           : em_kernel_ptr(c->precision, c->inst.bias_kind, c->inst.n_tab > 1, c->inst.all_S_pos != 0);
+                           : em_kernel_ptr(c->precision, c->inst.bias_kind, c->inst.n_tab > 1, c->inst.all_S_pos != 0,
+                                           c->inst.pot_kind);
     const size_t lds = two_d ? em2d_lds_bytes(c->inst.hist.n_bins, c->inst.n_tab)
                              : em_lds_bytes(c->inst.hist.n_bins, c->inst.n_tab, c->precision, grid_cells(c->inst));
     int rc = occupancy_grid(fn, block, lds, c->cu_count, c->opt.blocks_per_cu, grid);
@@ -1005,6 +1011,7 @@ extern "C" int fpt_batch_create(fpt_ctx *const *ctx, int32_t n_inst, const fpt_b
         if (ctx[i]->precision != ctx[0]->precision) return fail(FPT_EINVAL, "contexts mix FP64 and FP32 state");
         if (ctx[i]->inst.bias_kind == kBiasMlp) return fail(FPT_EINVAL, "a batch cannot hold a learned bias");
         if (ctx[i]->inst.noise_dim == 2) return fail(FPT_EINVAL, "a batch cannot hold 2D noise");
+        if (ctx[i]->inst.pot_kind == kPotGaussianBump) return fail(FPT_EINVAL, "a batch cannot hold the Gaussian bump");
     }
     int dev = -1;
     HIP_TRY(hipGetDevice(&dev));

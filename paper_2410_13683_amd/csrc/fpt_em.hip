@@ -252,6 +252,28 @@ __device__ __forceinline__ DriftConsts drift_consts(const Inst &I)
     return k;
 }
 
+// V'/V of the Gaussian bump, eq. (potential_swagat), as one fraction:
+//   2 m^2/(phi (m^2 + phi^2)) - x g/(Sigma (1 + g)),  x = (phi - phi_0)/Sigma,  g = K e^(-x^2/2).
+// In ultra-slow roll the two terms nearly cancel; the single division keeps that to one rounding
+// of the numerator's difference.
+struct BumpConsts {
+    double phi0, m2, two_m2, inv_sig, sig, K;
+};
+
+__device__ __forceinline__ BumpConsts bump_consts(const Inst &I)
+{
+    return BumpConsts{I.phi_T, I.bump_m2, 2.0 * I.bump_m2, 1.0 / I.bump_Sigma, I.bump_Sigma, I.bump_K};
+}
+
+__device__ __forceinline__ double bump_dlnV(const BumpConsts &b, double phi)
+{
+    const double x = (phi - b.phi0) * b.inv_sig;
+    const double g = b.K * exp(-0.5 * x * x);
+    const double d1 = phi * fma(phi, phi, b.m2);
+    const double d2 = b.sig * (1.0 + g);
+    return (b.two_m2 * d2 - x * g * d1) / (d1 * d2);
+}
+
 // The table size used by the kernels: a single node (constant noise) is
 // staged as two equal nodes so one lookup serves every table.
 __device__ __forceinline__ int staged_nodes(const Inst &I) { return I.n_tab > 1 ? I.n_tab : 2; }
@@ -410,13 +432,16 @@ __device__ __forceinline__ void grad_add(T s[4], T c, T f0, T f1)
 // rp.tail (cursor over the list) and scatter the gradient factors instead of
 // retiring into the histogram.
 // ---------------------------------------------------------------------------
-template <int BIAS, bool TAB, bool ALLPOS, bool GRAD>
+template <int BIAS, bool TAB, bool ALLPOS, bool GRAD, int POT = kPotPiecewiseLinear>
 __device__ __forceinline__ void lanes_fp64(const Inst &I, const RunArgs &R, const double2 *l_tab, const double2 *l_grid,
                                            const RetireTo &rt, const ReplayTo &rp, unsigned long long *cursor,
                                            uint64_t n_traj, uint64_t traj_offset)
 {
     static_assert(!GRAD || BIAS == kBiasMlp, "replay needs the tabulated control");
+    // POT: kPotPiecewiseLinear serves both linear-family potentials (V'/V = 1/d below);
+    // kPotGaussianBump computes the bump's V'/V
     const DriftConsts dk = drift_consts(I);
+    const BumpConsts bc = bump_consts(I);
     const GridConsts64 gc = grid_consts64(I);
     const double S0 = l_tab[0].x, t0 = l_tab[0].y;
     const double dN = R.dN, sqrt_dN = R.sqrt_dN, phi_end = I.phi_end, phi_T = I.phi_T;
@@ -456,10 +481,15 @@ __device__ __forceinline__ void lanes_fp64(const Inst &I, const RunArgs &R, cons
                 live = false;
                 fresh = true;
             }
-            const double d = fma(phi, dk.kx, (phi >= phi_T) ? s_plus : s_minus);
-            double r = __builtin_amdgcn_rcp(d);
-            r = fma(r, fma(-d, r, 1.0), r);
-            r = fma(r, fma(-d, r, 1.0), r);
+            double r;   // V'/V
+            if (POT == kPotGaussianBump) {
+                r = bump_dlnV(bc, phi);
+            } else {
+                const double d = fma(phi, dk.kx, (phi >= phi_T) ? s_plus : s_minus);
+                r = __builtin_amdgcn_rcp(d);
+                r = fma(r, fma(-d, r, 1.0), r);
+                r = fma(r, fma(-d, r, 1.0), r);
+            }
             double S, t;
             if (TAB) {
                 const double x = (phi - I.phi_lo) * I.inv_h;
@@ -959,9 +989,10 @@ __device__ __forceinline__ RetireTo retire_to(const EmParams &p, const LdsAcc &a
     return r;
 }
 
-template <int PREC, int BIAS, bool TAB, bool ALLPOS>
+template <int PREC, int BIAS, bool TAB, bool ALLPOS, int POT = kPotPiecewiseLinear>
 __global__ void __launch_bounds__(1024) FPT_EM_OCCUPANCY em_kernel(EmParams p)
 {
+    static_assert(POT == kPotPiecewiseLinear || (PREC == 0 && BIAS != kBiasMlp), "the bump runs in FP64 only");
     extern __shared__ __align__(16) unsigned char smem[];
     const LdsAcc acc = lds_acc(smem, p.inst.hist.n_bins);
     unsigned char *l_tab = smem + align16(acc_bytes(p.inst.hist.n_bins));
@@ -974,9 +1005,9 @@ __global__ void __launch_bounds__(1024) FPT_EM_OCCUPANCY em_kernel(EmParams p)
     const RetireTo rt = retire_to(p, acc);
     const ReplayTo rp{nullptr, nullptr, nullptr};
     if (PREC == 0)
-        lanes_fp64<BIAS, TAB, ALLPOS, false>(p.inst, p.run, reinterpret_cast<const double2 *>(l_tab),
-                                             reinterpret_cast<const double2 *>(l_grid), rt, rp, p.cursor, p.n_traj,
-                                             p.traj_offset);
+        lanes_fp64<BIAS, TAB, ALLPOS, false, POT>(p.inst, p.run, reinterpret_cast<const double2 *>(l_tab),
+                                                  reinterpret_cast<const double2 *>(l_grid), rt, rp, p.cursor,
+                                                  p.n_traj, p.traj_offset);
     else
         lanes_fp32<BIAS, TAB, ALLPOS, false>(p.inst, p.run, reinterpret_cast<const float4 *>(l_tab),
                                              reinterpret_cast<const float4 *>(l_grid), rt, rp, p.cursor, p.n_traj,
@@ -1094,8 +1125,8 @@ __global__ void zero_words_kernel(unsigned long long *ptr, size_t n)
         ptr[i] = 0ull;
 }
 
-template <int PREC, int BIAS, bool TAB, bool ALLPOS>
-const void *kptr() { return reinterpret_cast<const void *>(&em_kernel<PREC, BIAS, TAB, ALLPOS>); }
+template <int PREC, int BIAS, bool TAB, bool ALLPOS, int POT = kPotPiecewiseLinear>
+const void *kptr() { return reinterpret_cast<const void *>(&em_kernel<PREC, BIAS, TAB, ALLPOS, POT>); }
 template <int PREC, int BIAS, bool ALLPOS>
 const void *bptr() { return reinterpret_cast<const void *>(&batch_kernel<PREC, BIAS, ALLPOS>); }
 
@@ -1117,8 +1148,18 @@ size_t replay_lds_bytes(int n_tab, int precision, int n_cells, int n_nodes)
     return tab_bytes(precision, n_tab) + cell_bytes(precision, n_cells) + (size_t)n_nodes * 8;
 }
 
-const void *em_kernel_ptr(int precision, int bias_kind, bool table, bool all_pos)
+const void *em_kernel_ptr(int precision, int bias_kind, bool table, bool all_pos, int pot_kind)
 {
+    if (pot_kind == kPotGaussianBump) {
+        // FP64, bias none or constant (fpt_create rejects the rest)
+        constexpr int B = kPotGaussianBump;
+        static const void *const tb[2][2][2] = {
+            {{kptr<0, kBiasNone, false, false, B>(), kptr<0, kBiasNone, false, true, B>()},
+             {kptr<0, kBiasNone, true, false, B>(), kptr<0, kBiasNone, true, true, B>()}},
+            {{kptr<0, kBiasConst, false, false, B>(), kptr<0, kBiasConst, false, true, B>()},
+             {kptr<0, kBiasConst, true, false, B>(), kptr<0, kBiasConst, true, true, B>()}}};
+        return tb[bias_kind == kBiasConst ? 1 : 0][table ? 1 : 0][all_pos ? 1 : 0];
+    }
     static const KTab<0, kBiasNone> f0n;
     static const KTab<0, kBiasConst> f0c;
     static const KTab<0, kBiasMlp> f0m;
@@ -1134,7 +1175,8 @@ const void *em_kernel_ptr(int precision, int bias_kind, bool table, bool all_pos
 hipError_t em_launch(const EmParams &p, int precision, int grid, int block, hipStream_t stream)
 {
     const size_t lds = em_lds_bytes(p.inst.hist.n_bins, p.inst.n_tab, precision, grid_cells(p.inst));
-    const void *fn = em_kernel_ptr(precision, p.inst.bias_kind, p.inst.n_tab > 1, p.inst.all_S_pos != 0);
+    const void *fn = em_kernel_ptr(precision, p.inst.bias_kind, p.inst.n_tab > 1, p.inst.all_S_pos != 0,
+                                   p.inst.pot_kind);
     EmParams pp = p;
     void *args[] = {&pp};
     return hipLaunchKernel(fn, dim3(grid), dim3(block), args, lds, stream);

@@ -23,26 +23,10 @@ constexpr double kModeMaxStep = 2.5e-4;  // largest RK4 step of a mode, in e-fol
 constexpr double kStepsPerPeriod = 800.0;
 constexpr double kStartRatio = 100.0;    // a mode starts at k = 100 aH
 
-struct Pot {
-    int kind;
-    double V0, phi_T, Ap, Am;
-};
+using Pot = PotParams;
 
-// V, V' and V'' at phi.  `upper` takes the phi >= phi_T branch of the piecewise-linear
-// potential (continued below phi_T): the RK4 step that ends on the kink lies on that branch.
-__device__ inline void pot_eval(const Pot &p, double phi, bool upper, double &V, double &dV, double &d2V)
-{
-    if (p.kind == kPotExponential) {
-        V = p.V0 * exp(p.Ap * (phi - p.phi_T));
-        dV = p.Ap * V;
-        d2V = p.Ap * dV;
-        return;
-    }
-    const double A = (upper || phi >= p.phi_T) ? p.Ap : p.Am;
-    V = p.V0 + A * (phi - p.phi_T);
-    dV = A;
-    d2V = 0.0;
-}
+// The RK4 step that ends on the kink of the piecewise-linear potential is evaluated on the
+// upper branch (pot_eval's `upper`).
 
 __device__ inline double hubble2(const Pot &p, double phi, double pi_)
 {
@@ -51,14 +35,13 @@ __device__ inline double hubble2(const Pot &p, double phi, double pi_)
     return V / (3.0 - 0.5 * pi_ * pi_);
 }
 
-// nu of eq. (nu_squared_approximation) (NaN when nu^2 <= 0).
-__device__ inline double nu_of(const Pot &p, double phi)
+// nu^2 of eq. (nu_squared_approximation).
+__device__ inline double nu2_of(const Pot &p, double phi)
 {
     double V, dV, d2V;
     pot_eval(p, phi, false, V, dV, d2V);
     const double r1 = dV / V;
-    const double nu2 = 2.25 - 3.0 * (d2V / V - r1 * r1);
-    return nu2 > 0.0 ? sqrt(nu2) : NAN;
+    return 2.25 - 3.0 * (d2V / V - r1 * r1);
 }
 
 // Background (phi, pi) and, with MODE, the mode dphi = (fr, fi) and d dphi/dN = (gr, gi).
@@ -218,8 +201,9 @@ __global__ void match_node_kernel(Pot p, double sigma, int n, double phi_lo, dou
     // the Bunch-Davies node of eq. (covariance_constant_nu): sqrt(Xi_phiphi), tan theta_n
     double V, dV, d2V;
     pot_eval(p, phi_j, false, V, dV, d2V);
-    const double nu = nu_of(p, phi_j);
-    if (!(V > 0.0) || !(nu > 0.0)) {
+    const double nu2 = nu2_of(p, phi_j);
+    const double nu = nu2 > 0.0 ? sqrt(nu2) : 0.0;
+    if (!(V > 0.0) || !(nu2 > 0.0)) {
         atomicOr(status, 1);
         S[j] = tan_out[j] = fac_out[j] = 0.0;
         return;
@@ -264,8 +248,7 @@ __global__ void match_node_kernel(Pot p, double sigma, int n, double phi_lo, dou
                 // overall phase dropped; d/dN of it is [(-1 - iy)(1 + ic/y) + ic/y]/(a sqrt(2k))
                 const double a = exp(N);
                 const double y = k / (a * sqrt(hubble2(p, s.phi, s.pi_)));
-                const double nu0 = nu_of(p, s.phi);
-                const double c = (4.0 * nu0 * nu0 - 1.0) * 0.125;
+                const double c = (4.0 * nu2_of(p, s.phi) - 1.0) * 0.125;
                 const double amp = 1.0 / (a * sqrt(2.0 * k));
                 s.fr = amp;
                 s.fi = amp * c / y;
@@ -273,27 +256,19 @@ __global__ void match_node_kernel(Pot p, double sigma, int n, double phi_lo, dou
                 s.gi = amp * (-y);              // Im[...] = -c/y - y + c/y
             }
             advance<true>(p, k, N, Ns, s, phi_j < p.phi_T, kModeMaxStep);
-            // eq. (bessel_matching) at -k eta = sigma with nu(phi_j); a/sqrt(-eta) = e^N sqrt(k/sigma)
-            double sn, cn;
-            sincospi(nu, &sn, &cn);
-            if (fabs(sn) < 1e-3) {
-                atomicOr(status, 8);
-                fac = NAN;
-            } else {
-                double Jn, yJn, Jm, yJm;
-                bessel_j(nu, sigma, Jn, yJn);
-                bessel_j(-nu, sigma, Jm, yJm);
-                const double Y = (Jn * cn - Jm) / sn, yYp = (yJn * cn - yJm) / sn;
-                const double dJ = -yJn, dY = -yYp;
-                const double den = Jn * dY - dJ * Y;
-                const double pref = exp(N) * sqrt(k / sigma);
-                // (du/dN)/pref = 3/2 dphi + d dphi/dN;  B = -pref (dphi dJ - g J)/den
-                const double g_r = 1.5 * s.fr + s.gr, g_i = 1.5 * s.fi + s.gi;
-                const double b_r = -pref * (s.fr * dJ - g_r * Jn) / den;
-                const double b_i = -pref * (s.fi * dJ - g_i * Jn) / den;
-                fac = 4.0 * (b_r * b_r + b_i * b_i) / M_PI;
-                if (!(fac > 0.0) || !isfinite(fac)) atomicOr(status, 4);
-            }
+            // eq. (bessel_matching) at -k eta = sigma with nu(phi_j); a/sqrt(-eta) = e^N sqrt(k/sigma).
+            // The denominator J_nu dY_nu/dN - Y_nu dJ_nu/dN is -y W[J_nu, Y_nu](y) = -2/pi (the
+            // Bessel Wronskian), so B_k = (pi/2) pref (dphi dJ/dN - g J) with g = 3/2 dphi + d dphi/dN,
+            // for every nu > 0.
+            double Jn, yJn;
+            bessel_j(nu, sigma, Jn, yJn);
+            const double dJ = -yJn;
+            const double pref = exp(N) * sqrt(k / sigma);
+            const double g_r = 1.5 * s.fr + s.gr, g_i = 1.5 * s.fi + s.gi;
+            const double b_r = 0.5 * M_PI * pref * (s.fr * dJ - g_r * Jn);
+            const double b_i = 0.5 * M_PI * pref * (s.fi * dJ - g_i * Jn);
+            fac = 4.0 * (b_r * b_r + b_i * b_i) / M_PI;
+            if (!(fac > 0.0) || !isfinite(fac)) atomicOr(status, 4);
         }
     }
     fac_out[j] = fac;
@@ -304,11 +279,10 @@ __global__ void match_node_kernel(Pot p, double sigma, int n, double phi_lo, dou
 
 size_t matched_scratch_bytes(int n) { return (size_t)kMatchCap * 3 * sizeof(double) + (size_t)(n + 2) * sizeof(int); }
 
-hipError_t matched_table_launch(int kind, double V0, double phi_T, double Ap, double Am, double sigma, int n,
-                                double phi_lo, double h_node, double phi_start, double pi_start, void *scratch,
-                                double *d_S, double *d_tan, double *d_fac, int *d_status, hipStream_t stream)
+hipError_t matched_table_launch(const PotParams &p, double sigma, int n, double phi_lo, double h_node,
+                                double phi_start, double pi_start, void *scratch, double *d_S, double *d_tan,
+                                double *d_fac, int *d_status, hipStream_t stream)
 {
-    const Pot p{kind, V0, phi_T, Ap, Am};
     double *bN = static_cast<double *>(scratch);
     double *bphi = bN + kMatchCap, *bpi = bphi + kMatchCap;
     int *nb = reinterpret_cast<int *>(bpi + kMatchCap);

@@ -6,9 +6,11 @@
 #include <cstdint>
 #include <cstddef>
 
+#include "potential.hpp"
+
 namespace fpt {
 
-enum : int { kPotPiecewiseLinear = 0, kPotExponential = 1 };
+enum : int { kPotPiecewiseLinear = 0, kPotExponential = 1, kPotGaussianBump = 2 };
 enum : int { kBiasNone = 0, kBiasConst = 1, kBiasMlp = 2 };
 enum : int { kBinsLinear = 0, kBinsLog = 1 };
 
@@ -40,6 +42,8 @@ struct Inst {
     int32_t pot_kind;
     double V0, phi_T, A_plus, A_minus;
     double phi_in, pi_in, phi_end;
+    // Gaussian bump (pot_kind 2): m^2, K, Sigma; the centre phi_0 is phi_T
+    double bump_m2, bump_K, bump_Sigma;
     // phi-indexed noise table: n_tab nodes from phi_lo with spacing 1/inv_h
     int32_t n_tab;
     double phi_lo, inv_h;
@@ -121,7 +125,8 @@ struct ReplayParams {
 __host__ __device__ inline int grid_cells(const Inst &I) { return I.bias_kind == kBiasMlp ? (I.g_n0 - 1) * (I.g_n1 - 1) : 0; }
 size_t em_lds_bytes(int n_bins, int n_tab, int precision, int n_cells);
 size_t replay_lds_bytes(int n_tab, int precision, int n_cells, int n_nodes);
-const void *em_kernel_ptr(int precision, int bias_kind, bool table, bool all_pos);
+// pot_kind selects the Gaussian-bump variant (FP64, bias none or constant only).
+const void *em_kernel_ptr(int precision, int bias_kind, bool table, bool all_pos, int pot_kind = 0);
 hipError_t em_launch(const EmParams &p, int precision, int grid, int block, hipStream_t stream);
 const void *replay_kernel_ptr(int precision, bool all_pos);
 size_t em2d_lds_bytes(int n_bins, int n_tab);
@@ -158,11 +163,11 @@ hipError_t mlp_adam(float *params, float *m, float *v, const float *grad, int n,
 // Bessel-matched noise table (fpt_table.hip).  Scratch: kMatchCap trajectory samples
 // (N, phi, pi) then n + 1 ints; matched_scratch_bytes(n) bytes.  d_status collects
 // 1 (V <= 0 or nu^2 <= 0 at a node), 2 (a node reached before its mode can start),
-// 4 (non-finite or zero B_k), 8 (nu within 1e-3/pi of an integer at a reached node).
+// 4 (non-finite or zero B_k).
 constexpr int kMatchCap = (1 << 21) + 16;
 size_t matched_scratch_bytes(int n);
-hipError_t matched_table_launch(int kind, double V0, double phi_T, double Ap, double Am, double sigma, int n,
-                                double phi_lo, double h_node, double phi_start, double pi_start, void *scratch,
-                                double *d_S, double *d_tan, double *d_fac, int *d_status, hipStream_t stream);
+hipError_t matched_table_launch(const PotParams &pot, double sigma, int n, double phi_lo, double h_node,
+                                double phi_start, double pi_start, void *scratch, double *d_S, double *d_tan,
+                                double *d_fac, int *d_status, hipStream_t stream);
 
 }  // namespace fpt

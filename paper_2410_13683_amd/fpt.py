@@ -27,7 +27,7 @@ LIB_PATH = os.path.join(PKG, "libfpt.so")
 HEADER = os.path.join(ROOT, "include", "fpt.h")
 
 FPT_OK, FPT_EINVAL, FPT_ENOMEM, FPT_EHIP, FPT_ESTATE, FPT_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
-FPT_POT_PIECEWISE_LINEAR, FPT_POT_EXPONENTIAL = 0, 1
+FPT_POT_PIECEWISE_LINEAR, FPT_POT_EXPONENTIAL, FPT_POT_GAUSSIAN_BUMP = 0, 1, 2
 FPT_BIAS_NONE, FPT_BIAS_CONST, FPT_BIAS_MLP = 0, 1, 2
 FPT_FP64, FPT_FP32_STATE = 0, 1
 FPT_BINS_LINEAR, FPT_BINS_LOG = 0, 1
@@ -50,7 +50,8 @@ _u64p = ctypes.POINTER(ctypes.c_uint64)
 class fpt_potential(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("V0", ctypes.c_double), ("phi_T", ctypes.c_double),
                 ("A_plus", ctypes.c_double), ("A_minus", ctypes.c_double), ("phi_in", ctypes.c_double),
-                ("pi_in", ctypes.c_double), ("phi_end", ctypes.c_double)]
+                ("pi_in", ctypes.c_double), ("phi_end", ctypes.c_double), ("bump_m", ctypes.c_double),
+                ("bump_K", ctypes.c_double), ("bump_Sigma", ctypes.c_double)]
 
 
 class fpt_noise_table(ctypes.Structure):
@@ -177,8 +178,9 @@ def _stream_handle(stream):
     return stream.cuda_stream
 
 
-def make_potential(kind, V0, phi_T, A_plus, A_minus, phi_in, pi_in, phi_end) -> fpt_potential:
-    return fpt_potential(kind, V0, phi_T, A_plus, A_minus, phi_in, pi_in, phi_end)
+def make_potential(kind, V0, phi_T, A_plus, A_minus, phi_in, pi_in, phi_end, bump=(0.0, 0.0, 0.0)) -> fpt_potential:
+    """bump = (m, K, Sigma) of the Gaussian bump (its centre phi_0 is phi_T)."""
+    return fpt_potential(kind, V0, phi_T, A_plus, A_minus, phi_in, pi_in, phi_end, *bump)
 
 
 def fpt_noise_table_bessel(pot: fpt_potential, sigma: float, n: int, phi_lo: float, phi_hi: float):

@@ -13,7 +13,7 @@ from .workloads import Workload
 
 
 def potential_of(w: Workload) -> fpt.fpt_potential:
-    return fpt.make_potential(w.kind, w.V0, w.phi_T, w.A_plus, w.A_minus, w.phi_in, w.pi_in, w.phi_end)
+    return fpt.make_potential(w.kind, w.V0, w.phi_T, w.A_plus, w.A_minus, w.phi_in, w.pi_in, w.phi_end, w.bump)
 
 
 def table_of(w: Workload, pot=None):
@@ -32,6 +32,8 @@ def table_of(w: Workload, pot=None):
     if w.noise == "matched":
         S, t, _ = fpt.fpt_noise_table_matched(pot or potential_of(w), w.sigma, w.table_n, w.table_lo, w.table_hi,
                                               *w.match_start)
+        if w.noise_cut_below:
+            S[0] = 0.0
         return S, t, w.table_lo, w.table_hi
     raise ValueError(f"unknown noise kind {w.noise!r}")
 

@@ -20,13 +20,15 @@ def gpu_table(w: Workload, pot):
         return np.array([w.noise_S]), np.array([w.noise_tan]), 0.0, 0.0
     if w.noise == "matched":
         S, t, _ = fpt.fpt_noise_table_matched(pot, w.sigma, w.table_n, w.table_lo, w.table_hi, *w.match_start)
+        if w.noise_cut_below:
+            S[0] = 0.0
         return S, t, w.table_lo, w.table_hi
     S, t = fpt.fpt_noise_table_bessel(pot, w.sigma, w.table_n, w.table_lo, w.table_hi)
     return S, t, w.table_lo, w.table_hi
 
 
 def gpu_context(w: Workload, **kw) -> fpt.Context:
-    pot = fpt.make_potential(w.kind, w.V0, w.phi_T, w.A_plus, w.A_minus, w.phi_in, w.pi_in, w.phi_end)
+    pot = fpt.make_potential(w.kind, w.V0, w.phi_T, w.A_plus, w.A_minus, w.phi_in, w.pi_in, w.phi_end, w.bump)
     S, t, lo, hi = gpu_table(w, pot)
     args = dict(bias_kind=w.bias_kind, A=w.A_bias, precision=w.precision, bins_kind=w.bins_kind,
                 n_bins=w.n_bins, lo=w.lo, hi=w.hi, N_ref=w.N_ref, max_steps=w.max_steps,

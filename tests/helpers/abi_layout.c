@@ -11,7 +11,7 @@ int main(void)
 {
     S(fpt_potential); F(fpt_potential, kind); F(fpt_potential, V0); F(fpt_potential, phi_T);
     F(fpt_potential, A_plus); F(fpt_potential, A_minus); F(fpt_potential, phi_in); F(fpt_potential, pi_in);
-    F(fpt_potential, phi_end);
+    F(fpt_potential, phi_end); F(fpt_potential, bump_m); F(fpt_potential, bump_K); F(fpt_potential, bump_Sigma);
     S(fpt_noise_table); F(fpt_noise_table, n); F(fpt_noise_table, phi_lo); F(fpt_noise_table, phi_hi);
     F(fpt_noise_table, S); F(fpt_noise_table, tan_theta);
     F(fpt_noise_table, dim); F(fpt_noise_table, Xi_pp); F(fpt_noise_table, Xi_pq); F(fpt_noise_table, Xi_qq);

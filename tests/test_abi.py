@@ -66,6 +66,10 @@ def _pot(**kw):
     dict(bias=dict(kind=2, norm=(0.0, 0.0, 0.0, 1.0))),          # zero input scale
     dict(bias=dict(kind=2, grid_range=(1.0, -1.0, -1.0, 1.0))),  # reversed range
     dict(bias=dict(kind=2, nan_param=True)),                     # non-finite parameter
+    dict(pot=dict(kind=2, bump=(0.0, 1e-3, 0.01), phi_in=2.2, phi_end=2.0)),   # bump with m = 0
+    dict(pot=dict(kind=2, bump=(0.5, -1.0, 0.01), phi_in=2.2, phi_end=2.0)),   # K = -1: V = 0 at the centre
+    dict(pot=dict(kind=2, bump=(0.5, 1e-3, 0.0), phi_in=2.2, phi_end=2.0)),    # Sigma = 0
+    dict(pot=dict(kind=2, bump=(0.5, 1e-3, 0.01), phi_in=0.5, phi_end=0.0)),   # phi_end <= 0: V(0) = 0
 ])
 def test_invalid_arguments_are_rejected(lib, bad):
     pot = _pot(**bad.get("pot", {}))
@@ -177,3 +181,25 @@ def test_matched_table_validation(lib, case):
     rc = lib.fpt_noise_table_matched(ctypes.byref(pot), args["sigma"], args["n"], args["lo"], args["hi"],
                                      args["phi_start"], args["pi_start"], *outs)
     assert rc == fpt.FPT_EINVAL
+
+
+@pytest.mark.parametrize("case", ["fp32", "mlp", "2d"])
+def test_bump_variants_are_reported_unsupported(lib, case):
+    pot = _pot(kind=2, bump=(0.5, 1.17e-3, 1.59e-2), phi_T=2.18812, phi_in=2.2, pi_in=-1e-3, phi_end=2.0)
+    S, t = np.array([1e-6]), np.zeros(1)
+    X = [np.array([1e-12]), np.array([1e-13]), np.array([1e-12])]
+    if case == "2d":
+        tab = fpt.fpt_noise_table(1, 0.0, 0.0, None, None, 2, *[x.ctypes.data_as(fpt._dp) for x in X])
+    else:
+        tab = fpt.fpt_noise_table(1, 0.0, 0.0, S.ctypes.data_as(fpt._dp), t.ctypes.data_as(fpt._dp))
+    params = np.zeros(fpt.FPT_MLP_NPARAM, dtype=np.float32)
+    bias = fpt.fpt_bias(2 if case == "mlp" else 0, 0.0, params.ctypes.data_as(fpt._fp),
+                        (ctypes.c_double * 4)(0.0, 1.0, 0.0, 1.0), 0, (ctypes.c_int32 * 2)(8, 8),
+                        (ctypes.c_double * 4)(-1.0, 1.0, -1.0, 1.0))
+    opts = fpt.fpt_options(precision=1 if case == "fp32" else 0, bins_kind=0, n_bins=8, lo=-1.0, hi=1.0, N_ref=0.0,
+                           max_steps=1000, instance=0, block_size=0, blocks_per_cu=0, chunk=0)
+    h = ctypes.c_void_p()
+    rc = lib.fpt_create(ctypes.byref(pot), ctypes.byref(tab), ctypes.byref(bias), ctypes.byref(opts),
+                        ctypes.byref(h))
+    assert rc == fpt.FPT_EUNSUPPORTED, (rc, lib.fpt_last_error())
+    assert not h.value
