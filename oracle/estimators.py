@@ -1,0 +1,72 @@
+"""Error bars of the weighted first-passage histogram (Sec. 4.1) -- test infrastructure.
+
+Plain numpy versions of the three estimators the library computes from its
+histogram accumulators.  They share no code with the library.  Only tests/ and
+bench.py's CPU baseline use this module.
+
+* Direct sampling (no bias): delete-one jackknife over B blocks of trajectories.
+  The paper treats each simulation run as an independent sample and resamples them.
+* Importance sampling: the error of a per-bin lognormal mean.  Within slot j, ln w of
+  the n_j trajectories there is treated as normal with mean mu and variance s^2.  The
+  slot's mass is (n_j/n) exp(mu + s^2/2) and its one-standard-deviation interval is
+  Cox's, exp(mu + s^2/2 -+ sqrt(s^2/n_j + s^4/(2(n_j - 1)))).
+* Several bias amplitudes: the inverse-variance weighted mean per slot.
+
+Masses are per histogram slot (slot 0 underflow, 1..n_bins the bins, n_bins + 1
+overflow), sum_w/n_traj.  Dividing by the bin width gives the density.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+def jackknife(n_traj_blocks, sum_w_blocks):
+    """(p, err) per slot from B blocks: p = sum_b sw_b / sum_b n_b; the delete-one estimates
+    p_(b) = (sum sw - sw_b)/(N - n_b); err^2 = (B - 1)/B sum_b (p_(b) - mean_b p_(b))^2."""
+    n = np.asarray(n_traj_blocks, dtype=np.float64)
+    sw = np.asarray(sum_w_blocks, dtype=np.float64)        # (B, n_slots)
+    B = len(n)
+    N, SW = n.sum(), sw.sum(axis=0)
+    p = SW / N
+    loo = np.empty_like(sw)
+    for b in range(B):
+        loo[b] = (SW - sw[b]) / (N - n[b])
+    mean = loo.mean(axis=0)
+    err = np.sqrt((B - 1) / B * ((loo - mean) ** 2).sum(axis=0))
+    return p, err
+
+
+def lognormal(n_traj, count, sum_lnw, sum_lnw2):
+    """(p, lo, hi) per slot: (n_j/n) exp(mu + s^2/2) with Cox's interval; NaN where n_j < 2."""
+    c = np.asarray(count, dtype=np.float64)
+    p = np.full(len(c), np.nan)
+    lo = np.full(len(c), np.nan)
+    hi = np.full(len(c), np.nan)
+    for j in range(len(c)):
+        nj = c[j]
+        if nj < 2:
+            continue
+        mu = sum_lnw[j] / nj
+        s2 = max((sum_lnw2[j] - nj * mu * mu) / (nj - 1.0), 0.0)
+        theta = mu + 0.5 * s2
+        se = np.sqrt(s2 / nj + s2 * s2 / (2.0 * (nj - 1.0)))
+        f = nj / n_traj
+        p[j], lo[j], hi[j] = f * np.exp(theta), f * np.exp(theta - se), f * np.exp(theta + se)
+    return p, lo, hi
+
+
+def merge(p_runs, err_runs):
+    """Inverse-variance weighted mean per slot over runs; runs with a non-finite or non-positive
+    error in a slot are left out there; NaN where none is left."""
+    P = np.asarray(p_runs, dtype=np.float64)
+    E = np.asarray(err_runs, dtype=np.float64)
+    out_p = np.full(P.shape[1], np.nan)
+    out_e = np.full(P.shape[1], np.nan)
+    for j in range(P.shape[1]):
+        ok = np.isfinite(P[:, j]) & np.isfinite(E[:, j]) & (E[:, j] > 0)
+        if not ok.any():
+            continue
+        wgt = 1.0 / E[ok, j] ** 2
+        out_p[j] = (wgt * P[ok, j]).sum() / wgt.sum()
+        out_e[j] = 1.0 / np.sqrt(wgt.sum())
+    return out_p, out_e
