@@ -8,8 +8,11 @@ bench.py's CPU baseline use this module.
   The paper treats each simulation run as an independent sample and resamples them.
 * Importance sampling: the error of a per-bin lognormal mean.  Within slot j, ln w of
   the n_j trajectories there is treated as normal with mean mu and variance s^2.  The
-  slot's mass is (n_j/n) exp(mu + s^2/2) and its one-standard-deviation interval is
-  Cox's, exp(mu + s^2/2 -+ sqrt(s^2/n_j + s^4/(2(n_j - 1)))).
+  slot's mass is (n_j/n) exp(mu + s^2/2).  Its one-standard-deviation interval in
+  ln(mass) combines two independent parts:
+  - Cox's standard error of ln(mean w), s^2/n_j + s^4/(2(n_j - 1));
+  - the binomial fluctuation of the count, (1 - n_j/n)/n_j.
+  Without weights the interval is the binomial one.
 * Several bias amplitudes: the inverse-variance weighted mean per slot.
 
 Masses are per histogram slot (slot 0 underflow, 1..n_bins the bins, n_bins + 1
@@ -37,7 +40,8 @@ def jackknife(n_traj_blocks, sum_w_blocks):
 
 
 def lognormal(n_traj, count, sum_lnw, sum_lnw2):
-    """(p, lo, hi) per slot: (n_j/n) exp(mu + s^2/2) with Cox's interval; NaN where n_j < 2."""
+    """(p, lo, hi) per slot: (n_j/n) exp(mu + s^2/2), and exp(-+se) times it with
+    se^2 = s^2/n_j + s^4/(2(n_j - 1)) + (1 - n_j/n)/n_j; NaN where n_j < 2."""
     c = np.asarray(count, dtype=np.float64)
     p = np.full(len(c), np.nan)
     lo = np.full(len(c), np.nan)
@@ -49,8 +53,8 @@ def lognormal(n_traj, count, sum_lnw, sum_lnw2):
         mu = sum_lnw[j] / nj
         s2 = max((sum_lnw2[j] - nj * mu * mu) / (nj - 1.0), 0.0)
         theta = mu + 0.5 * s2
-        se = np.sqrt(s2 / nj + s2 * s2 / (2.0 * (nj - 1.0)))
         f = nj / n_traj
+        se = np.sqrt(s2 / nj + s2 * s2 / (2.0 * (nj - 1.0)) + (1.0 - f) / nj)
         p[j], lo[j], hi[j] = f * np.exp(theta), f * np.exp(theta - se), f * np.exp(theta + se)
     return p, lo, hi
 

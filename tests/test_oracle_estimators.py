@@ -1,9 +1,11 @@
 """Pins of the oracle's error-bar estimators (Sec. 4.1).
 - The delete-one jackknife equals the textbook standard error of a mean of equal blocks,
   and on direct-sampling counts it reproduces the binomial error.
-- Without weights the lognormal estimator is the count fraction with a zero-width interval.
+- Without weights the lognormal estimator is the count fraction with the binomial interval.
 - On lognormal samples Cox's interval covers the true mean at the one-sigma rate; the
   interval without its s^4 term does not.
+- With random counts and lognormal weights, the combined interval covers the true slot mass
+  at the one-sigma rate; Cox's part alone does not.
 - The inverse-variance merge against closed forms."""
 import math
 
@@ -50,29 +52,35 @@ def test_lognormal_without_weights_is_the_count_fraction():
     count = np.array([0, 1, 5, 300])
     p, lo, hi = E.lognormal(1000, count, np.zeros(4), np.zeros(4))
     assert np.isnan(p[0]) and np.isnan(p[1])
-    np.testing.assert_allclose(p[2:], count[2:] / 1000, rtol=1e-15)
-    np.testing.assert_array_equal(lo[2:], p[2:])
-    np.testing.assert_array_equal(hi[2:], p[2:])
+    f = count[2:] / 1000
+    np.testing.assert_allclose(p[2:], f, rtol=1e-15)
+    rel = np.sqrt((1 - f) / count[2:])          # binomial relative error of a count fraction
+    np.testing.assert_allclose(np.log(hi[2:] / p[2:]), rel, rtol=1e-14)
+    np.testing.assert_allclose(np.log(p[2:] / lo[2:]), rel, rtol=1e-14)
+    # a slot holding every trajectory has no count fluctuation
+    p, lo, hi = E.lognormal(50, [50], [0.0], [0.0])
+    assert lo[0] == hi[0] == p[0] == 1.0
 
 
 @pytest.mark.parametrize("s", [0.5, 1.0])
 def test_cox_interval_covers_the_lognormal_mean_at_one_sigma(s):
-    """2000 replicate slots of 60 lognormal weights (mu = -7): the interval holds the true slot mass
-    (n_j/n) e^(mu + s^2/2) in 68.3 % of them (binomial +-1 %).  Dropping the s^4 term of the
-    standard error takes the coverage visibly lower."""
+    """2000 replicate slots of 60 lognormal weights (mu = -7), each slot holding every trajectory
+    (no count fluctuation): the interval holds the true mean e^(mu + s^2/2) in 68.3 % of them
+    (binomial +-1 %).  Dropping the s^4 term of the standard error takes the coverage visibly lower."""
     rng = np.random.default_rng(int(s * 10))
-    R, nj, n, mu = 2000, 60, 10_000, -7.0
+    R, nj, mu = 2000, 60, -7.0
     lnw = rng.normal(mu, s, size=(R, nj))
-    truth = nj / n * math.exp(mu + 0.5 * s * s)
+    truth = math.exp(mu + 0.5 * s * s)
     cover = 0
     cover_short = 0
     for r in range(R):
-        p, lo, hi = E.lognormal(n, [nj], [lnw[r].sum()], [(lnw[r] ** 2).sum()])
+        # n_traj = n_j: the slot holds every trajectory, so only Cox's part is left
+        p, lo, hi = E.lognormal(nj, [nj], [lnw[r].sum()], [(lnw[r] ** 2).sum()])
         cover += lo[0] <= truth <= hi[0]
         m_ = lnw[r].mean()
         s2 = lnw[r].var(ddof=1)
         th, se = m_ + s2 / 2, math.sqrt(s2 / nj)
-        cover_short += nj / n * math.exp(th - se) <= truth <= nj / n * math.exp(th + se)
+        cover_short += math.exp(th - se) <= truth <= math.exp(th + se)
     assert abs(cover / R - 0.6827) < 0.035, cover / R
     if s == 1.0:
         assert cover_short / R < cover / R - 0.03
@@ -87,3 +95,27 @@ def test_merge_closed_forms():
     assert np.isnan(p[0]) and np.isnan(e[0])
     p, e = E.merge([[1.0], [4.0]], [[1.0], [2.0]])
     assert p[0] == pytest.approx((1.0 + 4.0 / 4) / 1.25)
+
+
+@pytest.mark.parametrize("s", [0.05, 0.7])
+def test_combined_interval_covers_the_slot_mass_at_one_sigma(s):
+    """1500 replicates of n = 4000 trajectories, each in the slot with probability 0.03, with
+    lognormal weights (mu = -5) there: the interval holds the true mass 0.03 e^(mu + s^2/2) in
+    68.3 % of replicates.  With nearly constant weights (s = 0.05) Cox's part alone is far too
+    narrow: the count fluctuation dominates."""
+    rng = np.random.default_rng(int(100 * s))
+    R, n, q, mu = 1500, 4000, 0.03, -5.0
+    truth = q * math.exp(mu + 0.5 * s * s)
+    cover = cover_cox = 0
+    for r in range(R):
+        nj = rng.binomial(n, q)
+        lnw = rng.normal(mu, s, size=nj)
+        p, lo, hi = E.lognormal(n, [nj], [lnw.sum()], [(lnw ** 2).sum()])
+        cover += lo[0] <= truth <= hi[0]
+        th = math.log(p[0])
+        s2 = lnw.var(ddof=1)
+        se = math.sqrt(s2 / nj + s2 * s2 / (2 * (nj - 1)))
+        cover_cox += math.exp(th - se) <= truth <= math.exp(th + se)
+    assert abs(cover / R - 0.6827) < 0.04, cover / R
+    if s == 0.05:
+        assert cover_cox / R < 0.2
