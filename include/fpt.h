@@ -406,6 +406,45 @@ int fpt_batch_last_ms(fpt_batch *b, double *ms);
 /* Free the batch (waits for the device; NULL is allowed). */
 void fpt_batch_destroy(fpt_batch *b);
 
+/* ---- error bars (Sec. 4.1) -------------------------------------------------- */
+
+/* Histogram slots throughout: n_slots = n_bins + 2 (underflow, the bins, overflow),
+ * the layout of fpt_hist.  "Mass" is sum_w / n_traj of a slot; divide by the bin
+ * width for the density.  All arrays are host memory owned by the caller; these
+ * calls run on the host and need no device. */
+
+/* Direct sampling: the paper resamples independent runs.  Delete-one jackknife over
+ * n_blocks >= 2 blocks of trajectories (for example consecutive fpt_run calls, each
+ * read with fpt_histogram and cleared with fpt_reset).  n_traj[b] is block b's
+ * trajectory count; sum_w is row-major [n_blocks][n_slots].  p_out is the mass of
+ * all blocks together.  err_out is sqrt((B - 1)/B sum_b (p_(b) - mean p_(b))^2),
+ * where p_(b) = (sum sum_w - sum_w[b]) / (sum n - n_b).  Errors: FPT_EINVAL (sizes,
+ * NULL, a block with no trajectories, non-finite sums). */
+int fpt_jackknife(int32_t n_slots, int32_t n_blocks, const uint64_t *n_traj, const double *sum_w, double *p_out,
+                  double *err_out);
+
+/* Importance sampling: the paper takes the error of a slot from the error of the
+ * mean of a lognormal distribution.  Within slot j the n_j = count[j] values of
+ * ln w are taken as normal, with mean mu = sum_lnw/n_j and variance
+ * s^2 = (sum_lnw2 - n_j mu^2)/(n_j - 1).  Outputs:
+ *   p_out  = (n_j/n_traj) exp(mu + s^2/2);
+ *   lo_out, hi_out = p_out exp(-+se), the one-sigma interval of ln(mass), with
+ *            se^2 = s^2/n_j + s^4/(2 (n_j - 1))  (Cox's, for ln of the mean weight)
+ *                 + (1 - n_j/n_traj)/n_j         (the count's binomial fluctuation).
+ * With constant weights the interval is the binomial one.  All three are NaN where
+ * n_j < 2.  The inputs are fpt_hist's count, sum_lnw_bin and sum_lnw2_bin.
+ * Errors: FPT_EINVAL (sizes, NULL, n_traj == 0). */
+int fpt_lognormal_bins(int32_t n_slots, uint64_t n_traj, const uint64_t *count, const double *sum_lnw,
+                       const double *sum_lnw2, double *p_out, double *lo_out, double *hi_out);
+
+/* Several bias amplitudes: the inverse-variance weighted mean per slot over n_runs
+ * runs, p and err row-major [n_runs][n_slots].  In each slot, a run with a
+ * non-finite value or error, or an error <= 0, is left out.  p_out = sum (p/err^2)
+ * / sum (1/err^2) and err_out = 1/sqrt(sum (1/err^2)); both are NaN where no run is
+ * left.  Errors: FPT_EINVAL (sizes, NULL). */
+int fpt_merge_bins(int32_t n_slots, int32_t n_runs, const double *p, const double *err, double *p_out,
+                   double *err_out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -9,7 +9,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libfpt.so")
-SOURCES = ["fpt_api.hip", "fpt_em.hip", "fpt_mlp.hip", "fpt_table.hip"]
+SOURCES = ["fpt_api.hip", "fpt_em.hip", "fpt_mlp.hip", "fpt_table.hip", "fpt_stats.hip"]
 ARCH = "gfx950"
 
 

@@ -1373,3 +1373,8 @@ extern "C" const char *fpt_strerror(int status)
 }
 
 extern "C" const char *fpt_last_error(void) { return g_last_error.c_str(); }
+
+namespace fpt {
+// The last-error message and status of the C ABI, for the other translation units.
+int report_error(int code, const char *msg) { return fail(code, "%s", msg); }
+}  // namespace fpt

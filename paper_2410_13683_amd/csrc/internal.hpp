@@ -170,4 +170,7 @@ hipError_t matched_table_launch(const PotParams &pot, double sigma, int n, doubl
                                 double phi_start, double pi_start, void *scratch, double *d_S, double *d_tan,
                                 double *d_fac, int *d_status, hipStream_t stream);
 
+// Sets the message fpt_last_error returns and returns code (defined in fpt_api.hip).
+int report_error(int code, const char *msg);
+
 }  // namespace fpt

@@ -129,6 +129,9 @@ def load():
                                            ctypes.c_double, _dp, _dp, _dp]
     L.fpt_noise_table_matched.argtypes = [P(fpt_potential), ctypes.c_double, ctypes.c_int32, ctypes.c_double,
                                           ctypes.c_double, ctypes.c_double, ctypes.c_double, _dp, _dp, _dp]
+    L.fpt_jackknife.argtypes = [ctypes.c_int32, ctypes.c_int32, _u64p, _dp, _dp, _dp]
+    L.fpt_lognormal_bins.argtypes = [ctypes.c_int32, ctypes.c_uint64, _u64p, _dp, _dp, _dp, _dp, _dp]
+    L.fpt_merge_bins.argtypes = [ctypes.c_int32, ctypes.c_int32, _dp, _dp, _dp, _dp]
     L.fpt_batch_create.argtypes = [P(ctypes.c_void_p), ctypes.c_int32, P(fpt_batch_options), P(ctypes.c_void_p)]
     L.fpt_batch_run.argtypes = [ctypes.c_void_p, _u64p, ctypes.c_double, ctypes.c_uint64, ctypes.c_uint64,
                                 ctypes.c_void_p]
@@ -147,7 +150,8 @@ def load():
     L.fpt_mlp_adam.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                ctypes.c_double, ctypes.c_void_p]
     for name in ("fpt_create", "fpt_run", "fpt_histogram", "fpt_reset", "fpt_last_kernel_ms",
-                 "fpt_noise_table_bessel", "fpt_noise_table_bessel2d", "fpt_noise_table_matched", "fpt_batch_create", "fpt_batch_run", "fpt_batch_autotune",
+                 "fpt_noise_table_bessel", "fpt_noise_table_bessel2d", "fpt_noise_table_matched", "fpt_jackknife", "fpt_lognormal_bins",
+                 "fpt_merge_bins", "fpt_batch_create", "fpt_batch_run", "fpt_batch_autotune",
                  "fpt_batch_config", "fpt_batch_last_ms", "fpt_mlp_set", "fpt_mlp_get", "fpt_mlp_table",
                  "fpt_mlp_grad", "fpt_mlp_adam"):
         getattr(L, name).restype = ctypes.c_int
@@ -211,6 +215,43 @@ def fpt_noise_table_matched(pot: fpt_potential, sigma: float, n: int, phi_lo: fl
                                           S.ctypes.data_as(_dp), t.ctypes.data_as(_dp), fac.ctypes.data_as(_dp)),
            "fpt_noise_table_matched")
     return S, t, fac
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def fpt_jackknife(n_traj_blocks, sum_w_blocks):
+    """(mass, error) per histogram slot from blocks of trajectories: delete-one jackknife."""
+    n = np.ascontiguousarray(n_traj_blocks, dtype=np.uint64)
+    sw = _f64(sum_w_blocks)
+    B, ns = sw.shape
+    p, e = np.empty(ns), np.empty(ns)
+    _check(load().fpt_jackknife(ns, B, n.ctypes.data_as(_u64p), sw.ctypes.data_as(_dp), p.ctypes.data_as(_dp),
+                                e.ctypes.data_as(_dp)), "fpt_jackknife")
+    return p, e
+
+
+def fpt_lognormal_bins(n_traj, count, sum_lnw, sum_lnw2):
+    """(mass, lo, hi) per slot: the lognormal mean of the slot's weights and Cox's one-sigma interval."""
+    c = np.ascontiguousarray(count, dtype=np.uint64)
+    a, b = _f64(sum_lnw), _f64(sum_lnw2)
+    ns = len(c)
+    p, lo, hi = np.empty(ns), np.empty(ns), np.empty(ns)
+    _check(load().fpt_lognormal_bins(ns, int(n_traj), c.ctypes.data_as(_u64p), a.ctypes.data_as(_dp),
+                                     b.ctypes.data_as(_dp), p.ctypes.data_as(_dp), lo.ctypes.data_as(_dp),
+                                     hi.ctypes.data_as(_dp)), "fpt_lognormal_bins")
+    return p, lo, hi
+
+
+def fpt_merge_bins(p_runs, err_runs):
+    """Inverse-variance merge per slot over runs (rows)."""
+    P, E = _f64(p_runs), _f64(err_runs)
+    R, ns = P.shape
+    p, e = np.empty(ns), np.empty(ns)
+    _check(load().fpt_merge_bins(ns, R, P.ctypes.data_as(_dp), E.ctypes.data_as(_dp), p.ctypes.data_as(_dp),
+                                 e.ctypes.data_as(_dp)), "fpt_merge_bins")
+    return p, e
 
 
 class Context:

@@ -73,3 +73,24 @@ def tail_ess(hist: dict, n_bins: int, bins_kind: int, lo: float, hi: float, p_ta
             x = edges[j - 1] if j <= n_bins else hi
             return float(x), float(tail[j]), float(ess), int(c)
     return None, 0.0, 0.0, 0
+
+
+def run_blocks(ctx: fpt.Context, w: Workload, n_blocks: int, stream, traj_offset: int = 0):
+    """Run w.n_traj trajectories as n_blocks consecutive blocks (trajectories traj_offset + b*m ..),
+    reading and clearing the context's histogram after each.  Returns the per-block n_traj and
+    sum_w arrays (inputs of fpt_jackknife) and the histogram of all blocks together."""
+    m = w.n_traj // n_blocks
+    ctx.reset()
+    n_b, sw_b, total = [], [], None
+    for b in range(n_blocks):
+        ctx.run(m, w.dN, w.seed, traj_offset + b * m, stream)
+        h = ctx.histogram()
+        ctx.reset()
+        n_b.append(int(h["n_traj"]))
+        sw_b.append(np.asarray(h["sum_w"], dtype=np.float64))
+        if total is None:
+            total = {k: (np.array(v, copy=True) if isinstance(v, np.ndarray) else v) for k, v in h.items()}
+        else:
+            for k, v in h.items():
+                total[k] = total[k] + v
+    return np.asarray(n_b, dtype=np.uint64), np.stack(sw_b), total
