@@ -164,6 +164,25 @@ def tail_at(hist, w, x):
     return sw / n, (sw * sw / sw2 if sw2 > 0 else 0.0), int(hist["count"][j + 1:].sum())
 
 
+def tail_errors(hist, w, x) -> dict:
+    """One-sigma errors of P(deltaN >= x): the plain standard error of sum w 1_T / n, and the
+    per-bin lognormal intervals of fpt_lognormal_bins added in quadrature over the tail bins."""
+    import math
+    import numpy as np
+    from paper_2410_13683_amd import fpt
+    edges = w.lo * (w.hi / w.lo) ** (np.arange(w.n_bins + 1) / w.n_bins) if w.bins_kind else \
+        w.lo + (w.hi - w.lo) * np.arange(w.n_bins + 1) / w.n_bins
+    j0 = int(np.argmin(np.abs(edges - x))) + 1       # first slot of the tail set
+    n = max(int(hist["n_traj"]), 1)
+    sw = float(hist["sum_w"][j0:].sum())
+    sw2 = float(hist["sum_w2"][j0:].sum())
+    plain = math.sqrt(max(sw2 / n - (sw / n) ** 2, 0.0) / n)
+    p, lo, hi = fpt.fpt_lognormal_bins(n, hist["count"], hist["sum_lnw"], hist["sum_lnw2"])
+    half = 0.5 * (hi - lo)[j0:]
+    half = half[np.isfinite(half)]
+    return {"P_tail_err": plain, "P_tail_err_lognormal": float(math.sqrt((half ** 2).sum()))}
+
+
 def train_learned(w, stream, train_traj: float = 1e7, iters: int = 40, lr: float = 0.03) -> dict:
     """Constant-bias fallback passes, then GPU training of the learned control (see the module
     docstring).  Returns the context holding the trained network and the figures."""
@@ -402,7 +421,8 @@ def main() -> int:
         },
         "ess_tail_per_s": ess_rate,
         "tail": {"deltaN_star": x_star, "P_tail": p_star, "ESS_T": ess_T, "samples_in_T": n_T,
-                 "t_5pct_s": (400.0 / ess_rate) if ess_rate > 0 else None},
+                 "t_5pct_s": (400.0 / ess_rate) if ess_rate > 0 else None,
+                 **(tail_errors(hist, w, x_star) if x_star is not None else {})},
         "trajectory_steps": steps_total,
         "table_setup_s": table_s,
         "roofline": {
