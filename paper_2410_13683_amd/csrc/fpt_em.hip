@@ -75,17 +75,63 @@ __device__ __forceinline__ void philox4x32_10(uint32_t c0, uint32_t c1, uint32_t
     w[0] = c0; w[1] = c1; w[2] = c2; w[3] = c3;
 }
 
-// Box-Muller in FP64 on uniforms (w + 1/2) 2^-32 (exact in double); returns
-// xi sqrt(dN) for the two steps of the pair.
-__device__ __forceinline__ void box_muller64(uint32_t wa, uint32_t wb, double sqrt_dN, double &za, double &zb)
+// Box-Muller in FP64 on uniforms u = (w + 1/2) 2^-32 (exact in double), table-driven: two
+// 256-entry tables in LDS (kBmBytes, staged once per block by stage_bm) replace the library
+// log and sincos, each by a table read and a short series.
+//   ln u:  u = m 2^e, m in [0.5, 1).  Bucket i (top 8 fraction bits of m) has centre c_i
+//          (c_255 = 1, so that u near 1 loses nothing to cancellation), r_i = fl(1/c_i) and
+//          L_i = -ln r_i.  Then ln m = L_i + ln(1 + t), t = m r_i - 1, |t| <= 2^-9, and the
+//          series to t^7 leaves t^8/8 < 3e-23.
+//   2 pi u: (2 w + 1) 2^-33 = (j + 1/2)/256 + d 2^-33, j = w >> 24, d = 2 (w mod 2^24) + 1 - 2^24
+//          (an exact integer, |d| < 2^24).  sin and cos of A_j = 2 pi (j + 1/2)/256 come from
+//          the table; theta = 2 pi d 2^-33 (|theta| <= pi/256) from series to theta^7 and
+//          theta^6 (errors < 2e-23), and the angle-addition formulas combine them.
+// Returns xi sqrt(dN) for the two steps of the pair.
+constexpr int kBmN = 256;
+constexpr size_t kBmBytes = 2 * kBmN * sizeof(double2);
+
+// l_bm[j] = (sin A_j, cos A_j); l_bm[kBmN + i] = (r_i, L_i)
+__device__ __forceinline__ void stage_bm(double2 *l_bm)
+{
+    for (int i = threadIdx.x; i < 2 * kBmN; i += blockDim.x) {
+        if (i < kBmN) {
+            double sn, cs;
+            sincospi((i + 0.5) * (1.0 / 128.0), &sn, &cs);
+            l_bm[i] = make_double2(sn, cs);
+        } else {
+            const int k = i - kBmN;
+            const double c = (k == kBmN - 1) ? 1.0 : 0.5 * (1.0 + (k + 0.5) * (1.0 / 256.0));
+            const double r = 1.0 / c;
+            l_bm[i] = make_double2(r, -log(r));
+        }
+    }
+}
+
+__device__ __forceinline__ void box_muller64(uint32_t wa, uint32_t wb, double sqrt_dN, const double2 *l_bm,
+                                             double &za, double &zb)
 {
     const double ua = fma((double)wa, 0x1p-32, 0x1p-33);
-    const double ub = fma((double)wb, 0x1p-32, 0x1p-33);
-    const double rho = sqrt(-2.0 * log(ua)) * sqrt_dN;
-    double s, c;
-    sincospi(2.0 * ub, &s, &c);
-    za = rho * c;
-    zb = rho * s;
+    const double m = __builtin_amdgcn_frexp_mant(ua);        // [0.5, 1)
+    const int e = __builtin_amdgcn_frexp_exp(ua);
+    const int i = (__double2hiint(m) >> 12) & 0xff;
+    const double2 lt = l_bm[kBmN + i];
+    const double t = fma(m, lt.x, -1.0);
+    double q = fma(t, 1.0 / 7.0, -1.0 / 6.0);
+    q = fma(t, q, 0.2);
+    q = fma(t, q, -0.25);
+    q = fma(t, q, 1.0 / 3.0);
+    q = fma(t, q, -0.5);
+    q = fma(t, q, 1.0);
+    const double ln_u = fma((double)e, 0x1.62e42fefa39efp-1, fma(t, q, lt.y));   // e ln 2 + L_i + ln(1 + t)
+    const double rho = sqrt(-2.0 * ln_u) * sqrt_dN;
+    const int d = (int)((wb & 0xffffffu) << 1) + 1 - (1 << 24);
+    const double th = (double)d * 0x1.921fb54442d18p-31;                          // 2 pi d 2^-33
+    const double th2 = th * th;
+    const double sn = th * fma(th2, fma(th2, fma(th2, -1.0 / 5040.0, 1.0 / 120.0), -1.0 / 6.0), 1.0);
+    const double cs = fma(th2, fma(th2, fma(th2, -1.0 / 720.0, 1.0 / 24.0), -0.5), 1.0);
+    const double2 sc = l_bm[wb >> 24];
+    za = rho * fma(sc.y, cs, -sc.x * sn);      // cos(A + theta)
+    zb = rho * fma(sc.x, cs, sc.y * sn);       // sin(A + theta)
 }
 
 // Box-Muller in FP32 on uniforms fl32(w) 2^-32 + 2^-33: the same uniform as the
@@ -278,10 +324,12 @@ __device__ __forceinline__ double bump_dlnV(const BumpConsts &b, double phi)
 // staged as two equal nodes so one lookup serves every table.
 __device__ __forceinline__ int staged_nodes(const Inst &I) { return I.n_tab > 1 ? I.n_tab : 2; }
 
+// FP64 staging: the noise nodes, then the Box-Muller tables right after them.
 __device__ __forceinline__ void stage_table64(const Inst &I, double2 *l_tab)
 {
     const int n = staged_nodes(I);
     for (int i = threadIdx.x; i < n; i += blockDim.x) l_tab[i] = I.tab64[I.n_tab > 1 ? i : 0];
+    stage_bm(l_tab + n);
 }
 
 // FP32 staging: the noise nodes, then the V'/V intervals right after them (all
@@ -444,6 +492,7 @@ __device__ __forceinline__ void lanes_fp64(const Inst &I, const RunArgs &R, cons
     const BumpConsts bc = bump_consts(I);
     const GridConsts64 gc = grid_consts64(I);
     const double S0 = l_tab[0].x, t0 = l_tab[0].y;
+    const double2 *l_bm = l_tab + staged_nodes(I);
     const double dN = R.dN, sqrt_dN = R.sqrt_dN, phi_end = I.phi_end, phi_T = I.phi_T;
     const double a_const = (BIAS == kBiasConst) ? I.A : 0.0;
     const double half_a2_dN = 0.5 * a_const * a_const * dN;
@@ -561,8 +610,8 @@ __device__ __forceinline__ void lanes_fp64(const Inst &I, const RunArgs &R, cons
             uint32_t w[4];
             philox4x32_10(n >> 2, (uint32_t)tr, (uint32_t)(tr >> 32), I.instance, R.key0, R.key1, w);
             double z[4];
-            box_muller64(w[0], w[1], sqrt_dN, z[0], z[1]);
-            box_muller64(w[2], w[3], sqrt_dN, z[2], z[3]);
+            box_muller64(w[0], w[1], sqrt_dN, l_bm, z[0], z[1]);
+            box_muller64(w[2], w[3], sqrt_dN, l_bm, z[2], z[3]);
             if (__any(live && n + 4 > I.max_steps)) group(std::integral_constant<bool, true>(), z);
             else group(std::integral_constant<bool, false>(), z);
         }
@@ -853,6 +902,7 @@ __device__ __forceinline__ void lanes_fp64_2d(const Inst &I, const RunArgs &R, c
     const double a = (BIAS == kBiasConst) ? I.A : 0.0;
     const double half_a2_dN = 0.5 * a * a * dN;
     const double jmax = (double)(staged_nodes(I) - 2);
+    const double2 *l_bm = l_tab + 3 * staged_nodes(I);
     const double s_plus = in_vgpr(dk.s_plus), s_minus = in_vgpr(dk.s_minus);
 
     bool exhausted = false;
@@ -922,8 +972,8 @@ __device__ __forceinline__ void lanes_fp64_2d(const Inst &I, const RunArgs &R, c
             uint32_t w[4];
             philox4x32_10(n >> 1, (uint32_t)traj, (uint32_t)(traj >> 32), I.instance, R.key0, R.key1, w);
             double z[4];
-            box_muller64(w[0], w[1], sqrt_dN, z[0], z[1]);
-            box_muller64(w[2], w[3], sqrt_dN, z[2], z[3]);
+            box_muller64(w[0], w[1], sqrt_dN, l_bm, z[0], z[1]);
+            box_muller64(w[2], w[3], sqrt_dN, l_bm, z[2], z[3]);
             if (__any(live && n + 2 > I.max_steps)) group(std::integral_constant<bool, true>(), z);
             else group(std::integral_constant<bool, false>(), z);
         }
@@ -939,10 +989,12 @@ __device__ __forceinline__ void lanes_fp64_2d(const Inst &I, const RunArgs &R, c
     }
 }
 
+// 2D staging: three double2 per node, then the Box-Muller tables.
 __device__ __forceinline__ void stage_table64_2d(const Inst &I, double2 *l_tab)
 {
     const int n = staged_nodes(I);
     for (int i = threadIdx.x; i < 3 * n; i += blockDim.x) l_tab[i] = I.tab64_2d[I.n_tab > 1 ? i : i % 3];
+    stage_bm(l_tab + 3 * n);
 }
 
 // ---------------------------------------------------------------------------
@@ -951,9 +1003,11 @@ __device__ __forceinline__ void stage_table64_2d(const Inst &I, double2 *l_tab)
 // ---------------------------------------------------------------------------
 __host__ __device__ __forceinline__ size_t align16(size_t b) { return (b + 15) & ~(size_t)15; }
 // FP64: double2 per node; FP32: float4 per node plus the float2 V'/V interval
+// LDS of a staged table: FP64 nodes (16 B) and the Box-Muller tables, or FP32 nodes and V'/V
+// intervals (24 B per node).
 __host__ __device__ __forceinline__ size_t tab_bytes(int precision, int n_tab)
 {
-    return align16((size_t)(n_tab > 1 ? n_tab : 2) * (precision == 0 ? 16 : 24));
+    return align16((size_t)(n_tab > 1 ? n_tab : 2) * (precision == 0 ? 16 : 24)) + (precision == 0 ? kBmBytes : 0);
 }
 __host__ __device__ __forceinline__ size_t cell_bytes(int precision, int n_cells)
 {
@@ -1184,7 +1238,7 @@ hipError_t em_launch(const EmParams &p, int precision, int grid, int block, hipS
 
 size_t em2d_lds_bytes(int n_bins, int n_tab)
 {
-    return align16(acc_bytes(n_bins)) + (size_t)(n_tab > 1 ? n_tab : 2) * 48;
+    return align16(acc_bytes(n_bins)) + (size_t)(n_tab > 1 ? n_tab : 2) * 48 + kBmBytes;
 }
 
 const void *em2d_kernel_ptr(int bias_kind, bool all_pos)
