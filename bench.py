@@ -77,9 +77,9 @@ PEAK_HBM_GBS = 8000.0
 # process (FETCH_SIZE reads 0.5 GiB: x2.0; WRITE_SIZE reads 1 GiB: x1.0).  Valid only for the
 # kernel source it was measured on (hash of the kernel file and its header).
 MEASURED_TRAFFIC = {
-    "source_sha256": "9ffbb3e5b621988f110990e1a8bdd4027b374e762140aaaedd0a4dd52c64814f",
+    "source_sha256": "5f1effd42da92fd61f7b5bd523f0a14191cd2433fa2ee573e0b02d29313f33b5",
     "workload": "srusr_is_fp32_A2", "n_traj": 100_000_000,
-    "fetch_bytes": 467.1875 * 1024 * 2.0, "write_bytes": 2081034.84375 * 1024 * 1.0,
+    "fetch_bytes": 463.25 * 1024 * 2.0, "write_bytes": 2082597.5625 * 1024 * 1.0,
 }
 
 

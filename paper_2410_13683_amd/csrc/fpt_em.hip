@@ -107,6 +107,20 @@ __device__ __forceinline__ void stage_bm(double2 *l_bm)
     }
 }
 
+// sqrt(x) for x in [2e-10, 50] (here -2 ln u: never 0, denormal or infinite, so the library's
+// scaling and special-case tests are not needed): the hardware reciprocal square root, one
+// Goldschmidt step and two residual corrections, s = g + (x - g^2) h.
+__device__ __forceinline__ double sqrt_mid(double x)
+{
+    const double y = __builtin_amdgcn_rsq(x);
+    double g = x * y, h = 0.5 * y;
+    const double r = fma(-g, h, 0.5);
+    g = fma(g, r, g);
+    h = fma(h, r, h);
+    g = fma(fma(-g, g, x), h, g);
+    return fma(fma(-g, g, x), h, g);
+}
+
 __device__ __forceinline__ void box_muller64(uint32_t wa, uint32_t wb, double sqrt_dN, const double2 *l_bm,
                                              double &za, double &zb)
 {
@@ -123,7 +137,7 @@ __device__ __forceinline__ void box_muller64(uint32_t wa, uint32_t wb, double sq
     q = fma(t, q, -0.5);
     q = fma(t, q, 1.0);
     const double ln_u = fma((double)e, 0x1.62e42fefa39efp-1, fma(t, q, lt.y));   // e ln 2 + L_i + ln(1 + t)
-    const double rho = sqrt(-2.0 * ln_u) * sqrt_dN;
+    const double rho = sqrt_mid(-2.0 * ln_u) * sqrt_dN;
     const int d = (int)((wb & 0xffffffu) << 1) + 1 - (1 << 24);
     const double th = (double)d * 0x1.921fb54442d18p-31;                          // 2 pi d 2^-33
     const double th2 = th * th;
