@@ -396,6 +396,7 @@ typedef struct {
     int n_tab;
     double phi_lo, phi_hi;
     const double *S_tab, *t_tab;
+    int tab_axis;             /* 0: nodes in phi; 1: nodes in the run's time N = n dN (phi_lo, phi_hi hold N) */
     double phi_in, pi_in, phi_end;
     int bias_kind;
     double A_bias;
@@ -435,9 +436,10 @@ static void orc_trajectory(const orc_problem *P, uint64_t traj, double *N_out, d
         double dV = orc_dV(P->kind, P->pot, phi);
         double D_phi = pi_;
         double D_pi = -(3.0 - pi_ * pi_ / 2.0) * (pi_ + dV / V);
-        /* 1D noise amplitude and direction at the local field value */
+        /* 1D noise amplitude and direction at the local field value (or at the run's time) */
         double S, tan_theta;
-        orc_table_lookup(P->n_tab, P->phi_lo, P->phi_hi, P->S_tab, P->t_tab, phi, &S, &tan_theta);
+        orc_table_lookup(P->n_tab, P->phi_lo, P->phi_hi, P->S_tab, P->t_tab, P->tab_axis ? (double)n * dN : phi,
+                         &S, &tan_theta);
         /* bias amplitude A (constant or learned) and bias vector parallel to the noise */
         double A = 0.0;
         if (P->bias_kind == ORC_BIAS_CONST) {
@@ -488,7 +490,7 @@ static void orc_trajectory(const orc_problem *P, uint64_t traj, double *N_out, d
 /* Run n_traj trajectories with global indices traj_offset .. traj_offset+n_traj-1.
  * Returns 0, or -1 on invalid input.  n_threads <= 0 uses the OpenMP default. */
 int orc_run(int kind, const double pot[7],
-            int n_tab, double phi_lo, double phi_hi, const double *S_tab, const double *t_tab,
+            int n_tab, double phi_lo, double phi_hi, const double *S_tab, const double *t_tab, int tab_axis,
             double phi_in, double pi_in, double phi_end,
             int bias_kind, double A_bias, const float *mlp_params, const double *mlp_norm,
             int mlp_every, const int grid_n[2], const double grid_range[4],
@@ -498,6 +500,7 @@ int orc_run(int kind, const double pot[7],
     if (n_tab < 1 || !(dN > 0.0) || max_steps < 1 || max_steps > (int64_t)ORC_STEP_MASK) return -1;
     if (!(phi_in > phi_end)) return -1;
     if (bias_kind == ORC_BIAS_MLP && (!mlp_params || !mlp_norm || mlp_every < 0)) return -1;
+    if (tab_axis && bias_kind == ORC_BIAS_MLP) return -1;
     orc_problem P;
     memset(&P, 0, sizeof P);
     double *grid_a = NULL;
@@ -515,6 +518,7 @@ int orc_run(int kind, const double pot[7],
     P.kind = kind;
     memcpy(P.pot, pot, sizeof P.pot);
     P.n_tab = n_tab; P.phi_lo = phi_lo; P.phi_hi = phi_hi; P.S_tab = S_tab; P.t_tab = t_tab;
+    P.tab_axis = tab_axis ? 1 : 0;
     P.phi_in = phi_in; P.pi_in = pi_in; P.phi_end = phi_end;
     P.bias_kind = bias_kind; P.A_bias = A_bias; P.mlp = mlp_params;
     if (mlp_norm) memcpy(P.norm, mlp_norm, sizeof P.norm);
@@ -1236,21 +1240,125 @@ static double orc_nu_approx(int kind, const double pot[7], double phi)
     return nu2 > 0.0 ? sqrt(nu2) : NAN;
 }
 
-/* Bessel-matched 1D noise table, eq. (covariance_constant_nu_bessel_matched). */
-/* The classical trajectory starts at (phi_start, pi_start) at N = 0.  For each */
-/* node phi_j it reaches, N_sigma is the time it passes phi_j and the mode is   */
-/* k_j = sigma a H there.  That mode starts at the time k_j = 100 a H in the    */
-/* Bunch-Davies state, eq. (bunch_davies) with the first correction of the     */
-/* Hankel function's large-argument expansion, e^(i y) (1 + i c/y) / (a         */
-/* sqrt(2k)), c = (4 nu^2 - 1)/8, y = k/(aH) (overall phase dropped), and is    */
-/* evolved through eq. (full_delta_phi) to N_sigma, where eq. (bessel_matching) */
-/* with nu = nu(phi_j) and -k eta = sigma gives B_k.  The node's noise is the   */
-/* Bunch-Davies table's (eq. covariance_constant_nu) times sqrt(4 |B_k|^2/pi); */
-/* tan theta_n = nu - 3/2 is unchanged.  Nodes the trajectory does not reach    */
-/* keep the factor 1.  The mode of a node below the kink takes the kink's kick; */
-/* that of a node at or above it stops before it.  fac_out[j] = 4 |B_k|^2/pi.   */
-/* Returns 0; -1 on invalid input, on a node reached before its mode can start  */
-/* at k = 100 aH at N >= 0, or on a non-finite result.                         */
+/* Classical trajectory from (phi_start, pi_start) at N = 0, sampled every 1e-4 e-folds (the  */
+/* kink landed on exactly), until phi < phi_stop, N >= N_stop, eps1 >= 1 or N > 200.  When    */
+/* phi_ref is finite, *N_ref receives the time the trajectory passes it (NaN if it does not   */
+/* before stopping), and the sampling stops at N_ref + N_after instead of N_stop.  Returns    */
+/* the sample count, or 0 on allocation failure (arrays freed).                             */
+static void orc_hermite_root(const double *bN, const double *bphi, const double *bpi, size_t i, double target,
+                             double *N_out, double *pi_out);
+
+static size_t orc_background(int kind, const double pot[7], double phi_start, double pi_start, double phi_stop,
+                             double N_stop, double phi_ref, double N_after, double *N_ref, double **bN_out,
+                             double **bphi_out, double **bpi_out)
+{
+    const double hb = 1e-4;
+    size_t cap = (size_t)1 << 16, nb = 0;
+    double *bN = NULL, *bphi = NULL, *bpi = NULL;
+    orc_mode_state s = {phi_start, pi_start, 0.0, 0.0, 0.0, 0.0};
+    double N = 0.0;
+    if (N_ref) *N_ref = NAN;
+    for (;;) {
+        if (nb == 0 || nb == cap) {
+            if (nb) cap *= 2;
+            double *a = (double *)realloc(bN, sizeof(double) * cap);
+            if (a) bN = a;
+            double *b = a ? (double *)realloc(bphi, sizeof(double) * cap) : NULL;
+            if (b) bphi = b;
+            double *c = b ? (double *)realloc(bpi, sizeof(double) * cap) : NULL;
+            if (c) bpi = c;
+            if (!a || !b || !c) { free(bN); free(bphi); free(bpi); return 0; }
+        }
+        bN[nb] = N; bphi[nb] = s.phi; bpi[nb] = s.pi_; ++nb;
+        if (N_ref && isnan(*N_ref) && nb >= 2 && bphi[nb - 2] > phi_ref && bphi[nb - 1] <= phi_ref) {
+            double pr;
+            orc_hermite_root(bN, bphi, bpi, nb - 1, phi_ref, N_ref, &pr);
+            N_stop = *N_ref + N_after;
+        }
+        if (s.phi < phi_stop || N >= N_stop || 0.5 * s.pi_ * s.pi_ >= 1.0 || N > 200.0) break;
+        orc_mode_advance(kind, pot, 0.0, &N, N + hb, &s, 0, 1, hb);
+    }
+    *bN_out = bN; *bphi_out = bphi; *bpi_out = bpi;
+    return nb;
+}
+
+/* The time at which phi(N) reaches target inside samples [i-1, i] (bphi[i-1] > target >= bphi[i]): */
+/* the root of the cubic Hermite interpolant of phi, by Newton; pi there interpolated linearly.   */
+static void orc_hermite_root(const double *bN, const double *bphi, const double *bpi, size_t i, double target,
+                             double *N_out, double *pi_out)
+{
+    const double N0 = bN[i - 1], dn = bN[i] - bN[i - 1];
+    const double p0 = bphi[i - 1], p1 = bphi[i], m0 = bpi[i - 1] * dn, m1 = bpi[i] * dn;
+    double t = (p0 - target) / (p0 - p1);
+    for (int it = 0; it < 50; ++it) {
+        const double t2 = t * t, t3 = t2 * t;
+        const double v = (2 * t3 - 3 * t2 + 1) * p0 + (t3 - 2 * t2 + t) * m0 + (-2 * t3 + 3 * t2) * p1 +
+                         (t3 - t2) * m1 - target;
+        const double dv = (6 * t2 - 6 * t) * p0 + (3 * t2 - 4 * t + 1) * m0 + (-6 * t2 + 6 * t) * p1 +
+                          (3 * t2 - 2 * t) * m1;
+        const double step = v / dv;
+        t -= step;
+        if (fabs(step) < 1e-16) break;
+    }
+    *N_out = N0 + t * dn;
+    *pi_out = bpi[i - 1] + t * (bpi[i] - bpi[i - 1]);
+}
+
+/* 4|B_k|^2/pi of the mode that crosses k = sigma a H at N_sigma, where the classical trajectory */
+/* is at (phi_j, pi_j).  The mode starts at the last sample with k >= 100 aH in the            */
+/* Bunch-Davies state of eq. (bunch_davies), with the first correction of the Hankel            */
+/* function's large-argument expansion, e^(i y)(1 + i c/y)/(a sqrt(2k)), c = (4 nu^2 - 1)/8,     */
+/* y = k/(aH) (overall phase dropped).  It is evolved through eq. (full_delta_phi) to N_sigma   */
+/* (taking the kink's kick when phi_j < phi_T) and matched by eq. (bessel_matching) with        */
+/* nu = nu(phi_j) and -k eta = sigma.  Returns 0; -1 if the mode would have to start before    */
+/* N = 0; -2 on a non-finite or zero result.                                                   */
+static int orc_matched_factor(int kind, const double pot[7], double sigma, double phi_j, double pi_j, double Ns,
+                              const double *bN, const double *bphi, const double *bpi, size_t nb, double *fac_out)
+{
+    const double Hs = sqrt(orc_V(kind, pot, phi_j) / (3.0 - 0.5 * pi_j * pi_j));
+    const double k = sigma * exp(Ns) * Hs;
+    const double aH0 = sqrt(orc_V(kind, pot, bphi[0]) / (3.0 - 0.5 * bpi[0] * bpi[0]));
+    if (k < 100.0 * aH0) return -1;
+    size_t i0 = 0;
+    while (i0 + 1 < nb) {
+        const double aH = exp(bN[i0 + 1]) * sqrt(orc_V(kind, pot, bphi[i0 + 1]) /
+                                                 (3.0 - 0.5 * bpi[i0 + 1] * bpi[i0 + 1]));
+        if (k < 100.0 * aH) break;
+        ++i0;
+    }
+    orc_mode_state st = {bphi[i0], bpi[i0], 0.0, 0.0, 0.0, 0.0};
+    double Nm = bN[i0];
+    {
+        const double a = exp(Nm);
+        const double y = k / (a * sqrt(orc_V(kind, pot, st.phi) / (3.0 - 0.5 * st.pi_ * st.pi_)));
+        const double c = (4.0 * orc_nu2_approx(kind, pot, st.phi) - 1.0) / 8.0;
+        const double complex F = (1.0 + I * c / y) / (a * sqrt(2.0 * k));
+        /* d/dN [e^(iy) (1 + ic/y) / a] e^(-iy) = [(-1 - iy)(1 + ic/y) + ic/y] / a */
+        const double complex G = ((-1.0 - I * y) * (1.0 + I * c / y) + I * c / y) / (a * sqrt(2.0 * k));
+        st.fr = creal(F); st.fi = cimag(F);
+        st.gr = creal(G); st.gi = cimag(G);
+    }
+    orc_mode_advance(kind, pot, k, &Nm, Ns, &st, 1, phi_j < pot[1], 2.5e-4);
+    const double nu_j = orc_nu_approx(kind, pot, phi_j);
+    const double dphi[2] = {st.fr, st.fi}, ddphi[2] = {st.gr, st.gi};
+    double A[2], B[2];
+    /* a/sqrt(-eta) at -k eta = sigma: e^N sqrt(k/sigma) */
+    orc_bessel_match(nu_j, sigma, exp(Nm) * sqrt(k / sigma), dphi, ddphi, A, B);
+    const double fac = 4.0 * (B[0] * B[0] + B[1] * B[1]) / M_PI;
+    if (!(fac > 0.0) || !isfinite(fac)) return -2;
+    *fac_out = fac;
+    return 0;
+}
+
+/* Bessel-matched 1D noise table, eq. (covariance_constant_nu_bessel_matched), on nodes in phi. */
+/* For each node phi_j the classical trajectory from (phi_start, pi_start) reaches, N_sigma is   */
+/* the time it passes phi_j; the node's noise is the Bunch-Davies table's (eq.                  */
+/* covariance_constant_nu) times sqrt(4 |B_k|^2/pi) of orc_matched_factor; tan theta_n = nu -   */
+/* 3/2 is unchanged.  Nodes the trajectory does not reach (at or above phi_start, or beyond     */
+/* where it is followed: phi < phi_lo, eps1 >= 1 or N > 200) keep the factor 1.  A node below   */
+/* the kink takes the kick; one at or above it stops before it.  fac_out[j] = 4 |B_k|^2/pi.     */
+/* Returns 0; -1 on invalid input, on a node reached before its mode can start at k = 100 aH at */
+/* N >= 0, or on a non-finite result.                                                          */
 int orc_noise_table_matched(int kind, const double pot[7], double sigma, int n, double phi_lo, double phi_hi,
                             double phi_start, double pi_start, double *S_out, double *tan_out, double *fac_out,
                             int n_threads)
@@ -1258,32 +1366,10 @@ int orc_noise_table_matched(int kind, const double pot[7], double sigma, int n, 
     if (orc_noise_table_bessel(kind, pot, sigma, n, phi_lo, phi_hi, S_out, tan_out) != 0) return -1;
     if (!(sigma > 0.0) || sigma > 2.0) return -1;
     const double h = (n > 1) ? (phi_hi - phi_lo) / (double)(n - 1) : 0.0;
-    const double phi_T = pot[1];
-
-    /* classical trajectory, sampled every 1e-4 e-folds, until phi < phi_lo,    */
-    /* eps1 >= 1 or N > 200                                                     */
-    const double hb = 1e-4;
-    size_t cap = (size_t)1 << 16, nb = 0;
-    double *bN = NULL, *bphi = NULL, *bpi = NULL;
-    orc_mode_state s = {phi_start, pi_start, 0.0, 0.0, 0.0, 0.0};
-    double N = 0.0;
-    int fail = 0;
-    for (;;) {
-        if (nb == 0 || nb == cap) {
-            if (nb) cap *= 2;
-            double *a = (double *)realloc(bN, sizeof(double) * cap), *b = a ? (double *)realloc(bphi, sizeof(double) * cap) : NULL;
-            double *c = b ? (double *)realloc(bpi, sizeof(double) * cap) : NULL;
-            if (a) bN = a;
-            if (b) bphi = b;
-            if (c) bpi = c;
-            if (!a || !b || !c) { fail = 1; break; }
-        }
-        bN[nb] = N; bphi[nb] = s.phi; bpi[nb] = s.pi_; ++nb;
-        if (s.phi < phi_lo || 0.5 * s.pi_ * s.pi_ >= 1.0 || N > 200.0) break;
-        orc_mode_advance(kind, pot, 0.0, &N, N + hb, &s, 0, 1, hb);
-    }
-    if (fail) { free(bN); free(bphi); free(bpi); return -1; }
-
+    double *bN, *bphi, *bpi;
+    const size_t nb = orc_background(kind, pot, phi_start, pi_start, phi_lo, INFINITY, NAN, 0.0, NULL, &bN, &bphi,
+                                     &bpi);
+    if (nb == 0) return -1;
 #ifdef _OPENMP
     if (n_threads > 0) omp_set_num_threads(n_threads);
 #else
@@ -1298,60 +1384,67 @@ int orc_noise_table_matched(int kind, const double pot[7], double sigma, int n, 
         size_t i = 1;
         while (i < nb && bphi[i] > phi_j) ++i;
         if (i >= nb) continue;                                /* never reached */
-        /* N_sigma: root of the cubic Hermite interpolant of phi(N) on [N_{i-1}, N_i] */
-        const double N0 = bN[i - 1], dn = bN[i] - bN[i - 1];
-        const double p0 = bphi[i - 1], p1 = bphi[i], m0 = bpi[i - 1] * dn, m1 = bpi[i] * dn;
-        double t = (p0 - phi_j) / (p0 - p1);
-        for (int it = 0; it < 50; ++it) {
-            const double t2 = t * t, t3 = t2 * t;
-            const double v = (2 * t3 - 3 * t2 + 1) * p0 + (t3 - 2 * t2 + t) * m0 + (-2 * t3 + 3 * t2) * p1 +
-                             (t3 - t2) * m1 - phi_j;
-            const double dv = (6 * t2 - 6 * t) * p0 + (3 * t2 - 4 * t + 1) * m0 + (-6 * t2 + 6 * t) * p1 +
-                              (3 * t2 - 2 * t) * m1;
-            const double step = v / dv;
-            t -= step;
-            if (fabs(step) < 1e-16) break;
-        }
-        const double Ns = N0 + t * dn;
-        const double pis = bpi[i - 1] + t * (bpi[i] - bpi[i - 1]);
-        const double Hs = sqrt(orc_V(kind, pot, phi_j) / (3.0 - 0.5 * pis * pis));
-        const double k = sigma * exp(Ns) * Hs;
-        /* start: the last sample with k >= 100 aH */
-        size_t i0 = 0;
-        {
-            const double aH0 = sqrt(orc_V(kind, pot, bphi[0]) / (3.0 - 0.5 * bpi[0] * bpi[0]));
-            if (k < 100.0 * aH0) {
+        double Ns, pis, fac;
+        orc_hermite_root(bN, bphi, bpi, i, phi_j, &Ns, &pis);
+        if (orc_matched_factor(kind, pot, sigma, phi_j, pis, Ns, bN, bphi, bpi, nb, &fac) != 0) {
 #pragma omp atomic write
-                bad = 1;
-                continue;
-            }
+            bad = 1;
+            continue;
         }
-        while (i0 + 1 < nb) {
-            const double aH = exp(bN[i0 + 1]) * sqrt(orc_V(kind, pot, bphi[i0 + 1]) /
-                                                     (3.0 - 0.5 * bpi[i0 + 1] * bpi[i0 + 1]));
-            if (k < 100.0 * aH) break;
-            ++i0;
+        fac_out[j] = fac;
+        S_out[j] *= sqrt(fac);
+    }
+    free(bN); free(bphi); free(bpi);
+    return bad ? -1 : 0;
+}
+
+/* The same noise on nodes in time: node j is the time tau_j = t_lo + j (t_hi - t_lo)/(n - 1)  */
+/* after the classical trajectory from (phi_start, pi_start) passes phi_ref (the run's phi_in), */
+/* so that a run indexes it by its own time n dN -- the paper's scheme, noise precomputed along */
+/* the classical trajectory and indexed by time (Sec. 4.1).  Node j takes phi_j, pi_j of the   */
+/* trajectory at N_sigma = N_ref + tau_j (cubic Hermite interpolation of phi, linear of pi),   */
+/* the Bunch-Davies node and nu at phi_j, and the factor of orc_matched_factor.  phi_out[j]     */
+/* (if not NULL) receives phi_j.  Returns 0; -1 on invalid input, if the trajectory does not   */
+/* pass phi_ref, if a node lies outside the followed trajectory, or as orc_noise_table_matched.  */
+int orc_noise_table_matched_time(int kind, const double pot[7], double sigma, int n, double t_lo, double t_hi,
+                                 double phi_start, double pi_start, double phi_ref, double *S_out, double *tan_out,
+                                 double *fac_out, double *phi_out, int n_threads)
+{
+    if (n < 1 || !(sigma > 0.0) || sigma > 2.0) return -1;
+    if (n > 1 && !(t_hi > t_lo)) return -1;
+    if (!(phi_start > phi_ref)) return -1;
+    const double h = (n > 1) ? (t_hi - t_lo) / (double)(n - 1) : 0.0;
+    double *bN, *bphi, *bpi, N_ref;
+    const size_t nb = orc_background(kind, pot, phi_start, pi_start, -INFINITY, INFINITY, phi_ref,
+                                     (n > 1 ? t_hi : t_lo) + 2e-4, &N_ref, &bN, &bphi, &bpi);
+    if (nb == 0) return -1;
+    if (isnan(N_ref)) { free(bN); free(bphi); free(bpi); return -1; }
+#ifdef _OPENMP
+    if (n_threads > 0) omp_set_num_threads(n_threads);
+#else
+    (void)n_threads;
+#endif
+    int bad = 0;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int j = 0; j < n; ++j) {
+        const double Ns = N_ref + t_lo + (double)j * h;
+        fac_out[j] = NAN;
+        if (!(Ns >= bN[0]) || !(Ns <= bN[nb - 1])) {
+#pragma omp atomic write
+            bad = 1;
+            continue;
         }
-        orc_mode_state st = {bphi[i0], bpi[i0], 0.0, 0.0, 0.0, 0.0};
-        double Nm = bN[i0];
-        {
-            const double a = exp(Nm);
-            const double y = k / (a * sqrt(orc_V(kind, pot, st.phi) / (3.0 - 0.5 * st.pi_ * st.pi_)));
-            const double c = (4.0 * orc_nu2_approx(kind, pot, st.phi) - 1.0) / 8.0;
-            const double complex F = (1.0 + I * c / y) / (a * sqrt(2.0 * k));
-            /* d/dN [e^(iy) (1 + ic/y) / a] e^(-iy) = [(-1 - iy)(1 + ic/y) + ic/y] / a */
-            const double complex G = ((-1.0 - I * y) * (1.0 + I * c / y) + I * c / y) / (a * sqrt(2.0 * k));
-            st.fr = creal(F); st.fi = cimag(F);
-            st.gr = creal(G); st.gi = cimag(G);
-        }
-        orc_mode_advance(kind, pot, k, &Nm, Ns, &st, 1, phi_j < phi_T, 2.5e-4);
-        const double nu_j = orc_nu_approx(kind, pot, phi_j);
-        const double dphi[2] = {st.fr, st.fi}, ddphi[2] = {st.gr, st.gi};
-        double A[2], B[2];
-        /* a/sqrt(-eta) at -k eta = sigma: e^N sqrt(k/sigma) */
-        orc_bessel_match(nu_j, sigma, exp(Nm) * sqrt(k / sigma), dphi, ddphi, A, B);
-        const double fac = 4.0 * (B[0] * B[0] + B[1] * B[1]) / M_PI;
-        if (!(fac > 0.0) || !isfinite(fac)) {
+        size_t i = 1;
+        while (i < nb - 1 && bN[i] < Ns) ++i;              /* bN[i-1] <= Ns <= bN[i] */
+        const double dn = bN[i] - bN[i - 1], t = (Ns - bN[i - 1]) / dn;
+        const double t2 = t * t, t3 = t2 * t;
+        const double phi_j = (2 * t3 - 3 * t2 + 1) * bphi[i - 1] + (t3 - 2 * t2 + t) * bpi[i - 1] * dn +
+                             (-2 * t3 + 3 * t2) * bphi[i] + (t3 - t2) * bpi[i] * dn;
+        const double pi_j = bpi[i - 1] + t * (bpi[i] - bpi[i - 1]);
+        if (phi_out) phi_out[j] = phi_j;
+        double fac;
+        if (orc_noise_table_bessel(kind, pot, sigma, 1, phi_j, phi_j, &S_out[j], &tan_out[j]) != 0 ||
+            orc_matched_factor(kind, pot, sigma, phi_j, pi_j, Ns, bN, bphi, bpi, nb, &fac) != 0) {
 #pragma omp atomic write
             bad = 1;
             continue;

@@ -73,7 +73,7 @@ def lib():
                                              ctypes.c_double, ctypes.c_double, dp, dp]
         L.orc_noise_table_bessel.restype = ctypes.c_int
         ip = ctypes.POINTER(ctypes.c_int)
-        L.orc_run.argtypes = [ctypes.c_int, dp, ctypes.c_int, ctypes.c_double, ctypes.c_double, dp, dp,
+        L.orc_run.argtypes = [ctypes.c_int, dp, ctypes.c_int, ctypes.c_double, ctypes.c_double, dp, dp, ctypes.c_int,
                               ctypes.c_double, ctypes.c_double, ctypes.c_double,
                               ctypes.c_int, ctypes.c_double, fp, dp, ctypes.c_int, ip, dp,
                               ctypes.c_double, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint64,
@@ -122,6 +122,10 @@ def lib():
                                               ctypes.c_double, ctypes.c_double, ctypes.c_double, dp, dp, dp,
                                               ctypes.c_int]
         L.orc_noise_table_matched.restype = ctypes.c_int
+        L.orc_noise_table_matched_time.argtypes = [ctypes.c_int, dp, ctypes.c_double, ctypes.c_int, ctypes.c_double,
+                                                   ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                                   ctypes.c_double, dp, dp, dp, dp, ctypes.c_int]
+        L.orc_noise_table_matched_time.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -187,6 +191,7 @@ class Problem:
     grid_n: tuple = (2, 2)            # tabulation grid over the normalised inputs (x0, x1)
     grid_range: tuple = (-1.0, 1.0, -1.0, 1.0)
     bump: tuple = (0.0, 0.0, 0.0)     # (m, K, Sigma) of the Gaussian bump (phi_0 = phi_T)
+    tab_axis: int = 0                 # 0: table nodes in phi; 1: in the run's time N = n dN
 
     def pot(self) -> np.ndarray:
         return _pot_array(self.V0, self.phi_T, self.A_plus, self.A_minus, self.bump)
@@ -236,6 +241,20 @@ def noise_table_matched(kind, V0, phi_T, A_plus, A_minus, sigma, n, phi_lo, phi_
     return S, t, fac
 
 
+def noise_table_matched_time(kind, V0, phi_T, A_plus, A_minus, sigma, n, t_lo, t_hi, phi_start, pi_start,
+                             phi_ref, n_threads: int = 0, bump=(0.0, 0.0, 0.0)):
+    """The matched table on nodes in time after the classical trajectory passes phi_ref:
+    (S, tan_theta, 4|B_k|^2/pi, phi at the nodes)."""
+    p = _pot_array(V0, phi_T, A_plus, A_minus, bump)
+    S = np.empty(n); t = np.empty(n); fac = np.empty(n); ph = np.empty(n)
+    rc = lib().orc_noise_table_matched_time(kind, _dp(p), sigma, n, t_lo, t_hi, phi_start, pi_start, phi_ref,
+                                            _dp(S), _dp(t), _dp(fac), _dp(ph), n_threads)
+    if rc != 0:
+        raise ValueError("invalid time-node matched table (start too late, phi_ref not passed, or a node "
+                         "outside the trajectory)")
+    return S, t, fac, ph
+
+
 def run(prob: Problem, dN: float, seed: int, n_traj: int, traj_offset: int = 0, instance: int = 0,
         max_steps: int = STEP_MASK, n_threads: int = 0):
     """Per-trajectory (N, ln w, steps|flags) for trajectories traj_offset .. +n_traj-1."""
@@ -251,7 +270,7 @@ def run(prob: Problem, dN: float, seed: int, n_traj: int, traj_offset: int = 0, 
     pot = prob.pot()
     gn = (ctypes.c_int * 2)(*prob.grid_n)
     gr = np.ascontiguousarray(prob.grid_range, dtype=np.float64)
-    rc = lib().orc_run(prob.kind, _dp(pot), len(S), prob.phi_lo, prob.phi_hi, _dp(S), _dp(t),
+    rc = lib().orc_run(prob.kind, _dp(pot), len(S), prob.phi_lo, prob.phi_hi, _dp(S), _dp(t), int(prob.tab_axis),
                        prob.phi_in, prob.pi_in, prob.phi_end, prob.bias_kind, prob.A_bias,
                        _fp(mlp), _dp(norm), prob.mlp_every, gn, _dp(gr), dN, seed, instance, traj_offset,
                        n_traj, max_steps, _dp(N), _dp(lnw), _u32p(steps), n_threads)
