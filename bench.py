@@ -67,6 +67,10 @@ ALG_FLOPS_2D = {"none": 71.0, "const": 89.0}
 # numerator 2 m^2 d2 - x g d1, the denominator and an IEEE division (reciprocal, two Newton steps and
 # the correction) = 28 FLOPs in place of the linear potentials' 13
 ALG_FLOPS_BUMP_FP64 = 58.5 - 13.0 + 28.0
+# FP32 state on a time-indexed table: V'/V exactly (phi - phi_T from the float pair, 3; the branch's
+# compare, 1; the FMA, 2; the reciprocal, 1) in place of its interpolation and NaN test (3); the last
+# node is zero, so the weight tests S > 0 (1)
+ALG_FLOPS_TIME_FP32 = 51.5 - 3.0 + 7.0 + 1.0
 ALG_INT_OPS_PER_STEP = 16.0          # Philox4x32-10 amortised over 4 steps + uniform conversions
 PEAK_TFLOPS = {"fp32": 157.3, "fp64": 78.6}   # MI355X published vector peaks
 PEAK_HBM_GBS = 8000.0
@@ -115,6 +119,8 @@ def _workload(name: str, n_traj: int | None):
         w = W.srusr_2d()
     elif name == "srusr_matched":
         w = W.srusr_is_fp32_matched(A_bias=2.0)
+    elif name == "srusr_time":
+        w = W.srusr_is_fp32_time(A_bias=2.0)
     elif name == "bump":
         w = W.gaussian_bump_is(A_bias=3.0)
     else:
@@ -390,6 +396,8 @@ def main() -> int:
         flops_step = ALG_FLOPS_2D["const" if w.bias_kind else "none"]
     if w.kind == 2:
         flops_step = ALG_FLOPS_BUMP_FP64
+    if w.noise == "matched_time" and prec == "fp32":
+        flops_step = ALG_FLOPS_TIME_FP32
     achieved = flops_step * steps_per_launch / (avg_ms * 1e-3) / 1e12
     result = {
         "metric": METRIC,
@@ -412,7 +420,11 @@ def main() -> int:
             "noise": (f"2D noise, full Bunch-Davies mode at -k eta = {w.sigma}, {w.table_n} phi nodes"
                       if w.noise == "bessel2d" else
                       f"Bessel-matched table (B_k from the mode equation), {w.table_n} phi nodes, sigma={w.sigma}"
-                      if w.noise == "matched" else f"Bessel-ansatz table, {w.table_n} phi nodes, sigma={w.sigma}"),
+                      if w.noise == "matched" else
+                      f"Bessel-matched table on {w.table_n} time nodes over tau in [0, {w.table_hi:g}] after the "
+                      f"reference trajectory passes phi_in, zero after it, sigma={w.sigma}"
+                      if w.noise == "matched_time" else
+                      f"Bessel-ansatz table, {w.table_n} phi nodes, sigma={w.sigma}"),
             "state": "FP32 pairs + FP64 log-weights" if prec == "fp32" else "FP64",
             "bias": "learned 2-64-64-2 tanh network, tabulated" if learned else f"constant A={w.A_bias:g}",
             "trajectories_per_step": w.n_traj,

@@ -72,6 +72,7 @@ enum { FPT_POT_PIECEWISE_LINEAR = 0, FPT_POT_EXPONENTIAL = 1, FPT_POT_GAUSSIAN_B
 enum { FPT_BIAS_NONE = 0, FPT_BIAS_CONST = 1, FPT_BIAS_MLP = 2 };
 enum { FPT_FP64 = 0, FPT_FP32_STATE = 1 };
 enum { FPT_BINS_LINEAR = 0, FPT_BINS_LOG = 1 };
+enum { FPT_AXIS_PHI = 0, FPT_AXIS_TIME = 1 };
 
 #define FPT_FLAG_CENSORED 0x80000000u    /* in d_steps: reached max_steps */
 #define FPT_FLAG_ENDED_EARLY 0x40000000u /* in d_steps: eps_1 >= 1 before phi_end */
@@ -120,7 +121,16 @@ typedef struct {
  *     Xi = s s^T it is the 1D bias a s) and dA = a e.xi sqrt(dN) + a^2 |e|^2 dN/2,
  *     eq. (weight_A) for B = S (a e).  Each step takes two normals: call n >> 1
  *     of the generator, (u0, u1) for step 2m and (u2, u3) for step 2m + 1.
- *     Supported with FP64 state and no or constant bias. */
+ *     Supported with FP64 state and no or constant bias.
+ *   axis FPT_AXIS_TIME (1D noise, n >= 2) -- the nodes are in the run's time
+ *     instead, N_j = phi_lo + j h (phi_lo, phi_hi then hold N): step n reads the
+ *     table at N = n dN.  This is the paper's own scheme (Sec. 4.1): the noise is
+ *     precomputed along the classical trajectory and indexed by time, and a last
+ *     node of zero switches it off after a fixed number of steps (the edge node
+ *     applies beyond the table).  The FP32-state path then computes V'/V exactly
+ *     every step.  Not with 2D noise or a learned bias (FPT_EUNSUPPORTED), nor in
+ *     batches (FPT_EINVAL).  A time-indexed table of n == 1 is constant noise.
+ *     fpt_noise_table_matched_time gives the Bessel-matched noise on such nodes. */
 typedef struct {
     int32_t n;
     double phi_lo, phi_hi;
@@ -128,6 +138,7 @@ typedef struct {
     const double *tan_theta;
     int32_t dim;
     const double *Xi_pp, *Xi_pq, *Xi_qq;
+    int32_t axis;                        /* FPT_AXIS_PHI (0) or FPT_AXIS_TIME (1) */
 } fpt_noise_table;
 
 /* Importance-sampling bias (Sec. 4.1): B_phi = a S, B_pi = tan(theta_n) a S.
@@ -348,6 +359,23 @@ int fpt_noise_table_bessel2d(const fpt_potential *pot, double sigma, int32_t n, 
  * mode would start before N = 0 -- start the trajectory earlier), FPT_EHIP. */
 int fpt_noise_table_matched(const fpt_potential *pot, double sigma, int32_t n, double phi_lo, double phi_hi,
                             double phi_start, double pi_start, double *S_out, double *tan_out, double *fac_out);
+
+/* The Bessel-matched noise of fpt_noise_table_matched on nodes in time, for a
+ * table of axis FPT_AXIS_TIME: node j is the time tau_j = t_lo + j (t_hi -
+ * t_lo)/(n - 1) after the classical trajectory from (phi_start, pi_start) passes
+ * phi_ref (normally the run's phi_in, so that the run's time n dN is tau).  The
+ * node takes the trajectory's phi_j and pi_j at N_sigma = N_ref + tau_j (cubic
+ * Hermite interpolation of phi between samples 1e-4 e-folds apart, linear of pi),
+ * the Bunch-Davies node and nu(phi_j), and the factor 4|B_k|^2/pi of the mode
+ * that crosses k = sigma a H at N_sigma.  Outputs (host, n each; fac_out and
+ * phi_out may be NULL): S_out, tan_out, fac_out, phi_out = phi_j.  Errors:
+ * FPT_EINVAL (sizes, sigma outside (0, 2], phi_start <= phi_ref, a trajectory
+ * that does not pass phi_ref, a node before N = 0 or after the trajectory ends
+ * (eps1 >= 1 or N > 200), a mode that would start before N = 0, V <= 0 or
+ * nu^2 <= 0 at a node), FPT_EHIP. */
+int fpt_noise_table_matched_time(const fpt_potential *pot, double sigma, int32_t n, double t_lo, double t_hi,
+                                 double phi_start, double pi_start, double phi_ref, double *S_out, double *tan_out,
+                                 double *fac_out, double *phi_out);
 
 /* ---- batches: many problems in one persistent launch ------------------------- */
 

@@ -6,6 +6,7 @@ passage times N_REF_SRUSR and N_REF_LINEAR stored in the workloads module.
 
     python -m oracle.derive_constants
     python -m oracle.derive_constants --bump     (the Gaussian-bump workload's constants)
+    python -m oracle.derive_constants --time     (the time-indexed SR -> USR workload's start)
 """
 from __future__ import annotations
 
@@ -60,7 +61,7 @@ def hubble_noise() -> float:
     return float(S[0])
 
 
-if __name__ == "__main__" and "--bump" not in sys.argv:
+if __name__ == "__main__" and "--bump" not in sys.argv and "--time" not in sys.argv:
     print(f"NOISE_S_HUBBLE = {hubble_noise()!r}")
     d = derive_delta_e()
     print(f"DELTA_E = {d!r}")
@@ -138,3 +139,38 @@ if __name__ == "__main__" and "--bump" in sys.argv:
     for k_, v_ in c.items():
         print(f"BUMP_{k_.upper()} = {v_!r}")
     print(f"BUMP_N_REF = {bump_noise_free_N(c, 2.0, 1e-3)!r}   # phi_end = 2.0, dN = 1e-3")
+
+
+# ---------------------------------------------------------------------------
+# Noise indexed by time on the SR -> USR problem (Sec. 4.1)
+# ---------------------------------------------------------------------------
+MATCH_PHI_START = 1.0      # the matched table's classical trajectory starts here, pi = -V'/V
+
+
+def time_start():
+    """(pi_ref, N_ref): the momentum with which the classical trajectory from (MATCH_PHI_START,
+    -V'/V) reaches the transition phi = 0 (scipy DOP853 on eq. klein_gordon in e-folds, slope A_+
+    above the transition), and the noise-free Euler-Maruyama passage from (0, pi_ref) to
+    -DELTA_E at dN = 1e-4."""
+    from scipy.integrate import solve_ivp
+
+    def rhs(N, s):
+        return [s[1], -(3.0 - 0.5 * s[1] ** 2) * (s[1] + A_PLUS / (V0 + A_PLUS * s[0]))]
+
+    hit = lambda N, s: s[0]
+    hit.terminal = True
+    sol = solve_ivp(rhs, [0.0, 50.0], [MATCH_PHI_START, -A_PLUS / (V0 + A_PLUS * MATCH_PHI_START)], events=hit,
+                    rtol=1e-13, atol=1e-16, method="DOP853")
+    pi_ref = float(sol.y_events[0][0][1])
+    d = derive_delta_e()
+    p = orc.Problem(kind=orc.POT_PIECEWISE_LINEAR, V0=V0, phi_T=0.0, A_plus=A_PLUS, A_minus=A_MINUS,
+                    phi_in=0.0, pi_in=pi_ref, phi_end=-d, S=np.zeros(1), tan_theta=np.zeros(1))
+    N, _, steps = orc.run(p, 1e-4, seed=0, n_traj=1)
+    assert steps[0] & (orc.FLAG_CENSORED | orc.FLAG_ENDED_EARLY) == 0
+    return pi_ref, float(N[0]), float(sol.t_events[0][0])
+
+
+if __name__ == "__main__" and "--time" in sys.argv:
+    pi_ref, n_ref, n_to_kink = time_start()
+    print(f"TIME_PI_IN = {pi_ref!r}   # {n_to_kink:.4f} e-folds from phi = {MATCH_PHI_START}")
+    print(f"N_REF_TIME = {n_ref!r}")

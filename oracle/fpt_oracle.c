@@ -1427,7 +1427,7 @@ int orc_noise_table_matched_time(int kind, const double pot[7], double sigma, in
     int bad = 0;
 #pragma omp parallel for schedule(dynamic, 1)
     for (int j = 0; j < n; ++j) {
-        const double Ns = N_ref + t_lo + (double)j * h;
+        const double tau = t_lo + (double)j * h, Ns = N_ref + tau;
         fac_out[j] = NAN;
         if (!(Ns >= bN[0]) || !(Ns <= bN[nb - 1])) {
 #pragma omp atomic write
@@ -1438,8 +1438,11 @@ int orc_noise_table_matched_time(int kind, const double pot[7], double sigma, in
         while (i < nb - 1 && bN[i] < Ns) ++i;              /* bN[i-1] <= Ns <= bN[i] */
         const double dn = bN[i] - bN[i - 1], t = (Ns - bN[i - 1]) / dn;
         const double t2 = t * t, t3 = t2 * t;
-        const double phi_j = (2 * t3 - 3 * t2 + 1) * bphi[i - 1] + (t3 - 2 * t2 + t) * bpi[i - 1] * dn +
-                             (-2 * t3 + 3 * t2) * bphi[i] + (t3 - t2) * bpi[i] * dn;
+        /* the node at tau = 0 is the reference point itself: phi_ref exactly, so that a reference */
+        /* on the kink (phi_ref = phi_T) keeps the node on the branch before it                     */
+        const double phi_j = tau == 0.0 ? phi_ref
+                                        : (2 * t3 - 3 * t2 + 1) * bphi[i - 1] + (t3 - 2 * t2 + t) * bpi[i - 1] * dn +
+                                              (-2 * t3 + 3 * t2) * bphi[i] + (t3 - t2) * bpi[i] * dn;
         const double pi_j = bpi[i - 1] + t * (bpi[i] - bpi[i - 1]);
         if (phi_out) phi_out[j] = phi_j;
         double fac;

@@ -87,7 +87,7 @@ __global__ void table_bessel_kernel(PotParams pp, double sigma, int n, double ph
 {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= n) return;
-    const double phi = phi_lo + (double)j * h;
+    const double phi = grid_node(phi_lo, j, h);
     double V, dV, d2V;
     pot_eval(pp, phi, false, V, dV, d2V);
     const double r1 = dV / V, r2 = d2V / V;   // V'/V, V''/V
@@ -152,7 +152,7 @@ __global__ void table_bessel2d_kernel(PotParams pp, double sigma, int n, double 
 {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= n) return;
-    const double phi = phi_lo + (double)j * h;
+    const double phi = grid_node(phi_lo, j, h);
     double V, dV, d2V;
     pot_eval(pp, phi, false, V, dV, d2V);
     const double r1 = dV / V, r2 = d2V / V;
@@ -255,6 +255,49 @@ extern "C" int fpt_noise_table_matched(const fpt_potential *pot, double sigma, i
     if (e == hipSuccess) e = hipMemcpy(&status, d_status, sizeof(int), hipMemcpyDeviceToHost);
     (void)hipFree(d);
     if (e != hipSuccess) return hip_fail(e, "matched noise table kernels");
+    if (status & 1) return fail(FPT_EINVAL, "V <= 0 or nu^2 <= 0 at a table node");
+    if (status & 2) return fail(FPT_EINVAL, "a node is reached before its mode can start at k = 100 aH: start earlier");
+    if (status & 4) return fail(FPT_EINVAL, "non-finite or zero Bessel coefficient at a node");
+    return FPT_OK;
+}
+
+extern "C" int fpt_noise_table_matched_time(const fpt_potential *pot, double sigma, int32_t n, double t_lo,
+                                            double t_hi, double phi_start, double pi_start, double phi_ref,
+                                            double *S_out, double *tan_out, double *fac_out, double *phi_out)
+{
+    int rc = check_potential(pot);
+    if (rc) return rc;
+    if (n < 1 || n > FPT_MAX_TABLE) return fail(FPT_EINVAL, "table size %d out of 1..%d", n, FPT_MAX_TABLE);
+    if (!(sigma > 0.0) || !(sigma <= 2.0)) return fail(FPT_EINVAL, "sigma must lie in (0, 2]");
+    if (!is_finite(t_lo) || !is_finite(t_hi) || (n > 1 && !(t_hi > t_lo)))
+        return fail(FPT_EINVAL, "need t_hi > t_lo");
+    if (!is_finite(phi_start) || !is_finite(pi_start) || !is_finite(phi_ref))
+        return fail(FPT_EINVAL, "start and phi_ref must be finite");
+    if (!(phi_start > phi_ref)) return fail(FPT_EINVAL, "need phi_start > phi_ref");
+    if (!(pot_V(*pot, phi_start) > 0.0)) return fail(FPT_EINVAL, "V(phi_start) must be > 0");
+    if (!(0.5 * pi_start * pi_start < 1.0)) return fail(FPT_EINVAL, "the start needs eps1 = pi^2/2 < 1");
+    if (!S_out || !tan_out) return fail(FPT_EINVAL, "output arrays are NULL");
+    const double h = (n > 1) ? (t_hi - t_lo) / (double)(n - 1) : 0.0;
+    const double N_after = (n > 1 ? t_hi : t_lo) + 2e-4;   // one sample beyond the last node
+    const size_t out_off = (fpt::matched_time_scratch_bytes() + 255) & ~(size_t)255;
+    char *d = nullptr;
+    HIP_TRY(hipMalloc(&d, out_off + 4 * sizeof(double) * n + sizeof(int)));
+    double *d_S = reinterpret_cast<double *>(d + out_off);
+    int *d_status = reinterpret_cast<int *>(d_S + 4 * n);
+    hipError_t e = hipMemset(d_status, 0, sizeof(int));
+    if (e == hipSuccess)
+        e = fpt::matched_time_launch(pot_params(*pot), sigma, n, t_lo, h, phi_start, pi_start, phi_ref, N_after, d,
+                                     d_S, d_S + n, d_S + 2 * n, d_S + 3 * n, d_status, nullptr);
+    int status = 0;
+    if (e == hipSuccess) e = hipMemcpy(S_out, d_S, sizeof(double) * n, hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = hipMemcpy(tan_out, d_S + n, sizeof(double) * n, hipMemcpyDeviceToHost);
+    if (e == hipSuccess && fac_out) e = hipMemcpy(fac_out, d_S + 2 * n, sizeof(double) * n, hipMemcpyDeviceToHost);
+    if (e == hipSuccess && phi_out) e = hipMemcpy(phi_out, d_S + 3 * n, sizeof(double) * n, hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = hipMemcpy(&status, d_status, sizeof(int), hipMemcpyDeviceToHost);
+    (void)hipFree(d);
+    if (e != hipSuccess) return hip_fail(e, "time-node matched noise table kernels");
+    if (status & 16)
+        return fail(FPT_EINVAL, "the trajectory does not pass phi_ref, or a node lies outside the followed trajectory");
     if (status & 1) return fail(FPT_EINVAL, "V <= 0 or nu^2 <= 0 at a table node");
     if (status & 2) return fail(FPT_EINVAL, "a node is reached before its mode can start at k = 100 aH: start earlier");
     if (status & 4) return fail(FPT_EINVAL, "non-finite or zero Bessel coefficient at a node");
@@ -470,6 +513,12 @@ extern "C" int fpt_create(const fpt_potential *pot, const fpt_noise_table *table
     if (nt < 1 || nt > FPT_MAX_TABLE) return fail(FPT_EINVAL, "table size %d out of 1..%d", nt, FPT_MAX_TABLE);
     const int dim = table->dim == 2 ? 2 : 1;
     if (table->dim != 0 && table->dim != 1 && table->dim != 2) return fail(FPT_EINVAL, "table dim must be 1 or 2");
+    if (table->axis != FPT_AXIS_PHI && table->axis != FPT_AXIS_TIME)
+        return fail(FPT_EINVAL, "table axis must be FPT_AXIS_PHI or FPT_AXIS_TIME");
+    const bool time_axis = table->axis == FPT_AXIS_TIME && nt > 1;
+    if (time_axis && dim == 2) return fail(FPT_EUNSUPPORTED, "a time-indexed table takes 1D noise only");
+    if (time_axis && bias && bias->kind == FPT_BIAS_MLP)
+        return fail(FPT_EUNSUPPORTED, "a time-indexed table takes no learned bias");
     if (dim == 1) {
         if (!table->S || !table->tan_theta) return fail(FPT_EINVAL, "table arrays are NULL");
         for (int i = 0; i < nt; ++i) {
@@ -596,6 +645,7 @@ extern "C" int fpt_create(const fpt_potential *pot, const fpt_noise_table *table
     I.phi_in = pot->phi_in; I.pi_in = pot->pi_in; I.phi_end = pot->phi_end;
     I.bump_m2 = pot->bump_m * pot->bump_m; I.bump_K = pot->bump_K; I.bump_Sigma = pot->bump_Sigma;
     I.n_tab = nt;
+    I.tab_axis = time_axis ? 1 : 0;
     I.phi_lo = (nt > 1) ? table->phi_lo : 0.0;
     I.inv_h = (nt > 1) ? (double)(nt - 1) / (table->phi_hi - table->phi_lo) : 0.0;
     I.tab64 = reinterpret_cast<const double2 *>(base);
@@ -677,7 +727,7 @@ extern "C" int fpt_run(fpt_ctx *c, uint64_t n_traj, double dN, uint64_t seed, ui
     int grid = 0;
     const bool two_d = c->inst.noise_dim == 2;
     const void *fn = two_d ? em2d_kernel_ptr(c->inst.bias_kind, c->inst.all_S_pos != 0)
-                           : em_kernel_ptr(c->precision, c->inst.bias_kind, c->inst.n_tab > 1, c->inst.all_S_pos != 0,
+                           : em_kernel_ptr(c->precision, c->inst.bias_kind, tab_mode(c->inst), c->inst.all_S_pos != 0,
                                            c->inst.pot_kind);
     const size_t lds = two_d ? em2d_lds_bytes(c->inst.hist.n_bins, c->inst.n_tab)
                              : em_lds_bytes(c->inst.hist.n_bins, c->inst.n_tab, c->precision, grid_cells(c->inst));
@@ -871,7 +921,7 @@ extern "C" int fpt_mlp_grad(fpt_ctx *c, uint64_t n_traj, double dN, uint64_t see
     const int block = c->opt.block_size ? c->opt.block_size : 1024;
     int grid_em = 0, grid_rp = 0;
     const int n_cells = grid_cells(c->inst);
-    rc = occupancy_grid(em_kernel_ptr(c->precision, kBiasMlp, c->inst.n_tab > 1, c->inst.all_S_pos != 0), block,
+    rc = occupancy_grid(em_kernel_ptr(c->precision, kBiasMlp, tab_mode(c->inst), c->inst.all_S_pos != 0), block,
                         em_lds_bytes(c->opt.n_bins, c->inst.n_tab, c->precision, n_cells), c->cu_count,
                         c->opt.blocks_per_cu, grid_em);
     if (rc) return rc;
@@ -1012,6 +1062,7 @@ extern "C" int fpt_batch_create(fpt_ctx *const *ctx, int32_t n_inst, const fpt_b
         if (ctx[i]->inst.bias_kind == kBiasMlp) return fail(FPT_EINVAL, "a batch cannot hold a learned bias");
         if (ctx[i]->inst.noise_dim == 2) return fail(FPT_EINVAL, "a batch cannot hold 2D noise");
         if (ctx[i]->inst.pot_kind == kPotGaussianBump) return fail(FPT_EINVAL, "a batch cannot hold the Gaussian bump");
+        if (ctx[i]->inst.tab_axis) return fail(FPT_EINVAL, "a batch cannot hold a time-indexed table");
     }
     int dev = -1;
     HIP_TRY(hipGetDevice(&dev));

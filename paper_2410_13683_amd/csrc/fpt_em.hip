@@ -494,7 +494,9 @@ __device__ __forceinline__ void grad_add(T s[4], T c, T f0, T f1)
 // rp.tail (cursor over the list) and scatter the gradient factors instead of
 // retiring into the histogram.
 // ---------------------------------------------------------------------------
-template <int BIAS, bool TAB, bool ALLPOS, bool GRAD, int POT = kPotPiecewiseLinear>
+// TAB: 0 a single node (constant noise); 1 nodes in phi; 2 nodes in the run's time n dN (the
+// table's phi_lo and inv_h then refer to N).
+template <int BIAS, int TAB, bool ALLPOS, bool GRAD, int POT = kPotPiecewiseLinear>
 __device__ __forceinline__ void lanes_fp64(const Inst &I, const RunArgs &R, const double2 *l_tab, const double2 *l_grid,
                                            const RetireTo &rt, const ReplayTo &rp, unsigned long long *cursor,
                                            uint64_t n_traj, uint64_t traj_offset)
@@ -555,7 +557,7 @@ __device__ __forceinline__ void lanes_fp64(const Inst &I, const RunArgs &R, cons
             }
             double S, t;
             if (TAB) {
-                const double x = (phi - I.phi_lo) * I.inv_h;
+                const double x = ((TAB == 2 ? (double)n * dN : phi) - I.phi_lo) * I.inv_h;
                 const double jf = fmin(fmax(floor(x), 0.0), jmax);
                 const double f = fmin(fmax(x - jf, 0.0), 1.0);
                 const int jj = (int)jf;
@@ -653,6 +655,7 @@ struct F32Consts {
     float kx, s_plus, s_minus; // V'/V = 1/(kx (phi - phi_T) + s), s = s_plus (phi >= phi_T) or s_minus
     float u_off;               // (phi_end - phi_lo) * inv_h: table coordinate of x = 0
     float inv_h;
+    float t_scale, t_off;      // time tables: coordinate n dN inv_h - N_lo inv_h
     float jmax;                // n_tab - 2
     float dN, sqrt_dN;
     float a;
@@ -674,6 +677,8 @@ __device__ __forceinline__ F32Consts f32_consts(const Inst &I, const RunArgs &R)
     }
     c.u_off = (float)((I.phi_end - I.phi_lo) * I.inv_h);
     c.inv_h = (float)I.inv_h;
+    c.t_scale = (float)(R.dN * I.inv_h);
+    c.t_off = (float)(-I.phi_lo * I.inv_h);
     c.jmax = (float)(staged_nodes(I) - 2);
     c.dN = (float)R.dN;
     c.sqrt_dN = (float)R.sqrt_dN;
@@ -690,7 +695,7 @@ __device__ __forceinline__ void two_sum_fast(float &hi, float &lo, float d)
     lo += e;
 }
 
-template <int BIAS, bool TAB, bool ALLPOS, bool GRAD>
+template <int BIAS, int TAB, bool ALLPOS, bool GRAD>
 __device__ __forceinline__ void lanes_fp32(const Inst &I, const RunArgs &R, const float4 *l_tab, const float4 *l_grid,
                                            const RetireTo &rt, const ReplayTo &rp, unsigned long long *cursor,
                                            uint64_t n_traj, uint64_t traj_offset)
@@ -757,7 +762,16 @@ __device__ __forceinline__ void lanes_fp32(const Inst &I, const RunArgs &R, cons
                 return __builtin_amdgcn_rcpf(fmaf(dT, c.kx, (dT >= 0.0f) ? s_plus : s_minus));
             };
             float S, t, r;
-            if (TAB) {
+            if (TAB == 2) {
+                // time table: the node at n dN; V'/V exactly (the V'/V intervals follow phi)
+                const float u = fmaf((float)n, c.t_scale, c.t_off);
+                const float jf = __builtin_amdgcn_fmed3f(floorf(u), 0.0f, c.jmax);
+                const float f = __builtin_amdgcn_fmed3f(u - jf, 0.0f, 1.0f);
+                const float4 node = l_tab[(int)jf];
+                S = fmaf(f, node.y, node.x);
+                t = fmaf(f, node.w, node.z);
+                r = drift_exact();
+            } else if (TAB) {
                 const float u = fmaf(xh, c.inv_h, c.u_off);
                 const float jf = __builtin_amdgcn_fmed3f(floorf(u), 0.0f, c.jmax);
                 const float f = __builtin_amdgcn_fmed3f(u - jf, 0.0f, 1.0f);
@@ -1057,7 +1071,7 @@ __device__ __forceinline__ RetireTo retire_to(const EmParams &p, const LdsAcc &a
     return r;
 }
 
-template <int PREC, int BIAS, bool TAB, bool ALLPOS, int POT = kPotPiecewiseLinear>
+template <int PREC, int BIAS, int TAB, bool ALLPOS, int POT = kPotPiecewiseLinear>
 __global__ void __launch_bounds__(1024) FPT_EM_OCCUPANCY em_kernel(EmParams p)
 {
     static_assert(POT == kPotPiecewiseLinear || (PREC == 0 && BIAS != kBiasMlp), "the bump runs in FP64 only");
@@ -1193,15 +1207,16 @@ __global__ void zero_words_kernel(unsigned long long *ptr, size_t n)
         ptr[i] = 0ull;
 }
 
-template <int PREC, int BIAS, bool TAB, bool ALLPOS, int POT = kPotPiecewiseLinear>
+template <int PREC, int BIAS, int TAB, bool ALLPOS, int POT = kPotPiecewiseLinear>
 const void *kptr() { return reinterpret_cast<const void *>(&em_kernel<PREC, BIAS, TAB, ALLPOS, POT>); }
 template <int PREC, int BIAS, bool ALLPOS>
 const void *bptr() { return reinterpret_cast<const void *>(&batch_kernel<PREC, BIAS, ALLPOS>); }
 
 template <int PREC, int BIAS>
 struct KTab {
-    const void *p[2][2] = {{kptr<PREC, BIAS, false, false>(), kptr<PREC, BIAS, false, true>()},
-                           {kptr<PREC, BIAS, true, false>(), kptr<PREC, BIAS, true, true>()}};
+    const void *p[3][2] = {{kptr<PREC, BIAS, 0, false>(), kptr<PREC, BIAS, 0, true>()},
+                           {kptr<PREC, BIAS, 1, false>(), kptr<PREC, BIAS, 1, true>()},
+                           {kptr<PREC, BIAS, 2, false>(), kptr<PREC, BIAS, 2, true>()}};
 };
 
 }  // namespace
@@ -1216,17 +1231,20 @@ size_t replay_lds_bytes(int n_tab, int precision, int n_cells, int n_nodes)
     return tab_bytes(precision, n_tab) + cell_bytes(precision, n_cells) + (size_t)n_nodes * 8;
 }
 
-const void *em_kernel_ptr(int precision, int bias_kind, bool table, bool all_pos, int pot_kind)
+const void *em_kernel_ptr(int precision, int bias_kind, int tab_mode, bool all_pos, int pot_kind)
 {
+    const int tm = tab_mode < 0 ? 0 : tab_mode > 2 ? 2 : tab_mode;
     if (pot_kind == kPotGaussianBump) {
         // FP64, bias none or constant (fpt_create rejects the rest)
         constexpr int B = kPotGaussianBump;
-        static const void *const tb[2][2][2] = {
-            {{kptr<0, kBiasNone, false, false, B>(), kptr<0, kBiasNone, false, true, B>()},
-             {kptr<0, kBiasNone, true, false, B>(), kptr<0, kBiasNone, true, true, B>()}},
-            {{kptr<0, kBiasConst, false, false, B>(), kptr<0, kBiasConst, false, true, B>()},
-             {kptr<0, kBiasConst, true, false, B>(), kptr<0, kBiasConst, true, true, B>()}}};
-        return tb[bias_kind == kBiasConst ? 1 : 0][table ? 1 : 0][all_pos ? 1 : 0];
+        static const void *const tb[2][3][2] = {
+            {{kptr<0, kBiasNone, 0, false, B>(), kptr<0, kBiasNone, 0, true, B>()},
+             {kptr<0, kBiasNone, 1, false, B>(), kptr<0, kBiasNone, 1, true, B>()},
+             {kptr<0, kBiasNone, 2, false, B>(), kptr<0, kBiasNone, 2, true, B>()}},
+            {{kptr<0, kBiasConst, 0, false, B>(), kptr<0, kBiasConst, 0, true, B>()},
+             {kptr<0, kBiasConst, 1, false, B>(), kptr<0, kBiasConst, 1, true, B>()},
+             {kptr<0, kBiasConst, 2, false, B>(), kptr<0, kBiasConst, 2, true, B>()}}};
+        return tb[bias_kind == kBiasConst ? 1 : 0][tm][all_pos ? 1 : 0];
     }
     static const KTab<0, kBiasNone> f0n;
     static const KTab<0, kBiasConst> f0c;
@@ -1237,13 +1255,13 @@ const void *em_kernel_ptr(int precision, int bias_kind, bool table, bool all_pos
     const void *const(*t)[2];
     if (precision == 0) t = bias_kind == kBiasNone ? f0n.p : bias_kind == kBiasConst ? f0c.p : f0m.p;
     else t = bias_kind == kBiasNone ? f1n.p : bias_kind == kBiasConst ? f1c.p : f1m.p;
-    return t[table ? 1 : 0][all_pos ? 1 : 0];
+    return t[tm][all_pos ? 1 : 0];
 }
 
 hipError_t em_launch(const EmParams &p, int precision, int grid, int block, hipStream_t stream)
 {
     const size_t lds = em_lds_bytes(p.inst.hist.n_bins, p.inst.n_tab, precision, grid_cells(p.inst));
-    const void *fn = em_kernel_ptr(precision, p.inst.bias_kind, p.inst.n_tab > 1, p.inst.all_S_pos != 0,
+    const void *fn = em_kernel_ptr(precision, p.inst.bias_kind, tab_mode(p.inst), p.inst.all_S_pos != 0,
                                    p.inst.pot_kind);
     EmParams pp = p;
     void *args[] = {&pp};

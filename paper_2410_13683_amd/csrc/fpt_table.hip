@@ -178,7 +178,7 @@ __global__ void match_background_kernel(Pot p, double phi_start, double pi_start
                     j1 = (int)b;
                 }
                 for (int j = j0; j <= j1; ++j) {
-                    const double pj = phi_lo + (double)j * h_node;
+                    const double pj = grid_node(phi_lo, j, h_node);
                     if (s.phi <= pj && pj < hi_phi && first_idx[j] < 0) first_idx[j] = nb;
                 }
             }
@@ -190,87 +190,183 @@ __global__ void match_background_kernel(Pot p, double phi_start, double pi_start
     *nb_out = nb;
 }
 
+// The Bunch-Davies node of eq. (covariance_constant_nu) at phi: sqrt(Xi_phiphi), nu.  False where
+// V <= 0 or nu^2 <= 0.
+__device__ inline bool bd_node(const Pot &p, double sigma, double phi, double &S_bd, double &nu, double &V)
+{
+    double dV, d2V;
+    pot_eval(p, phi, false, V, dV, d2V);
+    const double nu2 = nu2_of(p, phi);
+    if (!(V > 0.0) || !(nu2 > 0.0)) return false;
+    nu = sqrt(nu2);
+    S_bd = sqrt(V / 3.0) / (2.0 * M_PI) * (tgamma(nu) / (0.5 * sqrt(M_PI))) * pow(0.5 * sigma, 1.5 - nu);
+    return true;
+}
+
+// 4|B_k|^2/pi of the mode that crosses k = sigma a H at N_sigma = Ns, where the classical trajectory
+// is at (phi_j, pis) with V = V(phi_j) and nu = nu(phi_j).  Status bits: 2 (the mode would start
+// before N = 0), 4 (non-finite or zero B_k); the factor is then NaN.
+__device__ double matched_factor(const Pot &p, double sigma, double phi_j, double pis, double Ns, double V, double nu,
+                                 const double *bN, const double *bphi, const double *bpi, int nb, int *status)
+{
+    const double k = sigma * exp(Ns) * sqrt(V / (3.0 - 0.5 * pis * pis));
+    // start at the last sample with k >= 100 aH (aH grows while eps1 < 1)
+    auto aH = [&](int ii) { return exp(bN[ii]) * sqrt(hubble2(p, bphi[ii], bpi[ii])); };
+    if (k < kStartRatio * aH(0)) {
+        atomicOr(status, 2);
+        return NAN;
+    }
+    int lo = 0, hi = nb;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (k < kStartRatio * aH(mid)) hi = mid;
+        else lo = mid;
+    }
+    double N = bN[lo];
+    St s{bphi[lo], bpi[lo], 0.0, 0.0, 0.0, 0.0};
+    {
+        // Bunch-Davies: e^(iy)(1 + i c/y)/(a sqrt(2k)), c = (4 nu^2 - 1)/8, y = k/(aH), overall phase
+        // dropped; d/dN of it is [(-1 - iy)(1 + ic/y) + ic/y]/(a sqrt(2k))
+        const double a = exp(N);
+        const double y = k / (a * sqrt(hubble2(p, s.phi, s.pi_)));
+        const double c = (4.0 * nu2_of(p, s.phi) - 1.0) * 0.125;
+        const double amp = 1.0 / (a * sqrt(2.0 * k));
+        s.fr = amp;
+        s.fi = amp * c / y;
+        s.gr = amp * (-1.0 + c);        // Re[(-1 - iy)(1 + ic/y) + ic/y]
+        s.gi = amp * (-y);              // Im[...] = -c/y - y + c/y
+    }
+    advance<true>(p, k, N, Ns, s, phi_j < p.phi_T, kModeMaxStep);
+    // eq. (bessel_matching) at -k eta = sigma with nu(phi_j); a/sqrt(-eta) = e^N sqrt(k/sigma).  The
+    // denominator J_nu dY_nu/dN - Y_nu dJ_nu/dN is -y W[J_nu, Y_nu](y) = -2/pi (the Bessel Wronskian),
+    // so B_k = (pi/2) pref (dphi dJ/dN - g J) with g = 3/2 dphi + d dphi/dN, for every nu > 0.
+    double Jn, yJn;
+    bessel_j(nu, sigma, Jn, yJn);
+    const double dJ = -yJn;
+    const double pref = exp(N) * sqrt(k / sigma);
+    const double g_r = 1.5 * s.fr + s.gr, g_i = 1.5 * s.fi + s.gi;
+    const double b_r = 0.5 * M_PI * pref * (s.fr * dJ - g_r * Jn);
+    const double b_i = 0.5 * M_PI * pref * (s.fi * dJ - g_i * Jn);
+    const double fac = 4.0 * (b_r * b_r + b_i * b_i) / M_PI;
+    if (!(fac > 0.0) || !isfinite(fac)) {
+        atomicOr(status, 4);
+        return NAN;
+    }
+    return fac;
+}
+
+// The time at which phi(N) reaches target inside samples [i-1, i]: Newton on the cubic Hermite
+// interpolant of phi; pi there interpolated linearly.
+__device__ inline void hermite_root(const double *bN, const double *bphi, const double *bpi, int i, double target,
+                                    double &Ns, double &pis)
+{
+    const double dn = bN[i] - bN[i - 1];
+    const double p0 = bphi[i - 1], p1 = bphi[i], m0 = bpi[i - 1] * dn, m1 = bpi[i] * dn;
+    double t = (p0 - target) / (p0 - p1);
+    for (int it = 0; it < 50; ++it) {
+        const double t2 = t * t, t3 = t2 * t;
+        const double v = (2.0 * t3 - 3.0 * t2 + 1.0) * p0 + (t3 - 2.0 * t2 + t) * m0 + (3.0 * t2 - 2.0 * t3) * p1 +
+                         (t3 - t2) * m1 - target;
+        const double dv = 6.0 * (t2 - t) * (p0 - p1) + (3.0 * t2 - 4.0 * t + 1.0) * m0 + (3.0 * t2 - 2.0 * t) * m1;
+        const double step = v / dv;
+        t -= step;
+        if (fabs(step) < 1e-16) break;
+    }
+    Ns = bN[i - 1] + t * dn;
+    pis = bpi[i - 1] + t * (bpi[i] - bpi[i - 1]);
+}
+
 __global__ void match_node_kernel(Pot p, double sigma, int n, double phi_lo, double h_node, const double *bN,
                                   const double *bphi, const double *bpi, const int *nb_ptr, const int *first_idx,
                                   double *S, double *tan_out, double *fac_out, int *status)
 {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= n) return;
-    const double phi_j = phi_lo + (double)j * h_node;
-    const int nb = *nb_ptr;
-    // the Bunch-Davies node of eq. (covariance_constant_nu): sqrt(Xi_phiphi), tan theta_n
-    double V, dV, d2V;
-    pot_eval(p, phi_j, false, V, dV, d2V);
-    const double nu2 = nu2_of(p, phi_j);
-    const double nu = nu2 > 0.0 ? sqrt(nu2) : 0.0;
-    if (!(V > 0.0) || !(nu2 > 0.0)) {
+    const double phi_j = grid_node(phi_lo, j, h_node);
+    double S_bd, nu, V;
+    if (!bd_node(p, sigma, phi_j, S_bd, nu, V)) {
         atomicOr(status, 1);
         S[j] = tan_out[j] = fac_out[j] = 0.0;
         return;
     }
-    const double S_bd = sqrt(V / 3.0) / (2.0 * M_PI) * (tgamma(nu) / (0.5 * sqrt(M_PI))) * pow(0.5 * sigma, 1.5 - nu);
     tan_out[j] = nu - 1.5;
     double fac = 1.0;
     const int i = first_idx[j];
     if (i > 0) {
-        // N_sigma: Newton on the cubic Hermite interpolant of phi(N) over samples i-1, i
-        const double dn = bN[i] - bN[i - 1];
-        const double p0 = bphi[i - 1], p1 = bphi[i], m0 = bpi[i - 1] * dn, m1 = bpi[i] * dn;
-        double t = (p0 - phi_j) / (p0 - p1);
-        for (int it = 0; it < 50; ++it) {
-            const double t2 = t * t, t3 = t2 * t;
-            const double v = (2.0 * t3 - 3.0 * t2 + 1.0) * p0 + (t3 - 2.0 * t2 + t) * m0 +
-                             (3.0 * t2 - 2.0 * t3) * p1 + (t3 - t2) * m1 - phi_j;
-            const double dv = 6.0 * (t2 - t) * (p0 - p1) + (3.0 * t2 - 4.0 * t + 1.0) * m0 + (3.0 * t2 - 2.0 * t) * m1;
-            const double step = v / dv;
-            t -= step;
-            if (fabs(step) < 1e-16) break;
-        }
-        const double Ns = bN[i - 1] + t * dn;
-        const double pis = bpi[i - 1] + t * (bpi[i] - bpi[i - 1]);
-        const double k = sigma * exp(Ns) * sqrt(V / (3.0 - 0.5 * pis * pis));
-        // start at the last sample with k >= 100 aH (aH grows while eps1 < 1)
-        auto aH = [&](int ii) { return exp(bN[ii]) * sqrt(hubble2(p, bphi[ii], bpi[ii])); };
-        if (k < kStartRatio * aH(0)) {
-            atomicOr(status, 2);
-            fac = NAN;
-        } else {
-            int lo = 0, hi = nb;
-            while (hi - lo > 1) {
-                const int mid = (lo + hi) >> 1;
-                if (k < kStartRatio * aH(mid)) hi = mid;
-                else lo = mid;
-            }
-            double N = bN[lo];
-            St s{bphi[lo], bpi[lo], 0.0, 0.0, 0.0, 0.0};
-            {
-                // Bunch-Davies: e^(iy)(1 + i c/y)/(a sqrt(2k)), c = (4 nu^2 - 1)/8, y = k/(aH),
-                // overall phase dropped; d/dN of it is [(-1 - iy)(1 + ic/y) + ic/y]/(a sqrt(2k))
-                const double a = exp(N);
-                const double y = k / (a * sqrt(hubble2(p, s.phi, s.pi_)));
-                const double c = (4.0 * nu2_of(p, s.phi) - 1.0) * 0.125;
-                const double amp = 1.0 / (a * sqrt(2.0 * k));
-                s.fr = amp;
-                s.fi = amp * c / y;
-                s.gr = amp * (-1.0 + c);        // Re[(-1 - iy)(1 + ic/y) + ic/y]
-                s.gi = amp * (-y);              // Im[...] = -c/y - y + c/y
-            }
-            advance<true>(p, k, N, Ns, s, phi_j < p.phi_T, kModeMaxStep);
-            // eq. (bessel_matching) at -k eta = sigma with nu(phi_j); a/sqrt(-eta) = e^N sqrt(k/sigma).
-            // The denominator J_nu dY_nu/dN - Y_nu dJ_nu/dN is -y W[J_nu, Y_nu](y) = -2/pi (the
-            // Bessel Wronskian), so B_k = (pi/2) pref (dphi dJ/dN - g J) with g = 3/2 dphi + d dphi/dN,
-            // for every nu > 0.
-            double Jn, yJn;
-            bessel_j(nu, sigma, Jn, yJn);
-            const double dJ = -yJn;
-            const double pref = exp(N) * sqrt(k / sigma);
-            const double g_r = 1.5 * s.fr + s.gr, g_i = 1.5 * s.fi + s.gi;
-            const double b_r = 0.5 * M_PI * pref * (s.fr * dJ - g_r * Jn);
-            const double b_i = 0.5 * M_PI * pref * (s.fi * dJ - g_i * Jn);
-            fac = 4.0 * (b_r * b_r + b_i * b_i) / M_PI;
-            if (!(fac > 0.0) || !isfinite(fac)) atomicOr(status, 4);
-        }
+        double Ns, pis;
+        hermite_root(bN, bphi, bpi, i, phi_j, Ns, pis);
+        fac = matched_factor(p, sigma, phi_j, pis, Ns, V, nu, bN, bphi, bpi, *nb_ptr, status);
     }
+    fac_out[j] = fac;
+    S[j] = S_bd * sqrt(fac);
+}
+
+// Time nodes: the classical trajectory as in match_background_kernel, with the time N_ref at which
+// it passes phi_ref (NaN if it does not); it is followed until N_ref + N_after once that is known.
+__global__ void match_background_time_kernel(Pot p, double phi_start, double pi_start, double phi_ref, double N_after,
+                                             double *bN, double *bphi, double *bpi, int cap, int *nb_out,
+                                             double *N_ref_out)
+{
+    if (blockIdx.x != 0 || threadIdx.x != 0) return;
+    St s{phi_start, pi_start, 0.0, 0.0, 0.0, 0.0};
+    double N = 0.0, N_ref = NAN, N_stop = INFINITY;
+    int nb = 0;
+    for (;;) {
+        bN[nb] = N;
+        bphi[nb] = s.phi;
+        bpi[nb] = s.pi_;
+        ++nb;
+        if (isnan(N_ref) && nb >= 2 && bphi[nb - 2] > phi_ref && bphi[nb - 1] <= phi_ref) {
+            double pr;
+            hermite_root(bN, bphi, bpi, nb - 1, phi_ref, N_ref, pr);
+            N_stop = N_ref + N_after;
+        }
+        if (N >= N_stop || 0.5 * s.pi_ * s.pi_ >= 1.0 || N > kBgMaxN || nb == cap) break;
+        advance<false>(p, 0.0, N, N + kBgStep, s, true, kBgStep);
+    }
+    *nb_out = nb;
+    *N_ref_out = N_ref;
+}
+
+// Node j at N_sigma = N_ref + t_lo + j h: phi_j by the cubic Hermite interpolant of the samples,
+// pi_j linearly, then the Bunch-Davies node and the factor there.  Status 16: the trajectory does
+// not pass phi_ref, or the node lies outside the followed trajectory.
+__global__ void match_node_time_kernel(Pot p, double sigma, int n, double t_lo, double h, double phi_ref,
+                                       const double *bN, const double *bphi, const double *bpi, const int *nb_ptr,
+                                       const double *N_ref_ptr, double *S, double *tan_out, double *fac_out, double *phi_out, int *status)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    const int nb = *nb_ptr;
+    const double tau = grid_node(t_lo, j, h), Ns = *N_ref_ptr + tau;
+    S[j] = tan_out[j] = fac_out[j] = phi_out[j] = NAN;
+    if (!(Ns >= bN[0]) || !(Ns <= bN[nb - 1]) || nb < 2) {
+        atomicOr(status, 16);
+        return;
+    }
+    // first sample at or after Ns (from 1, at most nb - 1)
+    int lo = 0, hi = nb - 1;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (bN[mid] < Ns) lo = mid;
+        else hi = mid;
+    }
+    const int i = hi;
+    const double dn = bN[i] - bN[i - 1], t = (Ns - bN[i - 1]) / dn;
+    const double t2 = t * t, t3 = t2 * t;
+    // tau = 0 is the reference point: phi_ref exactly (on a kink at phi_ref, the branch before it)
+    const double phi_j = tau == 0.0 ? phi_ref
+                                    : (2.0 * t3 - 3.0 * t2 + 1.0) * bphi[i - 1] + (t3 - 2.0 * t2 + t) * bpi[i - 1] * dn +
+                                          (3.0 * t2 - 2.0 * t3) * bphi[i] + (t3 - t2) * bpi[i] * dn;
+    const double pi_j = bpi[i - 1] + t * (bpi[i] - bpi[i - 1]);
+    phi_out[j] = phi_j;
+    double S_bd, nu, V;
+    if (!bd_node(p, sigma, phi_j, S_bd, nu, V)) {
+        atomicOr(status, 1);
+        return;
+    }
+    tan_out[j] = nu - 1.5;
+    const double fac = matched_factor(p, sigma, phi_j, pi_j, Ns, V, nu, bN, bphi, bpi, nb, status);
     fac_out[j] = fac;
     S[j] = S_bd * sqrt(fac);
 }
@@ -295,6 +391,25 @@ hipError_t matched_table_launch(const PotParams &p, double sigma, int n, double 
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(match_node_kernel, dim3((n + 63) / 64), dim3(64), 0, stream, p, sigma, n, phi_lo, h_node,
                        bN, bphi, bpi, nb, first_idx, d_S, d_tan, d_fac, d_status);
+    return hipGetLastError();
+}
+
+size_t matched_time_scratch_bytes() { return (size_t)kMatchCap * 3 * sizeof(double) + 16; }
+
+hipError_t matched_time_launch(const PotParams &p, double sigma, int n, double t_lo, double h, double phi_start,
+                               double pi_start, double phi_ref, double N_after, void *scratch, double *d_S,
+                               double *d_tan, double *d_fac, double *d_phi, int *d_status, hipStream_t stream)
+{
+    double *bN = static_cast<double *>(scratch);
+    double *bphi = bN + kMatchCap, *bpi = bphi + kMatchCap;
+    int *nb = reinterpret_cast<int *>(bpi + kMatchCap);
+    double *N_ref = reinterpret_cast<double *>(bpi + kMatchCap) + 1;
+    hipLaunchKernelGGL(match_background_time_kernel, dim3(1), dim3(64), 0, stream, p, phi_start, pi_start, phi_ref,
+                       N_after, bN, bphi, bpi, (int)kMatchCap, nb, N_ref);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(match_node_time_kernel, dim3((n + 63) / 64), dim3(64), 0, stream, p, sigma, n, t_lo, h,
+                       phi_ref, bN, bphi, bpi, nb, N_ref, d_S, d_tan, d_fac, d_phi, d_status);
     return hipGetLastError();
 }
 

@@ -44,8 +44,9 @@ struct Inst {
     double phi_in, pi_in, phi_end;
     // Gaussian bump (pot_kind 2): m^2, K, Sigma; the centre phi_0 is phi_T
     double bump_m2, bump_K, bump_Sigma;
-    // phi-indexed noise table: n_tab nodes from phi_lo with spacing 1/inv_h
-    int32_t n_tab;
+    // noise table: n_tab nodes from phi_lo with spacing 1/inv_h, in phi (tab_axis 0) or in the
+    // run's time N = n dN (tab_axis 1: phi_lo and inv_h then refer to N)
+    int32_t n_tab, tab_axis;
     double phi_lo, inv_h;
     const double2 *tab64;            // node j: (S_j, tan_j)                                  (device)
     const float4 *tab32;             // node j: (S_j, S_j+1 - S_j, tan_j, tan_j+1 - tan_j) in FP32
@@ -125,8 +126,9 @@ struct ReplayParams {
 __host__ __device__ inline int grid_cells(const Inst &I) { return I.bias_kind == kBiasMlp ? (I.g_n0 - 1) * (I.g_n1 - 1) : 0; }
 size_t em_lds_bytes(int n_bins, int n_tab, int precision, int n_cells);
 size_t replay_lds_bytes(int n_tab, int precision, int n_cells, int n_nodes);
-// pot_kind selects the Gaussian-bump variant (FP64, bias none or constant only).
-const void *em_kernel_ptr(int precision, int bias_kind, bool table, bool all_pos, int pot_kind = 0);
+// tab_mode: 0 a single node, 1 nodes in phi, 2 nodes in time (tab_mode(inst)); pot_kind selects
+// the Gaussian-bump variant (FP64, bias none or constant only).
+const void *em_kernel_ptr(int precision, int bias_kind, int tab_mode, bool all_pos, int pot_kind = 0);
 hipError_t em_launch(const EmParams &p, int precision, int grid, int block, hipStream_t stream);
 const void *replay_kernel_ptr(int precision, bool all_pos);
 size_t em2d_lds_bytes(int n_bins, int n_tab);
@@ -169,8 +171,27 @@ size_t matched_scratch_bytes(int n);
 hipError_t matched_table_launch(const PotParams &pot, double sigma, int n, double phi_lo, double h_node,
                                 double phi_start, double pi_start, void *scratch, double *d_S, double *d_tan,
                                 double *d_fac, int *d_status, hipStream_t stream);
+// Time nodes N_ref + t_lo + j h after the trajectory passes phi_ref; the trajectory is followed
+// until N_ref + N_after.  Scratch: matched_time_scratch_bytes().  d_status as above plus 16 (no
+// passage of phi_ref, or a node outside the followed trajectory).
+size_t matched_time_scratch_bytes();
+hipError_t matched_time_launch(const PotParams &pot, double sigma, int n, double t_lo, double h, double phi_start,
+                               double pi_start, double phi_ref, double N_after, void *scratch, double *d_S,
+                               double *d_tan, double *d_fac, double *d_phi, int *d_status, hipStream_t stream);
 
 // Sets the message fpt_last_error returns and returns code (defined in fpt_api.hip).
 int report_error(int code, const char *msg);
+
+// Node j of a table grid, lo + j h, rounded as two separate operations (no fused multiply-add), so
+// that a node meant to sit on a point (a kink, a reference time) lands on the same double as in a
+// plain IEEE evaluation.
+__device__ inline double grid_node(double lo, int j, double h)
+{
+#pragma clang fp contract(off)
+    return lo + (double)j * h;
+}
+
+// The table mode of the kernels: a single node, nodes in phi, or nodes in time.
+__host__ __device__ inline int tab_mode(const Inst &I) { return I.n_tab > 1 ? (I.tab_axis ? 2 : 1) : 0; }
 
 }  // namespace fpt

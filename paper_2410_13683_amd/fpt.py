@@ -31,6 +31,7 @@ FPT_POT_PIECEWISE_LINEAR, FPT_POT_EXPONENTIAL, FPT_POT_GAUSSIAN_BUMP = 0, 1, 2
 FPT_BIAS_NONE, FPT_BIAS_CONST, FPT_BIAS_MLP = 0, 1, 2
 FPT_FP64, FPT_FP32_STATE = 0, 1
 FPT_BINS_LINEAR, FPT_BINS_LOG = 0, 1
+FPT_AXIS_PHI, FPT_AXIS_TIME = 0, 1
 FPT_FLAG_CENSORED = 0x80000000
 FPT_FLAG_ENDED_EARLY = 0x40000000
 FPT_STEP_MASK = 0x3FFFFFFF
@@ -57,7 +58,7 @@ class fpt_potential(ctypes.Structure):
 class fpt_noise_table(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int32), ("phi_lo", ctypes.c_double), ("phi_hi", ctypes.c_double),
                 ("S", _dp), ("tan_theta", _dp), ("dim", ctypes.c_int32), ("Xi_pp", _dp), ("Xi_pq", _dp),
-                ("Xi_qq", _dp)]
+                ("Xi_qq", _dp), ("axis", ctypes.c_int32)]
 
 
 class fpt_bias(ctypes.Structure):
@@ -129,6 +130,9 @@ def load():
                                            ctypes.c_double, _dp, _dp, _dp]
     L.fpt_noise_table_matched.argtypes = [P(fpt_potential), ctypes.c_double, ctypes.c_int32, ctypes.c_double,
                                           ctypes.c_double, ctypes.c_double, ctypes.c_double, _dp, _dp, _dp]
+    L.fpt_noise_table_matched_time.argtypes = [P(fpt_potential), ctypes.c_double, ctypes.c_int32, ctypes.c_double,
+                                               ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                               _dp, _dp, _dp, _dp]
     L.fpt_jackknife.argtypes = [ctypes.c_int32, ctypes.c_int32, _u64p, _dp, _dp, _dp]
     L.fpt_lognormal_bins.argtypes = [ctypes.c_int32, ctypes.c_uint64, _u64p, _dp, _dp, _dp, _dp, _dp]
     L.fpt_merge_bins.argtypes = [ctypes.c_int32, ctypes.c_int32, _dp, _dp, _dp, _dp]
@@ -150,7 +154,8 @@ def load():
     L.fpt_mlp_adam.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                ctypes.c_double, ctypes.c_void_p]
     for name in ("fpt_create", "fpt_run", "fpt_histogram", "fpt_reset", "fpt_last_kernel_ms",
-                 "fpt_noise_table_bessel", "fpt_noise_table_bessel2d", "fpt_noise_table_matched", "fpt_jackknife", "fpt_lognormal_bins",
+                 "fpt_noise_table_bessel", "fpt_noise_table_bessel2d", "fpt_noise_table_matched",
+                 "fpt_noise_table_matched_time", "fpt_jackknife", "fpt_lognormal_bins",
                  "fpt_merge_bins", "fpt_batch_create", "fpt_batch_run", "fpt_batch_autotune",
                  "fpt_batch_config", "fpt_batch_last_ms", "fpt_mlp_set", "fpt_mlp_get", "fpt_mlp_table",
                  "fpt_mlp_grad", "fpt_mlp_adam"):
@@ -217,6 +222,17 @@ def fpt_noise_table_matched(pot: fpt_potential, sigma: float, n: int, phi_lo: fl
     return S, t, fac
 
 
+def fpt_noise_table_matched_time(pot: fpt_potential, sigma: float, n: int, t_lo: float, t_hi: float,
+                                 phi_start: float, pi_start: float, phi_ref: float):
+    """(S, tan_theta, 4|B_k|^2/pi, phi_j) of the Bessel-matched table on time nodes t_lo + j h after the
+    classical trajectory passes phi_ref; device kernels."""
+    out = [np.empty(n, dtype=np.float64) for _ in range(4)]
+    _check(load().fpt_noise_table_matched_time(ctypes.byref(pot), sigma, n, t_lo, t_hi, phi_start, pi_start, phi_ref,
+                                               *[a.ctypes.data_as(_dp) for a in out]),
+           "fpt_noise_table_matched_time")
+    return tuple(out)
+
+
 def _f64(a):
     return np.ascontiguousarray(a, dtype=np.float64)
 
@@ -256,13 +272,14 @@ def fpt_merge_bins(p_runs, err_runs):
 
 class Context:
     """Owns one fpt_ctx; mirrors fpt_run / fpt_histogram / fpt_reset / fpt_destroy.  S, tan_theta give a
-    1D noise table; Xi = (Xi_pp, Xi_pq, Xi_qq) a 2D one (S and tan_theta are then ignored)."""
+    1D noise table; Xi = (Xi_pp, Xi_pq, Xi_qq) a 2D one (S and tan_theta are then ignored).  axis
+    FPT_AXIS_TIME puts the nodes in time (phi_lo, phi_hi then hold N)."""
 
     def __init__(self, pot: fpt_potential, S, tan_theta, phi_lo: float, phi_hi: float, *, bias_kind=FPT_BIAS_NONE,
                  A=0.0, mlp_params=None, norm=(0.0, 1.0, 0.0, 1.0), mlp_every=0, grid_n=(2, 2),
                  grid_range=(-1.0, 1.0, -1.0, 1.0), precision=FPT_FP64,
                  bins_kind=FPT_BINS_LINEAR, n_bins=64, lo=-1.0, hi=1.0, N_ref=0.0, max_steps=FPT_MAX_STEPS,
-                 instance=0, block_size=0, blocks_per_cu=0, chunk=0, Xi=None):
+                 instance=0, block_size=0, blocks_per_cu=0, chunk=0, Xi=None, axis=FPT_AXIS_PHI):
         L = load()
         if Xi is not None:
             self._X = [np.ascontiguousarray(x, dtype=np.float64) for x in Xi]
@@ -273,6 +290,7 @@ class Context:
             self._t = np.ascontiguousarray(tan_theta, dtype=np.float64)
             table = fpt_noise_table(len(self._S), phi_lo, phi_hi, self._S.ctypes.data_as(_dp),
                                     self._t.ctypes.data_as(_dp))
+        table.axis = axis
         self._mlp = (np.ascontiguousarray(mlp_params, dtype=np.float32) if mlp_params is not None else None)
         bias = fpt_bias(bias_kind, A, self._mlp.ctypes.data_as(_fp) if self._mlp is not None else None,
                         (ctypes.c_double * 4)(*norm), mlp_every, (ctypes.c_int32 * 2)(*grid_n),

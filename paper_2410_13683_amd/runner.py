@@ -35,6 +35,12 @@ def table_of(w: Workload, pot=None):
         if w.noise_cut_below:
             S[0] = 0.0
         return S, t, w.table_lo, w.table_hi
+    if w.noise == "matched_time":
+        S, t, _, _ = fpt.fpt_noise_table_matched_time(pot or potential_of(w), w.sigma, w.table_n, w.table_lo,
+                                                      w.table_hi, *w.match_start, w.phi_in)
+        if w.noise_cut_end:
+            S[-1] = 0.0
+        return S, t, w.table_lo, w.table_hi
     raise ValueError(f"unknown noise kind {w.noise!r}")
 
 
@@ -42,7 +48,8 @@ def context_for(w: Workload, **overrides) -> fpt.Context:
     pot = potential_of(w)
     S, t, lo, hi = table_of(w, pot)
     kw = dict(bias_kind=w.bias_kind, A=w.A_bias, precision=w.precision, bins_kind=w.bins_kind, n_bins=w.n_bins,
-              lo=w.lo, hi=w.hi, N_ref=w.N_ref, max_steps=w.max_steps, instance=w.extra.get("instance", 0))
+              lo=w.lo, hi=w.hi, N_ref=w.N_ref, max_steps=w.max_steps, instance=w.extra.get("instance", 0),
+              axis=fpt.FPT_AXIS_TIME if w.noise == "matched_time" else fpt.FPT_AXIS_PHI)
     if w.bias_kind == 2:
         kw.update(mlp_params=w.mlp_params, norm=w.mlp_norm, mlp_every=0, grid_n=w.grid_n, grid_range=w.grid_range)
     if t is None:

@@ -75,7 +75,9 @@ class Workload:
                                     # "xi_const": 2D noise with covariance noise_Xi (one node);
                                     # "bessel2d": 2D noise of eq. (covariance_matrix_direct) on the grid;
                                     # "matched": eq. (covariance_constant_nu_bessel_matched) on the grid,
-                                    # B_k from the classical trajectory started at match_start
+                                    # B_k from the classical trajectory started at match_start;
+                                    # "matched_time": the same noise on nodes in time, table_lo and
+                                    # table_hi the times after the trajectory passes phi_in
     dN: float
     n_traj: int
     seed: int
@@ -85,6 +87,7 @@ class Workload:
     sigma: float = 1.0              # coarse-graining ratio k_sigma / aH
     match_start: tuple = (0.0, 0.0)  # (phi, pi) at which the "matched" table's classical trajectory starts
     noise_cut_below: bool = False    # the table's lowest node carries no noise: none below the table
+    noise_cut_end: bool = False      # the table's last node carries no noise: none after the table
     bump: tuple = (0.0, 0.0, 0.0)    # (m, K, Sigma) of the Gaussian bump (centre phi_0 = phi_T)
     table_n: int = 1
     table_lo: float = 0.0
@@ -170,6 +173,35 @@ def srusr_matched(n_traj: int = 1_000_000, seed: int = 7, sigma: float = 1.0) ->
     pi0 = -A_PLUS / (V0 + A_PLUS * MATCH_PHI_START)
     return srusr_bessel(n_traj=n_traj, seed=seed).with_(
         name=f"srusr_matched_sigma{sigma:g}", noise="matched", sigma=sigma, match_start=(MATCH_PHI_START, pi0))
+
+
+# Noise indexed by time: the runs start on the matched table's classical trajectory, at the
+# transition, with the momentum it has there.  Written by `python -m oracle.derive_constants --time`
+# (scipy solve from MATCH_PHI_START; oracle Euler-Maruyama passage): 7.61 e-folds from phi = 1,
+# pi there is 0.65 % below -sqrt(2 eps_+) in magnitude, and the slow final phase turns that into
+# a noise-free passage of 12.18 e-folds to phi_end.
+TIME_PI_IN = -0.14049970258869465
+N_REF_TIME = 12.179564152175258
+
+
+def srusr_time(n_traj: int = 1_000_000, seed: int = 13, tau_hi: float = 12.5, table_n: int = TABLE_N,
+               sigma: float = 1.0) -> Workload:
+    """The SR -> USR problem with the Bessel-matched noise indexed by time, the paper's scheme
+    (Sec. 4.1): table_n nodes over tau in [0, tau_hi] after the classical trajectory from phi = 1
+    passes phi_in = 0, the runs started on it (TIME_PI_IN), the last node zero, so the noise (and
+    the bias) stop at tau_hi and the run goes on classically to phi_end.  tau_hi = 12.5 keeps the
+    noise on past the classical passage (12.18 e-folds); a smaller tau_hi switches it off earlier."""
+    return srusr_matched(n_traj=n_traj, seed=seed, sigma=sigma).with_(
+        name=f"srusr_time_tau{tau_hi:g}", noise="matched_time", pi_in=TIME_PI_IN, N_ref=N_REF_TIME,
+        table_n=table_n, table_lo=0.0, table_hi=tau_hi, noise_cut_end=True)
+
+
+def srusr_is_fp32_time(A_bias: float = 2.0, n_traj: int = 100_000_000, seed: int = 17) -> Workload:
+    """srusr_is_fp32 on the time-indexed problem of srusr_time."""
+    t = srusr_time()
+    return srusr_is_fp32(A_bias=A_bias, n_traj=n_traj, seed=seed).with_(
+        name=f"srusr_is_fp32_time_A{A_bias:g}", noise="matched_time", match_start=t.match_start, pi_in=t.pi_in,
+        N_ref=t.N_ref, table_lo=0.0, table_hi=t.table_hi, noise_cut_end=True)
 
 
 def srusr_is_fp32_matched(A_bias: float = 2.0, n_traj: int = 100_000_000, seed: int = 3) -> Workload:

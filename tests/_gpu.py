@@ -23,6 +23,12 @@ def gpu_table(w: Workload, pot):
         if w.noise_cut_below:
             S[0] = 0.0
         return S, t, w.table_lo, w.table_hi
+    if w.noise == "matched_time":
+        S, t, _, _ = fpt.fpt_noise_table_matched_time(pot, w.sigma, w.table_n, w.table_lo, w.table_hi,
+                                                      *w.match_start, w.phi_in)
+        if w.noise_cut_end:
+            S[-1] = 0.0
+        return S, t, w.table_lo, w.table_hi
     S, t = fpt.fpt_noise_table_bessel(pot, w.sigma, w.table_n, w.table_lo, w.table_hi)
     return S, t, w.table_lo, w.table_hi
 
@@ -32,7 +38,8 @@ def gpu_context(w: Workload, **kw) -> fpt.Context:
     S, t, lo, hi = gpu_table(w, pot)
     args = dict(bias_kind=w.bias_kind, A=w.A_bias, precision=w.precision, bins_kind=w.bins_kind,
                 n_bins=w.n_bins, lo=w.lo, hi=w.hi, N_ref=w.N_ref, max_steps=w.max_steps,
-                instance=w.extra.get("instance", 0))
+                instance=w.extra.get("instance", 0),
+                axis=fpt.FPT_AXIS_TIME if w.noise == "matched_time" else fpt.FPT_AXIS_PHI)
     if w.bias_kind == 2:
         args.update(mlp_params=w.mlp_params, norm=w.mlp_norm, mlp_every=0, grid_n=w.grid_n,
                     grid_range=w.grid_range)

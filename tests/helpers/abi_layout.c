@@ -15,6 +15,7 @@ int main(void)
     S(fpt_noise_table); F(fpt_noise_table, n); F(fpt_noise_table, phi_lo); F(fpt_noise_table, phi_hi);
     F(fpt_noise_table, S); F(fpt_noise_table, tan_theta);
     F(fpt_noise_table, dim); F(fpt_noise_table, Xi_pp); F(fpt_noise_table, Xi_pq); F(fpt_noise_table, Xi_qq);
+    F(fpt_noise_table, axis);
     S(fpt_bias); F(fpt_bias, kind); F(fpt_bias, A); F(fpt_bias, mlp_params); F(fpt_bias, norm);
     F(fpt_bias, mlp_every); F(fpt_bias, grid_n); F(fpt_bias, grid_range);
     S(fpt_options); F(fpt_options, precision); F(fpt_options, bins_kind); F(fpt_options, n_bins);

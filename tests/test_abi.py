@@ -203,3 +203,43 @@ def test_bump_variants_are_reported_unsupported(lib, case):
                         ctypes.byref(h))
     assert rc == fpt.FPT_EUNSUPPORTED, (rc, lib.fpt_last_error())
     assert not h.value
+
+
+@pytest.mark.parametrize("case", ["axis2", "axis_neg", "2d", "mlp", "reversed"])
+def test_time_axis_validation(lib, case):
+    """Tables with nodes in time: an unknown axis and a reversed range are invalid; 2D noise and the
+    learned bias do not take a time axis."""
+    pot = _pot()
+    S, t = np.array([1e-6, 2e-6, 0.0]), np.zeros(3)
+    X = [np.full(3, 1e-12), np.full(3, 1e-13), np.full(3, 1e-12)]
+    lo, hi = (1.0, 0.0) if case == "reversed" else (0.0, 1.0)
+    if case == "2d":
+        tab = fpt.fpt_noise_table(3, lo, hi, None, None, 2, *[x.ctypes.data_as(fpt._dp) for x in X])
+    else:
+        tab = fpt.fpt_noise_table(3, lo, hi, S.ctypes.data_as(fpt._dp), t.ctypes.data_as(fpt._dp))
+    tab.axis = {"axis2": 2, "axis_neg": -1}.get(case, fpt.FPT_AXIS_TIME)
+    params = np.zeros(fpt.FPT_MLP_NPARAM, dtype=np.float32)
+    bias = fpt.fpt_bias(2 if case == "mlp" else 0, 0.0, params.ctypes.data_as(fpt._fp),
+                        (ctypes.c_double * 4)(0, 1, 0, 1), 0, (ctypes.c_int32 * 2)(8, 8),
+                        (ctypes.c_double * 4)(-1, 1, -1, 1))
+    opts = fpt.fpt_options(0, 0, 8, -1.0, 1.0, 0.0, 1000, 0, 0, 0, 0)
+    h = ctypes.c_void_p()
+    rc = lib.fpt_create(ctypes.byref(pot), ctypes.byref(tab), ctypes.byref(bias), ctypes.byref(opts),
+                        ctypes.byref(h))
+    expect = fpt.FPT_EUNSUPPORTED if case in ("2d", "mlp") else fpt.FPT_EINVAL
+    assert rc == expect and not h.value, (rc, lib.fpt_last_error())
+
+
+@pytest.mark.parametrize("case", ["n0", "sigma", "t_range", "ref_above_start", "nan_ref", "eps1"])
+def test_time_node_matched_table_argument_errors(lib, case):
+    """Host-side checks of fpt_noise_table_matched_time (no device needed)."""
+    pot = _pot()
+    a = dict(sigma=1.0, n=4, t_lo=0.0, t_hi=1.0, phi_start=1.0, pi_start=-0.14, phi_ref=0.0)
+    a.update({"n0": dict(n=0), "sigma": dict(sigma=2.5), "t_range": dict(t_hi=0.0),
+              "ref_above_start": dict(phi_ref=1.0), "nan_ref": dict(phi_ref=float("nan")),
+              "eps1": dict(pi_start=-1.5)}[case])
+    outs = [np.empty(max(a["n"], 1)) for _ in range(4)]
+    rc = lib.fpt_noise_table_matched_time(ctypes.byref(pot), a["sigma"], a["n"], a["t_lo"], a["t_hi"],
+                                          a["phi_start"], a["pi_start"], a["phi_ref"],
+                                          *[o.ctypes.data_as(fpt._dp) for o in outs])
+    assert rc == fpt.FPT_EINVAL, (rc, lib.fpt_last_error())

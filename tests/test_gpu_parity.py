@@ -265,3 +265,31 @@ def test_full_size_srusr_fp64_sampled():
     d = N - w.N_ref
     say(f"  mean deltaN {d.mean():.4e} sd {d.std():.4e}")
     assert abs(d.std() / W.SIGMA_LIN_SRUSR - 1.0) < 0.05
+
+
+@pytest.mark.parametrize("case", ["fp64", "fp32", "2d"])
+def test_maximum_table_and_bins(case):
+    """FPT_MAX_BINS = 1024 log bins with the largest tables the kernels stage (4096 1D nodes; 2048
+    2D nodes): LDS holds both.  FP64 and 2D: the histogram equals the oracle's histogram of the
+    oracle's own trajectories (counts exactly, sums to 1e-9); FP32: of the FP32 run's own dumps."""
+    nb = fpt.FPT_MAX_BINS
+    if case == "2d":
+        w = W.srusr_2d(n_traj=700, A_bias=1.0)
+    else:
+        w = W.srusr_bessel(n_traj=2000, seed=21).with_(bias_kind=W.BIAS_CONST, A_bias=1.5,
+                                                       precision=1 if case == "fp32" else 0)
+    w = w.with_(bins_kind=W.BINS_LOG, n_bins=nb, lo=1e-3, hi=0.3)
+    assert w.table_n in (4096, 2048)
+    say(f"max sizes {case}")
+    (N, lnw, st), h = gpu_run(w)
+    ref_N, ref_l, ref_s = (N, lnw, st) if case == "fp32" else oracle_run(w)
+    if case != "fp32":
+        assert_fp64_parity((N, lnw, st), (ref_N, ref_l, ref_s))
+    ho = orc.histogram(ref_N, ref_l, ref_s, w.N_ref, w.bins_kind, nb, w.lo, w.hi)
+    assert len(h["count"]) == nb + 2
+    assert int(h["count"].sum()) == w.n_traj
+    diff = np.abs(h["count"].astype(np.int64) - ho["count"].astype(np.int64))
+    assert diff.sum() <= (0 if case == "fp32" else 2), diff.sum()   # an FP64 near-tie may move one trajectory
+    if case == "fp32" or diff.sum() == 0:
+        np.testing.assert_allclose(h["sum_w"], ho["sum_w"], rtol=1e-9, atol=1e-300)
+        np.testing.assert_allclose(h["sum_lnw"], ho["sum_lnw"], rtol=1e-9, atol=1e-9)

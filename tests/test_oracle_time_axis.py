@@ -24,6 +24,15 @@ def test_time_nodes_equal_phi_nodes(orc):
                                              *w.match_start)
         assert ph[0] < w.phi_in
         np.testing.assert_allclose([S[0], t[0], fac[0]], [Sp[0], tp[0], fp[0]], rtol=1e-12, atol=1e-15)
+    # the node at tau = 0 is the reference point: on the kink (phi_ref = phi_T = 0) it is the phi node
+    # at phi_T exactly, on the branch before the kink, whatever the rounding of the trajectory
+    S, t, fac, ph = orc.noise_table_matched_time(w.kind, w.V0, w.phi_T, w.A_plus, w.A_minus, 1.0, 2, 0.0, 0.01,
+                                                 *w.match_start, w.phi_T)
+    Sp, tp, fp = orc.noise_table_matched(w.kind, w.V0, w.phi_T, w.A_plus, w.A_minus, 1.0, 1, w.phi_T, w.phi_T,
+                                         *w.match_start)
+    assert ph[0] == w.phi_T and ph[1] < w.phi_T
+    np.testing.assert_allclose([S[0], t[0], fac[0]], [Sp[0], tp[0], fp[0]], rtol=1e-12, atol=1e-15)
+    assert abs(fac[0] - 1.0) < 1e-3 and fac[1] < 0.5      # before and after the kink's kick
     # a node outside the followed trajectory, and a reference the trajectory never passes, are errors
     with pytest.raises(ValueError):
         orc.noise_table_matched_time(w.kind, w.V0, w.phi_T, w.A_plus, w.A_minus, 1.0, 3, -50.0, 1.0,
