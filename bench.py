@@ -81,9 +81,9 @@ PEAK_HBM_GBS = 8000.0
 # process (FETCH_SIZE reads 0.5 GiB: x2.0; WRITE_SIZE reads 1 GiB: x1.0).  Valid only for the
 # kernel source it was measured on (hash of the kernel file and its header).
 MEASURED_TRAFFIC = {
-    "source_sha256": "5f1effd42da92fd61f7b5bd523f0a14191cd2433fa2ee573e0b02d29313f33b5",
+    "source_sha256": "748a325ef535b4d4ad257712b080f277f3e799a8cd0072cfd1ae1028440de45f",
     "workload": "srusr_is_fp32_A2", "n_traj": 100_000_000,
-    "fetch_bytes": 463.25 * 1024 * 2.0, "write_bytes": 2082597.5625 * 1024 * 1.0,
+    "fetch_bytes": 466.6875 * 1024 * 2.0, "write_bytes": 2083341.9375 * 1024 * 1.0,
 }
 
 
