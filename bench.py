@@ -139,10 +139,10 @@ def cpu_baseline(w, target_s: float = 20.0) -> dict:
     kw = dict(instance=w.extra.get("instance", 0), max_steps=w.max_steps)
     if w.noise in ("xi_const", "bessel2d"):
         p2 = oracle_problem2d(w)
-        run = lambda n, off: orc.run2d(p2, w.dN, w.seed, n, traj_offset=off, **kw)
+        run = lambda n, off, nt=0: orc.run2d(p2, w.dN, w.seed, n, traj_offset=off, n_threads=nt, **kw)
     else:
         p1 = oracle_problem(w)
-        run = lambda n, off: orc.run(p1, w.dN, w.seed, n, traj_offset=off, **kw)
+        run = lambda n, off, nt=0: orc.run(p1, w.dN, w.seed, n, traj_offset=off, n_threads=nt, **kw)
     n0 = max(64, threads * 8)
     t0 = time.perf_counter()
     _, _, st = run(n0, 0)
@@ -152,10 +152,29 @@ def cpu_baseline(w, target_s: float = 20.0) -> dict:
     _, _, st = run(n1, n0)
     dt1 = time.perf_counter() - t1
     steps1 = int((st & orc.STEP_MASK).astype("uint64").sum())
+    # one host thread on the trajectories that follow, for about a tenth of the time
+    n2 = max(1, int(n1 * 0.1 / threads))
+    t2 = time.perf_counter()
+    _, _, st2 = run(n2, n0 + n1, 1)
+    dt2 = time.perf_counter() - t2
+    steps2 = int((st2 & orc.STEP_MASK).astype("uint64").sum())
     return {"value": steps1 / dt1, "unit": "trajectory-steps/s", "cores": threads, "kind": "oracle",
             "sample": f"trajectories {n0}..{n0 + n1 - 1} of the same workload ({steps1} steps, "
                       f"{dt1:.1f} s, FP64 oracle, OpenMP over trajectories)",
-            "seconds": dt1}
+            "seconds": dt1, "cpu_model": _cpu_model(),
+            "value_1_thread": steps2 / dt2,
+            "sample_1_thread": f"trajectories {n0 + n1}..{n0 + n1 + n2 - 1} ({steps2} steps, {dt2:.1f} s)"}
+
+
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def tail_at(hist, w, x):

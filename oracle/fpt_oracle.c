@@ -50,6 +50,8 @@
 #include <omp.h>
 #endif
 
+static int orc_threads(int n_threads);
+
 #define ORC_POT_PIECEWISE_LINEAR 0
 #define ORC_POT_EXPONENTIAL 1
 #define ORC_POT_GAUSSIAN_BUMP 2
@@ -523,13 +525,10 @@ int orc_run(int kind, const double pot[7],
     P.bias_kind = bias_kind; P.A_bias = A_bias; P.mlp = mlp_params;
     if (mlp_norm) memcpy(P.norm, mlp_norm, sizeof P.norm);
     P.dN = dN; P.seed = seed; P.instance = instance; P.max_steps = max_steps;
-#ifdef _OPENMP
-    if (n_threads > 0) omp_set_num_threads(n_threads);
-#else
-    (void)n_threads;
-#endif
+    const int n_thr = orc_threads(n_threads);
+    (void)n_thr;
     int64_t nt = (int64_t)n_traj;
-#pragma omp parallel for schedule(dynamic, 16)
+#pragma omp parallel for num_threads(n_thr) schedule(dynamic, 16)
     for (int64_t i = 0; i < nt; ++i)
         orc_trajectory(&P, traj_offset + (uint64_t)i, &N_out[i], &lnw_out[i], &steps_out[i]);
     free(grid_a);
@@ -543,6 +542,13 @@ int orc_max_threads(void)
 #else
     return 1;
 #endif
+}
+
+/* Threads of one parallel region: n_threads if positive, else the OpenMP default.  A per-region */
+/* count leaves the process-wide default alone.                                                   */
+static int orc_threads(int n_threads)
+{
+    return n_threads > 0 ? n_threads : orc_max_threads();
 }
 
 /* ------------------------------------------------------------------------- */
@@ -579,16 +585,13 @@ int orc_mlp_replay_grad(int kind, const double pot[7],
     P.bias_kind = ORC_BIAS_MLP; P.mlp = theta_old; P.mlp_every = 1;
     memcpy(P.norm, mlp_norm, sizeof P.norm);
     P.dN = dN; P.seed = seed; P.instance = instance; P.max_steps = max_steps;
-#ifdef _OPENMP
-    if (n_threads > 0) omp_set_num_threads(n_threads);
-#else
-    (void)n_threads;
-#endif
+    const int n_thr = orc_threads(n_threads);
+    (void)n_thr;
     const double sqrt_dN = sqrt(dN);
     int64_t nt = (int64_t)n_traj;
     double J = 0.0;
     for (int k = 0; k < MLP_NPARAM; ++k) grad_out[k] = 0.0;
-#pragma omp parallel
+#pragma omp parallel num_threads(n_thr)
     {
         double *g_local = (double *)calloc(MLP_NPARAM, sizeof(double));
         double *g_path = (double *)calloc(MLP_NPARAM, sizeof(double));
@@ -691,15 +694,12 @@ int orc_grid_replay_grad(int kind, const double pot[7],
     P.bias_kind = ORC_BIAS_MLP; P.mlp = theta_old; P.mlp_every = 0; P.grid = g; P.grid_a = a_old;
     memcpy(P.norm, mlp_norm, sizeof P.norm);
     P.dN = dN; P.seed = seed; P.instance = instance; P.max_steps = max_steps;
-#ifdef _OPENMP
-    if (n_threads > 0) omp_set_num_threads(n_threads);
-#else
-    (void)n_threads;
-#endif
+    const int n_thr = orc_threads(n_threads);
+    (void)n_thr;
     const double sqrt_dN = sqrt(dN);
     const int64_t nt = (int64_t)n_traj;
     double J = 0.0;
-#pragma omp parallel
+#pragma omp parallel num_threads(n_thr)
     {
         double *G_local = (double *)calloc(ng, sizeof(double));
         double J_local = 0.0;
@@ -1058,13 +1058,10 @@ int orc_run2d(int kind, const double pot[7], int n_tab, double phi_lo, double ph
     P.phi_in = phi_in; P.pi_in = pi_in; P.phi_end = phi_end;
     P.bias_kind = bias_kind; P.A_bias = A_bias;
     P.dN = dN; P.seed = seed; P.instance = instance; P.max_steps = max_steps;
-#ifdef _OPENMP
-    if (n_threads > 0) omp_set_num_threads(n_threads);
-#else
-    (void)n_threads;
-#endif
+    const int n_thr = orc_threads(n_threads);
+    (void)n_thr;
     const int64_t nt = (int64_t)n_traj;
-#pragma omp parallel for schedule(dynamic, 16)
+#pragma omp parallel for num_threads(n_thr) schedule(dynamic, 16)
     for (int64_t i = 0; i < nt; ++i)
         orc_trajectory2d(&P, traj_offset + (uint64_t)i, &N_out[i], &lnw_out[i], &steps_out[i]);
     free(S);
@@ -1370,13 +1367,10 @@ int orc_noise_table_matched(int kind, const double pot[7], double sigma, int n, 
     const size_t nb = orc_background(kind, pot, phi_start, pi_start, phi_lo, INFINITY, NAN, 0.0, NULL, &bN, &bphi,
                                      &bpi);
     if (nb == 0) return -1;
-#ifdef _OPENMP
-    if (n_threads > 0) omp_set_num_threads(n_threads);
-#else
-    (void)n_threads;
-#endif
+    const int n_thr = orc_threads(n_threads);
+    (void)n_thr;
     int bad = 0;
-#pragma omp parallel for schedule(dynamic, 1)
+#pragma omp parallel for num_threads(n_thr) schedule(dynamic, 1)
     for (int j = 0; j < n; ++j) {
         fac_out[j] = 1.0;
         const double phi_j = phi_lo + (double)j * h;
@@ -1419,13 +1413,10 @@ int orc_noise_table_matched_time(int kind, const double pot[7], double sigma, in
                                      (n > 1 ? t_hi : t_lo) + 2e-4, &N_ref, &bN, &bphi, &bpi);
     if (nb == 0) return -1;
     if (isnan(N_ref)) { free(bN); free(bphi); free(bpi); return -1; }
-#ifdef _OPENMP
-    if (n_threads > 0) omp_set_num_threads(n_threads);
-#else
-    (void)n_threads;
-#endif
+    const int n_thr = orc_threads(n_threads);
+    (void)n_thr;
     int bad = 0;
-#pragma omp parallel for schedule(dynamic, 1)
+#pragma omp parallel for num_threads(n_thr) schedule(dynamic, 1)
     for (int j = 0; j < n; ++j) {
         const double tau = t_lo + (double)j * h, Ns = N_ref + tau;
         fac_out[j] = NAN;
