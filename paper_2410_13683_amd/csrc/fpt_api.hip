@@ -627,7 +627,9 @@ extern "C" int fpt_create(const fpt_potential *pot, const fpt_noise_table *table
     e = hipMemcpy(base, h64.data(), sizeof(double) * 2 * nt, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(base + off_tab32, h32.data(), sizeof(float) * 4 * nt, hipMemcpyHostToDevice);
     std::vector<float> hr;
-    c->drift_table_used = build_drift_table(*pot, nt, table->phi_lo, table->phi_hi, hr);
+    // the V'/V intervals follow phi nodes: a time-indexed table leaves them all NaN (computed exactly)
+    if (time_axis) hr.assign(2 * (size_t)nt, std::numeric_limits<float>::quiet_NaN());
+    else c->drift_table_used = build_drift_table(*pot, nt, table->phi_lo, table->phi_hi, hr);
     if (e == hipSuccess) e = hipMemcpy(base + off_rtab, hr.data(), sizeof(float) * 2 * nt, hipMemcpyHostToDevice);
     if (e == hipSuccess && dim == 2)
         e = hipMemcpy(base + off_tab2d, h2d.data(), sizeof(double) * h2d.size(), hipMemcpyHostToDevice);
