@@ -123,6 +123,8 @@ def _workload(name: str, n_traj: int | None):
         w = W.srusr_is_fp32_time(A_bias=2.0)
     elif name == "bump":
         w = W.gaussian_bump_is(A_bias=3.0)
+    elif name == "bump_time":
+        w = W.gaussian_bump_time_is(A_bias=3.0)
     else:
         raise SystemExit(f"unknown workload {name}")
     if n_traj:
@@ -440,7 +442,7 @@ def main() -> int:
                       if w.noise == "bessel2d" else
                       f"Bessel-matched table (B_k from the mode equation), {w.table_n} phi nodes, sigma={w.sigma}"
                       if w.noise == "matched" else
-                      f"Bessel-matched table on {w.table_n} time nodes over tau in [0, {w.table_hi:g}] after the "
+                      f"Bessel-matched table on {w.table_n} time nodes over tau in [0, {w.table_hi:.6g}] after the "
                       f"reference trajectory passes phi_in, zero after it, sigma={w.sigma}"
                       if w.noise == "matched_time" else
                       f"Bessel-ansatz table, {w.table_n} phi nodes, sigma={w.sigma}"),

@@ -122,7 +122,7 @@ def bump_constants():
     eps_V = 0.5 * dlnV(p_star) ** 2
     V0 = 2.1e-9 * 24.0 * math.pi ** 2 * eps_V / u
     return dict(N_T=N_T, N_usr_end=N_usr_end, N_end=N_end, eps2_hi=eps2(N_hi), phi_in=phi_in, pi_in=pi_in,
-                phi_lo=phi_lo, V0=V0, phi_star=p_star)
+                phi_lo=phi_lo, V0=V0, phi_star=p_star, tau_hi=N_hi - N_lo)
 
 
 def bump_noise_free_N(c, phi_end: float, dN: float) -> float:

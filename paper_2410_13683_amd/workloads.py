@@ -227,6 +227,7 @@ BUMP_EPS2 = 0.7316306386485752      # eps2 at N_T + 4.7 (the last mode's coarse-
 BUMP_PHI_END = 2.0                  # on the slow-roll attractor again, ~16 e-folds after phi_in
 BUMP_N_REF = 16.010232287737356     # noise-free passage to BUMP_PHI_END at dN = 1e-3
 BUMP_MATCH_START = 2.5              # the matched table's classical trajectory starts here
+BUMP_TAU_HI = 3.4955927519341046    # the same window in e-folds: N_T + 4.7 - (N_T + N_USR_END)/2
 
 
 def gaussian_bump(n_traj: int = 1_000_000, seed: int = 11, A_bias: float = 0.0, dN: float = 1e-3) -> Workload:
@@ -249,6 +250,23 @@ def gaussian_bump_is(A_bias: float = 3.0, n_traj: int = 10_000_000, seed: int = 
     tail, where the classical constant-eps2 form of eq. (delta_N_pdf_constant_epsilon_2) applies."""
     return gaussian_bump(n_traj=n_traj, seed=seed, A_bias=A_bias).with_(
         name=f"gaussian_bump_is_A{A_bias:g}", bins_kind=BINS_LOG, n_bins=96, lo=0.02, hi=3.0)
+
+
+def gaussian_bump_time(n_traj: int = 1_000_000, seed: int = 11, A_bias: float = 0.0, dN: float = 1e-3,
+                       table_n: int = TABLE_N) -> Workload:
+    """gaussian_bump with the noise indexed by time, the paper's scheme (Sec. 4.1): table_n nodes over
+    tau in [0, BUMP_TAU_HI] after the classical trajectory passes phi_in, the same window of modes in
+    e-folds, the last node zero, so the noise (and the bias) stop after BUMP_TAU_HI e-folds whatever
+    phi a trajectory has reached."""
+    return gaussian_bump(n_traj=n_traj, seed=seed, A_bias=A_bias, dN=dN).with_(
+        name=f"gaussian_bump_time_A{A_bias:g}", noise="matched_time", table_n=table_n, table_lo=0.0,
+        table_hi=BUMP_TAU_HI, noise_cut_below=False, noise_cut_end=True)
+
+
+def gaussian_bump_time_is(A_bias: float = 3.0, n_traj: int = 10_000_000, seed: int = 12) -> Workload:
+    """gaussian_bump_time with a constant bias and the far-tail bins of gaussian_bump_is."""
+    return gaussian_bump_time(n_traj=n_traj, seed=seed, A_bias=A_bias).with_(
+        name=f"gaussian_bump_time_is_A{A_bias:g}", bins_kind=BINS_LOG, n_bins=96, lo=0.02, hi=3.0)
 
 
 def batched_instances(n_inst: int = 64, seed: int = 4, n_min: float = 1e5, n_max: float = 1e7,

@@ -107,3 +107,20 @@ def test_linear_in_time_noise_closed_form(orc):
         assert int(np.argmax(phis <= 0.0)) == n
         N_ref = (n - 1) * dN + dN * phis[n - 1] / (phis[n - 1] - phis[n])
         assert abs(N[i] - N_ref) < 1e-10 * N_ref
+
+
+def test_bump_time_nodes_equal_phi_nodes(orc):
+    """The Gaussian bump: a time node is the phi node at the trajectory's phi there, and the window's
+    length in e-folds (from the scipy background) ends at the phi window's lower edge.  On the
+    plateau pi ~ 1e-4, so the phi node's root in N carries 1e-16/|pi| ~ 1e-12 e-folds of rounding
+    and k = sigma e^N H with it: 1e-10 here (1e-12 on the steeper SR -> USR trajectory)."""
+    w = W.gaussian_bump_time()
+    for tau in (0.0, 0.7, 2.1, W.BUMP_TAU_HI):
+        S, t, fac, ph = orc.noise_table_matched_time(w.kind, w.V0, w.phi_T, w.A_plus, w.A_minus, 1.0, 1, tau, tau,
+                                                     *w.match_start, w.phi_in, bump=w.bump)
+        Sp, tp, fp = orc.noise_table_matched(w.kind, w.V0, w.phi_T, w.A_plus, w.A_minus, 1.0, 1, ph[0], ph[0],
+                                             *w.match_start, bump=w.bump)
+        np.testing.assert_allclose([S[0], t[0], fac[0]], [Sp[0], tp[0], fp[0]], rtol=1e-10, atol=1e-15)
+        if tau == 0.0:
+            assert ph[0] == w.phi_in
+    assert abs(ph[0] - W.BUMP_PHI_LO) < 1e-12
