@@ -119,6 +119,8 @@ def _workload(name: str, n_traj: int | None):
         w = W.srusr_2d()
     elif name == "srusr_matched":
         w = W.srusr_is_fp32_matched(A_bias=2.0)
+    elif name == "srusr_2d_time":
+        w = W.srusr_2d_time()
     elif name == "srusr_time":
         w = W.srusr_is_fp32_time(A_bias=2.0)
     elif name == "bump":
@@ -139,7 +141,7 @@ def cpu_baseline(w, target_s: float = 20.0) -> dict:
     from tests._glue import oracle_problem, oracle_problem2d
     threads = orc.max_threads()
     kw = dict(instance=w.extra.get("instance", 0), max_steps=w.max_steps)
-    if w.noise in ("xi_const", "bessel2d"):
+    if w.noise in ("xi_const", "bessel2d", "bessel2d_time"):
         p2 = oracle_problem2d(w)
         run = lambda n, off, nt=0: orc.run2d(p2, w.dN, w.seed, n, traj_offset=off, n_threads=nt, **kw)
     else:
@@ -413,7 +415,7 @@ def main() -> int:
     avg_ms = float(np.mean(kernel_ms))
     steps_per_launch = steps_total / args.steps
     flops_step = ALG_FLOPS_PER_STEP[prec] + (ALG_FLOPS_LEARNED_EXTRA[prec] if learned else 0.0)
-    if w.noise == "bessel2d":
+    if w.noise in ("bessel2d", "bessel2d_time"):
         flops_step = ALG_FLOPS_2D["const" if w.bias_kind else "none"]
     if w.kind == 2:
         flops_step = ALG_FLOPS_BUMP_FP64
@@ -440,6 +442,9 @@ def main() -> int:
                           "piecewise-linear slow roll -> ultra-slow roll, V0=1e-10, eps+=0.01, eps-=1e-8"),
             "noise": (f"2D noise, full Bunch-Davies mode at -k eta = {w.sigma}, {w.table_n} phi nodes"
                       if w.noise == "bessel2d" else
+                      f"2D noise, full Bunch-Davies mode at -k eta = {w.sigma}, {w.table_n} time nodes over tau in "
+                      f"[0, {w.table_hi:.6g}] after the reference trajectory passes phi_in, zero after it"
+                      if w.noise == "bessel2d_time" else
                       f"Bessel-matched table (B_k from the mode equation), {w.table_n} phi nodes, sigma={w.sigma}"
                       if w.noise == "matched" else
                       f"Bessel-matched table on {w.table_n} time nodes over tau in [0, {w.table_hi:.6g}] after the "
@@ -465,7 +470,7 @@ def main() -> int:
             "unit": "TFLOP/s",
             "frac": achieved / PEAK_TFLOPS[prec],
             "traffic": None,
-            "kernel": ("em2d_kernel<FP64, 2D noise>" if w.noise == "bessel2d" else
+            "kernel": ("em2d_kernel<FP64, 2D noise>" if w.noise in ("bessel2d", "bessel2d_time") else
                        "em_kernel<FP64, Gaussian bump>" if w.kind == 2 else
                        "em_kernel<FP32 state, const bias, table>" if prec == "fp32" else "em_kernel<FP64>"),
             "kernel_ms": avg_ms,

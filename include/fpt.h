@@ -122,15 +122,16 @@ typedef struct {
  *     eq. (weight_A) for B = S (a e).  Each step takes two normals: call n >> 1
  *     of the generator, (u0, u1) for step 2m and (u2, u3) for step 2m + 1.
  *     Supported with FP64 state and no or constant bias.
- *   axis FPT_AXIS_TIME (1D noise, n >= 2) -- the nodes are in the run's time
- *     instead, N_j = phi_lo + j h (phi_lo, phi_hi then hold N): step n reads the
- *     table at N = n dN.  This is the paper's own scheme (Sec. 4.1): the noise is
+ *   axis FPT_AXIS_TIME (n >= 2) -- the nodes are in the run's time instead,
+ *     N_j = phi_lo + j h (phi_lo, phi_hi then hold N): step n reads the table at
+ *     N = n dN.  This is the paper's own scheme (Sec. 4.1): the noise is
  *     precomputed along the classical trajectory and indexed by time, and a last
  *     node of zero switches it off after a fixed number of steps (the edge node
  *     applies beyond the table).  The FP32-state path then computes V'/V exactly
- *     every step.  Not with 2D noise or a learned bias (FPT_EUNSUPPORTED), nor in
- *     batches (FPT_EINVAL).  A time-indexed table of n == 1 is constant noise.
- *     fpt_noise_table_matched_time gives the Bessel-matched noise on such nodes. */
+ *     every step.  1D and 2D noise; not with a learned bias (FPT_EUNSUPPORTED), nor
+ *     in batches (FPT_EINVAL).  A time-indexed table of n == 1 is constant noise.
+ *     fpt_noise_table_matched_time gives the Bessel-matched noise on such nodes,
+ *     fpt_noise_table_bessel2d_time the 2D covariance. */
 typedef struct {
     int32_t n;
     double phi_lo, phi_hi;
@@ -376,6 +377,22 @@ int fpt_noise_table_matched(const fpt_potential *pot, double sigma, int32_t n, d
 int fpt_noise_table_matched_time(const fpt_potential *pot, double sigma, int32_t n, double t_lo, double t_hi,
                                  double phi_start, double pi_start, double phi_ref, double *S_out, double *tan_out,
                                  double *fac_out, double *phi_out);
+
+/* The 2D covariance of fpt_noise_table_bessel2d (eq. covariance_matrix_direct)
+ * on nodes in time, for a 2D table of axis FPT_AXIS_TIME (Sec. 4.1: the noise
+ * precomputed along the classical trajectory and read by the run's time).  Node j
+ * is the time tau_j = t_lo + j (t_hi - t_lo)/(n - 1) after the classical
+ * trajectory from (phi_start, pi_start) passes phi_ref, and takes the covariance
+ * at the trajectory's phi there, found as in fpt_noise_table_matched_time (the
+ * node at tau = 0 is phi_ref itself).  Outputs (host, n each; phi_out may be
+ * NULL): Xpp_out, Xpq_out, Xqq_out, phi_out = phi_j.  Computed by device kernels
+ * on the current device (about 50 MB of device scratch for the call).  Errors:
+ * FPT_EINVAL (sizes, sigma outside (0, 2], phi_start <= phi_ref, a trajectory
+ * that does not pass phi_ref, a node before N = 0 or after the trajectory ends,
+ * V <= 0, nu^2 <= 0 or nu within 1e-3 of an integer at a node), FPT_EHIP. */
+int fpt_noise_table_bessel2d_time(const fpt_potential *pot, double sigma, int32_t n, double t_lo, double t_hi,
+                                  double phi_start, double pi_start, double phi_ref, double *Xpp_out,
+                                  double *Xpq_out, double *Xqq_out, double *phi_out);
 
 /* ---- batches: many problems in one persistent launch ------------------------- */
 

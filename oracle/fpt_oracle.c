@@ -901,7 +901,8 @@ typedef struct {
     int kind;
     double pot[7];
     int n_tab;
-    double phi_lo, phi_hi;
+    double phi_lo, phi_hi;           /* node coordinates: phi, or the run's time N = n dN with tab_axis */
+    int tab_axis;
     const double *Spp, *Spq, *Sqq;   /* square roots of the node covariances */
     const double *e1, *e2;           /* unit principal axis of the node covariances */
     double phi_in, pi_in, phi_end;
@@ -934,8 +935,9 @@ void orc_principal_axis(double a, double b, double c, double *e1, double *e2)
     *e2 = v2 / norm;
 }
 
-/* S(phi) and e(phi): linear interpolation of the nodes' square roots and principal */
-/* axes, clamped to the edge nodes.                                                  */
+/* S and e at the coordinate phi (or the time, for a time-indexed table): linear     */
+/* interpolation of the nodes' square roots and principal axes, clamped to the edge  */
+/* nodes.                                                                            */
 static void orc_table2d_lookup(const orc_problem2d *P, double phi, double S[3], double e[2])
 {
     if (P->n_tab == 1) {
@@ -990,7 +992,7 @@ static void orc_trajectory2d(const orc_problem2d *P, uint64_t traj, double *N_ou
         const double D_pi = -(3.0 - pi_ * pi_ / 2.0) * (pi_ + dV / V);
         /* noise matrix S, principal axis e, bias B = A S e */
         double S[3], e[2];
-        orc_table2d_lookup(P, phi, S, e);
+        orc_table2d_lookup(P, P->tab_axis ? (double)n * dN : phi, S, e);
         const double A = (P->bias_kind == ORC_BIAS_CONST) ? P->A_bias : 0.0;
         const double B_phi = A * (S[0] * e[0] + S[1] * e[1]);
         const double B_pi = A * (S[1] * e[0] + S[2] * e[1]);
@@ -1028,9 +1030,11 @@ static void orc_trajectory2d(const orc_problem2d *P, uint64_t traj, double *N_ou
 
 /* Trajectories traj_offset .. traj_offset + n_traj - 1 with 2D noise given by */
 /* the node covariances Xi (each zero or positive definite).  bias_kind: NONE  */
-/* or CONST.  Returns 0, or -1 on invalid input.                               */
+/* or CONST.  tab_axis 1: the nodes are in the run's time (phi_lo, phi_hi hold */
+/* N), read at N = n dN.  Returns 0, or -1 on invalid input.                   */
 int orc_run2d(int kind, const double pot[7], int n_tab, double phi_lo, double phi_hi, const double *Xpp,
-              const double *Xpq, const double *Xqq, double phi_in, double pi_in, double phi_end, int bias_kind,
+              const double *Xpq, const double *Xqq, int tab_axis, double phi_in, double pi_in, double phi_end,
+              int bias_kind,
               double A_bias, double dN, uint64_t seed, uint32_t instance, uint64_t traj_offset, uint64_t n_traj,
               int64_t max_steps, double *N_out, double *lnw_out, uint32_t *steps_out, int n_threads)
 {
@@ -1053,7 +1057,7 @@ int orc_run2d(int kind, const double pot[7], int n_tab, double phi_lo, double ph
     memset(&P, 0, sizeof P);
     P.kind = kind;
     memcpy(P.pot, pot, sizeof P.pot);
-    P.n_tab = n_tab; P.phi_lo = phi_lo; P.phi_hi = phi_hi;
+    P.n_tab = n_tab; P.phi_lo = phi_lo; P.phi_hi = phi_hi; P.tab_axis = tab_axis;
     P.Spp = S; P.Spq = S + n_tab; P.Sqq = S + 2 * n_tab; P.e1 = S + 3 * n_tab; P.e2 = S + 4 * n_tab;
     P.phi_in = phi_in; P.pi_in = pi_in; P.phi_end = phi_end;
     P.bias_kind = bias_kind; P.A_bias = A_bias;
@@ -1392,6 +1396,25 @@ int orc_noise_table_matched(int kind, const double pot[7], double sigma, int n, 
     return bad ? -1 : 0;
 }
 
+/* The classical trajectory at time Ns = N_ref + tau (samples bN, bphi, bpi): phi by the cubic  */
+/* Hermite interpolant of the samples around Ns, pi linearly.  The node at tau = 0 is the      */
+/* reference point itself: phi_ref exactly, so that a reference on the kink (phi_ref = phi_T)  */
+/* keeps the node on the branch before it.  -1 if Ns lies outside the samples.                 */
+static int orc_time_node(const double *bN, const double *bphi, const double *bpi, size_t nb, double tau, double Ns,
+                         double phi_ref, double *phi_j, double *pi_j)
+{
+    if (!(Ns >= bN[0]) || !(Ns <= bN[nb - 1])) return -1;
+    size_t i = 1;
+    while (i < nb - 1 && bN[i] < Ns) ++i;              /* bN[i-1] <= Ns <= bN[i] */
+    const double dn = bN[i] - bN[i - 1], t = (Ns - bN[i - 1]) / dn;
+    const double t2 = t * t, t3 = t2 * t;
+    *phi_j = tau == 0.0 ? phi_ref
+                        : (2 * t3 - 3 * t2 + 1) * bphi[i - 1] + (t3 - 2 * t2 + t) * bpi[i - 1] * dn +
+                              (-2 * t3 + 3 * t2) * bphi[i] + (t3 - t2) * bpi[i] * dn;
+    *pi_j = bpi[i - 1] + t * (bpi[i] - bpi[i - 1]);
+    return 0;
+}
+
 /* The same noise on nodes in time: node j is the time tau_j = t_lo + j (t_hi - t_lo)/(n - 1)  */
 /* after the classical trajectory from (phi_start, pi_start) passes phi_ref (the run's phi_in), */
 /* so that a run indexes it by its own time n dN -- the paper's scheme, noise precomputed along */
@@ -1420,21 +1443,12 @@ int orc_noise_table_matched_time(int kind, const double pot[7], double sigma, in
     for (int j = 0; j < n; ++j) {
         const double tau = t_lo + (double)j * h, Ns = N_ref + tau;
         fac_out[j] = NAN;
-        if (!(Ns >= bN[0]) || !(Ns <= bN[nb - 1])) {
+        double phi_j, pi_j;
+        if (orc_time_node(bN, bphi, bpi, nb, tau, Ns, phi_ref, &phi_j, &pi_j) != 0) {
 #pragma omp atomic write
             bad = 1;
             continue;
         }
-        size_t i = 1;
-        while (i < nb - 1 && bN[i] < Ns) ++i;              /* bN[i-1] <= Ns <= bN[i] */
-        const double dn = bN[i] - bN[i - 1], t = (Ns - bN[i - 1]) / dn;
-        const double t2 = t * t, t3 = t2 * t;
-        /* the node at tau = 0 is the reference point itself: phi_ref exactly, so that a reference */
-        /* on the kink (phi_ref = phi_T) keeps the node on the branch before it                     */
-        const double phi_j = tau == 0.0 ? phi_ref
-                                        : (2 * t3 - 3 * t2 + 1) * bphi[i - 1] + (t3 - 2 * t2 + t) * bpi[i - 1] * dn +
-                                              (-2 * t3 + 3 * t2) * bphi[i] + (t3 - t2) * bpi[i] * dn;
-        const double pi_j = bpi[i - 1] + t * (bpi[i] - bpi[i - 1]);
         if (phi_out) phi_out[j] = phi_j;
         double fac;
         if (orc_noise_table_bessel(kind, pot, sigma, 1, phi_j, phi_j, &S_out[j], &tan_out[j]) != 0 ||
@@ -1445,6 +1459,39 @@ int orc_noise_table_matched_time(int kind, const double pot[7], double sigma, in
         }
         fac_out[j] = fac;
         S_out[j] *= sqrt(fac);
+    }
+    free(bN); free(bphi); free(bpi);
+    return bad ? -1 : 0;
+}
+
+/* The 2D covariance of orc_noise_table_bessel2d on nodes in time (Sec. 4.1: the noise precomputed */
+/* along the classical trajectory and read by the run's time): node j is tau_j = t_lo + j h after */
+/* the trajectory from (phi_start, pi_start) passes phi_ref, and takes the covariance at the      */
+/* trajectory's phi there (orc_time_node).  phi_out (may be NULL) receives those phi.  Returns 0,  */
+/* or -1 on invalid input, a reference the trajectory does not pass, a node outside it, or a node  */
+/* the covariance rejects.                                                                         */
+int orc_noise_table_bessel2d_time(int kind, const double pot[7], double sigma, int n, double t_lo, double t_hi,
+                                  double phi_start, double pi_start, double phi_ref, double *Xpp_out,
+                                  double *Xpq_out, double *Xqq_out, double *phi_out)
+{
+    if (n < 1 || !(sigma > 0.0) || sigma > 2.0) return -1;
+    if (n > 1 && !(t_hi > t_lo)) return -1;
+    if (!(phi_start > phi_ref)) return -1;
+    const double h = (n > 1) ? (t_hi - t_lo) / (double)(n - 1) : 0.0;
+    double *bN, *bphi, *bpi, N_ref;
+    const size_t nb = orc_background(kind, pot, phi_start, pi_start, -INFINITY, INFINITY, phi_ref,
+                                     (n > 1 ? t_hi : t_lo) + 2e-4, &N_ref, &bN, &bphi, &bpi);
+    if (nb == 0) return -1;
+    int bad = isnan(N_ref);
+    for (int j = 0; j < n && !bad; ++j) {
+        const double tau = t_lo + (double)j * h, Ns = N_ref + tau;
+        double phi_j, pi_j;
+        if (orc_time_node(bN, bphi, bpi, nb, tau, Ns, phi_ref, &phi_j, &pi_j) != 0) {
+            bad = 1;
+            break;
+        }
+        if (phi_out) phi_out[j] = phi_j;
+        bad = orc_noise_table_bessel2d(kind, pot, sigma, 1, phi_j, phi_j, &Xpp_out[j], &Xpq_out[j], &Xqq_out[j]) != 0;
     }
     free(bN); free(bphi); free(bpi);
     return bad ? -1 : 0;

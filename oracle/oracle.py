@@ -110,7 +110,7 @@ def lib():
                                     ctypes.c_uint64, dp]
         L.orc_normals2d.restype = None
         L.orc_run2d.argtypes = [ctypes.c_int, dp, ctypes.c_int, ctypes.c_double, ctypes.c_double, dp, dp, dp,
-                                ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_int, ctypes.c_double,
+                                ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_int, ctypes.c_double,
                                 ctypes.c_double, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_uint64,
                                 ctypes.c_int64, dp, dp, u32p, ctypes.c_int]
         L.orc_run2d.restype = ctypes.c_int
@@ -126,6 +126,10 @@ def lib():
                                                    ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                                    ctypes.c_double, dp, dp, dp, dp, ctypes.c_int]
         L.orc_noise_table_matched_time.restype = ctypes.c_int
+        L.orc_noise_table_bessel2d_time.argtypes = [ctypes.c_int, dp, ctypes.c_double, ctypes.c_int, ctypes.c_double,
+                                                    ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                                    ctypes.c_double, dp, dp, dp, dp]
+        L.orc_noise_table_bessel2d_time.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -374,6 +378,7 @@ class Problem2D:
     phi_hi: float = 0.0
     bias_kind: int = BIAS_NONE
     A_bias: float = 0.0
+    tab_axis: int = 0                # 1: the nodes are in the run's time (phi_lo, phi_hi hold N)
 
     def pot(self) -> np.ndarray:
         return _pot_array(self.V0, self.phi_T, self.A_plus, self.A_minus)
@@ -386,6 +391,19 @@ def noise_table_bessel2d(kind, V0, phi_T, A_plus, A_minus, sigma, n, phi_lo, phi
     rc = lib().orc_noise_table_bessel2d(kind, _dp(p), sigma, n, phi_lo, phi_hi, *[_dp(x) for x in X])
     if rc != 0:
         raise ValueError("invalid noise-table parameters")
+    return tuple(X)
+
+
+def noise_table_bessel2d_time(kind, V0, phi_T, A_plus, A_minus, sigma, n, t_lo, t_hi, phi_start, pi_start, phi_ref):
+    """(Xi_pp, Xi_pq, Xi_qq, phi at the nodes) of the 2D table on nodes in time after the classical
+    trajectory from (phi_start, pi_start) passes phi_ref."""
+    p = _pot_array(V0, phi_T, A_plus, A_minus)
+    X = [np.empty(n, dtype=np.float64) for _ in range(4)]
+    rc = lib().orc_noise_table_bessel2d_time(kind, _dp(p), sigma, n, t_lo, t_hi, phi_start, pi_start, phi_ref,
+                                             *[_dp(x) for x in X])
+    if rc != 0:
+        raise ValueError("invalid 2D time-node table (phi_ref not passed, a node outside the trajectory, or a "
+                         "node the covariance rejects)")
     return tuple(X)
 
 
@@ -417,7 +435,7 @@ def run2d(prob: Problem2D, dN: float, seed: int, n_traj: int, traj_offset: int =
     steps = np.empty(n_traj, dtype=np.uint32)
     pot = prob.pot()
     rc = lib().orc_run2d(prob.kind, _dp(pot), len(X[0]), prob.phi_lo, prob.phi_hi, *[_dp(x) for x in X],
-                         prob.phi_in, prob.pi_in, prob.phi_end, prob.bias_kind, prob.A_bias, dN, seed, instance,
+                         int(prob.tab_axis), prob.phi_in, prob.pi_in, prob.phi_end, prob.bias_kind, prob.A_bias, dN, seed, instance,
                          traj_offset, n_traj, max_steps, _dp(N), _dp(lnw), _u32p(steps), n_threads)
     if rc != 0:
         raise ValueError("invalid oracle problem")

@@ -3,6 +3,7 @@
 // the device kernel that evaluates the Bessel-ansatz noise table.
 #include "fpt.h"
 #include "internal.hpp"
+#include "noise_node.hpp"
 #include "potential.hpp"
 
 #include <hip/hip_runtime.h>
@@ -140,55 +141,12 @@ extern "C" int fpt_noise_table_bessel(const fpt_potential *pot, double sigma, in
 // 2D noise table kernel: eq. (covariance_matrix_direct) from the full
 // Bunch-Davies mode of eq. (delta_phi_bessel) at -k eta = sigma
 // ---------------------------------------------------------------------------
-struct cplx {
-    double re, im;
-};
-__device__ __forceinline__ cplx cmul(cplx a, cplx b) { return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re}; }
-__device__ __forceinline__ cplx cscale(cplx a, double s) { return {a.re * s, a.im * s}; }
-__device__ __forceinline__ cplx cadd(cplx a, cplx b) { return {a.re + b.re, a.im + b.im}; }
-
 __global__ void table_bessel2d_kernel(PotParams pp, double sigma, int n, double phi_lo, double h, double *Xpp,
                                       double *Xpq, double *Xqq, int *bad)
 {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= n) return;
-    const double phi = grid_node(phi_lo, j, h);
-    double V, dV, d2V;
-    pot_eval(pp, phi, false, V, dV, d2V);
-    const double r1 = dV / V, r2 = d2V / V;
-    const double nu2 = 2.25 - 3.0 * (r2 - r1 * r1);
-    const double nu = nu2 > 0.0 ? sqrt(nu2) : 0.0;
-    double sn, cs;
-    sincospi(nu, &sn, &cs);
-    if (!(V > 0.0) || !(nu2 > 0.0) || fabs(sn) < 1e-3) {
-        atomicOr(bad, 1);
-        Xpp[j] = Xpq[j] = Xqq[j] = 0.0;
-        return;
-    }
-    // A_k, B_k of eq. (A_k_and_B_k): sqrt(pi)/2 exp(i (nu + 1/2) pi/2), sqrt(pi)/2 exp(i (nu + 3/2) pi/2)
-    const double hs = 0.5 * sqrt(M_PI);
-    double sa, ca, sb, cb;
-    sincospi(0.5 * (nu + 0.5), &sa, &ca);
-    sincospi(0.5 * (nu + 1.5), &sb, &cb);
-    const cplx Ak = {hs * ca, hs * sa}, Bk = {hs * cb, hs * sb};
-    // y^(3/2) (A J_nu + B Y_nu) = alpha_+ y^(3/2) J_nu + alpha_- y^(3/2) J_-nu
-    const cplx alpha[2] = {cadd(Ak, cscale(Bk, cs / sn)), cscale(Bk, -1.0 / sn)};
-    const double mus[2] = {nu, -nu};
-    cplx F = {0.0, 0.0}, G = {0.0, 0.0};
-    for (int k = 0; k < 2; ++k) {
-        const double mu = mus[k];
-        for (int m = 0; m < 30; ++m) {
-            const double p = 2.0 * m + mu + 1.5;
-            const double term = ((m & 1) ? -1.0 : 1.0) * pow(sigma, p) /
-                                (tgamma((double)m + 1.0) * tgamma((double)m + mu + 1.0) * pow(2.0, 2.0 * m + mu));
-            F = cadd(F, cscale(alpha[k], term));
-            G = cadd(G, cscale(alpha[k], -p * term));
-        }
-    }
-    const double c = (V / 3.0) / (2.0 * M_PI * M_PI);
-    Xpp[j] = c * (F.re * F.re + F.im * F.im);
-    Xpq[j] = c * (F.re * G.re + F.im * G.im);      // Re(F conj(G))
-    Xqq[j] = c * (G.re * G.re + G.im * G.im);
+    if (!bessel2d_node(pp, sigma, grid_node(phi_lo, j, h), Xpp[j], Xpq[j], Xqq[j])) atomicOr(bad, 1);
 }
 
 extern "C" int fpt_noise_table_bessel2d(const fpt_potential *pot, double sigma, int32_t n, double phi_lo,
@@ -301,6 +259,47 @@ extern "C" int fpt_noise_table_matched_time(const fpt_potential *pot, double sig
     if (status & 1) return fail(FPT_EINVAL, "V <= 0 or nu^2 <= 0 at a table node");
     if (status & 2) return fail(FPT_EINVAL, "a node is reached before its mode can start at k = 100 aH: start earlier");
     if (status & 4) return fail(FPT_EINVAL, "non-finite or zero Bessel coefficient at a node");
+    return FPT_OK;
+}
+
+extern "C" int fpt_noise_table_bessel2d_time(const fpt_potential *pot, double sigma, int32_t n, double t_lo,
+                                             double t_hi, double phi_start, double pi_start, double phi_ref,
+                                             double *Xpp_out, double *Xpq_out, double *Xqq_out, double *phi_out)
+{
+    int rc = check_potential(pot);
+    if (rc) return rc;
+    if (n < 1 || n > FPT_MAX_TABLE) return fail(FPT_EINVAL, "table size %d out of 1..%d", n, FPT_MAX_TABLE);
+    if (!(sigma > 0.0) || !(sigma <= 2.0)) return fail(FPT_EINVAL, "sigma must lie in (0, 2]");
+    if (!is_finite(t_lo) || !is_finite(t_hi) || (n > 1 && !(t_hi > t_lo)))
+        return fail(FPT_EINVAL, "need t_hi > t_lo");
+    if (!is_finite(phi_start) || !is_finite(pi_start) || !is_finite(phi_ref))
+        return fail(FPT_EINVAL, "start and phi_ref must be finite");
+    if (!(phi_start > phi_ref)) return fail(FPT_EINVAL, "need phi_start > phi_ref");
+    if (!(pot_V(*pot, phi_start) > 0.0)) return fail(FPT_EINVAL, "V(phi_start) must be > 0");
+    if (!(0.5 * pi_start * pi_start < 1.0)) return fail(FPT_EINVAL, "the start needs eps1 = pi^2/2 < 1");
+    if (!Xpp_out || !Xpq_out || !Xqq_out) return fail(FPT_EINVAL, "output arrays are NULL");
+    const double h = (n > 1) ? (t_hi - t_lo) / (double)(n - 1) : 0.0;
+    const double N_after = (n > 1 ? t_hi : t_lo) + 2e-4;   // one sample beyond the last node
+    const size_t out_off = (fpt::matched_time_scratch_bytes() + 255) & ~(size_t)255;
+    char *d = nullptr;
+    HIP_TRY(hipMalloc(&d, out_off + 4 * sizeof(double) * n + sizeof(int)));
+    double *d_X = reinterpret_cast<double *>(d + out_off);
+    int *d_status = reinterpret_cast<int *>(d_X + 4 * n);
+    hipError_t e = hipMemset(d_status, 0, sizeof(int));
+    if (e == hipSuccess)
+        e = fpt::bessel2d_time_launch(pot_params(*pot), sigma, n, t_lo, h, phi_start, pi_start, phi_ref, N_after, d,
+                                      d_X, d_X + n, d_X + 2 * n, d_X + 3 * n, d_status, nullptr);
+    int status = 0;
+    if (e == hipSuccess) e = hipMemcpy(Xpp_out, d_X, sizeof(double) * n, hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = hipMemcpy(Xpq_out, d_X + n, sizeof(double) * n, hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = hipMemcpy(Xqq_out, d_X + 2 * n, sizeof(double) * n, hipMemcpyDeviceToHost);
+    if (e == hipSuccess && phi_out) e = hipMemcpy(phi_out, d_X + 3 * n, sizeof(double) * n, hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = hipMemcpy(&status, d_status, sizeof(int), hipMemcpyDeviceToHost);
+    (void)hipFree(d);
+    if (e != hipSuccess) return hip_fail(e, "time-node 2D noise table kernels");
+    if (status & 16)
+        return fail(FPT_EINVAL, "the trajectory does not pass phi_ref, or a node lies outside the followed trajectory");
+    if (status & 1) return fail(FPT_EINVAL, "V <= 0, nu^2 <= 0 or nu near an integer at a table node");
     return FPT_OK;
 }
 
@@ -516,7 +515,6 @@ extern "C" int fpt_create(const fpt_potential *pot, const fpt_noise_table *table
     if (table->axis != FPT_AXIS_PHI && table->axis != FPT_AXIS_TIME)
         return fail(FPT_EINVAL, "table axis must be FPT_AXIS_PHI or FPT_AXIS_TIME");
     const bool time_axis = table->axis == FPT_AXIS_TIME && nt > 1;
-    if (time_axis && dim == 2) return fail(FPT_EUNSUPPORTED, "a time-indexed table takes 1D noise only");
     if (time_axis && bias && bias->kind == FPT_BIAS_MLP)
         return fail(FPT_EUNSUPPORTED, "a time-indexed table takes no learned bias");
     if (dim == 1) {
@@ -728,7 +726,7 @@ extern "C" int fpt_run(fpt_ctx *c, uint64_t n_traj, double dN, uint64_t seed, ui
     const int block = c->opt.block_size ? c->opt.block_size : 1024;
     int grid = 0;
     const bool two_d = c->inst.noise_dim == 2;
-    const void *fn = two_d ? em2d_kernel_ptr(c->inst.bias_kind, c->inst.all_S_pos != 0)
+    const void *fn = two_d ? em2d_kernel_ptr(c->inst.bias_kind, c->inst.all_S_pos != 0, tab_mode(c->inst) == 2)
                            : em_kernel_ptr(c->precision, c->inst.bias_kind, tab_mode(c->inst), c->inst.all_S_pos != 0,
                                            c->inst.pot_kind);
     const size_t lds = two_d ? em2d_lds_bytes(c->inst.hist.n_bins, c->inst.n_tab)

@@ -920,7 +920,7 @@ __device__ __forceinline__ Node2d lerp_node2d(const double2 *l_tab, int j, doubl
     return n;
 }
 
-template <int BIAS, bool ALLPOS>
+template <int BIAS, bool ALLPOS, bool TIME>
 __device__ __forceinline__ void lanes_fp64_2d(const Inst &I, const RunArgs &R, const double2 *l_tab,
                                               const RetireTo &rt, unsigned long long *cursor, uint64_t n_traj,
                                               uint64_t traj_offset)
@@ -960,7 +960,8 @@ __device__ __forceinline__ void lanes_fp64_2d(const Inst &I, const RunArgs &R, c
             double r = __builtin_amdgcn_rcp(d);
             r = fma(r, fma(-d, r, 1.0), r);
             r = fma(r, fma(-d, r, 1.0), r);
-            const double x = (phi - I.phi_lo) * I.inv_h;
+            // table coordinate: phi, or the run's time n dN for a time-indexed table
+            const double x = ((TIME ? (double)n * dN : phi) - I.phi_lo) * I.inv_h;
             const double jf = fmin(fmax(floor(x), 0.0), jmax);
             const double f = fmin(fmax(x - jf, 0.0), 1.0);
             const Node2d S = lerp_node2d(l_tab, (int)jf, f);
@@ -1099,7 +1100,7 @@ __global__ void __launch_bounds__(1024) FPT_EM_OCCUPANCY em_kernel(EmParams p)
 }
 
 // FP64 state with 2D noise: a persistent grid over one instance.
-template <int BIAS, bool ALLPOS>
+template <int BIAS, bool ALLPOS, bool TIME>
 __global__ void __launch_bounds__(1024) FPT_EM_OCCUPANCY em2d_kernel(EmParams p)
 {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -1109,7 +1110,7 @@ __global__ void __launch_bounds__(1024) FPT_EM_OCCUPANCY em2d_kernel(EmParams p)
     stage_table64_2d(p.inst, l_tab);
     __syncthreads();
     const RetireTo rt = retire_to(p, acc);
-    lanes_fp64_2d<BIAS, ALLPOS>(p.inst, p.run, l_tab, rt, p.cursor, p.n_traj, p.traj_offset);
+    lanes_fp64_2d<BIAS, ALLPOS, TIME>(p.inst, p.run, l_tab, rt, p.cursor, p.n_traj, p.traj_offset);
     __syncthreads();
     flush_lds_acc(acc, p.inst.acc);
 }
@@ -1273,20 +1274,24 @@ size_t em2d_lds_bytes(int n_bins, int n_tab)
     return align16(acc_bytes(n_bins)) + (size_t)(n_tab > 1 ? n_tab : 2) * 48 + kBmBytes;
 }
 
-const void *em2d_kernel_ptr(int bias_kind, bool all_pos)
+const void *em2d_kernel_ptr(int bias_kind, bool all_pos, bool time_axis)
 {
-    static const void *const t[2][2] = {
-        {reinterpret_cast<const void *>(&em2d_kernel<kBiasNone, false>),
-         reinterpret_cast<const void *>(&em2d_kernel<kBiasNone, true>)},
-        {reinterpret_cast<const void *>(&em2d_kernel<kBiasConst, false>),
-         reinterpret_cast<const void *>(&em2d_kernel<kBiasConst, true>)}};
-    return t[bias_kind == kBiasNone ? 0 : 1][all_pos ? 1 : 0];
+    static const void *const t[2][2][2] = {
+        {{reinterpret_cast<const void *>(&em2d_kernel<kBiasNone, false, false>),
+          reinterpret_cast<const void *>(&em2d_kernel<kBiasNone, false, true>)},
+         {reinterpret_cast<const void *>(&em2d_kernel<kBiasNone, true, false>),
+          reinterpret_cast<const void *>(&em2d_kernel<kBiasNone, true, true>)}},
+        {{reinterpret_cast<const void *>(&em2d_kernel<kBiasConst, false, false>),
+          reinterpret_cast<const void *>(&em2d_kernel<kBiasConst, false, true>)},
+         {reinterpret_cast<const void *>(&em2d_kernel<kBiasConst, true, false>),
+          reinterpret_cast<const void *>(&em2d_kernel<kBiasConst, true, true>)}}};
+    return t[bias_kind == kBiasNone ? 0 : 1][all_pos ? 1 : 0][time_axis ? 1 : 0];
 }
 
 hipError_t em2d_launch(const EmParams &p, int grid, int block, hipStream_t stream)
 {
     const size_t lds = em2d_lds_bytes(p.inst.hist.n_bins, p.inst.n_tab);
-    const void *fn = em2d_kernel_ptr(p.inst.bias_kind, p.inst.all_S_pos != 0);
+    const void *fn = em2d_kernel_ptr(p.inst.bias_kind, p.inst.all_S_pos != 0, tab_mode(p.inst) == 2);
     EmParams pp = p;
     void *args[] = {&pp};
     return hipLaunchKernel(fn, dim3(grid), dim3(block), args, lds, stream);

@@ -8,6 +8,7 @@
 // of the first sample at or below it.  match_node_kernel is one thread per node: each
 // mode is an independent ODE solve of some 10^4 RK4 steps, all in FP64.
 #include "internal.hpp"
+#include "noise_node.hpp"
 
 #include <hip/hip_runtime.h>
 
@@ -328,22 +329,16 @@ __global__ void match_background_time_kernel(Pot p, double phi_start, double pi_
     *N_ref_out = N_ref;
 }
 
-// Node j at N_sigma = N_ref + t_lo + j h: phi_j by the cubic Hermite interpolant of the samples,
-// pi_j linearly, then the Bunch-Davies node and the factor there.  Status 16: the trajectory does
-// not pass phi_ref, or the node lies outside the followed trajectory.
-__global__ void match_node_time_kernel(Pot p, double sigma, int n, double t_lo, double h, double phi_ref,
-                                       const double *bN, const double *bphi, const double *bpi, const int *nb_ptr,
-                                       const double *N_ref_ptr, double *S, double *tan_out, double *fac_out, double *phi_out, int *status)
+// The trajectory at N_sigma = N_ref + tau (tau = t_lo + j h, formed without a fused multiply-add):
+// phi by the cubic Hermite interpolant of the samples, pi linearly; tau = 0 is the reference point,
+// phi_ref exactly (on a kink at phi_ref, the branch before it).  False where the trajectory does
+// not pass phi_ref (N_ref NaN) or N_sigma lies outside the followed samples.
+__device__ inline bool time_node(double t_lo, int j, double h, double phi_ref, const double *bN, const double *bphi,
+                                 const double *bpi, int nb, double N_ref, double &Ns, double &phi_j, double &pi_j)
 {
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= n) return;
-    const int nb = *nb_ptr;
-    const double tau = grid_node(t_lo, j, h), Ns = *N_ref_ptr + tau;
-    S[j] = tan_out[j] = fac_out[j] = phi_out[j] = NAN;
-    if (!(Ns >= bN[0]) || !(Ns <= bN[nb - 1]) || nb < 2) {
-        atomicOr(status, 16);
-        return;
-    }
+    const double tau = grid_node(t_lo, j, h);
+    Ns = N_ref + tau;
+    if (!(Ns >= bN[0]) || !(Ns <= bN[nb - 1]) || nb < 2) return false;
     // first sample at or after Ns (from 1, at most nb - 1)
     int lo = 0, hi = nb - 1;
     while (hi - lo > 1) {
@@ -354,11 +349,30 @@ __global__ void match_node_time_kernel(Pot p, double sigma, int n, double t_lo, 
     const int i = hi;
     const double dn = bN[i] - bN[i - 1], t = (Ns - bN[i - 1]) / dn;
     const double t2 = t * t, t3 = t2 * t;
-    // tau = 0 is the reference point: phi_ref exactly (on a kink at phi_ref, the branch before it)
-    const double phi_j = tau == 0.0 ? phi_ref
-                                    : (2.0 * t3 - 3.0 * t2 + 1.0) * bphi[i - 1] + (t3 - 2.0 * t2 + t) * bpi[i - 1] * dn +
-                                          (3.0 * t2 - 2.0 * t3) * bphi[i] + (t3 - t2) * bpi[i] * dn;
-    const double pi_j = bpi[i - 1] + t * (bpi[i] - bpi[i - 1]);
+    phi_j = tau == 0.0 ? phi_ref
+                       : (2.0 * t3 - 3.0 * t2 + 1.0) * bphi[i - 1] + (t3 - 2.0 * t2 + t) * bpi[i - 1] * dn +
+                             (3.0 * t2 - 2.0 * t3) * bphi[i] + (t3 - t2) * bpi[i] * dn;
+    pi_j = bpi[i - 1] + t * (bpi[i] - bpi[i - 1]);
+    return true;
+}
+
+// Node j at N_sigma = N_ref + t_lo + j h: the trajectory's phi_j and pi_j there (time_node), the
+// Bunch-Davies node and the factor.  Status 16: the trajectory does not pass phi_ref, or the node
+// lies outside the followed trajectory.
+__global__ void match_node_time_kernel(Pot p, double sigma, int n, double t_lo, double h, double phi_ref,
+                                       const double *bN, const double *bphi, const double *bpi, const int *nb_ptr,
+                                       const double *N_ref_ptr, double *S, double *tan_out, double *fac_out,
+                                       double *phi_out, int *status)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    const int nb = *nb_ptr;
+    S[j] = tan_out[j] = fac_out[j] = phi_out[j] = NAN;
+    double Ns, phi_j, pi_j;
+    if (!time_node(t_lo, j, h, phi_ref, bN, bphi, bpi, nb, *N_ref_ptr, Ns, phi_j, pi_j)) {
+        atomicOr(status, 16);
+        return;
+    }
     phi_out[j] = phi_j;
     double S_bd, nu, V;
     if (!bd_node(p, sigma, phi_j, S_bd, nu, V)) {
@@ -369,6 +383,25 @@ __global__ void match_node_time_kernel(Pot p, double sigma, int n, double t_lo, 
     const double fac = matched_factor(p, sigma, phi_j, pi_j, Ns, V, nu, bN, bphi, bpi, nb, status);
     fac_out[j] = fac;
     S[j] = S_bd * sqrt(fac);
+}
+
+// 2D node j in time: the covariance of noise_node.hpp at the trajectory's phi there.  Status 16 as
+// above, 1 where the covariance rejects the node.
+__global__ void bessel2d_time_node_kernel(Pot p, double sigma, int n, double t_lo, double h, double phi_ref,
+                                          const double *bN, const double *bphi, const double *bpi,
+                                          const int *nb_ptr, const double *N_ref_ptr, double *Xpp, double *Xpq,
+                                          double *Xqq, double *phi_out, int *status)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    Xpp[j] = Xpq[j] = Xqq[j] = phi_out[j] = NAN;
+    double Ns, phi_j, pi_j;
+    if (!time_node(t_lo, j, h, phi_ref, bN, bphi, bpi, *nb_ptr, *N_ref_ptr, Ns, phi_j, pi_j)) {
+        atomicOr(status, 16);
+        return;
+    }
+    phi_out[j] = phi_j;
+    if (!bessel2d_node(p, sigma, phi_j, Xpp[j], Xpq[j], Xqq[j])) atomicOr(status, 1);
 }
 
 }  // namespace
@@ -410,6 +443,23 @@ hipError_t matched_time_launch(const PotParams &p, double sigma, int n, double t
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(match_node_time_kernel, dim3((n + 63) / 64), dim3(64), 0, stream, p, sigma, n, t_lo, h,
                        phi_ref, bN, bphi, bpi, nb, N_ref, d_S, d_tan, d_fac, d_phi, d_status);
+    return hipGetLastError();
+}
+
+hipError_t bessel2d_time_launch(const PotParams &p, double sigma, int n, double t_lo, double h, double phi_start,
+                                double pi_start, double phi_ref, double N_after, void *scratch, double *d_Xpp,
+                                double *d_Xpq, double *d_Xqq, double *d_phi, int *d_status, hipStream_t stream)
+{
+    double *bN = static_cast<double *>(scratch);
+    double *bphi = bN + kMatchCap, *bpi = bphi + kMatchCap;
+    int *nb = reinterpret_cast<int *>(bpi + kMatchCap);
+    double *N_ref = reinterpret_cast<double *>(bpi + kMatchCap) + 1;
+    hipLaunchKernelGGL(match_background_time_kernel, dim3(1), dim3(64), 0, stream, p, phi_start, pi_start, phi_ref,
+                       N_after, bN, bphi, bpi, (int)kMatchCap, nb, N_ref);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(bessel2d_time_node_kernel, dim3((n + 63) / 64), dim3(64), 0, stream, p, sigma, n, t_lo, h,
+                       phi_ref, bN, bphi, bpi, nb, N_ref, d_Xpp, d_Xpq, d_Xqq, d_phi, d_status);
     return hipGetLastError();
 }
 

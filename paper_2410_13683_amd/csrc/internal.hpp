@@ -132,7 +132,7 @@ const void *em_kernel_ptr(int precision, int bias_kind, int tab_mode, bool all_p
 hipError_t em_launch(const EmParams &p, int precision, int grid, int block, hipStream_t stream);
 const void *replay_kernel_ptr(int precision, bool all_pos);
 size_t em2d_lds_bytes(int n_bins, int n_tab);
-const void *em2d_kernel_ptr(int bias_kind, bool all_pos);
+const void *em2d_kernel_ptr(int bias_kind, bool all_pos, bool time_axis);
 hipError_t em2d_launch(const EmParams &p, int grid, int block, hipStream_t stream);
 hipError_t replay_launch(const ReplayParams &p, int precision, int grid, int block, hipStream_t stream);
 const void *batch_kernel_ptr(int precision, int bias_kind, bool all_pos);
@@ -178,6 +178,10 @@ size_t matched_time_scratch_bytes();
 hipError_t matched_time_launch(const PotParams &pot, double sigma, int n, double t_lo, double h, double phi_start,
                                double pi_start, double phi_ref, double N_after, void *scratch, double *d_S,
                                double *d_tan, double *d_fac, double *d_phi, int *d_status, hipStream_t stream);
+// The 2D Bunch-Davies covariance on the same time nodes (scratch as above; d_status 1 or 16).
+hipError_t bessel2d_time_launch(const PotParams &pot, double sigma, int n, double t_lo, double h, double phi_start,
+                                double pi_start, double phi_ref, double N_after, void *scratch, double *d_Xpp,
+                                double *d_Xpq, double *d_Xqq, double *d_phi, int *d_status, hipStream_t stream);
 
 // Sets the message fpt_last_error returns and returns code (defined in fpt_api.hip).
 int report_error(int code, const char *msg);

@@ -133,6 +133,9 @@ def load():
     L.fpt_noise_table_matched_time.argtypes = [P(fpt_potential), ctypes.c_double, ctypes.c_int32, ctypes.c_double,
                                                ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                                _dp, _dp, _dp, _dp]
+    L.fpt_noise_table_bessel2d_time.argtypes = [P(fpt_potential), ctypes.c_double, ctypes.c_int32, ctypes.c_double,
+                                                ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                                _dp, _dp, _dp, _dp]
     L.fpt_jackknife.argtypes = [ctypes.c_int32, ctypes.c_int32, _u64p, _dp, _dp, _dp]
     L.fpt_lognormal_bins.argtypes = [ctypes.c_int32, ctypes.c_uint64, _u64p, _dp, _dp, _dp, _dp, _dp]
     L.fpt_merge_bins.argtypes = [ctypes.c_int32, ctypes.c_int32, _dp, _dp, _dp, _dp]
@@ -155,7 +158,7 @@ def load():
                                ctypes.c_double, ctypes.c_void_p]
     for name in ("fpt_create", "fpt_run", "fpt_histogram", "fpt_reset", "fpt_last_kernel_ms",
                  "fpt_noise_table_bessel", "fpt_noise_table_bessel2d", "fpt_noise_table_matched",
-                 "fpt_noise_table_matched_time", "fpt_jackknife", "fpt_lognormal_bins",
+                 "fpt_noise_table_matched_time", "fpt_noise_table_bessel2d_time", "fpt_jackknife", "fpt_lognormal_bins",
                  "fpt_merge_bins", "fpt_batch_create", "fpt_batch_run", "fpt_batch_autotune",
                  "fpt_batch_config", "fpt_batch_last_ms", "fpt_mlp_set", "fpt_mlp_get", "fpt_mlp_table",
                  "fpt_mlp_grad", "fpt_mlp_adam"):
@@ -233,6 +236,17 @@ def fpt_noise_table_matched_time(pot: fpt_potential, sigma: float, n: int, t_lo:
     return tuple(out)
 
 
+def fpt_noise_table_bessel2d_time(pot: fpt_potential, sigma: float, n: int, t_lo: float, t_hi: float,
+                                  phi_start: float, pi_start: float, phi_ref: float):
+    """(Xi_pp, Xi_pq, Xi_qq, phi_j) of the 2D covariance on time nodes t_lo + j h after the classical
+    trajectory passes phi_ref; device kernels."""
+    out = [np.empty(n, dtype=np.float64) for _ in range(4)]
+    _check(load().fpt_noise_table_bessel2d_time(ctypes.byref(pot), sigma, n, t_lo, t_hi, phi_start, pi_start,
+                                                phi_ref, *[a.ctypes.data_as(_dp) for a in out]),
+           "fpt_noise_table_bessel2d_time")
+    return tuple(out)
+
+
 def _f64(a):
     return np.ascontiguousarray(a, dtype=np.float64)
 
@@ -285,6 +299,7 @@ class Context:
             self._X = [np.ascontiguousarray(x, dtype=np.float64) for x in Xi]
             n_tab = len(self._X[0])
             table = fpt_noise_table(n_tab, phi_lo, phi_hi, None, None, 2, *[x.ctypes.data_as(_dp) for x in self._X])
+            table.axis = axis
         else:
             self._S = np.ascontiguousarray(S, dtype=np.float64)
             self._t = np.ascontiguousarray(tan_theta, dtype=np.float64)

@@ -24,6 +24,13 @@ def table_of(w: Workload, pot=None):
     if w.noise == "bessel2d":
         X = fpt.fpt_noise_table_bessel2d(pot or potential_of(w), w.sigma, w.table_n, w.table_lo, w.table_hi)
         return X, None, w.table_lo, w.table_hi
+    if w.noise == "bessel2d_time":
+        X = fpt.fpt_noise_table_bessel2d_time(pot or potential_of(w), w.sigma, w.table_n, w.table_lo, w.table_hi,
+                                              *w.match_start, w.phi_in)[:3]
+        if w.noise_cut_end:
+            for x in X:
+                x[-1] = 0.0
+        return X, None, w.table_lo, w.table_hi
     if w.noise == "const":
         return np.array([w.noise_S]), np.array([w.noise_tan]), 0.0, 0.0
     if w.noise == "bessel":
@@ -49,7 +56,7 @@ def context_for(w: Workload, **overrides) -> fpt.Context:
     S, t, lo, hi = table_of(w, pot)
     kw = dict(bias_kind=w.bias_kind, A=w.A_bias, precision=w.precision, bins_kind=w.bins_kind, n_bins=w.n_bins,
               lo=w.lo, hi=w.hi, N_ref=w.N_ref, max_steps=w.max_steps, instance=w.extra.get("instance", 0),
-              axis=fpt.FPT_AXIS_TIME if w.noise == "matched_time" else fpt.FPT_AXIS_PHI)
+              axis=fpt.FPT_AXIS_TIME if w.noise in ("matched_time", "bessel2d_time") else fpt.FPT_AXIS_PHI)
     if w.bias_kind == 2:
         kw.update(mlp_params=w.mlp_params, norm=w.mlp_norm, mlp_every=0, grid_n=w.grid_n, grid_range=w.grid_range)
     if t is None:

@@ -74,6 +74,7 @@ class Workload:
                                     # "bessel": eq. (covariance_constant_nu) table on the grid below;
                                     # "xi_const": 2D noise with covariance noise_Xi (one node);
                                     # "bessel2d": 2D noise of eq. (covariance_matrix_direct) on the grid;
+                                    # "bessel2d_time": the same on nodes in time (as "matched_time");
                                     # "matched": eq. (covariance_constant_nu_bessel_matched) on the grid,
                                     # B_k from the classical trajectory started at match_start;
                                     # "matched_time": the same noise on nodes in time, table_lo and
@@ -357,6 +358,18 @@ def srusr_2d(n_traj: int = 1_000_000, seed: int = 6, sigma: float = 0.1, A_bias:
         name=f"srusr_2d_sigma{sigma:g}", noise="bessel2d", sigma=sigma, table_n=TABLE2D_N,
         table_lo=-TABLE2D_J_T * TABLE2D_H, table_hi=(TABLE2D_N - 1 - TABLE2D_J_T) * TABLE2D_H,
         bias_kind=BIAS_CONST if A_bias else BIAS_NONE, A_bias=A_bias)
+
+
+def srusr_2d_time(n_traj: int = 1_000_000, seed: int = 6, sigma: float = 0.1, A_bias: float = 0.0,
+                  tau_hi: float = 12.5, table_n: int = TABLE2D_N) -> Workload:
+    """srusr_2d with the covariance indexed by time, the paper's scheme (Sec. 4.1): table_n nodes over
+    tau in [0, tau_hi] after the matched table's reference trajectory (from phi = 1) passes phi_in = 0,
+    the runs started on it (TIME_PI_IN), the last node zero, so the noise and the bias stop at tau_hi."""
+    t = srusr_time()
+    return srusr_2d(n_traj=n_traj, seed=seed, sigma=sigma, A_bias=A_bias).with_(
+        name=f"srusr_2d_time_sigma{sigma:g}_tau{tau_hi:g}", noise="bessel2d_time", pi_in=TIME_PI_IN,
+        N_ref=N_REF_TIME, match_start=t.match_start, table_n=table_n, table_lo=0.0, table_hi=tau_hi,
+        noise_cut_end=True)
 
 
 def exponential_2d(n_traj: int = 4000, seed: int = 9, S: float = 0.05, rho: float = 0.8, ratio: float = 1.0,

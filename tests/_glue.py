@@ -83,17 +83,25 @@ def assert_fp64_parity(gpu, ora, max_step_mismatch=0.002):
 def oracle_problem2d(w: Workload) -> orc.Problem2D:
     if w.noise == "xi_const":
         X, lo, hi = tuple(np.array([v]) for v in w.noise_Xi), 0.0, 0.0
+    elif w.noise == "bessel2d_time":
+        X = orc.noise_table_bessel2d_time(w.kind, w.V0, w.phi_T, w.A_plus, w.A_minus, w.sigma, w.table_n,
+                                          w.table_lo, w.table_hi, *w.match_start, w.phi_in)[:3]
+        if w.noise_cut_end:
+            for x in X:
+                x[-1] = 0.0
+        lo, hi = w.table_lo, w.table_hi
     else:
         X = orc.noise_table_bessel2d(w.kind, w.V0, w.phi_T, w.A_plus, w.A_minus, w.sigma, w.table_n,
                                      w.table_lo, w.table_hi)
         lo, hi = w.table_lo, w.table_hi
     return orc.Problem2D(kind=w.kind, V0=w.V0, phi_T=w.phi_T, A_plus=w.A_plus, A_minus=w.A_minus,
                          phi_in=w.phi_in, pi_in=w.pi_in, phi_end=w.phi_end, Xpp=X[0], Xpq=X[1], Xqq=X[2],
-                         phi_lo=lo, phi_hi=hi, bias_kind=w.bias_kind, A_bias=w.A_bias)
+                         phi_lo=lo, phi_hi=hi, bias_kind=w.bias_kind, A_bias=w.A_bias,
+                         tab_axis=1 if w.noise == "bessel2d_time" else 0)
 
 
 def oracle_run(w: Workload, n_traj=None, traj_offset=0, n_threads=0, **kw):
-    if w.noise in ("xi_const", "bessel2d"):
+    if w.noise in ("xi_const", "bessel2d", "bessel2d_time"):
         return orc.run2d(oracle_problem2d(w), w.dN, w.seed, w.n_traj if n_traj is None else n_traj,
                          traj_offset=traj_offset, instance=w.extra.get("instance", 0), max_steps=w.max_steps,
                          n_threads=n_threads)

@@ -207,12 +207,12 @@ def test_bump_variants_are_reported_unsupported(lib, case):
 
 @pytest.mark.parametrize("case", ["axis2", "axis_neg", "2d", "mlp", "reversed"])
 def test_time_axis_validation(lib, case):
-    """Tables with nodes in time: an unknown axis and a reversed range are invalid; 2D noise and the
-    learned bias do not take a time axis."""
+    """Tables with nodes in time: an unknown axis and a reversed range (1D, and 2D in case "2d") are
+    invalid; the learned bias does not take a time axis."""
     pot = _pot()
     S, t = np.array([1e-6, 2e-6, 0.0]), np.zeros(3)
     X = [np.full(3, 1e-12), np.full(3, 1e-13), np.full(3, 1e-12)]
-    lo, hi = (1.0, 0.0) if case == "reversed" else (0.0, 1.0)
+    lo, hi = (1.0, 0.0) if case in ("reversed", "2d") else (0.0, 1.0)
     if case == "2d":
         tab = fpt.fpt_noise_table(3, lo, hi, None, None, 2, *[x.ctypes.data_as(fpt._dp) for x in X])
     else:
@@ -226,20 +226,20 @@ def test_time_axis_validation(lib, case):
     h = ctypes.c_void_p()
     rc = lib.fpt_create(ctypes.byref(pot), ctypes.byref(tab), ctypes.byref(bias), ctypes.byref(opts),
                         ctypes.byref(h))
-    expect = fpt.FPT_EUNSUPPORTED if case in ("2d", "mlp") else fpt.FPT_EINVAL
+    expect = fpt.FPT_EUNSUPPORTED if case == "mlp" else fpt.FPT_EINVAL
     assert rc == expect and not h.value, (rc, lib.fpt_last_error())
 
 
+@pytest.mark.parametrize("entry", ["fpt_noise_table_matched_time", "fpt_noise_table_bessel2d_time"])
 @pytest.mark.parametrize("case", ["n0", "sigma", "t_range", "ref_above_start", "nan_ref", "eps1"])
-def test_time_node_matched_table_argument_errors(lib, case):
-    """Host-side checks of fpt_noise_table_matched_time (no device needed)."""
+def test_time_node_matched_table_argument_errors(lib, case, entry):
+    """Host-side checks of the time-node table generators (no device needed)."""
     pot = _pot()
     a = dict(sigma=1.0, n=4, t_lo=0.0, t_hi=1.0, phi_start=1.0, pi_start=-0.14, phi_ref=0.0)
     a.update({"n0": dict(n=0), "sigma": dict(sigma=2.5), "t_range": dict(t_hi=0.0),
               "ref_above_start": dict(phi_ref=1.0), "nan_ref": dict(phi_ref=float("nan")),
               "eps1": dict(pi_start=-1.5)}[case])
     outs = [np.empty(max(a["n"], 1)) for _ in range(4)]
-    rc = lib.fpt_noise_table_matched_time(ctypes.byref(pot), a["sigma"], a["n"], a["t_lo"], a["t_hi"],
-                                          a["phi_start"], a["pi_start"], a["phi_ref"],
-                                          *[o.ctypes.data_as(fpt._dp) for o in outs])
+    rc = getattr(lib, entry)(ctypes.byref(pot), a["sigma"], a["n"], a["t_lo"], a["t_hi"], a["phi_start"],
+                             a["pi_start"], a["phi_ref"], *[o.ctypes.data_as(fpt._dp) for o in outs])
     assert rc == fpt.FPT_EINVAL, (rc, lib.fpt_last_error())

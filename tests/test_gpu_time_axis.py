@@ -9,7 +9,9 @@ steps) against the CPU oracle, through the C ABI.  Cases:
   the noise on past the classical passage (tau_hi = 12.5) and switched off half-way (tau_hi = 6);
 - FP32 state on the time table: coupled with the oracle (same streams), and its law against
   the FP64 path at 2e5 trajectories;
-- a batch refuses a time-indexed context."""
+- a batch refuses a time-indexed context;
+- 2D noise on time nodes: the covariance table against the oracle, per-trajectory parity with and
+  without bias and with a switch-off, and the 1e6-trajectory workload on sampled trajectories."""
 import math
 import sys
 
@@ -182,3 +184,53 @@ def test_batch_refuses_time_table():
         assert e.value.status == fpt.FPT_EINVAL
     finally:
         ctx.destroy()
+
+
+# ---------------------------------------------------------------------------
+# 2D noise indexed by time
+# ---------------------------------------------------------------------------
+def test_2d_time_table_matches_oracle():
+    """The 2D covariance (sigma = 0.1) on 2048 time nodes over tau in [0, 12.5]: against the oracle, and
+    the node phi against the 1D time table's."""
+    w = W.srusr_2d_time()
+    say("2D time table")
+    pot = fpt.make_potential(w.kind, w.V0, w.phi_T, w.A_plus, w.A_minus, w.phi_in, w.pi_in, w.phi_end)
+    X = fpt.fpt_noise_table_bessel2d_time(pot, w.sigma, w.table_n, w.table_lo, w.table_hi, *w.match_start, w.phi_in)
+    Xo = orc.noise_table_bessel2d_time(w.kind, w.V0, w.phi_T, w.A_plus, w.A_minus, w.sigma, w.table_n, w.table_lo,
+                                       w.table_hi, *w.match_start, w.phi_in)
+    np.testing.assert_allclose(X[3], Xo[3], rtol=0, atol=1e-13)
+    for k in range(3):
+        np.testing.assert_allclose(X[k], Xo[k], rtol=1e-11, atol=1e-13 * np.abs(Xo[0]).max())
+    assert X[3][0] == w.phi_in and X[3][-1] < w.phi_end
+    g1 = fpt.fpt_noise_table_matched_time(pot, 1.0, w.table_n, w.table_lo, w.table_hi, *w.match_start, w.phi_in)
+    assert np.array_equal(g1[3], X[3])
+    with pytest.raises(fpt.FptError):
+        fpt.fpt_noise_table_bessel2d_time(pot, w.sigma, 3, -50.0, 1.0, *w.match_start, w.phi_in)
+
+
+@pytest.mark.parametrize("tau_hi,A_bias", [(12.5, 0.0), (12.5, 2.0), (6.0, 1.0)])
+def test_fp64_2d_trajectories_on_time_table(tau_hi, A_bias):
+    """1500 SR -> USR trajectories with the time-indexed 2D noise: per-trajectory parity; with
+    tau_hi = 6 the noise and the bias stop half-way."""
+    w = W.srusr_2d_time(n_traj=1500, tau_hi=tau_hi, A_bias=A_bias)
+    say(f"fp64 2D time table tau_hi={tau_hi} A={A_bias}")
+    gpu, _ = gpu_run(w)
+    ora = oracle_run(w)
+    assert_fp64_parity(gpu, ora)
+    if A_bias:
+        assert np.std(gpu[1]) > 0.05
+
+
+def test_2d_time_full_size_sampled():
+    """The 1e6-trajectory 2D time-indexed workload in the bench's launch configuration, checked on
+    trajectories sampled across the range."""
+    w = W.srusr_2d_time()
+    say(f"fp64 2D time full size n={w.n_traj}")
+    (N, lnw, st), hist = gpu_run(w)
+    idx = np.unique(np.concatenate([np.linspace(0, w.n_traj - 1, 60).astype(np.int64), [w.n_traj - 1]]))
+    for i in idx:
+        No, lo_, so = oracle_run(w, n_traj=1, traj_offset=int(i))
+        assert_fp64_parity((N[i:i + 1], lnw[i:i + 1], st[i:i + 1]), (No, lo_, so), max_step_mismatch=1.0)
+    assert hist["n_traj"] == w.n_traj and int(hist["count"].sum()) == w.n_traj
+    d = N - w.N_ref
+    say(f"  mean deltaN {d.mean():.4e} sd {d.std():.4e}")

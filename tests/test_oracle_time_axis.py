@@ -124,3 +124,50 @@ def test_bump_time_nodes_equal_phi_nodes(orc):
         if tau == 0.0:
             assert ph[0] == w.phi_in
     assert abs(ph[0] - W.BUMP_PHI_LO) < 1e-12
+
+
+def test_2d_time_nodes_equal_phi_nodes(orc):
+    """2D covariance on time nodes: the phi node at the trajectory's phi there, bit for bit (the
+    same covariance routine at the same phi)."""
+    w = W.srusr_2d_time()
+    taus = np.array([0.0, 0.9, 3.3, 11.0])
+    for tau in taus:
+        X = orc.noise_table_bessel2d_time(w.kind, w.V0, w.phi_T, w.A_plus, w.A_minus, w.sigma, 1, tau, tau,
+                                          *w.match_start, w.phi_in)
+        Xp = orc.noise_table_bessel2d(w.kind, w.V0, w.phi_T, w.A_plus, w.A_minus, w.sigma, 1, X[3][0], X[3][0])
+        assert [X[0][0], X[1][0], X[2][0]] == [Xp[0][0], Xp[1][0], Xp[2][0]]
+        if tau == 0.0:
+            assert X[3][0] == w.phi_in
+    # and its phi nodes are those of the 1D time table (one trajectory, one interpolation)
+    S, t, fac, ph = orc.noise_table_matched_time(w.kind, w.V0, w.phi_T, w.A_plus, w.A_minus, 1.0, 4, 0.5, 9.5,
+                                                 *w.match_start, w.phi_in)
+    X = orc.noise_table_bessel2d_time(w.kind, w.V0, w.phi_T, w.A_plus, w.A_minus, w.sigma, 4, 0.5, 9.5,
+                                      *w.match_start, w.phi_in)
+    assert np.array_equal(X[3], ph)
+    with pytest.raises(ValueError):
+        orc.noise_table_bessel2d_time(w.kind, w.V0, w.phi_T, w.A_plus, w.A_minus, w.sigma, 3, -50.0, 1.0,
+                                      *w.match_start, w.phi_in)
+
+
+@pytest.mark.parametrize("A", [0.0, 1.1])
+def test_2d_switch_off_log_weight_closed_form(orc, A):
+    """Exponential potential, constant diagonal 2D noise Xi = diag(a, c) (a > c: principal axis (1, 0)
+    at every node, the zero node included) up to tau_off, zero there: dA = A xi_1 sqrt(dN) + A^2 dN/2
+    on exactly the steps with n dN < tau_off, whatever the path; the noise moves pi, so a table read
+    at phi would switch off elsewhere."""
+    alpha, dN, n_nodes, tau_off = 0.5, 1e-3, 9, 0.3217
+    a, c = 0.04 ** 2, 0.01 ** 2
+    Xpp, Xpq, Xqq = np.full(n_nodes, a), np.zeros(n_nodes), np.full(n_nodes, c)
+    Xpp[-1] = Xqq[-1] = 0.0
+    p = orc.Problem2D(kind=orc.POT_EXPONENTIAL, V0=1e-10, phi_T=0.0, A_plus=alpha, A_minus=0.0, phi_in=1.0,
+                      pi_in=-alpha, phi_end=0.0, Xpp=Xpp, Xpq=Xpq, Xqq=Xqq, phi_lo=0.0, phi_hi=tau_off,
+                      bias_kind=orc.BIAS_CONST if A else orc.BIAS_NONE, A_bias=A, tab_axis=1)
+    N, lnw, steps = orc.run2d(p, dN, 29, 10)
+    for i in range(10):
+        n = int(steps[i] & orc.STEP_MASK)
+        assert n * dN > tau_off
+        z = orc.normals2d(29, 0, i, 0, n)          # (n, 2)
+        on = np.array([k * dN < tau_off for k in range(n)])
+        m = int(on.sum())
+        ref = -A * math.sqrt(dN) * z[on, 0].sum() - m * A * A * dN / 2.0
+        assert abs(lnw[i] - ref) < 1e-10 * max(1.0, abs(ref)), (i, lnw[i], ref)
