@@ -81,9 +81,9 @@ PEAK_HBM_GBS = 8000.0
 # process (FETCH_SIZE reads 0.5 GiB: x2.0; WRITE_SIZE reads 1 GiB: x1.0).  Valid only for the
 # kernel source it was measured on (hash of the kernel file and its header).
 MEASURED_TRAFFIC = {
-    "source_sha256": "748a325ef535b4d4ad257712b080f277f3e799a8cd0072cfd1ae1028440de45f",
+    "source_sha256": "dbcf6de0a27b20879e5fee77b7efc69f2c59f0b4a766a1f1fabb23766e123850",
     "workload": "srusr_is_fp32_A2", "n_traj": 100_000_000,
-    "fetch_bytes": 466.6875 * 1024 * 2.0, "write_bytes": 2083341.9375 * 1024 * 1.0,
+    "fetch_bytes": 465.6875 * 1024 * 2.0, "write_bytes": 2082664.125 * 1024 * 1.0,
 }
 
 
