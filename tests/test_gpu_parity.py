@@ -296,14 +296,16 @@ def test_maximum_table_and_bins(case):
         np.testing.assert_allclose(h["sum_lnw"], ho["sum_lnw"], rtol=1e-9, atol=1e-9)
 
 
-def test_full_size_default_fp32_sampled():
-    """The bench's default workload at its full size and launch configuration (FP32 state, A = 2, 1e8
-    trajectories), dumped per trajectory and checked on 150 trajectories sampled across the range
-    against the FP64 oracle on the same streams (the coupled bar: N within FP32 rounding except at
-    near-ties, ln w where the crossing steps agree), plus the histogram's totals."""
-    w = W.srusr_is_fp32(A_bias=2.0)
+@pytest.mark.parametrize("which", ["default", "matched", "time"])
+def test_full_size_fp32_sampled(which):
+    """The bench's FP32 workloads at full size and in its launch configuration (FP32 state, A = 2, 1e8
+    trajectories: the default Bessel table, the matched table, the matched noise indexed by time),
+    dumped per trajectory and checked on 150 trajectories sampled across the range against the FP64
+    oracle on the same streams (the coupled bar: N within FP32 rounding except at near-ties, ln w
+    where the crossing steps agree), plus the histogram's totals."""
+    w = {"default": W.srusr_is_fp32, "matched": W.srusr_is_fp32_matched, "time": W.srusr_is_fp32_time}[which](2.0)
     assert w.n_traj == 100_000_000
-    say(f"fp32 default full size n={w.n_traj}")
+    say(f"fp32 {which} full size n={w.n_traj}")
     (N, lnw, st), hist = gpu_run(w)
     idx = np.unique(np.concatenate([np.linspace(0, w.n_traj - 1, 148).astype(np.int64),
                                     [w.n_traj - 2, w.n_traj - 1]]))
