@@ -54,7 +54,9 @@ METRIC = "trajectory-steps/s and ESS-weighted tail samples/s at 5% P(δN) tail e
 # piecewise-linear potential), counted operation by operation as the kernels do
 # it; FMA = 2 FLOPs, a transcendental or a compare = 1.  The FP32 path takes V'/V
 # from the interval table (an interpolation and a NaN test) where the FP64 path
-# computes the reciprocal.  Derivation in the design doc.
+# computes the reciprocal.  Per part, FP32 / FP64: Box-Muller (half a pair) 6.5 /
+# 6.5, V'/V 3 / 13, table lookup 11 / 15, the update 15 / 17, ln w 1 / 3, the
+# float-pair accumulation 8 / -, events 5 / 4, per-group bookkeeping 2 / -.
 ALG_FLOPS_PER_STEP = {"fp32": 51.5, "fp64": 58.5}
 # the tabulated learned control adds its grid coordinates (ln|pi| included), the clamped
 # cell and fractions, the bilinear interpolation and the per-step dA = a xi sqrt(dN) + a^2 dN/2
@@ -351,8 +353,8 @@ def main() -> int:
                          "profiler's FETCH_SIZE / WRITE_SIZE counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(trajectories would shard by index with one histogram all-reduce; see DESIGN.md).",
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
+              "(trajectories would shard by index, with one all-reduce of the histograms at the end).",
               file=sys.stderr)
         return 2
 

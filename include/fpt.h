@@ -64,7 +64,7 @@ enum {
     FPT_ENOMEM = -2,        /* a device or host allocation failed */
     FPT_EHIP = -3,          /* a HIP runtime call failed */
     FPT_ESTATE = -4,        /* the call is not valid in the context's current state */
-    FPT_EUNSUPPORTED = -5   /* a valid request this build does not implement */
+    FPT_EUNSUPPORTED = -5   /* a valid request the library does not implement */
 };
 
 /* ---- enumerations ---------------------------------------------------------- */

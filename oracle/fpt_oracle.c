@@ -19,10 +19,18 @@
  *   - weight w = exp(-sum dA), dA of the Mazonka form:          Sec. 4.1, eqs. (weight), (weight_A)
  *   - first-passage time N = n dN, deltaN = N - <N>:            Sec. 4.1 and Sec. 2.3
  *   - piecewise-linear potential:                               Sec. 4.2, eq. (potential_starobinsky)
+ *   - Gaussian-bump potential:                                  Sec. 4.3, eq. (potential_swagat)
  *   - constant-nu noise with Bunch-Davies coefficients:         Sec. 3.2, eq. (covariance_constant_nu)
  *   - nu^2 as a function of phi only after the transition:      Sec. 3.4, eq. (nu_squared_approximation)
+ *   - 2D noise from the full Bunch-Davies mode, general weight:  Sec. 3.3, eq. (covariance_matrix_direct);
+ *                                                               Sec. 2.3, eq. (full_langevin_equation)
+ *   - Bessel-matched noise from the mode equation:              Sec. 2.1, eqs. (full_delta_phi), (bunch_davies);
+ *                                                               Sec. 3.4, eqs. (bessel_matching),
+ *                                                               (covariance_constant_nu_bessel_matched)
+ *   - noise precomputed along the classical trajectory and read
+ *     by the run's time, switched off after a fixed time:       Sec. 4.1
  *
- * Readings where the paper is silent or garbled (each listed in the design doc):
+ * Readings where the paper is silent or garbled (the design notes list each):
  *   - the drift in the biased pi step carries the same minus sign as in the
  *     unbiased step;
  *   - the bias is parallel to the noise vector: B_pi = tan(theta_n) B_phi with
@@ -32,14 +40,15 @@
  *   - absorption when phi <= phi_end; N is interpolated linearly in phi over
  *     the crossing step; eps_1 = pi^2/2 >= 1 before phi_end only raises a flag;
  *   - the noise is a function of phi (linear interpolation of a uniform table,
- *     clamped to the edge nodes), H^2 = V/3 inside the table;
+ *     clamped to the edge nodes), H^2 = V/3 inside the table; a table may
+ *     instead have its nodes in the run's time, read at N = n dN;
  *   - random numbers: Philox4x32-10 keyed by the 64-bit seed, counter
  *     (step>>2, trajectory lo, trajectory hi, instance); the four 32-bit words
  *     give four uniforms u = (w + 1/2) 2^-32 and two Box-Muller pairs.
  *
- * Parity status: every function below is pinned by a CPU test (see the
- * oracle section of the design doc); the learned-bias replay gradient is pinned by
- * central finite differences of its own objective.
+ * Parity status: every function below is pinned by a CPU test under tests/
+ * (test_oracle_*.py); the learned-bias replay gradient is pinned by central
+ * finite differences of its own objective.
  */
 #include <complex.h>
 #include <math.h>

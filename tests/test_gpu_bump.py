@@ -184,3 +184,20 @@ def test_bump_time_and_phi_windows_agree_in_the_core():
     say(f"  sd: phi window {sp:.5f}, time window {st:.5f}; means {Np.mean():.5f} {Nt.mean():.5f}")
     assert abs(st / sp - 1) < 0.01
     assert abs(Nt.mean() - Np.mean()) < 2e-3
+
+
+@pytest.mark.parametrize("window", ["phi", "time"])
+def test_bump_bench_configuration_sampled(window):
+    """The bench's bump workloads at full size (1e7 trajectories, A = 3, 96 log bins; the phi window and
+    the time window) in the bench's launch configuration: 80 trajectories sampled across the range at
+    per-trajectory parity with the oracle, and the histogram's totals."""
+    w = (W.gaussian_bump_is if window == "phi" else W.gaussian_bump_time_is)(A_bias=3.0)
+    assert w.n_traj == 10_000_000
+    say(f"bump bench configuration, {window} window")
+    (N, lnw, st), hist = gpu_run(w)
+    idx = np.unique(np.concatenate([np.linspace(0, w.n_traj - 1, 79).astype(np.int64), [w.n_traj - 1]]))
+    for i in idx:
+        No, lo_, so = oracle_run(w, n_traj=1, traj_offset=int(i))
+        assert_fp64_parity((N[i:i + 1], lnw[i:i + 1], st[i:i + 1]), (No, lo_, so), max_step_mismatch=1.0)
+    assert hist["n_traj"] == w.n_traj and int(hist["count"].sum()) == w.n_traj
+    assert hist["n_steps_total"] == int((st & fpt.FPT_STEP_MASK).astype(np.int64).sum())
