@@ -39,10 +39,11 @@ MLP_NPARAM = 4482
 def build(force: bool = True) -> str:
     """Compile the oracle with gcc (plain C, FP64, OpenMP, no FMA contraction)."""
     if force or not os.path.exists(_LIB):
+        tmp = f"{_LIB}.{os.getpid()}.tmp"      # per process: concurrent builds (test workers) do not collide
         cmd = ["gcc", "-O2", "-std=c11", "-D_GNU_SOURCE", "-fPIC", "-shared", "-fopenmp",
-               "-ffp-contract=off", "-fno-fast-math", _SRC, "-o", _LIB + ".tmp", "-lm"]
+               "-ffp-contract=off", "-fno-fast-math", _SRC, "-o", tmp, "-lm"]
         subprocess.run(cmd, check=True)
-        os.replace(_LIB + ".tmp", _LIB)
+        os.replace(tmp, _LIB)
     return _LIB
 
 
