@@ -196,8 +196,9 @@ def test_bump_bench_configuration_sampled(window):
     say(f"bump bench configuration, {window} window")
     (N, lnw, st), hist = gpu_run(w)
     idx = np.unique(np.concatenate([np.linspace(0, w.n_traj - 1, 79).astype(np.int64), [w.n_traj - 1]]))
+    p = oracle_problem(w)              # the oracle's own table, built once
     for i in idx:
-        No, lo_, so = oracle_run(w, n_traj=1, traj_offset=int(i))
+        No, lo_, so = orc.run(p, w.dN, w.seed, 1, traj_offset=int(i))
         assert_fp64_parity((N[i:i + 1], lnw[i:i + 1], st[i:i + 1]), (No, lo_, so), max_step_mismatch=1.0)
     assert hist["n_traj"] == w.n_traj and int(hist["count"].sum()) == w.n_traj
     assert hist["n_steps_total"] == int((st & fpt.FPT_STEP_MASK).astype(np.int64).sum())

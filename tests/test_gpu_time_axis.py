@@ -25,7 +25,7 @@ torch = pytest.importorskip("torch")
 from oracle import oracle as orc  # noqa: E402
 from paper_2410_13683_amd import fpt  # noqa: E402
 from paper_2410_13683_amd import workloads as W  # noqa: E402
-from tests._glue import assert_fp64_parity, oracle_run  # noqa: E402
+from tests._glue import assert_fp64_parity, oracle_problem2d, oracle_run  # noqa: E402
 from tests._gpu import gpu_context, gpu_run  # noqa: E402
 
 
@@ -228,8 +228,9 @@ def test_2d_time_full_size_sampled():
     say(f"fp64 2D time full size n={w.n_traj}")
     (N, lnw, st), hist = gpu_run(w)
     idx = np.unique(np.concatenate([np.linspace(0, w.n_traj - 1, 60).astype(np.int64), [w.n_traj - 1]]))
+    p = oracle_problem2d(w)            # the oracle's own table, built once
     for i in idx:
-        No, lo_, so = oracle_run(w, n_traj=1, traj_offset=int(i))
+        No, lo_, so = orc.run2d(p, w.dN, w.seed, 1, traj_offset=int(i))
         assert_fp64_parity((N[i:i + 1], lnw[i:i + 1], st[i:i + 1]), (No, lo_, so), max_step_mismatch=1.0)
     assert hist["n_traj"] == w.n_traj and int(hist["count"].sum()) == w.n_traj
     d = N - w.N_ref
