@@ -98,6 +98,30 @@ def kernel_source_sha() -> str:
     return h.hexdigest()
 
 
+# rocprofv3's derived VALUBusy = 100 sum(SQ_ACTIVE_INST_VALU) / CU_NUM / GRBM_GUI_ACTIVE, from one
+# --pmc VALUBusy VALUUtilization pass of one launch per kernel.  On gfx950 sum(SQ_ACTIVE_INST_VALU)
+# equals the VALU instruction count to within a few per cent, so the figure is VALU instructions
+# issued per CU per cycle (x100; four SIMDs per CU).  Valid only for the kernel source it was
+# measured on, like the traffic.
+MEASURED_VALU = {
+    "source_sha256": "dbcf6de0a27b20879e5fee77b7efc69f2c59f0b4a766a1f1fabb23766e123850",
+    "srusr_is_fp32_A2": {"VALUBusy": 142.577, "VALUUtilization": 99.679},
+    "srusr_bessel_fp64": {"VALUBusy": 95.753, "VALUUtilization": 99.756},
+}
+# the measured issue ceiling of independent v_fma_f32 chains, wave-instructions per SIMD per cycle
+FMA_F32_ISSUE_CEILING = 0.352
+
+
+def measured_valu(name: str):
+    m = MEASURED_VALU
+    if name not in m or kernel_source_sha() != m["source_sha256"]:
+        return None
+    v = dict(m[name])
+    v["valu_issue_per_simd_cycle"] = v["VALUBusy"] / 100.0 / 4.0
+    v["fma_f32_issue_ceiling"] = FMA_F32_ISSUE_CEILING
+    return v
+
+
 def measured_traffic(w):
     m = MEASURED_TRAFFIC
     if w.name != m["workload"] or w.n_traj != m["n_traj"] or kernel_source_sha() != m["source_sha256"]:
@@ -480,6 +504,7 @@ def main() -> int:
             "int_ops_per_step": ALG_INT_OPS_PER_STEP,
         },
     }
+    result["roofline"]["valu"] = measured_valu(w.name)
     if not learned:
         traffic, detail = measured_traffic(w)
         result["roofline"]["traffic"] = traffic
@@ -508,7 +533,8 @@ def main() -> int:
         s64 = int(h64["n_steps_total"])
         result["fp64_srusr"] = {"trajectories": w64.n_traj, "trajectory_steps_per_s": s64 / wall64,
                                 "kernel_ms": ms64,
-                                "tflops": ALG_FLOPS_PER_STEP["fp64"] * s64 / (ms64 * 1e-3) / 1e12}
+                                "tflops": ALG_FLOPS_PER_STEP["fp64"] * s64 / (ms64 * 1e-3) / 1e12,
+                                "valu": measured_valu(w64.name)}
         print(f"[bench] fp64 side run: {s64 / wall64:.3e} steps/s", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         print("[bench] CPU oracle baseline ...", file=sys.stderr, flush=True)
