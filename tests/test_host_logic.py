@@ -1,0 +1,90 @@
+"""Host-side logic behind the benchmark's tail metric, on histograms whose answers are known
+by construction (no GPU needed):
+- runner.tail_ess picks the lowest bin edge whose weighted tail mass is at most p_tail, and its
+  ESS_T = (sum w)^2 / sum w^2 over the tail set (the sample count for equal weights);
+- bench.tail_at reads P(deltaN >= x) at a bin edge;
+- bench.tail_errors: the plain standard error of the tail mass and the lognormal intervals of the
+  library's host entry point added in quadrature.
+Slot layout: 0 underflow, 1..n_bins the bins, n_bins + 1 overflow."""
+import importlib.util
+import math
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2410_13683_amd import runner
+from paper_2410_13683_amd import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _bench():
+    spec = importlib.util.spec_from_file_location("bench_under_test", os.path.join(ROOT, "bench.py"))
+    mod = importlib.util.module_from_spec(spec)
+    argv, sys.argv = sys.argv, ["bench.py"]
+    try:
+        spec.loader.exec_module(mod)
+    finally:
+        sys.argv = argv
+    return mod
+
+
+def _hist(n_traj, count, sum_w, sum_w2, sum_lnw=None, sum_lnw2=None):
+    ns = len(count)
+    return {"n_traj": n_traj, "count": np.asarray(count, dtype=np.uint64), "sum_w": np.asarray(sum_w, float),
+            "sum_w2": np.asarray(sum_w2, float),
+            "sum_lnw": np.zeros(ns) if sum_lnw is None else np.asarray(sum_lnw, float),
+            "sum_lnw2": np.zeros(ns) if sum_lnw2 is None else np.asarray(sum_lnw2, float)}
+
+
+def test_tail_ess_equal_weights_is_the_count():
+    """10 linear bins over [0, 1), 1000 trajectories, unit weights: tail masses are count fractions,
+    the first slot with tail mass <= 0.05 starts at edge 0.7, and ESS_T is the count there."""
+    count = np.array([0, 300, 200, 150, 120, 80, 60, 40, 25, 15, 10, 0])
+    assert count.sum() == 1000
+    h = _hist(1000, count, count.astype(float), count.astype(float))
+    x, p, ess, c = runner.tail_ess(h, 10, 0, 0.0, 1.0, p_tail=0.05)
+    # tail from slot 8 (edge 0.7): 25 + 15 + 10 = 50 -> 0.05
+    assert x == pytest.approx(0.7) and p == pytest.approx(0.05) and c == 50 and ess == pytest.approx(50.0)
+    # a threshold no slot meets
+    assert runner.tail_ess(h, 10, 0, 0.0, 1.0, p_tail=1e-9)[0] is None
+
+
+def test_tail_ess_weighted_log_bins():
+    """Log bins over [0.01, 1): weights make the tail mass and ESS differ from the counts."""
+    nb = 4
+    edges = 0.01 * 100.0 ** (np.arange(nb + 1) / nb)
+    count = np.array([5, 10, 10, 10, 10, 2])
+    w_per = np.array([1.0, 1.0, 0.5, 1e-3, 1e-6, 1e-9])       # one weight per slot
+    sum_w, sum_w2 = count * w_per, count * w_per ** 2
+    h = _hist(100, count, sum_w, sum_w2)
+    x, p, ess, c = runner.tail_ess(h, nb, 1, 0.01, 1.0, p_tail=1e-4)
+    # tail masses from slot 3: (10e-3 + 10e-6 + 2e-9)/100 > 1e-4; from slot 4: (1e-5 + 2e-9)/100 <= 1e-4
+    j = 4
+    assert x == pytest.approx(edges[j - 1])
+    sw, sw2 = sum_w[j:].sum(), sum_w2[j:].sum()
+    assert p == pytest.approx(sw / 100) and ess == pytest.approx(sw * sw / sw2) and c == 12
+    assert ess < c                                  # unequal weights
+
+
+def test_tail_at_and_tail_errors():
+    b = _bench()
+    w = W.srusr_is_fp32().with_(n_bins=4, lo=0.01, hi=1.0)
+    edges = 0.01 * 100.0 ** (np.arange(5) / 4)
+    rng = np.random.default_rng(3)
+    count = np.array([50, 400, 300, 200, 40, 10])
+    lnw = [rng.normal(-8.0 - k, 0.5, size=int(n)) for k, n in enumerate(count)]
+    h = _hist(1000, count, [np.exp(v).sum() for v in lnw], [np.exp(2 * v).sum() for v in lnw],
+              [v.sum() for v in lnw], [(v ** 2).sum() for v in lnw])
+    p, ess, n_t = b.tail_at(h, w, edges[2])         # slots 3.. (from edge index 2)
+    sw, sw2 = h["sum_w"][3:].sum(), h["sum_w2"][3:].sum()
+    assert p == pytest.approx(sw / 1000) and ess == pytest.approx(sw * sw / sw2) and n_t == 250
+    e = b.tail_errors(h, w, edges[2])
+    plain = math.sqrt((sw2 / 1000 - (sw / 1000) ** 2) / 1000)
+    assert e["P_tail_err"] == pytest.approx(plain)
+    from oracle import estimators as E
+    _, lo, hi = E.lognormal(1000, h["count"], h["sum_lnw"], h["sum_lnw2"])
+    half = 0.5 * (hi - lo)[3:]
+    assert e["P_tail_err_lognormal"] == pytest.approx(math.sqrt((half[np.isfinite(half)] ** 2).sum()), rel=1e-12)
