@@ -235,3 +235,21 @@ def test_2d_time_full_size_sampled():
     assert hist["n_traj"] == w.n_traj and int(hist["count"].sum()) == w.n_traj
     d = N - w.N_ref
     say(f"  mean deltaN {d.mean():.4e} sd {d.std():.4e}")
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_time_table_without_noise_is_classical(precision):
+    """A time table that is zero everywhere (the noise switched off from the start), constant bias
+    A = 2, 5000 trajectories: every run is the noise-free Euler-Maruyama passage from the time
+    workload's start (N_REF_TIME, written by the oracle), and ln w stays 0 (no step has S > 0)."""
+    w = W.srusr_time(n_traj=5000)
+    say(f"time table without noise, precision {precision}")
+    pot = fpt.make_potential(w.kind, w.V0, w.phi_T, w.A_plus, w.A_minus, w.phi_in, w.pi_in, w.phi_end)
+    ctx = fpt.Context(pot, np.zeros(4), np.zeros(4), 0.0, 3.0, axis=fpt.FPT_AXIS_TIME, bias_kind=fpt.FPT_BIAS_CONST,
+                      A=2.0, precision=precision, n_bins=16, lo=-0.1, hi=0.1, N_ref=w.N_ref)
+    (N, lnw, st), h = gpu_run(w, ctx=ctx)
+    ctx.destroy()
+    tol = 1e-12 if precision == 0 else 2e-5       # FP32 state: the increments' rounding over 1.2e5 steps
+    assert np.all(np.abs(N - W.N_REF_TIME) <= tol * W.N_REF_TIME), np.abs(N - W.N_REF_TIME).max()
+    assert np.all(lnw == 0.0)
+    assert len(np.unique(st)) == 1 and h["count"].sum() == w.n_traj
