@@ -21,6 +21,7 @@ torch = pytest.importorskip("torch")
 
 from oracle import oracle as orc  # noqa: E402
 from paper_2410_13683_amd import fpt  # noqa: E402
+from paper_2410_13683_amd import runner  # noqa: E402
 from paper_2410_13683_amd import workloads as W  # noqa: E402
 from tests._glue import assert_fp64_parity, oracle_problem, oracle_run, oracle_table  # noqa: E402
 from tests._gpu import gpu_context, gpu_run, gpu_table  # noqa: E402
@@ -326,3 +327,27 @@ def test_full_size_fp32_sampled(which):
     assert len(dl) >= 0.90 * len(idx) and np.median(dl) < 1e-5 and dl.max() < 1e-3
     assert hist["n_traj"] == w.n_traj and int(hist["count"].sum()) == w.n_traj
     assert hist["n_steps_total"] == int((st & orc.STEP_MASK).astype(np.uint64).sum())
+
+
+def test_rare_tail_matches_oracle_at_1e_minus_10():
+    """The target of the method: the weighted tail probability P(deltaN >= x*) at the bin edge x*
+    where it is about 1e-10, from the bench's default run (FP32 state, A = 2, 1e8 trajectories),
+    against the FP64 oracle's own importance-sampled estimate on 1e5 independent trajectories
+    (disjoint indices): within 5 % and within 4 combined standard errors."""
+    w = W.srusr_is_fp32(A_bias=2.0)
+    say(f"rare tail: GPU {w.n_traj:.0e} trajectories")
+    _, h = gpu_run(w, dumps=False)
+    x, p_gpu, ess, n_t = runner.tail_ess(h, w.n_bins, w.bins_kind, w.lo, w.hi, 1e-10)
+    assert x is not None and 1e-11 < p_gpu <= 1e-10
+    j = int(np.argmin(np.abs(w.lo * (w.hi / w.lo) ** (np.arange(w.n_bins + 1) / w.n_bins) - x))) + 1
+    se_gpu = math.sqrt(max(float(h["sum_w2"][j:].sum()) / w.n_traj - p_gpu ** 2, 0.0) / w.n_traj)
+    n_o = 100_000
+    say(f"  oracle: {n_o} trajectories")
+    No, lo_, so = orc.run(oracle_problem(w), w.dN, w.seed, n_o, traj_offset=w.n_traj)
+    assert np.all((so & (orc.FLAG_CENSORED | orc.FLAG_ENDED_EARLY)) == 0)
+    wt = np.where(No - w.N_ref >= x, np.exp(lo_), 0.0)
+    p_o, se_o = wt.mean(), wt.std(ddof=1) / math.sqrt(n_o)
+    say(f"  x* = {x:.4f}: GPU P = {p_gpu:.4e} +- {se_gpu:.1e} (ESS {ess:.3g}), oracle P = {p_o:.4e} +- {se_o:.1e}")
+    assert se_o < 0.02 * p_o
+    assert abs(p_gpu / p_o - 1.0) < 0.05
+    assert abs(p_gpu - p_o) < 4.0 * math.sqrt(se_o ** 2 + se_gpu ** 2)
