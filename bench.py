@@ -83,9 +83,9 @@ PEAK_HBM_GBS = 8000.0
 # process (FETCH_SIZE reads 0.5 GiB: x2.0; WRITE_SIZE reads 1 GiB: x1.0).  Valid only for the
 # kernel source it was measured on (hash of the kernel file and its header).
 MEASURED_TRAFFIC = {
-    "source_sha256": "dbcf6de0a27b20879e5fee77b7efc69f2c59f0b4a766a1f1fabb23766e123850",
+    "source_sha256": "8d4f2329b39ddf6e1fe1eaa028e92acaa95725cff7827c17bffd91aec9ad218f",
     "workload": "srusr_is_fp32_A2", "n_traj": 100_000_000,
-    "fetch_bytes": 465.6875 * 1024 * 2.0, "write_bytes": 2082664.125 * 1024 * 1.0,
+    "fetch_bytes": 472.375 * 1024 * 2.0, "write_bytes": 2083392.125 * 1024 * 1.0,
 }
 
 
@@ -104,9 +104,9 @@ def kernel_source_sha() -> str:
 # issued per CU per cycle (x100; four SIMDs per CU).  Valid only for the kernel source it was
 # measured on, like the traffic.
 MEASURED_VALU = {
-    "source_sha256": "dbcf6de0a27b20879e5fee77b7efc69f2c59f0b4a766a1f1fabb23766e123850",
-    "srusr_is_fp32_A2": {"VALUBusy": 142.577, "VALUUtilization": 99.679},
-    "srusr_bessel_fp64": {"VALUBusy": 95.753, "VALUUtilization": 99.756},
+    "source_sha256": "8d4f2329b39ddf6e1fe1eaa028e92acaa95725cff7827c17bffd91aec9ad218f",
+    "srusr_is_fp32_A2": {"VALUBusy": 142.960, "VALUUtilization": 99.679},
+    "srusr_bessel_fp64": {"VALUBusy": 95.258, "VALUUtilization": 99.718},
 }
 # the measured issue ceiling of independent v_fma_f32 chains, wave-instructions per SIMD per cycle
 FMA_F32_ISSUE_CEILING = 0.352
