@@ -150,3 +150,38 @@ def test_batched_instances_workload_totals():
     b.destroy()
     for c in ctxs:
         c.destroy()
+
+
+def test_bench_batched_configuration_matches_single_runs(tmp_path):
+    """The bench's batched configuration as it times it (64 FP32 instances, trajectory counts scaled
+    by 0.1, step cap 2^20, autotuned, hipGraph): one pass, then four instances (the largest, the
+    smallest, the most censored and the median) rerun as single-context launches over the same
+    trajectories give the same histograms."""
+    ws = [w.with_(precision=1) for w in W.batched_instances()]
+    counts = np.array([max(1, int(round(w.n_traj * 0.1))) for w in ws], dtype=np.uint64)
+    ctxs = [runner.context_for(w) for w in ws]
+    stream = torch.cuda.Stream()
+    b = fpt.Batch(ctxs, use_graph=True)
+    dN, seed, off = ws[0].dN, ws[0].seed, 1 << 32
+    b.autotune(counts, dN, seed, cache_path=str(tmp_path / "tune.txt"), stream=stream)
+    say(f"bench batch configuration: {int(counts.sum())} trajectories, config {b.config()}")
+    for c in ctxs:
+        c.reset()
+    b.run(counts, dN, seed, off, stream)
+    stream.synchronize()
+    hb = [c.histogram() for c in ctxs]
+    for c, n, h in zip(ctxs, counts, hb):
+        assert h["n_traj"] == n and int(h["count"].sum()) + h["n_censored"] + h["n_ended_early"] == n
+    cens = [h["n_censored"] / h["n_traj"] for h in hb]
+    pick = sorted({int(np.argmax(counts)), int(np.argmin(counts)), int(np.argmax(cens)),
+                   int(np.argsort(counts)[len(counts) // 2])})
+    assert max(cens) > 0                        # the step cap is exercised
+    for i in pick:
+        ctxs[i].reset()
+        ctxs[i].run(int(counts[i]), dN, seed, off, None)
+        torch.cuda.synchronize()
+        _compare(hb[i], ctxs[i].histogram())
+    say(f"  instances {pick} equal to single launches")
+    b.destroy()
+    for c in ctxs:
+        c.destroy()
