@@ -55,20 +55,20 @@ METRIC = "trajectory-steps/s and ESS-weighted tail samples/s at 5% P(δN) tail e
 # it; FMA = 2 FLOPs, a transcendental or a compare = 1.  The FP32 path takes V'/V
 # from the interval table (an interpolation and a NaN test) where the FP64 path
 # computes the reciprocal.  Per part, FP32 / FP64: Box-Muller (half a pair) 6.5 /
-# 6.5, V'/V 3 / 13, table lookup 11 / 15, the update 15 / 17, ln w 1 / 3, the
+# 6.5, V'/V 3 / 9, table lookup 11 / 15, the update 15 / 17, ln w 1 / 3, the
 # float-pair accumulation 8 / -, events 5 / 4, per-group bookkeeping 2 / -.
-ALG_FLOPS_PER_STEP = {"fp32": 51.5, "fp64": 58.5}
+ALG_FLOPS_PER_STEP = {"fp32": 51.5, "fp64": 54.5}
 # the tabulated learned control adds its grid coordinates (ln|pi| included), the clamped
 # cell and fractions, the bilinear interpolation and the per-step dA = a xi sqrt(dN) + a^2 dN/2
 ALG_FLOPS_LEARNED_EXTRA = {"fp32": 31.0, "fp64": 31.0}
-# FP64 state with 2D noise, no bias: a Box-Muller pair per step (13), V'/V (13), five interpolated
+# FP64 state with 2D noise, no bias: a Box-Muller pair per step (13), V'/V (9), five interpolated
 # table entries (23), the 2x2 noise product (6), the update (12), events (4); a constant bias adds
 # B = a S e (8) and dA (10)
-ALG_FLOPS_2D = {"none": 71.0, "const": 89.0}
+ALG_FLOPS_2D = {"none": 67.0, "const": 85.0}
 # the Gaussian bump's V'/V (FP64): x, x^2/2, exp, K g, phi (m^2 + phi^2), Sigma (1 + g), the
 # numerator 2 m^2 d2 - x g d1, the denominator and an IEEE division (reciprocal, two Newton steps and
-# the correction) = 28 FLOPs in place of the linear potentials' 13
-ALG_FLOPS_BUMP_FP64 = 58.5 - 13.0 + 28.0
+# the correction) = 28 FLOPs in place of the linear potentials' 9
+ALG_FLOPS_BUMP_FP64 = 54.5 - 9.0 + 28.0
 # FP32 state on a time-indexed table: V'/V exactly (phi - phi_T from the float pair, 3; the branch's
 # compare, 1; the FMA, 2; the reciprocal, 1) in place of its interpolation and NaN test (3); the last
 # node is zero, so the weight tests S > 0 (1)
@@ -83,9 +83,9 @@ PEAK_HBM_GBS = 8000.0
 # process (FETCH_SIZE reads 0.5 GiB: x2.0; WRITE_SIZE reads 1 GiB: x1.0).  Valid only for the
 # kernel source it was measured on (hash of the kernel file and its header).
 MEASURED_TRAFFIC = {
-    "source_sha256": "8d4f2329b39ddf6e1fe1eaa028e92acaa95725cff7827c17bffd91aec9ad218f",
+    "source_sha256": "8663b1f61e02c7cc62312dd50f8493aeee6cc283ad8ced2157358ad67de29544",
     "workload": "srusr_is_fp32_A2", "n_traj": 100_000_000,
-    "fetch_bytes": 472.375 * 1024 * 2.0, "write_bytes": 2083392.125 * 1024 * 1.0,
+    "fetch_bytes": 472.5 * 1024 * 2.0, "write_bytes": 2081795.3125 * 1024 * 1.0,
 }
 
 
@@ -104,9 +104,9 @@ def kernel_source_sha() -> str:
 # issued per CU per cycle (x100; four SIMDs per CU).  Valid only for the kernel source it was
 # measured on, like the traffic.
 MEASURED_VALU = {
-    "source_sha256": "8d4f2329b39ddf6e1fe1eaa028e92acaa95725cff7827c17bffd91aec9ad218f",
-    "srusr_is_fp32_A2": {"VALUBusy": 142.960, "VALUUtilization": 99.679},
-    "srusr_bessel_fp64": {"VALUBusy": 95.258, "VALUUtilization": 99.718},
+    "source_sha256": "8663b1f61e02c7cc62312dd50f8493aeee6cc283ad8ced2157358ad67de29544",
+    "srusr_is_fp32_A2": {"VALUBusy": 142.787, "VALUUtilization": 99.679},
+    "srusr_bessel_fp64": {"VALUBusy": 95.727, "VALUUtilization": 99.732},
 }
 # the measured issue ceiling of independent v_fma_f32 chains, wave-instructions per SIMD per cycle
 FMA_F32_ISSUE_CEILING = 0.352
