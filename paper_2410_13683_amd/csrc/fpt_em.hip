@@ -330,7 +330,13 @@ __device__ __forceinline__ double bump_dlnV(const BumpConsts &b, double phi)
     const double g = b.K * exp(-0.5 * x * x);
     const double d1 = phi * fma(phi, phi, b.m2);
     const double d2 = b.sig * (1.0 + g);
-    return (b.two_m2 * d2 - x * g * d1) / (d1 * d2);
+    // the quotient as the hardware reciprocal of the denominator (a normal number here: phi > 0
+    // away from 0, Sigma (1 + g) > 0) with one Newton step, times the numerator: about 2e-15
+    // relative, where the IEEE division would spend twice the instructions on the last ulp
+    const double den = d1 * d2;
+    double r = __builtin_amdgcn_rcp(den);
+    r = fma(r, fma(-den, r, 1.0), r);
+    return (b.two_m2 * d2 - x * g * d1) * r;
 }
 
 // The table size used by the kernels: a single node (constant noise) is
