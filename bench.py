@@ -83,9 +83,9 @@ PEAK_HBM_GBS = 8000.0
 # process (FETCH_SIZE reads 0.5 GiB: x2.0; WRITE_SIZE reads 1 GiB: x1.0).  Valid only for the
 # kernel source it was measured on (hash of the kernel file and its header).
 MEASURED_TRAFFIC = {
-    "source_sha256": "c63dc6f8c7dacfec53bcf1b1f7def76529a0215aaecfad1862b7ff0bf31d4658",
+    "source_sha256": "91d1944d42065cbdef7135d4925cbd136d87d7accafccf63c4b719696df033e0",
     "workload": "srusr_is_fp32_A2", "n_traj": 100_000_000,
-    "fetch_bytes": 466.3125 * 1024 * 2.0, "write_bytes": 2082451.125 * 1024 * 1.0,
+    "fetch_bytes": 466.375 * 1024 * 2.0, "write_bytes": 2081229.9375 * 1024 * 1.0,
 }
 
 
@@ -104,9 +104,9 @@ def kernel_source_sha() -> str:
 # issued per CU per cycle (x100; four SIMDs per CU).  Valid only for the kernel source it was
 # measured on, like the traffic.
 MEASURED_VALU = {
-    "source_sha256": "c63dc6f8c7dacfec53bcf1b1f7def76529a0215aaecfad1862b7ff0bf31d4658",
-    "srusr_is_fp32_A2": {"VALUBusy": 142.424, "VALUUtilization": 99.679},
-    "srusr_bessel_fp64": {"VALUBusy": 95.648, "VALUUtilization": 99.728},
+    "source_sha256": "91d1944d42065cbdef7135d4925cbd136d87d7accafccf63c4b719696df033e0",
+    "srusr_is_fp32_A2": {"VALUBusy": 142.701, "VALUUtilization": 99.679},
+    "srusr_bessel_fp64": {"VALUBusy": 95.710, "VALUUtilization": 99.730},
 }
 # the measured issue ceiling of independent v_fma_f32 chains, wave-instructions per SIMD per cycle
 FMA_F32_ISSUE_CEILING = 0.352

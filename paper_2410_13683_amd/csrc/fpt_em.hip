@@ -440,10 +440,11 @@ __device__ __forceinline__ float grid_amp32(const GridConsts32 &g, const float4 
 {
     const float u0 = fmaf(x, g.k0, g.off0);
     const float u1 = fmaf(__builtin_amdgcn_logf(fmaxf(fabsf(pi_), 1e-30f)), g.k1, g.off1);
-    const float i0 = fminf(fmaxf(floorf(u0), 0.0f), g.imax0);
-    const float i1 = fminf(fmaxf(floorf(u1), 0.0f), g.imax1);
-    f0 = fminf(fmaxf(u0 - i0, 0.0f), 1.0f);
-    f1 = fminf(fmaxf(u1 - i1, 0.0f), 1.0f);
+    // clamps as one three-operand median each (both coordinates are finite)
+    const float i0 = __builtin_amdgcn_fmed3f(floorf(u0), 0.0f, g.imax0);
+    const float i1 = __builtin_amdgcn_fmed3f(floorf(u1), 0.0f, g.imax1);
+    f0 = __builtin_amdgcn_fmed3f(u0 - i0, 0.0f, 1.0f);
+    f1 = __builtin_amdgcn_fmed3f(u1 - i1, 0.0f, 1.0f);
     cell = (int)i0 * g.n1c + (int)i1;
     const float4 c = l_grid[cell];
     const float b0 = fmaf(f0, c.y - c.x, c.x);
