@@ -164,6 +164,14 @@ def test_edge_cases():
         (N, lnw, st), h = gpu_run(we.with_(precision=prec))
         assert np.all(st == (1 | orc.FLAG_ENDED_EARLY)) and h["n_ended_early"] == 70
         np.testing.assert_allclose(N, we.dN)
+    say("edge: trajectory indices across 2^32, instance word 5")
+    wi = W.srusr_bessel(n_traj=300, seed=8).with_(bias_kind=W.BIAS_CONST, A_bias=1.0, extra={"instance": 5})
+    off = (1 << 32) - 150                   # the counter's high word changes inside the range
+    gpu, _ = gpu_run(wi, traj_offset=off)
+    assert_fp64_parity(gpu, oracle_run(wi, traj_offset=off))
+    # and the instance word matters: instance 0 gives other trajectories
+    gpu0, _ = gpu_run(wi.with_(extra={"instance": 0}), traj_offset=off)
+    assert np.mean(gpu0[0] != gpu[0]) > 0.99
     say("edge: run errors")
     ctx = gpu_context(w)
     with pytest.raises(fpt.FptError):
