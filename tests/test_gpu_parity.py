@@ -339,13 +339,15 @@ def test_full_size_fp32_sampled(which):
     assert hist["n_steps_total"] == int((st & orc.STEP_MASK).astype(np.uint64).sum())
 
 
-def test_rare_tail_matches_oracle_at_1e_minus_10():
+@pytest.mark.parametrize("which", ["default", "matched", "time"])
+def test_rare_tail_matches_oracle_at_1e_minus_10(which):
     """The target of the method: the weighted tail probability P(deltaN >= x*) at the bin edge x*
-    where it is about 1e-10, from the bench's default run (FP32 state, A = 2, 1e8 trajectories),
-    against the FP64 oracle's own importance-sampled estimate on 1e5 independent trajectories
-    (disjoint indices): within 5 % and within 4 combined standard errors."""
-    w = W.srusr_is_fp32(A_bias=2.0)
-    say(f"rare tail: GPU {w.n_traj:.0e} trajectories")
+    where it is about 1e-10, from the bench's FP32 runs (A = 2, 1e8 trajectories: the default Bessel
+    table, the matched table, the matched noise indexed by time), against the FP64 oracle's own
+    importance-sampled estimate on 1e5 independent trajectories (disjoint indices): within 5 % and
+    within 4 combined standard errors."""
+    w = {"default": W.srusr_is_fp32, "matched": W.srusr_is_fp32_matched, "time": W.srusr_is_fp32_time}[which](2.0)
+    say(f"rare tail ({which}): GPU {w.n_traj:.0e} trajectories")
     _, h = gpu_run(w, dumps=False)
     x, p_gpu, ess, n_t = runner.tail_ess(h, w.n_bins, w.bins_kind, w.lo, w.hi, 1e-10)
     assert x is not None and 1e-11 < p_gpu <= 1e-10
