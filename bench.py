@@ -103,10 +103,22 @@ def kernel_source_sha() -> str:
 # equals the VALU instruction count to within a few per cent, so the figure is VALU instructions
 # issued per CU per cycle (x100; four SIMDs per CU).  Valid only for the kernel source it was
 # measured on, like the traffic.
+# "hw_flops_per_step" and "insts_per_step" come from one --pmc pass of eight SQ_INSTS_VALU_*
+# counters per kernel (one launch): 64 x wave-instructions / trajectory steps, FLOPs counted as
+# 2 FMA + ADD + MUL + TRANS of each precision.  They measure what the compiled kernel executes,
+# beside the operation-by-operation count of the method used for "achieved".
 MEASURED_VALU = {
     "source_sha256": "91d1944d42065cbdef7135d4925cbd136d87d7accafccf63c4b719696df033e0",
-    "srusr_is_fp32_A2": {"VALUBusy": 142.701, "VALUUtilization": 99.679},
-    "srusr_bessel_fp64": {"VALUBusy": 95.710, "VALUUtilization": 99.730},
+    "srusr_is_fp32_A2": {"VALUBusy": 142.701, "VALUUtilization": 99.679,
+                         "hw_flops_per_step": {"f32": 42.300, "f64": 0.334},
+                         "insts_per_step": {"FMA_F32": 10.011, "ADD_F32": 13.267, "MUL_F32": 7.007,
+                                            "TRANS_F32": 2.003, "CVT": 2.259, "INT32": 4.796,
+                                            "FMA_F64": 0.026, "ADD_F64": 0.283}},
+    "srusr_bessel_fp64": {"VALUBusy": 95.710, "VALUUtilization": 99.730,
+                          "hw_flops_per_step": {"f32": 0.0, "f64": 63.283},
+                          "insts_per_step": {"FMA_F64": 22.527, "ADD_F64": 4.812, "MUL_F64": 11.897,
+                                             "TRANS_F64": 1.519, "INT32": 4.087, "FMA_F32": 0.0,
+                                             "ADD_F32": 0.0, "MUL_F32": 0.0}},
 }
 # the measured issue ceiling of independent v_fma_f32 chains, wave-instructions per SIMD per cycle
 FMA_F32_ISSUE_CEILING = 0.352
@@ -120,6 +132,13 @@ def measured_valu(name: str):
     v["valu_issue_per_simd_cycle"] = v["VALUBusy"] / 100.0 / 4.0
     v["fma_f32_issue_ceiling"] = FMA_F32_ISSUE_CEILING
     return v
+
+
+def hw_counted_rate(valu, steps_per_s):
+    """TFLOP/s of the FLOPs the hardware counters saw the kernel execute (both precisions)."""
+    if not valu or "hw_flops_per_step" not in valu:
+        return None
+    return sum(valu["hw_flops_per_step"].values()) * steps_per_s / 1e12
 
 
 def measured_traffic(w):
@@ -505,6 +524,10 @@ def main() -> int:
         },
     }
     result["roofline"]["valu"] = measured_valu(w.name)
+    hw = hw_counted_rate(result["roofline"]["valu"], steps_per_launch / (avg_ms * 1e-3))
+    if hw:
+        result["roofline"]["achieved_hw_counted"] = hw
+        result["roofline"]["frac_hw_counted"] = hw / PEAK_TFLOPS[prec]
     if prec == "fp32":
         # the published FP32 peak counts packed FP32 (two lanes per instruction), which these kernels
         # are built without; a non-packed instruction stream peaks at half of it
@@ -540,6 +563,9 @@ def main() -> int:
                                 "kernel_ms": ms64,
                                 "tflops": ALG_FLOPS_PER_STEP["fp64"] * s64 / (ms64 * 1e-3) / 1e12,
                                 "valu": measured_valu(w64.name)}
+        hw64 = hw_counted_rate(result["fp64_srusr"]["valu"], s64 / (ms64 * 1e-3))
+        if hw64:
+            result["fp64_srusr"]["tflops_hw_counted"] = hw64
         print(f"[bench] fp64 side run: {s64 / wall64:.3e} steps/s", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         print("[bench] CPU oracle baseline ...", file=sys.stderr, flush=True)
