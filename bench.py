@@ -54,13 +54,18 @@ METRIC = "trajectory-steps/s and ESS-weighted tail samples/s at 5% P(δN) tail e
 # piecewise-linear potential), counted operation by operation as the kernels do
 # it; FMA = 2 FLOPs, a transcendental or a compare = 1.  The FP32 path takes V'/V
 # from the interval table (an interpolation and a NaN test) where the FP64 path
-# computes the reciprocal.  Per part, FP32 / FP64: Box-Muller (half a pair) 6.5 /
-# 6.5, V'/V 3 / 9, table lookup 11 / 15, the update 15 / 17, ln w 1 / 3, the
-# float-pair accumulation 8 / -, events 5 / 4, per-group bookkeeping 2 / -.
-ALG_FLOPS_PER_STEP = {"fp32": 51.5, "fp64": 54.5}
+# computes the reciprocal.  The FP32 step carries the constant bias in the normal
+# (z = xi sqrt(dN) + A dN, the Box-Muller products become FMAs) and V'/V scaled by
+# dN, so its update is B = S z, dphi = pi dN + B, dpi = t B - (3 - pi^2/2)(pi dN + r dN).
+# Per part, FP32 / FP64: Box-Muller (half a pair) 7.5 / 6.5, V'/V 3 / 9, table
+# lookup 11 / 15, the update 11 / 17, ln w 1 / 3, the float-pair accumulation 8 / -,
+# events 5 / 4, per-group bookkeeping 2 / -.
+ALG_FLOPS_PER_STEP = {"fp32": 48.5, "fp64": 54.5}
 # the tabulated learned control adds its grid coordinates (ln|pi| included), the clamped
 # cell and fractions, the bilinear interpolation and the per-step dA = a xi sqrt(dN) + a^2 dN/2
-ALG_FLOPS_LEARNED_EXTRA = {"fp32": 31.0, "fp64": 31.0}
+# (31); in FP32 also a S and its separate FMA into the increment (3), less the offset of the
+# Box-Muller FMAs, which it does not use (1)
+ALG_FLOPS_LEARNED_EXTRA = {"fp32": 33.0, "fp64": 31.0}
 # FP64 state with 2D noise, no bias: a Box-Muller pair per step (13), V'/V (9), five interpolated
 # table entries (23), the 2x2 noise product (6), the update (12), events (4); a constant bias adds
 # B = a S e (8) and dA (10)
@@ -72,7 +77,7 @@ ALG_FLOPS_BUMP_FP64 = 54.5 - 9.0 + 22.0
 # FP32 state on a time-indexed table: V'/V exactly (phi - phi_T from the float pair, 3; the branch's
 # compare, 1; the FMA, 2; the reciprocal, 1) in place of its interpolation and NaN test (3); the last
 # node is zero, so the weight tests S > 0 (1)
-ALG_FLOPS_TIME_FP32 = 51.5 - 3.0 + 7.0 + 1.0
+ALG_FLOPS_TIME_FP32 = 48.5 - 3.0 + 7.0 + 1.0
 ALG_INT_OPS_PER_STEP = 16.0          # Philox4x32-10 amortised over 4 steps + uniform conversions
 PEAK_TFLOPS = {"fp32": 157.3, "fp64": 78.6}   # MI355X published vector peaks
 PEAK_HBM_GBS = 8000.0

@@ -151,15 +151,15 @@ __device__ __forceinline__ void box_muller64(uint32_t wa, uint32_t wb, double sq
 // FP64 path, rounded to 24 significant bits (relative, not absolute, resolution,
 // so the radius stays accurate for small u).  Never 0; at most 1.0f, where the
 // radius is 0.  v_log_f32 returns log2, v_sin_f32 / v_cos_f32 take turns.
-// Returns xi sqrt(dN) for the two steps of the pair.
-__device__ __forceinline__ void box_muller32(uint32_t wa, uint32_t wb, float sqrt_dN, float &za, float &zb)
+// Returns xi sqrt(dN) + off for the two steps of the pair.
+__device__ __forceinline__ void box_muller32(uint32_t wa, uint32_t wb, float sqrt_dN, float off, float &za, float &zb)
 {
     const float ua = fmaf((float)wa, 0x1p-32f, 0x1p-33f);
     const float ub = fmaf((float)wb, 0x1p-32f, 0x1p-33f);
     const float m2lnu = fmaxf(-1.3862943611198906f * __builtin_amdgcn_logf(ua), 0.0f);  // -2 ln u
     const float rho = __builtin_amdgcn_sqrtf(m2lnu) * sqrt_dN;
-    za = rho * __builtin_amdgcn_cosf(ub);
-    zb = rho * __builtin_amdgcn_sinf(ub);
+    za = fmaf(rho, __builtin_amdgcn_cosf(ub), off);
+    zb = fmaf(rho, __builtin_amdgcn_sinf(ub), off);
 }
 
 // Copy a wave-uniform value into a VGPR once, so that a per-lane select between
@@ -351,15 +351,24 @@ __device__ __forceinline__ void stage_table64(const Inst &I, double2 *l_tab)
     stage_bm(l_tab + n);
 }
 
-// FP32 staging: the noise nodes, then the V'/V intervals right after them (all
-// NaN for a single-node table, so that V'/V is computed exactly there).
-__device__ __forceinline__ void stage_table32(const Inst &I, float4 *l_tab)
+// FP32 staging: the noise nodes, then the V'/V intervals right after them,
+// scaled by the time step (the step uses (V'/V) dN); all NaN for a single-node
+// table, so that V'/V is computed exactly there.
+__device__ __forceinline__ void stage_table32(const Inst &I, float4 *l_tab, float dN)
 {
     const int n = staged_nodes(I);
     for (int i = threadIdx.x; i < n; i += blockDim.x) l_tab[i] = I.tab32[I.n_tab > 1 ? i : 0];
     float2 *l_r = reinterpret_cast<float2 *>(l_tab + n);
     const float nan = __builtin_nanf("");
-    for (int i = threadIdx.x; i < n; i += blockDim.x) l_r[i] = I.n_tab > 1 ? I.rtab32[i] : make_float2(nan, nan);
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        float2 r = make_float2(nan, nan);
+        if (I.n_tab > 1) {
+            r = I.rtab32[i];
+            r.x *= dN;
+            r.y *= dN;
+        }
+        l_r[i] = r;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -658,13 +667,13 @@ __device__ __forceinline__ void lanes_fp64(const Inst &I, const RunArgs &R, cons
 // ---------------------------------------------------------------------------
 struct F32Consts {
     float xT_hi, xT_lo;        // phi_T - phi_end as a float pair
-    float kx, s_plus, s_minus; // V'/V = 1/(kx (phi - phi_T) + s), s = s_plus (phi >= phi_T) or s_minus
+    float kx, s_plus, s_minus; // (V'/V) dN = 1/(kx (phi - phi_T) + s), s = s_plus (phi >= phi_T) or s_minus
     float u_off;               // (phi_end - phi_lo) * inv_h: table coordinate of x = 0
     float inv_h;
     float t_scale, t_off;      // time tables: coordinate n dN inv_h - N_lo inv_h
     float jmax;                // n_tab - 2
     float dN, sqrt_dN;
-    float a;
+    float adN;                 // constant bias: A dN, the shift carried by each step's normal
 };
 
 __device__ __forceinline__ F32Consts f32_consts(const Inst &I, const RunArgs &R)
@@ -673,13 +682,14 @@ __device__ __forceinline__ F32Consts f32_consts(const Inst &I, const RunArgs &R)
     const double xT = I.phi_T - I.phi_end;
     c.xT_hi = (float)xT;
     c.xT_lo = (float)(xT - (double)c.xT_hi);
+    const double inv_dN = 1.0 / R.dN;
     if (I.pot_kind == kPotExponential) {
         c.kx = 0.0f;
-        c.s_plus = c.s_minus = (float)(1.0 / I.A_plus);
+        c.s_plus = c.s_minus = (float)(inv_dN / I.A_plus);
     } else {
-        c.kx = 1.0f;
-        c.s_plus = (float)(I.V0 / I.A_plus);
-        c.s_minus = (float)(I.V0 / I.A_minus);
+        c.kx = (float)inv_dN;
+        c.s_plus = (float)(I.V0 / I.A_plus * inv_dN);
+        c.s_minus = (float)(I.V0 / I.A_minus * inv_dN);
     }
     c.u_off = (float)((I.phi_end - I.phi_lo) * I.inv_h);
     c.inv_h = (float)I.inv_h;
@@ -688,7 +698,7 @@ __device__ __forceinline__ F32Consts f32_consts(const Inst &I, const RunArgs &R)
     c.jmax = (float)(staged_nodes(I) - 2);
     c.dN = (float)R.dN;
     c.sqrt_dN = (float)R.sqrt_dN;
-    c.a = (I.bias_kind == kBiasConst) ? (float)I.A : 0.0f;
+    c.adN = (I.bias_kind == kBiasConst) ? (float)(I.A * R.dN) : 0.0f;
     return c;
 }
 
@@ -725,7 +735,7 @@ __device__ __forceinline__ void lanes_fp32(const Inst &I, const RunArgs &R, cons
     bool has = claim(true, rel, cursor, n_traj, exhausted);
     bool live = has;          // has a trajectory that has not ended yet
     float xh = x_in_hi, xl = x_in_lo, ph = pi_in_hi, pl = pi_in_lo;
-    double zsum = 0.0;        // constant bias: sum of xi sqrt(dN) over steps with S > 0
+    double zsum = 0.0;        // constant bias: sum of z = xi sqrt(dN) + a dN over steps with S > 0
     uint32_t n_on = 0;        // constant bias: number of such steps (counted only when some node has S = 0)
     double lnw = 0.0;         // learned bias: ln w up to the current group
     uint32_t n = 0;
@@ -738,8 +748,12 @@ __device__ __forceinline__ void lanes_fp32(const Inst &I, const RunArgs &R, cons
         ww = rp.tail[rel].ww;
     }
 
+    // constant bias: each step's normal carries the drift shift, z = xi sqrt(dN) + c.adN with
+    // c.adN = fl32(A dN), so the exponent of eq. (weight_A) in 1D over k steps,
+    // -A sum xi sqrt(dN) - k A^2 dN / 2, is -A sum z + k (A c.adN - A^2 dN / 2)
+    const double lnw_step = A * (double)c.adN - half_a2_dN;
     auto lnw_of = [&](double zs_total, uint32_t steps_on) -> double {
-        return (BIAS == kBiasNone) ? 0.0 : -A * zs_total - (double)steps_on * half_a2_dN;
+        return (BIAS == kBiasNone) ? 0.0 : -A * zs_total + (double)steps_on * lnw_step;
     };
 
     auto group = [&](auto censor_tag, const float z[4]) {
@@ -762,12 +776,12 @@ __device__ __forceinline__ void lanes_fp32(const Inst &I, const RunArgs &R, cons
                 live = false;
                 fresh = true;
             }
-            // V'/V exactly: 1/(kx (phi - phi_T) + s), phi - phi_T = (xh - xT_hi) + (xl - xT_lo)
+            // (V'/V) dN exactly: 1/(kx (phi - phi_T) + s), phi - phi_T = (xh - xT_hi) + (xl - xT_lo)
             auto drift_exact = [&]() -> float {
                 const float dT = (xh - c.xT_hi) + (xl - c.xT_lo);
                 return __builtin_amdgcn_rcpf(fmaf(dT, c.kx, (dT >= 0.0f) ? s_plus : s_minus));
             };
-            float S, t, r;
+            float S, t, r;        // r = (V'/V) dN
             if (TAB == 2) {
                 // time table: the node at n dN; V'/V exactly (the V'/V intervals follow phi)
                 const float u = fmaf((float)n, c.t_scale, c.t_off);
@@ -801,15 +815,16 @@ __device__ __forceinline__ void lanes_fp32(const Inst &I, const RunArgs &R, cons
                 t = t0;
                 r = drift_exact();
             }
-            float a = c.a;
+            float a = 0.0f;       // the learned amplitude
             int cell = 0;
             float f0 = 0.0f, f1 = 0.0f;
             if (BIAS == kBiasMlp) a = grid_amp32(gc, l_grid, xh, ph, cell, f0, f1);
-            const float noise = S * z[j];                 // z is xi sqrt(dN)
-            const float aS = a * S;
-            const float dx = fmaf(ph + aS, c.dN, noise);
-            const float drift = fmaf(-0.5f * ph, ph, 3.0f) * (ph + r);
-            const float dpi = fmaf(t, fmaf(aS, c.dN, noise), -drift * c.dN);
+            // Bn = a S dN + S xi sqrt(dN): the bias and noise increments of phi (a constant bias
+            // rides in z = xi sqrt(dN) + a dN; the learned one is added here, z = xi sqrt(dN))
+            const float Bn = (BIAS == kBiasMlp) ? fmaf(a * S, c.dN, S * z[j]) : S * z[j];
+            const float dx = fmaf(ph, c.dN, Bn);
+            const float drift_dN = fmaf(-0.5f * ph, ph, 3.0f) * fmaf(ph, c.dN, r);
+            const float dpi = fmaf(t, Bn, -drift_dN);
             if (BIAS == kBiasConst) {
                 if (ALLPOS) {
                     zacc += z[j];
@@ -836,16 +851,18 @@ __device__ __forceinline__ void lanes_fp32(const Inst &I, const RunArgs &R, cons
             // eps_1 = pi^2/2 >= 1: |pi| >= the float just above sqrt(2) (no float lies between
             // sqrt(2) and it, so this is pi^2 >= 2 for float pi)
             const bool ended = fabsf(ph) >= 0x1.6a09e8p+0f;
-            if (live && (crossed || ended)) {
+            // live and fresh are updated outside the branch, so that they stay lane masks
+            const bool hit = live && (crossed || ended);
+            if (hit) {
                 ev_status = crossed ? 0u : kFlagEndedEarly;
                 ev_n = n + 1;
                 const double x0 = (double)x0h + (double)x0l;
                 const double x1 = (double)xh + (double)xl;
                 ev_N = crossed ? (double)n * dN + dN * (x0 / (x0 - x1)) : (double)(n + 1) * dN;
                 ev_lnw = lnw_now(n + 1);
-                live = false;
-                fresh = true;
             }
+            live = live && !hit;
+            fresh = fresh || hit;
             n += 1;
         }
         if (BIAS == kBiasMlp) lnw -= (double)zacc;
@@ -875,8 +892,9 @@ __device__ __forceinline__ void lanes_fp32(const Inst &I, const RunArgs &R, cons
             uint32_t w[4];
             philox4x32_10(n >> 2, (uint32_t)tr, (uint32_t)(tr >> 32), I.instance, R.key0, R.key1, w);
             float z[4];
-            box_muller32(w[0], w[1], c.sqrt_dN, z[0], z[1]);
-            box_muller32(w[2], w[3], c.sqrt_dN, z[2], z[3]);
+            const float off = (BIAS == kBiasConst) ? c.adN : 0.0f;
+            box_muller32(w[0], w[1], c.sqrt_dN, off, z[0], z[1]);
+            box_muller32(w[2], w[3], c.sqrt_dN, off, z[2], z[3]);
             if (__any(live && n + 4 > I.max_steps)) group(std::integral_constant<bool, true>(), z);
             else group(std::integral_constant<bool, false>(), z);
         }
@@ -1087,7 +1105,7 @@ __global__ void __launch_bounds__(1024) FPT_EM_OCCUPANCY em_kernel(EmParams p)
     unsigned char *l_grid = l_tab + tab_bytes(PREC, p.inst.n_tab);
     zero_lds_acc(acc);
     if (PREC == 0) stage_table64(p.inst, reinterpret_cast<double2 *>(l_tab));
-    else stage_table32(p.inst, reinterpret_cast<float4 *>(l_tab));
+    else stage_table32(p.inst, reinterpret_cast<float4 *>(l_tab), (float)p.run.dN);
     if (BIAS == kBiasMlp) stage_grid<PREC>(p.inst, l_grid);
     __syncthreads();
     const RetireTo rt = retire_to(p, acc);
@@ -1133,7 +1151,7 @@ __global__ void __launch_bounds__(1024) FPT_EM_OCCUPANCY replay_kernel(ReplayPar
     const int n_nodes = I.g_n0 * I.g_n1;
     for (int i = threadIdx.x; i < n_nodes; i += blockDim.x) l_G[i] = 0.0;
     if (PREC == 0) stage_table64(I, reinterpret_cast<double2 *>(l_tab));
-    else stage_table32(I, reinterpret_cast<float4 *>(l_tab));
+    else stage_table32(I, reinterpret_cast<float4 *>(l_tab), (float)p.run.dN);
     stage_grid<PREC>(I, l_grid);
     __syncthreads();
     RetireTo rt{};
@@ -1184,7 +1202,7 @@ __global__ void __launch_bounds__(1024) FPT_EM_OCCUPANCY batch_kernel(const Inst
         unsigned char *l_tab = smem + align16(acc_bytes(max_bins));
         zero_lds_acc(acc);
         if (PREC == 0) stage_table64(I, reinterpret_cast<double2 *>(l_tab));
-        else stage_table32(I, reinterpret_cast<float4 *>(l_tab));
+        else stage_table32(I, reinterpret_cast<float4 *>(l_tab), (float)R.dN);
         __syncthreads();
         RetireTo rt;
         rt.d_N = nullptr;

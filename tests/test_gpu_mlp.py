@@ -103,7 +103,10 @@ def test_fp64_learned_control_srusr_parity():
 @pytest.mark.parametrize("precision", [0, 1])
 def test_constant_network_equals_constant_bias(precision):
     """W3 = 0, b3 = (A, 0): the tabulated control is exactly A, so every trajectory equals the
-    constant-bias one (log-weights up to summation order)."""
+    constant-bias one: in FP64 up to summation order; in FP32 up to rounding, because the
+    constant bias rides in each step's normal (z = xi sqrt(dN) + A dN) while the learned one is
+    added to the phi increment, so the two round differently (8.9e-8 relative in N at most on
+    these 4000 paths; the bar is 2e-6)."""
     A = 1.5
     w = _srusr(4000, 43, W.mlp_constant_init(A, seed=2), precision=precision)
     wc = w.with_(bias_kind=W.BIAS_CONST, A_bias=A, mlp_params=None)
@@ -112,7 +115,7 @@ def test_constant_network_equals_constant_bias(precision):
     (Nc, lc, sc), _ = gpu_run(wc)
     assert np.mean(sm == sc) > 0.999
     same = sm == sc
-    np.testing.assert_allclose(Nm[same], Nc[same], rtol=1e-12 if precision == 0 else 1e-9)
+    np.testing.assert_allclose(Nm[same], Nc[same], rtol=1e-12 if precision == 0 else 2e-6)
     tol = 1e-10 if precision == 0 else 2e-5
     assert np.all(np.abs(lm[same] - lc[same]) <= tol * (1.0 + np.abs(lc[same])))
 
