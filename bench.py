@@ -88,9 +88,9 @@ PEAK_HBM_GBS = 8000.0
 # process (FETCH_SIZE reads 0.5 GiB: x2.0; WRITE_SIZE reads 1 GiB: x1.0).  Valid only for the
 # kernel source it was measured on (hash of the kernel file and its header).
 MEASURED_TRAFFIC = {
-    "source_sha256": "91d1944d42065cbdef7135d4925cbd136d87d7accafccf63c4b719696df033e0",
+    "source_sha256": "84c44a1f3ba1e3c3ba3089546b4e98cd4ea6a68cb3f6f8689b373c3e35ad4f27",
     "workload": "srusr_is_fp32_A2", "n_traj": 100_000_000,
-    "fetch_bytes": 466.375 * 1024 * 2.0, "write_bytes": 2081229.9375 * 1024 * 1.0,
+    "fetch_bytes": 467.5625 * 1024 * 2.0, "write_bytes": 2080563.9375 * 1024 * 1.0,
 }
 
 
@@ -113,16 +113,16 @@ def kernel_source_sha() -> str:
 # 2 FMA + ADD + MUL + TRANS of each precision.  They measure what the compiled kernel executes,
 # beside the operation-by-operation count of the method used for "achieved".
 MEASURED_VALU = {
-    "source_sha256": "91d1944d42065cbdef7135d4925cbd136d87d7accafccf63c4b719696df033e0",
-    "srusr_is_fp32_A2": {"VALUBusy": 142.701, "VALUUtilization": 99.679,
-                         "hw_flops_per_step": {"f32": 42.300, "f64": 0.334},
-                         "insts_per_step": {"FMA_F32": 10.011, "ADD_F32": 13.267, "MUL_F32": 7.007,
-                                            "TRANS_F32": 2.003, "CVT": 2.259, "INT32": 4.796,
+    "source_sha256": "84c44a1f3ba1e3c3ba3089546b4e98cd4ea6a68cb3f6f8689b373c3e35ad4f27",
+    "srusr_is_fp32_A2": {"VALUBusy": 136.304, "VALUUtilization": 99.678,
+                         "hw_flops_per_step": {"f32": 38.297, "f64": 0.334},
+                         "insts_per_step": {"FMA_F32": 10.012, "ADD_F32": 12.266, "MUL_F32": 4.004,
+                                            "TRANS_F32": 2.003, "CVT": 2.259, "INT32": 4.045,
                                             "FMA_F64": 0.026, "ADD_F64": 0.283}},
-    "srusr_bessel_fp64": {"VALUBusy": 95.710, "VALUUtilization": 99.730,
-                          "hw_flops_per_step": {"f32": 0.0, "f64": 63.283},
-                          "insts_per_step": {"FMA_F64": 22.527, "ADD_F64": 4.812, "MUL_F64": 11.897,
-                                             "TRANS_F64": 1.519, "INT32": 4.087, "FMA_F32": 0.0,
+    "srusr_bessel_fp64": {"VALUBusy": 95.329, "VALUUtilization": 99.731,
+                          "hw_flops_per_step": {"f32": 0.0, "f64": 63.133},
+                          "insts_per_step": {"FMA_F64": 22.474, "ADD_F64": 4.801, "MUL_F64": 11.869,
+                                             "TRANS_F64": 1.515, "INT32": 4.077, "FMA_F32": 0.0,
                                              "ADD_F32": 0.0, "MUL_F32": 0.0}},
 }
 # the measured issue ceiling of independent v_fma_f32 chains, wave-instructions per SIMD per cycle
