@@ -671,7 +671,7 @@ struct F32Consts {
     float u_off;               // (phi_end - phi_lo) * inv_h: table coordinate of x = 0
     float inv_h;
     float t_scale, t_off;      // time tables: coordinate n dN inv_h - N_lo inv_h
-    float jmax;                // n_tab - 2
+    float jtop;                // n_tab - 1: the last record (slope 0, V'/V interval NaN)
     float dN, sqrt_dN;
     float adN;                 // constant bias: A dN, the shift carried by each step's normal
 };
@@ -695,7 +695,7 @@ __device__ __forceinline__ F32Consts f32_consts(const Inst &I, const RunArgs &R)
     c.inv_h = (float)I.inv_h;
     c.t_scale = (float)(R.dN * I.inv_h);
     c.t_off = (float)(-I.phi_lo * I.inv_h);
-    c.jmax = (float)(staged_nodes(I) - 2);
+    c.jtop = (float)(staged_nodes(I) - 1);
     c.dN = (float)R.dN;
     c.sqrt_dN = (float)R.sqrt_dN;
     c.adN = (I.bias_kind == kBiasConst) ? (float)(I.A * R.dN) : 0.0f;
@@ -784,19 +784,20 @@ __device__ __forceinline__ void lanes_fp32(const Inst &I, const RunArgs &R, cons
             float S, t, r;        // r = (V'/V) dN
             if (TAB == 2) {
                 // time table: the node at n dN; V'/V exactly (the V'/V intervals follow phi)
-                const float u = fmaf((float)n, c.t_scale, c.t_off);
-                const float jf = __builtin_amdgcn_fmed3f(floorf(u), 0.0f, c.jmax);
-                const float f = __builtin_amdgcn_fmed3f(u - jf, 0.0f, 1.0f);
-                const float4 node = l_tab[(int)jf];
+                const float u = __builtin_amdgcn_fmed3f(fmaf((float)n, c.t_scale, c.t_off), 0.0f, c.jtop);
+                const float f = __builtin_amdgcn_fractf(u);
+                const float4 node = l_tab[(int)u];
                 S = fmaf(f, node.y, node.x);
                 t = fmaf(f, node.w, node.z);
                 r = drift_exact();
             } else if (TAB) {
-                const float u = fmaf(xh, c.inv_h, c.u_off);
-                const float jf = __builtin_amdgcn_fmed3f(floorf(u), 0.0f, c.jmax);
-                const float f = __builtin_amdgcn_fmed3f(u - jf, 0.0f, 1.0f);
-                const float4 node = l_tab[(int)jf];
-                const float2 rn = l_rtab[(int)jf];
+                // the coordinate clamped to [0, n_tab - 1]: its integer part is the record, its
+                // fraction the weight; past the last node the last record (slope 0) gives the
+                // edge value, and its NaN V'/V interval the exact V'/V
+                const float u = __builtin_amdgcn_fmed3f(fmaf(xh, c.inv_h, c.u_off), 0.0f, c.jtop);
+                const float f = __builtin_amdgcn_fractf(u);
+                const float4 node = l_tab[(int)u];
+                const float2 rn = l_rtab[(int)u];
                 S = fmaf(f, node.y, node.x);
                 t = fmaf(f, node.w, node.z);
                 // V'/V interpolated in the interval (error below FP32 resolution); NaN marks the
@@ -895,8 +896,10 @@ __device__ __forceinline__ void lanes_fp32(const Inst &I, const RunArgs &R, cons
             const float off = (BIAS == kBiasConst) ? c.adN : 0.0f;
             box_muller32(w[0], w[1], c.sqrt_dN, off, z[0], z[1]);
             box_muller32(w[2], w[3], c.sqrt_dN, off, z[2], z[3]);
-            if (__any(live && n + 4 > I.max_steps)) group(std::integral_constant<bool, true>(), z);
-            else group(std::integral_constant<bool, false>(), z);
+            if (__builtin_amdgcn_ballot_w64(live && n + 4 > I.max_steps) != 0)
+                group(std::integral_constant<bool, true>(), z);
+            else
+                group(std::integral_constant<bool, false>(), z);
         }
         if (!live) has = false;
         if (claim(!has, rel, cursor, n_traj, exhausted)) {
