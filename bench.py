@@ -56,11 +56,12 @@ METRIC = "trajectory-steps/s and ESS-weighted tail samples/s at 5% P(δN) tail e
 # from the interval table (an interpolation and a NaN test) where the FP64 path
 # computes the reciprocal.  The FP32 step carries the constant bias in the normal
 # (z = xi sqrt(dN) + A dN, the Box-Muller products become FMAs) and V'/V scaled by
-# dN, so its update is B = S z, dphi = pi dN + B, dpi = t B - (3 - pi^2/2)(pi dN + r dN).
-# Per part, FP32 / FP64: Box-Muller (half a pair) 7.5 / 6.5, V'/V 3 / 9, table
-# lookup 11 / 15, the update 11 / 17, ln w 1 / 3, the float-pair accumulation 8 / -,
-# events 5 / 4, per-group bookkeeping 2 / -.
-ALG_FLOPS_PER_STEP = {"fp32": 48.5, "fp64": 54.5}
+# dN, so its update is B = S z, dphi = pi dN + B, dpi = t B - (3 - pi^2/2)(pi dN + r dN);
+# its table coordinate is clamped once and split by truncation and fraction.  Per
+# part, FP32 / FP64: Box-Muller (half a pair) 7.5 / 6.5, V'/V 3 / 9, table lookup
+# 9 / 15, the update 11 / 17, ln w 1 / 3, the float-pair accumulation 8 / -, events
+# 5 / 4, per-group bookkeeping 2 / -.
+ALG_FLOPS_PER_STEP = {"fp32": 46.5, "fp64": 54.5}
 # the tabulated learned control adds its grid coordinates (ln|pi| included), the clamped
 # cell and fractions, the bilinear interpolation and the per-step dA = a xi sqrt(dN) + a^2 dN/2
 # (31); in FP32 also a S and its separate FMA into the increment (3), less the offset of the
@@ -77,7 +78,7 @@ ALG_FLOPS_BUMP_FP64 = 54.5 - 9.0 + 22.0
 # FP32 state on a time-indexed table: V'/V exactly (phi - phi_T from the float pair, 3; the branch's
 # compare, 1; the FMA, 2; the reciprocal, 1) in place of its interpolation and NaN test (3); the last
 # node is zero, so the weight tests S > 0 (1)
-ALG_FLOPS_TIME_FP32 = 48.5 - 3.0 + 7.0 + 1.0
+ALG_FLOPS_TIME_FP32 = 46.5 - 3.0 + 7.0 + 1.0
 ALG_INT_OPS_PER_STEP = 16.0          # Philox4x32-10 amortised over 4 steps + uniform conversions
 PEAK_TFLOPS = {"fp32": 157.3, "fp64": 78.6}   # MI355X published vector peaks
 PEAK_HBM_GBS = 8000.0
@@ -88,9 +89,9 @@ PEAK_HBM_GBS = 8000.0
 # process (FETCH_SIZE reads 0.5 GiB: x2.0; WRITE_SIZE reads 1 GiB: x1.0).  Valid only for the
 # kernel source it was measured on (hash of the kernel file and its header).
 MEASURED_TRAFFIC = {
-    "source_sha256": "84c44a1f3ba1e3c3ba3089546b4e98cd4ea6a68cb3f6f8689b373c3e35ad4f27",
+    "source_sha256": "85ad907ae402cf5c854863262fe1841f435a641e4434fc90b2271640e80256e9",
     "workload": "srusr_is_fp32_A2", "n_traj": 100_000_000,
-    "fetch_bytes": 467.5625 * 1024 * 2.0, "write_bytes": 2080563.9375 * 1024 * 1.0,
+    "fetch_bytes": 466.5625 * 1024 * 2.0, "write_bytes": 2079894.53125 * 1024 * 1.0,
 }
 
 
@@ -113,16 +114,16 @@ def kernel_source_sha() -> str:
 # 2 FMA + ADD + MUL + TRANS of each precision.  They measure what the compiled kernel executes,
 # beside the operation-by-operation count of the method used for "achieved".
 MEASURED_VALU = {
-    "source_sha256": "84c44a1f3ba1e3c3ba3089546b4e98cd4ea6a68cb3f6f8689b373c3e35ad4f27",
-    "srusr_is_fp32_A2": {"VALUBusy": 136.304, "VALUUtilization": 99.678,
-                         "hw_flops_per_step": {"f32": 38.297, "f64": 0.334},
-                         "insts_per_step": {"FMA_F32": 10.012, "ADD_F32": 12.266, "MUL_F32": 4.004,
+    "source_sha256": "85ad907ae402cf5c854863262fe1841f435a641e4434fc90b2271640e80256e9",
+    "srusr_is_fp32_A2": {"VALUBusy": 136.619, "VALUUtilization": 99.672,
+                         "hw_flops_per_step": {"f32": 37.294, "f64": 0.334},
+                         "insts_per_step": {"FMA_F32": 10.011, "ADD_F32": 11.264, "MUL_F32": 4.004,
                                             "TRANS_F32": 2.003, "CVT": 2.259, "INT32": 4.045,
                                             "FMA_F64": 0.026, "ADD_F64": 0.283}},
-    "srusr_bessel_fp64": {"VALUBusy": 95.329, "VALUUtilization": 99.731,
-                          "hw_flops_per_step": {"f32": 0.0, "f64": 63.133},
-                          "insts_per_step": {"FMA_F64": 22.474, "ADD_F64": 4.801, "MUL_F64": 11.869,
-                                             "TRANS_F64": 1.515, "INT32": 4.077, "FMA_F32": 0.0,
+    "srusr_bessel_fp64": {"VALUBusy": 95.789, "VALUUtilization": 99.732,
+                          "hw_flops_per_step": {"f32": 0.0, "f64": 63.160},
+                          "insts_per_step": {"FMA_F64": 22.484, "ADD_F64": 4.803, "MUL_F64": 11.874,
+                                             "TRANS_F64": 1.516, "INT32": 4.079, "FMA_F32": 0.0,
                                              "ADD_F32": 0.0, "MUL_F32": 0.0}},
 }
 # the measured issue ceiling of independent v_fma_f32 chains, wave-instructions per SIMD per cycle
