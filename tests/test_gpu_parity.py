@@ -243,6 +243,32 @@ def test_fp32_state_coupled_with_oracle(A_bias):
         assert ess > 500 and ksw < 10.0 / ess and rel < 1e-2
 
 
+def test_fp32_state_past_both_table_edges():
+    """A phi table that ends inside the trajectories' range on both sides (2048 dyadic nodes over
+    [-2600, -553] 2^-16, while the runs go from phi_in = 0 to phi_end = -0.0486): each path starts
+    above the last node and ends below the first, where the FP32 step clamps its coordinate to
+    the last or first record and computes V'/V exactly.  Per trajectory against the FP64 oracle
+    on the same streams, constant bias A = 2, 4000 trajectories, with the bars of the coupled
+    FP32 test."""
+    lo = -2600 * 2.0 ** -16
+    w = W.srusr_bessel(seed=17).with_(precision=1, bias_kind=W.BIAS_CONST, A_bias=2.0, table_n=2048,
+                                      table_lo=lo, table_hi=lo + 2047 * 2.0 ** -16)
+    assert w.phi_in > w.table_hi and w.phi_end < w.table_lo
+    n = 4000
+    say(f"fp32 past both table edges n={n}")
+    (Ng, lg, sg), _ = gpu_run(w, n_traj=n)
+    No, lo_, so = oracle_run(w, n_traj=n)
+    flags = orc.FLAG_CENSORED | orc.FLAG_ENDED_EARLY
+    assert np.all((sg & flags) == 0) and np.all((so & flags) == 0)
+    dn = Ng - No
+    same = sg == so
+    dl = np.abs(lg - lo_)[same]
+    say(f"  N32 - N64: median {np.median(dn):.3e}, max |.| {np.abs(dn).max():.3e}; same step {same.mean():.4f}; "
+        f"|dlnw| median {np.median(dl):.2e} max {dl.max():.2e}")
+    assert abs(np.median(dn)) < 2e-5 and np.mean(np.abs(dn) < 1e-4) > 0.99
+    assert same.mean() > 0.95 and np.median(dl) < 1e-5 and dl.max() < 1e-3
+
+
 @pytest.mark.parametrize("A_bias", [0.0, 2.0])
 def test_fp32_state_vs_fp64_path_at_scale(A_bias):
     """1e6 coupled trajectories: FP32-state path vs the FP64 path (itself at per-trajectory parity
