@@ -589,9 +589,12 @@ __device__ __forceinline__ void lanes_fp64(const Inst &I, const RunArgs &R, cons
             if (BIAS == kBiasMlp) a = grid_amp64(gc, l_grid, phi, pi_, cell, f0, f1);
             const double zs = z[j];                       // xi sqrt(dN)
             const double noise = S * zs;
+            // without a bias the amplitude is a literal 0, which IEEE arithmetic does not fold away:
+            // the terms are left out instead (the same values, up to the sign of a zero)
             const double aS = a * S;
-            const double phi_n = phi + (pi_ + aS) * dN + noise;
-            const double pi_n = pi_ - (3.0 - 0.5 * pi_ * pi_) * (pi_ + r) * dN + t * (aS * dN + noise);
+            const double phi_n = (BIAS == kBiasNone) ? phi + pi_ * dN + noise : phi + (pi_ + aS) * dN + noise;
+            const double drift_pi = pi_ - (3.0 - 0.5 * pi_ * pi_) * (pi_ + r) * dN;
+            const double pi_n = (BIAS == kBiasNone) ? drift_pi + t * noise : drift_pi + t * (aS * dN + noise);
             if (BIAS == kBiasConst) {
                 if (ALLPOS) {
                     lnw -= a * zs + half_a2_dN;
@@ -994,10 +997,14 @@ __device__ __forceinline__ void lanes_fp64_2d(const Inst &I, const RunArgs &R, c
             const double z1 = z[2 * j], z2 = z[2 * j + 1];          // xi sqrt(dN)
             const double noise_phi = S.Spp * z1 + S.Spq * z2;
             const double noise_pi = S.Spq * z1 + S.Sqq * z2;
+            // without a bias the amplitude is a literal 0, which IEEE arithmetic does not fold away:
+            // the terms are left out instead (the same values, up to the sign of a zero)
             const double B_phi = a * (S.Spp * S.e1 + S.Spq * S.e2);
             const double B_pi = a * (S.Spq * S.e1 + S.Sqq * S.e2);
-            const double phi_n = phi + (pi_ + B_phi) * dN + noise_phi;
-            const double pi_n = pi_ - (3.0 - 0.5 * pi_ * pi_) * (pi_ + r) * dN + B_pi * dN + noise_pi;
+            const double phi_n =
+                (BIAS == kBiasNone) ? phi + pi_ * dN + noise_phi : phi + (pi_ + B_phi) * dN + noise_phi;
+            const double drift_pi = pi_ - (3.0 - 0.5 * pi_ * pi_) * (pi_ + r) * dN;
+            const double pi_n = (BIAS == kBiasNone) ? drift_pi + noise_pi : drift_pi + B_pi * dN + noise_pi;
             if (BIAS != kBiasNone) {
                 const double dA = a * (S.e1 * z1 + S.e2 * z2) + half_a2_dN * (S.e1 * S.e1 + S.e2 * S.e2);
                 if (ALLPOS) lnw -= dA;
