@@ -56,23 +56,66 @@ __device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c)
     return d;
 }
 
-__device__ __forceinline__ void philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
-                                              uint32_t k0, uint32_t k1, uint32_t w[4])
+// Philox4x32-10 (Salmon et al., SC'11): ten rounds on the counter (c0, c1, c2, c3) with the key
+// (k0, k1); a round forms the 64-bit products M0 c0 and M1 c2 and maps the counter to
+// (hi(M1 c2) ^ c1 ^ k0, lo(M1 c2), hi(M0 c0) ^ c3 ^ k1, lo(M0 c0)), then adds the Weyl
+// increments (W0, W1) to the key.  Here the counter is (m, traj lo, traj hi, instance) for a fixed
+// trajectory, key and instance word, and only the call index m varies.  Of the first two rounds,
+// every product that does not involve m is a per-trajectory constant: round 1 multiplies the
+// trajectory's high word, round 2 the word that round 1 forms from the trajectory's low word and
+// the key.  They are computed once when a lane takes a trajectory (philox_pre), which leaves
+// rounds 1 and 2 one multiply each.
+struct PhiloxPre {
+    uint32_t a1;    // round 1 output word 0: hi(M1 thi) ^ tlo ^ k0
+    uint32_t b1k;   // round 1 output word 1, lo(M1 thi), with round 2's key word 0 folded in
+    uint32_t h2k;   // hi(M0 a1) with round 2's key word 1 folded in
+    uint32_t l2;    // lo(M0 a1): round 2 output word 3
+};
+
+__device__ __forceinline__ PhiloxPre philox_pre(uint64_t traj, uint32_t k0, uint32_t k1)
 {
+    const uint64_t p1 = (uint64_t)kPhiloxM1 * (uint32_t)(traj >> 32);
+    PhiloxPre q;
+    q.a1 = (uint32_t)(p1 >> 32) ^ (uint32_t)traj ^ k0;
+    q.b1k = (uint32_t)p1 ^ (k0 + kPhiloxW0);
+    const uint64_t p2 = (uint64_t)kPhiloxM0 * q.a1;
+    q.h2k = (uint32_t)(p2 >> 32) ^ (k1 + kPhiloxW1);
+    q.l2 = (uint32_t)p2;
+    return q;
+}
+
+// The four output words for call m from the trajectory's PhiloxPre; ik = instance ^ k1
+// (wave-uniform).
+__device__ __forceinline__ void philox_call(uint32_t m, const PhiloxPre &q, uint32_t ik, uint32_t k0, uint32_t k1,
+                                            uint32_t w[4])
+{
+    // round 1: (m, tlo, thi, inst) -> (a1, lo(M1 thi), hi(M0 m) ^ inst ^ k1, lo(M0 m))
+    const uint64_t p0 = (uint64_t)kPhiloxM0 * m;
+    const uint32_t c2 = (uint32_t)(p0 >> 32) ^ ik;
+    const uint32_t c3 = (uint32_t)p0;
+    // round 2: (a1, b1, c2, c3) -> (hi(M1 c2) ^ b1 ^ k0', lo(M1 c2), hi(M0 a1) ^ c3 ^ k1', lo(M0 a1))
+    const uint64_t p1 = (uint64_t)kPhiloxM1 * c2;
+    uint32_t d0 = (uint32_t)(p1 >> 32) ^ q.b1k;
+    uint32_t d1 = (uint32_t)p1;
+    uint32_t d2 = q.h2k ^ c3;
+    uint32_t d3 = q.l2;
+    k0 += 2u * kPhiloxW0;
+    k1 += 2u * kPhiloxW1;
+    // rounds 3 .. 10
 #pragma unroll
-    for (int r = 0; r < 10; ++r) {
-        const uint64_t p0 = (uint64_t)kPhiloxM0 * c0;
-        const uint64_t p1 = (uint64_t)kPhiloxM1 * c2;
-        const uint32_t n0 = xor3((uint32_t)(p1 >> 32), c1, k0);
-        const uint32_t n2 = xor3((uint32_t)(p0 >> 32), c3, k1);
-        c1 = (uint32_t)p1;
-        c3 = (uint32_t)p0;
-        c0 = n0;
-        c2 = n2;
+    for (int r = 2; r < 10; ++r) {
+        const uint64_t a = (uint64_t)kPhiloxM0 * d0;
+        const uint64_t b = (uint64_t)kPhiloxM1 * d2;
+        const uint32_t n0 = xor3((uint32_t)(b >> 32), d1, k0);
+        const uint32_t n2 = xor3((uint32_t)(a >> 32), d3, k1);
+        d1 = (uint32_t)b;
+        d3 = (uint32_t)a;
+        d0 = n0;
+        d2 = n2;
         k0 += kPhiloxW0;
         k1 += kPhiloxW1;
     }
-    w[0] = c0; w[1] = c1; w[2] = c2; w[3] = c3;
+    w[0] = d0; w[1] = d1; w[2] = d2; w[3] = d3;
 }
 
 // Box-Muller in FP64 on uniforms u = (w + 1/2) 2^-32 (exact in double), table-driven: two
@@ -145,21 +188,6 @@ __device__ __forceinline__ void box_muller64(uint32_t wa, uint32_t wb, double sq
     const double2 sc = l_bm[wb >> 24];
     za = rho * fma(sc.y, cs, -sc.x * sn);      // cos(A + theta)
     zb = rho * fma(sc.x, cs, sc.y * sn);       // sin(A + theta)
-}
-
-// Box-Muller in FP32 on uniforms fl32(w) 2^-32 + 2^-33: the same uniform as the
-// FP64 path, rounded to 24 significant bits (relative, not absolute, resolution,
-// so the radius stays accurate for small u).  Never 0; at most 1.0f, where the
-// radius is 0.  v_log_f32 returns log2, v_sin_f32 / v_cos_f32 take turns.
-// Returns xi sqrt(dN) + off for the two steps of the pair.
-__device__ __forceinline__ void box_muller32(uint32_t wa, uint32_t wb, float sqrt_dN, float off, float &za, float &zb)
-{
-    const float ua = fmaf((float)wa, 0x1p-32f, 0x1p-33f);
-    const float ub = fmaf((float)wb, 0x1p-32f, 0x1p-33f);
-    const float m2lnu = fmaxf(-1.3862943611198906f * __builtin_amdgcn_logf(ua), 0.0f);  // -2 ln u
-    const float rho = __builtin_amdgcn_sqrtf(m2lnu) * sqrt_dN;
-    za = fmaf(rho, __builtin_amdgcn_cosf(ub), off);
-    zb = fmaf(rho, __builtin_amdgcn_sinf(ub), off);
 }
 
 // Copy a wave-uniform value into a VGPR once, so that a per-lane select between
@@ -352,8 +380,8 @@ __device__ __forceinline__ void stage_table64(const Inst &I, double2 *l_tab)
 }
 
 // FP32 staging: the noise nodes, then the V'/V intervals right after them,
-// scaled by the time step (the step uses (V'/V) dN); all NaN for a single-node
-// table, so that V'/V is computed exactly there.
+// scaled by half the time step (the step uses (V'/V) dN/2); all NaN for a
+// single-node table, so that V'/V is computed exactly there.
 __device__ __forceinline__ void stage_table32(const Inst &I, float4 *l_tab, float dN)
 {
     const int n = staged_nodes(I);
@@ -364,8 +392,8 @@ __device__ __forceinline__ void stage_table32(const Inst &I, float4 *l_tab, floa
         float2 r = make_float2(nan, nan);
         if (I.n_tab > 1) {
             r = I.rtab32[i];
-            r.x *= dN;
-            r.y *= dN;
+            r.x *= 0.5f * dN;
+            r.y *= 0.5f * dN;
         }
         l_r[i] = r;
     }
@@ -545,6 +573,8 @@ __device__ __forceinline__ void lanes_fp64(const Inst &I, const RunArgs &R, cons
         traj = rp.tail[rel].traj;
         ww = rp.tail[rel].ww;
     }
+    const uint32_t ik = I.instance ^ R.key1;
+    PhiloxPre pre = philox_pre(GRAD ? traj : traj_offset + rel, R.key0, R.key1);
 
     auto group = [&](auto censor_tag, const double z[4]) {
         constexpr bool CENSOR = decltype(censor_tag)::value;
@@ -640,9 +670,8 @@ __device__ __forceinline__ void lanes_fp64(const Inst &I, const RunArgs &R, cons
     while (__any(has)) {
         for (int k = 0; k < R.chunk; k += 4) {
             if (!__any(live)) break;
-            const uint64_t tr = GRAD ? traj : traj_offset + rel;
             uint32_t w[4];
-            philox4x32_10(n >> 2, (uint32_t)tr, (uint32_t)(tr >> 32), I.instance, R.key0, R.key1, w);
+            philox_call(n >> 2, pre, ik, R.key0, R.key1, w);
             double z[4];
             box_muller64(w[0], w[1], sqrt_dN, l_bm, z[0], z[1]);
             box_muller64(w[2], w[3], sqrt_dN, l_bm, z[2], z[3]);
@@ -661,21 +690,28 @@ __device__ __forceinline__ void lanes_fp64(const Inst &I, const RunArgs &R, cons
                 traj = rp.tail[rel].traj;
                 ww = rp.tail[rel].ww;
             }
+            pre = philox_pre(GRAD ? traj : traj_offset + rel, R.key0, R.key1);
         }
     }
 }
 
 // ---------------------------------------------------------------------------
-// FP32 state: x = phi - phi_end and pi as float pairs (hi + lo).
+// FP32 state: x = phi - phi_end and pi each as an unevaluated pair of floats
+// hi + lo.  A step adds its increment to the low word only (lo += dx) and
+// reads the state as the rounded sum hi + lo; once per group of four steps the
+// pair is renormalised (Fast2Sum of hi and lo).  Against an exact two-sum per
+// step this leaves one rounding of the low word per step, at the scale of
+// ulp(4 increments), far below the FP32 resolution of the state itself.
 // ---------------------------------------------------------------------------
 struct F32Consts {
     float xT_hi, xT_lo;        // phi_T - phi_end as a float pair
-    float kx, s_plus, s_minus; // (V'/V) dN = 1/(kx (phi - phi_T) + s), s = s_plus (phi >= phi_T) or s_minus
+    float kx, s_plus, s_minus; // (V'/V) dN/2 = 1/(kx (phi - phi_T) + s), s = s_plus (phi >= phi_T) or s_minus
     float u_off;               // (phi_end - phi_lo) * inv_h: table coordinate of x = 0
     float inv_h;
     float t_scale, t_off;      // time tables: coordinate n dN inv_h - N_lo inv_h
     float jtop;                // n_tab - 1: the last record (slope 0, V'/V interval NaN)
-    float dN, sqrt_dN;
+    float dN, half_dN;
+    float m2ln2_dN;            // -2 ln 2 dN: rho = sqrt(log2(u) m2ln2_dN) = sqrt(-2 ln u) sqrt(dN)
     float adN;                 // constant bias: A dN, the shift carried by each step's normal
 };
 
@@ -685,14 +721,14 @@ __device__ __forceinline__ F32Consts f32_consts(const Inst &I, const RunArgs &R)
     const double xT = I.phi_T - I.phi_end;
     c.xT_hi = (float)xT;
     c.xT_lo = (float)(xT - (double)c.xT_hi);
-    const double inv_dN = 1.0 / R.dN;
+    const double two_over_dN = 2.0 / R.dN;
     if (I.pot_kind == kPotExponential) {
         c.kx = 0.0f;
-        c.s_plus = c.s_minus = (float)(inv_dN / I.A_plus);
+        c.s_plus = c.s_minus = (float)(two_over_dN / I.A_plus);
     } else {
-        c.kx = (float)inv_dN;
-        c.s_plus = (float)(I.V0 / I.A_plus * inv_dN);
-        c.s_minus = (float)(I.V0 / I.A_minus * inv_dN);
+        c.kx = (float)two_over_dN;
+        c.s_plus = (float)(I.V0 / I.A_plus * two_over_dN);
+        c.s_minus = (float)(I.V0 / I.A_minus * two_over_dN);
     }
     c.u_off = (float)((I.phi_end - I.phi_lo) * I.inv_h);
     c.inv_h = (float)I.inv_h;
@@ -700,18 +736,24 @@ __device__ __forceinline__ F32Consts f32_consts(const Inst &I, const RunArgs &R)
     c.t_off = (float)(-I.phi_lo * I.inv_h);
     c.jtop = (float)(staged_nodes(I) - 1);
     c.dN = (float)R.dN;
-    c.sqrt_dN = (float)R.sqrt_dN;
+    c.half_dN = (float)(0.5 * R.dN);
+    c.m2ln2_dN = (float)(-2.0 * 0.69314718055994531 * R.dN);
     c.adN = (I.bias_kind == kBiasConst) ? (float)(I.A * R.dN) : 0.0f;
     return c;
 }
 
-__device__ __forceinline__ void two_sum_fast(float &hi, float &lo, float d)
+// Box-Muller in FP32 on uniforms fl32(w) 2^-32 + 2^-33: the same uniform as the
+// FP64 path, rounded to 24 significant bits (relative, not absolute, resolution,
+// so the radius stays accurate for small u).  Never 0; at most 1.0f, where
+// log2 gives 0 and the radius -0 or 0.  v_log_f32 returns log2, v_sin_f32 /
+// v_cos_f32 take turns.  Returns xi sqrt(dN) + off for the two steps of the pair.
+__device__ __forceinline__ void box_muller32(uint32_t wa, uint32_t wb, float m2ln2_dN, float off, float &za, float &zb)
 {
-    // hi + lo += d with |hi| >= |d| (Fast2Sum of hi and d, error folded into lo)
-    const float s = hi + d;
-    const float e = d - (s - hi);
-    hi = s;
-    lo += e;
+    const float ua = fmaf((float)wa, 0x1p-32f, 0x1p-33f);
+    const float ub = fmaf((float)wb, 0x1p-32f, 0x1p-33f);
+    const float rho = __builtin_amdgcn_sqrtf(__builtin_amdgcn_logf(ua) * m2ln2_dN);
+    za = fmaf(rho, __builtin_amdgcn_cosf(ub), off);
+    zb = fmaf(rho, __builtin_amdgcn_sinf(ub), off);
 }
 
 template <int BIAS, int TAB, bool ALLPOS, bool GRAD>
@@ -730,14 +772,16 @@ __device__ __forceinline__ void lanes_fp32(const Inst &I, const RunArgs &R, cons
     const double dN = R.dN;
     const double A = (BIAS == kBiasConst) ? I.A : 0.0;
     const double half_a2_dN = 0.5 * A * A * dN;
-    const float half_dN = 0.5f * c.dN;
     const float s_plus = in_vgpr(c.s_plus), s_minus = in_vgpr(c.s_minus);
+    const uint32_t ik = I.instance ^ R.key1;
 
     bool exhausted = false;
     uint64_t rel = 0;
     bool has = claim(true, rel, cursor, n_traj, exhausted);
     bool live = has;          // has a trajectory that has not ended yet
+    // state: x = xh + xl, pi = ph + pl; xs, ps their rounded sums (what a step reads)
     float xh = x_in_hi, xl = x_in_lo, ph = pi_in_hi, pl = pi_in_lo;
+    float xs = x_in_hi, ps = pi_in_hi;
     double zsum = 0.0;        // constant bias: sum of z = xi sqrt(dN) + a dN over steps with S > 0
     uint32_t n_on = 0;        // constant bias: number of such steps (counted only when some node has S = 0)
     double lnw = 0.0;         // learned bias: ln w up to the current group
@@ -750,6 +794,7 @@ __device__ __forceinline__ void lanes_fp32(const Inst &I, const RunArgs &R, cons
         traj = rp.tail[rel].traj;
         ww = rp.tail[rel].ww;
     }
+    PhiloxPre pre = philox_pre(GRAD ? traj : traj_offset + rel, R.key0, R.key1);
 
     // constant bias: each step's normal carries the drift shift, z = xi sqrt(dN) + c.adN with
     // c.adN = fl32(A dN), so the exponent of eq. (weight_A) in 1D over k steps,
@@ -763,7 +808,7 @@ __device__ __forceinline__ void lanes_fp32(const Inst &I, const RunArgs &R, cons
         constexpr bool CENSOR = decltype(censor_tag)::value;
         float zacc = 0.0f;        // constant bias: sum of this group's xi sqrt(dN); learned: of its dA
         bool fresh = false;
-        uint32_t ev_status, ev_n;   // written before use: read only where fresh is set
+        uint32_t ev_code;         // written before use: read only where fresh is set
         double ev_N, ev_lnw;
         auto lnw_now = [&](uint32_t steps) -> double {
             if (BIAS == kBiasMlp) return lnw - (double)zacc;
@@ -771,23 +816,22 @@ __device__ __forceinline__ void lanes_fp32(const Inst &I, const RunArgs &R, cons
         };
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-            if (CENSOR && live && n == I.max_steps) {
-                ev_status = kFlagCensored;
-                ev_n = n;
+            if (CENSOR && live && n + j == I.max_steps) {
+                ev_code = (n + j) | kFlagCensored;
                 ev_N = __builtin_nan("");
-                ev_lnw = lnw_now(n);
+                ev_lnw = lnw_now(n + j);
                 live = false;
                 fresh = true;
             }
-            // (V'/V) dN exactly: 1/(kx (phi - phi_T) + s), phi - phi_T = (xh - xT_hi) + (xl - xT_lo)
+            // (V'/V) dN/2 exactly: 1/(kx (phi - phi_T) + s), phi - phi_T = (xh - xT_hi) + (xl - xT_lo)
             auto drift_exact = [&]() -> float {
                 const float dT = (xh - c.xT_hi) + (xl - c.xT_lo);
                 return __builtin_amdgcn_rcpf(fmaf(dT, c.kx, (dT >= 0.0f) ? s_plus : s_minus));
             };
-            float S, t, r;        // r = (V'/V) dN
+            float S, t, r;        // r = (V'/V) dN/2
             if (TAB == 2) {
                 // time table: the node at n dN; V'/V exactly (the V'/V intervals follow phi)
-                const float u = __builtin_amdgcn_fmed3f(fmaf((float)n, c.t_scale, c.t_off), 0.0f, c.jtop);
+                const float u = __builtin_amdgcn_fmed3f(fmaf((float)(n + j), c.t_scale, c.t_off), 0.0f, c.jtop);
                 const float f = __builtin_amdgcn_fractf(u);
                 const float4 node = l_tab[(int)u];
                 S = fmaf(f, node.y, node.x);
@@ -797,7 +841,7 @@ __device__ __forceinline__ void lanes_fp32(const Inst &I, const RunArgs &R, cons
                 // the coordinate clamped to [0, n_tab - 1]: its integer part is the record, its
                 // fraction the weight; past the last node the last record (slope 0) gives the
                 // edge value, and its NaN V'/V interval the exact V'/V
-                const float u = __builtin_amdgcn_fmed3f(fmaf(xh, c.inv_h, c.u_off), 0.0f, c.jtop);
+                const float u = __builtin_amdgcn_fmed3f(fmaf(xs, c.inv_h, c.u_off), 0.0f, c.jtop);
                 const float f = __builtin_amdgcn_fractf(u);
                 const float4 node = l_tab[(int)u];
                 const float2 rn = l_rtab[(int)u];
@@ -822,23 +866,23 @@ __device__ __forceinline__ void lanes_fp32(const Inst &I, const RunArgs &R, cons
             float a = 0.0f;       // the learned amplitude
             int cell = 0;
             float f0 = 0.0f, f1 = 0.0f;
-            if (BIAS == kBiasMlp) a = grid_amp32(gc, l_grid, xh, ph, cell, f0, f1);
+            if (BIAS == kBiasMlp) a = grid_amp32(gc, l_grid, xs, ps, cell, f0, f1);
             // Bn = a S dN + S xi sqrt(dN): the bias and noise increments of phi (a constant bias
             // rides in z = xi sqrt(dN) + a dN; the learned one is added here, z = xi sqrt(dN))
             const float Bn = (BIAS == kBiasMlp) ? fmaf(a * S, c.dN, S * z[j]) : S * z[j];
-            const float dx = fmaf(ph, c.dN, Bn);
-            const float drift_dN = fmaf(-0.5f * ph, ph, 3.0f) * fmaf(ph, c.dN, r);
-            const float dpi = fmaf(t, Bn, -drift_dN);
+            const float dx = fmaf(ps, c.dN, Bn);
+            // dpi = -(3 - pi^2/2)(pi + V'/V) dN + t Bn = (pi^2 - 6)(pi dN/2 + (V'/V) dN/2) + t Bn
+            const float dpi = fmaf(fmaf(ps, ps, -6.0f), fmaf(ps, c.half_dN, r), t * Bn);
             if (BIAS == kBiasConst) {
                 if (ALLPOS) {
-                    zacc += z[j];
+                    zacc = (j == 0) ? z[0] : zacc + z[j];
                 } else {
                     const bool on = S > 0.0f;
                     zacc += on ? z[j] : 0.0f;
                     n_on += on ? 1u : 0u;
                 }
             } else if (BIAS == kBiasMlp) {
-                const float dA = fmaf(a, z[j], a * a * half_dN);
+                const float dA = fmaf(a, z[j], a * a * (0.5f * c.dN));
                 zacc += (ALLPOS || S > 0.0f) ? dA : 0.0f;
             }
             if (GRAD && live) {
@@ -848,57 +892,57 @@ __device__ __forceinline__ void lanes_fp32(const Inst &I, const RunArgs &R, cons
                 }
                 grad_add(g_s, (ALLPOS || S > 0.0f) ? -z[j] : 0.0f, f0, f1);
             }
-            const float x0h = xh, x0l = xl;
-            two_sum_fast(xh, xl, dx);
-            two_sum_fast(ph, pl, dpi);
-            const bool crossed = xh + xl <= 0.0f;
+            const float x0l = xl;
+            xl += dx;
+            pl += dpi;
+            xs = xh + xl;
+            ps = ph + pl;
+            const bool crossed = xs <= 0.0f;
             // eps_1 = pi^2/2 >= 1: |pi| >= the float just above sqrt(2) (no float lies between
             // sqrt(2) and it, so this is pi^2 >= 2 for float pi)
-            const bool ended = fabsf(ph) >= 0x1.6a09e8p+0f;
+            const bool ended = fabsf(ps) >= 0x1.6a09e8p+0f;
             // live and fresh are updated outside the branch, so that they stay lane masks
             const bool hit = live && (crossed || ended);
             if (hit) {
-                ev_status = crossed ? 0u : kFlagEndedEarly;
-                ev_n = n + 1;
-                const double x0 = (double)x0h + (double)x0l;
+                const bool cr = xs <= 0.0f;
+                ev_code = (n + j + 1) | (cr ? 0u : kFlagEndedEarly);
+                const double x0 = (double)xh + (double)x0l;
                 const double x1 = (double)xh + (double)xl;
-                ev_N = crossed ? (double)n * dN + dN * (x0 / (x0 - x1)) : (double)(n + 1) * dN;
-                ev_lnw = lnw_now(n + 1);
+                ev_N = cr ? (double)(n + j) * dN + dN * (x0 / (x0 - x1)) : (double)(n + j + 1) * dN;
+                ev_lnw = lnw_now(n + j + 1);
             }
             live = live && !hit;
             fresh = fresh || hit;
-            n += 1;
         }
+        n += 4;
         if (BIAS == kBiasMlp) lnw -= (double)zacc;
         else zsum += (double)zacc;
         if (fresh) {
             if (GRAD) {
                 grad_flush(rp, gc.n1c, g_cell, g_s, ww);
                 g_cell = -1;
-                if (ev_status != 0u) atomicAdd(rp.mismatch, 1ull);
+                if ((ev_code & ~kStepMask) != 0u) atomicAdd(rp.mismatch, 1ull);
             } else {
-                retire(rt, rel, ev_status, ev_n, ev_N, ev_lnw);
+                retire(rt, rel, ev_code & ~kStepMask, ev_code & kStepMask, ev_N, ev_lnw);
             }
         }
-        // renormalise the pairs once per group
-        const float s = xh + xl;
-        xl = xl - (s - xh);
-        xh = s;
-        const float q = ph + pl;
-        pl = pl - (q - ph);
-        ph = q;
+        // renormalise the pairs once per group (Fast2Sum of hi and the accumulated lo; xs and ps
+        // are their rounded sums already)
+        xl = xl - (xs - xh);
+        xh = xs;
+        pl = pl - (ps - ph);
+        ph = ps;
     };
 
     while (__any(has)) {
         for (int k = 0; k < R.chunk; k += 4) {
             if (!__any(live)) break;
-            const uint64_t tr = GRAD ? traj : traj_offset + rel;
             uint32_t w[4];
-            philox4x32_10(n >> 2, (uint32_t)tr, (uint32_t)(tr >> 32), I.instance, R.key0, R.key1, w);
+            philox_call(n >> 2, pre, ik, R.key0, R.key1, w);
             float z[4];
             const float off = (BIAS == kBiasConst) ? c.adN : 0.0f;
-            box_muller32(w[0], w[1], c.sqrt_dN, off, z[0], z[1]);
-            box_muller32(w[2], w[3], c.sqrt_dN, off, z[2], z[3]);
+            box_muller32(w[0], w[1], c.m2ln2_dN, off, z[0], z[1]);
+            box_muller32(w[2], w[3], c.m2ln2_dN, off, z[2], z[3]);
             if (__builtin_amdgcn_ballot_w64(live && n + 4 > I.max_steps) != 0)
                 group(std::integral_constant<bool, true>(), z);
             else
@@ -908,9 +952,9 @@ __device__ __forceinline__ void lanes_fp32(const Inst &I, const RunArgs &R, cons
         if (claim(!has, rel, cursor, n_traj, exhausted)) {
             has = true;
             live = true;
-            xh = x_in_hi;
+            xh = xs = x_in_hi;
             xl = x_in_lo;
-            ph = pi_in_hi;
+            ph = ps = pi_in_hi;
             pl = pi_in_lo;
             zsum = 0.0;
             n_on = 0;
@@ -920,10 +964,10 @@ __device__ __forceinline__ void lanes_fp32(const Inst &I, const RunArgs &R, cons
                 traj = rp.tail[rel].traj;
                 ww = rp.tail[rel].ww;
             }
+            pre = philox_pre(GRAD ? traj : traj_offset + rel, R.key0, R.key1);
         }
     }
 }
-
 // ---------------------------------------------------------------------------
 // FP64 state with 2D noise (eq. full_langevin_equation): two normals per step,
 // noise S (xi_1, xi_2) sqrt(dN) with S the interpolated symmetric square root of
@@ -969,6 +1013,8 @@ __device__ __forceinline__ void lanes_fp64_2d(const Inst &I, const RunArgs &R, c
     bool live = has;
     double phi = I.phi_in, pi_ = I.pi_in, lnw = 0.0;
     uint32_t n = 0;
+    const uint32_t ik = I.instance ^ R.key1;
+    PhiloxPre pre = philox_pre(traj_offset + rel, R.key0, R.key1);
 
     // groups of two steps: one Philox call gives both steps' (xi_1, xi_2)
     auto group = [&](auto censor_tag, const double z[4]) {
@@ -1030,9 +1076,8 @@ __device__ __forceinline__ void lanes_fp64_2d(const Inst &I, const RunArgs &R, c
     while (__any(has)) {
         for (int k = 0; k < R.chunk; k += 2) {
             if (!__any(live)) break;
-            const uint64_t traj = traj_offset + rel;
             uint32_t w[4];
-            philox4x32_10(n >> 1, (uint32_t)traj, (uint32_t)(traj >> 32), I.instance, R.key0, R.key1, w);
+            philox_call(n >> 1, pre, ik, R.key0, R.key1, w);
             double z[4];
             box_muller64(w[0], w[1], sqrt_dN, l_bm, z[0], z[1]);
             box_muller64(w[2], w[3], sqrt_dN, l_bm, z[2], z[3]);
@@ -1047,6 +1092,7 @@ __device__ __forceinline__ void lanes_fp64_2d(const Inst &I, const RunArgs &R, c
             pi_ = I.pi_in;
             lnw = 0.0;
             n = 0;
+            pre = philox_pre(traj_offset + rel, R.key0, R.key1);
         }
     }
 }

@@ -16,6 +16,7 @@ enum : int { kBinsLinear = 0, kBinsLog = 1 };
 
 constexpr uint32_t kFlagCensored = 0x80000000u;
 constexpr uint32_t kFlagEndedEarly = 0x40000000u;
+constexpr uint32_t kStepMask = 0x3fffffffu;
 constexpr int kMlpHidden = 64;
 constexpr int kMlpParams = 4482;
 constexpr int kMlpMaxGrid = 1024;    // nodes of the tabulated network
