@@ -234,35 +234,28 @@ def _cpu_model() -> str:
     return "unknown"
 
 
-def tail_at(hist, w, x):
-    """(P(deltaN >= x), ESS over those bins, samples there) for a bin edge x of the workload."""
+def _tail_slot(hist, w, x):
+    """The slot whose lower edge (from the library's bin edges) is nearest to x."""
     import numpy as np
-    edges = w.lo * (w.hi / w.lo) ** (np.arange(w.n_bins + 1) / w.n_bins) if w.bins_kind else \
-        w.lo + (w.hi - w.lo) * np.arange(w.n_bins + 1) / w.n_bins
-    j = int(np.argmin(np.abs(edges - x)))            # slot j + 1 starts at edges[j]
-    sw = float(hist["sum_w"][j + 1:].sum())
-    sw2 = float(hist["sum_w2"][j + 1:].sum())
-    n = max(int(hist["n_traj"]), 1)
-    return sw / n, (sw * sw / sw2 if sw2 > 0 else 0.0), int(hist["count"][j + 1:].sum())
+    from paper_2410_13683_amd import fpt
+    _, edges, _ = fpt.fpt_density(hist, w.bins_kind, w.n_bins, w.lo, w.hi, moments=False)
+    return int(np.argmin(np.abs(edges - x))) + 1     # slot j + 1 starts at edges[j]
+
+
+def tail_at(hist, w, x):
+    """(P(deltaN >= x), ESS over those bins, samples there) for a bin edge x of the workload
+    (fpt_tail_at)."""
+    from paper_2410_13683_amd import fpt
+    t = fpt.fpt_tail_at(hist, w.bins_kind, w.n_bins, w.lo, w.hi, _tail_slot(hist, w, x))
+    return t["P"], t["ess"], int(t["count"])
 
 
 def tail_errors(hist, w, x) -> dict:
-    """One-sigma errors of P(deltaN >= x): the plain standard error of sum w 1_T / n, and the
-    per-bin lognormal intervals of fpt_lognormal_bins added in quadrature over the tail bins."""
-    import math
-    import numpy as np
+    """One-sigma errors of P(deltaN >= x) from fpt_tail_at: the plain standard error of
+    sum w 1_T / n, and the per-bin lognormal intervals added in quadrature over the tail bins."""
     from paper_2410_13683_amd import fpt
-    edges = w.lo * (w.hi / w.lo) ** (np.arange(w.n_bins + 1) / w.n_bins) if w.bins_kind else \
-        w.lo + (w.hi - w.lo) * np.arange(w.n_bins + 1) / w.n_bins
-    j0 = int(np.argmin(np.abs(edges - x))) + 1       # first slot of the tail set
-    n = max(int(hist["n_traj"]), 1)
-    sw = float(hist["sum_w"][j0:].sum())
-    sw2 = float(hist["sum_w2"][j0:].sum())
-    plain = math.sqrt(max(sw2 / n - (sw / n) ** 2, 0.0) / n)
-    p, lo, hi = fpt.fpt_lognormal_bins(n, hist["count"], hist["sum_lnw"], hist["sum_lnw2"])
-    half = 0.5 * (hi - lo)[j0:]
-    half = half[np.isfinite(half)]
-    return {"P_tail_err": plain, "P_tail_err_lognormal": float(math.sqrt((half ** 2).sum()))}
+    t = fpt.fpt_tail_at(hist, w.bins_kind, w.n_bins, w.lo, w.hi, _tail_slot(hist, w, x))
+    return {"P_tail_err": t["P_err"], "P_tail_err_lognormal": t["P_err_lognormal"]}
 
 
 def train_learned(w, stream, train_traj: float = 1e7, iters: int = 40, lr: float = 0.03) -> dict:

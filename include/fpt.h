@@ -451,6 +451,62 @@ int fpt_batch_last_ms(fpt_batch *b, double *ms);
 /* Free the batch (waits for the device; NULL is allowed). */
 void fpt_batch_destroy(fpt_batch *b);
 
+/* ---- normalisation (Sec. 4.1) ----------------------------------------------- */
+
+/* Sec. 4.1 reconstructs the distribution of the first-passage time from the weighted runs: with
+ * w = exp(ln w) per trajectory (w = 1 without a bias), the estimate of P(deltaN) in a bin is the
+ * bin's sum of w over n_traj times the bin width (the plain importance-sampling estimator; every
+ * trajectory run counts in n_traj, also the censored and the ones that ended early).  These calls
+ * work on a histogram read with fpt_histogram (host memory, the layout of fpt_hist, the bins of
+ * fpt_options), run on the host and need no device. */
+
+/* Whole-run figures of a histogram. */
+typedef struct {
+    double mean_w;      /* sum_w / n_traj over the trajectories that crossed phi_end: the estimate
+                           of P(passage); 1 for a complete run without a bias */
+    double mean_N;      /* the weighted mean passage time sum_wN / sum_w */
+    double var_N;       /* the weighted variance sum_wN2 / sum_w - mean_N^2 */
+    double ess;         /* effective sample size (sum_w)^2 / sum_w2 */
+    double mass_under;  /* sum_w / n_traj of the underflow slot (deltaN below the first edge) */
+    double mass_over;   /* sum_w / n_traj of the overflow slot (deltaN at or above the last edge) */
+} fpt_moments;
+
+/* Density of deltaN per bin: density_out[j] = sum_w_bin[j + 1] / (n_traj (e_{j+1} - e_j)) for
+ * j = 0 .. n_bins - 1, with the edges e_j of fpt_options (LINEAR lo + j (hi - lo)/n_bins, LOG
+ * lo (hi/lo)^(j/n_bins)).  edges_out (n_bins + 1 doubles) and m may be NULL.  bins_kind, n_bins,
+ * lo and hi must be the context's.  Errors: FPT_EINVAL (NULL h, h's arrays or density_out,
+ * n_bins outside 1..FPT_MAX_BINS, hi <= lo, lo <= 0 for LOG bins, n_traj == 0, a non-finite
+ * sum, sum_w == 0 when m is requested). */
+int fpt_density(const fpt_hist *h, int32_t bins_kind, int32_t n_bins, double lo, double hi, double *density_out,
+                double *edges_out, fpt_moments *m);
+
+/* A tail set T of the histogram: the slots slot .. n_bins + 1 (overflow included), i.e.
+ * deltaN >= x_star.  P = sum_T w / n_traj estimates P(deltaN >= x_star); its plain standard error
+ * is sqrt((sum_T w^2 / n_traj - P^2) / n_traj); ESS_T = (sum_T w)^2 / sum_T w^2, the number of
+ * equally weighted samples worth as much (its relative error is about 1/sqrt(ESS_T)). */
+typedef struct {
+    int32_t slot;       /* first slot of T: 1 .. n_bins + 1; -1 if no slot qualifies (fpt_tail_find) */
+    double x_star;      /* lower edge of T: e_{slot - 1} (hi for the overflow slot) */
+    double P;
+    double P_err;
+    double P_err_lognormal; /* the per-slot lognormal one-sigma half-widths (hi - lo)/2 of
+                               fpt_lognormal_bins over the slots of T, added in quadrature (slots
+                               with fewer than 2 samples contribute nothing; 0 without sum_lnw arrays) */
+    double ess;
+    uint64_t count;     /* trajectories in T */
+} fpt_tail;
+
+/* The tail set from a given first slot (1 .. n_bins + 1).  Errors: FPT_EINVAL (as fpt_density, or
+ * slot out of range). */
+int fpt_tail_at(const fpt_hist *h, int32_t bins_kind, int32_t n_bins, double lo, double hi, int32_t slot,
+                fpt_tail *out);
+
+/* The tail set at a target probability: the lowest slot whose tail mass sum_{slots >= j} w / n_traj
+ * is positive and at most p_target (the depth the estimate reaches).  out->slot = -1 and zeros
+ * when none is.  Errors: FPT_EINVAL (as fpt_density, or p_target not positive and finite). */
+int fpt_tail_find(const fpt_hist *h, int32_t bins_kind, int32_t n_bins, double lo, double hi, double p_target,
+                  fpt_tail *out);
+
 /* ---- error bars (Sec. 4.1) -------------------------------------------------- */
 
 /* Histogram slots throughout: n_slots = n_bins + 2 (underflow, the bins, overflow),

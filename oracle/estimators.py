@@ -1,8 +1,15 @@
-"""Error bars of the weighted first-passage histogram (Sec. 4.1) -- test infrastructure.
+"""Normalisation and error bars of the weighted first-passage histogram (Sec. 4.1) --
+test infrastructure.
 
-Plain numpy versions of the three estimators the library computes from its
-histogram accumulators.  They share no code with the library.  Only tests/ and
-bench.py's CPU baseline use this module.
+Plain numpy versions of what the library computes from its histogram
+accumulators.  They share no code with the library.  Only tests/ and bench.py's
+CPU baseline use this module.
+
+* Normalisation: Sec. 4.1 reconstructs P(deltaN) from the weighted runs.  A bin's
+  density is its sum of weights over n_traj (every trajectory run) times its width;
+  a tail set T = {deltaN >= x*} has P = sum_T w / n_traj, standard error
+  sqrt((sum_T w^2/n - P^2)/n) and ESS_T = (sum_T w)^2 / sum_T w^2.  The whole run has
+  mean_w = sum w / n, the weighted mean and variance of N and ESS = (sum w)^2 / sum w^2.
 
 * Direct sampling (no bias): delete-one jackknife over B blocks of trajectories.
   The paper treats each simulation run as an independent sample and resamples them.
@@ -74,3 +81,63 @@ def merge(p_runs, err_runs):
         out_p[j] = (wgt * P[ok, j]).sum() / wgt.sum()
         out_e[j] = 1.0 / np.sqrt(wgt.sum())
     return out_p, out_e
+
+
+def _edges(bins_kind, n_bins, lo, hi):
+    """e_j = lo + j (hi - lo)/n_bins (linear) or lo (hi/lo)^(j/n_bins) (log), j = 0..n_bins."""
+    e = np.empty(n_bins + 1)
+    for j in range(n_bins + 1):
+        t = j / n_bins
+        e[j] = lo + (hi - lo) * t if bins_kind == 0 else lo * (hi / lo) ** t
+    e[n_bins] = hi
+    return e
+
+
+def density(hist, bins_kind, n_bins, lo, hi):
+    """(density per bin, edges): sum_w of bin j over n_traj (e_{j+1} - e_j)."""
+    e = _edges(bins_kind, n_bins, lo, hi)
+    n = float(hist["n_traj"])
+    d = np.empty(n_bins)
+    for j in range(n_bins):
+        d[j] = float(hist["sum_w"][j + 1]) / (n * (e[j + 1] - e[j]))
+    return d, e
+
+
+def moments(hist):
+    """mean_w, mean_N, var_N, ess, mass_under, mass_over of a histogram dict."""
+    n = float(hist["n_traj"])
+    sw, sw2 = float(hist["sum_w_total"]), float(hist["sum_w2_total"])
+    mean_N = float(hist["sum_wN"]) / sw
+    return {"mean_w": sw / n, "mean_N": mean_N, "var_N": float(hist["sum_wN2"]) / sw - mean_N ** 2,
+            "ess": sw * sw / sw2 if sw2 > 0 else 0.0,
+            "mass_under": float(hist["sum_w"][0]) / n, "mass_over": float(hist["sum_w"][-1]) / n}
+
+
+def tail_at(hist, bins_kind, n_bins, lo, hi, slot):
+    """The tail set of slots slot .. n_bins + 1 (deltaN >= e_{slot-1}; the overflow slot starts at hi)."""
+    e = _edges(bins_kind, n_bins, lo, hi)
+    n = float(hist["n_traj"])
+    sw = float(np.sum(np.asarray(hist["sum_w"], dtype=np.float64)[slot:]))
+    sw2 = float(np.sum(np.asarray(hist["sum_w2"], dtype=np.float64)[slot:]))
+    P = sw / n
+    # the lognormal intervals of the slots of T, half-widths added in quadrature
+    _, lo_j, hi_j = lognormal(n, hist["count"], hist["sum_lnw"], hist["sum_lnw2"])
+    half = 0.5 * (hi_j - lo_j)[slot:]
+    half = half[np.isfinite(half)]
+    return {"slot": slot, "x_star": float(e[slot - 1]), "P": P,
+            "P_err": float(np.sqrt(max(sw2 / n - P * P, 0.0) / n)),
+            "P_err_lognormal": float(np.sqrt(np.sum(half ** 2))),
+            "ess": sw * sw / sw2 if sw2 > 0 else 0.0,
+            "count": int(np.sum(np.asarray(hist["count"], dtype=np.uint64)[slot:]))}
+
+
+def tail_find(hist, bins_kind, n_bins, lo, hi, p_target):
+    """The lowest slot j >= 1 whose tail mass sum_{slots >= j} w / n_traj is positive and at most
+    p_target, as tail_at; slot -1 when there is none."""
+    n = float(hist["n_traj"])
+    for j in range(1, n_bins + 2):
+        p = float(np.sum(np.asarray(hist["sum_w"], dtype=np.float64)[j:])) / n
+        if 0.0 < p <= p_target:
+            return tail_at(hist, bins_kind, n_bins, lo, hi, j)
+    return {"slot": -1, "x_star": 0.0, "P": 0.0, "P_err": 0.0, "P_err_lognormal": 0.0, "ess": 0.0, "count": 0}
+

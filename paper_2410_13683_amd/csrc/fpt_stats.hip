@@ -1,5 +1,8 @@
-// fpt_stats.hip -- error bars of the weighted first-passage histogram (Sec. 4.1), computed on
-// the host from the histogram accumulators: a few numbers per slot, so no kernel.
+// fpt_stats.hip -- normalisation and error bars of the weighted first-passage histogram
+// (Sec. 4.1), computed on the host from the histogram accumulators: a few numbers per slot, so
+// no kernel.
+//   fpt_density         P(deltaN) per bin, sum w / (n_traj width), and whole-run figures;
+//   fpt_tail_at/_find   a tail set deltaN >= x*: its probability, error and ESS_T;
 //   fpt_jackknife       delete-one jackknife over blocks of trajectories (direct sampling);
 //   fpt_lognormal_bins  per-slot lognormal mean of the weights, with Cox's interval and the
 //                       count's binomial fluctuation (importance sampling);
@@ -90,5 +93,134 @@ extern "C" int fpt_merge_bins(int32_t n_slots, int32_t n_runs, const double *p, 
         p_out[j] = sw > 0.0 ? swp / sw : NAN;
         err_out[j] = sw > 0.0 ? 1.0 / std::sqrt(sw) : NAN;
     }
+    return FPT_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Normalisation (Sec. 4.1): the density of deltaN per bin, whole-run figures and tail sets of a
+// histogram read with fpt_histogram.  Host code: a few numbers per slot.
+// ---------------------------------------------------------------------------
+namespace {
+
+// Checks shared by the normalisation calls: the histogram's arrays, the bin layout, a positive
+// trajectory count and finite sums.
+int check_hist(const fpt_hist *h, int32_t bins_kind, int32_t n_bins, double lo, double hi)
+{
+    if (!h || !h->count || !h->sum_w_bin || !h->sum_w2_bin) return report_error(FPT_EINVAL, "NULL histogram array");
+    if (n_bins < 1 || n_bins > FPT_MAX_BINS) return report_error(FPT_EINVAL, "n_bins out of 1..FPT_MAX_BINS");
+    if (bins_kind != FPT_BINS_LINEAR && bins_kind != FPT_BINS_LOG) return report_error(FPT_EINVAL, "bad bins_kind");
+    if (!std::isfinite(lo) || !std::isfinite(hi) || !(hi > lo)) return report_error(FPT_EINVAL, "need finite lo < hi");
+    if (bins_kind == FPT_BINS_LOG && !(lo > 0.0)) return report_error(FPT_EINVAL, "log bins need lo > 0");
+    if (h->n_traj == 0) return report_error(FPT_EINVAL, "the histogram holds no trajectories");
+    for (int j = 0; j < n_bins + 2; ++j)
+        if (!std::isfinite(h->sum_w_bin[j]) || !std::isfinite(h->sum_w2_bin[j]))
+            return report_error(FPT_EINVAL, "non-finite histogram sum");
+    return FPT_OK;
+}
+
+// Edge e_j of the bins, j = 0 .. n_bins (the kernels bin with the same scale: t = (x - lo)
+// n_bins/(hi - lo) or ln(x/lo) n_bins/ln(hi/lo)).
+double bin_edge(int32_t bins_kind, int32_t n_bins, double lo, double hi, int j)
+{
+    if (j == n_bins) return hi;
+    const double t = (double)j / (double)n_bins;
+    return bins_kind == FPT_BINS_LINEAR ? lo + (hi - lo) * t : lo * std::pow(hi / lo, t);
+}
+
+void tail_from(const fpt_hist *h, int32_t bins_kind, int32_t n_bins, double lo, double hi, int slot, fpt_tail *out)
+{
+    double sw = 0.0, sw2 = 0.0;
+    uint64_t c = 0;
+    for (int j = n_bins + 1; j >= slot; --j) {
+        sw += h->sum_w_bin[j];
+        sw2 += h->sum_w2_bin[j];
+        c += h->count[j];
+    }
+    const double n = (double)h->n_traj;
+    out->slot = slot;
+    out->x_star = bin_edge(bins_kind, n_bins, lo, hi, slot - 1);
+    out->P = sw / n;
+    out->P_err = std::sqrt(std::fmax(sw2 / n - out->P * out->P, 0.0) / n);
+    out->ess = sw2 > 0.0 ? sw * sw / sw2 : 0.0;
+    out->count = c;
+    // the per-slot lognormal intervals of fpt_lognormal_bins, half-widths added in quadrature
+    double q = 0.0;
+    if (h->sum_lnw_bin && h->sum_lnw2_bin) {
+        for (int j = slot; j <= n_bins + 1; ++j) {
+            double p, lo_j, hi_j;
+            if (fpt_lognormal_bins(1, h->n_traj, &h->count[j], &h->sum_lnw_bin[j], &h->sum_lnw2_bin[j], &p, &lo_j,
+                                   &hi_j) != FPT_OK || !std::isfinite(hi_j - lo_j))
+                continue;
+            q += 0.25 * (hi_j - lo_j) * (hi_j - lo_j);
+        }
+    }
+    out->P_err_lognormal = std::sqrt(q);
+}
+
+}  // namespace
+
+extern "C" int fpt_density(const fpt_hist *h, int32_t bins_kind, int32_t n_bins, double lo, double hi,
+                           double *density_out, double *edges_out, fpt_moments *m)
+{
+    const int rc = check_hist(h, bins_kind, n_bins, lo, hi);
+    if (rc != FPT_OK) return rc;
+    if (!density_out) return report_error(FPT_EINVAL, "NULL density_out");
+    if (m && !(h->sum_w > 0.0 && std::isfinite(h->sum_w) && std::isfinite(h->sum_w2) && std::isfinite(h->sum_wN) &&
+               std::isfinite(h->sum_wN2)))
+        return report_error(FPT_EINVAL, "whole-run sums must be finite with sum_w > 0");
+    const double n = (double)h->n_traj;
+    double e0 = bin_edge(bins_kind, n_bins, lo, hi, 0);
+    if (edges_out) edges_out[0] = e0;
+    for (int j = 0; j < n_bins; ++j) {
+        const double e1 = bin_edge(bins_kind, n_bins, lo, hi, j + 1);
+        density_out[j] = h->sum_w_bin[j + 1] / (n * (e1 - e0));
+        if (edges_out) edges_out[j + 1] = e1;
+        e0 = e1;
+    }
+    if (m) {
+        m->mean_w = h->sum_w / n;
+        m->mean_N = h->sum_wN / h->sum_w;
+        m->var_N = h->sum_wN2 / h->sum_w - m->mean_N * m->mean_N;
+        m->ess = h->sum_w2 > 0.0 ? h->sum_w * h->sum_w / h->sum_w2 : 0.0;
+        m->mass_under = h->sum_w_bin[0] / n;
+        m->mass_over = h->sum_w_bin[n_bins + 1] / n;
+    }
+    return FPT_OK;
+}
+
+extern "C" int fpt_tail_at(const fpt_hist *h, int32_t bins_kind, int32_t n_bins, double lo, double hi, int32_t slot,
+                           fpt_tail *out)
+{
+    const int rc = check_hist(h, bins_kind, n_bins, lo, hi);
+    if (rc != FPT_OK) return rc;
+    if (!out) return report_error(FPT_EINVAL, "NULL out");
+    if (slot < 1 || slot > n_bins + 1) return report_error(FPT_EINVAL, "slot out of 1..n_bins + 1");
+    tail_from(h, bins_kind, n_bins, lo, hi, slot, out);
+    return FPT_OK;
+}
+
+extern "C" int fpt_tail_find(const fpt_hist *h, int32_t bins_kind, int32_t n_bins, double lo, double hi,
+                             double p_target, fpt_tail *out)
+{
+    const int rc = check_hist(h, bins_kind, n_bins, lo, hi);
+    if (rc != FPT_OK) return rc;
+    if (!out) return report_error(FPT_EINVAL, "NULL out");
+    if (!(p_target > 0.0) || !std::isfinite(p_target)) return report_error(FPT_EINVAL, "p_target must be > 0");
+    // tail masses from the overflow slot down: the lowest slot whose mass is positive and at
+    // most p_target (the masses do not decrease towards lower slots)
+    const double n = (double)h->n_traj;
+    double sw = 0.0;
+    int best = -1;
+    for (int j = n_bins + 1; j >= 1; --j) {
+        sw += h->sum_w_bin[j];
+        const double p = sw / n;
+        if (p > p_target) break;
+        if (p > 0.0) best = j;
+    }
+    if (best < 0) {
+        *out = fpt_tail{-1, 0.0, 0.0, 0.0, 0.0, 0.0, 0};
+        return FPT_OK;
+    }
+    tail_from(h, bins_kind, n_bins, lo, hi, best, out);
     return FPT_OK;
 }

@@ -81,6 +81,17 @@ class fpt_hist(ctypes.Structure):
                 ("sum_w_bin", _dp), ("sum_w2_bin", _dp), ("sum_lnw_bin", _dp), ("sum_lnw2_bin", _dp)]
 
 
+class fpt_moments(ctypes.Structure):
+    _fields_ = [("mean_w", ctypes.c_double), ("mean_N", ctypes.c_double), ("var_N", ctypes.c_double),
+                ("ess", ctypes.c_double), ("mass_under", ctypes.c_double), ("mass_over", ctypes.c_double)]
+
+
+class fpt_tail(ctypes.Structure):
+    _fields_ = [("slot", ctypes.c_int32), ("x_star", ctypes.c_double), ("P", ctypes.c_double),
+                ("P_err", ctypes.c_double), ("P_err_lognormal", ctypes.c_double), ("ess", ctypes.c_double),
+                ("count", ctypes.c_uint64)]
+
+
 class fpt_batch_options(ctypes.Structure):
     _fields_ = [("block_size", ctypes.c_int32), ("chunk", ctypes.c_int32), ("item_size", ctypes.c_int32),
                 ("use_graph", ctypes.c_int32)]
@@ -139,6 +150,12 @@ def load():
     L.fpt_jackknife.argtypes = [ctypes.c_int32, ctypes.c_int32, _u64p, _dp, _dp, _dp]
     L.fpt_lognormal_bins.argtypes = [ctypes.c_int32, ctypes.c_uint64, _u64p, _dp, _dp, _dp, _dp, _dp]
     L.fpt_merge_bins.argtypes = [ctypes.c_int32, ctypes.c_int32, _dp, _dp, _dp, _dp]
+    L.fpt_density.argtypes = [P(fpt_hist), ctypes.c_int32, ctypes.c_int32, ctypes.c_double, ctypes.c_double, _dp,
+                              _dp, P(fpt_moments)]
+    L.fpt_tail_at.argtypes = [P(fpt_hist), ctypes.c_int32, ctypes.c_int32, ctypes.c_double, ctypes.c_double,
+                              ctypes.c_int32, P(fpt_tail)]
+    L.fpt_tail_find.argtypes = [P(fpt_hist), ctypes.c_int32, ctypes.c_int32, ctypes.c_double, ctypes.c_double,
+                                ctypes.c_double, P(fpt_tail)]
     L.fpt_batch_create.argtypes = [P(ctypes.c_void_p), ctypes.c_int32, P(fpt_batch_options), P(ctypes.c_void_p)]
     L.fpt_batch_run.argtypes = [ctypes.c_void_p, _u64p, ctypes.c_double, ctypes.c_uint64, ctypes.c_uint64,
                                 ctypes.c_void_p]
@@ -159,7 +176,7 @@ def load():
     for name in ("fpt_create", "fpt_run", "fpt_histogram", "fpt_reset", "fpt_last_kernel_ms",
                  "fpt_noise_table_bessel", "fpt_noise_table_bessel2d", "fpt_noise_table_matched",
                  "fpt_noise_table_matched_time", "fpt_noise_table_bessel2d_time", "fpt_jackknife", "fpt_lognormal_bins",
-                 "fpt_merge_bins", "fpt_batch_create", "fpt_batch_run", "fpt_batch_autotune",
+                 "fpt_merge_bins", "fpt_density", "fpt_tail_at", "fpt_tail_find", "fpt_batch_create", "fpt_batch_run", "fpt_batch_autotune",
                  "fpt_batch_config", "fpt_batch_last_ms", "fpt_mlp_set", "fpt_mlp_get", "fpt_mlp_table",
                  "fpt_mlp_grad", "fpt_mlp_adam"):
         getattr(L, name).restype = ctypes.c_int
@@ -282,6 +299,54 @@ def fpt_merge_bins(p_runs, err_runs):
     _check(load().fpt_merge_bins(ns, R, P.ctypes.data_as(_dp), E.ctypes.data_as(_dp), p.ctypes.data_as(_dp),
                                  e.ctypes.data_as(_dp)), "fpt_merge_bins")
     return p, e
+
+
+def _hist_struct(hist: dict):
+    """An fpt_hist over the arrays of a histogram dict (as Context.histogram returns); the arrays
+    are kept alive by the returned tuple."""
+    arrs = [np.ascontiguousarray(hist["count"], dtype=np.uint64)] + [
+        _f64(hist[k]) for k in ("sum_w", "sum_w2", "sum_lnw", "sum_lnw2")]
+    h = fpt_hist(int(hist["n_traj"]), int(hist.get("n_censored", 0)), int(hist.get("n_ended_early", 0)),
+                 int(hist.get("n_steps_total", 0)), float(hist.get("sum_w_total", 0.0)),
+                 float(hist.get("sum_w2_total", 0.0)), float(hist.get("sum_wN", 0.0)),
+                 float(hist.get("sum_wN2", 0.0)), arrs[0].ctypes.data_as(_u64p),
+                 *[a.ctypes.data_as(_dp) for a in arrs[1:]])
+    return h, arrs
+
+
+def fpt_density(hist: dict, bins_kind: int, n_bins: int, lo: float, hi: float, moments: bool = True):
+    """(density per bin, bin edges, whole-run figures or None) of a histogram dict."""
+    h, keep = _hist_struct(hist)
+    dens, edges = np.empty(n_bins), np.empty(n_bins + 1)
+    m = fpt_moments()
+    _check(load().fpt_density(ctypes.byref(h), bins_kind, n_bins, lo, hi, dens.ctypes.data_as(_dp),
+                              edges.ctypes.data_as(_dp), ctypes.byref(m) if moments else None), "fpt_density")
+    del keep
+    mo = {f: getattr(m, f) for f, _ in fpt_moments._fields_} if moments else None
+    return dens, edges, mo
+
+
+def _tail_dict(t: fpt_tail) -> dict:
+    return {f: getattr(t, f) for f, _ in fpt_tail._fields_}
+
+
+def fpt_tail_at(hist: dict, bins_kind: int, n_bins: int, lo: float, hi: float, slot: int) -> dict:
+    """The tail set of slots slot .. n_bins + 1: slot, x_star, P, P_err, ess, count."""
+    h, keep = _hist_struct(hist)
+    t = fpt_tail()
+    _check(load().fpt_tail_at(ctypes.byref(h), bins_kind, n_bins, lo, hi, slot, ctypes.byref(t)), "fpt_tail_at")
+    del keep
+    return _tail_dict(t)
+
+
+def fpt_tail_find(hist: dict, bins_kind: int, n_bins: int, lo: float, hi: float, p_target: float) -> dict:
+    """The tail set whose probability is the largest at or below p_target (slot -1 if none)."""
+    h, keep = _hist_struct(hist)
+    t = fpt_tail()
+    _check(load().fpt_tail_find(ctypes.byref(h), bins_kind, n_bins, lo, hi, p_target, ctypes.byref(t)),
+           "fpt_tail_find")
+    del keep
+    return _tail_dict(t)
 
 
 class Context:

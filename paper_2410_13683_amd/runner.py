@@ -66,27 +66,19 @@ def context_for(w: Workload, **overrides) -> fpt.Context:
     return fpt.Context(pot, S, t, lo, hi, **kw)
 
 
+def tail_set(hist: dict, n_bins: int, bins_kind: int, lo: float, hi: float, p_tail: float = 1e-10) -> dict:
+    """The library's tail set at probability p_tail (fpt_tail_find): the bins from the lowest edge
+    x* whose weighted tail mass P(deltaN >= x*) (overflow included) is at most p_tail, with P, its
+    errors, ESS_T and the samples in T (slot -1 when no edge qualifies)."""
+    return fpt.fpt_tail_find(hist, bins_kind, n_bins, lo, hi, p_tail)
+
+
 def tail_ess(hist: dict, n_bins: int, bins_kind: int, lo: float, hi: float, p_tail: float = 1e-10):
-    """Tail set T = bins from the lowest edge x* whose weighted tail mass
-    P(deltaN >= x*) = sum_{bins >= x*} w / n_traj is at most p_tail (overflow included).
-    Returns (x*, P(deltaN >= x*), ESS_T = (sum_T w)^2 / sum_T w^2, samples in T)."""
-    n = max(int(hist["n_traj"]), 1)
-    sw = np.asarray(hist["sum_w"], dtype=np.float64)
-    sw2 = np.asarray(hist["sum_w2"], dtype=np.float64)
-    cnt = np.asarray(hist["count"], dtype=np.float64)
-    tail = np.cumsum(sw[::-1])[::-1] / n        # tail[i] = sum over slots i.. (slot 0 = underflow)
-    if bins_kind == 0:
-        edges = lo + (hi - lo) * np.arange(n_bins + 1) / n_bins
-    else:
-        edges = lo * (hi / lo) ** (np.arange(n_bins + 1) / n_bins)
-    # slot j (1..n_bins) starts at edges[j-1]; slot n_bins+1 (overflow) starts at hi
-    for j in range(1, n_bins + 2):
-        if tail[j] <= p_tail and tail[j] > 0:
-            s_w, s_w2, c = sw[j:].sum(), sw2[j:].sum(), cnt[j:].sum()
-            ess = s_w * s_w / s_w2 if s_w2 > 0 else 0.0
-            x = edges[j - 1] if j <= n_bins else hi
-            return float(x), float(tail[j]), float(ess), int(c)
-    return None, 0.0, 0.0, 0
+    """(x*, P(deltaN >= x*), ESS_T, samples in T) of tail_set, or (None, 0, 0, 0)."""
+    t = tail_set(hist, n_bins, bins_kind, lo, hi, p_tail)
+    if t["slot"] < 0:
+        return None, 0.0, 0.0, 0
+    return t["x_star"], t["P"], t["ess"], int(t["count"])
 
 
 def run_blocks(ctx: fpt.Context, w: Workload, n_blocks: int, stream, traj_offset: int = 0):

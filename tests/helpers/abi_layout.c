@@ -25,6 +25,10 @@ int main(void)
     F(fpt_hist, n_steps_total); F(fpt_hist, sum_w); F(fpt_hist, sum_w2); F(fpt_hist, sum_wN);
     F(fpt_hist, sum_wN2); F(fpt_hist, count); F(fpt_hist, sum_w_bin); F(fpt_hist, sum_w2_bin);
     F(fpt_hist, sum_lnw_bin); F(fpt_hist, sum_lnw2_bin);
+    S(fpt_moments); F(fpt_moments, mean_w); F(fpt_moments, mean_N); F(fpt_moments, var_N); F(fpt_moments, ess);
+    F(fpt_moments, mass_under); F(fpt_moments, mass_over);
+    S(fpt_tail); F(fpt_tail, slot); F(fpt_tail, x_star); F(fpt_tail, P); F(fpt_tail, P_err); F(fpt_tail, P_err_lognormal); F(fpt_tail, ess);
+    F(fpt_tail, count);
     S(fpt_batch_options); F(fpt_batch_options, block_size); F(fpt_batch_options, chunk);
     F(fpt_batch_options, item_size); F(fpt_batch_options, use_graph);
     return 0;

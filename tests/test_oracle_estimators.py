@@ -119,3 +119,84 @@ def test_combined_interval_covers_the_slot_mass_at_one_sigma(s):
     assert abs(cover / R - 0.6827) < 0.04, cover / R
     if s == 0.05:
         assert cover_cox / R < 0.2
+
+
+# ---- normalisation (Sec. 4.1: P(deltaN) from the weighted runs) --------------------------------
+
+def _samples(rng, n, bins_kind):
+    """Synthetic per-trajectory outputs: N, ln w and flags (3 % censored, 2 % ended early)."""
+    from oracle import oracle as orc
+    x = rng.gamma(3.0, 0.02, size=n) - (0.01 if bins_kind == 0 else 0.0)
+    lnw = rng.normal(-1.0, 0.8, size=n)
+    steps = np.full(n, 1000, dtype=np.uint32)
+    u = rng.random(n)
+    steps[u < 0.03] |= orc.FLAG_CENSORED
+    steps[(u >= 0.03) & (u < 0.05)] |= orc.FLAG_ENDED_EARLY
+    return 10.0 + x, lnw, steps
+
+
+@pytest.mark.parametrize("bins_kind", [0, 1])
+def test_normalisation_equals_sums_over_samples(bins_kind):
+    """Brute force from the samples themselves, not from the histogram: the mass of each bin, of
+    every tail set and of the whole run, with n_traj counting every trajectory run (censored and
+    ended-early ones included), against the oracle's normalisation of its histogram."""
+    from oracle import oracle as orc
+    rng = np.random.default_rng(40 + bins_kind)
+    n, nb, lo, hi, N_ref = 20_000, 37, (0.005 if bins_kind else -0.02), 0.15, 10.0
+    N, lnw, steps = _samples(rng, n, bins_kind)
+    h = orc.histogram(N, lnw, steps, N_ref, bins_kind, nb, lo, hi)
+    crossed = (steps & (orc.FLAG_CENSORED | orc.FLAG_ENDED_EARLY)) == 0
+    x, w = N[crossed] - N_ref, np.exp(lnw[crossed])
+    e = lo + (hi - lo) * np.arange(nb + 1) / nb if bins_kind == 0 else lo * (hi / lo) ** (np.arange(nb + 1) / nb)
+    d, edges = E.density(h, bins_kind, nb, lo, hi)
+    np.testing.assert_allclose(edges, e, rtol=1e-15)
+    for j in range(nb):
+        inside = (x >= e[j]) & (x < e[j + 1])
+        np.testing.assert_allclose(d[j] * n * (e[j + 1] - e[j]), w[inside].sum(), rtol=1e-12, atol=1e-300)
+    m = E.moments(h)
+    np.testing.assert_allclose(m["mean_w"], w.sum() / n, rtol=1e-12)
+    np.testing.assert_allclose(m["mean_N"], (w * N[crossed]).sum() / w.sum(), rtol=1e-13)
+    var = (w * (N[crossed] - (w * N[crossed]).sum() / w.sum()) ** 2).sum() / w.sum()
+    np.testing.assert_allclose(m["var_N"], var, rtol=1e-6)
+    np.testing.assert_allclose(m["ess"], w.sum() ** 2 / (w * w).sum(), rtol=1e-12)
+    np.testing.assert_allclose(m["mass_under"], w[x < lo].sum() / n, rtol=1e-12, atol=1e-300)
+    np.testing.assert_allclose(m["mass_over"], w[x >= hi].sum() / n, rtol=1e-12, atol=1e-300)
+    # every bin's mass plus the two outer slots is the whole weight
+    np.testing.assert_allclose((d * np.diff(e)).sum() + m["mass_under"] + m["mass_over"], w.sum() / n, rtol=1e-12)
+    for slot in (1, 5, nb, nb + 1):
+        t = E.tail_at(h, bins_kind, nb, lo, hi, slot)
+        x_star = e[slot - 1]
+        wt = w[x >= x_star]
+        assert abs(t["x_star"] - x_star) <= 4e-16 * abs(x_star) and t["count"] == len(wt)
+        np.testing.assert_allclose(t["P"], wt.sum() / n, rtol=1e-12, atol=1e-300)
+        # the plain standard error of the mean of w 1_T over all n trajectories
+        full = np.zeros(n)
+        full[np.flatnonzero(crossed)[x >= x_star]] = wt
+        np.testing.assert_allclose(t["P_err"], full.std() / math.sqrt(n), rtol=1e-9)
+        np.testing.assert_allclose(t["ess"], wt.sum() ** 2 / (wt * wt).sum(), rtol=1e-12)
+    checked = 0
+    for p in (1e-3, 1e-2, 0.1, 0.3):
+        t = E.tail_find(h, bins_kind, nb, lo, hi, p)
+        mass = [w[x >= e[j - 1]].sum() / n for j in range(1, nb + 2)]
+        want = next((j for j in range(1, nb + 2) if 0.0 < mass[j - 1] <= p), -1)
+        assert t["slot"] == want, (p, t["slot"], want)
+        checked += want > 0
+    assert checked >= 2
+    assert E.tail_find(h, bins_kind, nb, lo, hi, 1e-12)["slot"] == -1
+
+
+def test_density_closed_form():
+    """One sample at the centre of each linear bin j with weight j + 1, n = 2 n_bins trajectories
+    (half of them censored): density_j = (j + 1) / (n width)."""
+    from oracle import oracle as orc
+    nb, lo, hi = 12, -0.3, 0.9
+    width = (hi - lo) / nb
+    centres = lo + width * (np.arange(nb) + 0.5)
+    N = np.concatenate([centres, np.full(nb, np.nan)])
+    lnw = np.concatenate([np.log(np.arange(1, nb + 1, dtype=float)), np.zeros(nb)])
+    steps = np.concatenate([np.full(nb, 7, dtype=np.uint32), np.full(nb, 7 | orc.FLAG_CENSORED, dtype=np.uint32)])
+    h = orc.histogram(N, lnw, steps, 0.0, 0, nb, lo, hi)
+    d, _ = E.density(h, 0, nb, lo, hi)
+    np.testing.assert_allclose(d, np.arange(1, nb + 1) / (2 * nb * width), rtol=1e-13)
+    t = E.tail_at(h, 0, nb, lo, hi, nb)                 # the last bin alone
+    assert t["count"] == 1 and abs(t["P"] - nb / (2 * nb)) < 1e-15 and t["ess"] == 1.0
