@@ -299,6 +299,20 @@ int fpt_mlp_grad(fpt_ctx *ctx, uint64_t n_traj, double dN, uint64_t seed, uint64
                  int32_t objective, void *hip_stream, float *d_grad, double *d_G, double *J_out,
                  uint64_t *n_tail_out);
 
+/* fpt_mlp_grad for callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): the same computation, arguments and results, with
+ * its per-trajectory scratch in a fixed device array of the library (about 9.4 MB per GPU the
+ * library runs on, held until the process ends) instead of memory allocated on first use.  It calls
+ * no hipMalloc or hipFree.  n_traj is at most FPT_MLP_GRAD_NOALLOC_MAX (else FPT_EINVAL with a
+ * message; fpt_mlp_grad has no such limit).  Every call on a GPU shares that GPU's array: calls that
+ * overlap on one GPU (other streams, other threads, other contexts) race and must be ordered by the
+ * caller.  Errors: as fpt_mlp_grad (FPT_ENOMEM aside), FPT_EHIP if the array's address cannot be
+ * obtained. */
+#define FPT_MLP_GRAD_NOALLOC_MAX 262144
+int fpt_mlp_grad_noalloc(fpt_ctx *ctx, uint64_t n_traj, double dN, uint64_t seed, uint64_t traj_offset,
+                         double tail_lo, int32_t objective, void *hip_stream, float *d_grad, double *d_G,
+                         double *J_out, uint64_t *n_tail_out);
+
 /* One Adam step (Kingma and Ba, 2015) on the context's parameters with the
  * gradient d_grad (device, FPT_MLP_NPARAM floats): m = b1 m + (1 - b1) g,
  * v = b2 v + (1 - b2) g^2, theta -= lr (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps),

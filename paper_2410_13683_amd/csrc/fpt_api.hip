@@ -16,6 +16,7 @@
 #include <algorithm>
 #include <vector>
 #include <limits>
+#include <mutex>
 
 using namespace fpt;
 
@@ -862,9 +863,9 @@ extern "C" int fpt_mlp_table(fpt_ctx *c, double *a_out)
     return FPT_OK;
 }
 
-extern "C" int fpt_mlp_grad(fpt_ctx *c, uint64_t n_traj, double dN, uint64_t seed, uint64_t traj_offset,
-                            double tail_lo, int32_t objective, void *hip_stream, float *d_grad, double *d_G,
-                            double *J_out, uint64_t *n_tail_out)
+// Argument checks shared by the two gradient entry points.
+static int mlp_grad_check(fpt_ctx *c, uint64_t n_traj, double dN, uint64_t traj_offset, double tail_lo,
+                          int32_t objective, const float *d_grad)
 {
     int rc = mlp_check(c);
     if (rc) return rc;
@@ -875,25 +876,17 @@ extern "C" int fpt_mlp_grad(fpt_ctx *c, uint64_t n_traj, double dN, uint64_t see
         return fail(FPT_EINVAL, "unknown objective %d", objective);
     if (n_traj == 0) return fail(FPT_EINVAL, "n_traj must be > 0");
     if (traj_offset + n_traj < traj_offset) return fail(FPT_EINVAL, "trajectory range overflows 64 bits");
-    hipStream_t s = static_cast<hipStream_t>(hip_stream);
-    // per-trajectory scratch: N, ln w (8 B each), steps (4 B) and a tail entry (16 B)
-    const size_t slice = std::min<uint64_t>(n_traj, kGradSlice);
-    if (slice > c->scratch_cap) {
-        if (c->d_scratch) {
-            HIP_TRY(hipDeviceSynchronize());
-            HIP_TRY(hipFree(c->d_scratch));
-            c->d_scratch = nullptr;
-            c->scratch_cap = 0;
-        }
-        const size_t bytes = slice * (8 + 8 + 4 + 16) + 1024;
-        if (hipMalloc(&c->d_scratch, bytes) != hipSuccess) {
-            c->d_scratch = nullptr;
-            return fail(FPT_ENOMEM, "gradient scratch of %zu bytes", bytes);
-        }
-        c->scratch_cap = slice;
-    }
-    const size_t cap = c->scratch_cap;
-    unsigned char *sb = static_cast<unsigned char *>(c->d_scratch);
+    return FPT_OK;
+}
+
+// The gradient run of fpt_mlp_grad on per-trajectory scratch sb of cap trajectories (N, ln w, steps
+// and a tail entry each, 36 bytes): slices of at most cap trajectories are integrated, their tail
+// compacted and replayed, then the node weights are propagated through the network.
+static int mlp_grad_run(fpt_ctx *c, uint64_t n_traj, double dN, uint64_t seed, uint64_t traj_offset, double tail_lo,
+                        int32_t objective, hipStream_t s, float *d_grad, double *d_G, double *J_out,
+                        uint64_t *n_tail_out, unsigned char *sb, size_t cap)
+{
+    int rc = FPT_OK;
     TailEntry *d_tail = reinterpret_cast<TailEntry *>(sb);
     double *d_N = reinterpret_cast<double *>(sb + 16 * cap);
     double *d_lnw = d_N + cap;
@@ -969,6 +962,78 @@ extern "C" int fpt_mlp_grad(fpt_ctx *c, uint64_t n_traj, double dN, uint64_t see
         if (n_tail_out) *n_tail_out = h_cnt[1];
     }
     return FPT_OK;
+}
+
+extern "C" int fpt_mlp_grad(fpt_ctx *c, uint64_t n_traj, double dN, uint64_t seed, uint64_t traj_offset,
+                            double tail_lo, int32_t objective, void *hip_stream, float *d_grad, double *d_G,
+                            double *J_out, uint64_t *n_tail_out)
+{
+    int rc = mlp_grad_check(c, n_traj, dN, traj_offset, tail_lo, objective, d_grad);
+    if (rc) return rc;
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    // per-trajectory scratch: N, ln w (8 B each), steps (4 B) and a tail entry (16 B)
+    const size_t slice = std::min<uint64_t>(n_traj, kGradSlice);
+    if (slice > c->scratch_cap) {
+        if (c->d_scratch) {
+            HIP_TRY(hipDeviceSynchronize());
+            HIP_TRY(hipFree(c->d_scratch));
+            c->d_scratch = nullptr;
+            c->scratch_cap = 0;
+        }
+        const size_t bytes = slice * (8 + 8 + 4 + 16) + 1024;
+        if (hipMalloc(&c->d_scratch, bytes) != hipSuccess) {
+            c->d_scratch = nullptr;
+            return fail(FPT_ENOMEM, "gradient scratch of %zu bytes", bytes);
+        }
+        c->scratch_cap = slice;
+    }
+    return mlp_grad_run(c, n_traj, dN, seed, traj_offset, tail_lo, objective, s, d_grad, d_G, J_out, n_tail_out,
+                        static_cast<unsigned char *>(c->d_scratch), c->scratch_cap);
+}
+
+// ---------------------------------------------------------------------------
+// fpt_mlp_grad without allocation: its per-trajectory scratch is a file-scope device array, one
+// copy per GPU the library runs on (held until the process ends), reached through the address
+// hipGetSymbolAddress gives on each device.  In host code the array's name is no device address.
+// ---------------------------------------------------------------------------
+static constexpr size_t kNoAllocMaxTraj = size_t(1) << 18;
+static constexpr size_t kNoAllocBytes = kNoAllocMaxTraj * (16 + 8 + 8 + 4) + 1024;
+static_assert(kNoAllocMaxTraj == FPT_MLP_GRAD_NOALLOC_MAX, "the header's limit");
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+static constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static unsigned char *g_scratch_ptr[kMaxDevices] = {};
+
+// The device address of this device's copy of scratch (the current device must be dev).
+static int noalloc_scratch(int dev, unsigned char **out)
+{
+    if (dev < 0 || dev >= kMaxDevices) return fail(FPT_EUNSUPPORTED, "device %d beyond the scratch table", dev);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+        g_scratch_ptr[dev] = static_cast<unsigned char *>(ptr);
+    }
+    *out = g_scratch_ptr[dev];
+    return FPT_OK;
+}
+
+extern "C" int fpt_mlp_grad_noalloc(fpt_ctx *c, uint64_t n_traj, double dN, uint64_t seed, uint64_t traj_offset,
+                                    double tail_lo, int32_t objective, void *hip_stream, float *d_grad,
+                                    double *d_G, double *J_out, uint64_t *n_tail_out)
+{
+    int rc = mlp_grad_check(c, n_traj, dN, traj_offset, tail_lo, objective, d_grad);
+    if (rc) return rc;
+    if (n_traj > kNoAllocMaxTraj)
+        return fail(FPT_EINVAL, "n_traj %llu exceeds FPT_MLP_GRAD_NOALLOC_MAX (%zu): the static scratch holds no more",
+                    (unsigned long long)n_traj, kNoAllocMaxTraj);
+    unsigned char *sb = nullptr;
+    rc = noalloc_scratch(c->device, &sb);
+    if (rc) return rc;
+    return mlp_grad_run(c, n_traj, dN, seed, traj_offset, tail_lo, objective, static_cast<hipStream_t>(hip_stream),
+                        d_grad, d_G, J_out, n_tail_out, sb, kNoAllocMaxTraj);
 }
 
 extern "C" int fpt_mlp_adam(fpt_ctx *c, const float *d_grad, double lr, double beta1, double beta2, double eps,

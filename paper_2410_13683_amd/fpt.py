@@ -41,6 +41,7 @@ FPT_MAX_BINS = 1024
 FPT_MLP_NPARAM = 4482
 FPT_MLP_MAX_GRID = 1024
 FPT_MLP_OBJ_J, FPT_MLP_OBJ_LOG_J = 0, 1
+FPT_MLP_GRAD_NOALLOC_MAX = 1 << 18
 
 _dp = ctypes.POINTER(ctypes.c_double)
 _fp = ctypes.POINTER(ctypes.c_float)
@@ -171,6 +172,7 @@ def load():
     L.fpt_mlp_grad.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_double, ctypes.c_uint64, ctypes.c_uint64,
                                ctypes.c_double, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, _dp,
                                _u64p]
+    L.fpt_mlp_grad_noalloc.argtypes = L.fpt_mlp_grad.argtypes
     L.fpt_mlp_adam.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                ctypes.c_double, ctypes.c_void_p]
     for name in ("fpt_create", "fpt_run", "fpt_histogram", "fpt_reset", "fpt_last_kernel_ms",
@@ -178,7 +180,7 @@ def load():
                  "fpt_noise_table_matched_time", "fpt_noise_table_bessel2d_time", "fpt_jackknife", "fpt_lognormal_bins",
                  "fpt_merge_bins", "fpt_density", "fpt_tail_at", "fpt_tail_find", "fpt_batch_create", "fpt_batch_run", "fpt_batch_autotune",
                  "fpt_batch_config", "fpt_batch_last_ms", "fpt_mlp_set", "fpt_mlp_get", "fpt_mlp_table",
-                 "fpt_mlp_grad", "fpt_mlp_adam"):
+                 "fpt_mlp_grad", "fpt_mlp_grad_noalloc", "fpt_mlp_adam"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -442,15 +444,17 @@ class Context:
         return a.reshape(self.grid_n)
 
     def mlp_grad(self, n_traj: int, dN: float, seed: int, tail_lo: float, d_grad, traj_offset: int = 0, stream=None,
-                 d_G=None, want_J: bool = True, objective: int = FPT_MLP_OBJ_J):
+                 d_G=None, want_J: bool = True, objective: int = FPT_MLP_OBJ_J, noalloc: bool = False):
         """Fill d_grad (device, 4482 float32) with dJ/dtheta (or d ln J/dtheta); returns (J, n_tail)
-        when want_J."""
+        when want_J.  noalloc selects fpt_mlp_grad_noalloc (no device allocation; n_traj at most
+        FPT_MLP_GRAD_NOALLOC_MAX)."""
         J = ctypes.c_double()
         nt = ctypes.c_uint64()
-        _check(self._lib.fpt_mlp_grad(self._h, n_traj, dN, seed, traj_offset, tail_lo, objective,
-                                      _stream_handle(stream),
-                                      _ptr(d_grad), _ptr(d_G), ctypes.byref(J) if want_J else None,
-                                      ctypes.byref(nt) if want_J else None), "fpt_mlp_grad")
+        name = "fpt_mlp_grad_noalloc" if noalloc else "fpt_mlp_grad"
+        _check(getattr(self._lib, name)(self._h, n_traj, dN, seed, traj_offset, tail_lo, objective,
+                                        _stream_handle(stream),
+                                        _ptr(d_grad), _ptr(d_G), ctypes.byref(J) if want_J else None,
+                                        ctypes.byref(nt) if want_J else None), name)
         return (J.value, int(nt.value)) if want_J else None
 
     def mlp_adam(self, d_grad, lr: float, beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8,
