@@ -212,6 +212,18 @@ __device__ __forceinline__ uint32_t lanes_below(uint64_t mask)
     return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
 }
 
+// Steps left before max_steps for the wave's most advanced lane that holds a trajectory, as a
+// wave-uniform value (such a lane has at most max_steps steps: a lane reaching it is censored).
+// At the start of a chunk it bounds every lane's count inside the chunk (all lanes step
+// together), so whether a group can reach max_steps is one scalar comparison per group.
+__device__ __forceinline__ uint32_t wave_steps_left(bool has, uint32_t n, uint32_t max_steps)
+{
+    uint32_t v = has ? n : 0u;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = max(v, (uint32_t)__shfl_xor((int)v, o));
+    return max_steps - __builtin_amdgcn_readfirstlane(v);
+}
+
 // Wave-aggregated claim of trajectories from the global cursor.  Must be
 // reached by every lane of the wave.  Returns true in lanes that got one.
 __device__ __forceinline__ bool claim(bool need, uint64_t &rel, unsigned long long *cursor, uint64_t n_traj,
@@ -533,7 +545,8 @@ __device__ __forceinline__ void grad_add(T s[4], T c, T f0, T f1)
 // trajectory (first passage, eps_1 >= 1) is recorded in a branch that is taken
 // about once per 1e4-1e5 steps and retired once the group is done.  Censoring
 // at max_steps needs a test before every step, so groups that can reach
-// max_steps take a separate variant.  GRAD: replay the trajectories listed in
+// max_steps take a separate variant; which groups can is decided once per chunk
+// from the wave's largest step count (wave_steps_left).  GRAD: replay the trajectories listed in
 // rp.tail (cursor over the list) and scatter the gradient factors instead of
 // retiring into the histogram.
 // ---------------------------------------------------------------------------
@@ -668,6 +681,7 @@ __device__ __forceinline__ void lanes_fp64(const Inst &I, const RunArgs &R, cons
     };
 
     while (__any(has)) {
+        const uint32_t left = wave_steps_left(has, n, I.max_steps);
         for (int k = 0; k < R.chunk; k += 4) {
             if (!__any(live)) break;
             uint32_t w[4];
@@ -675,7 +689,7 @@ __device__ __forceinline__ void lanes_fp64(const Inst &I, const RunArgs &R, cons
             double z[4];
             box_muller64(w[0], w[1], sqrt_dN, l_bm, z[0], z[1]);
             box_muller64(w[2], w[3], sqrt_dN, l_bm, z[2], z[3]);
-            if (__any(live && n + 4 > I.max_steps)) group(std::integral_constant<bool, true>(), z);
+            if ((uint32_t)k + 4 > left) group(std::integral_constant<bool, true>(), z);
             else group(std::integral_constant<bool, false>(), z);
         }
         if (!live) has = false;
@@ -904,12 +918,19 @@ __device__ __forceinline__ void lanes_fp32(const Inst &I, const RunArgs &R, cons
             // live and fresh are updated outside the branch, so that they stay lane masks
             const bool hit = live && (crossed || ended);
             if (hit) {
-                const bool cr = xs <= 0.0f;
-                ev_code = (n + j + 1) | (cr ? 0u : kFlagEndedEarly);
-                const double x0 = (double)xh + (double)x0l;
-                const double x1 = (double)xh + (double)xl;
-                ev_N = cr ? (double)(n + j) * dN + dN * (x0 / (x0 - x1)) : (double)(n + j + 1) * dN;
-                ev_lnw = lnw_now(n + j + 1);
+                // both candidates, then a select on the crossing mask: no divergent branch inside.
+                // The state passes through an empty volatile asm first, which keeps the compiler
+                // from moving this rarely taken work in front of the branch (into every step).
+                float bh = xh, b0 = x0l, b1 = xl;
+                uint32_t nb = n + j;
+                asm volatile("; passage event" : "+v"(bh), "+v"(b0), "+v"(b1), "+v"(nb));
+                const double x0 = (double)bh + (double)b0;
+                const double x1 = (double)bh + (double)b1;
+                const double N_cross = (double)nb * dN + dN * (x0 / (x0 - x1));
+                const double N_end = (double)(nb + 1) * dN;
+                ev_code = (nb + 1) | (crossed ? 0u : kFlagEndedEarly);
+                ev_N = crossed ? N_cross : N_end;
+                ev_lnw = lnw_now(nb + 1);
             }
             live = live && !hit;
             fresh = fresh || hit;
@@ -935,6 +956,7 @@ __device__ __forceinline__ void lanes_fp32(const Inst &I, const RunArgs &R, cons
     };
 
     while (__any(has)) {
+        const uint32_t left = wave_steps_left(has, n, I.max_steps);
         for (int k = 0; k < R.chunk; k += 4) {
             if (!__any(live)) break;
             uint32_t w[4];
@@ -943,7 +965,7 @@ __device__ __forceinline__ void lanes_fp32(const Inst &I, const RunArgs &R, cons
             const float off = (BIAS == kBiasConst) ? c.adN : 0.0f;
             box_muller32(w[0], w[1], c.m2ln2_dN, off, z[0], z[1]);
             box_muller32(w[2], w[3], c.m2ln2_dN, off, z[2], z[3]);
-            if (__builtin_amdgcn_ballot_w64(live && n + 4 > I.max_steps) != 0)
+            if ((uint32_t)k + 4 > left)
                 group(std::integral_constant<bool, true>(), z);
             else
                 group(std::integral_constant<bool, false>(), z);
@@ -1074,6 +1096,7 @@ __device__ __forceinline__ void lanes_fp64_2d(const Inst &I, const RunArgs &R, c
     };
 
     while (__any(has)) {
+        const uint32_t left = wave_steps_left(has, n, I.max_steps);
         for (int k = 0; k < R.chunk; k += 2) {
             if (!__any(live)) break;
             uint32_t w[4];
@@ -1081,7 +1104,7 @@ __device__ __forceinline__ void lanes_fp64_2d(const Inst &I, const RunArgs &R, c
             double z[4];
             box_muller64(w[0], w[1], sqrt_dN, l_bm, z[0], z[1]);
             box_muller64(w[2], w[3], sqrt_dN, l_bm, z[2], z[3]);
-            if (__any(live && n + 2 > I.max_steps)) group(std::integral_constant<bool, true>(), z);
+            if ((uint32_t)k + 2 > left) group(std::integral_constant<bool, true>(), z);
             else group(std::integral_constant<bool, false>(), z);
         }
         if (!live) has = false;
