@@ -422,7 +422,11 @@ typedef struct {
     int64_t max_steps;
 } orc_problem;
 
-static void orc_trajectory(const orc_problem *P, uint64_t traj, double *N_out, double *lnw_out, uint32_t *steps_out)
+/* phi2_out (may be NULL): phi before and after the last step taken (both the current phi for a */
+/* censored trajectory), what a reader needs to tell a floating-point near-tie at phi_end and a */
+/* short last step apart from a real disagreement.                                               */
+static void orc_trajectory(const orc_problem *P, uint64_t traj, double *N_out, double *lnw_out, uint32_t *steps_out,
+                           double *phi2_out)
 {
     const double dN = P->dN;
     const double sqrt_dN = sqrt(dN);
@@ -436,6 +440,7 @@ static void orc_trajectory(const orc_problem *P, uint64_t traj, double *N_out, d
             *N_out = NAN;
             *lnw_out = lnw;
             *steps_out = (uint32_t)n | ORC_FLAG_CENSORED;
+            if (phi2_out) { phi2_out[0] = phi; phi2_out[1] = phi; }
             return;
         }
         /* xi^(i) */
@@ -484,6 +489,7 @@ static void orc_trajectory(const orc_problem *P, uint64_t traj, double *N_out, d
             *N_out = (double)(n - 1) * dN + dN * frac;
             *lnw_out = lnw;
             *steps_out = (uint32_t)n;
+            if (phi2_out) { phi2_out[0] = phi; phi2_out[1] = phi_next; }
             return;
         }
         if (pi_next * pi_next / 2.0 >= 1.0) {
@@ -491,6 +497,7 @@ static void orc_trajectory(const orc_problem *P, uint64_t traj, double *N_out, d
             *N_out = (double)n * dN;
             *lnw_out = lnw;
             *steps_out = (uint32_t)n | ORC_FLAG_ENDED_EARLY;
+            if (phi2_out) { phi2_out[0] = phi; phi2_out[1] = phi_next; }
             return;
         }
         phi = phi_next;
@@ -506,7 +513,8 @@ int orc_run(int kind, const double pot[7],
             int bias_kind, double A_bias, const float *mlp_params, const double *mlp_norm,
             int mlp_every, const int grid_n[2], const double grid_range[4],
             double dN, uint64_t seed, uint32_t instance, uint64_t traj_offset, uint64_t n_traj,
-            int64_t max_steps, double *N_out, double *lnw_out, uint32_t *steps_out, int n_threads)
+            int64_t max_steps, double *N_out, double *lnw_out, uint32_t *steps_out, double *phi2_out,
+            int n_threads)
 {
     if (n_tab < 1 || !(dN > 0.0) || max_steps < 1 || max_steps > (int64_t)ORC_STEP_MASK) return -1;
     if (!(phi_in > phi_end)) return -1;
@@ -539,7 +547,8 @@ int orc_run(int kind, const double pot[7],
     int64_t nt = (int64_t)n_traj;
 #pragma omp parallel for num_threads(n_thr) schedule(dynamic, 16)
     for (int64_t i = 0; i < nt; ++i)
-        orc_trajectory(&P, traj_offset + (uint64_t)i, &N_out[i], &lnw_out[i], &steps_out[i]);
+        orc_trajectory(&P, traj_offset + (uint64_t)i, &N_out[i], &lnw_out[i], &steps_out[i],
+                       phi2_out ? &phi2_out[2 * i] : NULL);
     free(grid_a);
     return 0;
 }
@@ -610,7 +619,7 @@ int orc_mlp_replay_grad(int kind, const double pot[7],
             uint64_t traj = traj_offset + (uint64_t)i;
             double N, lnw_old;
             uint32_t steps;
-            orc_trajectory(&P, traj, &N, &lnw_old, &steps);
+            orc_trajectory(&P, traj, &N, &lnw_old, &steps, NULL);
             if (steps & (ORC_FLAG_CENSORED | ORC_FLAG_ENDED_EARLY)) continue;
             if (!(N - N_ref >= tail_lo)) continue;
             /* replay the same path: states and noise are those drawn under theta_old */
@@ -717,7 +726,7 @@ int orc_grid_replay_grad(int kind, const double pot[7],
             const uint64_t traj = traj_offset + (uint64_t)i;
             double N, lnw_old;
             uint32_t steps;
-            orc_trajectory(&P, traj, &N, &lnw_old, &steps);
+            orc_trajectory(&P, traj, &N, &lnw_old, &steps, NULL);
             if (steps & (ORC_FLAG_CENSORED | ORC_FLAG_ENDED_EARLY)) continue;
             if (!(N - N_ref >= tail_lo)) continue;
             const uint32_t n_steps = steps & ORC_STEP_MASK;
@@ -976,7 +985,7 @@ static void orc_table2d_lookup(const orc_problem2d *P, double phi, double S[3], 
 /* axis of Xi (phi component >= 0), i.e. the push A along e in noise space:    */
 /* in the rank-1 limit Xi = s s^T it is B = A s, the 1D bias of Sec. 4.1.       */
 static void orc_trajectory2d(const orc_problem2d *P, uint64_t traj, double *N_out, double *lnw_out,
-                             uint32_t *steps_out)
+                             uint32_t *steps_out, double *phi2_out)
 {
     const double dN = P->dN;
     const double sqrt_dN = sqrt(dN);
@@ -989,6 +998,7 @@ static void orc_trajectory2d(const orc_problem2d *P, uint64_t traj, double *N_ou
             *N_out = NAN;
             *lnw_out = lnw;
             *steps_out = (uint32_t)n | ORC_FLAG_CENSORED;
+            if (phi2_out) { phi2_out[0] = phi; phi2_out[1] = phi; }
             return;
         }
         const uint64_t call = (uint64_t)n >> 1;
@@ -1024,12 +1034,14 @@ static void orc_trajectory2d(const orc_problem2d *P, uint64_t traj, double *N_ou
             *N_out = (double)(n - 1) * dN + dN * frac;
             *lnw_out = lnw;
             *steps_out = (uint32_t)n;
+            if (phi2_out) { phi2_out[0] = phi; phi2_out[1] = phi_next; }
             return;
         }
         if (pi_next * pi_next / 2.0 >= 1.0) {
             *N_out = (double)n * dN;
             *lnw_out = lnw;
             *steps_out = (uint32_t)n | ORC_FLAG_ENDED_EARLY;
+            if (phi2_out) { phi2_out[0] = phi; phi2_out[1] = phi_next; }
             return;
         }
         phi = phi_next;
@@ -1045,7 +1057,8 @@ int orc_run2d(int kind, const double pot[7], int n_tab, double phi_lo, double ph
               const double *Xpq, const double *Xqq, int tab_axis, double phi_in, double pi_in, double phi_end,
               int bias_kind,
               double A_bias, double dN, uint64_t seed, uint32_t instance, uint64_t traj_offset, uint64_t n_traj,
-              int64_t max_steps, double *N_out, double *lnw_out, uint32_t *steps_out, int n_threads)
+              int64_t max_steps, double *N_out, double *lnw_out, uint32_t *steps_out, double *phi2_out,
+              int n_threads)
 {
     if (n_tab < 1 || !(dN > 0.0) || max_steps < 1 || max_steps > (int64_t)ORC_STEP_MASK) return -1;
     if (!(phi_in > phi_end)) return -1;
@@ -1076,7 +1089,8 @@ int orc_run2d(int kind, const double pot[7], int n_tab, double phi_lo, double ph
     const int64_t nt = (int64_t)n_traj;
 #pragma omp parallel for num_threads(n_thr) schedule(dynamic, 16)
     for (int64_t i = 0; i < nt; ++i)
-        orc_trajectory2d(&P, traj_offset + (uint64_t)i, &N_out[i], &lnw_out[i], &steps_out[i]);
+        orc_trajectory2d(&P, traj_offset + (uint64_t)i, &N_out[i], &lnw_out[i], &steps_out[i],
+                         phi2_out ? &phi2_out[2 * i] : NULL);
     free(S);
     return 0;
 }

@@ -78,7 +78,7 @@ def lib():
                               ctypes.c_double, ctypes.c_double, ctypes.c_double,
                               ctypes.c_int, ctypes.c_double, fp, dp, ctypes.c_int, ip, dp,
                               ctypes.c_double, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint64,
-                              ctypes.c_uint64, ctypes.c_int64, dp, dp, u32p, ctypes.c_int]
+                              ctypes.c_uint64, ctypes.c_int64, dp, dp, u32p, dp, ctypes.c_int]
         L.orc_run.restype = ctypes.c_int
         L.orc_max_threads.argtypes = []
         L.orc_max_threads.restype = ctypes.c_int
@@ -113,7 +113,7 @@ def lib():
         L.orc_run2d.argtypes = [ctypes.c_int, dp, ctypes.c_int, ctypes.c_double, ctypes.c_double, dp, dp, dp,
                                 ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_int, ctypes.c_double,
                                 ctypes.c_double, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_uint64,
-                                ctypes.c_int64, dp, dp, u32p, ctypes.c_int]
+                                ctypes.c_int64, dp, dp, u32p, dp, ctypes.c_int]
         L.orc_run2d.restype = ctypes.c_int
         L.orc_principal_axis.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_double, dp, dp]
         L.orc_principal_axis.restype = None
@@ -261,13 +261,15 @@ def noise_table_matched_time(kind, V0, phi_T, A_plus, A_minus, sigma, n, t_lo, t
 
 
 def run(prob: Problem, dN: float, seed: int, n_traj: int, traj_offset: int = 0, instance: int = 0,
-        max_steps: int = STEP_MASK, n_threads: int = 0):
-    """Per-trajectory (N, ln w, steps|flags) for trajectories traj_offset .. +n_traj-1."""
+        max_steps: int = STEP_MASK, n_threads: int = 0, last_phi: bool = False):
+    """Per-trajectory (N, ln w, steps|flags) for trajectories traj_offset .. +n_traj-1; with
+    last_phi also an (n_traj, 2) array of phi before and after each trajectory's last step."""
     S = np.ascontiguousarray(prob.S, dtype=np.float64)
     t = np.ascontiguousarray(prob.tan_theta, dtype=np.float64)
     N = np.empty(n_traj, dtype=np.float64)
     lnw = np.empty(n_traj, dtype=np.float64)
     steps = np.empty(n_traj, dtype=np.uint32)
+    phi2 = np.empty((n_traj, 2)) if last_phi else None
     mlp = (np.ascontiguousarray(prob.mlp_params, dtype=np.float32)
            if prob.mlp_params is not None else np.zeros(MLP_NPARAM, dtype=np.float32))
     norm = (np.ascontiguousarray(prob.mlp_norm, dtype=np.float64)
@@ -278,10 +280,11 @@ def run(prob: Problem, dN: float, seed: int, n_traj: int, traj_offset: int = 0, 
     rc = lib().orc_run(prob.kind, _dp(pot), len(S), prob.phi_lo, prob.phi_hi, _dp(S), _dp(t), int(prob.tab_axis),
                        prob.phi_in, prob.pi_in, prob.phi_end, prob.bias_kind, prob.A_bias,
                        _fp(mlp), _dp(norm), prob.mlp_every, gn, _dp(gr), dN, seed, instance, traj_offset,
-                       n_traj, max_steps, _dp(N), _dp(lnw), _u32p(steps), n_threads)
+                       n_traj, max_steps, _dp(N), _dp(lnw), _u32p(steps), _dp(phi2) if last_phi else None,
+                       n_threads)
     if rc != 0:
         raise ValueError("invalid oracle problem")
-    return N, lnw, steps
+    return (N, lnw, steps, phi2) if last_phi else (N, lnw, steps)
 
 
 def max_threads() -> int:
@@ -429,18 +432,21 @@ def normals2d(seed: int, instance: int, traj: int, n0: int, count: int) -> np.nd
 
 
 def run2d(prob: Problem2D, dN: float, seed: int, n_traj: int, traj_offset: int = 0, instance: int = 0,
-          max_steps: int = STEP_MASK, n_threads: int = 0):
+          max_steps: int = STEP_MASK, n_threads: int = 0, last_phi: bool = False):
+    """As run, with 2D noise."""
     X = [np.ascontiguousarray(x, dtype=np.float64) for x in (prob.Xpp, prob.Xpq, prob.Xqq)]
     N = np.empty(n_traj, dtype=np.float64)
     lnw = np.empty(n_traj, dtype=np.float64)
     steps = np.empty(n_traj, dtype=np.uint32)
+    phi2 = np.empty((n_traj, 2)) if last_phi else None
     pot = prob.pot()
     rc = lib().orc_run2d(prob.kind, _dp(pot), len(X[0]), prob.phi_lo, prob.phi_hi, *[_dp(x) for x in X],
                          int(prob.tab_axis), prob.phi_in, prob.pi_in, prob.phi_end, prob.bias_kind, prob.A_bias, dN, seed, instance,
-                         traj_offset, n_traj, max_steps, _dp(N), _dp(lnw), _u32p(steps), n_threads)
+                         traj_offset, n_traj, max_steps, _dp(N), _dp(lnw), _u32p(steps),
+                         _dp(phi2) if last_phi else None, n_threads)
     if rc != 0:
         raise ValueError("invalid oracle problem")
-    return N, lnw, steps
+    return (N, lnw, steps, phi2) if last_phi else (N, lnw, steps)
 
 
 # --------------------------------------------------------------------------

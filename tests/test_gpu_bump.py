@@ -19,7 +19,7 @@ from oracle import oracle as orc  # noqa: E402
 from paper_2410_13683_amd import fpt  # noqa: E402
 from paper_2410_13683_amd import runner  # noqa: E402
 from paper_2410_13683_amd import workloads as W  # noqa: E402
-from tests._glue import assert_fp64_parity, oracle_problem, oracle_run  # noqa: E402
+from tests._glue import assert_fp64_parity, oracle_problem, oracle_run, oracle_sampled  # noqa: E402
 from tests._gpu import gpu_run  # noqa: E402
 
 
@@ -59,8 +59,8 @@ def test_fp64_bump_parity(A_bias):
     w = W.gaussian_bump(n_traj=1500, A_bias=A_bias)
     say(f"fp64 bump A={A_bias}")
     gpu, _ = gpu_run(w)
-    ora = oracle_run(w)
-    assert_fp64_parity(gpu, ora)
+    ora = oracle_run(w, last_phi=True)
+    assert_fp64_parity(gpu, ora, w)
     if A_bias:
         assert np.std(gpu[1]) > 0.1
 
@@ -169,8 +169,8 @@ def test_fp64_bump_time_parity(A_bias):
     w = W.gaussian_bump_time(n_traj=2000, A_bias=A_bias)
     say(f"fp64 bump time A={A_bias}")
     gpu, _ = gpu_run(w)
-    ora = oracle_run(w)
-    assert_fp64_parity(gpu, ora)
+    ora = oracle_run(w, last_phi=True)
+    assert_fp64_parity(gpu, ora, w)
 
 
 def test_bump_time_and_phi_windows_agree_in_the_core():
@@ -196,9 +196,7 @@ def test_bump_bench_configuration_sampled(window):
     say(f"bump bench configuration, {window} window")
     (N, lnw, st), hist = gpu_run(w)
     idx = np.unique(np.concatenate([np.linspace(0, w.n_traj - 1, 79).astype(np.int64), [w.n_traj - 1]]))
-    p = oracle_problem(w)              # the oracle's own table, built once
-    for i in idx:
-        No, lo_, so = orc.run(p, w.dN, w.seed, 1, traj_offset=int(i))
-        assert_fp64_parity((N[i:i + 1], lnw[i:i + 1], st[i:i + 1]), (No, lo_, so), max_step_mismatch=1.0)
+    ex = assert_fp64_parity((N[idx], lnw[idx], st[idx]), oracle_sampled(w, idx, oracle_problem(w)), w)
+    say(f"  {len(idx)} sampled: {ex}")
     assert hist["n_traj"] == w.n_traj and int(hist["count"].sum()) == w.n_traj
     assert hist["n_steps_total"] == int((st & fpt.FPT_STEP_MASK).astype(np.int64).sum())

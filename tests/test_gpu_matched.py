@@ -145,8 +145,8 @@ def test_fp64_trajectories_on_matched_table():
     w = W.srusr_matched(n_traj=1500)
     say("fp64 trajectories matched table")
     gpu, _ = gpu_run(w)
-    ora = oracle_run(w)
-    assert_fp64_parity(gpu, ora)
+    ora = oracle_run(w, last_phi=True)
+    assert_fp64_parity(gpu, ora, w)
 
 
 def test_fp32_trajectories_on_matched_table():

@@ -85,8 +85,8 @@ def test_fp64_learned_control_ig_parity():
     w = _ig(n=3000)
     say(f"fp64 learned ig n={w.n_traj}")
     gpu, hist = gpu_run(w)
-    ora = oracle_run(w)
-    assert_fp64_parity(gpu, ora)
+    ora = oracle_run(w, last_phi=True)
+    assert_fp64_parity(gpu, ora, w)
     assert np.std(gpu[1]) > 0.1          # the control varies: log-weights are not trivial
 
 
@@ -96,8 +96,8 @@ def test_fp64_learned_control_srusr_parity():
     w = _srusr(1500, 41, W.mlp_random(7, scale=0.2, out_bias=1.0))
     say(f"fp64 learned srusr n={w.n_traj}")
     gpu, _ = gpu_run(w)
-    ora = oracle_run(w)
-    assert_fp64_parity(gpu, ora)
+    ora = oracle_run(w, last_phi=True)
+    assert_fp64_parity(gpu, ora, w)
 
 
 @pytest.mark.parametrize("precision", [0, 1])
@@ -250,7 +250,8 @@ def test_training_lowers_tail_second_moment_and_stays_unbiased():
     """Inverse-Gaussian companion, tail T = {deltaN >= 5 sigma_N}: start from the constant
     control a = 1 (too weak for this tail), take Adam steps on the replay gradient, and compare
     the tail second moment J and the estimate of P_T before and after on fresh trajectories.
-    Training must lower J by a large factor and both estimates must match the closed form."""
+    Training must lower J by a large factor (17x measured; the bar is 8x) and both estimates must
+    match the closed form."""
     w = _ig(n=100_000, seed=50, params=W.mlp_constant_init(1.0, seed=3), dN=1e-4)
     mu = (w.phi_in - w.phi_end) / w.A_plus
     lam = (w.phi_in - w.phi_end) ** 2 / w.noise_S ** 2
@@ -282,4 +283,4 @@ def test_training_lowers_tail_second_moment_and_stays_unbiased():
     ctx.destroy()
     for p, se in ((p0, se0), (p1, se1)):
         assert abs(p / exact - 1.0) < 0.05 + 4 * se / exact
-    assert J1 < 0.5 * J0
+    assert J1 < J0 / 8.0

@@ -18,7 +18,7 @@ torch = pytest.importorskip("torch")
 from oracle import oracle as orc  # noqa: E402
 from paper_2410_13683_amd import fpt  # noqa: E402
 from paper_2410_13683_amd import workloads as W  # noqa: E402
-from tests._glue import assert_fp64_parity, oracle_run  # noqa: E402
+from tests._glue import assert_fp64_parity, oracle_run, oracle_sampled  # noqa: E402
 from tests._gpu import gpu_run  # noqa: E402
 
 
@@ -59,8 +59,8 @@ def test_fp64_2d_exponential_parity(A_bias):
     w = W.exponential_2d(n_traj=3000, A_bias=A_bias)
     say(f"fp64 2D exponential A={A_bias}")
     gpu, _ = gpu_run(w)
-    ora = oracle_run(w)
-    assert_fp64_parity(gpu, ora)
+    ora = oracle_run(w, last_phi=True)
+    assert_fp64_parity(gpu, ora, w)
     if A_bias:
         assert np.std(gpu[1]) > 0.1
 
@@ -71,8 +71,8 @@ def test_fp64_2d_srusr_parity(A_bias):
     w = W.srusr_2d(n_traj=1500, A_bias=A_bias)
     say(f"fp64 2D srusr A={A_bias}")
     gpu, _ = gpu_run(w)
-    ora = oracle_run(w)
-    assert_fp64_parity(gpu, ora)
+    ora = oracle_run(w, last_phi=True)
+    assert_fp64_parity(gpu, ora, w)
 
 
 def test_2d_launch_configuration_does_not_change_results():
@@ -89,9 +89,8 @@ def test_2d_full_size_sampled():
     say(f"fp64 2D full size n={w.n_traj}")
     (N, lnw, st), hist = gpu_run(w)
     idx = np.unique(np.concatenate([np.linspace(0, w.n_traj - 1, 100).astype(np.int64), [w.n_traj - 1]]))
-    for i in idx:
-        No, lo_, so = oracle_run(w, n_traj=1, traj_offset=int(i))
-        assert_fp64_parity((N[i:i + 1], lnw[i:i + 1], st[i:i + 1]), (No, lo_, so), max_step_mismatch=1.0)
+    ex = assert_fp64_parity((N[idx], lnw[idx], st[idx]), oracle_sampled(w, idx), w)
+    say(f"  {len(idx)} sampled: {ex}")
     assert hist["n_traj"] == w.n_traj and int(hist["count"].sum()) == w.n_traj
 
 

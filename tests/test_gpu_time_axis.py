@@ -25,7 +25,7 @@ torch = pytest.importorskip("torch")
 from oracle import oracle as orc  # noqa: E402
 from paper_2410_13683_amd import fpt  # noqa: E402
 from paper_2410_13683_amd import workloads as W  # noqa: E402
-from tests._glue import assert_fp64_parity, oracle_problem2d, oracle_run  # noqa: E402
+from tests._glue import assert_fp64_parity, oracle_problem2d, oracle_run, oracle_sampled  # noqa: E402
 from tests._gpu import gpu_context, gpu_run  # noqa: E402
 
 
@@ -119,8 +119,8 @@ def test_fp64_trajectories_on_time_table(tau_hi, A_bias):
                                                        A_bias=A_bias)
     say(f"fp64 time table tau_hi={tau_hi} A={A_bias}")
     gpu, _ = gpu_run(w)
-    ora = oracle_run(w)
-    assert_fp64_parity(gpu, ora)
+    ora = oracle_run(w, last_phi=True)
+    assert_fp64_parity(gpu, ora, w)
     N = gpu[0]
     if tau_hi == 6.0:
         # every run outlasts the noise
@@ -215,8 +215,8 @@ def test_fp64_2d_trajectories_on_time_table(tau_hi, A_bias):
     w = W.srusr_2d_time(n_traj=1500, tau_hi=tau_hi, A_bias=A_bias)
     say(f"fp64 2D time table tau_hi={tau_hi} A={A_bias}")
     gpu, _ = gpu_run(w)
-    ora = oracle_run(w)
-    assert_fp64_parity(gpu, ora)
+    ora = oracle_run(w, last_phi=True)
+    assert_fp64_parity(gpu, ora, w)
     if A_bias:
         assert np.std(gpu[1]) > 0.05
 
@@ -228,10 +228,8 @@ def test_2d_time_full_size_sampled():
     say(f"fp64 2D time full size n={w.n_traj}")
     (N, lnw, st), hist = gpu_run(w)
     idx = np.unique(np.concatenate([np.linspace(0, w.n_traj - 1, 60).astype(np.int64), [w.n_traj - 1]]))
-    p = oracle_problem2d(w)            # the oracle's own table, built once
-    for i in idx:
-        No, lo_, so = orc.run2d(p, w.dN, w.seed, 1, traj_offset=int(i))
-        assert_fp64_parity((N[i:i + 1], lnw[i:i + 1], st[i:i + 1]), (No, lo_, so), max_step_mismatch=1.0)
+    ex = assert_fp64_parity((N[idx], lnw[idx], st[idx]), oracle_sampled(w, idx, oracle_problem2d(w)), w)
+    say(f"  {len(idx)} sampled: {ex}")
     assert hist["n_traj"] == w.n_traj and int(hist["count"].sum()) == w.n_traj
     d = N - w.N_ref
     say(f"  mean deltaN {d.mean():.4e} sd {d.std():.4e}")

@@ -200,3 +200,21 @@ def test_censoring_and_early_end_flags(orc):
     N, lnw, steps = orc.run(p, 1e-3, 1, 3)
     assert np.all(steps == (1 | orc.FLAG_ENDED_EARLY))
     np.testing.assert_allclose(N, 1e-3)
+
+
+def test_last_step_phi_values(orc):
+    """The oracle's phi before and after each trajectory's last step (what the per-trajectory
+    parity check uses to recognise near-ties): phi before it is the state a run capped one step
+    earlier ends in, the step crosses phi_end, and the interpolation N = (n - 1 + f) dN with
+    f = (phi_(n-1) - phi_end)/(phi_(n-1) - phi_n) gives the oracle's N."""
+    w = W.srusr_bessel(n_traj=40, seed=29).with_(bias_kind=W.BIAS_CONST, A_bias=1.0)
+    N, lnw, st, phi2 = oracle_run(w, last_phi=True)
+    n = (st & orc.STEP_MASK).astype(np.int64)
+    assert np.all((st & (orc.FLAG_CENSORED | orc.FLAG_ENDED_EARLY)) == 0)
+    assert np.all(phi2[:, 0] > w.phi_end) and np.all(phi2[:, 1] <= w.phi_end)
+    f = (phi2[:, 0] - w.phi_end) / (phi2[:, 0] - phi2[:, 1])
+    np.testing.assert_allclose(N, (n - 1) * w.dN + w.dN * f, rtol=1e-15)
+    for i in (0, 17, 39):
+        _, _, st_c, phi2_c = oracle_run(w.with_(max_steps=int(n[i] - 1)), n_traj=1, traj_offset=i, last_phi=True)
+        assert st_c[0] == (n[i] - 1) | orc.FLAG_CENSORED
+        assert phi2_c[0, 0] == phi2_c[0, 1] == phi2[i, 0]
