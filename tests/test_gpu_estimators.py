@@ -168,3 +168,43 @@ def test_merge_across_bias_amplitudes_follows_closed_form(_gpu):
     assert ok.sum() >= 15 and exact[ok].min() < 1e-6
     # the Euler-Maruyama overshoot (O(S sqrt(dN))) shifts the law slightly; allow 5 % beside the errors
     assert np.all(rel < 0.05 + 4 * em[1:-1][ok] / exact[ok]), rel
+
+
+def test_normalisation_of_gpu_histogram_matches_oracle():
+    """Sec. 4.1's reconstruction of P(deltaN) end to end: the library's normalisation
+    (fpt_density, fpt_tail_find, fpt_tail_at) of a GPU histogram against the oracle's
+    normalisation of the oracle's histogram of its own trajectories.  SR -> USR problem, FP64,
+    bias A = 2, 2e4 trajectories, the 256 log bins of the FP32 benchmark: the densities and tail
+    sets agree to 1e-9 wherever the two histograms hold the same trajectories (an FP64 near-tie
+    may move one across an edge)."""
+    import torch
+    from oracle import oracle as orc
+    from tests._glue import oracle_run
+    from tests._gpu import gpu_run
+    w = W.srusr_is_fp32(2.0, n_traj=20_000).with_(precision=0, seed=51)
+    say(f"normalisation of a GPU histogram: {w.n_traj} trajectories")
+    torch.cuda.set_device(0)
+    _, h = gpu_run(w, dumps=False)
+    ho = orc.histogram(*oracle_run(w), w.N_ref, w.bins_kind, w.n_bins, w.lo, w.hi)
+    cg, co = h["count"].astype(np.int64), ho["count"].astype(np.int64)
+    assert np.abs(cg - co).sum() <= 2
+    d, edges, m = fpt.fpt_density(h, w.bins_kind, w.n_bins, w.lo, w.hi)
+    d_o, e_o = E.density(ho, w.bins_kind, w.n_bins, w.lo, w.hi)
+    m_o = E.moments(ho)
+    np.testing.assert_allclose(edges, e_o, rtol=1e-15)
+    same = (cg == co)[1:-1]
+    np.testing.assert_allclose(d[same], d_o[same], rtol=1e-9, atol=1e-300)
+    for k in ("mean_w", "mean_N", "ess"):
+        np.testing.assert_allclose(m[k], m_o[k], rtol=1e-6 if k == "ess" else 1e-9, err_msg=k)
+    suffix_same = np.cumsum((cg != co)[::-1])[::-1] == 0       # slots j.. hold the same trajectories
+    checked = 0
+    for p in (1e-4, 1e-6, 1e-8):
+        t, t_o = fpt.fpt_tail_find(h, w.bins_kind, w.n_bins, w.lo, w.hi, p), \
+            E.tail_find(ho, w.bins_kind, w.n_bins, w.lo, w.hi, p)
+        if t["slot"] > 0 and suffix_same[t["slot"]] and t["slot"] == t_o["slot"]:
+            for k in ("P", "P_err", "ess"):
+                np.testing.assert_allclose(t[k], t_o[k], rtol=1e-8, err_msg=(p, k))
+            assert t["count"] == t_o["count"]
+            checked += 1
+        say(f"  p = {p:g}: slot {t['slot']} (oracle {t_o['slot']}), P = {t['P']:.4e}, ESS_T = {t['ess']:.1f}")
+    assert checked >= 2
