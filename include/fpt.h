@@ -234,11 +234,14 @@ int fpt_create(const fpt_potential *pot, const fpt_noise_table *table, const fpt
 int fpt_run(fpt_ctx *ctx, uint64_t n_traj, double dN, uint64_t seed, uint64_t traj_offset,
             void *hip_stream, double *d_N, double *d_lnw, uint32_t *d_steps);
 
-/* Wait for the context's runs to finish and copy the accumulated histogram to
- * *out (host).  Errors: FPT_EINVAL (NULL arrays), FPT_EHIP. */
+/* Wait for the context's last run (fpt_run or a batch run) to finish and copy the accumulated
+ * histogram to *out (host).  Only that run is waited for, through the context's own event and
+ * stream, not other streams or contexts on the device; a caller that ran the context on several
+ * streams orders them itself.  Errors: FPT_EINVAL (NULL arrays), FPT_EHIP. */
 int fpt_histogram(fpt_ctx *ctx, fpt_hist *out);
 
-/* Zero the accumulated histogram (waits for outstanding runs first). */
+/* Zero the accumulated histogram after the context's last run (waited for as in fpt_histogram);
+ * returns when the accumulators are zero. */
 int fpt_reset(fpt_ctx *ctx);
 
 /* Wait for outstanding runs and free the context (NULL is allowed). */

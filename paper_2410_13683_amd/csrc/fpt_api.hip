@@ -317,7 +317,9 @@ struct fpt_ctx {
     unsigned long long *cursor = nullptr;
     void *d_mem = nullptr;
     hipEvent_t ev_start = nullptr, ev_stop = nullptr, ev_done = nullptr;
-    bool ran = false;
+    bool ran = false;                        // ev_start/ev_stop bracket the last fpt_run's kernel
+    bool pending = false;                    // ev_done marks the end of the last work on the accumulators
+    hipStream_t io_stream = nullptr;         // the context's own stream for reading and clearing them
     uint64_t n_traj_total = 0;
     bool drift_table_used = false;           // FP32 V'/V intervals (see build_drift_table)
     // learned control (FPT_BIAS_MLP)
@@ -534,8 +536,6 @@ extern "C" int fpt_create(const fpt_potential *pot, const fpt_noise_table *table
             if (!zero && !(a > 0.0 && a * c - b * b > 0.0))
                 return fail(FPT_EINVAL, "2D table node %d is neither zero nor positive definite", i);
         }
-        if (opts && opts->precision != FPT_FP64)
-            return fail(FPT_EUNSUPPORTED, "2D noise is implemented with FP64 state only");
         if (bias && bias->kind == FPT_BIAS_MLP) return fail(FPT_EUNSUPPORTED, "2D noise takes no learned bias");
     }
     if (nt > 1 && (!is_finite(table->phi_lo) || !is_finite(table->phi_hi) || !(table->phi_hi > table->phi_lo)))
@@ -591,7 +591,8 @@ extern "C" int fpt_create(const fpt_potential *pot, const fpt_noise_table *table
     const size_t off_tab32 = sizeof(double) * 2 * nt;
     const size_t off_rtab = off_tab32 + sizeof(float) * 4 * nt;
     const size_t off_tab2d = (off_rtab + sizeof(float) * 2 * nt + 15) & ~size_t(15);
-    const size_t off_cursor = (off_tab2d + (dim == 2 ? sizeof(double) * 6 * nt : 0) + 255) & ~size_t(255);
+    const size_t off_tab2d32 = off_tab2d + (dim == 2 ? sizeof(double) * 6 * nt : 0);
+    const size_t off_cursor = (off_tab2d32 + (dim == 2 ? sizeof(float) * 12 * nt : 0) + 255) & ~size_t(255);
     const size_t off_acc = off_cursor + 256;
     const size_t total = off_acc + acc_bytes(o.n_bins);
     if (e == hipSuccess) e = hipMalloc(&c->d_mem, total);
@@ -632,10 +633,28 @@ extern "C" int fpt_create(const fpt_potential *pot, const fpt_noise_table *table
     if (e == hipSuccess) e = hipMemcpy(base + off_rtab, hr.data(), sizeof(float) * 2 * nt, hipMemcpyHostToDevice);
     if (e == hipSuccess && dim == 2)
         e = hipMemcpy(base + off_tab2d, h2d.data(), sizeof(double) * h2d.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess && dim == 2) {
+        // FP32 records: value and slope to the next node of S_pp, S_pq, S_qq, e_phi, e_pi (the last
+        // node's slopes 0), then the V'/V interval of the FP32 table
+        std::vector<float> h2f(12 * (size_t)nt);
+        for (int i = 0; i < nt; ++i) {
+            const int k = (i + 1 < nt) ? i + 1 : i;
+            const double *q = &h2d[6 * (size_t)i], *qk = &h2d[6 * (size_t)k];
+            float *f = &h2f[12 * (size_t)i];
+            for (int m = 0; m < 5; ++m) {
+                f[2 * m] = (float)q[m];
+                f[2 * m + 1] = (float)qk[m] - (float)q[m];
+            }
+            f[10] = hr[2 * (size_t)i];
+            f[11] = hr[2 * (size_t)i + 1];
+        }
+        e = hipMemcpy(base + off_tab2d32, h2f.data(), sizeof(float) * h2f.size(), hipMemcpyHostToDevice);
+    }
     if (e == hipSuccess) e = hipMemset(base + off_cursor, 0, 256 + acc_bytes(o.n_bins));
     if (e == hipSuccess) e = hipEventCreate(&c->ev_start);
     if (e == hipSuccess) e = hipEventCreate(&c->ev_stop);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_done, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->io_stream, hipStreamNonBlocking);
     if (e != hipSuccess) {
         fpt_destroy(c);
         return hip_fail(e, "fpt_create initialisation");
@@ -654,6 +673,7 @@ extern "C" int fpt_create(const fpt_potential *pot, const fpt_noise_table *table
     I.rtab32 = reinterpret_cast<const float2 *>(base + off_rtab);
     I.noise_dim = dim;
     I.tab64_2d = reinterpret_cast<const double2 *>(base + off_tab2d);
+    I.tab32_2d = reinterpret_cast<const float4 *>(base + off_tab2d32);
     I.all_S_pos = all_pos ? 1 : 0;
     I.bias_kind = b.kind;
     I.A = (b.kind == FPT_BIAS_CONST) ? b.A : 0.0;
@@ -675,7 +695,7 @@ extern "C" int fpt_create(const fpt_potential *pot, const fpt_noise_table *table
         }
     }
     const int n_cells = grid_cells(I);
-    size_t need = dim == 2 ? em2d_lds_bytes(o.n_bins, nt) : em_lds_bytes(o.n_bins, nt, o.precision, n_cells);
+    size_t need = dim == 2 ? em2d_lds_bytes(o.n_bins, nt, o.precision) : em_lds_bytes(o.n_bins, nt, o.precision, n_cells);
     if (b.kind == FPT_BIAS_MLP)
         need = std::max(need, replay_lds_bytes(nt, o.precision, n_cells, c->grid.n0 * c->grid.n1));
     if (need > c->lds_per_block_max) {
@@ -727,20 +747,22 @@ extern "C" int fpt_run(fpt_ctx *c, uint64_t n_traj, double dN, uint64_t seed, ui
     const int block = c->opt.block_size ? c->opt.block_size : 1024;
     int grid = 0;
     const bool two_d = c->inst.noise_dim == 2;
-    const void *fn = two_d ? em2d_kernel_ptr(c->inst.bias_kind, c->inst.all_S_pos != 0, tab_mode(c->inst) == 2)
+    const void *fn = two_d ? em2d_kernel_ptr(c->precision, c->inst.bias_kind, c->inst.all_S_pos != 0,
+                                             tab_mode(c->inst) == 2)
                            : em_kernel_ptr(c->precision, c->inst.bias_kind, tab_mode(c->inst), c->inst.all_S_pos != 0,
                                            c->inst.pot_kind);
-    const size_t lds = two_d ? em2d_lds_bytes(c->inst.hist.n_bins, c->inst.n_tab)
+    const size_t lds = two_d ? em2d_lds_bytes(c->inst.hist.n_bins, c->inst.n_tab, c->precision)
                              : em_lds_bytes(c->inst.hist.n_bins, c->inst.n_tab, c->precision, grid_cells(c->inst));
     int rc = occupancy_grid(fn, block, lds, c->cu_count, c->opt.blocks_per_cu, grid);
     if (rc) return rc;
     HIP_TRY(zero_words(p.cursor, 1, s));
     HIP_TRY(hipEventRecord(c->ev_start, s));
-    if (two_d) HIP_TRY(em2d_launch(p, grid, block, s));
+    if (two_d) HIP_TRY(em2d_launch(p, c->precision, grid, block, s));
     else HIP_TRY(em_launch(p, c->precision, grid, block, s));
     HIP_TRY(hipEventRecord(c->ev_stop, s));
     HIP_TRY(hipEventRecord(c->ev_done, s));
     c->ran = true;
+    c->pending = true;
     c->n_traj_total += n_traj;
     return FPT_OK;
 }
@@ -756,11 +778,20 @@ extern "C" int fpt_last_kernel_ms(fpt_ctx *c, double *ms)
     return FPT_OK;
 }
 
-static int read_acc(const void *d_acc, int n_bins, fpt_hist *out, uint64_t n_traj_total)
+// Order the context's own stream after the last work recorded on its accumulators (its event:
+// other streams and contexts on the device are not waited for).
+static int wait_context(fpt_ctx *c)
+{
+    if (c->pending) HIP_TRY(hipStreamWaitEvent(c->io_stream, c->ev_done, 0));
+    return FPT_OK;
+}
+
+static int read_acc(const void *d_acc, int n_bins, fpt_hist *out, uint64_t n_traj_total, hipStream_t s)
 {
     const int nb = n_bins + 2;
     std::vector<unsigned char> h(acc_bytes(n_bins));
-    HIP_TRY(hipMemcpy(h.data(), d_acc, h.size(), hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpyAsync(h.data(), d_acc, h.size(), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
     const unsigned long long *cnt = reinterpret_cast<const unsigned long long *>(h.data());
     const double *sum = reinterpret_cast<const double *>(cnt + nb + 4);
     for (int i = 0; i < nb; ++i) {
@@ -786,17 +817,20 @@ extern "C" int fpt_histogram(fpt_ctx *c, fpt_hist *out)
     if (!c || !out) return fail(FPT_EINVAL, "NULL argument");
     if (!out->count || !out->sum_w_bin || !out->sum_w2_bin || !out->sum_lnw_bin || !out->sum_lnw2_bin)
         return fail(FPT_EINVAL, "histogram arrays are NULL");
-    if (c->ran) HIP_TRY(hipEventSynchronize(c->ev_done));
-    HIP_TRY(hipDeviceSynchronize());
-    return read_acc(c->inst.acc, c->opt.n_bins, out, c->n_traj_total);
+    int rc = wait_context(c);
+    if (rc) return rc;
+    return read_acc(c->inst.acc, c->opt.n_bins, out, c->n_traj_total, c->io_stream);
 }
 
 extern "C" int fpt_reset(fpt_ctx *c)
 {
     if (!c) return fail(FPT_EINVAL, "context is NULL");
-    HIP_TRY(hipDeviceSynchronize());
-    HIP_TRY(hipMemset(c->inst.acc, 0, acc_bytes(c->opt.n_bins)));
-    HIP_TRY(hipDeviceSynchronize());
+    int rc = wait_context(c);
+    if (rc) return rc;
+    // cleared by a kernel on the context's own stream after its last work, then waited for
+    HIP_TRY(zero_words(reinterpret_cast<unsigned long long *>(c->inst.acc), acc_words(c->opt.n_bins), c->io_stream));
+    HIP_TRY(hipStreamSynchronize(c->io_stream));
+    c->pending = false;
     c->n_traj_total = 0;
     return FPT_OK;
 }
@@ -809,6 +843,7 @@ extern "C" void fpt_destroy(fpt_ctx *c)
     if (c->ev_start) (void)hipEventDestroy(c->ev_start);
     if (c->ev_stop) (void)hipEventDestroy(c->ev_stop);
     if (c->ev_done) (void)hipEventDestroy(c->ev_done);
+    if (c->io_stream) (void)hipStreamDestroy(c->io_stream);
     if (c->d_mem) (void)hipFree(c->d_mem);
     if (c->d_mlp) (void)hipFree(c->d_mlp);
     if (c->d_scratch) (void)hipFree(c->d_scratch);
@@ -1329,8 +1364,12 @@ extern "C" int fpt_batch_run(fpt_batch *b, const uint64_t *n_traj, double dN, ui
     rc = batch_launch_items(b, items, b->d_inst, dN, seed, b->block, b->chunk, s, b->use_graph && s != nullptr);
     if (rc) return rc;
     for (int i = 0; i < b->n_inst; ++i) {
-        b->ctx[i]->n_traj_total += n_traj[i];
-        b->ctx[i]->ran = false;     // its accumulators were written by the batch: fpt_histogram syncs the device
+        fpt_ctx *c = b->ctx[i];
+        c->n_traj_total += n_traj[i];
+        c->ran = false;             // no kernel time of its own
+        // the batch wrote the accumulators: the context's reads wait for this stream
+        HIP_TRY(hipEventRecord(c->ev_done, s));
+        c->pending = true;
     }
     return FPT_OK;
 }

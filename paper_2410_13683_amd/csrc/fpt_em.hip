@@ -1120,12 +1120,166 @@ __device__ __forceinline__ void lanes_fp64_2d(const Inst &I, const RunArgs &R, c
     }
 }
 
+// ---------------------------------------------------------------------------
+// FP32 state with 2D noise (eq. full_langevin_equation): the float-pair state of
+// lanes_fp32 with the noise, bias and weight of lanes_fp64_2d.  Step n takes
+// (xi_1, xi_2) from generator call n >> 1 as the FP64 2D path does ((u0, u1) for
+// step 2m, (u2, u3) for step 2m + 1), so the two paths see the same numbers and
+// a group of two steps takes one call.  Node record, three float4:
+// (S_pp, slope, S_pq, slope), (S_qq, slope, e_phi, slope), (e_pi, slope, r, slope)
+// with r = (V'/V) dN/2 interpolated in the interval, NaN where V'/V is computed
+// exactly (as in the 1D FP32 table; all NaN on a time axis).  A constant bias
+// B = a S e enters through shifted normals, B dN + S xi sqrt(dN) = S (xi sqrt(dN)
+// + a dN e), and dA = a e.xi sqrt(dN) + a^2 |e|^2 dN/2 is summed per group in
+// FP32 and across groups in FP64.
+// ---------------------------------------------------------------------------
+template <int BIAS, bool ALLPOS, bool TIME>
+__device__ __forceinline__ void lanes_fp32_2d(const Inst &I, const RunArgs &R, const float4 *l_tab, const RetireTo &rt,
+                                              unsigned long long *cursor, uint64_t n_traj, uint64_t traj_offset)
+{
+    const F32Consts c = f32_consts(I, R);
+    const double x_in = I.phi_in - I.phi_end;
+    const float x_in_hi = (float)x_in, x_in_lo = (float)(x_in - (double)x_in_hi);
+    const float pi_in_hi = (float)I.pi_in, pi_in_lo = (float)(I.pi_in - (double)pi_in_hi);
+    const double dN = R.dN;
+    const float a = (BIAS == kBiasConst) ? (float)I.A : 0.0f;
+    const float adN = a * c.dN;                 // the normals' shift per unit of e
+    const float half_a2_dN = 0.5f * a * a * c.dN;
+    const float s_plus = in_vgpr(c.s_plus), s_minus = in_vgpr(c.s_minus);
+    const uint32_t ik = I.instance ^ R.key1;
+
+    bool exhausted = false;
+    uint64_t rel = 0;
+    bool has = claim(true, rel, cursor, n_traj, exhausted);
+    bool live = has;
+    float xh = x_in_hi, xl = x_in_lo, ph = pi_in_hi, pl = pi_in_lo;
+    float xs = x_in_hi, ps = pi_in_hi;
+    double lnw = 0.0;
+    uint32_t n = 0;
+    PhiloxPre pre = philox_pre(traj_offset + rel, R.key0, R.key1);
+
+    auto group = [&](auto censor_tag, const float z[4]) {
+        constexpr bool CENSOR = decltype(censor_tag)::value;
+        float zacc = 0.0f;        // this group's sum of dA
+        bool fresh = false;
+        uint32_t ev_code;
+        double ev_N, ev_lnw;
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            if (CENSOR && live && n + j == I.max_steps) {
+                ev_code = (n + j) | kFlagCensored;
+                ev_N = __builtin_nan("");
+                ev_lnw = lnw - (double)zacc;
+                live = false;
+                fresh = true;
+            }
+            const float u = __builtin_amdgcn_fmed3f(
+                TIME ? fmaf((float)(n + j), c.t_scale, c.t_off) : fmaf(xs, c.inv_h, c.u_off), 0.0f, c.jtop);
+            const float f = __builtin_amdgcn_fractf(u);
+            const float4 *rec = l_tab + 3 * (int)u;
+            const float4 A0 = rec[0], A1 = rec[1], A2 = rec[2];
+            const float Spp = fmaf(f, A0.y, A0.x), Spq = fmaf(f, A0.w, A0.z);
+            const float Sqq = fmaf(f, A1.y, A1.x), e1 = fmaf(f, A1.w, A1.z), e2 = fmaf(f, A2.y, A2.x);
+            float r = fmaf(f, A2.w, A2.z);      // (V'/V) dN/2
+            if (__any(r != r)) {
+                asm volatile("; exact V'/V");
+                if (r != r) {
+                    const float dT = (xh - c.xT_hi) + (xl - c.xT_lo);
+                    r = __builtin_amdgcn_rcpf(fmaf(dT, c.kx, (dT >= 0.0f) ? s_plus : s_minus));
+                }
+            }
+            const float z1 = z[2 * j], z2 = z[2 * j + 1];            // xi sqrt(dN)
+            // noise plus bias through the shifted normals
+            const float zb1 = (BIAS == kBiasConst) ? fmaf(adN, e1, z1) : z1;
+            const float zb2 = (BIAS == kBiasConst) ? fmaf(adN, e2, z2) : z2;
+            const float nphi = fmaf(Spp, zb1, Spq * zb2);
+            const float npi = fmaf(Spq, zb1, Sqq * zb2);
+            const float dx = fmaf(ps, c.dN, nphi);
+            const float dpi = fmaf(fmaf(ps, ps, -6.0f), fmaf(ps, c.half_dN, r), npi);
+            if (BIAS == kBiasConst) {
+                const float dA = fmaf(a, fmaf(e1, z1, e2 * z2), half_a2_dN * fmaf(e1, e1, e2 * e2));
+                zacc += (ALLPOS || Spp != 0.0f || Spq != 0.0f || Sqq != 0.0f) ? dA : 0.0f;
+            }
+            const float x0l = xl;
+            xl += dx;
+            pl += dpi;
+            xs = xh + xl;
+            ps = ph + pl;
+            const bool crossed = xs <= 0.0f;
+            const bool ended = fabsf(ps) >= 0x1.6a09e8p+0f;
+            const bool hit = live && (crossed || ended);
+            if (hit) {
+                float bh = xh, b0 = x0l, b1 = xl, bz = zacc;
+                uint32_t nb = n + j;
+                asm volatile("; passage event" : "+v"(bh), "+v"(b0), "+v"(b1), "+v"(nb), "+v"(bz));
+                const double x0 = (double)bh + (double)b0;
+                const double x1 = (double)bh + (double)b1;
+                const double N_cross = (double)nb * dN + dN * (x0 / (x0 - x1));
+                const double N_end = (double)(nb + 1) * dN;
+                ev_code = (nb + 1) | (crossed ? 0u : kFlagEndedEarly);
+                ev_N = crossed ? N_cross : N_end;
+                ev_lnw = lnw - (double)bz;
+            }
+            live = live && !hit;
+            fresh = fresh || hit;
+        }
+        n += 2;
+        lnw -= (double)zacc;
+        if (fresh) retire(rt, rel, ev_code & ~kStepMask, ev_code & kStepMask, ev_N, ev_lnw);
+        xl = xl - (xs - xh);
+        xh = xs;
+        pl = pl - (ps - ph);
+        ph = ps;
+    };
+
+    while (__any(has)) {
+        const uint32_t left = wave_steps_left(has, n, I.max_steps);
+        for (int k = 0; k < R.chunk; k += 2) {
+            if (!__any(live)) break;
+            uint32_t w[4];
+            philox_call(n >> 1, pre, ik, R.key0, R.key1, w);
+            float z[4];
+            box_muller32(w[0], w[1], c.m2ln2_dN, 0.0f, z[0], z[1]);
+            box_muller32(w[2], w[3], c.m2ln2_dN, 0.0f, z[2], z[3]);
+            if ((uint32_t)k + 2 > left) group(std::integral_constant<bool, true>(), z);
+            else group(std::integral_constant<bool, false>(), z);
+        }
+        if (!live) has = false;
+        if (claim(!has, rel, cursor, n_traj, exhausted)) {
+            has = true;
+            live = true;
+            xh = xs = x_in_hi;
+            xl = x_in_lo;
+            ph = ps = pi_in_hi;
+            pl = pi_in_lo;
+            lnw = 0.0;
+            n = 0;
+            pre = philox_pre(traj_offset + rel, R.key0, R.key1);
+        }
+    }
+}
+
 // 2D staging: three double2 per node, then the Box-Muller tables.
 __device__ __forceinline__ void stage_table64_2d(const Inst &I, double2 *l_tab)
 {
     const int n = staged_nodes(I);
     for (int i = threadIdx.x; i < 3 * n; i += blockDim.x) l_tab[i] = I.tab64_2d[I.n_tab > 1 ? i : i % 3];
     stage_bm(l_tab + 3 * n);
+}
+
+// FP32 2D staging: three float4 per node, the V'/V interval (last pair) scaled by dN/2 (NaN kept);
+// a single node is staged twice with zero slopes and a NaN interval.
+__device__ __forceinline__ void stage_table32_2d(const Inst &I, float4 *l_tab, float dN)
+{
+    const int n = staged_nodes(I);
+    for (int i = threadIdx.x; i < 3 * n; i += blockDim.x) {
+        float4 v = I.tab32_2d[I.n_tab > 1 ? i : i % 3];
+        if (i % 3 == 2) {
+            v.z *= 0.5f * dN;
+            v.w *= 0.5f * dN;
+        }
+        l_tab[i] = v;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -1201,18 +1355,24 @@ __global__ void __launch_bounds__(1024) FPT_EM_OCCUPANCY em_kernel(EmParams p)
     flush_lds_acc(acc, p.inst.acc);
 }
 
-// FP64 state with 2D noise: a persistent grid over one instance.
-template <int BIAS, bool ALLPOS, bool TIME>
+// 2D noise, FP64 or FP32 state: a persistent grid over one instance.
+template <int PREC, int BIAS, bool ALLPOS, bool TIME>
 __global__ void __launch_bounds__(1024) FPT_EM_OCCUPANCY em2d_kernel(EmParams p)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     const LdsAcc acc = lds_acc(smem, p.inst.hist.n_bins);
-    double2 *l_tab = reinterpret_cast<double2 *>(smem + align16(acc_bytes(p.inst.hist.n_bins)));
+    unsigned char *l_tab = smem + align16(acc_bytes(p.inst.hist.n_bins));
     zero_lds_acc(acc);
-    stage_table64_2d(p.inst, l_tab);
+    if (PREC == 0) stage_table64_2d(p.inst, reinterpret_cast<double2 *>(l_tab));
+    else stage_table32_2d(p.inst, reinterpret_cast<float4 *>(l_tab), (float)p.run.dN);
     __syncthreads();
     const RetireTo rt = retire_to(p, acc);
-    lanes_fp64_2d<BIAS, ALLPOS, TIME>(p.inst, p.run, l_tab, rt, p.cursor, p.n_traj, p.traj_offset);
+    if (PREC == 0)
+        lanes_fp64_2d<BIAS, ALLPOS, TIME>(p.inst, p.run, reinterpret_cast<const double2 *>(l_tab), rt, p.cursor,
+                                          p.n_traj, p.traj_offset);
+    else
+        lanes_fp32_2d<BIAS, ALLPOS, TIME>(p.inst, p.run, reinterpret_cast<const float4 *>(l_tab), rt, p.cursor,
+                                          p.n_traj, p.traj_offset);
     __syncthreads();
     flush_lds_acc(acc, p.inst.acc);
 }
@@ -1371,29 +1531,35 @@ hipError_t em_launch(const EmParams &p, int precision, int grid, int block, hipS
     return hipLaunchKernel(fn, dim3(grid), dim3(block), args, lds, stream);
 }
 
-size_t em2d_lds_bytes(int n_bins, int n_tab)
+size_t em2d_lds_bytes(int n_bins, int n_tab, int precision)
 {
-    return align16(acc_bytes(n_bins)) + (size_t)(n_tab > 1 ? n_tab : 2) * 48 + kBmBytes;
+    // FP64: three double2 per node and the Box-Muller tables; FP32: three float4 per node
+    return align16(acc_bytes(n_bins)) + (size_t)(n_tab > 1 ? n_tab : 2) * 48 + (precision == 0 ? kBmBytes : 0);
 }
 
-const void *em2d_kernel_ptr(int bias_kind, bool all_pos, bool time_axis)
+template <int PREC, int BIAS>
+struct K2Tab {
+    const void *p[2][2] = {{reinterpret_cast<const void *>(&em2d_kernel<PREC, BIAS, false, false>),
+                            reinterpret_cast<const void *>(&em2d_kernel<PREC, BIAS, false, true>)},
+                           {reinterpret_cast<const void *>(&em2d_kernel<PREC, BIAS, true, false>),
+                            reinterpret_cast<const void *>(&em2d_kernel<PREC, BIAS, true, true>)}};
+};
+
+const void *em2d_kernel_ptr(int precision, int bias_kind, bool all_pos, bool time_axis)
 {
-    static const void *const t[2][2][2] = {
-        {{reinterpret_cast<const void *>(&em2d_kernel<kBiasNone, false, false>),
-          reinterpret_cast<const void *>(&em2d_kernel<kBiasNone, false, true>)},
-         {reinterpret_cast<const void *>(&em2d_kernel<kBiasNone, true, false>),
-          reinterpret_cast<const void *>(&em2d_kernel<kBiasNone, true, true>)}},
-        {{reinterpret_cast<const void *>(&em2d_kernel<kBiasConst, false, false>),
-          reinterpret_cast<const void *>(&em2d_kernel<kBiasConst, false, true>)},
-         {reinterpret_cast<const void *>(&em2d_kernel<kBiasConst, true, false>),
-          reinterpret_cast<const void *>(&em2d_kernel<kBiasConst, true, true>)}}};
-    return t[bias_kind == kBiasNone ? 0 : 1][all_pos ? 1 : 0][time_axis ? 1 : 0];
+    static const K2Tab<0, kBiasNone> d_n;
+    static const K2Tab<0, kBiasConst> d_c;
+    static const K2Tab<1, kBiasNone> f_n;
+    static const K2Tab<1, kBiasConst> f_c;
+    const bool c = bias_kind != kBiasNone;
+    const void *const(*t)[2] = precision == 0 ? (c ? d_c.p : d_n.p) : (c ? f_c.p : f_n.p);
+    return t[all_pos ? 1 : 0][time_axis ? 1 : 0];
 }
 
-hipError_t em2d_launch(const EmParams &p, int grid, int block, hipStream_t stream)
+hipError_t em2d_launch(const EmParams &p, int precision, int grid, int block, hipStream_t stream)
 {
-    const size_t lds = em2d_lds_bytes(p.inst.hist.n_bins, p.inst.n_tab);
-    const void *fn = em2d_kernel_ptr(p.inst.bias_kind, p.inst.all_S_pos != 0, tab_mode(p.inst) == 2);
+    const size_t lds = em2d_lds_bytes(p.inst.hist.n_bins, p.inst.n_tab, precision);
+    const void *fn = em2d_kernel_ptr(precision, p.inst.bias_kind, p.inst.all_S_pos != 0, tab_mode(p.inst) == 2);
     EmParams pp = p;
     void *args[] = {&pp};
     return hipLaunchKernel(fn, dim3(grid), dim3(block), args, lds, stream);

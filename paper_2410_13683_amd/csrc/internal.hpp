@@ -59,6 +59,9 @@ struct Inst {
     // square root of the node covariance and its unit principal axis
     int32_t noise_dim;
     const double2 *tab64_2d;
+    // the same in FP32 for FP32 state, three float4 per node: (S_pp, slope, S_pq, slope),
+    // (S_qq, slope, e_phi, slope), (e_pi, slope, V'/V interval value, slope) -- the interval as in rtab32
+    const float4 *tab32_2d;
     int32_t bias_kind;
     double A;
     // learned amplitude tabulated on g_n0 x g_n1 nodes of the normalised inputs;
@@ -132,9 +135,9 @@ size_t replay_lds_bytes(int n_tab, int precision, int n_cells, int n_nodes);
 const void *em_kernel_ptr(int precision, int bias_kind, int tab_mode, bool all_pos, int pot_kind = 0);
 hipError_t em_launch(const EmParams &p, int precision, int grid, int block, hipStream_t stream);
 const void *replay_kernel_ptr(int precision, bool all_pos);
-size_t em2d_lds_bytes(int n_bins, int n_tab);
-const void *em2d_kernel_ptr(int bias_kind, bool all_pos, bool time_axis);
-hipError_t em2d_launch(const EmParams &p, int grid, int block, hipStream_t stream);
+size_t em2d_lds_bytes(int n_bins, int n_tab, int precision);
+const void *em2d_kernel_ptr(int precision, int bias_kind, bool all_pos, bool time_axis);
+hipError_t em2d_launch(const EmParams &p, int precision, int grid, int block, hipStream_t stream);
 hipError_t replay_launch(const ReplayParams &p, int precision, int grid, int block, hipStream_t stream);
 const void *batch_kernel_ptr(int precision, int bias_kind, bool all_pos);
 hipError_t batch_launch(int precision, int bias_kind, bool all_pos, const Inst *insts, const WorkItem *items,

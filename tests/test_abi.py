@@ -97,21 +97,21 @@ def test_invalid_arguments_are_rejected(lib, bad):
     assert lib.fpt_last_error()
 
 
-@pytest.mark.parametrize("case", ["indefinite", "dim3", "fp32", "mlp"])
+@pytest.mark.parametrize("case", ["indefinite", "dim3", "mlp", "mlp_fp32"])
 def test_2d_table_validation(lib, case):
     pot = _pot()
     X = [np.array([1e-12]), np.array([2e-12 if case == "indefinite" else 1e-13]), np.array([1e-12])]
     tab = fpt.fpt_noise_table(1, 0.0, 0.0, None, None, 3 if case == "dim3" else 2,
                               *[x.ctypes.data_as(fpt._dp) for x in X])
     params = np.zeros(fpt.FPT_MLP_NPARAM, dtype=np.float32)
-    bias = fpt.fpt_bias(2 if case == "mlp" else 0, 0.0, params.ctypes.data_as(fpt._fp),
+    bias = fpt.fpt_bias(2 if case.startswith("mlp") else 0, 0.0, params.ctypes.data_as(fpt._fp),
                         (ctypes.c_double * 4)(0, 1, 0, 1), 0, (ctypes.c_int32 * 2)(4, 4),
                         (ctypes.c_double * 4)(-1, 1, -1, 1))
-    opts = fpt.fpt_options(1 if case == "fp32" else 0, 0, 8, -1.0, 1.0, 0.0, 1000, 0, 0, 0, 0)
+    opts = fpt.fpt_options(1 if case == "mlp_fp32" else 0, 0, 8, -1.0, 1.0, 0.0, 1000, 0, 0, 0, 0)
     h = ctypes.c_void_p()
     rc = lib.fpt_create(ctypes.byref(pot), ctypes.byref(tab), ctypes.byref(bias), ctypes.byref(opts),
                         ctypes.byref(h))
-    expect = fpt.FPT_EUNSUPPORTED if case in ("fp32", "mlp") else fpt.FPT_EINVAL
+    expect = fpt.FPT_EUNSUPPORTED if case.startswith("mlp") else fpt.FPT_EINVAL
     assert rc == expect and not h.value, (rc, lib.fpt_last_error())
 
 
@@ -193,7 +193,7 @@ def test_bump_variants_are_reported_unsupported(lib, case):
     else:
         tab = fpt.fpt_noise_table(1, 0.0, 0.0, S.ctypes.data_as(fpt._dp), t.ctypes.data_as(fpt._dp))
     params = np.zeros(fpt.FPT_MLP_NPARAM, dtype=np.float32)
-    bias = fpt.fpt_bias(2 if case == "mlp" else 0, 0.0, params.ctypes.data_as(fpt._fp),
+    bias = fpt.fpt_bias(2 if case.startswith("mlp") else 0, 0.0, params.ctypes.data_as(fpt._fp),
                         (ctypes.c_double * 4)(0.0, 1.0, 0.0, 1.0), 0, (ctypes.c_int32 * 2)(8, 8),
                         (ctypes.c_double * 4)(-1.0, 1.0, -1.0, 1.0))
     opts = fpt.fpt_options(precision=1 if case == "fp32" else 0, bins_kind=0, n_bins=8, lo=-1.0, hi=1.0, N_ref=0.0,
@@ -219,7 +219,7 @@ def test_time_axis_validation(lib, case):
         tab = fpt.fpt_noise_table(3, lo, hi, S.ctypes.data_as(fpt._dp), t.ctypes.data_as(fpt._dp))
     tab.axis = {"axis2": 2, "axis_neg": -1}.get(case, fpt.FPT_AXIS_TIME)
     params = np.zeros(fpt.FPT_MLP_NPARAM, dtype=np.float32)
-    bias = fpt.fpt_bias(2 if case == "mlp" else 0, 0.0, params.ctypes.data_as(fpt._fp),
+    bias = fpt.fpt_bias(2 if case.startswith("mlp") else 0, 0.0, params.ctypes.data_as(fpt._fp),
                         (ctypes.c_double * 4)(0, 1, 0, 1), 0, (ctypes.c_int32 * 2)(8, 8),
                         (ctypes.c_double * 4)(-1, 1, -1, 1))
     opts = fpt.fpt_options(0, 0, 8, -1.0, 1.0, 0.0, 1000, 0, 0, 0, 0)

@@ -106,3 +106,45 @@ def test_1d_and_2d_noise_agree_at_small_sigma():
     say(f"  mean {d1.mean():.4e} / {d2.mean():.4e}; std {d1.std():.4e} / {d2.std():.4e}")
     assert abs(d2.std() / d1.std() - 1.0) < 0.02
     assert abs(d2.mean() - d1.mean()) < 0.02 * d1.std()
+
+
+def _ks(a, b, wa=None, wb=None):
+    xs = np.sort(np.concatenate([a, b]))
+
+    def cdf(x, wt):
+        o = np.argsort(x)
+        c = np.cumsum(np.ones_like(x) if wt is None else wt[o])
+        c /= c[-1]
+        return np.concatenate([[0.0], c])[np.searchsorted(x[o], xs, side="right")]
+    return np.max(np.abs(cdf(a, wa) - cdf(b, wb)))
+
+
+@pytest.mark.parametrize("A_bias", [0.0, 1.2])
+def test_fp32_2d_coupled_with_oracle(A_bias):
+    """FP32 state with 2D noise (the float-pair state of the 1D FP32 path, the noise, bias and
+    weight of the 2D path) against the FP64 oracle on the same random streams: SR -> USR with the
+    2D Bessel table (sigma = 0.1), 2e4 trajectories.  Per trajectory N within FP32 rounding except
+    at crossing near-ties, the KS distance of P(deltaN) below 1e-3; with a bias, ln w where the
+    crossing steps agree and the weighted law of the biased region."""
+    w = W.srusr_2d(n_traj=20_000, A_bias=A_bias, seed=44).with_(precision=1)
+    say(f"fp32 2D coupled A={A_bias} n={w.n_traj}")
+    (Ng, lg, sg), hist = gpu_run(w)
+    No, lo_, so = oracle_run(w)
+    flags = orc.FLAG_CENSORED | orc.FLAG_ENDED_EARLY
+    assert np.all((sg & flags) == 0) and np.all((so & flags) == 0)
+    dn = Ng - No
+    ks = _ks(Ng, No)
+    say(f"  N32 - N64: median {np.median(dn):.3e}, max |.| {np.abs(dn).max():.3e}; KS {ks:.2e}")
+    assert abs(np.median(dn)) < 2e-5 and np.mean(np.abs(dn) < 1e-4) > 0.99
+    assert ks < 1e-3
+    assert hist["n_traj"] == w.n_traj and int(hist["count"].sum()) == w.n_traj
+    if A_bias:
+        same = sg == so
+        dl = np.abs(lg - lo_)[same]
+        q = np.quantile(No - w.N_ref, 0.3)
+        ta, tb = (Ng - w.N_ref) >= q, (No - w.N_ref) >= q
+        ksw = _ks(Ng[ta], No[tb], np.exp(lg[ta]), np.exp(lo_[tb]))
+        say(f"  same step {same.mean():.4f}; |dlnw| median {np.median(dl):.2e} max {dl.max():.2e}; "
+            f"weighted KS above the 30th percentile {ksw:.2e}")
+        assert same.mean() > 0.95 and np.median(dl) < 1e-5 and dl.max() < 1e-3
+        assert ksw < 5e-3
