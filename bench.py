@@ -170,6 +170,8 @@ def _workload(name: str, n_traj: int | None):
         w = W.srusr_learned(n_traj=100_000_000, A_init=1.0)
     elif name == "srusr_2d":
         w = W.srusr_2d()
+    elif name == "srusr_2d_fp32":
+        w = W.srusr_2d(n_traj=10_000_000).with_(name="srusr_2d_fp32", precision=1)
     elif name == "srusr_matched":
         w = W.srusr_is_fp32_matched(A_bias=2.0)
     elif name == "srusr_2d_time":
@@ -307,6 +309,95 @@ def train_learned(w, stream, train_traj: float = 1e7, iters: int = 40, lr: float
     return out
 
 
+def bench_multi_amplitude(args) -> dict:
+    """Configuration 3 as written: the SR -> USR problem in FP32 state with the bias amplitudes
+    A in {0.5, 1, 2}, 1e8 trajectories per pass.  Step k is one pass at amplitude A_(k mod 3) (its
+    own context and histogram, fresh trajectory indices each pass), so the timed steps cover every
+    amplitude; at the end the tail masses of the three histograms are merged slot by slot with
+    inverse-variance weights (fpt_tail_at for P(deltaN >= e_j) and its error at every slot,
+    fpt_merge_bins), as Sec. 4.2 combines amplitudes where they agree."""
+    import numpy as np
+    import torch
+    from paper_2410_13683_amd import fpt, runner
+    from paper_2410_13683_amd import workloads as W
+    amps = (0.5, 1.0, 2.0)
+    n = int(args.n_traj) if args.n_traj else 100_000_000
+    ws = [W.srusr_is_fp32(A_bias=A, n_traj=n) for A in amps]
+    t_tab = time.perf_counter()
+    ctxs = [runner.context_for(w) for w in ws]
+    table_s = time.perf_counter() - t_tab
+    stream = torch.cuda.current_stream()
+    passes = [0, 0, 0]
+    print(f"[bench] workload srusr_is_fp32_multiA: A in {amps}, {n:.3g} trajectories per pass, warmup "
+          f"{args.warmup}, steps {args.steps}", file=sys.stderr, flush=True)
+    for i in range(args.warmup):
+        a = i % 3
+        ctxs[a].run(n, ws[a].dN, ws[a].seed, 0, stream)
+        torch.cuda.synchronize()
+        print(f"[bench] warmup {i + 1} (A={amps[a]:g}) done ({ctxs[a].last_kernel_ms():.0f} ms)", file=sys.stderr,
+              flush=True)
+    for c in ctxs:
+        c.reset()
+    kernel_ms = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        a = k % 3
+        ctxs[a].run(n, ws[a].dN, ws[a].seed, passes[a] * n, stream)
+        passes[a] += 1
+        kernel_ms.append(ctxs[a].last_kernel_ms())
+        print(f"[bench] step {k + 1}/{args.steps} (A={amps[a]:g}): {kernel_ms[-1]:.0f} ms", file=sys.stderr,
+              flush=True)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    hists = [c.histogram() for c in ctxs]
+    for c in ctxs:
+        c.destroy()
+    w = ws[0]
+    steps_total = int(sum(h["n_steps_total"] for h in hists))
+    used = [i for i in range(3) if passes[i] > 0]
+    # tail mass P(deltaN >= e_j) of every slot j = 1 .. n_bins + 1 and its standard error, per amplitude
+    slots = range(1, w.n_bins + 2)
+    P = np.full((len(used), len(slots)), np.nan)
+    E = np.full_like(P, np.nan)
+    for r, i in enumerate(used):
+        for j in slots:
+            t = fpt.fpt_tail_at(hists[i], w.bins_kind, w.n_bins, w.lo, w.hi, j)
+            if t["count"] >= 2:
+                P[r, j - 1], E[r, j - 1] = t["P"], t["P_err"]
+    Pm, Em = fpt.fpt_merge_bins(P, E)
+    _, edges, _ = fpt.fpt_density(hists[used[0]], w.bins_kind, w.n_bins, w.lo, w.hi, moments=False)
+    deep = np.flatnonzero(np.isfinite(Pm) & (Pm > 0) & (Pm <= 1e-10))
+    merged = None
+    if len(deep):
+        j = int(deep[0])                                 # lowest edge whose merged tail mass is <= 1e-10
+        x_star = float(edges[j]) if j < w.n_bins else float(w.hi)
+        ess_eq = (Pm[j] / Em[j]) ** 2                    # equally weighted samples with the same relative error
+        merged = {"deltaN_star": x_star, "P_tail": float(Pm[j]), "P_tail_err": float(Em[j]), "ESS_equiv": ess_eq,
+                  "ess_tail_per_s": ess_eq / wall, "t_5pct_s": 400.0 / (ess_eq / wall),
+                  "per_amplitude": {f"{amps[i]:g}": {"passes": passes[i], "P_tail": float(P[r, j]),
+                                                    "P_tail_err": float(E[r, j])}
+                                    for r, i in enumerate(used)}}
+    avg_ms = float(np.mean(kernel_ms))
+    achieved = ALG_FLOPS_PER_STEP["fp32"] * (steps_total / args.steps) / (avg_ms * 1e-3) / 1e12
+    return {
+        "metric": METRIC, "value": steps_total / wall, "unit": "trajectory-steps/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": wall * 1e3 / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "srusr_is_fp32_multiA", "amplitudes": list(amps), "trajectories_per_step": n,
+                   "potential": "piecewise-linear slow roll -> ultra-slow roll, V0=1e-10, eps+=0.01, eps-=1e-8",
+                   "noise": f"Bessel-ansatz table, {w.table_n} phi nodes, sigma={w.sigma}",
+                   "state": "FP32 pairs + FP64 log-weights", "dN": w.dN,
+                   "bins": f"{w.n_bins} log over deltaN in [{w.lo:.4g}, {w.hi:.4g})"},
+        "ess_tail_per_s": merged["ess_tail_per_s"] if merged else 0.0,
+        "tail": merged, "trajectory_steps": steps_total, "table_setup_s": table_s,
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_TFLOPS["fp32"], "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_TFLOPS["fp32"], "traffic": None,
+                     "kernel": "em_kernel<FP32 state, const bias, table>", "kernel_ms": avg_ms,
+                     "flops_per_step": ALG_FLOPS_PER_STEP["fp32"]},
+    }
+
+
 def bench_batched(args) -> dict:
     """Timed passes of the 64-instance batch (see the module docstring)."""
     import tempfile
@@ -410,6 +501,9 @@ def main() -> int:
     torch.cuda.set_device(0)
     if args.workload == "batched":
         print(json.dumps(bench_batched(args)), flush=True)
+        return 0
+    if args.workload == "srusr_is_fp32_multiA":
+        print(json.dumps(bench_multi_amplitude(args)), flush=True)
         return 0
     if args.copy_calibration:
         src = torch.ones(args.copy_calibration // 4, dtype=torch.float32, device="cuda")
@@ -518,7 +612,7 @@ def main() -> int:
             "unit": "TFLOP/s",
             "frac": achieved / PEAK_TFLOPS[prec],
             "traffic": None,
-            "kernel": ("em2d_kernel<FP64, 2D noise>" if w.noise in ("bessel2d", "bessel2d_time") else
+            "kernel": (f"em2d_kernel<{prec.upper()}, 2D noise>" if w.noise in ("bessel2d", "bessel2d_time") else
                        "em_kernel<FP64, Gaussian bump>" if w.kind == 2 else
                        "em_kernel<FP32 state, const bias, table>" if prec == "fp32" else "em_kernel<FP64>"),
             "kernel_ms": avg_ms,
