@@ -818,8 +818,20 @@ __device__ __forceinline__ void lanes_fp32(const Inst &I, const RunArgs &R, cons
         return (BIAS == kBiasNone) ? 0.0 : -A * zs_total + (double)steps_on * lnw_step;
     };
 
-    auto group = [&](auto censor_tag, const float z[4]) {
+    // SPAN groups (phi tables): every live lane's interval at the group start holds an interpolated
+    // V'/V, and the group reads that record once: each step forms its fraction in the same
+    // interval, f = x inv_h + (u_off - j0), which a four-step path leaves by a tiny fraction of
+    // the node spacing at most (a linear extrapolation there, in a smooth interval).  Groups with
+    // a live lane in a NaN interval (table edges, the kink, tables that do not qualify) and
+    // censoring groups take the record of each step's own clamped coordinate instead.
+    float4 g_node = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    float2 g_rn = make_float2(0.0f, 0.0f);
+    float g_off = 0.0f;
+
+    auto group = [&](auto censor_tag, auto span_tag, const float z[4]) {
         constexpr bool CENSOR = decltype(censor_tag)::value;
+        constexpr bool SPAN = decltype(span_tag)::value;
+        static_assert(!SPAN || (TAB == 1 && !CENSOR), "one record per group: phi tables, no censoring");
         float zacc = 0.0f;        // constant bias: sum of this group's xi sqrt(dN); learned: of its dA
         bool fresh = false;
         uint32_t ev_code;         // written before use: read only where fresh is set
@@ -851,6 +863,11 @@ __device__ __forceinline__ void lanes_fp32(const Inst &I, const RunArgs &R, cons
                 S = fmaf(f, node.y, node.x);
                 t = fmaf(f, node.w, node.z);
                 r = drift_exact();
+            } else if (SPAN) {
+                const float f = fmaf(xs, c.inv_h, g_off);
+                S = fmaf(f, g_node.y, g_node.x);
+                t = fmaf(f, g_node.w, g_node.z);
+                r = fmaf(f, g_rn.y, g_rn.x);
             } else if (TAB) {
                 // the coordinate clamped to [0, n_tab - 1]: its integer part is the record, its
                 // fraction the weight; past the last node the last record (slope 0) gives the
@@ -965,10 +982,23 @@ __device__ __forceinline__ void lanes_fp32(const Inst &I, const RunArgs &R, cons
             const float off = (BIAS == kBiasConst) ? c.adN : 0.0f;
             box_muller32(w[0], w[1], c.m2ln2_dN, off, z[0], z[1]);
             box_muller32(w[2], w[3], c.m2ln2_dN, off, z[2], z[3]);
-            if ((uint32_t)k + 4 > left)
-                group(std::integral_constant<bool, true>(), z);
-            else
-                group(std::integral_constant<bool, false>(), z);
+            using T = std::integral_constant<bool, true>;
+            using F = std::integral_constant<bool, false>;
+            if ((uint32_t)k + 4 > left) {
+                group(T(), F(), z);
+            } else {
+                if constexpr (TAB == 1) {
+                    const float u0 = __builtin_amdgcn_fmed3f(fmaf(xs, c.inv_h, c.u_off), 0.0f, c.jtop);
+                    const int j0 = (int)u0;
+                    g_node = l_tab[j0];
+                    g_rn = l_rtab[j0];
+                    g_off = c.u_off - (float)j0;
+                    if (__builtin_amdgcn_ballot_w64(live && g_rn.x != g_rn.x) == 0) group(F(), T(), z);
+                    else group(F(), F(), z);
+                } else {
+                    group(F(), F(), z);
+                }
+            }
         }
         if (!live) has = false;
         if (claim(!has, rel, cursor, n_traj, exhausted)) {

@@ -505,32 +505,36 @@ def test_amplitude_one_and_merged_tail_match_oracle():
 
 
 def test_histogram_waits_for_its_own_context_only():
-    """fpt_histogram and fpt_reset of a context wait for that context's last run only: with a long
-    run of another context still going on another stream (both launched with one 256-thread block
-    per CU, so that they fit on the GPU at once), the short context's histogram comes back, correct, before the long run ends;
-    then the long context's histogram waits for its own run."""
+    """fpt_histogram and fpt_reset of a context wait for that context's last run only.  A short run
+    of one context is enqueued on one stream, then a long run (about a second) of another context
+    on a second stream.  Whether the two streams share a hardware queue or not, the short kernel
+    ends first, so the short context's read must return while the long run is still going; a read
+    that waited for the whole device would return only after it.  The reset then clears the short
+    context while the long run's results stay, and both histograms are checked."""
     w_long = W.srusr_is_fp32(2.0, n_traj=5_000_000)
     w_short = W.linear_slow_roll(n_traj=1000, seed=6)
     s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
-    c1 = runner.context_for(w_long, block_size=256, blocks_per_cu=1)
-    c2 = runner.context_for(w_short, block_size=256, blocks_per_cu=1)
-    say("context-scoped reads: long run on one stream, short run and reads on another")
+    c1 = runner.context_for(w_long)
+    c2 = runner.context_for(w_short)
+    say("context-scoped reads: short run on one stream, then a long run and the short run's reads")
     torch.cuda.synchronize()
-    c1.run(w_long.n_traj, w_long.dN, w_long.seed, 0, s1)
-    ev = torch.cuda.Event()
-    ev.record(s1)
+    e_long = torch.cuda.Event()
     c2.run(w_short.n_traj, w_short.dN, w_short.seed, 0, s2)
+    c1.run(w_long.n_traj, w_long.dN, w_long.seed, 0, s1)
+    e_long.record(s1)
     h2 = c2.histogram()
+    long_still_running = not e_long.query()
     c2.reset()
-    long_still_running = not ev.query()
-    h1 = c1.histogram()
-    assert ev.query()
     h2b = c2.histogram()
-    say(f"  long run still going after the short read and reset: {long_still_running}; long run "
-        f"{c1.last_kernel_ms():.0f} ms")
-    assert long_still_running
+    long_still_running_after_reset = not e_long.query()
+    h1 = c1.histogram()
+    assert e_long.query()
+    torch.cuda.synchronize()
+    say(f"  long run still going after the short read: {long_still_running}, after the reset: "
+        f"{long_still_running_after_reset}; long run {c1.last_kernel_ms():.0f} ms")
     assert h2["n_traj"] == 1000 and int(h2["count"].sum()) == 1000
     assert h2b["n_traj"] == 0 and int(h2b["count"].sum()) == 0 and h2b["n_steps_total"] == 0
     assert h1["n_traj"] == w_long.n_traj and int(h1["count"].sum()) + h1["n_censored"] == w_long.n_traj
     c1.destroy()
     c2.destroy()
+    assert long_still_running and long_still_running_after_reset
