@@ -190,10 +190,10 @@ def cpu_baseline(w, target_s: float = 20.0) -> dict:
     """The CPU oracle, as it stands, on the first trajectories of the same workload (its noise table
     built once, outside the timing)."""
     from oracle import oracle as orc
-    from tests._glue import oracle_problem, oracle_problem2d
+    from oracle.problems import NOISE_2D, oracle_problem, oracle_problem2d
     threads = orc.max_threads()
     kw = dict(instance=w.extra.get("instance", 0), max_steps=w.max_steps)
-    if w.noise in ("xi_const", "bessel2d", "bessel2d_time"):
+    if w.noise in NOISE_2D:
         p2 = oracle_problem2d(w)
         run = lambda n, off, nt=0: orc.run2d(p2, w.dN, w.seed, n, traj_offset=off, n_threads=nt, **kw)
     else:

@@ -1,56 +1,17 @@
-"""Test-side glue: turn a workload description into an oracle problem.
+"""Test-side glue: the oracle's runs of a workload description and the per-trajectory FP64
+parity check.
 
-The oracle builds its own noise table with its own generator; the GPU side
-builds its table with the library's generator (see tests/_gpu.py).  Nothing
-here computes any step of the method.
+The oracle builds its own noise table with its own generator (oracle/problems.py); the GPU side
+builds its table with the library's generator (see tests/_gpu.py).  Nothing here computes any
+step of the method.
 """
 from __future__ import annotations
 
 import numpy as np
 
 from oracle import oracle as orc
+from oracle.problems import NOISE_2D, oracle_problem, oracle_problem2d, oracle_table  # noqa: F401
 from paper_2410_13683_amd.workloads import Workload
-
-
-def oracle_table(w: Workload):
-    if w.noise == "const":
-        return np.array([w.noise_S]), np.array([w.noise_tan]), 0.0, 0.0
-    if w.noise == "bessel":
-        S, t = orc.noise_table_bessel(w.kind, w.V0, w.phi_T, w.A_plus, w.A_minus, w.sigma,
-                                      w.table_n, w.table_lo, w.table_hi, bump=w.bump)
-        return S, t, w.table_lo, w.table_hi
-    if w.noise == "matched":
-        S, t, _ = orc.noise_table_matched(w.kind, w.V0, w.phi_T, w.A_plus, w.A_minus, w.sigma, w.table_n,
-                                          w.table_lo, w.table_hi, *w.match_start, bump=w.bump)
-        if w.noise_cut_below:
-            S[0] = 0.0
-        return S, t, w.table_lo, w.table_hi
-    if w.noise == "matched_time":
-        S, t, _, _ = orc.noise_table_matched_time(w.kind, w.V0, w.phi_T, w.A_plus, w.A_minus, w.sigma, w.table_n,
-                                                  w.table_lo, w.table_hi, *w.match_start, w.phi_in, bump=w.bump)
-        if w.noise_cut_end:
-            S[-1] = 0.0
-        return S, t, w.table_lo, w.table_hi
-    raise ValueError(w.noise)
-
-
-def oracle_problem(w: Workload, mlp_params=None, mlp_norm=None) -> orc.Problem:
-    """The oracle problem of a workload.  A learned control given by the workload
-    (w.mlp_params) is the tabulated network on the workload's grid; parameters passed
-    here instead select the network evaluated at every step."""
-    S, t, lo, hi = oracle_table(w)
-    p = orc.Problem(kind=w.kind, V0=w.V0, phi_T=w.phi_T, A_plus=w.A_plus, A_minus=w.A_minus,
-                    phi_in=w.phi_in, pi_in=w.pi_in, phi_end=w.phi_end, S=S, tan_theta=t,
-                    phi_lo=lo, phi_hi=hi, bias_kind=w.bias_kind, A_bias=w.A_bias,
-                    mlp_params=mlp_params, mlp_norm=mlp_norm, bump=w.bump,
-                    tab_axis=1 if w.noise == "matched_time" else 0)
-    if mlp_params is None and w.mlp_params is not None:
-        p.mlp_params = np.ascontiguousarray(w.mlp_params, dtype=np.float32)
-        p.mlp_norm = np.asarray(w.mlp_norm, dtype=np.float64)
-        p.mlp_every = 0
-        p.grid_n = tuple(w.grid_n)
-        p.grid_range = tuple(w.grid_range)
-    return p
 
 
 def phi_drift(w: Workload) -> float:
@@ -101,30 +62,10 @@ def assert_fp64_parity(gpu, ora, w):
     return {"step_ties": int((ng != no).sum()), "short_last_step": int((fin & (rel > 1e-9)).sum())}
 
 
-def oracle_problem2d(w: Workload) -> orc.Problem2D:
-    if w.noise == "xi_const":
-        X, lo, hi = tuple(np.array([v]) for v in w.noise_Xi), 0.0, 0.0
-    elif w.noise == "bessel2d_time":
-        X = orc.noise_table_bessel2d_time(w.kind, w.V0, w.phi_T, w.A_plus, w.A_minus, w.sigma, w.table_n,
-                                          w.table_lo, w.table_hi, *w.match_start, w.phi_in)[:3]
-        if w.noise_cut_end:
-            for x in X:
-                x[-1] = 0.0
-        lo, hi = w.table_lo, w.table_hi
-    else:
-        X = orc.noise_table_bessel2d(w.kind, w.V0, w.phi_T, w.A_plus, w.A_minus, w.sigma, w.table_n,
-                                     w.table_lo, w.table_hi)
-        lo, hi = w.table_lo, w.table_hi
-    return orc.Problem2D(kind=w.kind, V0=w.V0, phi_T=w.phi_T, A_plus=w.A_plus, A_minus=w.A_minus,
-                         phi_in=w.phi_in, pi_in=w.pi_in, phi_end=w.phi_end, Xpp=X[0], Xpq=X[1], Xqq=X[2],
-                         phi_lo=lo, phi_hi=hi, bias_kind=w.bias_kind, A_bias=w.A_bias,
-                         tab_axis=1 if w.noise == "bessel2d_time" else 0)
-
-
 def oracle_run(w: Workload, n_traj=None, traj_offset=0, n_threads=0, last_phi=False, **kw):
     """The oracle's (N, ln w, steps) for the workload's trajectories, plus phi before and after
     each last step with last_phi (the form assert_fp64_parity takes)."""
-    if w.noise in ("xi_const", "bessel2d", "bessel2d_time"):
+    if w.noise in NOISE_2D:
         return orc.run2d(oracle_problem2d(w), w.dN, w.seed, w.n_traj if n_traj is None else n_traj,
                          traj_offset=traj_offset, instance=w.extra.get("instance", 0), max_steps=w.max_steps,
                          n_threads=n_threads, last_phi=last_phi)
@@ -138,7 +79,7 @@ def oracle_sampled(w: Workload, idx, prob=None):
     """oracle_run(..., last_phi=True) of the trajectories at the given (sorted) indices, one oracle
     call per run of consecutive indices; prob: the oracle problem (1D or 2D) if already built."""
     idx = np.asarray(idx, dtype=np.int64)
-    two_d = w.noise in ("xi_const", "bessel2d", "bessel2d_time")
+    two_d = w.noise in NOISE_2D
     if prob is None:
         prob = oracle_problem2d(w) if two_d else oracle_problem(w)
     run = orc.run2d if two_d else orc.run
