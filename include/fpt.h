@@ -158,8 +158,15 @@ typedef struct {
  *          grid_range[1]] and x1 in [grid_range[2], grid_range[3]] (node
  *          (i, j) at x0 = lo0 + (hi0 - lo0) i/(n0 - 1), likewise x1); a(phi, pi)
  *          is the bilinear interpolation of the node values at (x0, x1),
- *          clamped to the edge cells.  mlp_every must be 0 (the tabulated
- *          network; other values are reserved: FPT_EUNSUPPORTED).  Any
+ *          clamped to the edge cells.  mlp_every = 0 runs this tabulated
+ *          network.  mlp_every = k >= 1 makes fpt_run evaluate the network itself
+ *          every k steps instead (in FP64 for FP64 state, in FP32 for FP32 state)
+ *          and hold its output between evaluations: step n uses the network at the
+ *          state of step k floor(n/k).  That costs about 4500 multiply-adds and 64
+ *          to 512 tanh per evaluation per trajectory; it is fastest when k divides
+ *          the launch's chunk (all lanes of a wave then evaluate at the same step).
+ *          The table is still built (fpt_mlp_table), and fpt_mlp_grad, whose replay
+ *          uses the table, needs mlp_every = 0 (else FPT_EUNSUPPORTED).  Any
  *          deterministic function of the state is an admissible control; the
  *          weights use the same a, so the estimates stay unbiased.
  *          Requires 2 <= grid_n[k], grid_n[0] grid_n[1] <= FPT_MLP_MAX_GRID,

@@ -481,6 +481,12 @@ static int mlp_setup(fpt_ctx *c, const fpt_bias &b)
     I.g_off1 = -(b.norm[2] / b.norm[3] + g.lo1) * q1;
     I.grid64 = c->d_grid64;
     I.grid32 = c->d_grid32;
+    I.mlp_every = b.mlp_every;
+    I.mlp_params = c->d_params;
+    I.m_k0 = 1.0 / b.norm[1];
+    I.m_off0 = -b.norm[0] / b.norm[1];
+    I.m_k1 = 1.0 / b.norm[3];
+    I.m_off1 = -b.norm[2] / b.norm[3];
     HIP_TRY(mlp_tabulate(c->d_params, g, c->d_node_a, c->d_grid64, c->d_grid32, nullptr));
     HIP_TRY(hipDeviceSynchronize());
     return FPT_OK;
@@ -551,7 +557,7 @@ extern "C" int fpt_create(const fpt_potential *pot, const fpt_noise_table *table
         for (int i = 0; i < 4; ++i)
             if (!is_finite(b.norm[i]) || !is_finite(b.grid_range[i])) return fail(FPT_EINVAL, "MLP norm and grid range must be finite");
         if (b.norm[1] == 0.0 || b.norm[3] == 0.0) return fail(FPT_EINVAL, "MLP norm scales must be non-zero");
-        if (b.mlp_every != 0) return fail(FPT_EUNSUPPORTED, "only the tabulated network (mlp_every = 0) is implemented");
+        if (b.mlp_every < 0) return fail(FPT_EINVAL, "mlp_every must be >= 0");
         if (b.grid_n[0] < 2 || b.grid_n[1] < 2 || (int64_t)b.grid_n[0] * b.grid_n[1] > FPT_MLP_MAX_GRID)
             return fail(FPT_EINVAL, "MLP grid needs 2 <= n0, n1 and n0 n1 <= %d", FPT_MLP_MAX_GRID);
         if (!(b.grid_range[1] > b.grid_range[0]) || !(b.grid_range[3] > b.grid_range[2]))
@@ -695,7 +701,8 @@ extern "C" int fpt_create(const fpt_potential *pot, const fpt_noise_table *table
         }
     }
     const int n_cells = grid_cells(I);
-    size_t need = dim == 2 ? em2d_lds_bytes(o.n_bins, nt, o.precision) : em_lds_bytes(o.n_bins, nt, o.precision, n_cells);
+    size_t need = dim == 2 ? em2d_lds_bytes(o.n_bins, nt, o.precision)
+                           : em_lds_bytes(o.n_bins, nt, o.precision, n_cells, b.kind == FPT_BIAS_MLP && b.mlp_every > 0);
     if (b.kind == FPT_BIAS_MLP)
         need = std::max(need, replay_lds_bytes(nt, o.precision, n_cells, c->grid.n0 * c->grid.n1));
     if (need > c->lds_per_block_max) {
@@ -747,18 +754,22 @@ extern "C" int fpt_run(fpt_ctx *c, uint64_t n_traj, double dN, uint64_t seed, ui
     const int block = c->opt.block_size ? c->opt.block_size : 1024;
     int grid = 0;
     const bool two_d = c->inst.noise_dim == 2;
+    // the learned control runs its tabulated network, or the network itself every mlp_every steps
+    const bool exact = c->inst.bias_kind == kBiasMlp && c->inst.mlp_every > 0;
+    const int bias_k = exact ? kBiasMlpExact : c->inst.bias_kind;
     const void *fn = two_d ? em2d_kernel_ptr(c->precision, c->inst.bias_kind, c->inst.all_S_pos != 0,
                                              tab_mode(c->inst) == 2)
-                           : em_kernel_ptr(c->precision, c->inst.bias_kind, tab_mode(c->inst), c->inst.all_S_pos != 0,
+                           : em_kernel_ptr(c->precision, bias_k, tab_mode(c->inst), c->inst.all_S_pos != 0,
                                            c->inst.pot_kind);
     const size_t lds = two_d ? em2d_lds_bytes(c->inst.hist.n_bins, c->inst.n_tab, c->precision)
-                             : em_lds_bytes(c->inst.hist.n_bins, c->inst.n_tab, c->precision, grid_cells(c->inst));
+                             : em_lds_bytes(c->inst.hist.n_bins, c->inst.n_tab, c->precision, grid_cells(c->inst),
+                                            exact);
     int rc = occupancy_grid(fn, block, lds, c->cu_count, c->opt.blocks_per_cu, grid);
     if (rc) return rc;
     HIP_TRY(zero_words(p.cursor, 1, s));
     HIP_TRY(hipEventRecord(c->ev_start, s));
     if (two_d) HIP_TRY(em2d_launch(p, c->precision, grid, block, s));
-    else HIP_TRY(em_launch(p, c->precision, grid, block, s));
+    else HIP_TRY(em_launch(p, c->precision, grid, block, s, exact));
     HIP_TRY(hipEventRecord(c->ev_stop, s));
     HIP_TRY(hipEventRecord(c->ev_done, s));
     c->ran = true;
@@ -904,6 +915,8 @@ static int mlp_grad_check(fpt_ctx *c, uint64_t n_traj, double dN, uint64_t traj_
 {
     int rc = mlp_check(c);
     if (rc) return rc;
+    if (c->inst.mlp_every > 0)
+        return fail(FPT_EUNSUPPORTED, "the replay gradient is that of the tabulated network (mlp_every = 0)");
     if (!d_grad) return fail(FPT_EINVAL, "d_grad is NULL");
     if (!(dN > 0.0) || !is_finite(dN)) return fail(FPT_EINVAL, "dN must be finite and > 0");
     if (!is_finite(tail_lo)) return fail(FPT_EINVAL, "tail_lo must be finite");

@@ -535,6 +535,119 @@ __device__ __forceinline__ void grad_add(T s[4], T c, T f0, T f1)
 }
 
 // ---------------------------------------------------------------------------
+// Learned control, exact: output 0 of the 2 -> 64 -> 64 -> 2 tanh network itself at the
+// normalised state (x0, x1), evaluated every mlp_every steps and held in between (the bias may be
+// any deterministic function of the path's past states; the weights use the same amplitude, so
+// the estimator stays unbiased).  Both evaluations take the network's sums in their own order.
+//
+// FP64 state: the parameters are staged in LDS as doubles, W2 transposed (word j 64 + i holds
+// W2[i][j]), then W1, b1, b2, row 0 of W3 and b3[0]; the second layer is accumulated eight units
+// at a time, each pass recomputing the 64 first-layer activations, so that a lane holds eight
+// accumulators instead of 64 activations.
+//
+// FP32 state: the parameters are read in place from global memory through the constant address
+// space.  Every lane of a wave reads the same word, so the loads become scalar loads and the
+// multiply-adds take the weights as scalar operands (no LDS traffic); a lane keeps its 64
+// first-layer activations in registers.  tanh s = 1 - 2/(e^(2s) + 1) from the hardware exp2 and
+// reciprocal, exactly +-1 for large |s|.
+// ---------------------------------------------------------------------------
+constexpr int kMlpChunk = 8;
+constexpr int kMlpLdsWords = kMlpHidden * kMlpHidden + 2 * kMlpHidden + 3 * kMlpHidden + 1;
+constexpr size_t kMlpLdsBytes64 = ((size_t)kMlpLdsWords * 8 + 15) / 16 * 16;
+
+__device__ __forceinline__ void stage_mlp64(const float *params, double *l_w)
+{
+    constexpr int H = kMlpHidden;
+    for (int k = threadIdx.x; k < kMlpLdsWords; k += blockDim.x) {
+        int src;
+        if (k < H * H) {
+            src = kOffW2 + (k % H) * H + k / H;       // word j H + i <- W2[i][j]
+        } else {
+            const int r = k - H * H;
+            src = r < 2 * H ? kOffW1 + r                      // W1 [64][2]
+                : r < 3 * H ? kOffB1 + (r - 2 * H)            // b1
+                : r < 4 * H ? kOffB2 + (r - 3 * H)            // b2
+                : r < 5 * H ? kOffW3 + (r - 4 * H)            // W3 row 0
+                            : kOffB3;                         // b3[0]
+        }
+        l_w[k] = (double)params[src];
+    }
+}
+
+__device__ __forceinline__ double mlp_out0_64(const double *l_w, double x0, double x1)
+{
+    constexpr int H = kMlpHidden;
+    const double *W2t = l_w, *W1 = l_w + H * H, *b1 = W1 + 2 * H, *b2 = b1 + H, *W3 = b2 + H;
+    double out = W3[H];
+    for (int c = 0; c < H; c += kMlpChunk) {
+        double acc[kMlpChunk];
+#pragma unroll
+        for (int i = 0; i < kMlpChunk; ++i) acc[i] = b2[c + i];
+        for (int j = 0; j < H; ++j) {
+            const double h = tanh(fma(W1[2 * j], x0, fma(W1[2 * j + 1], x1, b1[j])));
+#pragma unroll
+            for (int i = 0; i < kMlpChunk; ++i) acc[i] = fma(W2t[j * H + c + i], h, acc[i]);
+        }
+#pragma unroll
+        for (int i = 0; i < kMlpChunk; ++i) out = fma(W3[c + i], tanh(acc[i]), out);
+    }
+    return out;
+}
+
+typedef __attribute__((address_space(4))) const float const_float;
+
+// z[j] by a run-time index, as selects (folded away where j is a constant)
+template <typename T>
+__device__ __forceinline__ T pick4(const T z[4], int j)
+{
+    return j == 0 ? z[0] : j == 1 ? z[1] : j == 2 ? z[2] : z[3];
+}
+
+__device__ __forceinline__ float mlp_tanh32(float s)
+{
+    const float e = __builtin_amdgcn_exp2f(s * 2.8853900817779268f);   // e^(2s) = 2^(2 s log2 e)
+    return fmaf(-2.0f, __builtin_amdgcn_rcpf(e + 1.0f), 1.0f);
+}
+
+__device__ __forceinline__ float mlp_out0_32(const_float *p, float x0, float x1)
+{
+    constexpr int H = kMlpHidden;
+    float h[H];
+#pragma unroll
+    for (int j = 0; j < H; ++j)
+        h[j] = mlp_tanh32(fmaf(p[kOffW1 + 2 * j], x0, fmaf(p[kOffW1 + 2 * j + 1], x1, p[kOffB1 + j])));
+    float out = p[kOffB3];
+    for (int o = 0; o < H; ++o) {
+        const_float *row = p + kOffW2 + o * H;
+        // two partial sums: two independent chains of multiply-adds
+        float s0 = p[kOffB2 + o], s1 = 0.0f;
+#pragma unroll
+        for (int j = 0; j < H; j += 2) {
+            s0 = fmaf(row[j], h[j], s0);
+            s1 = fmaf(row[j + 1], h[j + 1], s1);
+        }
+        out = fmaf(p[kOffW3 + o], mlp_tanh32(s0 + s1), out);
+    }
+    return out;
+}
+
+// The network's normalised inputs: x0 = phi m_k0 + m_off0, x1 = ln max(|pi|, 1e-30) m_k1 + m_off1;
+// FP32 state reads phi as x = phi - phi_end and takes log2.
+struct NetConsts32 {
+    float k0, off0, k1, off1;
+};
+
+__device__ __forceinline__ NetConsts32 net_consts32(const Inst &I)
+{
+    NetConsts32 q;
+    q.k0 = (float)I.m_k0;
+    q.off0 = (float)fma(I.phi_end, I.m_k0, I.m_off0);
+    q.k1 = (float)(I.m_k1 * 0.69314718055994531);
+    q.off1 = (float)I.m_off1;
+    return q;
+}
+
+// ---------------------------------------------------------------------------
 // FP64 state: the lanes of one wave integrate trajectories of instance I,
 // claimed from `cursor` (global or LDS), until the range is exhausted.
 //
@@ -558,6 +671,9 @@ __device__ __forceinline__ void lanes_fp64(const Inst &I, const RunArgs &R, cons
                                            uint64_t n_traj, uint64_t traj_offset)
 {
     static_assert(!GRAD || BIAS == kBiasMlp, "replay needs the tabulated control");
+    constexpr bool LEARNED = BIAS == kBiasMlp || BIAS == kBiasMlpExact;
+    const double *l_w = reinterpret_cast<const double *>(l_grid);
+    const uint32_t every = (uint32_t)I.mlp_every;
     // POT: kPotPiecewiseLinear serves both linear-family potentials (V'/V = 1/d below);
     // kPotGaussianBump computes the bump's V'/V
     const DriftConsts dk = drift_consts(I);
@@ -578,6 +694,8 @@ __device__ __forceinline__ void lanes_fp64(const Inst &I, const RunArgs &R, cons
     bool live = has;          // has a trajectory that has not ended yet
     double phi = I.phi_in, pi_ = I.pi_in, lnw = 0.0;
     uint32_t n = 0;
+    double a_held = 0.0;      // exact network: its output at the last evaluation
+    uint32_t next_eval = 0;   // exact network: the step of the next evaluation
     uint64_t traj = 0;        // GRAD: the listed trajectory
     double ww = 0.0;          // GRAD: its weight w^2
     int g_cell = -1;          // GRAD: cell of the running sums
@@ -594,7 +712,7 @@ __device__ __forceinline__ void lanes_fp64(const Inst &I, const RunArgs &R, cons
         bool fresh = false;
         uint32_t ev_status, ev_n;   // written before use: read only where fresh is set
         double ev_N, ev_lnw;
-#pragma unroll
+#pragma unroll(BIAS == kBiasMlpExact ? 1 : 4)   // the exact network: one copy of its code
         for (int j = 0; j < 4; ++j) {
             if (CENSOR && live && n == I.max_steps) {
                 ev_status = kFlagCensored;
@@ -630,7 +748,15 @@ __device__ __forceinline__ void lanes_fp64(const Inst &I, const RunArgs &R, cons
             int cell = 0;
             double f0 = 0.0, f1 = 0.0;
             if (BIAS == kBiasMlp) a = grid_amp64(gc, l_grid, phi, pi_, cell, f0, f1);
-            const double zs = z[j];                       // xi sqrt(dN)
+            if (BIAS == kBiasMlpExact) {
+                if (n == next_eval) {
+                    a_held = mlp_out0_64(l_w, fma(phi, I.m_k0, I.m_off0),
+                                         fma(log(fmax(fabs(pi_), 1e-30)), I.m_k1, I.m_off1));
+                    next_eval += every;
+                }
+                a = a_held;
+            }
+            const double zs = pick4(z, j);                // xi sqrt(dN)
             const double noise = S * zs;
             // without a bias the amplitude is a literal 0, which IEEE arithmetic does not fold away:
             // the terms are left out instead (the same values, up to the sign of a zero)
@@ -644,7 +770,7 @@ __device__ __forceinline__ void lanes_fp64(const Inst &I, const RunArgs &R, cons
                 } else {
                     lnw -= (S > 0.0) ? a * zs + half_a2_dN : 0.0;
                 }
-            } else if (BIAS == kBiasMlp) {
+            } else if (LEARNED) {
                 const double dA = fma(a, zs, a * a * half_dN);
                 lnw -= (ALLPOS || S > 0.0) ? dA : 0.0;
             }
@@ -700,6 +826,8 @@ __device__ __forceinline__ void lanes_fp64(const Inst &I, const RunArgs &R, cons
             pi_ = I.pi_in;
             lnw = 0.0;
             n = 0;
+            a_held = 0.0;
+            next_eval = 0;
             if (GRAD) {
                 traj = rp.tail[rel].traj;
                 ww = rp.tail[rel].ww;
@@ -776,6 +904,10 @@ __device__ __forceinline__ void lanes_fp32(const Inst &I, const RunArgs &R, cons
                                            uint64_t n_traj, uint64_t traj_offset)
 {
     static_assert(!GRAD || BIAS == kBiasMlp, "replay needs the tabulated control");
+    constexpr bool LEARNED = BIAS == kBiasMlp || BIAS == kBiasMlpExact;
+    const_float *wp = (const_float *)(uintptr_t)I.mlp_params;
+    const NetConsts32 nq = net_consts32(I);
+    const uint32_t every = (uint32_t)I.mlp_every;
     const F32Consts c = f32_consts(I, R);
     const GridConsts32 gc = grid_consts32(I);
     const float S0 = l_tab[0].x, t0 = l_tab[0].z;
@@ -800,6 +932,8 @@ __device__ __forceinline__ void lanes_fp32(const Inst &I, const RunArgs &R, cons
     uint32_t n_on = 0;        // constant bias: number of such steps (counted only when some node has S = 0)
     double lnw = 0.0;         // learned bias: ln w up to the current group
     uint32_t n = 0;
+    float a_held = 0.0f;      // exact network: its output at the last evaluation
+    uint32_t next_eval = 0;   // exact network: the step of the next evaluation
     uint64_t traj = 0;        // GRAD: the listed trajectory
     double ww = 0.0;          // GRAD: its weight w^2
     int g_cell = -1;          // GRAD: cell of the running sums
@@ -837,11 +971,12 @@ __device__ __forceinline__ void lanes_fp32(const Inst &I, const RunArgs &R, cons
         uint32_t ev_code;         // written before use: read only where fresh is set
         double ev_N, ev_lnw;
         auto lnw_now = [&](uint32_t steps) -> double {
-            if (BIAS == kBiasMlp) return lnw - (double)zacc;
+            if (LEARNED) return lnw - (double)zacc;
             return lnw_of(zsum + (double)zacc, ALLPOS ? steps : n_on);
         };
-#pragma unroll
+#pragma unroll(BIAS == kBiasMlpExact ? 1 : 4)   // the exact network: one copy of its code
         for (int j = 0; j < 4; ++j) {
+            const float zj = pick4(z, j);
             if (CENSOR && live && n + j == I.max_steps) {
                 ev_code = (n + j) | kFlagCensored;
                 ev_N = __builtin_nan("");
@@ -898,22 +1033,30 @@ __device__ __forceinline__ void lanes_fp32(const Inst &I, const RunArgs &R, cons
             int cell = 0;
             float f0 = 0.0f, f1 = 0.0f;
             if (BIAS == kBiasMlp) a = grid_amp32(gc, l_grid, xs, ps, cell, f0, f1);
+            if (BIAS == kBiasMlpExact) {
+                if (n + j == next_eval) {
+                    a_held = mlp_out0_32(wp, fmaf(xs, nq.k0, nq.off0),
+                                         fmaf(__builtin_amdgcn_logf(fmaxf(fabsf(ps), 1e-30f)), nq.k1, nq.off1));
+                    next_eval += every;
+                }
+                a = a_held;
+            }
             // Bn = a S dN + S xi sqrt(dN): the bias and noise increments of phi (a constant bias
             // rides in z = xi sqrt(dN) + a dN; the learned one is added here, z = xi sqrt(dN))
-            const float Bn = (BIAS == kBiasMlp) ? fmaf(a * S, c.dN, S * z[j]) : S * z[j];
+            const float Bn = LEARNED ? fmaf(a * S, c.dN, S * zj) : S * zj;
             const float dx = fmaf(ps, c.dN, Bn);
             // dpi = -(3 - pi^2/2)(pi + V'/V) dN + t Bn = (pi^2 - 6)(pi dN/2 + (V'/V) dN/2) + t Bn
             const float dpi = fmaf(fmaf(ps, ps, -6.0f), fmaf(ps, c.half_dN, r), t * Bn);
             if (BIAS == kBiasConst) {
                 if (ALLPOS) {
-                    zacc = (j == 0) ? z[0] : zacc + z[j];
+                    zacc = (j == 0) ? z[0] : zacc + zj;
                 } else {
                     const bool on = S > 0.0f;
-                    zacc += on ? z[j] : 0.0f;
+                    zacc += on ? zj : 0.0f;
                     n_on += on ? 1u : 0u;
                 }
-            } else if (BIAS == kBiasMlp) {
-                const float dA = fmaf(a, z[j], a * a * (0.5f * c.dN));
+            } else if (LEARNED) {
+                const float dA = fmaf(a, zj, a * a * (0.5f * c.dN));
                 zacc += (ALLPOS || S > 0.0f) ? dA : 0.0f;
             }
             if (GRAD && live) {
@@ -921,7 +1064,7 @@ __device__ __forceinline__ void lanes_fp32(const Inst &I, const RunArgs &R, cons
                     grad_flush(rp, gc.n1c, g_cell, g_s, ww);
                     g_cell = cell;
                 }
-                grad_add(g_s, (ALLPOS || S > 0.0f) ? -z[j] : 0.0f, f0, f1);
+                grad_add(g_s, (ALLPOS || S > 0.0f) ? -zj : 0.0f, f0, f1);
             }
             const float x0l = xl;
             xl += dx;
@@ -953,7 +1096,7 @@ __device__ __forceinline__ void lanes_fp32(const Inst &I, const RunArgs &R, cons
             fresh = fresh || hit;
         }
         n += 4;
-        if (BIAS == kBiasMlp) lnw -= (double)zacc;
+        if (LEARNED) lnw -= (double)zacc;
         else zsum += (double)zacc;
         if (fresh) {
             if (GRAD) {
@@ -1012,6 +1155,8 @@ __device__ __forceinline__ void lanes_fp32(const Inst &I, const RunArgs &R, cons
             n_on = 0;
             lnw = 0.0;
             n = 0;
+            a_held = 0.0f;
+            next_eval = 0;
             if (GRAD) {
                 traj = rp.tail[rel].traj;
                 ww = rp.tail[rel].ww;
@@ -1361,7 +1506,8 @@ __device__ __forceinline__ RetireTo retire_to(const EmParams &p, const LdsAcc &a
 template <int PREC, int BIAS, int TAB, bool ALLPOS, int POT = kPotPiecewiseLinear>
 __global__ void __launch_bounds__(1024) FPT_EM_OCCUPANCY em_kernel(EmParams p)
 {
-    static_assert(POT == kPotPiecewiseLinear || (PREC == 0 && BIAS != kBiasMlp), "the bump runs in FP64 only");
+    static_assert(POT == kPotPiecewiseLinear || (PREC == 0 && (BIAS == kBiasNone || BIAS == kBiasConst)),
+                  "the bump runs in FP64 only, without a learned bias");
     extern __shared__ __align__(16) unsigned char smem[];
     const LdsAcc acc = lds_acc(smem, p.inst.hist.n_bins);
     unsigned char *l_tab = smem + align16(acc_bytes(p.inst.hist.n_bins));
@@ -1370,6 +1516,7 @@ __global__ void __launch_bounds__(1024) FPT_EM_OCCUPANCY em_kernel(EmParams p)
     if (PREC == 0) stage_table64(p.inst, reinterpret_cast<double2 *>(l_tab));
     else stage_table32(p.inst, reinterpret_cast<float4 *>(l_tab), (float)p.run.dN);
     if (BIAS == kBiasMlp) stage_grid<PREC>(p.inst, l_grid);
+    if (BIAS == kBiasMlpExact && PREC == 0) stage_mlp64(p.inst.mlp_params, reinterpret_cast<double *>(l_grid));
     __syncthreads();
     const RetireTo rt = retire_to(p, acc);
     const ReplayTo rp{nullptr, nullptr, nullptr};
@@ -1514,9 +1661,11 @@ struct KTab {
 
 }  // namespace
 
-size_t em_lds_bytes(int n_bins, int n_tab, int precision, int n_cells)
+size_t em_lds_bytes(int n_bins, int n_tab, int precision, int n_cells, bool mlp_exact)
 {
-    return align16(acc_bytes(n_bins)) + tab_bytes(precision, n_tab) + cell_bytes(precision, n_cells);
+    // the exact network stages its parameters (FP64 state) instead of the tabulated cells
+    const size_t bias = mlp_exact ? (precision == 0 ? kMlpLdsBytes64 : 0) : cell_bytes(precision, n_cells);
+    return align16(acc_bytes(n_bins)) + tab_bytes(precision, n_tab) + bias;
 }
 
 size_t replay_lds_bytes(int n_tab, int precision, int n_cells, int n_nodes)
@@ -1542,20 +1691,24 @@ const void *em_kernel_ptr(int precision, int bias_kind, int tab_mode, bool all_p
     static const KTab<0, kBiasNone> f0n;
     static const KTab<0, kBiasConst> f0c;
     static const KTab<0, kBiasMlp> f0m;
+    static const KTab<0, kBiasMlpExact> f0x;
     static const KTab<1, kBiasNone> f1n;
     static const KTab<1, kBiasConst> f1c;
     static const KTab<1, kBiasMlp> f1m;
+    static const KTab<1, kBiasMlpExact> f1x;
     const void *const(*t)[2];
-    if (precision == 0) t = bias_kind == kBiasNone ? f0n.p : bias_kind == kBiasConst ? f0c.p : f0m.p;
-    else t = bias_kind == kBiasNone ? f1n.p : bias_kind == kBiasConst ? f1c.p : f1m.p;
+    if (precision == 0)
+        t = bias_kind == kBiasNone ? f0n.p : bias_kind == kBiasConst ? f0c.p : bias_kind == kBiasMlp ? f0m.p : f0x.p;
+    else
+        t = bias_kind == kBiasNone ? f1n.p : bias_kind == kBiasConst ? f1c.p : bias_kind == kBiasMlp ? f1m.p : f1x.p;
     return t[tm][all_pos ? 1 : 0];
 }
 
-hipError_t em_launch(const EmParams &p, int precision, int grid, int block, hipStream_t stream)
+hipError_t em_launch(const EmParams &p, int precision, int grid, int block, hipStream_t stream, bool mlp_exact)
 {
-    const size_t lds = em_lds_bytes(p.inst.hist.n_bins, p.inst.n_tab, precision, grid_cells(p.inst));
-    const void *fn = em_kernel_ptr(precision, p.inst.bias_kind, tab_mode(p.inst), p.inst.all_S_pos != 0,
-                                   p.inst.pot_kind);
+    const size_t lds = em_lds_bytes(p.inst.hist.n_bins, p.inst.n_tab, precision, grid_cells(p.inst), mlp_exact);
+    const void *fn = em_kernel_ptr(precision, mlp_exact ? kBiasMlpExact : p.inst.bias_kind, tab_mode(p.inst),
+                                   p.inst.all_S_pos != 0, p.inst.pot_kind);
     EmParams pp = p;
     void *args[] = {&pp};
     return hipLaunchKernel(fn, dim3(grid), dim3(block), args, lds, stream);

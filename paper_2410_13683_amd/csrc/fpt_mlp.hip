@@ -25,7 +25,6 @@ namespace fpt {
 namespace {
 
 constexpr int H = kMlpHidden;
-constexpr int kOffB1 = 128, kOffW2 = 192, kOffB2 = 4288, kOffW3 = 4352, kOffB3 = 4480;
 
 __device__ __forceinline__ double grid_x(double lo, double hi, int n, int k)
 {

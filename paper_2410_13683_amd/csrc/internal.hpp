@@ -12,6 +12,9 @@ namespace fpt {
 
 enum : int { kPotPiecewiseLinear = 0, kPotExponential = 1, kPotGaussianBump = 2 };
 enum : int { kBiasNone = 0, kBiasConst = 1, kBiasMlp = 2 };
+// kernel-side bias variant (not in the ABI): the learned control's network evaluated exactly every
+// mlp_every steps instead of read from its table
+constexpr int kBiasMlpExact = 3;
 enum : int { kBinsLinear = 0, kBinsLog = 1 };
 
 constexpr uint32_t kFlagCensored = 0x80000000u;
@@ -19,6 +22,8 @@ constexpr uint32_t kFlagEndedEarly = 0x40000000u;
 constexpr uint32_t kStepMask = 0x3fffffffu;
 constexpr int kMlpHidden = 64;
 constexpr int kMlpParams = 4482;
+// parameter offsets (row-major, out x in): W1[64x2] b1[64] W2[64x64] b2[64] W3[2x64] b3[2]
+constexpr int kOffW1 = 0, kOffB1 = 128, kOffW2 = 192, kOffB2 = 4288, kOffW3 = 4352, kOffB3 = 4480;
 constexpr int kMlpMaxGrid = 1024;    // nodes of the tabulated network
 
 // Histogram of deltaN = N - N_ref.  scale = n_bins/(hi - lo) for linear bins,
@@ -70,6 +75,11 @@ struct Inst {
     double g_k0, g_off0, g_k1, g_off1;
     const double2 *grid64;           // cell c = i0 (n1 - 1) + i1: [2c] = (a00, a10), [2c+1] = (a01, a11)
     const float4 *grid32;            // cell c: (a00, a10, a01, a11) in FP32
+    // the network itself (fpt_run with mlp_every >= 1): its FP32 parameters and the normalised
+    // inputs x0 = phi m_k0 + m_off0, x1 = ln max(|pi|, 1e-30) m_k1 + m_off1
+    int32_t mlp_every;
+    const float *mlp_params;
+    double m_k0, m_off0, m_k1, m_off1;
     uint32_t instance;               // fourth Philox counter word
     uint32_t max_steps;
     HistSpec hist;
@@ -128,12 +138,13 @@ struct ReplayParams {
 
 // Euler-Maruyama kernels (fpt_em.hip).
 __host__ __device__ inline int grid_cells(const Inst &I) { return I.bias_kind == kBiasMlp ? (I.g_n0 - 1) * (I.g_n1 - 1) : 0; }
-size_t em_lds_bytes(int n_bins, int n_tab, int precision, int n_cells);
+size_t em_lds_bytes(int n_bins, int n_tab, int precision, int n_cells, bool mlp_exact = false);
 size_t replay_lds_bytes(int n_tab, int precision, int n_cells, int n_nodes);
 // tab_mode: 0 a single node, 1 nodes in phi, 2 nodes in time (tab_mode(inst)); pot_kind selects
 // the Gaussian-bump variant (FP64, bias none or constant only).
 const void *em_kernel_ptr(int precision, int bias_kind, int tab_mode, bool all_pos, int pot_kind = 0);
-hipError_t em_launch(const EmParams &p, int precision, int grid, int block, hipStream_t stream);
+hipError_t em_launch(const EmParams &p, int precision, int grid, int block, hipStream_t stream,
+                     bool mlp_exact = false);
 const void *replay_kernel_ptr(int precision, bool all_pos);
 size_t em2d_lds_bytes(int n_bins, int n_tab, int precision);
 const void *em2d_kernel_ptr(int precision, int bias_kind, bool all_pos, bool time_axis);

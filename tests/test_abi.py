@@ -115,19 +115,20 @@ def test_2d_table_validation(lib, case):
     assert rc == expect and not h.value, (rc, lib.fpt_last_error())
 
 
-def test_in_loop_network_is_reported_unsupported(lib):
+def test_in_loop_network_rejects_negative_stride(lib):
+    """mlp_every >= 1 selects the network evaluated every k steps; a negative stride is invalid."""
     pot = _pot()
     S = np.array([1e-6])
     t = np.zeros(1)
     tab = fpt.fpt_noise_table(1, 0.0, 0.0, S.ctypes.data_as(fpt._dp), t.ctypes.data_as(fpt._dp))
     params = np.zeros(fpt.FPT_MLP_NPARAM, dtype=np.float32)
-    bias = fpt.fpt_bias(2, 0.0, params.ctypes.data_as(fpt._fp), (ctypes.c_double * 4)(0, 1, 0, 1), 4,
+    bias = fpt.fpt_bias(2, 0.0, params.ctypes.data_as(fpt._fp), (ctypes.c_double * 4)(0, 1, 0, 1), -4,
                         (ctypes.c_int32 * 2)(8, 8), (ctypes.c_double * 4)(-1, 1, -1, 1))
     opts = fpt.fpt_options(0, 0, 8, -1.0, 1.0, 0.0, 1000, 0, 0, 0, 0)
     h = ctypes.c_void_p()
     rc = lib.fpt_create(ctypes.byref(pot), ctypes.byref(tab), ctypes.byref(bias), ctypes.byref(opts),
                         ctypes.byref(h))
-    assert rc == fpt.FPT_EUNSUPPORTED and not h.value
+    assert rc == fpt.FPT_EINVAL and not h.value
 
 
 def test_mlp_entry_points_reject_null_contexts(lib):

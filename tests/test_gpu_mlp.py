@@ -284,3 +284,59 @@ def test_training_lowers_tail_second_moment_and_stays_unbiased():
     for p, se in ((p0, se0), (p1, se1)):
         assert abs(p / exact - 1.0) < 0.05 + 4 * se / exact
     assert J1 < J0 / 8.0
+
+
+# ---- the network evaluated in the step (mlp_every = k >= 1) ------------------------------------
+
+def _exact_problem(w, k):
+    p = oracle_problem(w, mlp_params=np.ascontiguousarray(w.mlp_params, dtype=np.float32),
+                       mlp_norm=np.asarray(w.mlp_norm, dtype=np.float64))
+    p.mlp_every = k
+    return p
+
+
+@pytest.mark.parametrize("k", [1, 7, 16])
+def test_exact_network_every_k_steps_fp64_parity(k):
+    """The network itself every k steps in FP64 state (the amplitude held in between, evaluated at
+    the state of step k floor(n/k)) on 2000 inverse-Gaussian paths with a random network: per
+    trajectory against the oracle's own network every k steps (N within 1e-9, the same crossing
+    step, ln w within 1e-9).  k = 7 does not divide the launch's chunk of 128 steps, so the lanes
+    of a wave evaluate at different steps."""
+    w = _ig(n=2000, seed=33, params=W.mlp_random(13, scale=0.2, out_bias=1.0))
+    say(f"exact network every {k} steps, fp64 ig n={w.n_traj}")
+    gpu, _ = gpu_run(w, mlp_every=k)
+    ora = orc.run(_exact_problem(w, k), w.dN, w.seed, w.n_traj, last_phi=True)
+    assert np.std(gpu[1]) > 0.05                      # the network varies along the paths
+    assert_fp64_parity(gpu, ora, w)
+    # and it differs from the tabulated control: the network is not constant
+    tab, _ = gpu_run(w)
+    assert np.mean(np.abs(tab[1] - gpu[1]) > 1e-6) > 0.5
+
+
+def test_exact_network_srusr_fp64_parity_and_fp32_coupled():
+    """The SR -> USR problem (table noise, two branches, pi over decades) with the network every 8
+    steps: FP64 state per trajectory against the oracle (800 paths), and FP32 state (its network
+    in FP32) coupled with the oracle on the same streams: N within FP32 rounding except at near-ties,
+    ln w where the crossing steps agree."""
+    w = _srusr(800, 47, W.mlp_random(14, scale=0.2, out_bias=1.0))
+    p = _exact_problem(w, 8)
+    say(f"exact network every 8 steps, srusr n={w.n_traj}")
+    gpu, _ = gpu_run(w, mlp_every=8)
+    ora = orc.run(p, w.dN, w.seed, w.n_traj, last_phi=True)
+    assert_fp64_parity(gpu, ora, w)
+    (N32, l32, s32), _ = gpu_run(w.with_(precision=1), mlp_every=8)
+    dn = np.abs(N32 - ora[0])
+    same = s32 == ora[2]
+    dl = np.abs(l32 - ora[1])[same]
+    say(f"  fp32: |dN| median {np.median(dn):.2e} max {dn.max():.2e}; same step {same.mean():.4f}; "
+        f"|dlnw| median {np.median(dl):.2e} max {dl.max():.2e}")
+    assert np.mean(dn < 1e-4) > 0.98 and same.mean() > 0.95 and np.median(dl) < 1e-5 and dl.max() < 1e-3
+
+
+def test_exact_network_context_rejects_the_gradient():
+    w = _ig(n=100, params=W.mlp_random(15))
+    ctx = gpu_context(w, mlp_every=4)
+    d_grad = torch.zeros(fpt.FPT_MLP_NPARAM, dtype=torch.float32, device="cuda")
+    with pytest.raises(fpt.FptError):
+        ctx.mlp_grad(w.n_traj, w.dN, w.seed, 0.0, d_grad)
+    ctx.destroy()
