@@ -22,7 +22,9 @@ constant-bias fallback A in {0.5, 1, 2} (one pass each; its best ESS_T rate is
 the comparison), then training of the 2->64->64->2 network from the constant
 A = 1 on 1e7 generated trajectories (replay gradient of ln E[w^2 1_T] with T the
 P = 1e-10 tail found by the A = 2 pass, Adam), then the timed passes with the
-trained, tabulated control.
+trained, tabulated control.  After them (outside the timed region) the trained
+network itself, evaluated every 64 and every 16 steps, runs one pass of 1e7 fresh
+trajectories each: its rate and tail ESS beside the tabulated control's.
 
 --workload srusr_2d runs the SR -> USR problem with 2D noise (the covariance of the
 full Bunch-Davies mode at -k eta = 0.1 on 2048 nodes), FP64 state, 1e6 trajectories.
@@ -306,6 +308,34 @@ def train_learned(w, stream, train_traj: float = 1e7, iters: int = 40, lr: float
     return out
 
 
+def exact_network_passes(w, params, x_star, stream, every=(64, 16), n_traj: int = 10_000_000) -> list:
+    """After the timed passes of the tabulated control: the trained network itself evaluated every
+    k steps (mlp_every = k), one pass of n_traj fresh trajectories per k, each with its own context.
+    Reports the rate and the tail ESS at the same deltaN*, beside the tabulated control's."""
+    import torch
+    from paper_2410_13683_amd import runner
+    out = []
+    for k in every:
+        c = runner.context_for(w, mlp_params=params, mlp_every=k)
+        c.run(n_traj // 100, w.dN, w.seed, 1 << 41, stream)          # warm-up, trajectories set apart
+        torch.cuda.synchronize()
+        c.reset()
+        t0 = time.perf_counter()
+        c.run(n_traj, w.dN, w.seed, (1 << 41) + k * n_traj, stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        h = c.histogram()
+        ms = c.last_kernel_ms()
+        c.destroy()
+        p, ess, nT = tail_at(h, w, x_star)
+        steps = int(h["n_steps_total"])
+        out.append({"every": k, "trajectories": n_traj, "trajectory_steps_per_s": steps / wall, "kernel_ms": ms,
+                    "P_tail": p, "ESS_T": ess, "samples_in_T": nT, "ess_tail_per_s": ess / wall})
+        print(f"[bench] exact network every {k} steps: {steps / wall:.3e} steps/s, ESS_T {ess:.3g}", file=sys.stderr,
+              flush=True)
+    return out
+
+
 def bench_multi_amplitude(args) -> dict:
     """Configuration 3 as written: the SR -> USR problem in FP32 state with the bias amplitudes
     A in {0.5, 1, 2}, 1e8 trajectories per pass.  Step k is one pass at amplitude A_(k mod 3) (its
@@ -539,6 +569,8 @@ def main() -> int:
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     hist = ctx.histogram()
+    if learned:
+        learned["exact_network"] = exact_network_passes(w, ctx.mlp_get(), learned["deltaN_star"], stream)
     ctx.destroy()
 
     steps_total = int(hist["n_steps_total"])

@@ -952,12 +952,14 @@ __device__ __forceinline__ void lanes_fp32(const Inst &I, const RunArgs &R, cons
         return (BIAS == kBiasNone) ? 0.0 : -A * zs_total + (double)steps_on * lnw_step;
     };
 
-    // SPAN groups (phi tables): every live lane's interval at the group start holds an interpolated
-    // V'/V, and the group reads that record once: each step forms its fraction in the same
-    // interval, f = x inv_h + (u_off - j0), which a four-step path leaves by a tiny fraction of
-    // the node spacing at most (a linear extrapolation there, in a smooth interval).  Groups with
-    // a live lane in a NaN interval (table edges, the kink, tables that do not qualify) and
-    // censoring groups take the record of each step's own clamped coordinate instead.
+    // Phi tables: a lane whose interval at the group start holds an interpolated V'/V reads that
+    // record once for the group's four steps, each step forming its fraction in the same interval,
+    // f = x inv_h + (u_off - j0), which a four-step path leaves by a tiny fraction of the node
+    // spacing at most (a linear extrapolation there, in a smooth interval).  A lane whose interval
+    // is NaN-marked (table edges, the kink, tables that do not qualify) takes the record of each
+    // step's own clamped coordinate instead.  The choice is the lane's own, so a trajectory's
+    // arithmetic does not depend on the other lanes of its wave: SPAN groups, where no live lane is
+    // in a NaN interval, run the first form only; the other groups run both and select per lane.
     float4 g_node = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
     float2 g_rn = make_float2(0.0f, 0.0f);
     float g_off = 0.0f;
@@ -1018,6 +1020,13 @@ __device__ __forceinline__ void lanes_fp32(const Inst &I, const RunArgs &R, cons
                 // also take every clamped coordinate outside the table, the two intervals at the
                 // kink phi_T, and every interval of a table that does not qualify
                 r = fmaf(f, rn.y, rn.x);
+                if (TAB == 1 && g_rn.x == g_rn.x) {
+                    // the lane's group-start interval is smooth: the arithmetic of a SPAN group
+                    const float fs = fmaf(xs, c.inv_h, g_off);
+                    S = fmaf(fs, g_node.y, g_node.x);
+                    t = fmaf(fs, g_node.w, g_node.z);
+                    r = fmaf(fs, g_rn.y, g_rn.x);
+                }
                 if (__any(r != r)) {
                     // a real branch (rarely taken): the volatile asm keeps the compiler from
                     // computing the exact value in every step and selecting
@@ -1127,15 +1136,18 @@ __device__ __forceinline__ void lanes_fp32(const Inst &I, const RunArgs &R, cons
             box_muller32(w[2], w[3], c.m2ln2_dN, off, z[2], z[3]);
             using T = std::integral_constant<bool, true>;
             using F = std::integral_constant<bool, false>;
+            if constexpr (TAB == 1) {
+                // the record of the lane's interval at the group start
+                const float u0 = __builtin_amdgcn_fmed3f(fmaf(xs, c.inv_h, c.u_off), 0.0f, c.jtop);
+                const int j0 = (int)u0;
+                g_node = l_tab[j0];
+                g_rn = l_rtab[j0];
+                g_off = c.u_off - (float)j0;
+            }
             if ((uint32_t)k + 4 > left) {
                 group(T(), F(), z);
             } else {
                 if constexpr (TAB == 1) {
-                    const float u0 = __builtin_amdgcn_fmed3f(fmaf(xs, c.inv_h, c.u_off), 0.0f, c.jtop);
-                    const int j0 = (int)u0;
-                    g_node = l_tab[j0];
-                    g_rn = l_rtab[j0];
-                    g_off = c.u_off - (float)j0;
                     if (__builtin_amdgcn_ballot_w64(live && g_rn.x != g_rn.x) == 0) group(F(), T(), z);
                     else group(F(), F(), z);
                 } else {

@@ -127,6 +127,31 @@ def test_launch_configuration_does_not_change_results():
                 assert np.array_equal(N, ref[0]) and np.array_equal(lnw, ref[1]) and np.array_equal(st, ref[2])
 
 
+def test_fp32_results_do_not_depend_on_the_wave():
+    """FP32 state on the bench's problem (SR -> USR, A = 2) at a size where the lanes of a wave
+    drift through different table intervals: per-trajectory N, ln w and step counts are identical
+    across launch shapes (which regroup the trajectories into waves), and a batch of the one
+    context gives the same counts and step total."""
+    w = W.srusr_is_fp32(2.0, n_traj=2**17 + 4321)
+    ref = None
+    for cfg in [dict(), dict(block_size=256, chunk=64), dict(block_size=1024, blocks_per_cu=1, chunk=256),
+                dict(block_size=64, blocks_per_cu=2, chunk=12)]:
+        say(f"fp32 wave independence {cfg} n={w.n_traj}")
+        (N, lnw, st), h = gpu_run(w, **cfg)
+        if ref is None:
+            ref = (N, lnw, st, h)
+            continue
+        diff = np.flatnonzero((N != ref[0]) | (lnw != ref[1]) | (st != ref[2]))
+        assert len(diff) == 0, (cfg, len(diff), diff[:5])
+    ctx = gpu_context(w)
+    b = fpt.Batch([ctx], item_size=2048)
+    b.run([w.n_traj], w.dN, w.seed, 0, torch.cuda.current_stream())
+    hb = ctx.histogram()
+    b.destroy()
+    ctx.destroy()
+    assert np.array_equal(hb["count"], ref[3]["count"]) and hb["n_steps_total"] == ref[3]["n_steps_total"]
+
+
 def test_split_runs_equal_one_run():
     w = W.linear_slow_roll(seed=4).with_(bias_kind=W.BIAS_CONST, A_bias=0.5)
     say("split runs")
