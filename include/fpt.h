@@ -422,11 +422,14 @@ int fpt_noise_table_bessel2d_time(const fpt_potential *pot, double sigma, int32_
 
 /* Several contexts (each its own potential, noise table, bias amplitude,
  * histogram, step cap and Philox instance word) integrated by one persistent
- * kernel launch.  Each block takes a work item -- a slice of one instance's
- * trajectories -- from a queue ordered longest estimated cost first, stages
- * that instance's table and histogram in LDS, runs the slice and flushes the
- * histogram into the instance's context; results are identical to fpt_run on
- * each context with the same seed and trajectory range.  The launch is
+ * kernel launch.  Each instance has a trajectory cursor of its own.  Each block
+ * takes a ticket naming one instance from a queue that spreads the blocks over
+ * the instances in proportion to their estimated cost, stages that instance's
+ * table and histogram in LDS, claims its trajectories until none is left,
+ * flushes the histogram into the instance's context and takes the next ticket
+ * (skipping instances with nothing left); when the tickets are used up it joins
+ * any instance that still has trajectories.  Results are identical to fpt_run
+ * on each context with the same seed and trajectory range.  The launch is
  * captured in a hipGraph on the first run on a (non-null) stream and replayed
  * afterwards with the new work list, seed and dN.  The contexts must share the
  * device and the precision; NONE and CONST biases may be mixed; MLP is not
@@ -436,8 +439,9 @@ typedef struct fpt_batch fpt_batch;
 typedef struct {
     int32_t block_size;   /* 64..1024, multiple of 64; 0 = 1024 (or the tuned value) */
     int32_t chunk;        /* steps between retire/refill, multiple of 4; 0 = 128 */
-    int32_t item_size;    /* trajectories per work item; 0 = k x block_size with k in 1..16 chosen
-                             so that each resident block takes about 32 items per run */
+    int32_t item_size;    /* sets the number of tickets: one per item_size trajectories in total,
+                             shared among the instances by estimated cost; 0 = k x block_size with
+                             k in 1..16 chosen for about 32 tickets per resident block */
     int32_t use_graph;    /* 1 = capture/replay the launch as a hipGraph (non-null streams) */
 } fpt_batch_options;
 
@@ -458,8 +462,8 @@ int fpt_batch_run(fpt_batch *b, const uint64_t *n_traj, double dN, uint64_t seed
  * cache_path (text lines "key block chunk"; may be NULL), else time a probe
  * launch for each of block {256, 512, 1024} x chunk {32, 64, 128, 256} on
  * about 8192 trajectories per compute unit (spread over the instances in
- * proportion to n_traj, capped at 2^15 steps, one trajectory per lane per work
- * item) beyond index 2^62 with private accumulators, keep the fastest,
+ * proportion to n_traj, capped at 2^15 steps, one ticket per block_size
+ * trajectories) beyond index 2^62 with private accumulators, keep the fastest,
  * measure each instance's mean steps per trajectory for the work order and
  * append the result to cache_path.  Contexts' histograms are not touched.
  * Synchronous.  Errors: FPT_EINVAL, FPT_EHIP. */

@@ -1124,7 +1124,7 @@ struct fpt_batch {
     WorkItem *d_items = nullptr;
     size_t items_cap = 0;
     BatchRun *d_run = nullptr;
-    unsigned long long *d_item_cursor = nullptr;
+    unsigned long long *d_cursors = nullptr;   // [0] tickets, [1 + i] instance i
     WorkItem *h_items = nullptr;            // pinned staging
     size_t h_items_cap = 0;
     BatchRun *h_run = nullptr;              // pinned staging
@@ -1213,13 +1213,13 @@ extern "C" int fpt_batch_create(fpt_ctx *const *ctx, int32_t n_inst, const fpt_b
     hipError_t e = hipMalloc(&b->d_inst, sizeof(Inst) * n_inst);
     if (e == hipSuccess) e = hipMalloc(&b->d_inst_probe, sizeof(Inst) * n_inst);
     if (e == hipSuccess) e = hipMalloc(&b->d_probe_acc, probe_bytes);
-    if (e == hipSuccess) e = hipMalloc(&b->d_run, 256 + sizeof(BatchRun));
+    if (e == hipSuccess) e = hipMalloc(&b->d_run, 128 + sizeof(unsigned long long) * (1 + (size_t)n_inst));
     if (e == hipSuccess) e = hipHostMalloc(&b->h_run, sizeof(BatchRun));
     if (e == hipSuccess) e = hipEventCreate(&b->ev_start);
     if (e == hipSuccess) e = hipEventCreate(&b->ev_stop);
     if (e == hipSuccess) {
-        static_assert(sizeof(BatchRun) <= 128, "run parameters and cursor share one allocation");
-        b->d_item_cursor = reinterpret_cast<unsigned long long *>(reinterpret_cast<unsigned char *>(b->d_run) + 128);
+        static_assert(sizeof(BatchRun) <= 128, "run parameters and cursors share one allocation");
+        b->d_cursors = reinterpret_cast<unsigned long long *>(reinterpret_cast<unsigned char *>(b->d_run) + 128);
         for (int i = 0; i < n_inst; ++i) {
             hp[i] = h[i];
             hp[i].acc = static_cast<unsigned char *>(b->d_probe_acc) + b->probe_acc_off[i];
@@ -1254,10 +1254,8 @@ static int ensure_items(fpt_batch *b, size_t n)
     return FPT_OK;
 }
 
-// Work items of every instance, longest estimated cost first (longest-processing-time order).
-// Default work-item size: whole trajectories per lane (1..16 per lane of a
-// block), as many as keep about 32 items per resident block, so the queue,
-// taken longest first, ends with short items and the blocks finish together.
+// Default ticket size: whole trajectories per lane (1..16 per lane of a block), as many as give
+// about 32 tickets per resident block in total.
 static int default_item_size(const fpt_batch *b, const uint64_t *n_traj, int block)
 {
     uint64_t total = 0;
@@ -1275,33 +1273,58 @@ static int default_item_size(const fpt_batch *b, const uint64_t *n_traj, int blo
     return k * block;
 }
 
+// The work list of a run: tickets, then one entry per instance (longest estimated cost first);
+// every entry of instance i covers its whole range [traj_offset, traj_offset + n_traj[i]).  There
+// are as many tickets in total as item_size-sized slices, shared among the instances in proportion
+// to their estimated cost (mean steps x trajectories; at least one each) and interleaved by
+// stride: ticket k of instance i has the key (k + 1/2)/T_i, so that any prefix of the list holds
+// the instances in proportion to their tickets.  n_tickets receives the number of tickets.
 static std::vector<WorkItem> make_items(const fpt_batch *b, const uint64_t *n_traj, uint64_t traj_offset,
-                                        int item_size)
+                                        int item_size, uint64_t &n_tickets)
 {
-    std::vector<WorkItem> items;
-    std::vector<double> cost;
+    std::vector<int> live;
+    std::vector<double> cost(b->n_inst, 0.0);
+    double total_cost = 0.0;
+    uint64_t slices = 0;
     for (int i = 0; i < b->n_inst; ++i) {
-        const double steps = b->est_steps[i] > 0.0 ? b->est_steps[i] : 1.0;
-        for (uint64_t k = 0; k < n_traj[i]; k += (uint64_t)item_size) {
-            WorkItem w{};
-            w.inst = (uint32_t)i;
-            w.begin = traj_offset + k;
-            w.count = std::min<uint64_t>((uint64_t)item_size, n_traj[i] - k);
-            items.push_back(w);
-            cost.push_back(steps * (double)w.count);
-        }
+        if (n_traj[i] == 0) continue;
+        live.push_back(i);
+        cost[i] = (b->est_steps[i] > 0.0 ? b->est_steps[i] : 1.0) * (double)n_traj[i];
+        total_cost += cost[i];
+        slices += (n_traj[i] + (uint64_t)item_size - 1) / (uint64_t)item_size;
     }
-    std::vector<size_t> order(items.size());
-    for (size_t k = 0; k < order.size(); ++k) order[k] = k;
-    std::stable_sort(order.begin(), order.end(), [&](size_t x, size_t y) { return cost[x] > cost[y]; });
-    std::vector<WorkItem> sorted(items.size());
-    for (size_t k = 0; k < order.size(); ++k) sorted[k] = items[order[k]];
-    return sorted;
+    struct Key {
+        double key, cost;
+        int inst;
+    };
+    std::vector<Key> keys;
+    for (int i : live) {
+        const uint64_t T = std::max<uint64_t>(1, (uint64_t)std::llround((double)slices * cost[i] / total_cost));
+        for (uint64_t k = 0; k < T; ++k) keys.push_back({((double)k + 0.5) / (double)T, cost[i], i});
+    }
+    std::stable_sort(keys.begin(), keys.end(), [](const Key &x, const Key &y) {
+        return x.key < y.key || (x.key == y.key && x.cost > y.cost);
+    });
+    std::vector<WorkItem> items;
+    items.reserve(keys.size() + live.size());
+    auto entry = [&](int i) {
+        WorkItem w{};
+        w.inst = (uint32_t)i;
+        w.begin = traj_offset;
+        w.count = n_traj[i];
+        return w;
+    };
+    for (const Key &k : keys) items.push_back(entry(k.inst));
+    n_tickets = keys.size();
+    std::stable_sort(live.begin(), live.end(), [&](int x, int y) { return cost[x] > cost[y]; });
+    for (int i : live) items.push_back(entry(i));
+    return items;
 }
 
 // One persistent launch over `items` with descriptors `d_inst` (direct, or through a captured graph).
-static int batch_launch_items(fpt_batch *b, const std::vector<WorkItem> &items, const Inst *d_inst, double dN,
-                              uint64_t seed, int block, int chunk, hipStream_t s, bool graph)
+static int batch_launch_items(fpt_batch *b, const std::vector<WorkItem> &items, uint64_t n_tickets,
+                              const Inst *d_inst, double dN, uint64_t seed, int block, int chunk, hipStream_t s,
+                              bool graph)
 {
     int rc = ensure_items(b, items.size());
     if (rc) return rc;
@@ -1312,7 +1335,8 @@ static int batch_launch_items(fpt_batch *b, const std::vector<WorkItem> &items, 
     b->h_run->run.key0 = (uint32_t)seed;
     b->h_run->run.key1 = (uint32_t)(seed >> 32);
     b->h_run->run.chunk = chunk;
-    b->h_run->n_items = items.size();
+    b->h_run->n_items = n_tickets;
+    b->h_run->n_inst = items.size() - n_tickets;
     HIP_TRY(hipMemcpyAsync(b->d_items, b->h_items, sizeof(WorkItem) * items.size(), hipMemcpyHostToDevice, s));
     HIP_TRY(hipMemcpyAsync(b->d_run, b->h_run, sizeof(BatchRun), hipMemcpyHostToDevice, s));
     const void *fn = batch_kernel_ptr(b->precision, b->bias_kind, b->all_pos);
@@ -1326,9 +1350,9 @@ static int batch_launch_items(fpt_batch *b, const std::vector<WorkItem> &items, 
             b->gexec = nullptr;
             b->graph = nullptr;
             HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-            hipError_t e1 = zero_words(b->d_item_cursor, 1, s);
+            hipError_t e1 = zero_words(b->d_cursors, 1 + (size_t)b->n_inst, s);
             hipError_t e2 = batch_launch(b->precision, b->bias_kind, b->all_pos, d_inst, b->d_items, b->d_run,
-                                         b->d_item_cursor, b->max_bins, b->max_tab, grid, block, s);
+                                         b->d_cursors, b->max_bins, b->max_tab, grid, block, s);
             hipError_t e3 = hipStreamEndCapture(s, &b->graph);
             if (e1 != hipSuccess) return hip_fail(e1, "capture: cursor reset");
             if (e2 != hipSuccess) return hip_fail(e2, "capture: batch kernel");
@@ -1342,10 +1366,10 @@ static int batch_launch_items(fpt_batch *b, const std::vector<WorkItem> &items, 
         HIP_TRY(hipGraphLaunch(b->gexec, s));
         HIP_TRY(hipEventRecord(b->ev_stop, s));
     } else {
-        HIP_TRY(zero_words(b->d_item_cursor, 1, s));
+        HIP_TRY(zero_words(b->d_cursors, 1 + (size_t)b->n_inst, s));
         HIP_TRY(hipEventRecord(b->ev_start, s));
         HIP_TRY(batch_launch(b->precision, b->bias_kind, b->all_pos, d_inst, b->d_items, b->d_run,
-                             b->d_item_cursor, b->max_bins, b->max_tab, grid, block, s));
+                             b->d_cursors, b->max_bins, b->max_tab, grid, block, s));
         HIP_TRY(hipEventRecord(b->ev_stop, s));
     }
     b->ran = true;
@@ -1371,10 +1395,12 @@ extern "C" int fpt_batch_run(fpt_batch *b, const uint64_t *n_traj, double dN, ui
     if (rc) return rc;
     hipStream_t s = static_cast<hipStream_t>(hip_stream);
     const int item_size = b->item_size ? b->item_size : default_item_size(b, n_traj, b->block);
-    std::vector<WorkItem> items = make_items(b, n_traj, traj_offset, item_size);
+    uint64_t n_tickets = 0;
+    std::vector<WorkItem> items = make_items(b, n_traj, traj_offset, item_size, n_tickets);
     if (items.empty()) return FPT_OK;
     // graph capture needs a stream other than the legacy null stream
-    rc = batch_launch_items(b, items, b->d_inst, dN, seed, b->block, b->chunk, s, b->use_graph && s != nullptr);
+    rc = batch_launch_items(b, items, n_tickets, b->d_inst, dN, seed, b->block, b->chunk, s,
+                            b->use_graph && s != nullptr);
     if (rc) return rc;
     for (int i = 0; i < b->n_inst; ++i) {
         fpt_ctx *c = b->ctx[i];
@@ -1486,8 +1512,9 @@ extern "C" int fpt_batch_autotune(fpt_batch *b, const uint64_t *n_traj, double d
     const uint64_t probe_offset = 1ull << 62;
     for (int blk : blocks)
         for (int chk : chunks) {
-            std::vector<WorkItem> items = make_items(b, probe_n.data(), probe_offset, blk);
-            rc = batch_launch_items(b, items, b->d_inst_probe, dN, seed, blk, chk, s, false);
+            uint64_t n_tickets = 0;
+            std::vector<WorkItem> items = make_items(b, probe_n.data(), probe_offset, blk, n_tickets);
+            rc = batch_launch_items(b, items, n_tickets, b->d_inst_probe, dN, seed, blk, chk, s, false);
             if (rc) return rc;
             double ms = 0.0;
             rc = fpt_batch_last_ms(b, &ms);
@@ -1510,8 +1537,9 @@ extern "C" int fpt_batch_autotune(fpt_batch *b, const uint64_t *n_traj, double d
     HIP_TRY(hipMemcpy(b->d_inst_probe, hp.data(), sizeof(Inst) * b->n_inst, hipMemcpyHostToDevice));
     std::vector<uint64_t> few(b->n_inst);
     for (int i = 0; i < b->n_inst; ++i) few[i] = n_traj[i] ? 64 : 0;
-    std::vector<WorkItem> items = make_items(b, few.data(), probe_offset, 64);
-    rc = batch_launch_items(b, items, b->d_inst_probe, dN, seed, best_block, best_chunk, s, false);
+    uint64_t n_tickets = 0;
+    std::vector<WorkItem> items = make_items(b, few.data(), probe_offset, 64, n_tickets);
+    rc = batch_launch_items(b, items, n_tickets, b->d_inst_probe, dN, seed, best_block, best_chunk, s, false);
     if (rc) return rc;
     HIP_TRY(hipEventSynchronize(b->ev_stop));
     rc = probe_steps(b, steps);

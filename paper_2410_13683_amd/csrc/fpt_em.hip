@@ -1599,32 +1599,58 @@ __global__ void __launch_bounds__(1024) FPT_EM_OCCUPANCY replay_kernel(ReplayPar
 }
 
 // ---------------------------------------------------------------------------
-// Batch kernel: a persistent grid over many instances.  A block takes one
-// work item (a slice of one instance's trajectories) at a time from a global
-// queue ordered longest-first, stages that instance's table and histogram in
-// LDS, lets its waves claim the slice's trajectories from an LDS cursor,
-// flushes the histogram to the instance's accumulators and takes the next
-// item.  The run parameters are read from device memory so that a captured
-// graph can be replayed with a new seed or time step.
+// Batch kernel: a persistent grid over many instances.  Each instance has a
+// trajectory cursor of its own (cursors[1 + i], over its whole range of the
+// run).  The work list holds tickets, each sending a block to one instance
+// (ordered so that the blocks spread over the instances in proportion to their
+// estimated cost), then one entry per instance, longest estimated cost first.
+// A block takes a ticket (cursors[0]) and skips it when its instance has no
+// trajectory left; otherwise it stages that instance's table and histogram in
+// LDS, and its waves claim the instance's trajectories from its global cursor
+// until all are claimed, as in the single-instance kernel.  It then flushes the
+// histogram and takes the next ticket; once the tickets are used up it joins
+// any instance that still has trajectories left.  A block leaves an instance
+// only when the instance has no trajectory left, so its lanes drain once per
+// instance it works on, not once per ticket.  Every selection either finds an
+// instance with trajectories left or ends the block's loop, and an instance
+// found empty is never selected again: the loop ends.  The run parameters are
+// read from device memory so that a captured graph can be replayed with a new
+// seed or time step.
 // ---------------------------------------------------------------------------
+__device__ __forceinline__ bool has_left(const WorkItem &W, unsigned long long *cursors)
+{
+    return __hip_atomic_load(&cursors[1 + W.inst], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < W.count;
+}
+
 template <int PREC, int BIAS, bool ALLPOS>
 __global__ void __launch_bounds__(1024) FPT_EM_OCCUPANCY batch_kernel(const Inst *insts, const WorkItem *items,
                                                                       const BatchRun *brun,
-                                                                      unsigned long long *item_cursor, int max_bins)
+                                                                      unsigned long long *cursors, int max_bins)
 {
     extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ unsigned long long s_item, s_cursor;
+    __shared__ long long s_sel;
     const RunArgs R = brun->run;
-    const uint64_t n_items = brun->n_items;
+    const uint64_t n_items = brun->n_items, n_inst = brun->n_inst;
+    uint64_t scan = 0;     // thread 0: the next per-instance entry to look at once the tickets are used up
     for (;;) {
         if (threadIdx.x == 0) {
-            s_item = atomicAdd(item_cursor, 1ull);
-            s_cursor = 0ull;
+            long long sel = -1;
+            for (;;) {
+                const uint64_t t = atomicAdd(&cursors[0], 1ull);
+                if (t >= n_items) break;
+                if (has_left(items[t], cursors)) {
+                    sel = (long long)t;
+                    break;
+                }
+            }
+            for (; sel < 0 && scan < n_inst; ++scan)
+                if (has_left(items[n_items + scan], cursors)) sel = (long long)(n_items + scan);
+            s_sel = sel;
         }
         __syncthreads();
-        const uint64_t it = s_item;
-        if (it >= n_items) break;
-        const WorkItem W = items[it];
+        const long long sel = s_sel;
+        if (sel < 0) break;
+        const WorkItem W = items[sel];
         const Inst I = insts[W.inst];
         const LdsAcc acc = lds_acc(smem, I.hist.n_bins);
         unsigned char *l_tab = smem + align16(acc_bytes(max_bins));
@@ -1643,10 +1669,10 @@ __global__ void __launch_bounds__(1024) FPT_EM_OCCUPANCY batch_kernel(const Inst
         const ReplayTo rp{nullptr, nullptr, nullptr};
         if (PREC == 0)
             lanes_fp64<BIAS, true, ALLPOS, false>(I, R, reinterpret_cast<const double2 *>(l_tab), nullptr, rt, rp,
-                                                  &s_cursor, W.count, W.begin);
+                                                  &cursors[1 + W.inst], W.count, W.begin);
         else
             lanes_fp32<BIAS, true, ALLPOS, false>(I, R, reinterpret_cast<const float4 *>(l_tab), nullptr, rt, rp,
-                                                  &s_cursor, W.count, W.begin);
+                                                  &cursors[1 + W.inst], W.count, W.begin);
         __syncthreads();
         flush_lds_acc(acc, I.acc);
         __syncthreads();
@@ -1788,12 +1814,12 @@ const void *batch_kernel_ptr(int precision, int bias_kind, bool all_pos)
 }
 
 hipError_t batch_launch(int precision, int bias_kind, bool all_pos, const Inst *insts, const WorkItem *items,
-                        const BatchRun *run, unsigned long long *item_cursor, int max_bins, int max_tab, int grid,
+                        const BatchRun *run, unsigned long long *cursors, int max_bins, int max_tab, int grid,
                         int block, hipStream_t stream)
 {
     const size_t lds = em_lds_bytes(max_bins, max_tab, precision, 0);
     const void *fn = batch_kernel_ptr(precision, bias_kind, all_pos);
-    void *args[] = {&insts, &items, &run, &item_cursor, &max_bins};
+    void *args[] = {&insts, &items, &run, &cursors, &max_bins};
     return hipLaunchKernel(fn, dim3(grid), dim3(block), args, lds, stream);
 }
 

@@ -104,6 +104,8 @@ struct EmParams {
 };
 
 // A slice of one instance's trajectories, processed by one block of the batch kernel.
+// One entry of a batch's work list: instance inst and its whole trajectory range
+// [begin, begin + count) of the run (tickets and the per-instance entries alike).
 struct WorkItem {
     uint32_t inst;
     uint32_t pad;
@@ -114,7 +116,8 @@ struct WorkItem {
 // captured graph can be replayed with new values).
 struct BatchRun {
     RunArgs run;
-    uint64_t n_items;
+    uint64_t n_items;      // tickets at the start of the work list
+    uint64_t n_inst;       // per-instance entries after them
 };
 
 // One entry of the list of trajectories whose gradient contribution is replayed.
@@ -151,8 +154,9 @@ const void *em2d_kernel_ptr(int precision, int bias_kind, bool all_pos, bool tim
 hipError_t em2d_launch(const EmParams &p, int precision, int grid, int block, hipStream_t stream);
 hipError_t replay_launch(const ReplayParams &p, int precision, int grid, int block, hipStream_t stream);
 const void *batch_kernel_ptr(int precision, int bias_kind, bool all_pos);
+// cursors: [0] the ticket cursor, [1 + i] instance i's trajectory cursor (zeroed before each launch)
 hipError_t batch_launch(int precision, int bias_kind, bool all_pos, const Inst *insts, const WorkItem *items,
-                        const BatchRun *run, unsigned long long *item_cursor, int max_bins, int max_tab, int grid,
+                        const BatchRun *run, unsigned long long *cursors, int max_bins, int max_tab, int grid,
                         int block, hipStream_t stream);
 hipError_t zero_words(unsigned long long *ptr, size_t n, hipStream_t stream);
 
