@@ -92,9 +92,9 @@ PEAK_HBM_GBS = 8000.0
 # process (FETCH_SIZE reads 0.5 GiB: x2.0; WRITE_SIZE reads 1 GiB: x1.0).  Valid only for the
 # kernel source it was measured on (hash of the kernel file and its header).
 MEASURED_TRAFFIC = {
-    "source_sha256": "e6832e08bc11c2c373f34d13e5d428bd182e4e443ec5dad870785319e395f54b",
+    "source_sha256": "86f48db16ca024c451e8e1d2b37887e3d57ef0b94b0dcb1512ace05610db39b2",
     "workload": "srusr_is_fp32_A2", "n_traj": 100_000_000,
-    "fetch_bytes": 470.125 * 1024 * 2.0, "write_bytes": 2081469.1875 * 1024 * 1.0,
+    "fetch_bytes": 493.8125 * 1024 * 2.0, "write_bytes": 2089673.78125 * 1024 * 1.0,
 }
 
 
@@ -117,19 +117,20 @@ def kernel_source_sha() -> str:
 # 2 FMA + ADD + MUL + TRANS of each precision.  They measure what the compiled kernel executes,
 # beside the operation-by-operation count of the method used for "achieved".
 MEASURED_VALU = {
-    "source_sha256": "e6832e08bc11c2c373f34d13e5d428bd182e4e443ec5dad870785319e395f54b",
-    "srusr_is_fp32_A2": {"VALUBusy": 136.397, "VALUUtilization": 99.672,
-                         "hw_flops_per_step": {"f32": 37.295, "f64": 0.334},
-                         "insts_per_step": {"FMA_F32": 10.012, "ADD_F32": 11.265, "MUL_F32": 4.004,
-                                            "TRANS_F32": 2.003, "CVT": 2.259, "INT32": 4.045,
+    "source_sha256": "86f48db16ca024c451e8e1d2b37887e3d57ef0b94b0dcb1512ace05610db39b2",
+    "srusr_is_fp32_A2": {"VALUBusy": 137.536, "VALUUtilization": 99.475,
+                         "hw_flops_per_step": {"f32": 31.052, "f64": 0.334},
+                         "insts_per_step": {"FMA_F32": 10.268, "ADD_F32": 6.009, "MUL_F32": 2.503,
+                                            "TRANS_F32": 2.003, "CVT": 2.009, "INT32": 1.398,
                                             "FMA_F64": 0.026, "ADD_F64": 0.283}},
-    "srusr_bessel_fp64": {"VALUBusy": 95.534, "VALUUtilization": 99.746,
-                          "hw_flops_per_step": {"f32": 0.0, "f64": 57.795},
-                          "insts_per_step": {"FMA_F64": 20.353, "ADD_F64": 4.777, "MUL_F64": 10.805,
-                                             "TRANS_F64": 1.508, "INT32": 4.057, "FMA_F32": 0.0,
+    "srusr_bessel_fp64": {"VALUBusy": 95.815, "VALUUtilization": 99.693,
+                          "hw_flops_per_step": {"f32": 0.0, "f64": 58.185},
+                          "insts_per_step": {"FMA_F64": 20.49, "ADD_F64": 4.809, "MUL_F64": 10.878,
+                                             "TRANS_F64": 1.518, "INT32": 3.674, "FMA_F32": 0.0,
                                              "ADD_F32": 0.0, "MUL_F32": 0.0}},
 }
-# the measured issue ceiling of independent v_fma_f32 chains, wave-instructions per SIMD per cycle
+# the issue rate of independent v_fma_f32 chains, wave-instructions per SIMD per cycle, recorded
+# with a register-only micro-kernel (16 waves per SIMD)
 FMA_F32_ISSUE_CEILING = 0.352
 
 
