@@ -187,6 +187,37 @@ def test_bench_batched_configuration_matches_single_runs(tmp_path):
         c.destroy()
 
 
+@pytest.mark.parametrize("use_graph", [False, True])
+def test_more_instances_than_blocks(use_graph):
+    """300 instances (more than the resident blocks, so blocks take several instances and, once the
+    tickets are used up, join instances that still have trajectories), counts from 0 to 20000 with
+    one large instance: every instance's totals add up, and a sample of instances (the large one,
+    small ones, one with a single trajectory) equals single-context launches over the same
+    trajectories."""
+    rng = np.random.default_rng(12)
+    n_inst = 300
+    ws = [W.linear_slow_roll(seed=3).with_(extra={"instance": 100 + i}, precision=1) for i in range(n_inst)]
+    counts = rng.integers(0, 200, n_inst)
+    counts[7], counts[11], counts[13] = 20_000, 1, 0
+    ctxs = [runner.context_for(w) for w in ws]
+    b = fpt.Batch(ctxs, block_size=256, item_size=256, use_graph=use_graph)
+    stream = torch.cuda.Stream()
+    say(f"{n_inst} instances, {int(counts.sum())} trajectories, graph {use_graph}")
+    b.run(counts.astype(np.uint64), 1e-3, 21, 5000, stream)
+    stream.synchronize()
+    hb = [c.histogram() for c in ctxs]
+    for h, n in zip(hb, counts):
+        assert h["n_traj"] == n and int(h["count"].sum()) + h["n_censored"] + h["n_ended_early"] == n
+    for i in (7, 11, 13, 0, 150, 299):
+        r = runner.context_for(ws[i])
+        r.run(int(counts[i]), 1e-3, 21, 5000, torch.cuda.current_stream())
+        _compare(hb[i], r.histogram())
+        r.destroy()
+    b.destroy()
+    for c in ctxs:
+        c.destroy()
+
+
 def _ks_binned(ca, cb):
     """KS distance of two binned laws (cumulative masses compared at every slot edge)."""
     fa, fb = np.cumsum(ca) / np.sum(ca), np.cumsum(cb) / np.sum(cb)

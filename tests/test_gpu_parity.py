@@ -535,8 +535,10 @@ def test_histogram_waits_for_its_own_context_only():
     on a second stream.  Whether the two streams share a hardware queue or not, the short kernel
     ends first, so the short context's read must return while the long run is still going; a read
     that waited for the whole device would return only after it.  The reset then clears the short
-    context while the long run's results stay, and both histograms are checked."""
-    w_long = W.srusr_is_fp32(2.0, n_traj=5_000_000)
+    context while the long run's results stay, and both histograms are checked.  (The reset's
+    zeroing is a kernel on the context's own stream; while the long persistent kernel fills every
+    CU it cannot start, so the read after the reset may wait for the GPU: that is not checked.)"""
+    w_long = W.srusr_is_fp32(2.0, n_traj=10_000_000)
     w_short = W.linear_slow_roll(n_traj=1000, seed=6)
     s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
     c1 = runner.context_for(w_long)
@@ -551,15 +553,14 @@ def test_histogram_waits_for_its_own_context_only():
     long_still_running = not e_long.query()
     c2.reset()
     h2b = c2.histogram()
-    long_still_running_after_reset = not e_long.query()
     h1 = c1.histogram()
     assert e_long.query()
     torch.cuda.synchronize()
-    say(f"  long run still going after the short read: {long_still_running}, after the reset: "
-        f"{long_still_running_after_reset}; long run {c1.last_kernel_ms():.0f} ms")
+    say(f"  long run still going after the short read: {long_still_running}; long run "
+        f"{c1.last_kernel_ms():.0f} ms")
     assert h2["n_traj"] == 1000 and int(h2["count"].sum()) == 1000
     assert h2b["n_traj"] == 0 and int(h2b["count"].sum()) == 0 and h2b["n_steps_total"] == 0
     assert h1["n_traj"] == w_long.n_traj and int(h1["count"].sum()) + h1["n_censored"] == w_long.n_traj
     c1.destroy()
     c2.destroy()
-    assert long_still_running and long_still_running_after_reset
+    assert long_still_running
