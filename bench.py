@@ -20,9 +20,9 @@ and the CPU oracle timed on a bounded sample on the host cores.
 --workload srusr_learned measures the learned control on the same problem: the
 constant-bias fallback A in {0.5, 1, 2} (one pass each; its best ESS_T rate is
 the comparison), then training of the 2->64->64->2 network from the constant
-A = 1 on 1e7 generated trajectories (replay gradient of ln E[w^2 1_T] with T the
-P = 1e-10 tail found by the A = 2 pass, Adam), then the timed passes with the
-trained, tabulated control.  After them (outside the timed region) the trained
+A = 1 on 3e7 generated trajectories in 120 iterations (replay gradient of
+ln E[w^2 1_T] with T the P = 1e-10 tail found by the A = 2 pass, Adam), then
+the timed passes with the trained, tabulated control.  After them (outside the timed region) the trained
 network itself, evaluated every 64 and every 16 steps, runs one pass of 1e7 fresh
 trajectories each: its rate and tail ESS beside the tabulated control's.
 
@@ -262,7 +262,7 @@ def tail_errors(hist, w, x) -> dict:
     return {"P_tail_err": t["P_err"], "P_tail_err_lognormal": t["P_err_lognormal"]}
 
 
-def train_learned(w, stream, train_traj: float = 1e7, iters: int = 40, lr: float = 0.03) -> dict:
+def train_learned(w, stream, train_traj: float = 3e7, iters: int = 120, lr: float = 0.03) -> dict:
     """Constant-bias fallback passes, then GPU training of the learned control (see the module
     docstring).  Returns the context holding the trained network and the figures."""
     import torch
