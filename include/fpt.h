@@ -162,9 +162,11 @@ typedef struct {
  *          network.  mlp_every = k >= 1 makes fpt_run evaluate the network itself
  *          every k steps instead (in FP64 for FP64 state, in FP32 for FP32 state)
  *          and hold its output between evaluations: step n uses the network at the
- *          state of step k floor(n/k).  That costs about 4500 multiply-adds and 64
- *          to 512 tanh per evaluation per trajectory; it is fastest when k divides
- *          the launch's chunk (all lanes of a wave then evaluate at the same step).
+ *          state of step k floor(n/k).  An evaluation costs about 4200 multiply-adds
+ *          and 128 tanh per trajectory in FP32 state (576 tanh in FP64 state, which
+ *          recomputes the first layer for every 8 units of the second); it is fastest
+ *          when k divides the launch's chunk (all lanes of a wave then evaluate at
+ *          the same step).
  *          The table is still built (fpt_mlp_table), and fpt_mlp_grad, whose replay
  *          uses the table, needs mlp_every = 0 (else FPT_EUNSUPPORTED).  Any
  *          deterministic function of the state is an admissible control; the
