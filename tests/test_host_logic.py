@@ -88,3 +88,28 @@ def test_tail_at_and_tail_errors():
     _, lo, hi = E.lognormal(1000, h["count"], h["sum_lnw"], h["sum_lnw2"])
     half = 0.5 * (hi - lo)[3:]
     assert e["P_tail_err_lognormal"] == pytest.approx(math.sqrt((half[np.isfinite(half)] ** 2).sum()), rel=1e-12)
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py --gpus N with N > 1 exits with status 2 and says why, before touching a GPU."""
+    import subprocess
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2 and "one GPU only" in r.stderr and r.stdout == ""
+
+
+def test_measured_counter_figures_follow_the_kernel_source():
+    """The replayed traffic and VALU figures are reported only for the kernel source they were
+    measured on: a different source hash gives null."""
+    b = _bench()
+    w = W.srusr_is_fp32(2.0)
+    real = b.kernel_source_sha
+    try:
+        b.kernel_source_sha = lambda: "0" * 64
+        assert b.measured_traffic(w) == (None, None) and b.measured_valu("srusr_is_fp32_A2") is None
+        b.kernel_source_sha = lambda: b.MEASURED_VALU["source_sha256"]
+        traffic, detail = b.measured_traffic(w)
+        assert traffic is not None and detail["fetch_bytes"] > 0
+        assert b.measured_valu("srusr_is_fp32_A2")["VALUBusy"] > 0
+    finally:
+        b.kernel_source_sha = real
