@@ -18,7 +18,10 @@ import pytest
 from scipy import integrate, optimize
 
 from paper_2410_13683_amd import workloads as W
+from tests.golden.printed import printed
 from tests.test_oracle_dynamics import _kg_passage
+
+GOLD = printed()
 
 KIND = 2
 M, K, SIG = W.BUMP
@@ -73,15 +76,26 @@ def _background(orc, phi_start=3.2):
     return sol, eps2, N_T
 
 
+def test_bump_parameters_are_the_printed_ones():
+    """The workload's potential is the one Sec. 5.2 prints (tests/golden/printed_values.txt), and the
+    two printed times are ln(sigma1/sigma2) apart to their printed precision."""
+    assert W.BUMP == (GOLD["bump.m"], GOLD["bump.K"], GOLD["bump.Sigma"])
+    assert W.BUMP_PHI0 == GOLD["bump.phi0"]
+    gap = GOLD["bump.N2_minus_NT"] - GOLD["bump.N1_minus_NT"]
+    assert abs(gap - math.log(GOLD["bump.sigma1"] / GOLD["bump.sigma2"])) < 0.05
+
+
 def test_bump_background_reproduces_printed_eps2(orc):
-    """eps2(N_T + 4.7) = 0.732 and eps2(N_T + 9.3) = 1.02 as printed (three figures)."""
+    """eps2(N_T + 4.7) = 0.732 and eps2(N_T + 9.3) = 1.02 as printed (three figures; values from
+    tests/golden/printed_values.txt)."""
     sol, eps2, N_T = _background(orc)
-    assert abs(eps2(N_T + 4.7) - 0.732) < 0.001, eps2(N_T + 4.7)
-    assert abs(eps2(N_T + 9.3) - 1.02) < 0.005, eps2(N_T + 9.3)
+    N1, N2 = N_T + GOLD["bump.N1_minus_NT"], N_T + GOLD["bump.N2_minus_NT"]
+    assert abs(eps2(N1) - GOLD["bump.eps2_1"]) < 0.001, eps2(N1)
+    assert abs(eps2(N2) - GOLD["bump.eps2_2"]) < 0.005, eps2(N2)
     # ultra-slow roll in between: eps2 near -6
     assert min(eps2(N) for N in np.arange(N_T, N_T + 2.5, 0.05)) < -5.5
     # the workload's stored constants come from this background
-    assert math.isclose(eps2(N_T + 4.7), W.BUMP_EPS2, rel_tol=1e-6)
+    assert math.isclose(eps2(N1), W.BUMP_EPS2, rel_tol=1e-6)
     assert math.isclose(sol.sol(N_T + 4.7)[0], W.BUMP_PHI_LO, rel_tol=1e-9)
 
 
