@@ -77,7 +77,7 @@ def _background(orc, phi_start=3.2):
 
 
 def test_bump_parameters_are_the_printed_ones():
-    """The workload's potential is the one Sec. 5.2 prints (tests/golden/printed_values.txt), and the
+    """The workload's potential is the one Sec. 4.3 prints (tests/golden/printed_values.txt), and the
     two printed times are ln(sigma1/sigma2) apart to their printed precision."""
     assert W.BUMP == (GOLD["bump.m"], GOLD["bump.K"], GOLD["bump.Sigma"])
     assert W.BUMP_PHI0 == GOLD["bump.phi0"]

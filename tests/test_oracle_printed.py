@@ -1,4 +1,4 @@
-"""The oracle on the piecewise-linear model with the parameters Sec. 5.1 prints (eq.
+"""The oracle on the piecewise-linear model with the parameters Sec. 4.2 prints (eq.
 potential_starobinsky; tests/golden/printed_values.txt): V0 = 2.8719e-12 and A_+ = 1e-14 are said
 to give a scale-invariant spectrum with the CMB amplitude on large scales.  On the slow-roll side
 the oracle's Bessel-ansatz noise (eq. covariance_constant_nu with nu from eq.
