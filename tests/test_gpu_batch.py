@@ -218,6 +218,28 @@ def test_more_instances_than_blocks(use_graph):
         c.destroy()
 
 
+def test_batch_with_no_trajectories():
+    """All counts zero: the run launches nothing and leaves every histogram empty; a later run
+    with counts still works (the graph is captured then)."""
+    ws = [w for w in _instances(1) if w.dN == 1e-4]
+    ctxs = [runner.context_for(w) for w in ws]
+    b = fpt.Batch(ctxs, use_graph=True)
+    stream = torch.cuda.Stream()
+    b.run([0] * len(ws), 1e-4, 5, 0, stream)
+    stream.synchronize()
+    for c in ctxs:
+        h = c.histogram()
+        assert h["n_traj"] == 0 and int(h["count"].sum()) == 0 and h["n_steps_total"] == 0
+    b.run([100] * len(ws), 1e-4, 5, 0, stream)
+    stream.synchronize()
+    for c in ctxs:
+        h = c.histogram()
+        assert h["n_traj"] == 100 and int(h["count"].sum()) + h["n_censored"] + h["n_ended_early"] == 100
+    b.destroy()
+    for c in ctxs:
+        c.destroy()
+
+
 def _ks_binned(ca, cb):
     """KS distance of two binned laws (cumulative masses compared at every slot edge)."""
     fa, fb = np.cumsum(ca) / np.sum(ca), np.cumsum(cb) / np.sum(cb)
