@@ -92,9 +92,9 @@ PEAK_HBM_GBS = 8000.0
 # process (FETCH_SIZE reads 0.5 GiB: x2.0; WRITE_SIZE reads 1 GiB: x1.0).  Valid only for the
 # kernel source it was measured on (hash of the kernel file and its header).
 MEASURED_TRAFFIC = {
-    "source_sha256": "86f48db16ca024c451e8e1d2b37887e3d57ef0b94b0dcb1512ace05610db39b2",
+    "source_sha256": "b36f3c0c71be7e820091a614250d75edb9aeead7fa3798630a9b487018716aaf",
     "workload": "srusr_is_fp32_A2", "n_traj": 100_000_000,
-    "fetch_bytes": 493.8125 * 1024 * 2.0, "write_bytes": 2089673.78125 * 1024 * 1.0,
+    "fetch_bytes": 5708.9375 * 1024 * 2.0, "write_bytes": 2118314.03125 * 1024 * 1.0,
 }
 
 
@@ -117,16 +117,16 @@ def kernel_source_sha() -> str:
 # 2 FMA + ADD + MUL + TRANS of each precision.  They measure what the compiled kernel executes,
 # beside the operation-by-operation count of the method used for "achieved".
 MEASURED_VALU = {
-    "source_sha256": "86f48db16ca024c451e8e1d2b37887e3d57ef0b94b0dcb1512ace05610db39b2",
-    "srusr_is_fp32_A2": {"VALUBusy": 137.536, "VALUUtilization": 99.475,
-                         "hw_flops_per_step": {"f32": 31.052, "f64": 0.334},
-                         "insts_per_step": {"FMA_F32": 10.268, "ADD_F32": 6.009, "MUL_F32": 2.503,
-                                            "TRANS_F32": 2.003, "CVT": 2.009, "INT32": 1.398,
-                                            "FMA_F64": 0.026, "ADD_F64": 0.283}},
-    "srusr_bessel_fp64": {"VALUBusy": 95.815, "VALUUtilization": 99.693,
-                          "hw_flops_per_step": {"f32": 0.0, "f64": 58.185},
-                          "insts_per_step": {"FMA_F64": 20.49, "ADD_F64": 4.809, "MUL_F64": 10.878,
-                                             "TRANS_F64": 1.518, "INT32": 3.674, "FMA_F32": 0.0,
+    "source_sha256": "b36f3c0c71be7e820091a614250d75edb9aeead7fa3798630a9b487018716aaf",
+    "srusr_is_fp32_A2": {"VALUBusy": 137.569, "VALUUtilization": 99.133,
+                         "hw_flops_per_step": {"f32": 29.159, "f64": 0.143},
+                         "insts_per_step": {"FMA_F32": 11.165, "ADD_F32": 3.325, "MUL_F32": 1.502,
+                                            "TRANS_F32": 2.003, "CVT": 1.263, "INT32": 0.657,
+                                            "FMA_F64": 0.025, "ADD_F64": 0.094}},
+    "srusr_bessel_fp64": {"VALUBusy": 95.980, "VALUUtilization": 99.699,
+                          "hw_flops_per_step": {"f32": 0.0, "f64": 58.044},
+                          "insts_per_step": {"FMA_F64": 20.44, "ADD_F64": 4.797, "MUL_F64": 10.852,
+                                             "TRANS_F64": 1.514, "INT32": 3.665, "FMA_F32": 0.0,
                                              "ADD_F32": 0.0, "MUL_F32": 0.0}},
 }
 # the issue rate of independent v_fma_f32 chains, wave-instructions per SIMD per cycle, recorded
@@ -646,6 +646,7 @@ def main() -> int:
             "traffic": None,
             "kernel": (f"em2d_kernel<{prec.upper()}, 2D noise>" if w.noise in ("bessel2d", "bessel2d_time") else
                        "em_kernel<FP64, Gaussian bump>" if w.kind == 2 else
+                       "em_kernel<FP32 state, learned control, table>" if prec == "fp32" and learned else
                        "em_kernel<FP32 state, const bias, table>" if prec == "fp32" else "em_kernel<FP64>"),
             "kernel_ms": avg_ms,
             "flops_per_step": flops_step,

@@ -193,8 +193,9 @@ typedef struct {
  * t = ln(x/lo) * (n_bins/ln(hi/lo)) (LOG, x <= 0 is underflow), in FP64.
  * max_steps: 1..FPT_MAX_STEPS.  instance: the fourth Philox counter word.
  * block_size (64..1024, multiple of 64), blocks_per_cu (>= 1) and chunk
- * (steps between retire/refill, multiple of 4) select the launch; 0 picks the
- * built-in default.  They never change results. */
+ * (steps between retire/refill, multiple of 4; FP32 state steps in groups of
+ * 16, 4 with mlp_every > 0, and rounds it up to a multiple of the group) select
+ * the launch; 0 picks the built-in default.  They never change results. */
 typedef struct {
     int32_t precision;
     int32_t bins_kind, n_bins;
@@ -440,7 +441,8 @@ typedef struct fpt_batch fpt_batch;
 
 typedef struct {
     int32_t block_size;   /* 64..1024, multiple of 64; 0 = 1024 (or the tuned value) */
-    int32_t chunk;        /* steps between retire/refill, multiple of 4; 0 = 128 */
+    int32_t chunk;        /* steps between retire/refill, multiple of 4 (rounded up to a multiple
+                             of 16 for FP32 state); 0 = 128 */
     int32_t item_size;    /* sets the number of tickets: one per item_size trajectories in total,
                              shared among the instances by estimated cost; 0 = k x block_size with
                              k in 1..16 chosen for about 32 tickets per resident block */

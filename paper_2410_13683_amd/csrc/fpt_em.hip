@@ -13,9 +13,11 @@
 // Work distribution: a persistent grid; each wave claims trajectories from a
 // global cursor with one atomic per refill (ballot + popcount + mbcnt), runs
 // `chunk` steps, retires the lanes whose trajectory ended, and refills them.
-// New trajectories only start at chunk boundaries and chunks are a multiple of
-// 4 steps, so every active lane of a wave is at the same step modulo 4 and the
-// Philox call that feeds four steps is taken by the whole wave at once.
+// New trajectories only start at chunk boundaries and a chunk is a whole number
+// of step groups (4 steps; 16 in the FP32 kernels, except the one that evaluates
+// the network in the step, which round a chunk up to a multiple of 16), so every
+// active lane of a wave is at the same step modulo the group length and each
+// Philox call, which feeds four steps, is taken by the whole wave at once.
 //
 // Random numbers: Philox4x32-10 (Salmon et al., SC'11), key = seed, counter =
 // (n >> 2, traj lo, traj hi, instance); u = (w + 1/2) 2^-32; Box-Muller pairs
@@ -840,10 +842,12 @@ __device__ __forceinline__ void lanes_fp64(const Inst &I, const RunArgs &R, cons
 // ---------------------------------------------------------------------------
 // FP32 state: x = phi - phi_end and pi each as an unevaluated pair of floats
 // hi + lo.  A step adds its increment to the low word only (lo += dx) and
-// reads the state as the rounded sum hi + lo; once per group of four steps the
-// pair is renormalised (Fast2Sum of hi and lo).  Against an exact two-sum per
-// step this leaves one rounding of the low word per step, at the scale of
-// ulp(4 increments), far below the FP32 resolution of the state itself.
+// reads the state as the rounded sum hi + lo; once per step group (16 steps, 4
+// where the network is evaluated in the step) the pair is renormalised (Fast2Sum
+// of hi and lo).
+// Against an exact two-sum per step this leaves one rounding of the low word per
+// step, at the scale of ulp(16 increments), far below the FP32 resolution of the
+// state itself.
 // ---------------------------------------------------------------------------
 struct F32Consts {
     float xT_hi, xT_lo;        // phi_T - phi_end as a float pair
@@ -905,6 +909,10 @@ __device__ __forceinline__ void lanes_fp32(const Inst &I, const RunArgs &R, cons
 {
     static_assert(!GRAD || BIAS == kBiasMlp, "replay needs the tabulated control");
     constexpr bool LEARNED = BIAS == kBiasMlp || BIAS == kBiasMlpExact;
+    // steps per group: 16 (four generator calls), so that the group's fixed work (table record,
+    // renormalisation, FP64 sums, loop control) is shared by 16 steps; the normals of the whole
+    // group are formed first.  The exact network keeps groups of 4 and one copy of its code.
+    constexpr int G = (BIAS == kBiasMlpExact) ? 4 : 16;
     const_float *wp = (const_float *)(uintptr_t)I.mlp_params;
     const NetConsts32 nq = net_consts32(I);
     const uint32_t every = (uint32_t)I.mlp_every;
@@ -925,7 +933,8 @@ __device__ __forceinline__ void lanes_fp32(const Inst &I, const RunArgs &R, cons
     uint64_t rel = 0;
     bool has = claim(true, rel, cursor, n_traj, exhausted);
     bool live = has;          // has a trajectory that has not ended yet
-    // state: x = xh + xl, pi = ph + pl; xs, ps their rounded sums (what a step reads)
+    // state: x = xh + xl, pi = ph + pl; xs, ps their rounded sums (what a step reads; xs is formed
+    // each step only where a step reads it, and otherwise once per group)
     float xh = x_in_hi, xl = x_in_lo, ph = pi_in_hi, pl = pi_in_lo;
     float xs = x_in_hi, ps = pi_in_hi;
     double zsum = 0.0;        // constant bias: sum of z = xi sqrt(dN) + a dN over steps with S > 0
@@ -953,21 +962,26 @@ __device__ __forceinline__ void lanes_fp32(const Inst &I, const RunArgs &R, cons
     };
 
     // Phi tables: a lane whose interval at the group start holds an interpolated V'/V reads that
-    // record once for the group's four steps, each step forming its fraction in the same interval,
-    // f = x inv_h + (u_off - j0), which a four-step path leaves by a tiny fraction of the node
-    // spacing at most (a linear extrapolation there, in a smooth interval).  A lane whose interval
-    // is NaN-marked (table edges, the kink, tables that do not qualify) takes the record of each
-    // step's own clamped coordinate instead.  The choice is the lane's own, so a trajectory's
+    // record once for the whole group, and each step evaluates S, tan theta and V'/V on that
+    // interval's linear piece at its own fraction f = x inv_h + (u_off - j0).  Inside the interval
+    // this is the table's interpolation; where the group's path passes a node it extends the start
+    // interval's piece instead of switching to the next one, which differs from the interpolation
+    // by the change of slope at the node times the distance past it (second order in the node
+    // spacing for a table of a smooth function).  A lane whose interval is NaN-marked (table
+    // edges, the kink, tables that do not qualify) takes the record of each step's own clamped
+    // coordinate instead.  The choice is the lane's own, so a trajectory's
     // arithmetic does not depend on the other lanes of its wave: SPAN groups, where no live lane is
     // in a NaN interval, run the first form only; the other groups run both and select per lane.
     float4 g_node = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
     float2 g_rn = make_float2(0.0f, 0.0f);
-    float g_off = 0.0f;
+    float g_fh = 0.0f;        // the record's fraction at x = xh: a step's fraction is xl inv_h + g_fh
 
-    auto group = [&](auto censor_tag, auto span_tag, const float z[4]) {
+    auto group = [&](auto censor_tag, auto span_tag, const float z[G]) {
         constexpr bool CENSOR = decltype(censor_tag)::value;
         constexpr bool SPAN = decltype(span_tag)::value;
         static_assert(!SPAN || (TAB == 1 && !CENSOR), "one record per group: phi tables, no censoring");
+        // the rounded sum xs is read by a step only for a per-step table lookup and by the control
+        constexpr bool STEP_XS = LEARNED || (TAB == 1 && !SPAN);
         float zacc = 0.0f;        // constant bias: sum of this group's xi sqrt(dN); learned: of its dA
         bool fresh = false;
         uint32_t ev_code;         // written before use: read only where fresh is set
@@ -976,9 +990,9 @@ __device__ __forceinline__ void lanes_fp32(const Inst &I, const RunArgs &R, cons
             if (LEARNED) return lnw - (double)zacc;
             return lnw_of(zsum + (double)zacc, ALLPOS ? steps : n_on);
         };
-#pragma unroll(BIAS == kBiasMlpExact ? 1 : 4)   // the exact network: one copy of its code
-        for (int j = 0; j < 4; ++j) {
-            const float zj = pick4(z, j);
+#pragma unroll(BIAS == kBiasMlpExact ? 1 : G)   // the exact network: one copy of its code
+        for (int j = 0; j < G; ++j) {
+            const float zj = (G == 4) ? pick4(z, j) : z[j];
             if (CENSOR && live && n + j == I.max_steps) {
                 ev_code = (n + j) | kFlagCensored;
                 ev_N = __builtin_nan("");
@@ -1001,7 +1015,7 @@ __device__ __forceinline__ void lanes_fp32(const Inst &I, const RunArgs &R, cons
                 t = fmaf(f, node.w, node.z);
                 r = drift_exact();
             } else if (SPAN) {
-                const float f = fmaf(xs, c.inv_h, g_off);
+                const float f = fmaf(xl, c.inv_h, g_fh);
                 S = fmaf(f, g_node.y, g_node.x);
                 t = fmaf(f, g_node.w, g_node.z);
                 r = fmaf(f, g_rn.y, g_rn.x);
@@ -1022,7 +1036,7 @@ __device__ __forceinline__ void lanes_fp32(const Inst &I, const RunArgs &R, cons
                 r = fmaf(f, rn.y, rn.x);
                 if (TAB == 1 && g_rn.x == g_rn.x) {
                     // the lane's group-start interval is smooth: the arithmetic of a SPAN group
-                    const float fs = fmaf(xs, c.inv_h, g_off);
+                    const float fs = fmaf(xl, c.inv_h, g_fh);
                     S = fmaf(fs, g_node.y, g_node.x);
                     t = fmaf(fs, g_node.w, g_node.z);
                     r = fmaf(fs, g_rn.y, g_rn.x);
@@ -1050,12 +1064,9 @@ __device__ __forceinline__ void lanes_fp32(const Inst &I, const RunArgs &R, cons
                 }
                 a = a_held;
             }
-            // Bn = a S dN + S xi sqrt(dN): the bias and noise increments of phi (a constant bias
+            // Bn = S (a dN + xi sqrt(dN)): the bias and noise increments of phi (a constant bias
             // rides in z = xi sqrt(dN) + a dN; the learned one is added here, z = xi sqrt(dN))
-            const float Bn = LEARNED ? fmaf(a * S, c.dN, S * zj) : S * zj;
-            const float dx = fmaf(ps, c.dN, Bn);
-            // dpi = -(3 - pi^2/2)(pi + V'/V) dN + t Bn = (pi^2 - 6)(pi dN/2 + (V'/V) dN/2) + t Bn
-            const float dpi = fmaf(fmaf(ps, ps, -6.0f), fmaf(ps, c.half_dN, r), t * Bn);
+            const float Bn = S * (LEARNED ? fmaf(a, c.dN, zj) : zj);
             if (BIAS == kBiasConst) {
                 if (ALLPOS) {
                     zacc = (j == 0) ? z[0] : zacc + zj;
@@ -1075,12 +1086,18 @@ __device__ __forceinline__ void lanes_fp32(const Inst &I, const RunArgs &R, cons
                 }
                 grad_add(g_s, (ALLPOS || S > 0.0f) ? -zj : 0.0f, f0, f1);
             }
+            // x += pi dN + Bn; pi += (pi^2 - 6)(pi dN/2 + (V'/V) dN/2) + tan(theta) Bn, i.e.
+            // -(3 - pi^2/2)(pi + V'/V) dN plus the bias and noise along (1, tan theta).  The pi
+            // terms go into their low word by two FMAs; the x increment is formed first and added
+            // once, since adding its two parts one at a time rounds twice at the low word's scale,
+            // which shifted the crossing (the mean N by ~1e-6 against FP64 on the same normals).
             const float x0l = xl;
-            xl += dx;
-            pl += dpi;
-            xs = xh + xl;
+            xl += fmaf(ps, c.dN, Bn);
+            pl = fmaf(fmaf(ps, ps, -6.0f), fmaf(ps, c.half_dN, r), fmaf(t, Bn, pl));
+            if (STEP_XS) xs = xh + xl;
             ps = ph + pl;
-            const bool crossed = xs <= 0.0f;
+            // x <= 0: the sign of a rounded sum is that of the exact one, so this is xs <= 0
+            const bool crossed = xl <= -xh;
             // eps_1 = pi^2/2 >= 1: |pi| >= the float just above sqrt(2) (no float lies between
             // sqrt(2) and it, so this is pi^2 >= 2 for float pi)
             const bool ended = fabsf(ps) >= 0x1.6a09e8p+0f;
@@ -1104,7 +1121,7 @@ __device__ __forceinline__ void lanes_fp32(const Inst &I, const RunArgs &R, cons
             live = live && !hit;
             fresh = fresh || hit;
         }
-        n += 4;
+        n += G;
         if (LEARNED) lnw -= (double)zacc;
         else zsum += (double)zacc;
         if (fresh) {
@@ -1116,8 +1133,9 @@ __device__ __forceinline__ void lanes_fp32(const Inst &I, const RunArgs &R, cons
                 retire(rt, rel, ev_code & ~kStepMask, ev_code & kStepMask, ev_N, ev_lnw);
             }
         }
-        // renormalise the pairs once per group (Fast2Sum of hi and the accumulated lo; xs and ps
-        // are their rounded sums already)
+        // renormalise the pairs once per group (Fast2Sum of hi and the accumulated lo; ps, and xs
+        // where a step reads it, are their rounded sums already)
+        if (!STEP_XS) xs = xh + xl;
         xl = xl - (xs - xh);
         xh = xs;
         pl = pl - (ps - ph);
@@ -1126,14 +1144,15 @@ __device__ __forceinline__ void lanes_fp32(const Inst &I, const RunArgs &R, cons
 
     while (__any(has)) {
         const uint32_t left = wave_steps_left(has, n, I.max_steps);
-        for (int k = 0; k < R.chunk; k += 4) {
+        for (int k = 0; k < R.chunk; k += G) {
             if (!__any(live)) break;
-            uint32_t w[4];
-            philox_call(n >> 2, pre, ik, R.key0, R.key1, w);
-            float z[4];
+            uint32_t w[G];
+#pragma unroll
+            for (int q = 0; q < G; q += 4) philox_call((n >> 2) + (uint32_t)(q >> 2), pre, ik, R.key0, R.key1, w + q);
+            float z[G];
             const float off = (BIAS == kBiasConst) ? c.adN : 0.0f;
-            box_muller32(w[0], w[1], c.m2ln2_dN, off, z[0], z[1]);
-            box_muller32(w[2], w[3], c.m2ln2_dN, off, z[2], z[3]);
+#pragma unroll
+            for (int q = 0; q < G; q += 2) box_muller32(w[q], w[q + 1], c.m2ln2_dN, off, z[q], z[q + 1]);
             using T = std::integral_constant<bool, true>;
             using F = std::integral_constant<bool, false>;
             if constexpr (TAB == 1) {
@@ -1142,9 +1161,9 @@ __device__ __forceinline__ void lanes_fp32(const Inst &I, const RunArgs &R, cons
                 const int j0 = (int)u0;
                 g_node = l_tab[j0];
                 g_rn = l_rtab[j0];
-                g_off = c.u_off - (float)j0;
+                g_fh = fmaf(xh, c.inv_h, c.u_off - (float)j0);
             }
-            if ((uint32_t)k + 4 > left) {
+            if ((uint32_t)k + G > left) {
                 group(T(), F(), z);
             } else {
                 if constexpr (TAB == 1) {

@@ -90,7 +90,7 @@ struct Inst {
 struct RunArgs {
     double dN, sqrt_dN;
     uint32_t key0, key1;             // Philox key = seed
-    int32_t chunk;                   // steps between retire/refill (multiple of 4)
+    int32_t chunk;                   // steps between retire/refill (multiple of 4; whole step groups are run)
 };
 
 // One launch of the single-problem Euler-Maruyama kernel.
