@@ -33,7 +33,7 @@
  *   A trajectory that reaches max_steps steps without either is "censored".
  *
  * Random numbers: Philox4x32-10 (Salmon et al., SC'11) with key = (seed low
- * 32 bits, seed high 32 bits) and counter = (n >> 2, trajectory low 32 bits,
+ * 32 bits, seed high 32 bits) and counter = (trajectory low 32 bits, n >> 2,
  * trajectory high 32 bits, instance).  Its words w0..w3 give uniforms
  * u_j = (w_j + 1/2) 2^-32 and, by Box-Muller, xi_{4m}, xi_{4m+1} =
  * rho cos(2 pi u1), rho sin(2 pi u1), rho = sqrt(-2 ln u0), and xi_{4m+2},

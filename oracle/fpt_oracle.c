@@ -101,13 +101,14 @@ void orc_philox4x32_10(const uint32_t ctr_in[4], const uint32_t key_in[2], uint3
 }
 
 /* The unit Gaussian xi of step n of trajectory `traj` (global index) of
- * instance `instance`.  Call m = n >> 2 of the generator yields four words;
+ * instance `instance`.  Call m = n >> 2 of the generator, on the counter
+ * (traj lo, m, traj hi, instance) and the key (seed lo, seed hi), yields four words;
  * u_j = (w_j + 1/2) / 2^32 lies strictly inside (0, 1).  Box-Muller (1958):
  * (u0, u1) -> rho cos(2 pi u1), rho sin(2 pi u1) with rho = sqrt(-2 ln u0),
  * and (u2, u3) likewise; xi_n is entry n & 3 of these four. */
 static void orc_four_normals(uint64_t seed, uint32_t instance, uint64_t traj, uint64_t m, double z[4])
 {
-    uint32_t ctr[4] = {(uint32_t)m, (uint32_t)traj, (uint32_t)(traj >> 32), instance};
+    uint32_t ctr[4] = {(uint32_t)traj, (uint32_t)m, (uint32_t)(traj >> 32), instance};
     uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
     uint32_t w[4];
     orc_philox4x32_10(ctr, key, w);
@@ -136,7 +137,7 @@ void orc_normals(uint64_t seed, uint32_t instance, uint64_t traj, uint64_t n0, u
 /* Uniforms u_j of call m (exported for the Box-Muller invariance tests). */
 void orc_uniforms(uint64_t seed, uint32_t instance, uint64_t traj, uint64_t m, double u_out[4])
 {
-    uint32_t ctr[4] = {(uint32_t)m, (uint32_t)traj, (uint32_t)(traj >> 32), instance};
+    uint32_t ctr[4] = {(uint32_t)traj, (uint32_t)m, (uint32_t)(traj >> 32), instance};
     uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
     uint32_t w[4];
     orc_philox4x32_10(ctr, key, w);

@@ -20,7 +20,7 @@
 // Philox call, which feeds four steps, is taken by the whole wave at once.
 //
 // Random numbers: Philox4x32-10 (Salmon et al., SC'11), key = seed, counter =
-// (n >> 2, traj lo, traj hi, instance); u = (w + 1/2) 2^-32; Box-Muller pairs
+// (traj lo, n >> 2, traj hi, instance); u = (w + 1/2) 2^-32; Box-Muller pairs
 // (u0, u1) -> steps 4m, 4m+1 and (u2, u3) -> steps 4m+2, 4m+3.
 //
 // Two state precisions: FP64 (phi, pi, ln w in double) and FP32 state (the
@@ -61,51 +61,55 @@ __device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c)
 // Philox4x32-10 (Salmon et al., SC'11): ten rounds on the counter (c0, c1, c2, c3) with the key
 // (k0, k1); a round forms the 64-bit products M0 c0 and M1 c2 and maps the counter to
 // (hi(M1 c2) ^ c1 ^ k0, lo(M1 c2), hi(M0 c0) ^ c3 ^ k1, lo(M0 c0)), then adds the Weyl
-// increments (W0, W1) to the key.  Here the counter is (m, traj lo, traj hi, instance) for a fixed
-// trajectory, key and instance word, and only the call index m varies.  Of the first two rounds,
-// every product that does not involve m is a per-trajectory constant: round 1 multiplies the
-// trajectory's high word, round 2 the word that round 1 forms from the trajectory's low word and
-// the key.  They are computed once when a lane takes a trajectory (philox_pre), which leaves
-// rounds 1 and 2 one multiply each.
+// increments (W0, W1) to the key.  Here the counter is (traj lo, m, traj hi, instance) for a fixed
+// trajectory, key and instance word, and only the call index m varies.  It sits in a word that
+// round 1 XORs but does not multiply, so every product that does not depend on m is a
+// per-trajectory constant: both products of round 1, M1 times round 1's word 2 in round 2, and
+// M0 times round 2's word 0 in round 3.  They are computed once when a lane takes a trajectory
+// (philox_pre), which leaves rounds 1 to 3 two multiplies in all instead of six.
 struct PhiloxPre {
-    uint32_t a1;    // round 1 output word 0: hi(M1 thi) ^ tlo ^ k0
-    uint32_t b1k;   // round 1 output word 1, lo(M1 thi), with round 2's key word 0 folded in
-    uint32_t h2k;   // hi(M0 a1) with round 2's key word 1 folded in
-    uint32_t l2;    // lo(M0 a1): round 2 output word 3
+    uint32_t a;     // round 1 output word 0 without m: hi(M1 thi) ^ k0 (the word is a ^ m)
+    uint32_t y;     // lo(M0 tlo) ^ round 2's key word 1 (round 2 output word 2 is hi(M0 (a ^ m)) ^ y)
+    uint32_t x1k;   // lo(M1 (hi(M0 tlo) ^ inst ^ k1)) ^ round 3's key word 0
+    uint32_t z;     // hi(M0 x0) ^ round 3's key word 1, x0 round 2's output word 0 (constant)
+    uint32_t w;     // lo(M0 x0): round 3 output word 3
 };
 
-__device__ __forceinline__ PhiloxPre philox_pre(uint64_t traj, uint32_t k0, uint32_t k1)
+__device__ __forceinline__ PhiloxPre philox_pre(uint64_t traj, uint32_t inst, uint32_t k0, uint32_t k1)
 {
-    const uint64_t p1 = (uint64_t)kPhiloxM1 * (uint32_t)(traj >> 32);
-    PhiloxPre q;
-    q.a1 = (uint32_t)(p1 >> 32) ^ (uint32_t)traj ^ k0;
-    q.b1k = (uint32_t)p1 ^ (k0 + kPhiloxW0);
-    const uint64_t p2 = (uint64_t)kPhiloxM0 * q.a1;
-    q.h2k = (uint32_t)(p2 >> 32) ^ (k1 + kPhiloxW1);
-    q.l2 = (uint32_t)p2;
-    return q;
+    const uint64_t p = (uint64_t)kPhiloxM0 * (uint32_t)traj;            // round 1: M0 c0
+    const uint64_t q = (uint64_t)kPhiloxM1 * (uint32_t)(traj >> 32);    // round 1: M1 c2
+    PhiloxPre r;
+    r.a = (uint32_t)(q >> 32) ^ k0;
+    const uint32_t d = (uint32_t)(p >> 32) ^ inst ^ k1;                 // round 1 output word 2
+    r.y = (uint32_t)p ^ (k1 + kPhiloxW1);
+    const uint64_t q2 = (uint64_t)kPhiloxM1 * d;                        // round 2: M1 c2
+    const uint32_t x0 = (uint32_t)(q2 >> 32) ^ (uint32_t)q ^ (k0 + kPhiloxW0);
+    r.x1k = (uint32_t)q2 ^ (k0 + 2u * kPhiloxW0);
+    const uint64_t p3 = (uint64_t)kPhiloxM0 * x0;                       // round 3: M0 c0
+    r.z = (uint32_t)(p3 >> 32) ^ (k1 + 2u * kPhiloxW1);
+    r.w = (uint32_t)p3;
+    return r;
 }
 
-// The four output words for call m from the trajectory's PhiloxPre; ik = instance ^ k1
-// (wave-uniform).
-__device__ __forceinline__ void philox_call(uint32_t m, const PhiloxPre &q, uint32_t ik, uint32_t k0, uint32_t k1,
-                                            uint32_t w[4])
+// The four output words for call m from the trajectory's PhiloxPre.
+__device__ __forceinline__ void philox_call(uint32_t m, const PhiloxPre &q, uint32_t k0, uint32_t k1, uint32_t w[4])
 {
-    // round 1: (m, tlo, thi, inst) -> (a1, lo(M1 thi), hi(M0 m) ^ inst ^ k1, lo(M0 m))
-    const uint64_t p0 = (uint64_t)kPhiloxM0 * m;
-    const uint32_t c2 = (uint32_t)(p0 >> 32) ^ ik;
-    const uint32_t c3 = (uint32_t)p0;
-    // round 2: (a1, b1, c2, c3) -> (hi(M1 c2) ^ b1 ^ k0', lo(M1 c2), hi(M0 a1) ^ c3 ^ k1', lo(M0 a1))
-    const uint64_t p1 = (uint64_t)kPhiloxM1 * c2;
-    uint32_t d0 = (uint32_t)(p1 >> 32) ^ q.b1k;
-    uint32_t d1 = (uint32_t)p1;
-    uint32_t d2 = q.h2k ^ c3;
-    uint32_t d3 = q.l2;
-    k0 += 2u * kPhiloxW0;
-    k1 += 2u * kPhiloxW1;
-    // rounds 3 .. 10
+    // round 2: M0 (a ^ m); words 0 and 1 are per-trajectory constants
+    const uint64_t p2 = (uint64_t)kPhiloxM0 * (q.a ^ m);
+    const uint32_t v2 = (uint32_t)(p2 >> 32) ^ q.y;
+    const uint32_t v3 = (uint32_t)p2;
+    // round 3: M1 v2; M0 times the constant word 0 is precomputed
+    const uint64_t q3 = (uint64_t)kPhiloxM1 * v2;
+    uint32_t d0 = (uint32_t)(q3 >> 32) ^ q.x1k;
+    uint32_t d1 = (uint32_t)q3;
+    uint32_t d2 = q.z ^ v3;
+    uint32_t d3 = q.w;
+    k0 += 3u * kPhiloxW0;
+    k1 += 3u * kPhiloxW1;
+    // rounds 4 .. 10
 #pragma unroll
-    for (int r = 2; r < 10; ++r) {
+    for (int r = 3; r < 10; ++r) {
         const uint64_t a = (uint64_t)kPhiloxM0 * d0;
         const uint64_t b = (uint64_t)kPhiloxM1 * d2;
         const uint32_t n0 = xor3((uint32_t)(b >> 32), d1, k0);
@@ -706,8 +710,7 @@ __device__ __forceinline__ void lanes_fp64(const Inst &I, const RunArgs &R, cons
         traj = rp.tail[rel].traj;
         ww = rp.tail[rel].ww;
     }
-    const uint32_t ik = I.instance ^ R.key1;
-    PhiloxPre pre = philox_pre(GRAD ? traj : traj_offset + rel, R.key0, R.key1);
+    PhiloxPre pre = philox_pre(GRAD ? traj : traj_offset + rel, I.instance, R.key0, R.key1);
 
     auto group = [&](auto censor_tag, const double z[4]) {
         constexpr bool CENSOR = decltype(censor_tag)::value;
@@ -813,7 +816,7 @@ __device__ __forceinline__ void lanes_fp64(const Inst &I, const RunArgs &R, cons
         for (int k = 0; k < R.chunk; k += 4) {
             if (!__any(live)) break;
             uint32_t w[4];
-            philox_call(n >> 2, pre, ik, R.key0, R.key1, w);
+            philox_call(n >> 2, pre, R.key0, R.key1, w);
             double z[4];
             box_muller64(w[0], w[1], sqrt_dN, l_bm, z[0], z[1]);
             box_muller64(w[2], w[3], sqrt_dN, l_bm, z[2], z[3]);
@@ -834,7 +837,7 @@ __device__ __forceinline__ void lanes_fp64(const Inst &I, const RunArgs &R, cons
                 traj = rp.tail[rel].traj;
                 ww = rp.tail[rel].ww;
             }
-            pre = philox_pre(GRAD ? traj : traj_offset + rel, R.key0, R.key1);
+            pre = philox_pre(GRAD ? traj : traj_offset + rel, I.instance, R.key0, R.key1);
         }
     }
 }
@@ -927,7 +930,6 @@ __device__ __forceinline__ void lanes_fp32(const Inst &I, const RunArgs &R, cons
     const double A = (BIAS == kBiasConst) ? I.A : 0.0;
     const double half_a2_dN = 0.5 * A * A * dN;
     const float s_plus = in_vgpr(c.s_plus), s_minus = in_vgpr(c.s_minus);
-    const uint32_t ik = I.instance ^ R.key1;
 
     bool exhausted = false;
     uint64_t rel = 0;
@@ -951,7 +953,7 @@ __device__ __forceinline__ void lanes_fp32(const Inst &I, const RunArgs &R, cons
         traj = rp.tail[rel].traj;
         ww = rp.tail[rel].ww;
     }
-    PhiloxPre pre = philox_pre(GRAD ? traj : traj_offset + rel, R.key0, R.key1);
+    PhiloxPre pre = philox_pre(GRAD ? traj : traj_offset + rel, I.instance, R.key0, R.key1);
 
     // constant bias: each step's normal carries the drift shift, z = xi sqrt(dN) + c.adN with
     // c.adN = fl32(A dN), so the exponent of eq. (weight_A) in 1D over k steps,
@@ -963,7 +965,8 @@ __device__ __forceinline__ void lanes_fp32(const Inst &I, const RunArgs &R, cons
 
     // Phi tables: a lane whose interval at the group start holds an interpolated V'/V reads that
     // record once for the whole group, and each step evaluates S, tan theta and V'/V on that
-    // interval's linear piece at its own fraction f = x inv_h + (u_off - j0).  Inside the interval
+    // interval's linear piece: value at x = xh plus slope per unit x times xl (x - xh = xl within
+    // the group), the values and slopes formed once per group.  Inside the interval
     // this is the table's interpolation; where the group's path passes a node it extends the start
     // interval's piece instead of switching to the next one, which differs from the interpolation
     // by the change of slope at the node times the distance past it (second order in the node
@@ -972,9 +975,8 @@ __device__ __forceinline__ void lanes_fp32(const Inst &I, const RunArgs &R, cons
     // coordinate instead.  The choice is the lane's own, so a trajectory's
     // arithmetic does not depend on the other lanes of its wave: SPAN groups, where no live lane is
     // in a NaN interval, run the first form only; the other groups run both and select per lane.
-    float4 g_node = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-    float2 g_rn = make_float2(0.0f, 0.0f);
-    float g_fh = 0.0f;        // the record's fraction at x = xh: a step's fraction is xl inv_h + g_fh
+    // the group-start record's S, tan theta and V'/V at x = xh and their slopes per unit x
+    float g_S = 0.0f, g_dS = 0.0f, g_t = 0.0f, g_dt = 0.0f, g_r = 0.0f, g_dr = 0.0f;
 
     auto group = [&](auto censor_tag, auto span_tag, const float z[G]) {
         constexpr bool CENSOR = decltype(censor_tag)::value;
@@ -1015,10 +1017,9 @@ __device__ __forceinline__ void lanes_fp32(const Inst &I, const RunArgs &R, cons
                 t = fmaf(f, node.w, node.z);
                 r = drift_exact();
             } else if (SPAN) {
-                const float f = fmaf(xl, c.inv_h, g_fh);
-                S = fmaf(f, g_node.y, g_node.x);
-                t = fmaf(f, g_node.w, g_node.z);
-                r = fmaf(f, g_rn.y, g_rn.x);
+                S = fmaf(xl, g_dS, g_S);
+                t = fmaf(xl, g_dt, g_t);
+                r = fmaf(xl, g_dr, g_r);
             } else if (TAB) {
                 // the coordinate clamped to [0, n_tab - 1]: its integer part is the record, its
                 // fraction the weight; past the last node the last record (slope 0) gives the
@@ -1034,12 +1035,11 @@ __device__ __forceinline__ void lanes_fp32(const Inst &I, const RunArgs &R, cons
                 // also take every clamped coordinate outside the table, the two intervals at the
                 // kink phi_T, and every interval of a table that does not qualify
                 r = fmaf(f, rn.y, rn.x);
-                if (TAB == 1 && g_rn.x == g_rn.x) {
+                if (TAB == 1 && g_r == g_r) {
                     // the lane's group-start interval is smooth: the arithmetic of a SPAN group
-                    const float fs = fmaf(xl, c.inv_h, g_fh);
-                    S = fmaf(fs, g_node.y, g_node.x);
-                    t = fmaf(fs, g_node.w, g_node.z);
-                    r = fmaf(fs, g_rn.y, g_rn.x);
+                    S = fmaf(xl, g_dS, g_S);
+                    t = fmaf(xl, g_dt, g_t);
+                    r = fmaf(xl, g_dr, g_r);
                 }
                 if (__any(r != r)) {
                     // a real branch (rarely taken): the volatile asm keeps the compiler from
@@ -1148,7 +1148,7 @@ __device__ __forceinline__ void lanes_fp32(const Inst &I, const RunArgs &R, cons
             if (!__any(live)) break;
             uint32_t w[G];
 #pragma unroll
-            for (int q = 0; q < G; q += 4) philox_call((n >> 2) + (uint32_t)(q >> 2), pre, ik, R.key0, R.key1, w + q);
+            for (int q = 0; q < G; q += 4) philox_call((n >> 2) + (uint32_t)(q >> 2), pre, R.key0, R.key1, w + q);
             float z[G];
             const float off = (BIAS == kBiasConst) ? c.adN : 0.0f;
 #pragma unroll
@@ -1159,15 +1159,21 @@ __device__ __forceinline__ void lanes_fp32(const Inst &I, const RunArgs &R, cons
                 // the record of the lane's interval at the group start
                 const float u0 = __builtin_amdgcn_fmed3f(fmaf(xs, c.inv_h, c.u_off), 0.0f, c.jtop);
                 const int j0 = (int)u0;
-                g_node = l_tab[j0];
-                g_rn = l_rtab[j0];
-                g_fh = fmaf(xh, c.inv_h, c.u_off - (float)j0);
+                const float4 g_node = l_tab[j0];
+                const float2 g_rn = l_rtab[j0];
+                const float fh = fmaf(xh, c.inv_h, c.u_off - (float)j0);   // the fraction at x = xh
+                g_S = fmaf(fh, g_node.y, g_node.x);
+                g_dS = g_node.y * c.inv_h;
+                g_t = fmaf(fh, g_node.w, g_node.z);
+                g_dt = g_node.w * c.inv_h;
+                g_r = fmaf(fh, g_rn.y, g_rn.x);
+                g_dr = g_rn.y * c.inv_h;
             }
             if ((uint32_t)k + G > left) {
                 group(T(), F(), z);
             } else {
                 if constexpr (TAB == 1) {
-                    if (__builtin_amdgcn_ballot_w64(live && g_rn.x != g_rn.x) == 0) group(F(), T(), z);
+                    if (__builtin_amdgcn_ballot_w64(live && g_r != g_r) == 0) group(F(), T(), z);
                     else group(F(), F(), z);
                 } else {
                     group(F(), F(), z);
@@ -1192,7 +1198,7 @@ __device__ __forceinline__ void lanes_fp32(const Inst &I, const RunArgs &R, cons
                 traj = rp.tail[rel].traj;
                 ww = rp.tail[rel].ww;
             }
-            pre = philox_pre(GRAD ? traj : traj_offset + rel, R.key0, R.key1);
+            pre = philox_pre(GRAD ? traj : traj_offset + rel, I.instance, R.key0, R.key1);
         }
     }
 }
@@ -1241,8 +1247,7 @@ __device__ __forceinline__ void lanes_fp64_2d(const Inst &I, const RunArgs &R, c
     bool live = has;
     double phi = I.phi_in, pi_ = I.pi_in, lnw = 0.0;
     uint32_t n = 0;
-    const uint32_t ik = I.instance ^ R.key1;
-    PhiloxPre pre = philox_pre(traj_offset + rel, R.key0, R.key1);
+    PhiloxPre pre = philox_pre(traj_offset + rel, I.instance, R.key0, R.key1);
 
     // groups of two steps: one Philox call gives both steps' (xi_1, xi_2)
     auto group = [&](auto censor_tag, const double z[4]) {
@@ -1306,7 +1311,7 @@ __device__ __forceinline__ void lanes_fp64_2d(const Inst &I, const RunArgs &R, c
         for (int k = 0; k < R.chunk; k += 2) {
             if (!__any(live)) break;
             uint32_t w[4];
-            philox_call(n >> 1, pre, ik, R.key0, R.key1, w);
+            philox_call(n >> 1, pre, R.key0, R.key1, w);
             double z[4];
             box_muller64(w[0], w[1], sqrt_dN, l_bm, z[0], z[1]);
             box_muller64(w[2], w[3], sqrt_dN, l_bm, z[2], z[3]);
@@ -1321,7 +1326,7 @@ __device__ __forceinline__ void lanes_fp64_2d(const Inst &I, const RunArgs &R, c
             pi_ = I.pi_in;
             lnw = 0.0;
             n = 0;
-            pre = philox_pre(traj_offset + rel, R.key0, R.key1);
+            pre = philox_pre(traj_offset + rel, I.instance, R.key0, R.key1);
         }
     }
 }
@@ -1352,7 +1357,6 @@ __device__ __forceinline__ void lanes_fp32_2d(const Inst &I, const RunArgs &R, c
     const float adN = a * c.dN;                 // the normals' shift per unit of e
     const float half_a2_dN = 0.5f * a * a * c.dN;
     const float s_plus = in_vgpr(c.s_plus), s_minus = in_vgpr(c.s_minus);
-    const uint32_t ik = I.instance ^ R.key1;
 
     bool exhausted = false;
     uint64_t rel = 0;
@@ -1362,7 +1366,7 @@ __device__ __forceinline__ void lanes_fp32_2d(const Inst &I, const RunArgs &R, c
     float xs = x_in_hi, ps = pi_in_hi;
     double lnw = 0.0;
     uint32_t n = 0;
-    PhiloxPre pre = philox_pre(traj_offset + rel, R.key0, R.key1);
+    PhiloxPre pre = philox_pre(traj_offset + rel, I.instance, R.key0, R.key1);
 
     auto group = [&](auto censor_tag, const float z[4]) {
         constexpr bool CENSOR = decltype(censor_tag)::value;
@@ -1443,7 +1447,7 @@ __device__ __forceinline__ void lanes_fp32_2d(const Inst &I, const RunArgs &R, c
         for (int k = 0; k < R.chunk; k += 2) {
             if (!__any(live)) break;
             uint32_t w[4];
-            philox_call(n >> 1, pre, ik, R.key0, R.key1, w);
+            philox_call(n >> 1, pre, R.key0, R.key1, w);
             float z[4];
             box_muller32(w[0], w[1], c.m2ln2_dN, 0.0f, z[0], z[1]);
             box_muller32(w[2], w[3], c.m2ln2_dN, 0.0f, z[2], z[3]);
@@ -1460,7 +1464,7 @@ __device__ __forceinline__ void lanes_fp32_2d(const Inst &I, const RunArgs &R, c
             pl = pi_in_lo;
             lnw = 0.0;
             n = 0;
-            pre = philox_pre(traj_offset + rel, R.key0, R.key1);
+            pre = philox_pre(traj_offset + rel, I.instance, R.key0, R.key1);
         }
     }
 }

@@ -53,10 +53,10 @@ def test_philox_matches_rocrand(orc, rocrand_words):
 
 
 def test_counter_layout_and_uniforms(orc):
-    """u_j * 2^32 - 1/2 are the Philox words of counter (m, traj lo, traj hi, instance)."""
+    """u_j * 2^32 - 1/2 are the Philox words of counter (traj lo, m, traj hi, instance)."""
     for seed, inst, traj, m in [(5, 0, 0, 0), (5, 3, 2**40 + 17, 123456), (2**63 + 9, 7, 99, 2**31 + 5)]:
         u = orc.uniforms(seed, inst, traj, m)
-        w = orc.philox4x32_10([m & 0xFFFFFFFF, traj & 0xFFFFFFFF, traj >> 32, inst],
+        w = orc.philox4x32_10([traj & 0xFFFFFFFF, m & 0xFFFFFFFF, traj >> 32, inst],
                               [seed & 0xFFFFFFFF, seed >> 32])
         assert np.array_equal(u * 2.0**32 - 0.5, w.astype(np.float64))
         assert np.all((u > 0) & (u < 1))

@@ -78,11 +78,18 @@ def test_vanishing_noise_time_axis_equals_phi_axis(orc):
                   pi_in=w.pi_in, phi_end=w.phi_end, bias_kind=orc.BIAS_CONST, A_bias=1.0)
     pp = orc.Problem(S=Sp * 1e-9, tan_theta=tp, phi_lo=w.table_lo, phi_hi=w.table_hi, **common)
     pt = orc.Problem(S=St * 1e-9, tan_theta=tt, phi_lo=0.0, phi_hi=10.5, tab_axis=1, **common)
-    Np, lp, sp = orc.run(pp, w.dN, 5, 6)
+    Np, lp, sp, php = orc.run(pp, w.dN, 5, 6, last_phi=True)
     Nt, lt, st = orc.run(pt, w.dN, 5, 6)
-    assert np.all(sp == st)
+    # phi_end sits where the noise-free passage falls on a step boundary (N = 10 at this dN), so a
+    # path with vanishing noise ends within ~1e-15 of phi_end and its crossing step is a near-tie
+    # (the identity of the crossing step, reading 16): it may move by one step there, N may not
+    tie = np.minimum(np.abs(php[:, 0] - w.phi_end), np.abs(php[:, 1] - w.phi_end)) < 1e-12
+    same = (sp & orc.STEP_MASK) == (st & orc.STEP_MASK)
+    d = (sp & orc.STEP_MASK).astype(np.int64) - (st & orc.STEP_MASK).astype(np.int64)
+    assert np.all(same | (tie & (np.abs(d) == 1))) and same.sum() >= 3
+    assert np.all((sp & ~np.uint32(orc.STEP_MASK)) == (st & ~np.uint32(orc.STEP_MASK)))
     np.testing.assert_allclose(Nt, Np, rtol=1e-12)
-    np.testing.assert_allclose(lt, lp, rtol=1e-12)
+    np.testing.assert_allclose(lt[same], lp[same], rtol=1e-12)
 
 
 def test_linear_in_time_noise_closed_form(orc):
