@@ -1348,6 +1348,8 @@ template <int BIAS, bool ALLPOS, bool TIME>
 __device__ __forceinline__ void lanes_fp32_2d(const Inst &I, const RunArgs &R, const float4 *l_tab, const RetireTo &rt,
                                               unsigned long long *cursor, uint64_t n_traj, uint64_t traj_offset)
 {
+    // steps per group: 16 (eight generator calls, the normals of the whole group formed first)
+    constexpr int G = 16;
     const F32Consts c = f32_consts(I, R);
     const double x_in = I.phi_in - I.phi_end;
     const float x_in_hi = (float)x_in, x_in_lo = (float)(x_in - (double)x_in_hi);
@@ -1363,19 +1365,30 @@ __device__ __forceinline__ void lanes_fp32_2d(const Inst &I, const RunArgs &R, c
     bool has = claim(true, rel, cursor, n_traj, exhausted);
     bool live = has;
     float xh = x_in_hi, xl = x_in_lo, ph = pi_in_hi, pl = pi_in_lo;
-    float xs = x_in_hi, ps = pi_in_hi;
+    float xs = x_in_hi, ps = pi_in_hi;          // xs is formed each step only for a per-step lookup
     double lnw = 0.0;
     uint32_t n = 0;
     PhiloxPre pre = philox_pre(traj_offset + rel, I.instance, R.key0, R.key1);
 
-    auto group = [&](auto censor_tag, const float z[4]) {
+    // Phi tables: the lane's group-start record, as in lanes_fp32: each entry's value at x = xh
+    // and its slope per unit x, so that a step of a lane whose start interval is smooth evaluates
+    // every entry as value + slope * xl (the start interval's linear piece, extended past a node
+    // the group's path passes); lanes in NaN-marked intervals read each step's own record.
+    float g_v[6], g_d[6];           // S_pp, S_pq, S_qq, e_phi, e_pi, r
+#pragma unroll
+    for (int q = 0; q < 6; ++q) g_v[q] = g_d[q] = 0.0f;
+
+    auto group = [&](auto censor_tag, auto span_tag, const float z[2 * G]) {
         constexpr bool CENSOR = decltype(censor_tag)::value;
+        constexpr bool SPAN = decltype(span_tag)::value;
+        static_assert(!SPAN || (!TIME && !CENSOR), "one record per group: phi tables, no censoring");
+        constexpr bool STEP_XS = !TIME && !SPAN;
         float zacc = 0.0f;        // this group's sum of dA
         bool fresh = false;
         uint32_t ev_code;
         double ev_N, ev_lnw;
 #pragma unroll
-        for (int j = 0; j < 2; ++j) {
+        for (int j = 0; j < G; ++j) {
             if (CENSOR && live && n + j == I.max_steps) {
                 ev_code = (n + j) | kFlagCensored;
                 ev_N = __builtin_nan("");
@@ -1383,19 +1396,41 @@ __device__ __forceinline__ void lanes_fp32_2d(const Inst &I, const RunArgs &R, c
                 live = false;
                 fresh = true;
             }
-            const float u = __builtin_amdgcn_fmed3f(
-                TIME ? fmaf((float)(n + j), c.t_scale, c.t_off) : fmaf(xs, c.inv_h, c.u_off), 0.0f, c.jtop);
-            const float f = __builtin_amdgcn_fractf(u);
-            const float4 *rec = l_tab + 3 * (int)u;
-            const float4 A0 = rec[0], A1 = rec[1], A2 = rec[2];
-            const float Spp = fmaf(f, A0.y, A0.x), Spq = fmaf(f, A0.w, A0.z);
-            const float Sqq = fmaf(f, A1.y, A1.x), e1 = fmaf(f, A1.w, A1.z), e2 = fmaf(f, A2.y, A2.x);
-            float r = fmaf(f, A2.w, A2.z);      // (V'/V) dN/2
-            if (__any(r != r)) {
-                asm volatile("; exact V'/V");
-                if (r != r) {
-                    const float dT = (xh - c.xT_hi) + (xl - c.xT_lo);
-                    r = __builtin_amdgcn_rcpf(fmaf(dT, c.kx, (dT >= 0.0f) ? s_plus : s_minus));
+            float Spp, Spq, Sqq, e1, e2, r;     // r = (V'/V) dN/2
+            if (SPAN) {
+                Spp = fmaf(xl, g_d[0], g_v[0]);
+                Spq = fmaf(xl, g_d[1], g_v[1]);
+                Sqq = fmaf(xl, g_d[2], g_v[2]);
+                e1 = fmaf(xl, g_d[3], g_v[3]);
+                e2 = fmaf(xl, g_d[4], g_v[4]);
+                r = fmaf(xl, g_d[5], g_v[5]);
+            } else {
+                const float u = __builtin_amdgcn_fmed3f(
+                    TIME ? fmaf((float)(n + j), c.t_scale, c.t_off) : fmaf(xs, c.inv_h, c.u_off), 0.0f, c.jtop);
+                const float f = __builtin_amdgcn_fractf(u);
+                const float4 *rec = l_tab + 3 * (int)u;
+                const float4 A0 = rec[0], A1 = rec[1], A2 = rec[2];
+                Spp = fmaf(f, A0.y, A0.x);
+                Spq = fmaf(f, A0.w, A0.z);
+                Sqq = fmaf(f, A1.y, A1.x);
+                e1 = fmaf(f, A1.w, A1.z);
+                e2 = fmaf(f, A2.y, A2.x);
+                r = fmaf(f, A2.w, A2.z);
+                if (!TIME && g_v[5] == g_v[5]) {
+                    // the lane's group-start interval is smooth: the arithmetic of a SPAN group
+                    Spp = fmaf(xl, g_d[0], g_v[0]);
+                    Spq = fmaf(xl, g_d[1], g_v[1]);
+                    Sqq = fmaf(xl, g_d[2], g_v[2]);
+                    e1 = fmaf(xl, g_d[3], g_v[3]);
+                    e2 = fmaf(xl, g_d[4], g_v[4]);
+                    r = fmaf(xl, g_d[5], g_v[5]);
+                }
+                if (__any(r != r)) {
+                    asm volatile("; exact V'/V");
+                    if (r != r) {
+                        const float dT = (xh - c.xT_hi) + (xl - c.xT_lo);
+                        r = __builtin_amdgcn_rcpf(fmaf(dT, c.kx, (dT >= 0.0f) ? s_plus : s_minus));
+                    }
                 }
             }
             const float z1 = z[2 * j], z2 = z[2 * j + 1];            // xi sqrt(dN)
@@ -1413,9 +1448,10 @@ __device__ __forceinline__ void lanes_fp32_2d(const Inst &I, const RunArgs &R, c
             const float x0l = xl;
             xl += dx;
             pl += dpi;
-            xs = xh + xl;
+            if (STEP_XS) xs = xh + xl;
             ps = ph + pl;
-            const bool crossed = xs <= 0.0f;
+            // x <= 0: the sign of a rounded sum is that of the exact one, so this is xs <= 0
+            const bool crossed = xl <= -xh;
             const bool ended = fabsf(ps) >= 0x1.6a09e8p+0f;
             const bool hit = live && (crossed || ended);
             if (hit) {
@@ -1433,9 +1469,10 @@ __device__ __forceinline__ void lanes_fp32_2d(const Inst &I, const RunArgs &R, c
             live = live && !hit;
             fresh = fresh || hit;
         }
-        n += 2;
+        n += G;
         lnw -= (double)zacc;
         if (fresh) retire(rt, rel, ev_code & ~kStepMask, ev_code & kStepMask, ev_N, ev_lnw);
+        if (!STEP_XS) xs = xh + xl;
         xl = xl - (xs - xh);
         xh = xs;
         pl = pl - (ps - ph);
@@ -1444,15 +1481,41 @@ __device__ __forceinline__ void lanes_fp32_2d(const Inst &I, const RunArgs &R, c
 
     while (__any(has)) {
         const uint32_t left = wave_steps_left(has, n, I.max_steps);
-        for (int k = 0; k < R.chunk; k += 2) {
+        for (int k = 0; k < R.chunk; k += G) {
             if (!__any(live)) break;
-            uint32_t w[4];
-            philox_call(n >> 1, pre, R.key0, R.key1, w);
-            float z[4];
-            box_muller32(w[0], w[1], c.m2ln2_dN, 0.0f, z[0], z[1]);
-            box_muller32(w[2], w[3], c.m2ln2_dN, 0.0f, z[2], z[3]);
-            if ((uint32_t)k + 2 > left) group(std::integral_constant<bool, true>(), z);
-            else group(std::integral_constant<bool, false>(), z);
+            uint32_t w[2 * G];
+#pragma unroll
+            for (int q = 0; q < G / 2; ++q) philox_call((n >> 1) + (uint32_t)q, pre, R.key0, R.key1, w + 4 * q);
+            float z[2 * G];
+#pragma unroll
+            for (int q = 0; q < 2 * G; q += 2) box_muller32(w[q], w[q + 1], c.m2ln2_dN, 0.0f, z[q], z[q + 1]);
+            using T = std::integral_constant<bool, true>;
+            using F = std::integral_constant<bool, false>;
+            if constexpr (!TIME) {
+                // the record of the lane's interval at the group start
+                const float u0 = __builtin_amdgcn_fmed3f(fmaf(xh, c.inv_h, c.u_off), 0.0f, c.jtop);
+                const int j0 = (int)u0;
+                const float4 *rec = l_tab + 3 * j0;
+                const float4 A0 = rec[0], A1 = rec[1], A2 = rec[2];
+                const float fh = fmaf(xh, c.inv_h, c.u_off - (float)j0);   // the fraction at x = xh
+                const float v0[6] = {A0.x, A0.z, A1.x, A1.z, A2.x, A2.z};
+                const float d0[6] = {A0.y, A0.w, A1.y, A1.w, A2.y, A2.w};
+#pragma unroll
+                for (int q = 0; q < 6; ++q) {
+                    g_v[q] = fmaf(fh, d0[q], v0[q]);
+                    g_d[q] = d0[q] * c.inv_h;
+                }
+            }
+            if ((uint32_t)k + G > left) {
+                group(T(), F(), z);
+            } else {
+                if constexpr (!TIME) {
+                    if (__builtin_amdgcn_ballot_w64(live && g_v[5] != g_v[5]) == 0) group(F(), T(), z);
+                    else group(F(), F(), z);
+                } else {
+                    group(F(), F(), z);
+                }
+            }
         }
         if (!live) has = false;
         if (claim(!has, rel, cursor, n_traj, exhausted)) {

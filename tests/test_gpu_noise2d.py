@@ -75,12 +75,16 @@ def test_fp64_2d_srusr_parity(A_bias):
     assert_fp64_parity(gpu, ora, w)
 
 
-def test_2d_launch_configuration_does_not_change_results():
-    w = W.srusr_2d(n_traj=5000, A_bias=1.0)
+@pytest.mark.parametrize("precision", [0, 1])
+def test_2d_launch_configuration_does_not_change_results(precision):
+    """Per-trajectory results and histogram counts do not depend on the block size, the blocks
+    per CU or the chunk (also one that is not a multiple of the FP32 kernel's 16-step group)."""
+    w = W.srusr_2d(n_traj=5000, A_bias=1.0).with_(precision=precision)
     a, ha = gpu_run(w)
-    b, hb = gpu_run(w, block_size=256, chunk=32)
-    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]) and np.array_equal(a[2], b[2])
-    assert np.array_equal(ha["count"], hb["count"])
+    for cfg in (dict(block_size=256, chunk=32), dict(block_size=64, blocks_per_cu=2, chunk=20)):
+        b, hb = gpu_run(w, **cfg)
+        assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]) and np.array_equal(a[2], b[2])
+        assert np.array_equal(ha["count"], hb["count"])
 
 
 def test_2d_full_size_sampled():
