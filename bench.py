@@ -92,9 +92,9 @@ PEAK_HBM_GBS = 8000.0
 # process (FETCH_SIZE reads 0.5 GiB: x2.0; WRITE_SIZE reads 1 GiB: x1.0).  Valid only for the
 # kernel source it was measured on (hash of the kernel file and its header).
 MEASURED_TRAFFIC = {
-    "source_sha256": "b36f3c0c71be7e820091a614250d75edb9aeead7fa3798630a9b487018716aaf",
+    "source_sha256": "c514e7190f6d2252270e64013524c56cd4a93399386bd17a26e3516feb650027",
     "workload": "srusr_is_fp32_A2", "n_traj": 100_000_000,
-    "fetch_bytes": 5708.9375 * 1024 * 2.0, "write_bytes": 2118314.03125 * 1024 * 1.0,
+    "fetch_bytes": 7753.8125 * 1024 * 2.0, "write_bytes": 2121458.90625 * 1024 * 1.0,
 }
 
 
@@ -117,16 +117,16 @@ def kernel_source_sha() -> str:
 # 2 FMA + ADD + MUL + TRANS of each precision.  They measure what the compiled kernel executes,
 # beside the operation-by-operation count of the method used for "achieved".
 MEASURED_VALU = {
-    "source_sha256": "b36f3c0c71be7e820091a614250d75edb9aeead7fa3798630a9b487018716aaf",
-    "srusr_is_fp32_A2": {"VALUBusy": 137.569, "VALUUtilization": 99.133,
-                         "hw_flops_per_step": {"f32": 29.159, "f64": 0.143},
-                         "insts_per_step": {"FMA_F32": 11.165, "ADD_F32": 3.325, "MUL_F32": 1.502,
-                                            "TRANS_F32": 2.003, "CVT": 1.263, "INT32": 0.657,
+    "source_sha256": "c514e7190f6d2252270e64013524c56cd4a93399386bd17a26e3516feb650027",
+    "srusr_is_fp32_A2": {"VALUBusy": 136.690, "VALUUtilization": 99.087,
+                         "hw_flops_per_step": {"f32": 27.720, "f64": 0.143},
+                         "insts_per_step": {"FMA_F32": 10.351, "ADD_F32": 3.325, "MUL_F32": 1.689,
+                                            "TRANS_F32": 2.003, "CVT": 1.263, "INT32": 0.656,
                                             "FMA_F64": 0.025, "ADD_F64": 0.094}},
-    "srusr_bessel_fp64": {"VALUBusy": 95.980, "VALUUtilization": 99.699,
-                          "hw_flops_per_step": {"f32": 0.0, "f64": 58.044},
-                          "insts_per_step": {"FMA_F64": 20.44, "ADD_F64": 4.797, "MUL_F64": 10.852,
-                                             "TRANS_F64": 1.514, "INT32": 3.665, "FMA_F32": 0.0,
+    "srusr_bessel_fp64": {"VALUBusy": 95.981, "VALUUtilization": 99.695,
+                          "hw_flops_per_step": {"f32": 0.0, "f64": 58.105},
+                          "insts_per_step": {"FMA_F64": 20.462, "ADD_F64": 4.802, "MUL_F64": 10.863,
+                                             "TRANS_F64": 1.516, "INT32": 3.669, "FMA_F32": 0.0,
                                              "ADD_F32": 0.0, "MUL_F32": 0.0}},
 }
 # the issue rate of independent v_fma_f32 chains, wave-instructions per SIMD per cycle, recorded
