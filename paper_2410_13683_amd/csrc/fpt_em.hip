@@ -14,10 +14,11 @@
 // global cursor with one atomic per refill (ballot + popcount + mbcnt), runs
 // `chunk` steps, retires the lanes whose trajectory ended, and refills them.
 // New trajectories only start at chunk boundaries and a chunk is a whole number
-// of step groups (4 steps; 16 in the FP32 kernels, except the one that evaluates
-// the network in the step, which round a chunk up to a multiple of 16), so every
-// active lane of a wave is at the same step modulo the group length and each
-// Philox call, which feeds four steps, is taken by the whole wave at once.
+// of step groups (FP64: 4 steps, 2 with 2D noise; FP32: 16, except the kernel
+// that evaluates the network in the step, 4; a chunk is rounded up to a whole
+// group), so every active lane of a wave is at the same step modulo the group
+// length and each Philox call (four steps of 1D noise, two of 2D noise) is
+// taken by the whole wave at once.
 //
 // Random numbers: Philox4x32-10 (Salmon et al., SC'11), key = seed, counter =
 // (traj lo, n >> 2, traj hi, instance); u = (w + 1/2) 2^-32; Box-Muller pairs
@@ -1208,7 +1209,7 @@ __device__ __forceinline__ void lanes_fp32(const Inst &I, const RunArgs &R, cons
 // the covariance, bias B = a S e with e the interpolated principal axis, and
 // dA = a e.xi sqrt(dN) + a^2 |e|^2 dN / 2, eq. (weight_A) for B = S (a e).  Step
 // n takes call n >> 1 of the generator: (u0, u1) for step 2m, (u2, u3) for
-// 2m + 1, so a group of four steps takes two calls.  The structure (groups,
+// 2m + 1, so a group of two steps takes one call.  The structure (groups,
 // event capture, claims) is that of lanes_fp64.
 // ---------------------------------------------------------------------------
 struct Node2d {
@@ -1335,8 +1336,8 @@ __device__ __forceinline__ void lanes_fp64_2d(const Inst &I, const RunArgs &R, c
 // FP32 state with 2D noise (eq. full_langevin_equation): the float-pair state of
 // lanes_fp32 with the noise, bias and weight of lanes_fp64_2d.  Step n takes
 // (xi_1, xi_2) from generator call n >> 1 as the FP64 2D path does ((u0, u1) for
-// step 2m, (u2, u3) for step 2m + 1), so the two paths see the same numbers and
-// a group of two steps takes one call.  Node record, three float4:
+// step 2m, (u2, u3) for step 2m + 1), so the two paths see the same numbers; a
+// group of 16 steps takes eight calls.  Node record, three float4:
 // (S_pp, slope, S_pq, slope), (S_qq, slope, e_phi, slope), (e_pi, slope, r, slope)
 // with r = (V'/V) dN/2 interpolated in the interval, NaN where V'/V is computed
 // exactly (as in the 1D FP32 table; all NaN on a time axis).  A constant bias

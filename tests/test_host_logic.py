@@ -98,6 +98,17 @@ def test_bench_refuses_more_than_one_gpu():
     assert r.returncode == 2 and "one GPU only" in r.stderr and r.stdout == ""
 
 
+def test_kernel_source_hash_ignores_comments_only():
+    """The measured figures are keyed to the kernels' code: comments and whitespace do not change
+    the hash, any other edit does (also inside a string literal)."""
+    b = _bench()
+    src = 'int f(int x) { // one\n  return x /* two */ + 1; }\nconst char *s = "a // b";\n'
+    same = 'int f(int x)\n{\n    return x + 1;   // three\n}\nconst char *s = "a // b"; /* four */\n'
+    assert b._code_tokens(src) == b._code_tokens(same)
+    assert b._code_tokens(src) != b._code_tokens(src.replace("+ 1", "+ 2"))
+    assert b._code_tokens(src) != b._code_tokens(src.replace('"a // b"', '"a / b"'))
+
+
 def test_measured_counter_figures_follow_the_kernel_source():
     """The replayed traffic and VALU figures are reported only for the kernel source they were
     measured on: a different source hash gives null."""
