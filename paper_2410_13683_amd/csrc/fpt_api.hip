@@ -677,6 +677,16 @@ extern "C" int fpt_create(const fpt_potential *pot, const fpt_noise_table *table
     I.tab64 = reinterpret_cast<const double2 *>(base);
     I.tab32 = reinterpret_cast<const float4 *>(base + off_tab32);
     I.rtab32 = reinterpret_cast<const float2 *>(base + off_rtab);
+    I.rec_S = I.rec_dS = I.rec_t = I.rec_dt = I.rec_r = I.rec_dr = 0.0f;
+    for (int i = 0; i < nt && dim == 1; ++i) {
+        if (!(hr[2 * (size_t)i] == hr[2 * (size_t)i])) continue;      // NaN-marked: read per step
+        I.rec_S = std::max(I.rec_S, std::fabs(h32[4 * (size_t)i]));
+        I.rec_dS = std::max(I.rec_dS, std::fabs(h32[4 * (size_t)i + 1]));
+        I.rec_t = std::max(I.rec_t, std::fabs(h32[4 * (size_t)i + 2]));
+        I.rec_dt = std::max(I.rec_dt, std::fabs(h32[4 * (size_t)i + 3]));
+        I.rec_r = std::max(I.rec_r, std::fabs(hr[2 * (size_t)i]));
+        I.rec_dr = std::max(I.rec_dr, std::fabs(hr[2 * (size_t)i + 1]));
+    }
     I.noise_dim = dim;
     I.tab64_2d = reinterpret_cast<const double2 *>(base + off_tab2d);
     I.tab32_2d = reinterpret_cast<const float4 *>(base + off_tab2d32);

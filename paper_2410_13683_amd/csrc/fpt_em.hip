@@ -979,6 +979,26 @@ __device__ __forceinline__ void lanes_fp32(const Inst &I, const RunArgs &R, cons
     // the group-start record's S, tan theta and V'/V at x = xh and their slopes per unit x
     float g_S = 0.0f, g_dS = 0.0f, g_t = 0.0f, g_dt = 0.0f, g_r = 0.0f, g_dr = 0.0f;
 
+    // The epsilon_1 = 1 end (|pi| >= sqrt 2) in SPAN groups.  While |pi| < sqrt 2, a step changes pi
+    // by at most delta = 6 (sqrt2 dN/2 + |V'/V| dN/2) + |tan theta| S |z| (|pi^2 - 6| <= 6), where
+    // S, tan theta and V'/V are read from a smooth record extended past its interval by at most
+    // the D intervals a group's path can move (|dx| <= sqrt2 dN + S |z|), and |z| <= 6.8 sqrt(dN) +
+    // |a| dN (the Box-Muller radius is at most sqrt(66 ln 2 dN)).  A lane with |pi| <= pi_safe at
+    // the group start therefore stays below sqrt 2 (1 - 1e-3) for 16 steps (5 % margin on delta),
+    // and a SPAN group, which needs every live lane there, leaves the end test out.  With no
+    // usable bound pi_safe is -1: no lane qualifies, and every group keeps the test.
+    float pi_safe = -1.0f;
+    if (TAB == 1 && !LEARNED) {
+        const float zmax = fmaf(6.8f, __builtin_amdgcn_sqrtf(c.dN), fabsf((float)A) * c.dN);
+        const float D = fmaf(16.0f * c.inv_h, fmaf(2.0f * I.rec_S, zmax, 1.4143f * c.dN), 1.0f);
+        const float Sx = fmaf(I.rec_dS, D, I.rec_S);
+        const float Tx = fmaf(I.rec_dt, D, I.rec_t);
+        const float Rx = fmaf(I.rec_dr, D, I.rec_r) * c.half_dN;
+        const float delta = fmaf(6.0f, fmaf(0.7072f, c.dN, Rx), Tx * Sx * zmax);
+        if (Sx <= 2.0f * I.rec_S && delta == delta && delta >= 0.0f && delta < 1.0f)
+            pi_safe = fmaf(-16.8f, delta, 1.4128f);
+    }
+
     auto group = [&](auto censor_tag, auto span_tag, const float z[G]) {
         constexpr bool CENSOR = decltype(censor_tag)::value;
         constexpr bool SPAN = decltype(span_tag)::value;
@@ -1100,8 +1120,9 @@ __device__ __forceinline__ void lanes_fp32(const Inst &I, const RunArgs &R, cons
             // x <= 0: the sign of a rounded sum is that of the exact one, so this is xs <= 0
             const bool crossed = xl <= -xh;
             // eps_1 = pi^2/2 >= 1: |pi| >= the float just above sqrt(2) (no float lies between
-            // sqrt(2) and it, so this is pi^2 >= 2 for float pi)
-            const bool ended = fabsf(ps) >= 0x1.6a09e8p+0f;
+            // sqrt(2) and it, so this is pi^2 >= 2 for float pi); no lane of a SPAN group can get
+            // there (pi_safe above)
+            const bool ended = (SPAN && !LEARNED) ? false : fabsf(ps) >= 0x1.6a09e8p+0f;
             // live and fresh are updated outside the branch, so that they stay lane masks
             const bool hit = live && (crossed || ended);
             if (hit) {
@@ -1174,7 +1195,8 @@ __device__ __forceinline__ void lanes_fp32(const Inst &I, const RunArgs &R, cons
                 group(T(), F(), z);
             } else {
                 if constexpr (TAB == 1) {
-                    if (__builtin_amdgcn_ballot_w64(live && g_r != g_r) == 0) group(F(), T(), z);
+                    if (__builtin_amdgcn_ballot_w64(live && (g_r != g_r || (!LEARNED && fabsf(ps) > pi_safe))) == 0)
+                        group(F(), T(), z);
                     else group(F(), F(), z);
                 } else {
                     group(F(), F(), z);

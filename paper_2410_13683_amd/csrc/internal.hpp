@@ -59,6 +59,10 @@ struct Inst {
     // FP32 V'/V per table interval j: (r_j, r_j+1 - r_j) of the interval's own branch of the
     // potential, or NaN where V'/V must be computed exactly (see fpt_api.hip)
     const float2 *rtab32;
+    // over the FP32 records whose V'/V interval is a number (the smooth ones): the largest |S_j|,
+    // |S_j+1 - S_j|, |tan_j|, |tan_j+1 - tan_j|, |V'/V_j| and |V'/V_j+1 - V'/V_j|, which bound what
+    // a group evaluating one record for all its steps can read (all 0 without a smooth record)
+    float rec_S, rec_dS, rec_t, rec_dt, rec_r, rec_dr;
     int32_t all_S_pos;               // every node has S > 0 (the ln w update needs no test)
     // 2D noise (noise_dim == 2): node j is (S_pp, S_pq), (S_qq, e_phi), (e_pi, 0) -- the symmetric
     // square root of the node covariance and its unit principal axis

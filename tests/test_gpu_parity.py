@@ -294,6 +294,54 @@ def test_fp32_state_past_both_table_edges():
     assert same.mean() > 0.95 and np.median(dl) < 1e-5 and dl.max() < 1e-3
 
 
+@pytest.mark.gpu
+@pytest.mark.parametrize("A_bias", [0.0, 1.0])
+def test_fp32_state_ends_at_eps1_on_a_phi_table(A_bias):
+    """Inflation ending (eps_1 = pi^2/2 >= 1) in FP32 state on a smooth phi table: the FP32 kernels
+    leave the end test out of a group whose live lanes all start with |pi| at most a bound below
+    sqrt 2 (the bound from the table's records, dN and the bias), so paths that start at
+    |pi| = 1 and end at sqrt 2 about 200 steps later run both kinds of group.  Exponential potential
+    with V'/V = 2 (pi runs from -1 towards -2), 256 phi nodes, dN = 1e-3, 4000 trajectories, against
+    the FP64 oracle on the same streams: every path ends early on both sides, at the same step
+    except FP32 near-ties at |pi| = sqrt 2, with N = (n + 1) dN and ln w where the steps agree."""
+    lo, hi, n_nodes = 0.4, 1.2, 256
+    phi = np.linspace(lo, hi, n_nodes)
+    S = 2e-3 * (1.0 + 0.3 * (phi - 0.8))
+    t = 0.05 + 0.05 * phi
+    w = W.exponential_ig(n_traj=4000, seed=21, alpha=2.0, S=0.0, delta_phi=1.0, dN=1e-3).with_(
+        pi_in=-1.0, precision=1, bias_kind=W.BIAS_CONST if A_bias else W.BIAS_NONE, A_bias=A_bias)
+    # the bound the kernel forms: early groups (|pi| near 1) qualify, the end (sqrt 2) does not
+    zmax = 6.8 * math.sqrt(w.dN) + abs(A_bias) * w.dN
+    inv_h = (n_nodes - 1) / (hi - lo)
+    D = 16 * inv_h * (2 * S.max() * zmax + 1.4143 * w.dN) + 1
+    Sx = S.max() + np.abs(np.diff(S)).max() * D
+    Tx = t.max() + np.abs(np.diff(t)).max() * D
+    delta = 6 * (0.7072 * w.dN + 2.0 * w.dN / 2) + Tx * Sx * zmax
+    pi_safe = 1.4128 - 16.8 * delta
+    assert 1.0 < pi_safe < math.sqrt(2.0)
+    say(f"fp32 eps_1 end on a phi table A={A_bias}: pi_safe {pi_safe:.3f}")
+    pot = fpt.make_potential(w.kind, w.V0, w.phi_T, w.A_plus, w.A_minus, w.phi_in, w.pi_in, w.phi_end)
+    ctx = fpt.Context(pot, S, t, lo, hi, bias_kind=w.bias_kind, A=w.A_bias, precision=1, bins_kind=w.bins_kind,
+                      n_bins=w.n_bins, lo=w.lo, hi=w.hi, N_ref=w.N_ref, max_steps=w.max_steps)
+    (Ng, lg, sg), h = gpu_run(w, ctx=ctx)
+    ctx.destroy()
+    p = orc.Problem(kind=w.kind, V0=w.V0, phi_T=w.phi_T, A_plus=w.A_plus, A_minus=w.A_minus, phi_in=w.phi_in,
+                    pi_in=w.pi_in, phi_end=w.phi_end, S=S, tan_theta=t, phi_lo=lo, phi_hi=hi,
+                    bias_kind=w.bias_kind, A_bias=w.A_bias)
+    No, lo_, so = orc.run(p, w.dN, w.seed, w.n_traj)
+    assert np.all((sg & 0xC0000000) == orc.FLAG_ENDED_EARLY) and np.all((so & 0xC0000000) == orc.FLAG_ENDED_EARLY)
+    assert h["n_ended_early"] == w.n_traj
+    ng, no = sg & orc.STEP_MASK, so & orc.STEP_MASK
+    same = ng == no
+    say(f"  steps {no.min()}..{no.max()}; same step {same.mean():.4f}")
+    assert no.min() > 100 and same.mean() > 0.99 and np.all(np.abs(ng.astype(np.int64) - no) <= 1)
+    np.testing.assert_array_equal(Ng[same], No[same])
+    if A_bias:
+        dl = np.abs(lg - lo_)[same]
+        say(f"  |lnw32 - lnw64| where the steps agree: median {np.median(dl):.2e}, max {dl.max():.2e}")
+        assert np.median(dl) < 1e-5 and dl.max() < 1e-3
+
+
 # FP32 state against the oracle at scale, on the same 1e6 coupled trajectories (bias A = 2): the
 # oracle needs about 1e11 steps there, so the comparison runs in five parts of 2e5 trajectories
 # (each a GPU run and the oracle on the same indices, about 40 s of oracle time on 16 host
