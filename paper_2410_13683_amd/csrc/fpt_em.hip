@@ -985,8 +985,9 @@ __device__ __forceinline__ void lanes_fp32(const Inst &I, const RunArgs &R, cons
     // the D intervals a group's path can move (|dx| <= sqrt2 dN + S |z|), and |z| <= 6.8 sqrt(dN) +
     // |a| dN (the Box-Muller radius is at most sqrt(66 ln 2 dN)).  A lane with |pi| <= pi_safe at
     // the group start therefore stays below sqrt 2 (1 - 1e-3) for 16 steps (5 % margin on delta),
-    // and a SPAN group, which needs every live lane there, leaves the end test out.  With no
-    // usable bound pi_safe is -1: no lane qualifies, and every group keeps the test.
+    // and a SPAN group whose live lanes all qualify leaves the end test out; the other SPAN groups
+    // keep it.  With no usable bound (fine grids, where D is large) pi_safe is -1: no lane
+    // qualifies, and every group keeps the test.
     float pi_safe = -1.0f;
     if (TAB == 1 && !LEARNED) {
         const float zmax = fmaf(6.8f, __builtin_amdgcn_sqrtf(c.dN), fabsf((float)A) * c.dN);
@@ -999,9 +1000,10 @@ __device__ __forceinline__ void lanes_fp32(const Inst &I, const RunArgs &R, cons
             pi_safe = fmaf(-16.8f, delta, 1.4128f);
     }
 
-    auto group = [&](auto censor_tag, auto span_tag, const float z[G]) {
+    auto group = [&](auto censor_tag, auto span_tag, auto end_tag, const float z[G]) {
         constexpr bool CENSOR = decltype(censor_tag)::value;
         constexpr bool SPAN = decltype(span_tag)::value;
+        constexpr bool END = decltype(end_tag)::value;   // test the eps_1 = 1 end in each step
         static_assert(!SPAN || (TAB == 1 && !CENSOR), "one record per group: phi tables, no censoring");
         // the rounded sum xs is read by a step only for a per-step table lookup and by the control
         constexpr bool STEP_XS = LEARNED || (TAB == 1 && !SPAN);
@@ -1120,9 +1122,9 @@ __device__ __forceinline__ void lanes_fp32(const Inst &I, const RunArgs &R, cons
             // x <= 0: the sign of a rounded sum is that of the exact one, so this is xs <= 0
             const bool crossed = xl <= -xh;
             // eps_1 = pi^2/2 >= 1: |pi| >= the float just above sqrt(2) (no float lies between
-            // sqrt(2) and it, so this is pi^2 >= 2 for float pi); no lane of a SPAN group can get
-            // there (pi_safe above)
-            const bool ended = (SPAN && !LEARNED) ? false : fabsf(ps) >= 0x1.6a09e8p+0f;
+            // sqrt(2) and it, so this is pi^2 >= 2 for float pi); left out of the groups where no
+            // live lane can get there (pi_safe above)
+            const bool ended = END && fabsf(ps) >= 0x1.6a09e8p+0f;
             // live and fresh are updated outside the branch, so that they stay lane masks
             const bool hit = live && (crossed || ended);
             if (hit) {
@@ -1192,14 +1194,20 @@ __device__ __forceinline__ void lanes_fp32(const Inst &I, const RunArgs &R, cons
                 g_dr = g_rn.y * c.inv_h;
             }
             if ((uint32_t)k + G > left) {
-                group(T(), F(), z);
+                group(T(), F(), T(), z);
             } else {
                 if constexpr (TAB == 1) {
-                    if (__builtin_amdgcn_ballot_w64(live && (g_r != g_r || (!LEARNED && fabsf(ps) > pi_safe))) == 0)
-                        group(F(), T(), z);
-                    else group(F(), F(), z);
+                    if (__builtin_amdgcn_ballot_w64(live && g_r != g_r) != 0) {
+                        group(F(), F(), T(), z);
+                    } else if constexpr (LEARNED) {
+                        group(F(), T(), T(), z);
+                    } else {
+                        if (__builtin_amdgcn_ballot_w64(live && fabsf(ps) > pi_safe) == 0)
+                            group(F(), T(), F(), z);
+                        else group(F(), T(), T(), z);
+                    }
                 } else {
-                    group(F(), F(), z);
+                    group(F(), F(), T(), z);
                 }
             }
         }
