@@ -92,9 +92,9 @@ PEAK_HBM_GBS = 8000.0
 # process (FETCH_SIZE reads 0.5 GiB: x2.0; WRITE_SIZE reads 1 GiB: x1.0).  Valid only for the
 # kernel source it was measured on (hash of the kernel file and its header).
 MEASURED_TRAFFIC = {
-    "source_sha256": "bd0bc184a1d54b1b3baa0f150ecceb104a1e552941d587ae881cb26cdf991b31",
+    "source_sha256": "c683ad549ea2f9f7ac26ef7e2fea702467ae2d7b5b0a30dc67d977eeb32ee554",
     "workload": "srusr_is_fp32_A2", "n_traj": 100_000_000,
-    "fetch_bytes": 7753.8125 * 1024 * 2.0, "write_bytes": 2121458.90625 * 1024 * 1.0,
+    "fetch_bytes": 10945.125 * 1024 * 2.0, "write_bytes": 2126128.75 * 1024 * 1.0,
 }
 
 
@@ -143,16 +143,16 @@ def kernel_source_sha() -> str:
 # 2 FMA + ADD + MUL + TRANS of each precision.  They measure what the compiled kernel executes,
 # beside the operation-by-operation count of the method used for "achieved".
 MEASURED_VALU = {
-    "source_sha256": "bd0bc184a1d54b1b3baa0f150ecceb104a1e552941d587ae881cb26cdf991b31",
-    "srusr_is_fp32_A2": {"VALUBusy": 136.690, "VALUUtilization": 99.087,
+    "source_sha256": "c683ad549ea2f9f7ac26ef7e2fea702467ae2d7b5b0a30dc67d977eeb32ee554",
+    "srusr_is_fp32_A2": {"VALUBusy": 138.600, "VALUUtilization": 99.068,
                          "hw_flops_per_step": {"f32": 27.720, "f64": 0.143},
                          "insts_per_step": {"FMA_F32": 10.351, "ADD_F32": 3.325, "MUL_F32": 1.689,
-                                            "TRANS_F32": 2.003, "CVT": 1.263, "INT32": 0.656,
+                                            "TRANS_F32": 2.003, "CVT": 1.263, "INT32": 0.719,
                                             "FMA_F64": 0.025, "ADD_F64": 0.094}},
-    "srusr_bessel_fp64": {"VALUBusy": 95.981, "VALUUtilization": 99.695,
-                          "hw_flops_per_step": {"f32": 0.0, "f64": 58.105},
-                          "insts_per_step": {"FMA_F64": 20.462, "ADD_F64": 4.802, "MUL_F64": 10.863,
-                                             "TRANS_F64": 1.516, "INT32": 3.669, "FMA_F32": 0.0,
+    "srusr_bessel_fp64": {"VALUBusy": 95.493, "VALUUtilization": 99.709,
+                          "hw_flops_per_step": {"f32": 0.0, "f64": 57.993},
+                          "insts_per_step": {"FMA_F64": 20.422, "ADD_F64": 4.793, "MUL_F64": 10.842,
+                                             "TRANS_F64": 1.513, "INT32": 3.662, "FMA_F32": 0.0,
                                              "ADD_F32": 0.0, "MUL_F32": 0.0}},
 }
 # the issue rate of independent v_fma_f32 chains, wave-instructions per SIMD per cycle, recorded
