@@ -76,6 +76,47 @@ def test_batch_equals_single_runs(precision):
             c.destroy()
 
 
+def test_batch_equals_single_runs_with_eps1_ends_on_a_phi_table():
+    """FP32 state, constant bias A = 1, on a smooth 256-node phi table where every path starts at
+    |pi| = 1 and ends at eps_1 = 1 (|pi| = sqrt 2) about 200 steps later (exponential potential,
+    V'/V = 2, dN = 1e-3): its groups run on the table record both with the end test (near sqrt 2)
+    and without it (the early groups, whose lanes the bound clears).  Batched with a single-node
+    instance of the same dN, the histogram must equal the single launch's."""
+    lo, hi, n_nodes = 0.4, 1.2, 256
+    phi = np.linspace(lo, hi, n_nodes)
+    S = 2e-3 * (1.0 + 0.3 * (phi - 0.8))
+    t = 0.05 + 0.05 * phi
+    w = W.exponential_ig(seed=21, alpha=2.0, S=0.0, delta_phi=1.0, dN=1e-3).with_(
+        pi_in=-1.0, precision=1, bias_kind=W.BIAS_CONST, A_bias=1.0)
+    other = W.exponential_ig(dN=1e-3).with_(precision=1, extra={"instance": 7}, bias_kind=W.BIAS_CONST, A_bias=0.7)
+    assert other.dN == w.dN
+    pot = fpt.make_potential(w.kind, w.V0, w.phi_T, w.A_plus, w.A_minus, w.phi_in, w.pi_in, w.phi_end)
+
+    def eps1_ctx():
+        return fpt.Context(pot, S, t, lo, hi, bias_kind=w.bias_kind, A=w.A_bias, precision=1,
+                           bins_kind=w.bins_kind, n_bins=w.n_bins, lo=w.lo, hi=w.hi, N_ref=w.N_ref,
+                           max_steps=w.max_steps)
+
+    counts, seed = [3000, 1000], 123
+    say(f"batch fp32 eps_1 ends on a phi table, counts {counts}")
+    singles = []
+    for make, n in ((eps1_ctx, counts[0]), (lambda: runner.context_for(other), counts[1])):
+        c = make()
+        c.run(n, w.dN, seed, 0, torch.cuda.current_stream())
+        singles.append(c.histogram())
+        c.destroy()
+    assert singles[0]["n_ended_early"] == counts[0]
+    ctxs = [eps1_ctx(), runner.context_for(other)]
+    b = fpt.Batch(ctxs, block_size=256, item_size=512, use_graph=False)
+    b.run(counts, w.dN, seed, 0, torch.cuda.current_stream())
+    torch.cuda.synchronize()
+    for c, hs in zip(ctxs, singles):
+        _compare(c.histogram(), hs)
+    b.destroy()
+    for c in ctxs:
+        c.destroy()
+
+
 def test_graph_replays_match_eager_runs():
     """Capture on a side stream, replay with new seeds, offsets and counts; each replay's
     accumulated histograms equal eager single runs."""
