@@ -1166,9 +1166,18 @@ __device__ __forceinline__ void lanes_fp32(const Inst &I, const RunArgs &R, cons
         ph = ps;
     };
 
+    // n_hi: a wave-uniform upper bound on n over the lanes that hold a trajectory.  All lanes step
+    // together and a refilled lane restarts at 0, so adding each chunk's steps keeps it a bound;
+    // the exact maximum (a cross-lane reduction) is formed only once the bound comes within a
+    // chunk of max_steps, so the groups that can reach max_steps are the same as with the exact
+    // count at every chunk
+    uint32_t n_hi = 0;
     while (__any(has)) {
-        const uint32_t left = wave_steps_left(has, n, I.max_steps);
-        for (int k = 0; k < R.chunk; k += G) {
+        if ((uint64_t)n_hi + (uint64_t)R.chunk + G > I.max_steps)
+            n_hi = I.max_steps - wave_steps_left(has, n, I.max_steps);
+        const uint32_t left = I.max_steps - n_hi;
+        int k = 0;
+        for (; k < R.chunk; k += G) {
             if (!__any(live)) break;
             uint32_t w[G];
 #pragma unroll
@@ -1211,6 +1220,7 @@ __device__ __forceinline__ void lanes_fp32(const Inst &I, const RunArgs &R, cons
                 }
             }
         }
+        n_hi += (uint32_t)k;
         if (!live) has = false;
         if (claim(!has, rel, cursor, n_traj, exhausted)) {
             has = true;
