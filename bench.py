@@ -92,9 +92,9 @@ PEAK_HBM_GBS = 8000.0
 # process (FETCH_SIZE reads 0.5 GiB: x2.0; WRITE_SIZE reads 1 GiB: x1.0).  Valid only for the
 # kernel source it was measured on (hash of the kernel file and its header).
 MEASURED_TRAFFIC = {
-    "source_sha256": "c683ad549ea2f9f7ac26ef7e2fea702467ae2d7b5b0a30dc67d977eeb32ee554",
+    "source_sha256": "fdc53c6b19b7b05f38b14be916129ce282f97ac0dc66d910ad5b255d6c16be41",
     "workload": "srusr_is_fp32_A2", "n_traj": 100_000_000,
-    "fetch_bytes": 10945.125 * 1024 * 2.0, "write_bytes": 2126128.75 * 1024 * 1.0,
+    "fetch_bytes": 10942.5625 * 1024 * 2.0, "write_bytes": 2127586.59375 * 1024 * 1.0,
 }
 
 
@@ -143,16 +143,16 @@ def kernel_source_sha() -> str:
 # 2 FMA + ADD + MUL + TRANS of each precision.  They measure what the compiled kernel executes,
 # beside the operation-by-operation count of the method used for "achieved".
 MEASURED_VALU = {
-    "source_sha256": "c683ad549ea2f9f7ac26ef7e2fea702467ae2d7b5b0a30dc67d977eeb32ee554",
-    "srusr_is_fp32_A2": {"VALUBusy": 138.600, "VALUUtilization": 99.068,
+    "source_sha256": "fdc53c6b19b7b05f38b14be916129ce282f97ac0dc66d910ad5b255d6c16be41",
+    "srusr_is_fp32_A2": {"VALUBusy": 139.295, "VALUUtilization": 98.989,
                          "hw_flops_per_step": {"f32": 27.720, "f64": 0.143},
-                         "insts_per_step": {"FMA_F32": 10.351, "ADD_F32": 3.325, "MUL_F32": 1.689,
-                                            "TRANS_F32": 2.003, "CVT": 1.263, "INT32": 0.719,
+                         "insts_per_step": {"FMA_F32": 10.352, "ADD_F32": 3.325, "MUL_F32": 1.689,
+                                            "TRANS_F32": 2.003, "CVT": 1.263, "INT32": 0.625,
                                             "FMA_F64": 0.025, "ADD_F64": 0.094}},
-    "srusr_bessel_fp64": {"VALUBusy": 95.493, "VALUUtilization": 99.709,
-                          "hw_flops_per_step": {"f32": 0.0, "f64": 57.993},
-                          "insts_per_step": {"FMA_F64": 20.422, "ADD_F64": 4.793, "MUL_F64": 10.842,
-                                             "TRANS_F64": 1.513, "INT32": 3.662, "FMA_F32": 0.0,
+    "srusr_bessel_fp64": {"VALUBusy": 95.481, "VALUUtilization": 99.712,
+                          "hw_flops_per_step": {"f32": 0.0, "f64": 58.024},
+                          "insts_per_step": {"FMA_F64": 20.433, "ADD_F64": 4.796, "MUL_F64": 10.848,
+                                             "TRANS_F64": 1.514, "INT32": 3.664, "FMA_F32": 0.0,
                                              "ADD_F32": 0.0, "MUL_F32": 0.0}},
 }
 # the issue rate of independent v_fma_f32 chains, wave-instructions per SIMD per cycle, recorded
